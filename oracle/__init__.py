@@ -1,0 +1,27 @@
+"""FP64 CPU oracle for batched optimal clip alignment (TEST INFRASTRUCTURE).
+
+This package is a plain, slow, obviously-correct restatement of what the
+alignment path computes, written from the paper (Sections 2.2, 3.1-3.3,
+Eqs. 1-9).  It exists to check the GPU library: only the test suite, the
+smoke entry and the CPU-baseline leg of the benchmark may import it.  It
+shares no code with the HIP path; its only common dependency is the seeded
+input generator ``clipgen``, which holds none of the method's arithmetic.
+
+Modules
+-------
+raster  -- clip model (Eq. 1): half-open rectangle rasterisation, 4-connected
+           polygons and their bounding boxes.
+cosine  -- cosine track: spectra, whitening, phase-correlation surface
+           (Eqs. 3-5), masked argmax with the tie rule, cosine score and
+           thresholded bit (Eq. 2).
+edge    -- edge track: polygon correspondence (Sec. 2.2.2) and the separable
+           L-infinity Min-Max midpoint solve (Eq. 6).
+prune   -- safe pre-screening bounds (area, row/column signatures, polygon
+           bounding-box sizes).
+scp     -- surprisal-based greedy set cover, eager and lazy (Eqs. 7-9).
+loop    -- coarse-to-fine closed loop with orphan re-injection (Sec. 3.1).
+cover   -- drivers that run the above over pair lists.
+
+Readings of the paper where it is silent or ambiguous are fixed in the
+module docstrings; every function names the passage it follows.
+"""

@@ -1,0 +1,193 @@
+"""Pair-list drivers for the oracle: per-pair alignment results and clusters.
+
+An unordered candidate pair is given as (rep[k], mem[k]).  Both directions
+are evaluated, each by the plain per-direction definition:
+
+* direction 0: member mem[k] aligned to representative rep[k]
+  -> bit0 = "rep[k] covers mem[k]", shift[k, 0] = member displacement;
+* direction 1: member rep[k] aligned to representative mem[k]
+  -> bit1 = "mem[k] covers rep[k]", shift[k, 1].
+
+Pairs of clips with different raster sizes are never comparable (different
+pattern radii give incomparable windows).
+"""
+from __future__ import annotations
+
+import multiprocessing as mp
+import os
+
+import numpy as np
+
+from . import cosine, edge, loop, raster
+
+_SHARED = {}
+
+
+class Prepared:
+    """Per-clip rasters, pixel counts and whitened FP64 spectra (lazy)."""
+
+    def __init__(self, clips):
+        self.clips = clips
+        self._a, self._W = {}, {}
+
+    def a(self, i):
+        i = int(i)
+        if i not in self._a:
+            self._a[i] = raster.clip_raster(self.clips, i)
+        return self._a[i]
+
+    def W(self, i):
+        i = int(i)
+        if i not in self._W:
+            self._W[i] = cosine.whiten(cosine.spectrum(self.a(i)))
+        return self._W[i]
+
+    def w(self, i):
+        return int(self.clips.marker_w[int(i)])
+
+
+def _cosine_chunk(args):
+    rep, mem, p, q = args
+    prep = _SHARED["prep"]
+    n = rep.size
+    bits = np.zeros(n, np.uint8)
+    shift = np.zeros((n, 2, 2), np.int16)
+    c = np.zeros((n, 2), np.int32)
+    sc = np.zeros((n, 2), np.float64)
+    r1 = np.zeros((n, 2), np.float64)
+    for k in range(n):
+        j, i = int(rep[k]), int(mem[k])
+        for d, (m, r) in enumerate(((i, j), (j, i))):
+            res = cosine.align(prep.a(m), prep.a(r), prep.W(m), prep.W(r), prep.w(m), p, q)
+            bits[k] |= np.uint8(res["bit"]) << d
+            shift[k, d] = res["s"]
+            c[k, d] = res["c"]
+            sc[k, d] = res["score"]
+            r1[k, d] = res["r1"]
+    return bits, shift, c, sc, r1
+
+
+def _edge_chunk(args):
+    rep, mem, t_edge = args
+    prep = _SHARED["prep"]
+    n = rep.size
+    bits = np.zeros(n, np.uint8)
+    shift = np.zeros((n, 2, 2), np.int16)
+    E = np.zeros((n, 2), np.int32)
+    ok = np.zeros((n, 2), bool)
+    for k in range(n):
+        j, i = int(rep[k]), int(mem[k])
+        for d, (m, r) in enumerate(((i, j), (j, i))):
+            res = edge.align(prep.a(m), prep.a(r), prep.w(m), t_edge)
+            bits[k] |= np.uint8(res["bit"]) << d
+            shift[k, d] = res["s"]
+            E[k, d] = res["E"]
+            ok[k, d] = res["ok"]
+    return bits, shift, E, ok
+
+
+def _run(fn, clips, rep, mem, extra, workers):
+    rep = np.asarray(rep, np.int64)
+    mem = np.asarray(mem, np.int64)
+    if np.any(clips.raster_n[rep] != clips.raster_n[mem]):
+        raise ValueError("pairs must have equal raster sizes")
+    _SHARED["prep"] = Prepared(clips)
+    workers = workers or 1
+    if workers == 1 or rep.size < 64:
+        parts = [fn((rep, mem) + extra)]
+    else:
+        chunks = np.array_split(np.arange(rep.size), workers * 4)
+        ctx = mp.get_context("fork")
+        with ctx.Pool(workers) as pool:
+            parts = pool.map(fn, [(rep[c], mem[c]) + extra for c in chunks])
+    return [np.concatenate([p[t] for p in parts]) for t in range(len(parts[0]))]
+
+
+def align_pairs_cosine(clips, rep, mem, p, q, workers=None):
+    """Cosine track on a pair list: dict(bits, shift, c, score, r1)."""
+    bits, shift, c, sc, r1 = _run(_cosine_chunk, clips, rep, mem, (p, q), workers)
+    return dict(bits=bits, shift=shift, c=c, score=sc, r1=r1)
+
+
+def align_pairs_edge(clips, rep, mem, t_edge, workers=None):
+    """Edge track on a pair list: dict(bits, shift, E, ok)."""
+    bits, shift, E, ok = _run(_edge_chunk, clips, rep, mem, (t_edge,), workers)
+    return dict(bits=bits, shift=shift, E=E, ok=ok)
+
+
+def pixel_counts(clips):
+    return np.array([int(raster.clip_raster(clips, i).sum()) for i in range(clips.n)], np.int64)
+
+
+def cluster_cosine(clips, p, q, K=1, rep=None, mem=None, res=None, workers=None):
+    """Closed loop on the cosine track over a candidate pair list (default: all
+    same-size pairs).  Returns dict(rep_of, shift, n_clusters, reps, log)."""
+    n = clips.n
+    if rep is None:
+        from clipgen import same_size_pairs
+        rep, mem = same_size_pairs(clips)
+    if res is None:
+        res = align_pairs_cosine(clips, rep, mem, p, q, workers)
+    cnt = pixel_counts(clips)
+    rep = np.asarray(rep, np.int64)
+    mem = np.asarray(mem, np.int64)
+
+    def bits_at(tau):
+        pt, qt = tau
+        cov = np.zeros((n, n), bool)
+        np.fill_diagonal(cov, True)
+        for d, (r_, m_) in enumerate(((rep, mem), (mem, rep))):
+            c = res["c"][:, d].astype(object)
+            nm, nr = cnt[m_].astype(object), cnt[r_].astype(object)
+            ok = (nm > 0) & (nr > 0) & (c * c * qt * qt > pt * pt * nm * nr)
+            ok = ok.astype(bool)
+            cov[r_[ok], m_[ok]] = True
+        return cov
+
+    sched = loop.cosine_schedule(p, q, K)
+    rep_of, reps, log = loop.run(n, bits_at, sched)
+    return dict(rep_of=rep_of, shift=_center_shift(n, rep, mem, res["shift"], rep_of),
+                n_clusters=len(reps), reps=reps, log=log)
+
+
+def cluster_edge(clips, t_edge, K=1, rep=None, mem=None, res=None, workers=None):
+    """Closed loop on the edge track (see cluster_cosine)."""
+    n = clips.n
+    if rep is None:
+        from clipgen import same_size_pairs
+        rep, mem = same_size_pairs(clips)
+    if res is None:
+        res = align_pairs_edge(clips, rep, mem, t_edge, workers)
+    rep = np.asarray(rep, np.int64)
+    mem = np.asarray(mem, np.int64)
+
+    def bits_at(tau):
+        cov = np.zeros((n, n), bool)
+        np.fill_diagonal(cov, True)
+        for d, (r_, m_) in enumerate(((rep, mem), (mem, rep))):
+            ok = res["ok"][:, d] & (res["E"][:, d] >= 0) & (res["E"][:, d] <= tau)
+            cov[r_[ok], m_[ok]] = True
+        return cov
+
+    sched = loop.edge_schedule(t_edge, K)
+    rep_of, reps, log = loop.run(n, bits_at, sched)
+    return dict(rep_of=rep_of, shift=_center_shift(n, rep, mem, res["shift"], rep_of),
+                n_clusters=len(reps), reps=reps, log=log)
+
+
+def _center_shift(n, rep, mem, shift, rep_of):
+    """Each node's shift relative to its representative (0 for representatives)."""
+    out = np.zeros((n, 2), np.int16)
+    lookup = {}
+    for k in range(rep.size):
+        lookup[(int(rep[k]), int(mem[k]))] = shift[k, 0]
+        lookup[(int(mem[k]), int(rep[k]))] = shift[k, 1]
+    for i in range(n):
+        r = int(rep_of[i])
+        if r != i:
+            out[i] = lookup[(r, i)]
+    return out
+
+
+def default_workers():
+    return max(1, len(os.sched_getaffinity(0)))

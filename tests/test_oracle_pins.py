@@ -1,0 +1,481 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+None of these re-types the oracle's formula: each checks it against a closed
+form (Fourier shift theorem, Parseval), a brute force over all shifts or all
+covers, a worked example printed in the paper, or an independently written
+textbook routine.
+"""
+import itertools
+import json
+import math
+import os
+from collections import deque
+
+import numpy as np
+import pytest
+from scipy.fft import dctn
+
+import clipgen
+from oracle import cosine, cover, edge, loop, prune, raster, scp
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_clip(rng, N, k=4, lo=1):
+    rects = []
+    for _ in range(k):
+        x0, x1 = sorted(rng.choice(N + 1, 2, replace=False))
+        y0, y1 = sorted(rng.choice(N + 1, 2, replace=False))
+        rects.append((x0, x1, y0, y1))
+    return raster.rasterize(rects, N)
+
+
+# ---------------------------------------------------------------- raster
+
+
+def test_raster_half_open_and_clipping():
+    a = raster.rasterize([(1, 3, 2, 4), (-5, 1, 7, 20)], 8)
+    want = np.zeros((8, 8), bool)
+    for y in range(8):
+        for x in range(8):
+            want[y, x] = (1 <= x < 3 and 2 <= y < 4) or (-5 <= x < 1 and 7 <= y < 20)
+    assert (a == want).all()
+
+
+def _flood_components(a):
+    """Independent BFS labelling with 4-neighbourhood."""
+    N = a.shape[0]
+    lab = np.zeros(a.shape, int)
+    nxt = 0
+    for y in range(N):
+        for x in range(N):
+            if a[y, x] and not lab[y, x]:
+                nxt += 1
+                dq = deque([(y, x)])
+                lab[y, x] = nxt
+                while dq:
+                    cy, cx = dq.popleft()
+                    for ny, nx in ((cy + 1, cx), (cy - 1, cx), (cy, cx + 1), (cy, cx - 1)):
+                        if 0 <= ny < N and 0 <= nx < N and a[ny, nx] and not lab[ny, nx]:
+                            lab[ny, nx] = nxt
+                            dq.append((ny, nx))
+    return lab, nxt
+
+
+def test_components_match_flood_fill():
+    rng = np.random.default_rng(5)
+    for _ in range(30):
+        a = rng.random((12, 12)) < 0.45
+        lab, boxes = raster.components(a)
+        ref, P = _flood_components(a)
+        assert boxes.shape[0] == P
+        # same partition of pixels (labels may differ by permutation)
+        pairs = set(zip(lab[a].tolist(), ref[a].tolist()))
+        assert len(pairs) == P
+        for p in range(1, P + 1):
+            ys, xs = np.nonzero(lab == p)
+            assert tuple(boxes[p - 1]) == (xs.min(), xs.max() + 1, ys.min(), ys.max() + 1)
+
+
+# ---------------------------------------------------------------- cosine
+
+
+def test_spectrum_equals_explicit_dft():
+    rng = np.random.default_rng(1)
+    N = 8
+    a = rng.random((N, N)) < 0.5
+    D = np.exp(-2j * np.pi * np.outer(np.arange(N), np.arange(N)) / N)
+    F_ref = D @ a.astype(float) @ D.T  # sum_y sum_x a[y,x] e^{-2pi i (u y + v x)/N}
+    assert np.allclose(cosine.spectrum(a), F_ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [16, 32, 64])
+def test_self_match_peaks_at_one_at_zero(N):
+    rng = np.random.default_rng(N)
+    for _ in range(5):
+        a = rand_clip(rng, N)
+        if a.sum() == 0:
+            continue
+        W = cosine.whiten(cosine.spectrum(a))
+        res = cosine.align(a, a, W, W, N // 4, 19, 20)
+        assert res["s"] == (0, 0)
+        assert abs(res["r1"] - 1.0) < 1e-12
+        assert res["c"] == a.sum() and res["score"] == 1.0 and res["bit"]
+
+
+@pytest.mark.parametrize("N,w", [(16, 3), (32, 8), (64, 8)])
+def test_cyclic_shift_recovered_exactly(N, w):
+    """Fourier shift theorem (Eqs. 3-5): g = f shifted by t gives a unit delta at t."""
+    rng = np.random.default_rng(100 + N)
+    for _ in range(6):
+        f = rand_clip(rng, N)
+        if f.sum() == 0:
+            continue
+        t = tuple(int(v) for v in rng.integers(-w, w + 1, size=2))
+        g = np.roll(f, shift=t, axis=(0, 1))  # g(x) = f(x - t)
+        Wf, Wg = (cosine.whiten(cosine.spectrum(x)) for x in (f, g))
+        r, K = cosine.surface(Wg, Wf)
+        assert abs(r[t[0] % N, t[1] % N] - 1.0) < 1e-12
+        # off the peak only the whitened-out bins remain: |r| <= (N^2 - K)/K < 1
+        off = r.copy()
+        off[t[0] % N, t[1] % N] = 0
+        assert np.abs(off).max() <= (N * N - K) / K + 1e-12
+        res = cosine.align(g, f, Wg, Wf, w, 19, 20)
+        assert res["s"] == t and res["c"] == f.sum()
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_surface_equals_spatial_correlation_of_whitened_images(N):
+    """r(s) = (N^2/K) sum_x w_rep(x) w_mem(x+s), w = inverse DFT of the whitened spectrum."""
+    rng = np.random.default_rng(7 + N)
+    for _ in range(4):
+        a, b = rand_clip(rng, N), rand_clip(rng, N)
+        if a.sum() == 0 or b.sum() == 0:
+            continue
+        Wa, Wb = (cosine.whiten(cosine.spectrum(x)) for x in (a, b))
+        r, K = cosine.surface(Wa, Wb)  # member a, rep b
+        wa = np.fft.ifft2(Wa)
+        wb = np.fft.ifft2(Wb)
+        for dy in range(N):
+            for dx in range(N):
+                acc = 0j
+                for y in range(N):
+                    for x in range(N):
+                        acc += np.conj(wb[y, x]) * wa[(y + dy) % N, (x + dx) % N]
+                assert abs(acc.real * N * N / K - r[dy, dx]) < 1e-12
+        # and the term-by-term sum of Eq. 5 at a few shifts
+        sh = [(0, 0), (1, -2), (-3, 3)]
+        assert np.allclose(cosine.surface_at(Wa, Wb, sh), [r[dy % N, dx % N] for dy, dx in sh], atol=1e-12)
+
+
+def test_surface_reverse_is_mirror():
+    rng = np.random.default_rng(11)
+    N = 32
+    for _ in range(5):
+        a, b = rand_clip(rng, N), rand_clip(rng, N)
+        Wa, Wb = (cosine.whiten(cosine.spectrum(x)) for x in (a, b))
+        r_ab, _ = cosine.surface(Wa, Wb)
+        r_ba, _ = cosine.surface(Wb, Wa)
+        idx = (-np.arange(N)) % N
+        assert np.abs(r_ab - r_ba[np.ix_(idx, idx)]).max() < 1e-12
+
+
+def test_window_residue_rule():
+    assert list(cosine.window_axis(2, 8)) == [-2, -1, 0, 1, 2]
+    assert list(cosine.window_axis(3, 7)) == [-3, -2, -1, 0, 1, 2, 3]
+    assert list(cosine.window_axis(4, 8)) == [-4, -3, -2, -1, 0, 1, 2, 3]  # 9 > 8
+    assert list(cosine.window_axis(32, 64)) == list(range(-32, 32))
+    assert cosine.window(1, 8).shape == (9, 2)
+
+
+def test_overlap_count_is_explicit_sum():
+    rng = np.random.default_rng(3)
+    N = 10
+    a, b = rng.random((N, N)) < 0.4, rng.random((N, N)) < 0.6
+    for dy in range(-4, 5):
+        for dx in range(-4, 5):
+            ref = sum(int(a[y, x] and b[(y + dy) % N, (x + dx) % N]) for y in range(N) for x in range(N))
+            assert cosine.overlap(a, b, dy, dx) == ref
+
+
+def test_argmax_and_tie_rule_brute_force():
+    """Scan every window shift; pick max r, then within 1e-9: max c, min |s|_1, lex."""
+    rng = np.random.default_rng(21)
+    N, w = 16, 4
+    # symmetric patterns create exact ties in r
+    for trial in range(25):
+        if trial % 3 == 0:
+            h = rand_clip(rng, N // 2, k=2)
+            a = np.zeros((N, N), bool)
+            a[:N // 2, :N // 2] = h
+            a[N // 2:, N // 2:] = h
+            b = np.roll(a, (trial % 5, 1), axis=(0, 1))
+        else:
+            a, b = rand_clip(rng, N), rand_clip(rng, N)
+        if a.sum() == 0 or b.sum() == 0:
+            continue
+        Wa, Wb = (cosine.whiten(cosine.spectrum(x)) for x in (a, b))
+        res = cosine.align(a, b, Wa, Wb, w, 3, 4)
+        shifts = [(dy, dx) for dy in range(-w, w + 1) for dx in range(-w, w + 1)]
+        vals = cosine.surface_at(Wa, Wb, shifts)
+        top = vals.max()
+        cands = []
+        for (dy, dx), v in zip(shifts, vals):
+            if v >= top - 1e-9:
+                c = sum(int(b[y, x] and a[(y + dy) % N, (x + dx) % N]) for y in range(N) for x in range(N))
+                cands.append((-c, abs(dy) + abs(dx), dy, dx))
+        best = min(cands)
+        assert res["s"] == (best[2], best[3]) and res["c"] == -best[0]
+
+
+def test_dct_parseval_reading_of_eq2():
+    """Eq. 2 on orthonormal DCT-II coefficients equals the pixel cosine."""
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        a, b = rand_clip(rng, 32), rand_clip(rng, 32)
+        A, B = dctn(a.astype(float), norm="ortho"), dctn(b.astype(float), norm="ortho")
+        dct_cos = (A * B).sum() / math.sqrt((A * A).sum() * (B * B).sum())
+        c = int((a & b).sum())
+        assert abs(dct_cos - cosine.score(c, int(a.sum()), int(b.sum()))) < 1e-12
+
+
+def test_threshold_is_exact_rational():
+    # c^2 / (n n) = 361/400 = 0.9025 = (19/20)^2 exactly: strict ">" fails
+    assert cosine.bit(19, 20, 20, 19, 20) is False
+    assert cosine.bit(20, 20, 21, 19, 20) is True  # 400/420 > 0.9025
+    assert cosine.bit(0, 0, 5, 19, 20) is False
+    assert cosine.score(19, 20, 20) == 0.95
+
+
+# ---------------------------------------------------------------- edge
+
+
+def test_minmax_worked_example_from_paper():
+    g = json.load(open(os.path.join(GOLDEN, "minmax_worked_example.json")))
+    s, E = edge.minmax_1d([g["d_min"], 7, 4, g["d_max"]], w=100)
+    assert s == g["T_opt"] and E == g["E_min"]
+    assert abs(g["d_min"] - s) == g["left_error"] and abs(g["d_max"] - s) == g["right_error"]
+
+
+def test_minmax_1d_brute_force_with_tie_rule():
+    rng = np.random.default_rng(4)
+    for _ in range(400):
+        ds = list(rng.integers(-20, 21, size=int(rng.integers(1, 7))))
+        w = int(rng.integers(0, 25))
+        best = min(range(-w, w + 1), key=lambda s: (max(abs(d - s) for d in ds), abs(s)))
+        s, E = edge.minmax_1d(ds, w)
+        assert s == best and E == max(abs(d - s) for d in ds)
+
+
+def test_linf_separability_brute_force():
+    """min over 2-D integer T of max_i |d_i - T|_inf equals max of the two 1-D solves."""
+    rng = np.random.default_rng(8)
+    for _ in range(100):
+        dx = rng.integers(-9, 10, size=4)
+        dy = rng.integers(-9, 10, size=4)
+        w = 9
+        brute = min(max(max(abs(int(a) - sx), abs(int(b) - sy)) for a, b in zip(dx, dy))
+                    for sx in range(-w, w + 1) for sy in range(-w, w + 1))
+        _, ex = edge.minmax_1d(dx, w)
+        _, ey = edge.minmax_1d(dy, w)
+        assert brute == max(ex, ey)
+
+
+def test_translated_rectangles_align_exactly():
+    N = 32
+    for t in [(0, 0), (3, -2), (-5, 5)]:
+        rep = raster.rasterize([(4, 12, 6, 10), (16, 20, 14, 28)], N)
+        mem = raster.rasterize([(4 + t[1], 12 + t[1], 6 + t[0], 10 + t[0]),
+                                (16 + t[1], 20 + t[1], 14 + t[0], 28 + t[0])], N)
+        res = edge.align(mem, rep, 8, 0)
+        assert res["s"] == t and res["E"] == 0 and res["bit"]
+
+
+def _overlaps(mem_lab, rep_lab, p, q, dy, dx):
+    N = rep_lab.shape[0]
+    for y in range(N):
+        for x in range(N):
+            if rep_lab[y, x] == q and 0 <= y + dy < N and 0 <= x + dx < N and mem_lab[y + dy, x + dx] == p:
+                return True
+    return False
+
+
+def test_edge_bit_brute_force_tiny():
+    """Whenever the edge bit is set, an independent check confirms the rule at s."""
+    rng = np.random.default_rng(12)
+    N = 12
+    seen = 0
+    for _ in range(120):
+        a = rand_clip(rng, N, k=int(rng.integers(1, 3)))
+        b = np.roll(a, tuple(rng.integers(-2, 3, size=2)), axis=(0, 1))
+        if rng.random() < 0.3:
+            b = rand_clip(rng, N, k=2)
+        if a.sum() == 0 or b.sum() == 0:
+            continue
+        res = edge.align(a, b, 3, 2)
+        if not res["bit"]:
+            continue
+        seen += 1
+        dy, dx = res["s"]
+        la, P = _flood_components(a)
+        lb, Q = _flood_components(b)
+        fewer_a, fewer_b = P <= Q, Q <= P
+        ds_x, ds_y = [], []
+        for p in range(1, P + 1):
+            hits = [q for q in range(1, Q + 1) if _overlaps(la, lb, p, q, dy, dx)]
+            if fewer_a:
+                assert len(hits) == 1
+        for q in range(1, Q + 1):
+            hits = [p for p in range(1, P + 1) if _overlaps(la, lb, p, q, dy, dx)]
+            if fewer_b:
+                assert len(hits) == 1
+        # residual at s over matched bounding boxes
+        for p in range(1, P + 1):
+            for q in range(1, Q + 1):
+                if _overlaps(la, lb, p, q, dy, dx):
+                    ya, xa = np.nonzero(la == p)
+                    yb, xb = np.nonzero(lb == q)
+                    ds_x += [xa.min() - xb.min(), xa.max() - xb.max()]
+                    ds_y += [ya.min() - yb.min(), ya.max() - yb.max()]
+        E = max(max(abs(d - dx) for d in ds_x), max(abs(d - dy) for d in ds_y))
+        assert E == res["E"] <= 2
+    assert seen > 10
+
+
+# ---------------------------------------------------------------- pruning
+
+
+def test_pruning_bounds_are_safe():
+    rng = np.random.default_rng(13)
+    N, w = 16, 3
+    for _ in range(60):
+        a, b = rand_clip(rng, N, k=3), rand_clip(rng, N, k=3)
+        if a.sum() == 0 or b.sum() == 0:
+            continue
+        best = max(cosine.overlap(b, a, dy, dx) for dy in range(-w, w + 1) for dx in range(-w, w + 1))
+        assert prune.signature_bound(a, b, w) >= best
+        assert min(a.sum(), b.sum()) >= best
+        Wa, Wb = (cosine.whiten(cosine.spectrum(x)) for x in (a, b))
+        for p, q in [(19, 20), (3, 5), (1, 2)]:
+            res = cosine.align(a, b, Wa, Wb, w, p, q)
+            if res["bit"]:
+                assert prune.area_pass(int(a.sum()), int(b.sum()), p, q)
+                assert prune.signature_pass(a, b, w, p, q)
+
+
+def test_edge_box_bound_is_safe():
+    rng = np.random.default_rng(14)
+    N = 16
+    for _ in range(80):
+        a = rand_clip(rng, N, k=2)
+        b = np.roll(a, tuple(rng.integers(-2, 3, size=2)), axis=(0, 1)) if rng.random() < 0.5 else rand_clip(rng, N, k=2)
+        if a.sum() == 0 or b.sum() == 0:
+            continue
+        for t in (0, 1, 2):
+            res = edge.align(a, b, 4, t)
+            if res["bit"]:
+                assert prune.edge_pair_pass(raster.components(a)[1], raster.components(b)[1], t)
+
+
+# ---------------------------------------------------------------- set cover
+
+
+def _chvatal(n, covers):
+    """Textbook greedy set cover: sets are {j} + out(j); pick the set covering the
+    most uncovered elements, lowest index on ties."""
+    sets = [set([j]) | set(np.flatnonzero(covers[j]).tolist()) for j in range(n)]
+    U, chosen = set(range(n)), []
+    while U:
+        j = max((j for j in range(n) if j in U), key=lambda j: (len(sets[j] & U), -j))
+        chosen.append(j)
+        U -= sets[j]
+    return chosen
+
+
+def _random_cover(rng, n, p):
+    cov = rng.random((n, n)) < p
+    np.fill_diagonal(cov, True)
+    return cov
+
+
+def test_lazy_equals_eager():
+    rng = np.random.default_rng(15)
+    for _ in range(40):
+        n = int(rng.integers(1, 40))
+        cov = _random_cover(rng, n, rng.uniform(0.02, 0.4))
+        if rng.random() < 0.5:
+            cov = cov | cov.T
+        pool = np.sort(rng.choice(n, size=int(rng.integers(1, n + 1)), replace=False))
+        assert scp.lazy(pool, cov) == scp.eager(pool, cov)
+
+
+def test_surprisal_reduces_to_chvatal_on_regular_graphs():
+    """Equal in-degrees make every S_i equal, so Score_j ranks like |covered|."""
+    rng = np.random.default_rng(16)
+    for n, d in [(12, 2), (20, 4), (31, 6)]:
+        for _ in range(5):
+            perm = rng.permutation(n)
+            cov = np.zeros((n, n), bool)
+            for k in range(1, d + 1):  # circulant: i covers i+k -> every in-degree is d
+                cov[perm, perm[(np.arange(n) + k) % n]] = True
+            np.fill_diagonal(cov, True)
+            reps, _ = scp.lazy(np.arange(n), cov)
+            assert reps == _chvatal(n, cov & ~np.eye(n, dtype=bool))
+
+
+def test_cover_result_is_a_partition():
+    rng = np.random.default_rng(17)
+    for _ in range(20):
+        n = 30
+        cov = _random_cover(rng, n, 0.1)
+        reps, assign = scp.lazy(np.arange(n), cov)
+        assert sorted(assign) == list(range(n))
+        for i, r in assign.items():
+            assert cov[r, i] and assign[r] == r
+        assert set(reps) == set(assign.values())
+
+
+def test_surprisal_prefers_rare_nodes():
+    """A hub covering 3 common nodes loses to one covering 2 rare nodes."""
+    n = 8
+    cov = np.eye(n, dtype=bool)
+    cov[0, [1, 2, 3]] = True  # hub 0
+    for j in (4, 5, 6):  # 1,2,3 are each covered by many
+        cov[j, [1, 2, 3]] = True
+    cov[7, [4, 5]] = True  # 7 covers nodes that only 0.. nobody else covers
+    reps, _ = scp.eager(np.arange(n), cov)
+    # Score_7 = 1 + 1/2 + 1/2 (4,5 each covered only by 7) beats Score_0 = 1 + 3 * 1/5
+    assert reps[0] == 7
+
+
+# ---------------------------------------------------------------- loop
+
+
+def test_loop_single_iteration_is_set_cover():
+    rng = np.random.default_rng(18)
+    n = 25
+    cov = _random_cover(rng, n, 0.15)
+    rep_of, reps, _ = loop.run(n, lambda tau: cov, [None])
+    r2, assign = scp.lazy(np.arange(n), cov)
+    assert reps == r2 and all(rep_of[i] == assign[i] for i in range(n))
+
+
+def test_loop_converges_and_members_pass_strict():
+    rng = np.random.default_rng(19)
+    n = 40
+    scores = rng.random((n, n))
+    scores = np.maximum(scores, scores.T)
+    np.fill_diagonal(scores, 9)
+
+    def bits_at(tau):
+        return scores >= tau
+
+    rep_of, reps, log = loop.run(n, bits_at, [0.6, 0.75, 0.9])
+    strict = bits_at(0.9)
+    assert (rep_of >= 0).all()
+    for i in range(n):
+        assert strict[rep_of[i], i] and rep_of[rep_of[i]] == rep_of[i]
+    assert len(set(rep_of.tolist())) == len(reps)
+
+
+def test_schedules():
+    assert loop.cosine_schedule(19, 20, 3) == [(93, 100), (47, 50), (19, 20)]
+    assert loop.cosine_schedule(19, 20, 1) == [(19, 20)]
+    assert loop.edge_schedule(2, 3) == [4, 3, 2]
+
+
+# ---------------------------------------------------------------- drivers
+
+
+def test_small_workload_symmetry_and_cover():
+    cs = clipgen.small(n_clips=40)
+    rep, mem = clipgen.all_pairs(cs.n)
+    res = cover.align_pairs_cosine(cs, rep, mem, 19, 20)
+    # equal windows: the relation and the shifts are mirror-symmetric
+    assert ((res["bits"] & 1) == (res["bits"] >> 1)).all()
+    assert (res["shift"][:, 0] == -res["shift"][:, 1]).all()
+    assert (res["c"][:, 0] == res["c"][:, 1]).all()
+    er = cover.align_pairs_edge(cs, rep, mem, 2)
+    assert ((er["bits"] & 1) == (er["bits"] >> 1)).all()
+    cl = cover.cluster_cosine(cs, 19, 20, K=1, rep=rep, mem=mem, res=res)
+    assert 1 <= cl["n_clusters"] <= cs.n
