@@ -1,0 +1,220 @@
+/* clipalign.h -- C ABI of the MI355X clip-alignment library.
+ *
+ * Batched pairwise optimal alignment and scoring of rasterised layout clips:
+ * the hot path of the optimal-alignment clustering framework (arXiv
+ * 2512.13133).  Inputs follow the paper's problem statement (Sec. 2.1-2.3):
+ * clips given as Manhattan rectangles in their marker-centred window, the
+ * marker half-window that bounds each clip's center shift, and a constraint
+ * type with its threshold.  Outputs are the cover bits, the optimal integer
+ * shifts (the member's center offset from its marker center) and scores, and,
+ * from ca_cluster, the partition with its centers.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns ca_status (0 = CA_OK, < 0 = error).  No C++ exception,
+ *   longjmp or abort crosses the ABI.  On error ca_last_error() returns a
+ *   message that stays valid until the next call on the same context.
+ * - Handles (ca_ctx, ca_clipset, ca_server) are owned by the library and freed
+ *   only by their *_destroy call.  Every output buffer is owned by the caller.
+ * - "Device pointer" means memory on the context's GPU (hipMalloc or a torch
+ *   CUDA tensor); "host pointer" means ordinary host memory.  Each argument
+ *   states which it accepts.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Asynchronous calls enqueue work on it and return; outputs are valid once
+ *   that stream has reached the call's last operation.  Calls that return
+ *   host-side results synchronise the stream before returning.
+ * - A ca_ctx is used from one thread at a time; ca_server_submit and
+ *   ca_server_poll may be called from any thread.
+ * - A shift is (dy, dx) in pixels: the member's displacement relative to its
+ *   representative, taken circularly on the N x N grid for the cosine track
+ *   and linearly for the edge track.
+ */
+#ifndef CLIPALIGN_H
+#define CLIPALIGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CA_OK = 0,
+  CA_EINVAL = -1,       /* malformed argument (null pointer, bad size, bad id) */
+  CA_ENOMEM = -2,       /* device allocation failed or over the HBM budget */
+  CA_EDEVICE = -3,      /* a HIP runtime call failed */
+  CA_EBUSY = -4,        /* admission refused for now; retry later */
+  CA_ETRUNC = -5,       /* caller buffer too small; required size written back */
+  CA_ESTATE = -6,       /* call not valid in the object's current state */
+  CA_EUNSUPPORTED = -7  /* input outside the library's supported envelope */
+} ca_status;
+
+typedef struct ca_ctx ca_ctx;
+typedef struct ca_clipset ca_clipset;
+typedef struct ca_server ca_server;
+
+/* Context configuration.  device: HIP device ordinal.  hbm_budget_bytes: cap
+ * on the library's own device allocations (0 = no cap); allocations that would
+ * exceed it fail with CA_ENOMEM instead of exhausting HBM. */
+typedef struct {
+  int32_t device;
+  int32_t reserved;
+  uint64_t hbm_budget_bytes;
+} ca_config;
+
+/* Constraint (paper Sec. 2.2).  CA_COSINE: Eq. 2, cosine strictly greater than
+ * thr_num/thr_den (an exact rational, e.g. 19/20).  CA_EDGE: Sec. 2.2.2,
+ * residual edge displacement at most thr_num pixels (thr_den must be 1). */
+enum { CA_COSINE = 1, CA_EDGE = 2 };
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  int64_t thr_num;
+  int64_t thr_den;
+} ca_constraint;
+
+/* Alignment paths for the cosine track (paper Sec. 3.2.1(1), Eqs. 3-5).
+ *   CA_PATH_MIXED: FP16 whitened spectra, batched per representative, pruned
+ *     inverse transform as dense contractions on MFMA with FP32 accumulation;
+ *     near-tied peaks are re-decided in FP64.  Raster 128 with half-window
+ *     <= 16 only; other shapes use CA_PATH_FP32.
+ *   CA_PATH_FP32: FP32 whitened spectra of both clips read per pair, one
+ *     workgroup per pair, inverse transform by FFT on the vector ALUs; near
+ *     ties re-decided in FP64.  All raster sizes and windows.
+ *   CA_PATH_FP64: the FP64 surface and exact tie rule for every pair.
+ * All three return identical shifts, counts, scores and bits. */
+enum { CA_PATH_MIXED = 0, CA_PATH_FP32 = 1, CA_PATH_FP64 = 2 };
+
+/* Per-pair flag bits written by the alignment calls. */
+enum {
+  CA_FLAG_RESCORED_FWD = 1u << 0, /* forward peak re-decided in FP64 */
+  CA_FLAG_RESCORED_REV = 1u << 1, /* reverse peak re-decided in FP64 */
+  CA_FLAG_EMPTY = 1u << 2,        /* a clip of the pair has no set pixel */
+  CA_FLAG_NO_MATCH_FWD = 1u << 3, /* edge: no polygon correspondence (forward) */
+  CA_FLAG_NO_MATCH_REV = 1u << 4, /* edge: no polygon correspondence (reverse) */
+  CA_FLAG_RECHECK_FWD = 1u << 5,  /* edge: correspondence changed at final shift */
+  CA_FLAG_RECHECK_REV = 1u << 6
+};
+
+/* Run statistics accumulated on a context since creation or the last reset. */
+typedef struct {
+  int64_t pairs_aligned;      /* unordered pairs through a cosine alignment call */
+  int64_t pairs_rescored;     /* of those, pairs with a direction re-decided in FP64 */
+  int64_t pairs_edge;         /* unordered pairs through the edge track */
+  int64_t pairs_screened;     /* unordered pairs examined by ca_prune */
+  int64_t pairs_survived;     /* of those, pairs written as candidates */
+  double max_surface_err;     /* max |low-precision - FP64| surface value seen on
+                                 re-decided pairs (normalised surface units) */
+  double tie_band_mixed;      /* band under which CA_PATH_MIXED re-decides a peak */
+  double tie_band_fp32;       /* band under which CA_PATH_FP32 re-decides a peak */
+} ca_run_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on cfg->device.  out: receives the handle. */
+ca_status ca_create(const ca_config* cfg, ca_ctx** out);
+/* Destroy a context.  All clip sets and servers made on it must be destroyed
+ * first (CA_ESTATE otherwise). */
+ca_status ca_destroy(ca_ctx* ctx);
+/* Last error message of this context ("" if none).  ctx may be NULL, then the
+ * message of the last failed ca_create is returned. */
+const char* ca_last_error(const ca_ctx* ctx);
+ca_status ca_get_stats(const ca_ctx* ctx, ca_run_stats* out);
+ca_status ca_reset_stats(ca_ctx* ctx);
+
+/* ---- clips: rasterise, pack and transform (paper Sec. 2.1 Eq. 1, Sec. 2.2.1
+ *      steps 1-2, Sec. 3.2.1(1) Eq. 4 per-clip whitening) ------------------- */
+
+/* Build a device-resident clip set of n clips.
+ *   rect_ptr [n+1] int64: clip i owns rectangles rect_ptr[i] .. rect_ptr[i+1]-1.
+ *   rects [rect_ptr[n]][4] int32: (x0, x1, y0, y1) in the clip's window frame;
+ *     pixel (y, x) is set iff x0 <= x < x1 and y0 <= y < y1 for some rectangle;
+ *     coordinates outside [0, N) are clipped.
+ *   raster_n [n] int16: N_i in {64, 128, 256}.
+ *   marker_w [n] int16: half-window w_i in [0, 32767]; the member's shifts are
+ *     [-w_i, w_i]^2 (mod N_i on the cosine track, every residue once).
+ *   flags: CA_CLIPS_DEVICE_PTRS if the four arrays are device pointers (else
+ *     host pointers; the library copies them either way).
+ *     CA_CLIPS_FP32 keeps FP32 spectra for CA_PATH_FP32 (doubles the spectra).
+ * The library rasterises, counts pixels, row/column sums, 4-connected polygons
+ * (at most 64 per clip; larger counts mark the clip and make the edge track
+ * fail with CA_EUNSUPPORTED on it), and computes FP64 spectra, whitened with
+ * |F| > 1e-2 kept, stored as FP16 (and FP32 / FP64 as requested).
+ * Returns CA_EINVAL on a bad size or N, CA_ENOMEM if it does not fit. */
+enum { CA_CLIPS_DEVICE_PTRS = 1, CA_CLIPS_FP32 = 2, CA_CLIPS_FP64 = 4 };
+ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr,
+                          const int32_t* rects, const int16_t* raster_n,
+                          const int16_t* marker_w, int32_t flags, ca_clipset** out);
+ca_status ca_clips_destroy(ca_clipset* cs);
+ca_status ca_clips_count(const ca_clipset* cs, int64_t* n);
+
+/* Copy per-clip tables of clip i to host buffers (test and inspection
+ * access; any pointer may be NULL to skip it).
+ *   bits [N*N/64] uint64: row-major, bit x of row y at word y*N/64 + x/64, bit x%64.
+ *   n_pix: set pixels.  rowsum [N], colsum [N] uint16.
+ *   n_poly: polygon count (-1 if over the 64 cap).  boxes [64][4] int16 of
+ *   (x0, x1, y0, y1), half-open.  zero_bins: count of grid bins with |F| <= 1e-2.
+ *   spec16 [N][N/2+1][2] float: the FP16 whitened half-spectrum widened to
+ *   float, bin (u, v) at (u*(N/2+1) + v)*2. */
+ca_status ca_clips_inspect(const ca_clipset* cs, int64_t i, uint64_t* bits, int32_t* n_pix,
+                           uint16_t* rowsum, uint16_t* colsum, int32_t* n_poly,
+                           int16_t* boxes, int32_t* zero_bins, float* spec16);
+
+/* ---- alignment on an explicit pair list (paper Sec. 3.2) ----------------- */
+
+/* Align n_pairs unordered pairs (rep[k], mem[k]) in both directions.
+ * Direction 0 aligns member mem[k] to the fixed representative rep[k];
+ * direction 1 aligns rep[k] to mem[k].  Both clips of a pair must have the
+ * same raster size (else CA_EINVAL).  All arrays are device pointers:
+ *   rep, mem [n_pairs] int32 (clip ids)
+ *   bits [n_pairs] uint8: bit0 = rep covers mem, bit1 = mem covers rep
+ *   shift [n_pairs][2][2] int16: (dy, dx) of direction 0, then direction 1
+ *   count [n_pairs][2] int32: cosine track: overlap count c at the shift;
+ *     edge track: residual E in pixels (-1 if no correspondence)
+ *   score [n_pairs][2] double: cosine c / sqrt(n_mem n_rep) (0 for the edge track)
+ *   flags [n_pairs] uint32: CA_FLAG_* bits
+ * Cosine track (con->kind == CA_COSINE, paper Eqs. 2-5): the shift is the
+ * window maximum of the whitened phase-correlation surface; shifts within
+ * 1e-9 of the maximum are tied and resolved by the larger overlap count, then
+ * the smaller |dy|+|dx|, then the lexicographically smaller (dy, dx).
+ * Edge track (CA_EDGE, paper Sec. 2.2.2, Eq. 6): polygon correspondence at the
+ * global-bounding-box Min-Max shift, per-axis Min-Max midpoint over matched
+ * bounding-box edges, re-check at the final shift, bit iff E <= thr_num;
+ * `path` is ignored.
+ * Asynchronous on `stream` for CA_PATH_FP64 and the edge track; the other
+ * paths synchronise once to size the FP64 re-decision pass. */
+ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
+                         const ca_constraint* con, int32_t path, int64_t n_pairs,
+                         const int32_t* rep, const int32_t* mem, uint8_t* bits,
+                         int16_t* shift, int32_t* count, double* score, uint32_t* flags);
+
+/* ---- multi-stage pruning (paper Sec. 3.1 stage 1, Table 2) --------------- */
+
+/* Candidate generation over all same-size unordered pairs of the clip set,
+ * with safe bounds: pixel-area (B1) and row/column signature (B2) bounds for
+ * CA_COSINE, and B1 plus polygon bounding-box size (B3) for CA_EDGE.  A
+ * rejected pair can never pass `con`, so pruned results equal unpruned ones.
+ * Output (device pointers): rep[k] < mem[k], sorted by (rep, mem); capacity
+ * `cap` pairs.  *n_out (host) receives the survivor count; if it exceeds cap,
+ * nothing is written past cap and CA_ETRUNC is returned.  Synchronises. */
+ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                   int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out);
+
+/* ---- clustering: set cover and closed loop (paper Secs. 3.1, 3.3) -------- */
+
+/* Full method on a clip set: prune, align (path), surprisal lazy-greedy set
+ * cover (Eqs. 7-9) inside the coarse-to-fine loop with `iterations` >= 1
+ * relaxed-to-strict thresholds (cosine T - 0.02 (K-t)/(K-1); edge
+ * T + (K - t) px), orphans re-injected.  Outputs are host arrays of length n:
+ *   rep_of [n] int32: representative of each clip (itself for representatives)
+ *   center_shift [n][2] int16: the clip's shift relative to its representative
+ *   n_clusters: number of representatives. */
+ca_status ca_cluster(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                     int32_t path, int32_t iterations, int32_t* rep_of, int16_t* center_shift,
+                     int64_t* n_clusters);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLIPALIGN_H */

@@ -1,0 +1,230 @@
+"""Python binding of the MI355X clip-alignment library (libclipalign.so).
+
+Argument marshalling only: every step of the alignment path runs in the
+library's HIP kernels.  PyTorch supplies device memory (CUDA tensors on the
+ROCm build) and the current stream.  The binding fails loudly when the built
+library is missing; there is no fallback implementation.
+
+Names follow ``include/clipalign.h``: ``Context.clips`` wraps
+``ca_clips_create``, ``Context.align_pairs`` wraps ``ca_align_pairs``,
+``Context.prune`` wraps ``ca_prune`` and ``Context.cluster`` wraps
+``ca_cluster``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libclipalign.so")
+
+CA_OK, CA_EINVAL, CA_ENOMEM, CA_EDEVICE, CA_EBUSY, CA_ETRUNC, CA_ESTATE, CA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+CA_COSINE, CA_EDGE = 1, 2
+PATHS = {"mixed": 0, "fp32": 1, "fp64": 2}
+CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64 = 1, 2, 4
+FLAG_RESCORED_FWD, FLAG_RESCORED_REV, FLAG_EMPTY = 1, 2, 4
+FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16, 32, 64
+
+SYMBOLS = [
+    "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
+    "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect",
+    "ca_align_pairs", "ca_prune", "ca_cluster",
+]
+
+
+class ClipAlignError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"clipalign status {status}: {msg}")
+        self.status = status
+
+
+class _Config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("reserved", C.c_int32), ("hbm_budget_bytes", C.c_uint64)]
+
+
+class _Constraint(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("thr_num", C.c_int64), ("thr_den", C.c_int64)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("pairs_aligned", C.c_int64), ("pairs_rescored", C.c_int64), ("pairs_edge", C.c_int64),
+                ("pairs_screened", C.c_int64), ("pairs_survived", C.c_int64),
+                ("max_surface_err", C.c_double), ("tie_band_mixed", C.c_double),
+                ("tie_band_fp32", C.c_double)]
+
+
+_LIB = None
+P = C.c_void_p
+
+
+def load():
+    """Load the built library (raises ImportError if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2512_13133_amd.build.build() first")
+    lib = C.CDLL(LIB_PATH)
+    lib.ca_create.argtypes = [C.POINTER(_Config), C.POINTER(P)]
+    lib.ca_destroy.argtypes = [P]
+    lib.ca_last_error.argtypes = [P]
+    lib.ca_last_error.restype = C.c_char_p
+    lib.ca_get_stats.argtypes = [P, C.POINTER(_Stats)]
+    lib.ca_reset_stats.argtypes = [P]
+    lib.ca_clips_create.argtypes = [P, P, C.c_int64, P, P, P, P, C.c_int32, C.POINTER(P)]
+    lib.ca_clips_destroy.argtypes = [P]
+    lib.ca_clips_count.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.ca_clips_inspect.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P]
+    lib.ca_align_pairs.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64,
+                                   P, P, P, P, P, P, P]
+    lib.ca_prune.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int64, P, P, C.POINTER(C.c_int64)]
+    lib.ca_cluster.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int32, P, P,
+                               C.POINTER(C.c_int64)]
+    for name in SYMBOLS:
+        if name != "ca_last_error":
+            getattr(lib, name).restype = C.c_int
+    _LIB = lib
+    return lib
+
+
+def _ptr(a):
+    """Raw address of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def constraint(kind, thr):
+    """('cosine', (p, q)) or ('edge', t_px) -> ca_constraint."""
+    if kind == "cosine":
+        p, q = thr
+        return _Constraint(CA_COSINE, 0, int(p), int(q))
+    if kind == "edge":
+        return _Constraint(CA_EDGE, 0, int(thr), 1)
+    raise ValueError(kind)
+
+
+class ClipSet:
+    def __init__(self, ctx, handle, n):
+        self.ctx, self.handle, self.n = ctx, handle, n
+
+    def close(self):
+        if self.handle:
+            self.ctx._check(self.ctx.lib.ca_clips_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context on one GPU (``ca_create``)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        import torch  # device memory and streams come from torch
+
+        self.torch = torch
+        self.lib = load()
+        self.device = device
+        h = P()
+        st = self.lib.ca_create(C.byref(_Config(device, 0, hbm_budget_bytes)), C.byref(h))
+        if st != CA_OK:
+            raise ClipAlignError(st, self.lib.ca_last_error(None).decode())
+        self.h = h
+        self.dev = torch.device("cuda", device)
+
+    def _check(self, st):
+        if st != CA_OK:
+            raise ClipAlignError(st, self.lib.ca_last_error(self.h).decode())
+
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.dev).cuda_stream
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._check(self.lib.ca_destroy(self.h))
+            self.h = None
+
+    # -------------------------------------------------------------- clips
+    def clips(self, cs, fp32=False):
+        """Build a device clip set from a ``clipgen.ClipSet`` (host arrays)."""
+        ptr = np.ascontiguousarray(cs.rect_ptr, dtype=np.int64)
+        rects = np.ascontiguousarray(cs.rects, dtype=np.int32).reshape(-1, 4)
+        rn = np.ascontiguousarray(cs.raster_n, dtype=np.int16)
+        mw = np.ascontiguousarray(cs.marker_w, dtype=np.int16)
+        flags = CA_CLIPS_FP32 if fp32 else 0
+        h = P()
+        self._check(self.lib.ca_clips_create(self.h, self._stream(), rn.size, _ptr(ptr),
+                                             _ptr(rects) if rects.size else None, _ptr(rn), _ptr(mw),
+                                             flags, C.byref(h)))
+        return ClipSet(self, h, rn.size)
+
+    def inspect(self, clips, i, N):
+        out = dict(bits=np.zeros(N * N // 64, np.uint64), n_pix=np.zeros(1, np.int32),
+                   rowsum=np.zeros(N, np.uint16), colsum=np.zeros(N, np.uint16),
+                   n_poly=np.zeros(1, np.int32), boxes=np.zeros((64, 4), np.int16),
+                   zero_bins=np.zeros(1, np.int32), spec16=np.zeros((N, N // 2 + 1, 2), np.float32))
+        self._check(self.lib.ca_clips_inspect(clips.handle, int(i), *[_ptr(out[k]) for k in (
+            "bits", "n_pix", "rowsum", "colsum", "n_poly", "boxes", "zero_bins", "spec16")]))
+        return out
+
+    # -------------------------------------------------------------- pairs
+    def align_pairs(self, clips, rep, mem, kind="cosine", thr=(19, 20), path="mixed"):
+        """Align unordered pairs on the GPU; returns a dict of CUDA tensors."""
+        torch = self.torch
+        rep = torch.as_tensor(rep, dtype=torch.int32, device=self.dev).contiguous()
+        mem = torch.as_tensor(mem, dtype=torch.int32, device=self.dev).contiguous()
+        n = rep.numel()
+        out = dict(
+            bits=torch.empty(n, dtype=torch.uint8, device=self.dev),
+            shift=torch.empty((n, 2, 2), dtype=torch.int16, device=self.dev),
+            count=torch.empty((n, 2), dtype=torch.int32, device=self.dev),
+            score=torch.empty((n, 2), dtype=torch.float64, device=self.dev),
+            flags=torch.empty(n, dtype=torch.int32, device=self.dev),
+        )
+        con = constraint(kind, thr)
+        self._check(self.lib.ca_align_pairs(self.h, self._stream(), clips.handle, C.byref(con),
+                                            PATHS[path], n, _ptr(rep), _ptr(mem), _ptr(out["bits"]),
+                                            _ptr(out["shift"]), _ptr(out["count"]), _ptr(out["score"]),
+                                            _ptr(out["flags"])))
+        return out
+
+    def prune(self, clips, kind="cosine", thr=(19, 20)):
+        """Candidate pairs surviving the safe bounds: (rep, mem) CUDA int32 tensors."""
+        torch = self.torch
+        con = constraint(kind, thr)
+        n = C.c_int64(0)
+        self._check(self.lib.ca_prune(self.h, self._stream(), clips.handle, C.byref(con), 0, None, None,
+                                      C.byref(n)))
+        rep = torch.empty(max(n.value, 1), dtype=torch.int32, device=self.dev)
+        mem = torch.empty(max(n.value, 1), dtype=torch.int32, device=self.dev)
+        got = C.c_int64(0)
+        if n.value:
+            self._check(self.lib.ca_prune(self.h, self._stream(), clips.handle, C.byref(con), n.value,
+                                          _ptr(rep), _ptr(mem), C.byref(got)))
+        return rep[:n.value], mem[:n.value]
+
+    def cluster(self, clips, kind="cosine", thr=(19, 20), iterations=1, path="mixed"):
+        """Full method; returns dict(rep_of, center_shift, n_clusters) as numpy."""
+        rep_of = np.zeros(clips.n, np.int32)
+        shift = np.zeros((clips.n, 2), np.int16)
+        k = C.c_int64(0)
+        con = constraint(kind, thr)
+        self._check(self.lib.ca_cluster(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path],
+                                        int(iterations), _ptr(rep_of), _ptr(shift), C.byref(k)))
+        return dict(rep_of=rep_of, center_shift=shift, n_clusters=int(k.value))
+
+    def stats(self):
+        s = _Stats()
+        self._check(self.lib.ca_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in _Stats._fields_}
+
+    def reset_stats(self):
+        self._check(self.lib.ca_reset_stats(self.h))

@@ -1,0 +1,522 @@
+// Host runtime behind the C ABI in include/clipalign.h: contexts, device
+// clip sets, pair alignment dispatch with the FP64 re-decision queue,
+// candidate generation, and the set cover + closed loop on the host.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace ca;
+
+// Bands (normalised surface units) under which a low-precision window peak is
+// re-decided in FP64.  A band must exceed twice the path's worst surface error
+// plus the tie tolerance.
+static constexpr double BAND_FP32 = 1e-5;
+static constexpr double BAND_MIXED = 4e-4;
+
+struct ca_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  std::string err;
+  ca_run_stats stats{};
+  int live_clipsets = 0;
+  float2* tw32 = nullptr;   // exp(-2 pi i m / 256), m < 128
+  double2* tw64 = nullptr;
+  // reusable per-call scratch
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+};
+
+struct ca_clipset {
+  ca_ctx* ctx = nullptr;
+  int64_t n = 0;
+  int flags = 0;
+  ClipsDev d{};
+  std::vector<void*> owned;
+  std::vector<int16_t> hN, hw;
+  std::vector<int32_t> hnpix, hnpoly;
+  int maxN = 0, Lmax = 0;
+};
+
+static thread_local std::string g_create_err;
+
+namespace {
+
+ca_status fail(ca_ctx* ctx, ca_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_create_err = msg;
+  return st;
+}
+
+#define HIP_OR_FAIL(ctx, expr)                                                        \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((ctx), CA_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+ca_status dev_alloc(ca_ctx* ctx, void** p, size_t bytes, std::vector<void*>* owner) {
+  *p = nullptr;
+  if (bytes == 0) return CA_OK;
+  if (ctx->budget && ctx->used + bytes > ctx->budget)
+    return fail(ctx, CA_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(ctx, CA_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  ctx->used += bytes;
+  if (owner) owner->push_back(*p);
+  return CA_OK;
+}
+
+// Per-call scratch, grown on demand and kept on the context.
+ca_status scratch(ca_ctx* ctx, size_t bytes, void** out) {
+  if (ctx->scratch_bytes < bytes) {
+    if (ctx->scratch) {
+      (void)hipFree(ctx->scratch);
+      ctx->used -= ctx->scratch_bytes;
+      ctx->scratch = nullptr;
+      ctx->scratch_bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    ca_status st = dev_alloc(ctx, &ctx->scratch, want, nullptr);
+    if (st != CA_OK) return st;
+    ctx->scratch_bytes = want;
+  }
+  *out = ctx->scratch;
+  return CA_OK;
+}
+
+int axis_len(int w, int N) { return (2 * w + 1 <= N) ? 2 * w + 1 : N; }
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool valid_constraint(const ca_constraint* c) {
+  if (!c) return false;
+  if (c->kind == CA_COSINE) return c->thr_num >= 0 && c->thr_den > 0 && c->thr_num <= c->thr_den &&
+                                   c->thr_den <= (1 << 24);
+  if (c->kind == CA_EDGE) return c->thr_num >= 0 && c->thr_den == 1 && c->thr_num < (1 << 20);
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+ca_status ca_create(const ca_config* cfg, ca_ctx** out) {
+  if (!cfg || !out) return fail(nullptr, CA_EINVAL, "null argument");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return fail(nullptr, CA_EDEVICE, "no HIP device visible");
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(nullptr, CA_EINVAL, "bad device ordinal");
+  if (hipSetDevice(cfg->device) != hipSuccess) return fail(nullptr, CA_EDEVICE, "hipSetDevice failed");
+  ca_ctx* ctx = new ca_ctx();
+  ctx->device = cfg->device;
+  ctx->budget = cfg->hbm_budget_bytes;
+  ctx->stats.tie_band_mixed = BAND_MIXED;
+  ctx->stats.tie_band_fp32 = BAND_FP32;
+  std::vector<float2> t32(128);
+  std::vector<double2> t64(128);
+  for (int m = 0; m < 128; ++m) {
+    const double a = -2.0 * M_PI * (double)m / 256.0;
+    t64[m] = make_double2(std::cos(a), std::sin(a));
+    t32[m] = make_float2((float)t64[m].x, (float)t64[m].y);
+  }
+  void* p32 = nullptr;
+  void* p64 = nullptr;
+  if (dev_alloc(ctx, &p32, sizeof(float2) * 128, nullptr) != CA_OK ||
+      dev_alloc(ctx, &p64, sizeof(double2) * 128, nullptr) != CA_OK) {
+    g_create_err = ctx->err;
+    delete ctx;
+    return CA_ENOMEM;
+  }
+  ctx->tw32 = (float2*)p32;
+  ctx->tw64 = (double2*)p64;
+  if (hipMemcpy(p32, t32.data(), sizeof(float2) * 128, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p64, t64.data(), sizeof(double2) * 128, hipMemcpyHostToDevice) != hipSuccess) {
+    g_create_err = "twiddle upload failed";
+    (void)hipFree(p32);
+    (void)hipFree(p64);
+    delete ctx;
+    return CA_EDEVICE;
+  }
+  *out = ctx;
+  return CA_OK;
+}
+
+ca_status ca_destroy(ca_ctx* ctx) {
+  if (!ctx) return CA_EINVAL;
+  if (ctx->live_clipsets) return fail(ctx, CA_ESTATE, "clip sets still alive on this context");
+  (void)hipSetDevice(ctx->device);
+  (void)hipFree(ctx->tw32);
+  (void)hipFree(ctx->tw64);
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  delete ctx;
+  return CA_OK;
+}
+
+const char* ca_last_error(const ca_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+ca_status ca_get_stats(const ca_ctx* ctx, ca_run_stats* out) {
+  if (!ctx || !out) return CA_EINVAL;
+  *out = ctx->stats;
+  return CA_OK;
+}
+
+ca_status ca_reset_stats(ca_ctx* ctx) {
+  if (!ctx) return CA_EINVAL;
+  ctx->stats = ca_run_stats{};
+  ctx->stats.tie_band_mixed = BAND_MIXED;
+  ctx->stats.tie_band_fp32 = BAND_FP32;
+  return CA_OK;
+}
+
+ca_status ca_clips_destroy(ca_clipset* cs) {
+  if (!cs) return CA_EINVAL;
+  (void)hipSetDevice(cs->ctx->device);
+  for (void* p : cs->owned) (void)hipFree(p);
+  cs->ctx->live_clipsets--;
+  delete cs;
+  return CA_OK;
+}
+
+ca_status ca_clips_count(const ca_clipset* cs, int64_t* n) {
+  if (!cs || !n) return CA_EINVAL;
+  *n = cs->n;
+  return CA_OK;
+}
+
+ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr,
+                          const int32_t* rects, const int16_t* raster_n, const int16_t* marker_w,
+                          int32_t flags, ca_clipset** out) {
+  if (!ctx) return CA_EINVAL;
+  if (!out || !rect_ptr || !raster_n || !marker_w || n <= 0 || n > (1ll << 31) - 1)
+    return fail(ctx, CA_EINVAL, "bad clip-set arguments");
+  *out = nullptr;
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const bool on_dev = flags & CA_CLIPS_DEVICE_PTRS;
+  std::vector<int64_t> hptr(n + 1);
+  std::vector<int16_t> hN(n), hw(n);
+  auto fetch = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (on_dev) return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+    std::memcpy(dst, src, bytes);
+    return hipSuccess;
+  };
+  HIP_OR_FAIL(ctx, fetch(hptr.data(), rect_ptr, sizeof(int64_t) * (n + 1)));
+  HIP_OR_FAIL(ctx, fetch(hN.data(), raster_n, sizeof(int16_t) * n));
+  HIP_OR_FAIL(ctx, fetch(hw.data(), marker_w, sizeof(int16_t) * n));
+  if (hptr[0] != 0) return fail(ctx, CA_EINVAL, "rect_ptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i) {
+    if (hptr[i + 1] < hptr[i]) return fail(ctx, CA_EINVAL, "rect_ptr must be non-decreasing");
+    if (hN[i] != 64 && hN[i] != 128 && hN[i] != 256)
+      return fail(ctx, CA_EINVAL, "raster size must be 64, 128 or 256 (clip " + std::to_string(i) + ")");
+    if (hw[i] < 0) return fail(ctx, CA_EINVAL, "marker half-window must be >= 0");
+    if (axis_len(hw[i], hN[i]) > MAX_AXIS)
+      return fail(ctx, CA_EUNSUPPORTED, "half-window above 32 px on a raster larger than 64");
+  }
+  const int64_t m = hptr[n];
+  if (m > 0 && !rects) return fail(ctx, CA_EINVAL, "null rects");
+
+  ca_clipset* cs = new ca_clipset();
+  cs->ctx = ctx;
+  cs->n = n;
+  cs->flags = flags | CA_CLIPS_FP64;  // FP64 spectra back the re-decision pass
+  cs->hN = hN;
+  cs->hw = hw;
+  ctx->live_clipsets++;
+  auto bail = [&](ca_status st) {
+    ca_clips_destroy(cs);
+    return st;
+  };
+  std::vector<int64_t> bits_off(n), sig_off(n), rowptr_off(n), spec_off(n);
+  int64_t nb = 0, ns = 0, nr = 0, nsp = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int N = hN[i];
+    bits_off[i] = nb; nb += (int64_t)N * N / 64;
+    sig_off[i] = ns; ns += N;
+    rowptr_off[i] = nr; nr += N + 1;
+    spec_off[i] = nsp; nsp += (int64_t)N * (N / 2 + 1);
+    cs->maxN = std::max(cs->maxN, N);
+    cs->Lmax = std::max(cs->Lmax, axis_len(hw[i], N));
+  }
+  void* p;
+  ca_status st;
+#define ALLOC(field, type, count)                                              \
+  do {                                                                         \
+    st = dev_alloc(ctx, &p, sizeof(type) * (size_t)(count), &cs->owned);       \
+    if (st != CA_OK) return bail(st);                                          \
+    cs->d.field = (type*)p;                                                    \
+  } while (0)
+  int16_t *dN, *dw;
+  int64_t *dbo, *dso, *dro, *dspo, *drun_off;
+  st = dev_alloc(ctx, &p, sizeof(int16_t) * n, &cs->owned); if (st) return bail(st); dN = (int16_t*)p;
+  st = dev_alloc(ctx, &p, sizeof(int16_t) * n, &cs->owned); if (st) return bail(st); dw = (int16_t*)p;
+  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); dbo = (int64_t*)p;
+  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); dso = (int64_t*)p;
+  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); dro = (int64_t*)p;
+  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); dspo = (int64_t*)p;
+  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); drun_off = (int64_t*)p;
+  cs->d.n = n;
+  cs->d.N = dN; cs->d.w = dw; cs->d.bits_off = dbo; cs->d.sig_off = dso;
+  cs->d.rowptr_off = dro; cs->d.spec_off = dspo; cs->d.run_off = drun_off;
+  ALLOC(bits, uint64_t, nb);
+  ALLOC(npix, int32_t, n);
+  ALLOC(rowsum, uint16_t, ns);
+  ALLOC(colsum, uint16_t, ns);
+  ALLOC(nruns, int32_t, n);
+  ALLOC(npoly, int32_t, n);
+  ALLOC(boxes, int16_t, n * MAX_POLY * 4);
+  ALLOC(gbox, int16_t, n * 4);
+  ALLOC(run_rowptr, uint16_t, nr);
+  ALLOC(zero_bins, int32_t, n);
+  ALLOC(spec16, __half2, nsp);
+  if (flags & CA_CLIPS_FP32) ALLOC(spec32, float2, nsp);
+  ALLOC(spec64, double2, nsp);
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(dN, hN.data(), sizeof(int16_t) * n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(dw, hw.data(), sizeof(int16_t) * n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(dbo, bits_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(dso, sig_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(dro, rowptr_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(dspo, spec_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(ctx, hipMemsetAsync(cs->d.zero_bins, 0, sizeof(int32_t) * n, s));
+  // inputs on the device
+  const int64_t* d_ptr = rect_ptr;
+  const int32_t* d_rects = rects;
+  std::vector<void*> temp;
+  if (!on_dev) {
+    st = dev_alloc(ctx, &p, sizeof(int64_t) * (n + 1), &temp); if (st) return bail(st);
+    d_ptr = (const int64_t*)p;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(p, rect_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    if (m > 0) {
+      st = dev_alloc(ctx, &p, sizeof(int32_t) * 4 * m, &temp); if (st) return bail(st);
+      d_rects = (const int32_t*)p;
+      HIP_OR_FAIL(ctx, hipMemcpyAsync(p, rects, sizeof(int32_t) * 4 * m, hipMemcpyHostToDevice, s));
+    }
+  }
+  HIP_OR_FAIL(ctx, launch_pack(d_ptr, d_rects, cs->d, n, s));
+  std::vector<int32_t> nruns(n);
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(nruns.data(), cs->d.nruns, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  for (void* t : temp) (void)hipFree(t);
+  if (!on_dev) ctx->used -= sizeof(int64_t) * (n + 1) + (m > 0 ? sizeof(int32_t) * 4 * m : 0);
+  std::vector<int64_t> run_off(n);
+  int64_t total_runs = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    run_off[i] = total_runs;
+    if (nruns[i] <= MAX_RUNS) total_runs += nruns[i];
+  }
+  ALLOC(runs, uint32_t, std::max<int64_t>(total_runs, 1));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(drun_off, run_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(ctx, launch_label(cs->d, n, s));
+  // spectra per raster size, in batches through an FP64 scratch
+  for (int N : {64, 128, 256}) {
+    std::vector<int64_t> ids;
+    for (int64_t i = 0; i < n; ++i)
+      if (hN[i] == N) ids.push_back(i);
+    if (ids.empty()) continue;
+    const size_t per = (size_t)N * (N / 2 + 1) * sizeof(double2);
+    const int64_t batch = std::max<int64_t>(1, std::min<int64_t>((int64_t)ids.size(), (512ll << 20) / (int64_t)per));
+    void* sc;
+    st = scratch(ctx, align_up(per * batch) + align_up(sizeof(int64_t) * batch), &sc);
+    if (st) return bail(st);
+    double2* sbuf = (double2*)sc;
+    int64_t* dids = (int64_t*)((char*)sc + align_up(per * batch));
+    for (int64_t b0 = 0; b0 < (int64_t)ids.size(); b0 += batch) {
+      const int64_t nb2 = std::min<int64_t>(batch, (int64_t)ids.size() - b0);
+      HIP_OR_FAIL(ctx, hipMemcpyAsync(dids, ids.data() + b0, sizeof(int64_t) * nb2, hipMemcpyHostToDevice, s));
+      HIP_OR_FAIL(ctx, launch_spectrum(cs->d, dids, nb2, N, sbuf, ctx->tw64, s));
+      HIP_OR_FAIL(ctx, hipStreamSynchronize(s));  // scratch reuse
+    }
+  }
+  cs->hnpix.resize(n);
+  cs->hnpoly.resize(n);
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(cs->hnpix.data(), cs->d.npix, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(cs->hnpoly.data(), cs->d.npoly, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+#undef ALLOC
+  *out = cs;
+  return CA_OK;
+}
+
+ca_status ca_clips_inspect(const ca_clipset* cs, int64_t i, uint64_t* bits, int32_t* n_pix,
+                           uint16_t* rowsum, uint16_t* colsum, int32_t* n_poly, int16_t* boxes,
+                           int32_t* zero_bins, float* spec16) {
+  if (!cs) return CA_EINVAL;
+  ca_ctx* ctx = cs->ctx;
+  if (i < 0 || i >= cs->n) return fail(ctx, CA_EINVAL, "clip id out of range");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  const int N = cs->hN[i];
+  std::vector<int64_t> off(4);
+  HIP_OR_FAIL(ctx, hipMemcpy(&off[0], cs->d.bits_off + i, 8, hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(ctx, hipMemcpy(&off[1], cs->d.sig_off + i, 8, hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(ctx, hipMemcpy(&off[2], cs->d.spec_off + i, 8, hipMemcpyDeviceToHost));
+  if (bits) HIP_OR_FAIL(ctx, hipMemcpy(bits, cs->d.bits + off[0], (size_t)N * N / 8, hipMemcpyDeviceToHost));
+  if (n_pix) HIP_OR_FAIL(ctx, hipMemcpy(n_pix, cs->d.npix + i, 4, hipMemcpyDeviceToHost));
+  if (rowsum) HIP_OR_FAIL(ctx, hipMemcpy(rowsum, cs->d.rowsum + off[1], 2 * N, hipMemcpyDeviceToHost));
+  if (colsum) HIP_OR_FAIL(ctx, hipMemcpy(colsum, cs->d.colsum + off[1], 2 * N, hipMemcpyDeviceToHost));
+  if (n_poly) HIP_OR_FAIL(ctx, hipMemcpy(n_poly, cs->d.npoly + i, 4, hipMemcpyDeviceToHost));
+  if (boxes) HIP_OR_FAIL(ctx, hipMemcpy(boxes, cs->d.boxes + (size_t)i * MAX_POLY * 4, MAX_POLY * 8, hipMemcpyDeviceToHost));
+  if (zero_bins) HIP_OR_FAIL(ctx, hipMemcpy(zero_bins, cs->d.zero_bins + i, 4, hipMemcpyDeviceToHost));
+  if (spec16) {
+    const int H = N / 2;
+    std::vector<__half2> h((size_t)N * (H + 1));
+    HIP_OR_FAIL(ctx, hipMemcpy(h.data(), cs->d.spec16 + off[2], sizeof(__half2) * h.size(), hipMemcpyDeviceToHost));
+    for (int u = 0; u < N; ++u)
+      for (int v = 0; v <= H; ++v) {
+        const __half2 x = (v < H) ? h[(size_t)u * H + v] : h[(size_t)N * H + u];
+        spec16[((size_t)u * (H + 1) + v) * 2 + 0] = __half2float(__low2half(x));
+        spec16[((size_t)u * (H + 1) + v) * 2 + 1] = __half2float(__high2half(x));
+      }
+  }
+  return CA_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ alignment
+
+namespace {
+
+ca_status validate_pairs(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, int64_t n_pairs,
+                         const int32_t* rep, const int32_t* mem, bool need_poly) {
+  void* sc;
+  ca_status st = scratch(ctx, 256, &sc);
+  if (st) return st;
+  int* bad = (int*)sc;
+  HIP_OR_FAIL(ctx, hipMemsetAsync(bad, 0, sizeof(int), s));
+  HIP_OR_FAIL(ctx, launch_validate(cs->d, n_pairs, rep, mem, need_poly ? 1 : 0, bad, s));
+  int hbad = 0;
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  if (hbad & 1) return fail(ctx, CA_EINVAL, "pair list has an out-of-range id or unequal raster sizes");
+  if (hbad & 2) return fail(ctx, CA_EUNSUPPORTED, "edge track on a clip with more than 64 polygons");
+  return CA_OK;
+}
+
+struct FftPlan {
+  int CH, LINES;
+  size_t smem;
+};
+
+FftPlan plan_fft(const ca_clipset* cs, int scalar_bytes) {
+  const size_t budget = 150 * 1024;
+  FftPlan p;
+  const int N = cs->maxN, L = cs->Lmax;
+  p.LINES = 8;
+  const size_t c = 2 * (size_t)scalar_bytes;
+  const size_t fixed = (size_t)p.LINES * N * c + (size_t)L * L * scalar_bytes;
+  int ch = (int)((budget - fixed) / ((size_t)N * c));
+  p.CH = std::max(1, std::min(L, ch));
+  p.smem = pcm_fft_smem(scalar_bytes, N, p.CH, p.LINES, L);
+  return p;
+}
+
+}  // namespace
+
+// Cosine alignment of a device pair list with the chosen path (no validation).
+static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshold thr, int path,
+                              const PairIO& io) {
+  const int64_t n = io.n_pairs;
+  const RescoreQueue none{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (path == CA_PATH_FP64) {
+    FftPlan pl = plan_fft(cs, 8);
+    HIP_OR_FAIL(ctx, launch_pcm_fft64(cs->d, io, nullptr, n, MODE_EXACT, thr, 0.0, ctx->tw64, pl.CH,
+                                      pl.LINES, cs->Lmax, cs->maxN, none, s));
+    ctx->stats.pairs_aligned += n;
+    return CA_OK;
+  }
+  if (path == CA_PATH_FP32 && !cs->d.spec32)
+    return fail(ctx, CA_ESTATE, "CA_PATH_FP32 needs a clip set created with CA_CLIPS_FP32");
+  // queue storage: need[n], list[n], len, r1_low[2n], err
+  const size_t b_need = align_up(n), b_list = align_up(8 * (size_t)n), b_r1 = align_up(8 * (size_t)n);
+  void* sc;
+  ca_status st = scratch(ctx, b_need + b_list + b_r1 + 256, &sc);
+  if (st) return st;
+  RescoreQueue q;
+  char* base = (char*)sc;
+  q.need = (uint8_t*)base;
+  q.list = (int64_t*)(base + b_need);
+  q.r1_low = (float*)(base + b_need + b_list);
+  q.len = (unsigned long long*)(base + b_need + b_list + b_r1);
+  q.peak_err_bits = q.len + 1;
+  HIP_OR_FAIL(ctx, hipMemsetAsync(q.len, 0, 16, s));
+  if (path == CA_PATH_FP32) {
+    FftPlan pl = plan_fft(cs, 4);
+    HIP_OR_FAIL(ctx, launch_pcm_fft32(cs->d, io, nullptr, n, MODE_LOW, thr, BAND_FP32, ctx->tw32, pl.CH,
+                                      pl.LINES, cs->Lmax, cs->maxN, q, s));
+  } else {
+    return fail(ctx, CA_EUNSUPPORTED, "mixed-precision path not available in this build");
+  }
+  unsigned long long h[2] = {0, 0};
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(h, q.len, 16, hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  if (h[0] > 0) {
+    FftPlan pl = plan_fft(cs, 8);
+    HIP_OR_FAIL(ctx, launch_pcm_fft64(cs->d, io, q.list, (int64_t)h[0], MODE_RESCORE, thr, 0.0, ctx->tw64,
+                                      pl.CH, pl.LINES, cs->Lmax, cs->maxN, q, s));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(h, q.len, 16, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+    double err;
+    std::memcpy(&err, &h[1], 8);
+    ctx->stats.max_surface_err = std::max(ctx->stats.max_surface_err, err);
+  }
+  ctx->stats.pairs_aligned += n;
+  ctx->stats.pairs_rescored += (int64_t)h[0];
+  return CA_OK;
+}
+
+extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
+                                    const ca_constraint* con, int32_t path, int64_t n_pairs,
+                                    const int32_t* rep, const int32_t* mem, uint8_t* bits,
+                                    int16_t* shift, int32_t* count, double* score, uint32_t* flags) {
+  if (!ctx) return CA_EINVAL;
+  if (!cs || cs->ctx != ctx) return fail(ctx, CA_EINVAL, "clip set of another context");
+  if (!valid_constraint(con)) return fail(ctx, CA_EINVAL, "bad constraint");
+  if (n_pairs < 0) return fail(ctx, CA_EINVAL, "negative pair count");
+  if (n_pairs == 0) return CA_OK;
+  if (!rep || !mem || !bits || !shift || !count || !score || !flags)
+    return fail(ctx, CA_EINVAL, "null output or pair pointer");
+  if (n_pairs > (1ll << 31) - 1) return fail(ctx, CA_EINVAL, "pair list longer than 2^31 - 1");
+  if (path < CA_PATH_MIXED || path > CA_PATH_FP64) return fail(ctx, CA_EINVAL, "bad path");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  ca_status st = validate_pairs(ctx, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE);
+  if (st) return st;
+  PairIO io{n_pairs, rep, mem, bits, shift, count, score, flags};
+  if (con->kind == CA_EDGE) {
+    HIP_OR_FAIL(ctx, hipMemsetAsync(score, 0, sizeof(double) * 2 * n_pairs, s));
+    HIP_OR_FAIL(ctx, launch_edge(cs->d, io, Threshold{con->thr_num, 1}, s));
+    ctx->stats.pairs_edge += n_pairs;
+    return CA_OK;
+  }
+  return align_cosine(ctx, cs, s, Threshold{con->thr_num, con->thr_den}, path, io);
+}
+
+// Accessors used by api_cluster.hip.
+namespace capriv {
+ca_status fail_ctx(ca_ctx* ctx, ca_status st, const char* msg) { return fail(ctx, st, msg); }
+ca_status scratch_ctx(ca_ctx* ctx, size_t bytes, void** out) { return scratch(ctx, bytes, out); }
+ca_status alloc_ctx(ca_ctx* ctx, void** p, size_t bytes) { return dev_alloc(ctx, p, bytes, nullptr); }
+void free_ctx(ca_ctx* ctx, void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->used -= bytes;
+}
+int device_of(const ca_ctx* ctx) { return ctx->device; }
+ca_run_stats* stats_of(ca_ctx* ctx) { return &ctx->stats; }
+const ca::ClipsDev& dev_of(const ca_clipset* cs) { return cs->d; }
+ca_ctx* ctx_of(const ca_clipset* cs) { return cs->ctx; }
+const std::vector<int16_t>& hN_of(const ca_clipset* cs) { return cs->hN; }
+const std::vector<int32_t>& hnpix_of(const ca_clipset* cs) { return cs->hnpix; }
+int64_t n_of(const ca_clipset* cs) { return cs->n; }
+}  // namespace capriv

@@ -1,0 +1,87 @@
+// Library-internal declarations shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/clipalign.h"
+
+namespace ca {
+
+// Tie tolerance of the peak (shifts within TAU of the window maximum are tied)
+// and the whitening cut |F| > EPS, both in the units of the paper's Eqs. 4-5
+// as read in the library's documentation.
+constexpr double TAU = 1e-9;
+constexpr double EPS = 1e-2;
+constexpr int MAX_POLY = 64;       // polygons per clip kept for the edge track
+constexpr int MAX_RUNS = 4096;     // row runs per clip handled by the labeller
+constexpr int MAX_AXIS = 65;       // window positions per axis (half-window <= 32)
+
+// Device-resident clip set.  Per-clip arrays are indexed by clip id; pools are
+// addressed through per-clip offsets that depend only on the raster size.
+struct ClipsDev {
+  int64_t n;
+  const int16_t* N;          // [n] raster size
+  const int16_t* w;          // [n] marker half-window
+  const int64_t* bits_off;   // [n] word offset into bits (N*N/64 words)
+  uint64_t* bits;
+  int32_t* npix;             // [n]
+  const int64_t* sig_off;    // [n] element offset into rowsum/colsum (N each)
+  uint16_t* rowsum;
+  uint16_t* colsum;
+  int32_t* nruns;            // [n] total runs
+  int32_t* npoly;            // [n] polygon count, -1 over the cap
+  int16_t* boxes;            // [n][MAX_POLY][4] (x0, x1, y0, y1)
+  int16_t* gbox;             // [n][4] global bounding box (zeros if empty)
+  const int64_t* rowptr_off; // [n] offset into run_rowptr (N+1 each)
+  uint16_t* run_rowptr;      // per clip: first run of each row, relative
+  const int64_t* run_off;    // [n] offset into runs
+  uint32_t* runs;            // x0 | x1 << 9 | label << 18 (label 0..63)
+  int32_t* zero_bins;        // [n] full-grid bins with |F| <= EPS
+  const int64_t* spec_off;   // [n] offset in bins: N*(N/2+1) per clip
+  __half2* spec16;           // per clip: [u][v < N/2] then Nyquist column [u]
+  float2* spec32;            // per clip: [u][v <= N/2] (optional)
+  double2* spec64;           // per clip: [u][v <= N/2] (optional)
+};
+
+// Per-call alignment problem in device-visible form.
+struct PairIO {
+  int64_t n_pairs;
+  const int32_t* rep;
+  const int32_t* mem;
+  uint8_t* bits;
+  int16_t* shift;   // [n][2][2]
+  int32_t* count;   // [n][2]
+  double* score;    // [n][2]
+  uint32_t* flags;  // [n]
+};
+
+struct Threshold {
+  int64_t p, q;  // cosine: p/q ; edge: p px (q = 1)
+};
+
+// Surface modes of the per-pair FFT kernel.
+enum { MODE_LOW = 0, MODE_EXACT = 1, MODE_RESCORE = 2 };
+
+// Queue of pair directions whose low-precision peak is too close to call.
+struct RescoreQueue {
+  uint8_t* need;                      // [n_pairs] directions queued for FP64 (bit d)
+  int64_t* list;                      // queued pair ids
+  unsigned long long* len;            // number of queued pairs
+  float* r1_low;                      // [n_pairs][2] low-precision normalised peak value
+  unsigned long long* peak_err_bits;  // max |r1_low - r1_fp64| as double bits
+};
+
+// Candidate generation: anchors, their partner ranges and the output list.
+struct PruneArgs {
+  const int32_t* order;  // clip ids, grouped by raster size (cosine: by (n, id) within a size)
+  const int32_t* hi;     // [n_anchor] exclusive end of each anchor's partner range in `order`
+  int64_t n_anchor;
+  int64_t* counts;       // [n_anchor] survivors (count pass)
+  const int64_t* offs;   // [n_anchor] write offsets (write pass), or null
+  int32_t* out_rep;
+  int32_t* out_mem;
+};
+
+}  // namespace ca

@@ -1,0 +1,266 @@
+// Rasterise and pack clips (paper Sec. 2.1 Eq. 1; Sec. 2.2.1 step 1).
+//
+// pack_kernel: one workgroup per clip.  The N x N raster is built in LDS as
+// bit-packed rows (bit x of row y in word y*N/64 + x/64), one thread per
+// 64-bit word ORing the span masks of every rectangle that crosses its row.
+// It then writes the packed bits, the pixel count, row and column sums and
+// the number of row runs.
+//
+// label_kernel: one workgroup per clip.  Row runs are extracted in parallel,
+// then the 4-connected polygons are labelled by union-find over runs of
+// adjacent rows (one thread; runs are few), giving each polygon its
+// bounding box, and each run its polygon label.
+#include "kernels.h"
+
+namespace ca {
+
+__device__ __forceinline__ uint64_t span_mask(int a, int b) {
+  // bits a..b-1 of a word, 0 <= a < b <= 64
+  uint64_t hi = (b >= 64) ? ~0ull : ((1ull << b) - 1ull);
+  uint64_t lo = (1ull << a) - 1ull;
+  return hi & ~lo;
+}
+
+__global__ void __launch_bounds__(256) pack_kernel(const int64_t* __restrict__ rect_ptr,
+                                                   const int32_t* __restrict__ rects,
+                                                   ClipsDev cs) {
+  __shared__ uint64_t sb[256 * 4];
+  __shared__ int red[256];
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int N = cs.N[i];
+  const int wpr = N / 64;
+  const int nw = N * wpr;
+  const int64_t lo = rect_ptr[i], hi = rect_ptr[i + 1];
+  for (int t = tid; t < nw; t += blockDim.x) {
+    const int y = t / wpr, k = t - y * wpr;
+    uint64_t m = 0;
+    for (int64_t r = lo; r < hi; ++r) {
+      const int32_t* rc = rects + 4 * r;
+      int x0 = max(rc[0], 0), x1 = min(rc[1], N);
+      int y0 = max(rc[2], 0), y1 = min(rc[3], N);
+      if (y < y0 || y >= y1) continue;
+      int a = max(x0, 64 * k), b = min(x1, 64 * k + 64);
+      if (a < b) m |= span_mask(a - 64 * k, b - 64 * k);
+    }
+    sb[t] = m;
+  }
+  __syncthreads();
+  uint64_t* gbits = cs.bits + cs.bits_off[i];
+  for (int t = tid; t < nw; t += blockDim.x) gbits[t] = sb[t];
+  // row sums, run counts and the pixel total: one thread per row
+  int cnt = 0;
+  int runs = 0;
+  uint16_t* rs = cs.rowsum + cs.sig_off[i];
+  uint16_t* cls = cs.colsum + cs.sig_off[i];
+  if (tid < N) {
+    int c = 0, prev = 0;
+    for (int k = 0; k < wpr; ++k) {
+      uint64_t wv = sb[tid * wpr + k];
+      c += __popcll(wv);
+      // run starts: set bits whose left neighbour is clear
+      uint64_t starts = wv & ~((wv << 1) | (uint64_t)prev);
+      runs += __popcll(starts);
+      prev = (int)(wv >> 63);
+    }
+    rs[tid] = (uint16_t)c;
+    cnt = c;
+    // column sum of column tid
+    int cc = 0;
+    const int kk = tid >> 6, bb = tid & 63;
+    for (int y = 0; y < N; ++y) cc += (int)((sb[y * wpr + kk] >> bb) & 1ull);
+    cls[tid] = (uint16_t)cc;
+  }
+  red[tid] = cnt;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) cs.npix[i] = red[0];
+  __syncthreads();
+  red[tid] = runs;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) cs.nruns[i] = red[0];
+}
+
+__device__ __forceinline__ int uf_find(int16_t* parent, int x) {
+  while (parent[x] != x) {
+    parent[x] = parent[parent[x]];
+    x = parent[x];
+  }
+  return x;
+}
+
+__global__ void __launch_bounds__(256) label_kernel(ClipsDev cs) {
+  __shared__ uint32_t srun[MAX_RUNS];   // x0 | x1 << 9
+  __shared__ int16_t parent[MAX_RUNS];
+  __shared__ int16_t slabel[MAX_RUNS];
+  __shared__ uint16_t rowp[257];
+  __shared__ int16_t box[MAX_POLY][4];
+  __shared__ int s_npoly;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int N = cs.N[i];
+  const int wpr = N / 64;
+  const int total = cs.nruns[i];
+  int16_t* gb = cs.gbox + 4 * i;
+  int16_t* bx = cs.boxes + (int64_t)i * MAX_POLY * 4;
+  if (total > MAX_RUNS) {  // too fragmented for the labeller: no polygons kept
+    if (tid == 0) {
+      cs.npoly[i] = -1;
+      gb[0] = gb[1] = gb[2] = gb[3] = 0;
+    }
+    return;
+  }
+  const uint64_t* bits = cs.bits + cs.bits_off[i];
+  // per-row run counts -> exclusive prefix in rowp (serial over <= 256 rows)
+  __shared__ uint16_t rcount[256];
+  if (tid < N) {
+    int runs = 0;
+    int prev = 0;
+    for (int k = 0; k < wpr; ++k) {
+      uint64_t wv = bits[tid * wpr + k];
+      runs += __popcll(wv & ~((wv << 1) | (uint64_t)prev));
+      prev = (int)(wv >> 63);
+    }
+    rcount[tid] = (uint16_t)runs;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int y = 0; y < N; ++y) {
+      rowp[y] = (uint16_t)acc;
+      acc += rcount[y];
+    }
+    rowp[N] = (uint16_t)acc;
+  }
+  __syncthreads();
+  // extract runs of each row in x order
+  if (tid < N) {
+    int o = rowp[tid];
+    int x = 0;
+    while (x < N) {
+      // find next set bit at or after x
+      int k = x >> 6;
+      uint64_t wv = bits[tid * wpr + k] & (~0ull << (x & 63));
+      while (wv == 0 && ++k < wpr) wv = bits[tid * wpr + k];
+      if (k >= wpr) break;
+      int a = 64 * k + __ffsll((unsigned long long)wv) - 1;
+      // find next clear bit at or after a
+      int k2 = a >> 6;
+      uint64_t nv = ~bits[tid * wpr + k2] & (~0ull << (a & 63));
+      while (nv == 0 && ++k2 < wpr) nv = ~bits[tid * wpr + k2];
+      int b = (k2 >= wpr) ? N : 64 * k2 + __ffsll((unsigned long long)nv) - 1;
+      srun[o++] = (uint32_t)a | ((uint32_t)b << 9);
+      x = b;
+    }
+  }
+  for (int t = tid; t < total; t += blockDim.x) parent[t] = (int16_t)t;
+  __syncthreads();
+  if (tid == 0) {
+    // union runs of row y-1 and row y that share a column (4-connectivity)
+    for (int y = 1; y < N; ++y) {
+      int a = rowp[y - 1], ae = rowp[y];
+      int b = rowp[y], be = rowp[y + 1];
+      while (a < ae && b < be) {
+        int a0 = srun[a] & 511, a1 = (srun[a] >> 9) & 511;
+        int b0 = srun[b] & 511, b1 = (srun[b] >> 9) & 511;
+        if (a0 < b1 && b0 < a1) {
+          int ra = uf_find(parent, a), rb = uf_find(parent, b);
+          if (ra != rb) {
+            if (ra < rb) parent[rb] = (int16_t)ra;
+            else parent[ra] = (int16_t)rb;
+          }
+        }
+        if (a1 < b1) ++a;
+        else ++b;
+      }
+    }
+    // labels in order of each polygon's first run (raster order)
+    int np = 0;
+    int gx0 = N, gx1 = 0, gy0 = N, gy1 = 0;
+    int y = 0;
+    for (int r = 0; r < total; ++r) {
+      while (rowp[y + 1] <= r) ++y;
+      int root = uf_find(parent, r);
+      int lab;
+      if (root == r) {
+        lab = np++;
+        if (lab < MAX_POLY) {
+          box[lab][0] = N; box[lab][1] = 0; box[lab][2] = N; box[lab][3] = 0;
+        }
+      } else {
+        lab = slabel[root];
+      }
+      slabel[r] = (int16_t)lab;
+      int x0 = srun[r] & 511, x1 = (srun[r] >> 9) & 511;
+      if (lab < MAX_POLY) {
+        box[lab][0] = (int16_t)min((int)box[lab][0], x0);
+        box[lab][1] = (int16_t)max((int)box[lab][1], x1);
+        box[lab][2] = (int16_t)min((int)box[lab][2], y);
+        box[lab][3] = (int16_t)max((int)box[lab][3], y + 1);
+      }
+      gx0 = min(gx0, x0); gx1 = max(gx1, x1);
+      gy0 = min(gy0, y); gy1 = max(gy1, y + 1);
+    }
+    s_npoly = np;
+    if (total == 0) { gx0 = gx1 = gy0 = gy1 = 0; }
+    gb[0] = (int16_t)gx0; gb[1] = (int16_t)gx1; gb[2] = (int16_t)gy0; gb[3] = (int16_t)gy1;
+    cs.npoly[i] = np > MAX_POLY ? -1 : np;
+  }
+  __syncthreads();
+  const int np = min(s_npoly, MAX_POLY);
+  for (int t = tid; t < np * 4; t += blockDim.x) bx[t] = box[t >> 2][t & 3];
+  uint32_t* gr = cs.runs + cs.run_off[i];
+  for (int t = tid; t < total; t += blockDim.x)
+    gr[t] = srun[t] | ((uint32_t)min((int)slabel[t], MAX_POLY - 1) << 18);
+  uint16_t* grp = cs.run_rowptr + cs.rowptr_off[i];
+  for (int t = tid; t <= N; t += blockDim.x) grp[t] = rowp[t];
+}
+
+}  // namespace ca
+
+namespace ca {
+
+// Pair validation: ids in range, equal raster sizes, and (for the edge track)
+// polygon tables within the cap.  Sets *bad to 1 (ids/sizes) or 2 (polygons).
+__global__ void validate_pairs_kernel(ClipsDev cs, int64_t n_pairs, const int32_t* __restrict__ rep,
+                                      const int32_t* __restrict__ mem, int need_poly, int* bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pairs) return;
+  const int a = rep[k], b = mem[k];
+  if (a < 0 || b < 0 || a >= cs.n || b >= cs.n || cs.N[a] != cs.N[b]) {
+    atomicOr(bad, 1);
+    return;
+  }
+  if (need_poly && (cs.npoly[a] < 0 || cs.npoly[b] < 0)) atomicOr(bad, 2);
+}
+
+hipError_t launch_pack(const int64_t* rect_ptr, const int32_t* rects, const ClipsDev& cs, int64_t n,
+                       hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)n), dim3(256), 0, s, rect_ptr, rects, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_label(const ClipsDev& cs, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(label_kernel, dim3((unsigned)n), dim3(256), 0, s, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const ClipsDev& cs, int64_t n_pairs, const int32_t* rep, const int32_t* mem,
+                           int need_poly, int* bad, hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n_pairs + 255) / 256);
+  hipLaunchKernelGGL(validate_pairs_kernel, dim3(blocks), dim3(256), 0, s, cs, n_pairs, rep, mem,
+                     need_poly, bad);
+  return hipGetLastError();
+}
+
+}  // namespace ca

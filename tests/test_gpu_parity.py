@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar: bit-exact for rasters, counts, polygon tables, shifts, overlap counts,
+cover bits and cluster assignments; FP64 scores within 1e-12 absolute (both
+sides divide the same integers); FP16 spectra within their rounding.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import clipgen
+from oracle import cosine, cover, edge, prune, raster
+
+pytestmark = pytest.mark.gpu
+
+WORKERS = 8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_13133_amd as ca
+    c = ca.Context(0)
+    yield c
+
+
+def small_set(n=64):
+    return clipgen.small(n_clips=n)
+
+
+def mixed_set(seed=7, per=(24, 16, 8)):
+    """Mixed raster sizes and windows, including full-residue windows at 64."""
+    rng = np.random.default_rng(seed)
+    sets = []
+    for N, cnt in zip((64, 128, 256), per):
+        tpl = clipgen.make_templates(rng, 4, N, 3, 10)
+        w = rng.integers(0, 33, size=cnt)
+        sets.append(clipgen.make_clips(rng, tpl, N, cnt, 4, w))
+    cs = clipgen.concat(sets)
+    # an empty clip and a clip whose content is clipped away
+    cs = clipgen.concat([cs, clipgen.ClipSet(np.array([0, 0, 1], np.int64), np.array([[200, 300, 0, 5]], np.int32),
+                                             np.array([64, 64], np.int16), np.array([3, 5], np.int16),
+                                             np.array([-1, -1], np.int32), np.zeros((2, 2), np.int16))])
+    return cs
+
+
+def c128_subset(n=160, seed=3):
+    cs = clipgen.c128(n_clips=2000, n_templates=40)
+    idx = np.sort(np.random.default_rng(seed).choice(cs.n, size=n, replace=False))
+    return cs.subset(idx)
+
+
+def pairs_for(cs, n_pairs=None, seed=0):
+    rep, mem = clipgen.same_size_pairs(cs, np.random.default_rng(seed), n_pairs)
+    return rep, mem
+
+
+def to_np(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def check_cosine(got, ref, rep, mem, label):
+    bits = got["bits"]
+    bad = np.flatnonzero((bits != ref["bits"]) | np.any(got["shift"] != ref["shift"], axis=(1, 2)) |
+                         np.any(got["count"] != ref["c"], axis=1))
+    if bad.size:
+        k = bad[0]
+        raise AssertionError(f"{label}: {bad.size} pairs differ; first k={k} rep={rep[k]} mem={mem[k]} "
+                             f"got bits={bits[k]} shift={got['shift'][k].tolist()} c={got['count'][k].tolist()} "
+                             f"ref bits={ref['bits'][k]} shift={ref['shift'][k].tolist()} c={ref['c'][k].tolist()}")
+    assert np.abs(got["score"] - ref["score"]).max() <= 1e-12
+
+
+# ------------------------------------------------------------------ a1, a2
+
+
+@pytest.mark.parametrize("which", ["small", "mixed"])
+def test_pack_and_spectrum_match_oracle(ctx, which):
+    cs = small_set(48) if which == "small" else mixed_set()
+    say(f"[pack] {which} n={cs.n}")
+    h = ctx.clips(cs)
+    for i in range(cs.n):
+        N = int(cs.raster_n[i])
+        got = ctx.inspect(h, i, N)
+        a = raster.clip_raster(cs, i)
+        bits = np.unpackbits(got["bits"].view(np.uint8), bitorder="little").reshape(N, N).astype(bool)
+        assert (bits == a).all(), f"raster of clip {i}"
+        assert got["n_pix"][0] == a.sum()
+        assert (got["rowsum"] == a.sum(axis=1)).all() and (got["colsum"] == a.sum(axis=0)).all()
+        lab, boxes = raster.components(a)
+        assert got["n_poly"][0] == boxes.shape[0], f"polygons of clip {i}"
+        P = boxes.shape[0]
+        assert sorted(map(tuple, got["boxes"][:P].tolist())) == sorted(map(tuple, boxes.tolist()))
+        F = cosine.spectrum(a)
+        W = cosine.whiten(F)
+        assert got["zero_bins"][0] == int((np.abs(F) <= cosine.EPS).sum()), f"zero bins of clip {i}"
+        half = W[:, :N // 2 + 1]
+        sp = got["spec16"][..., 0] + 1j * got["spec16"][..., 1]
+        assert np.abs(sp.real - half.real).max() <= 2.0 ** -11 + 1e-7
+        assert np.abs(sp.imag - half.imag).max() <= 2.0 ** -11 + 1e-7
+        assert ((sp == 0) == (half == 0)).all()
+    h.close()
+
+
+# ------------------------------------------------------------------ a4-a6 cosine
+
+
+@pytest.mark.parametrize("path", ["fp64", "fp32"])
+def test_cosine_small_all_pairs(ctx, path):
+    cs = small_set(64)
+    rep, mem = clipgen.all_pairs(cs.n)
+    say(f"[cosine] small all pairs path={path} pairs={rep.size}")
+    h = ctx.clips(cs, fp32=True)
+    got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (19, 20), path))
+    ref = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
+    check_cosine(got, ref, rep, mem, f"small/{path}")
+    h.close()
+
+
+@pytest.mark.parametrize("path", ["fp64", "fp32"])
+def test_cosine_mixed_sizes_and_windows(ctx, path):
+    cs = mixed_set()
+    rep, mem = pairs_for(cs, 900, seed=1)
+    say(f"[cosine] mixed sizes path={path} pairs={rep.size}")
+    h = ctx.clips(cs, fp32=True)
+    got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (97, 100), path))
+    ref = cover.align_pairs_cosine(cs, rep, mem, 97, 100, workers=WORKERS)
+    check_cosine(got, ref, rep, mem, f"mixed/{path}")
+    empty = (got["flags"] & 4) != 0
+    assert empty.any()
+    h.close()
+
+
+@pytest.mark.parametrize("path", ["fp32", "fp64"])
+def test_cosine_c128(ctx, path):
+    cs = c128_subset(160)
+    rep, mem = pairs_for(cs, 1500, seed=2)
+    say(f"[cosine] c128 path={path} pairs={rep.size}")
+    h = ctx.clips(cs, fp32=True)
+    got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (19, 20), path))
+    ref = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
+    check_cosine(got, ref, rep, mem, f"c128/{path}")
+    h.close()
+
+
+# ------------------------------------------------------------------ a7 edge
+
+
+@pytest.mark.parametrize("which", ["small", "mixed"])
+def test_edge_track(ctx, which):
+    cs = small_set(64) if which == "small" else mixed_set()
+    rep, mem = (clipgen.all_pairs(cs.n) if which == "small" else pairs_for(cs, 900, seed=4))
+    t = 2
+    say(f"[edge] {which} pairs={rep.size}")
+    h = ctx.clips(cs)
+    got = to_np(ctx.align_pairs(h, rep, mem, "edge", t))
+    ref = cover.align_pairs_edge(cs, rep, mem, t, workers=WORKERS)
+    bad = np.flatnonzero((got["bits"] != ref["bits"]) | np.any(got["shift"] != ref["shift"], axis=(1, 2)) |
+                         np.any(got["count"] != ref["E"], axis=1))
+    assert bad.size == 0, (bad[:5], got["shift"][bad[:1]], ref["shift"][bad[:1]], got["count"][bad[:1]], ref["E"][bad[:1]])
+    assert (got["score"] == 0).all()
+    h.close()
+
+
+# ------------------------------------------------------------------ a3 pruning
+
+
+def test_prune_is_safe_and_matches_bounds(ctx):
+    cs = small_set(96)
+    say(f"[prune] cosine n={cs.n}")
+    h = ctx.clips(cs)
+    r, m = ctx.prune(h, "cosine", (19, 20))
+    got = set(zip(r.cpu().numpy().tolist(), m.cpu().numpy().tolist()))
+    got_u = {(min(a, b), max(a, b)) for a, b in got}
+    assert len(got_u) == len(got)
+    A = raster.rasters(cs)
+    want = set()
+    for i in range(cs.n):
+        for j in range(i + 1, cs.n):
+            if prune.cosine_pair_pass(A[i], A[j], int(cs.marker_w[i]), int(cs.marker_w[j]), 19, 20):
+                want.add((i, j))
+    assert got_u == want
+    # safety: every covering pair survives
+    rep, mem = clipgen.all_pairs(cs.n)
+    ref = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
+    for k in np.flatnonzero(ref["bits"]):
+        assert (int(rep[k]), int(mem[k])) in got_u
+    say(f"[prune] edge n={cs.n}")
+    r, m = ctx.prune(h, "edge", 2)
+    got_e = set(zip(r.cpu().numpy().tolist(), m.cpu().numpy().tolist()))
+    want_e = set()
+    boxes = [raster.components(a)[1] for a in A]
+    for i in range(cs.n):
+        for j in range(i + 1, cs.n):
+            if prune.edge_pair_pass(boxes[i], boxes[j], 2):
+                want_e.add((i, j))
+    assert got_e == want_e
+    h.close()
+
+
+# ------------------------------------------------------------------ a10 clusters
+
+
+@pytest.mark.parametrize("kind,thr,K", [("cosine", (19, 20), 1), ("cosine", (19, 20), 3), ("edge", 2, 1),
+                                        ("edge", 2, 3)])
+def test_cluster_matches_oracle(ctx, kind, thr, K):
+    cs = small_set(96)
+    say(f"[cluster] {kind} K={K} n={cs.n}")
+    h = ctx.clips(cs, fp32=True)
+    got = ctx.cluster(h, kind, thr, iterations=K, path="fp32")
+    rep, mem = clipgen.all_pairs(cs.n)
+    if kind == "cosine":
+        ref = cover.cluster_cosine(cs, thr[0], thr[1], K=K, rep=rep, mem=mem, workers=WORKERS)
+    else:
+        ref = cover.cluster_edge(cs, thr, K=K, rep=rep, mem=mem, workers=WORKERS)
+    assert got["n_clusters"] == ref["n_clusters"]
+    assert (got["rep_of"] == ref["rep_of"]).all()
+    assert (got["center_shift"] == ref["shift"]).all()
+    h.close()
+
+
+# ------------------------------------------------------------------ errors
+
+
+def test_error_paths(ctx):
+    import paper_2512_13133_amd as ca
+    cs = small_set(8)
+    h = ctx.clips(cs)
+    with pytest.raises(ca.ClipAlignError) as e:
+        ctx.align_pairs(h, [0, 1], [1, 99], "cosine", (19, 20), "fp64")
+    assert e.value.status == ca.CA_EINVAL
+    with pytest.raises(ca.ClipAlignError) as e:
+        ctx.align_pairs(h, [0], [1], "cosine", (19, 20), "fp32")  # no FP32 spectra kept
+    assert e.value.status == ca.CA_ESTATE
+    bad = clipgen.small(n_clips=2)
+    bad.raster_n[:] = 100
+    with pytest.raises(ca.ClipAlignError) as e:
+        ctx.clips(bad)
+    assert e.value.status == ca.CA_EINVAL
+    tiny = ca.Context(0, hbm_budget_bytes=1 << 16)
+    with pytest.raises(ca.ClipAlignError) as e:
+        tiny.clips(clipgen.small(n_clips=64))
+    assert e.value.status == ca.CA_ENOMEM
+    h.close()
