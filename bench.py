@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark of the clip-alignment hot path on one MI355X.
+
+Workload: 50,000 clips of 128 x 128 from 1,000 templates of 6-24 rectangles,
+edge jitter +-4 px, pattern offsets +-16 px, marker half-window 16 (33 x 33
+shifts); cosine threshold 19/20 and edge tolerance 3 px.  Inputs are seeded
+and synthetic; the rectangle lists are resident in HBM before timing starts.
+
+One step is one pass of the hot path over the clip set:
+  rasterise + pack + FP64 spectra (ca_clips_create), cosine candidate
+  generation (ca_prune), mixed-precision alignment with FP64 re-decision of
+  near ties (ca_align_pairs), edge candidate generation and edge-track
+  alignment.
+`value` counts the unordered cosine pairs carried through alignment per second
+of the whole step.  Beside it the JSON line carries the roofline of the
+dominant kernel, the plain FP32 per-pair kernel on the same pair list, the
+edge track's rate and the FP64 oracle timed on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "c128_bench_hbm_counters.md")
+KERNEL_SOURCES = ["paper_2512_13133_amd/csrc/pcm_mfma.hip", "paper_2512_13133_amd/csrc/pair_common.h",
+                  "paper_2512_13133_amd/csrc/internal.h"]
+
+
+def profiled_traffic(kernel):
+    """Scaled HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing or the kernel's sources changed since."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    m = re.search(r"sha256 of [^:]*: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != h.hexdigest():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip("|").split("|")]
+        if len(cells) == 5 and cells[0] == "ca::" + kernel:
+            return float(cells[4]) * 1e9
+    return None
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--path", default="mixed", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--clips", type=int, default=50_000)
+    ap.add_argument("--templates", type=int, default=1_000)
+    ap.add_argument("--no-edge", action="store_true", help="skip the edge track (diagnostics only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration) and exit")
+    args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; multi-GPU sharding is described in "
+                          "DESIGN.md and not launched", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import clipgen
+    import paper_2512_13133_amd as ca
+
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    cs = clipgen.c128(n_clips=args.clips, n_templates=args.templates)
+    log(f"[bench] generated {cs.n} clips in {time.time() - t0:.1f}s")
+    d_ptr = torch.from_numpy(cs.rect_ptr).to(dev)
+    d_rects = torch.from_numpy(cs.rects.reshape(-1).copy()).to(dev)
+    d_n = torch.from_numpy(cs.raster_n).to(dev)
+    d_w = torch.from_numpy(cs.marker_w).to(dev)
+    ctx = ca.Context(0)
+    lib = ctx.lib
+    P = ca.P
+    import ctypes as C
+
+    def make_clips(fp32=False):
+        h = P()
+        flags = ca.CA_CLIPS_DEVICE_PTRS | (ca.CA_CLIPS_FP32 if fp32 else 0)
+        ctx._check(lib.ca_clips_create(ctx.h, ctx._stream(), cs.n, d_ptr.data_ptr(), d_rects.data_ptr(),
+                                       d_n.data_ptr(), d_w.data_ptr(), flags, C.byref(h)))
+        return ca.ClipSet(ctx, h, cs.n)
+
+    stage_t = {}
+
+    def timed(name, fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        stage_t[name] = stage_t.get(name, 0.0) + time.perf_counter() - t
+        return r
+
+    def step(keep=False):
+        h = timed("clips", lambda: make_clips(args.path == "fp32"))
+        rep, mem = timed("prune_cosine", lambda: ctx.prune(h, "cosine", (19, 20)))
+        out = timed("align_cosine", lambda: ctx.align_pairs(h, rep, mem, "cosine", (19, 20), args.path))
+        n_e = 0
+        if not args.no_edge:
+            rep_e, mem_e = timed("prune_edge", lambda: ctx.prune(h, "edge", 3))
+            timed("align_edge", lambda: ctx.align_pairs(h, rep_e, mem_e, "edge", 3))
+            n_e = rep_e.numel()
+            del rep_e, mem_e
+        res = (h, rep, mem, out) if keep else None
+        if not keep:
+            h.close()
+        return rep.numel(), n_e, res
+
+    for w in range(args.warmup):
+        n_c, n_e, _ = step()
+        log(f"[bench] warmup {w}: cosine pairs {n_c}, edge pairs {n_e}")
+    stage_t.clear()
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    tot_c = tot_e = 0
+    last = None
+    for s in range(args.steps):
+        n_c, n_e, last = step(keep=(s == args.steps - 1))
+        tot_c += n_c
+        tot_e += n_e
+        log(f"[bench] step {s}: cosine pairs {n_c}, edge pairs {n_e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    st = ctx.stats()
+    ms_per_step = elapsed * 1000.0 / args.steps
+    value = tot_c / elapsed
+
+    # dominant kernel of the cosine path: HIP events recorded by the library on
+    # the launch stream around each launch of the main alignment kernel
+    main_ms = st["t_main_ms"] / max(st["n_main_launch"], 1)
+    main_bytes = st["main_alg_bytes"] / max(st["n_main_launch"], 1)
+    achieved = main_bytes / (main_ms * 1e-3) / 1e9
+    roofline = {"kernel": "pcm_mfma128_kernel" if args.path == "mixed" else "pcm_fft_kernel",
+                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic("pcm_mfma128_kernel") if args.path == "mixed" else None,
+                "avg_launch_ms": round(main_ms, 3), "alg_bytes_per_launch": main_bytes}
+
+    h, rep, mem, out = last
+    n_pairs = rep.numel()
+    kernel_rate = n_pairs / (main_ms * 1e-3) if main_ms > 0 else None
+    # plain FP32 per-pair comparator on the identical pair list
+    comparator = None
+    if args.path == "mixed":
+        h32 = make_clips(fp32=True)
+        ctx.align_pairs(h32, rep, mem, "cosine", (19, 20), "fp32")  # warm
+        ctx.reset_stats()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out32 = ctx.align_pairs(h32, rep, mem, "cosine", (19, 20), "fp32")
+        torch.cuda.synchronize()
+        call_s = time.perf_counter() - t1
+        st32 = ctx.stats()
+        same = all(bool(torch.equal(out[k], out32[k])) for k in ("bits", "shift", "count", "score"))
+        comparator = {"path": "fp32 per-pair FFT", "kernel_pairs_per_s": n_pairs / (st32["t_main_ms"] * 1e-3),
+                      "call_pairs_per_s": n_pairs / call_s, "identical_results": same,
+                      "kernel_ms": st32["t_main_ms"], "rescored": st32["pairs_rescored"]}
+        h32.close()
+    stats_out = {k: st[k] for k in ("pairs_rescored", "max_surface_err", "tie_band_mixed", "pairs_screened",
+                                    "pairs_survived")}
+    stage_ms = {k: round(v * 1000.0 / args.steps, 2) for k, v in stage_t.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cs, rep.cpu().numpy(), mem.cpu().numpy(), args.cpu_seconds)
+    h.close()
+
+    line = {
+        "metric": "aligned pairs/s at 128x128 +-16px (mixed-prec batched vs plain FP32); p99 latency",
+        "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"mixed": "f16/f32+f64", "fp32": "f32+f64",
+                                                          "fp64": "f64"}[args.path],
+        "data": "synthetic",
+        "config": {"workload": "c128: 50k clips 128x128, 1k templates of 6-24 rects, jitter 4, window +-16, "
+                               "cosine 19/20 + edge 3px", "clips": cs.n, "path": args.path,
+                   "cosine_pairs_per_step": n_pairs, "edge_pairs_per_step": tot_e // max(args.steps, 1)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_pairs_per_s": kernel_rate,
+        "plain_fp32": comparator,
+        "stage_ms": stage_ms,
+        "stats": stats_out,
+    }
+    print(json.dumps(line))
+
+
+def copy_probe(nbytes, reps=3):
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+    counters calibrate the traffic figures of the roofline."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    print(json.dumps({"copy_bytes": src.numel() * 4, "reps": reps, "ms": dt * 1e3,
+                      "GBps_read_plus_write": 2 * src.numel() * 4 / dt / 1e9}))
+
+
+def _cpu_worker(args):
+    import numpy as np
+
+    from oracle import cover
+    cs, rep, mem = args
+    t = time.perf_counter()
+    cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=1)
+    return rep.size, time.perf_counter() - t
+
+
+def cpu_baseline(cs, rep, mem, seconds):
+    """The FP64 oracle on a bounded sample of the same cosine pairs, all host cores."""
+    import multiprocessing as mp
+
+    import numpy as np
+    cores = len(os.sched_getaffinity(0))
+    cores = max(1, min(cores, 16))
+    # size the sample from a short single-core probe
+    rng = np.random.default_rng(1234)
+    probe = rng.choice(rep.size, size=min(200, rep.size), replace=False)
+    n, dt = _cpu_worker((cs, rep[probe], mem[probe]))
+    per_core = n / dt
+    total = int(min(rep.size, per_core * cores * seconds))
+    pick = np.sort(rng.choice(rep.size, size=max(total, cores), replace=False))
+    chunks = np.array_split(pick, cores)
+    ctx = mp.get_context("fork")
+    t = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(cs, rep[c], mem[c]) for c in chunks])
+    wall = time.perf_counter() - t
+    done = sum(r[0] for r in res)
+    return {"value": round(done / wall, 1), "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} cosine candidate pairs of the timed step, uniform sample, FP64 numpy oracle, "
+                      f"both directions per pair"}
+
+
+if __name__ == "__main__":
+    main()

@@ -76,8 +76,8 @@ typedef struct {
 /* Alignment paths for the cosine track (paper Sec. 3.2.1(1), Eqs. 3-5).
  *   CA_PATH_MIXED: FP16 whitened spectra, batched per representative, pruned
  *     inverse transform as dense contractions on MFMA with FP32 accumulation;
- *     near-tied peaks are re-decided in FP64.  Raster 128 with half-window
- *     <= 16 only; other shapes use CA_PATH_FP32.
+ *     near-tied peaks are re-decided in FP64.  Clip sets of 128 x 128 clips
+ *     with half-windows <= 16 only (CA_EUNSUPPORTED otherwise).
  *   CA_PATH_FP32: FP32 whitened spectra of both clips read per pair, one
  *     workgroup per pair, inverse transform by FFT on the vector ALUs; near
  *     ties re-decided in FP64.  All raster sizes and windows.
@@ -103,6 +103,9 @@ typedef struct {
   int64_t pairs_edge;         /* unordered pairs through the edge track */
   int64_t pairs_screened;     /* unordered pairs examined by ca_prune */
   int64_t pairs_survived;     /* of those, pairs written as candidates */
+  int64_t n_main_launch;      /* launches of the main cosine alignment kernel */
+  double t_main_ms;           /* their summed duration (HIP events on the launch stream) */
+  double main_alg_bytes;      /* their algorithmic HBM bytes (spectra and bit rasters read) */
   double max_surface_err;     /* max |low-precision - FP64| surface value seen on
                                  re-decided pairs (normalised surface units) */
   double tie_band_mixed;      /* band under which CA_PATH_MIXED re-decides a peak */
@@ -187,6 +190,17 @@ ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
                          const ca_constraint* con, int32_t path, int64_t n_pairs,
                          const int32_t* rep, const int32_t* mem, uint8_t* bits,
                          int16_t* shift, int32_t* count, double* score, uint32_t* flags);
+
+/* Test and calibration access: the low-precision window surface of direction
+ * 0 (member mem[k] against representative rep[k]) exactly as CA_PATH_MIXED
+ * computes it before any FP64 re-decision, for dy, dx in [-16, 16]:
+ * surf[k][dy + 16][dx + 16] = K r(dy, dx) / K_hi with K_hi = N^2 minus the
+ * larger zero-bin count of the two clips (paper Eq. 5 up to that positive
+ * factor).  rep, mem, surf are device pointers; surf has n_pairs*33*33 floats.
+ * CA_EUNSUPPORTED unless path == CA_PATH_MIXED on a set that path accepts.
+ * Synchronises. */
+ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs, int32_t path, int64_t n_pairs,
+                     const int32_t* rep, const int32_t* mem, float* surf);
 
 /* ---- multi-stage pruning (paper Sec. 3.1 stage 1, Table 2) --------------- */
 

@@ -30,7 +30,7 @@ FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16
 SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
     "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect",
-    "ca_align_pairs", "ca_prune", "ca_cluster",
+    "ca_align_pairs", "ca_surface", "ca_prune", "ca_cluster",
 ]
 
 
@@ -51,6 +51,7 @@ class _Constraint(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("pairs_aligned", C.c_int64), ("pairs_rescored", C.c_int64), ("pairs_edge", C.c_int64),
                 ("pairs_screened", C.c_int64), ("pairs_survived", C.c_int64),
+                ("n_main_launch", C.c_int64), ("t_main_ms", C.c_double), ("main_alg_bytes", C.c_double),
                 ("max_surface_err", C.c_double), ("tie_band_mixed", C.c_double),
                 ("tie_band_fp32", C.c_double)]
 
@@ -79,6 +80,7 @@ def load():
     lib.ca_clips_inspect.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P]
     lib.ca_align_pairs.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64,
                                    P, P, P, P, P, P, P]
+    lib.ca_surface.argtypes = [P, P, P, C.c_int32, C.c_int64, P, P, P]
     lib.ca_prune.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int64, P, P, C.POINTER(C.c_int64)]
     lib.ca_cluster.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int32, P, P,
                                C.POINTER(C.c_int64)]
@@ -195,6 +197,16 @@ class Context:
                                             _ptr(out["shift"]), _ptr(out["count"]), _ptr(out["score"]),
                                             _ptr(out["flags"])))
         return out
+
+    def surface(self, clips, rep, mem, path="mixed"):
+        """Low-precision window surfaces [n, 33, 33] (direction 0), normalised by K_hi."""
+        torch = self.torch
+        rep = torch.as_tensor(rep, dtype=torch.int32, device=self.dev).contiguous()
+        mem = torch.as_tensor(mem, dtype=torch.int32, device=self.dev).contiguous()
+        surf = torch.zeros((rep.numel(), 33, 33), dtype=torch.float32, device=self.dev)
+        self._check(self.lib.ca_surface(self.h, self._stream(), clips.handle, PATHS[path], rep.numel(),
+                                        _ptr(rep), _ptr(mem), _ptr(surf)))
+        return surf
 
     def prune(self, clips, kind="cosine", thr=(19, 20)):
         """Candidate pairs surviving the safe bounds: (rep, mem) CUDA int32 tensors."""

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "host_internal.h"
 #include "kernels.h"
 
 using namespace ca;
@@ -18,7 +19,7 @@ using namespace ca;
 // re-decided in FP64.  A band must exceed twice the path's worst surface error
 // plus the tie tolerance.
 static constexpr double BAND_FP32 = 1e-5;
-static constexpr double BAND_MIXED = 4e-4;
+static constexpr double BAND_MIXED = 1e-4;
 
 struct ca_ctx {
   int device = 0;
@@ -32,6 +33,13 @@ struct ca_ctx {
   // reusable per-call scratch
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  // MFMA fragment tables of the mixed path (raster 128)
+  void* mf_b1 = nullptr;
+  void* mf_a2 = nullptr;
+  // HIP events bracketing the main alignment kernel
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  capriv::PruneCache prune_cache;
+  uint64_t next_gen = 1;
 };
 
 struct ca_clipset {
@@ -43,6 +51,8 @@ struct ca_clipset {
   std::vector<int16_t> hN, hw;
   std::vector<int32_t> hnpix, hnpoly;
   int maxN = 0, Lmax = 0;
+  bool mixed_ok = false;  // every clip is 128 x 128 with half-window <= 16
+  uint64_t gen = 0;       // unique per clip set within its context
 };
 
 static thread_local std::string g_create_err;
@@ -149,6 +159,18 @@ ca_status ca_create(const ca_config* cfg, ca_ctx** out) {
     delete ctx;
     return CA_EDEVICE;
   }
+  {
+    std::vector<_Float16> b1(4 * 3 * 64 * 8), a2(8 * 3 * 64 * 8);
+    build_mfma128_tables(b1.data(), a2.data());
+    if (dev_alloc(ctx, &ctx->mf_b1, b1.size() * 2, nullptr) != CA_OK ||
+        dev_alloc(ctx, &ctx->mf_a2, a2.size() * 2, nullptr) != CA_OK ||
+        hipMemcpy(ctx->mf_b1, b1.data(), b1.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->mf_a2, a2.data(), a2.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+      g_create_err = "context set-up failed";
+      return CA_EDEVICE;
+    }
+  }
   *out = ctx;
   return CA_OK;
 }
@@ -160,6 +182,11 @@ ca_status ca_destroy(ca_ctx* ctx) {
   (void)hipFree(ctx->tw32);
   (void)hipFree(ctx->tw64);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->mf_b1) (void)hipFree(ctx->mf_b1);
+  if (ctx->mf_a2) (void)hipFree(ctx->mf_a2);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->prune_cache.dev) (void)hipFree(ctx->prune_cache.dev);
   delete ctx;
   return CA_OK;
 }
@@ -183,6 +210,7 @@ ca_status ca_reset_stats(ca_ctx* ctx) {
 ca_status ca_clips_destroy(ca_clipset* cs) {
   if (!cs) return CA_EINVAL;
   (void)hipSetDevice(cs->ctx->device);
+  if (cs->ctx->prune_cache.gen == cs->gen) cs->ctx->prune_cache.gen = 0;
   for (void* p : cs->owned) (void)hipFree(p);
   cs->ctx->live_clipsets--;
   delete cs;
@@ -229,6 +257,7 @@ ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
 
   ca_clipset* cs = new ca_clipset();
   cs->ctx = ctx;
+  cs->gen = ctx->next_gen++;
   cs->n = n;
   cs->flags = flags | CA_CLIPS_FP64;  // FP64 spectra back the re-decision pass
   cs->hN = hN;
@@ -249,6 +278,9 @@ ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
     cs->maxN = std::max(cs->maxN, N);
     cs->Lmax = std::max(cs->Lmax, axis_len(hw[i], N));
   }
+  cs->mixed_ok = true;
+  for (int64_t i = 0; i < n; ++i)
+    if (hN[i] != 128 || hw[i] > 16) cs->mixed_ok = false;
   void* p;
   ca_status st;
 #define ALLOC(field, type, count)                                              \
@@ -273,6 +305,8 @@ ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
   ALLOC(npix, int32_t, n);
   ALLOC(rowsum, uint16_t, ns);
   ALLOC(colsum, uint16_t, ns);
+  ALLOC(winrow, uint16_t, ns);
+  ALLOC(wincol, uint16_t, ns);
   ALLOC(nruns, int32_t, n);
   ALLOC(npoly, int32_t, n);
   ALLOC(boxes, int16_t, n * MAX_POLY * 4);
@@ -403,6 +437,12 @@ ca_status validate_pairs(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, int64
   return CA_OK;
 }
 
+// Algorithmic bytes of the FP32 per-pair kernel: both FP32 half-spectra and both bit rasters.
+double io_bytes_fp32(const ca_clipset* cs, int64_t n) {
+  const double N = cs->maxN;
+  return (double)n * (2.0 * N * (N / 2 + 1) * 8.0 + 2.0 * N * N / 8.0);
+}
+
 struct FftPlan {
   int CH, LINES;
   size_t smem;
@@ -437,41 +477,71 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, 
   }
   if (path == CA_PATH_FP32 && !cs->d.spec32)
     return fail(ctx, CA_ESTATE, "CA_PATH_FP32 needs a clip set created with CA_CLIPS_FP32");
-  // queue storage: need[n], list[n], len, r1_low[2n], err
+  // queue storage: need[n], list[n], r1_low[2n], counters, candidate groups and shifts
+  const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
   const size_t b_need = align_up(n), b_list = align_up(8 * (size_t)n), b_r1 = align_up(8 * (size_t)n);
+  const size_t b_cnt = 256, b_grp = align_up(sizeof(CandGroup) * (size_t)cap_g), b_sh = align_up(2 * (size_t)cap_s);
   void* sc;
-  ca_status st = scratch(ctx, b_need + b_list + b_r1 + 256, &sc);
+  ca_status st = scratch(ctx, b_need + b_list + b_r1 + b_cnt + b_grp + b_sh, &sc);
   if (st) return st;
   RescoreQueue q;
   char* base = (char*)sc;
   q.need = (uint8_t*)base;
   q.list = (int64_t*)(base + b_need);
   q.r1_low = (float*)(base + b_need + b_list);
-  q.len = (unsigned long long*)(base + b_need + b_list + b_r1);
-  q.peak_err_bits = q.len + 1;
-  HIP_OR_FAIL(ctx, hipMemsetAsync(q.len, 0, 16, s));
+  unsigned long long* counters = (unsigned long long*)(base + b_need + b_list + b_r1);
+  q.len = counters;
+  q.peak_err_bits = counters + 1;
+  CandQueue cq;
+  cq.n_groups = counters + 2;
+  cq.n_shifts = counters + 3;
+  cq.groups = (CandGroup*)(base + b_need + b_list + b_r1 + b_cnt);
+  cq.shifts = (int16_t*)(base + b_need + b_list + b_r1 + b_cnt + b_grp);
+  cq.cap_groups = cap_g;
+  cq.cap_shifts = cap_s;
+  HIP_OR_FAIL(ctx, hipMemsetAsync(counters, 0, 32, s));
   if (path == CA_PATH_FP32) {
     FftPlan pl = plan_fft(cs, 4);
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
     HIP_OR_FAIL(ctx, launch_pcm_fft32(cs->d, io, nullptr, n, MODE_LOW, thr, BAND_FP32, ctx->tw32, pl.CH,
                                       pl.LINES, cs->Lmax, cs->maxN, q, s));
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
   } else {
-    return fail(ctx, CA_EUNSUPPORTED, "mixed-precision path not available in this build");
+    if (!cs->mixed_ok)
+      return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
+    HIP_OR_FAIL(ctx, launch_pcm_mfma128(cs->d, io, thr, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
+                                        nullptr, s));
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
   }
-  unsigned long long h[2] = {0, 0};
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(h, q.len, 16, hipMemcpyDeviceToHost, s));
+  unsigned long long h[4] = {0, 0, 0, 0};
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, 32, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  {
+    float ms = 0.f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->stats.t_main_ms += ms;
+    ctx->stats.n_main_launch += 1;
+    ctx->stats.main_alg_bytes += path == CA_PATH_MIXED ? (double)n * (33280.0 + 2048.0) : io_bytes_fp32(cs, n);
+  }
+  const int64_t n_groups = std::min<int64_t>((int64_t)h[2], cap_g);
+  if (n_groups > 0)
+    HIP_OR_FAIL(ctx, launch_rescore_candidates(cs->d, io, thr, cq, n_groups, ctx->tw64, q.peak_err_bits,
+                                               q.r1_low, s));
   if (h[0] > 0) {
     FftPlan pl = plan_fft(cs, 8);
     HIP_OR_FAIL(ctx, launch_pcm_fft64(cs->d, io, q.list, (int64_t)h[0], MODE_RESCORE, thr, 0.0, ctx->tw64,
                                       pl.CH, pl.LINES, cs->Lmax, cs->maxN, q, s));
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(h, q.len, 16, hipMemcpyDeviceToHost, s));
+  }
+  if (n_groups > 0 || h[0] > 0) {
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, 16, hipMemcpyDeviceToHost, s));
     HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
     double err;
     std::memcpy(&err, &h[1], 8);
     ctx->stats.max_surface_err = std::max(ctx->stats.max_surface_err, err);
   }
   ctx->stats.pairs_aligned += n;
-  ctx->stats.pairs_rescored += (int64_t)h[0];
+  ctx->stats.pairs_rescored += n_groups + (int64_t)h[0];
   return CA_OK;
 }
 
@@ -519,4 +589,44 @@ ca_ctx* ctx_of(const ca_clipset* cs) { return cs->ctx; }
 const std::vector<int16_t>& hN_of(const ca_clipset* cs) { return cs->hN; }
 const std::vector<int32_t>& hnpix_of(const ca_clipset* cs) { return cs->hnpix; }
 int64_t n_of(const ca_clipset* cs) { return cs->n; }
+int maxN_of(const ca_clipset* cs) { return cs->maxN; }
+bool mixed_ok_of(const ca_clipset* cs) { return cs->mixed_ok; }
+uint64_t gen_of(const ca_clipset* cs) { return cs->gen; }
+PruneCache* prune_cache_of(ca_ctx* ctx) { return &ctx->prune_cache; }
 }  // namespace capriv
+
+extern "C" ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs, int32_t path,
+                                int64_t n_pairs, const int32_t* rep, const int32_t* mem, float* surf) {
+  if (!ctx) return CA_EINVAL;
+  if (!cs || cs->ctx != ctx || n_pairs < 0 || (n_pairs > 0 && (!rep || !mem || !surf)))
+    return fail(ctx, CA_EINVAL, "bad arguments");
+  if (path != CA_PATH_MIXED || !cs->mixed_ok)
+    return fail(ctx, CA_EUNSUPPORTED, "surface access is provided for CA_PATH_MIXED on 128 x 128 sets");
+  if (n_pairs == 0) return CA_OK;
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  ca_status st = validate_pairs(ctx, cs, s, n_pairs, rep, mem, false);
+  if (st) return st;
+  const size_t n = (size_t)n_pairs;
+  const size_t b_bits = align_up(n), b_shift = align_up(8 * n), b_cnt = align_up(8 * n), b_sc = align_up(16 * n),
+               b_fl = align_up(4 * n), b_need = align_up(n), b_list = align_up(8 * n), b_r1 = align_up(8 * n);
+  void* sc;
+  st = scratch(ctx, b_bits + b_shift + b_cnt + b_sc + b_fl + b_need + b_list + b_r1 + 512, &sc);
+  if (st) return st;
+  char* p = (char*)sc;
+  PairIO io{n_pairs, rep, mem, (uint8_t*)p, (int16_t*)(p + b_bits), (int32_t*)(p + b_bits + b_shift),
+            (double*)(p + b_bits + b_shift + b_cnt), (uint32_t*)(p + b_bits + b_shift + b_cnt + b_sc)};
+  p += b_bits + b_shift + b_cnt + b_sc + b_fl;
+  RescoreQueue q;
+  q.need = (uint8_t*)p;
+  q.list = (int64_t*)(p + b_need);
+  q.r1_low = (float*)(p + b_need + b_list);
+  q.len = (unsigned long long*)(p + b_need + b_list + b_r1);
+  q.peak_err_bits = q.len + 1;
+  HIP_OR_FAIL(ctx, hipMemsetAsync(q.len, 0, 32, s));
+  CandQueue cq{nullptr, nullptr, q.len + 2, q.len + 3, 0, 0};
+  HIP_OR_FAIL(ctx, launch_pcm_mfma128(cs->d, io, Threshold{1, 1}, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
+                                      surf, s));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  return CA_OK;
+}

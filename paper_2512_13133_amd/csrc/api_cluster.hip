@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "host_internal.h"
 #include "kernels.h"
 
 // Context and clip-set internals shared with api.hip.
@@ -25,6 +26,10 @@ ca_ctx* ctx_of(const ca_clipset* cs);
 const std::vector<int16_t>& hN_of(const ca_clipset* cs);
 const std::vector<int32_t>& hnpix_of(const ca_clipset* cs);
 int64_t n_of(const ca_clipset* cs);
+int maxN_of(const ca_clipset* cs);
+bool mixed_ok_of(const ca_clipset* cs);
+uint64_t gen_of(const ca_clipset* cs);
+PruneCache* prune_cache_of(ca_ctx* ctx);
 }  // namespace capriv
 
 using namespace ca;
@@ -80,9 +85,84 @@ void build_ranges(const ca_clipset* cs, const ca_constraint* con, std::vector<in
 
 }  // namespace
 
+// Specialised path (all clips 128 x 128, half-windows <= 16, cosine): the
+// bounds pass runs once per (clip set, threshold); its bitmask and counts are
+// cached on the context, so sizing and writing calls share it.
+static ca_status prune128_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
+                                 int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
+  PruneCache* pc = prune_cache_of(ctx);
+  const bool hit = pc->gen == gen_of(cs) && pc->kind == con->kind && pc->p == con->thr_num && pc->q == con->thr_den;
+  std::vector<int32_t> order, hi;
+  int64_t screened = 0;
+  build_ranges(cs, con, order, hi, screened);
+  const int64_t na = (int64_t)order.size();
+  std::vector<int64_t> range_off(na);
+  int64_t bits = 0;
+  for (int64_t a = 0; a < na; ++a) {
+    range_off[a] = bits;
+    bits += hi[a] - a - 1;
+  }
+  const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na), b_mask = aup(4 * (size_t)(bits / 32 + 1));
+  const size_t need = 2 * b_ord + 2 * b_rng + b_mask;
+  char* base;
+  if (!hit) {
+    if (pc->bytes < need) {
+      free_ctx(ctx, pc->dev, pc->bytes);
+      pc->dev = nullptr;
+      pc->bytes = 0;
+      pc->gen = 0;
+      ca_status st = alloc_ctx(ctx, &pc->dev, need);
+      if (st) return st;
+      pc->bytes = need;
+    }
+    base = (char*)pc->dev;
+    int32_t* d_order = (int32_t*)base;
+    int32_t* d_hi = (int32_t*)(base + b_ord);
+    int64_t* d_roff = (int64_t*)(base + 2 * b_ord);
+    int64_t* d_cnt = (int64_t*)(base + 2 * b_ord + b_rng);
+    uint32_t* d_mask = (uint32_t*)(base + 2 * b_ord + 2 * b_rng);
+    HIP_TRY(ctx, hipMemcpyAsync(d_order, order.data(), 4 * na, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(d_hi, hi.data(), 4 * na, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(d_roff, range_off.data(), 8 * na, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
+    PruneArgs pa{d_order, d_hi, na, d_cnt, nullptr, nullptr, nullptr};
+    HIP_TRY(ctx, launch_prune128(dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff, d_mask, false, s));
+    pc->counts.assign(na, 0);
+    HIP_TRY(ctx, hipMemcpyAsync(pc->counts.data(), d_cnt, 8 * na, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    pc->total = 0;
+    for (int64_t a = 0; a < na; ++a) pc->total += pc->counts[a];
+    pc->gen = gen_of(cs);
+    pc->kind = con->kind;
+    pc->p = con->thr_num;
+    pc->q = con->thr_den;
+    pc->na = na;
+    stats_of(ctx)->pairs_screened += screened;
+    stats_of(ctx)->pairs_survived += pc->total;
+  }
+  base = (char*)pc->dev;
+  *n_out = pc->total;
+  if (!rep) return CA_OK;
+  if (pc->total > cap) return fail_ctx(ctx, CA_ETRUNC, "candidate buffer too small");
+  std::vector<int64_t> off(na);
+  int64_t acc = 0;
+  for (int64_t a = 0; a < na; ++a) {
+    off[a] = acc;
+    acc += pc->counts[a];
+  }
+  int64_t* d_off = (int64_t*)(base + 2 * b_ord + b_rng);  // reuses the count slots
+  HIP_TRY(ctx, hipMemcpyAsync(d_off, off.data(), 8 * na, hipMemcpyHostToDevice, s));
+  PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), na, nullptr, d_off, rep, mem};
+  HIP_TRY(ctx, launch_prune128(dev_of(cs), pa, Threshold{con->thr_num, con->thr_den},
+                               (int64_t*)(base + 2 * b_ord), (uint32_t*)(base + 2 * b_ord + 2 * b_rng), true, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return CA_OK;
+}
+
 // Device candidate generation into caller buffers (or sizing only when rep is null).
 static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
                               int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
+  if (con->kind == CA_COSINE && mixed_ok_of(cs)) return prune128_device(ctx, s, cs, con, cap, rep, mem, n_out);
   std::vector<int32_t> order, hi;
   int64_t screened = 0;
   build_ranges(cs, con, order, hi, screened);
@@ -100,7 +180,7 @@ static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, 
   HIP_TRY(ctx, hipMemcpyAsync(d_hi, hi.data(), 4 * na, hipMemcpyHostToDevice, s));
   PruneArgs pa{d_order, d_hi, na, d_cnt, nullptr, nullptr, nullptr};
   const Threshold thr{con->thr_num, con->thr_den};
-  if (con->kind == CA_COSINE) HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, s));
+  if (con->kind == CA_COSINE) HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, maxN_of(cs), s));
   else HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, thr, s));
   std::vector<int64_t> cnt(na), off(na);
   HIP_TRY(ctx, hipMemcpyAsync(cnt.data(), d_cnt, 8 * na, hipMemcpyDeviceToHost, s));
@@ -119,7 +199,7 @@ static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, 
   pa.offs = d_off;
   pa.out_rep = rep;
   pa.out_mem = mem;
-  if (con->kind == CA_COSINE) HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, s));
+  if (con->kind == CA_COSINE) HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, maxN_of(cs), s));
   else HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, thr, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return CA_OK;

@@ -1,7 +1,7 @@
 // Edge track (paper Sec. 2.2.2 edge movement constraint; Sec. 3.2.2, Eq. 6).
 //
-// One 64-lane wavefront per unordered pair, both directions in turn.  For a
-// direction (member m against representative r):
+// One 64-lane wavefront takes a batch of pairs.  For a direction (member m
+// against representative r):
 //   1. T0 = per-axis Min-Max midpoint of the two global bounding boxes;
 //   2. the overlap relation member-polygon x rep-polygon at T0, from the row
 //      runs of both clips (linear shift, zero fill): lanes sweep rep rows,
@@ -72,12 +72,11 @@ __device__ bool correspondence_ok(const unsigned long long* relM, const unsigned
   return ok;
 }
 
-__global__ void __launch_bounds__(64) edge_kernel(ClipsDev cs, PairIO io, Threshold thr) {
-  __shared__ unsigned long long relM[MAX_POLY], relR[MAX_POLY];
-  __shared__ unsigned long long relM0[MAX_POLY], relR0[MAX_POLY];
-  __shared__ int sflag;
-  __shared__ int red[4][64];
-  const int64_t k = blockIdx.x;
+// LDS path: any polygon count up to the cap, relation masks in LDS.
+__device__ void edge_pair_lds(const ClipsDev& cs, const PairIO& io, Threshold thr, int64_t k,
+                              unsigned long long* relM, unsigned long long* relR, unsigned long long* relM0,
+                              unsigned long long* relR0, int* sflag_p, int (*red)[64]) {
+  int& sflag = *sflag_p;
   const int lane = threadIdx.x;
   const int j = io.rep[k], i = io.mem[k];
   const int N = cs.N[i];
@@ -86,6 +85,7 @@ __global__ void __launch_bounds__(64) edge_kernel(ClipsDev cs, PairIO io, Thresh
     const int m = d == 0 ? i : j, r = d == 0 ? j : i;
     const int w = cs.w[m];
     const int Pm = cs.npoly[m], Pr = cs.npoly[r];
+    __syncthreads();
     const uint32_t nomatch = d == 0 ? CA_FLAG_NO_MATCH_FWD : CA_FLAG_NO_MATCH_REV;
     const uint32_t recheck = d == 0 ? CA_FLAG_RECHECK_FWD : CA_FLAG_RECHECK_REV;
     if (Pm <= 0 || Pr <= 0) {
@@ -164,14 +164,226 @@ __global__ void __launch_bounds__(64) edge_kernel(ClipsDev cs, PairIO io, Thresh
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register path for polygon counts <= 8 on both sides: the relation is one
+// 64-bit word (bit 8 p + q: member polygon p overlaps rep polygon q), built by
+// each lane over its rows and OR-reduced across the wave with shuffles; no LDS
+// and no barriers.  Larger counts take the LDS path above.
+
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off);
+  return x;
+}
+
+__device__ unsigned long long relation8(const ClipsDev& cs, int m, int r, int N, int dy, int dx, int lane) {
+  const uint16_t* rp_m = cs.run_rowptr + cs.rowptr_off[m];
+  const uint16_t* rp_r = cs.run_rowptr + cs.rowptr_off[r];
+  const uint32_t* ru_m = cs.runs + cs.run_off[m];
+  const uint32_t* ru_r = cs.runs + cs.run_off[r];
+  const int y0 = max(0, -dy), y1 = min(N, N - dy);
+  unsigned long long rel = 0ull;
+  for (int y = y0 + lane; y < y1; y += 64) {
+    const int ym = y + dy;
+    int a = rp_r[y], ae = rp_r[y + 1];
+    int b = rp_m[ym], be = rp_m[ym + 1];
+    while (a < ae && b < be) {
+      const uint32_t ra = ru_r[a], rb = ru_m[b];
+      const int a0 = ra & 511, a1 = (ra >> 9) & 511, qa = (ra >> 18) & 63;
+      const int b0 = (int)(rb & 511) - dx, b1 = (int)((rb >> 9) & 511) - dx, pb = (rb >> 18) & 63;
+      if (max(a0, b0) < min(a1, b1)) rel |= 1ull << (8 * pb + qa);
+      if (a1 < b1) ++a;
+      else ++b;
+    }
+  }
+  return wave_or64(rel);
+}
+
+// Exactly-one rule on an 8 x 8 relation word (uniform).
+__device__ __forceinline__ bool corr8_ok(unsigned long long rel, int Pm, int Pr) {
+  if (Pm <= Pr)
+    for (int p = 0; p < Pm; ++p)
+      if (__popcll((rel >> (8 * p)) & 0xffull) != 1) return false;
+  if (Pr <= Pm)
+    for (int q = 0; q < Pr; ++q)
+      if (__popcll(rel & (0x0101010101010101ull << q)) != 1) return false;
+  return true;
+}
+
+// One direction (member m against rep r) on the register path.
+__device__ void edge_dir8(const ClipsDev& cs, int m, int r, int N, int Pm, int Pr, int lane, int& sy, int& sx,
+                          int& E, bool& matched, bool& ok) {
+  const int w = cs.w[m];
+  const int16_t* gm = cs.gbox + 4 * m;
+  const int16_t* gr = cs.gbox + 4 * r;
+  int s0x, s0y, eu;
+  {
+    const int a = gm[0] - gr[0], b = gm[1] - gr[1];
+    minmax_axis(min(a, b), max(a, b), w, s0x, eu);
+    const int c = gm[2] - gr[2], e = gm[3] - gr[3];
+    minmax_axis(min(c, e), max(c, e), w, s0y, eu);
+  }
+  const unsigned long long rel0 = relation8(cs, m, r, N, s0y, s0x, lane);
+  if (!corr8_ok(rel0, Pm, Pr)) {
+    sy = s0y; sx = s0x; E = -1; matched = false; ok = false;
+    return;
+  }
+  const int16_t* bm = cs.boxes + (int64_t)m * MAX_POLY * 4;
+  const int16_t* br = cs.boxes + (int64_t)r * MAX_POLY * 4;
+  int xlo = 1 << 20, xhi = -(1 << 20), ylo = 1 << 20, yhi = -(1 << 20);
+  const bool from_member = Pm <= Pr;
+  const int P = from_member ? Pm : Pr;
+  for (int t = 0; t < P; ++t) {
+    int p, q;
+    if (from_member) { p = t; q = __ffsll((unsigned long long)((rel0 >> (8 * t)) & 0xffull)) - 1; }
+    else {
+      q = t;
+      const unsigned long long col = rel0 & (0x0101010101010101ull << t);
+      p = (__ffsll(col) - 1) >> 3;
+    }
+    const int16_t* a = bm + 4 * p;
+    const int16_t* b = br + 4 * q;
+    const int d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2], d3 = a[3] - b[3];
+    xlo = min(xlo, min(d0, d1)); xhi = max(xhi, max(d0, d1));
+    ylo = min(ylo, min(d2, d3)); yhi = max(yhi, max(d2, d3));
+  }
+  int ex, ey;
+  minmax_axis(xlo, xhi, w, sx, ex);
+  minmax_axis(ylo, yhi, w, sy, ey);
+  E = max(ex, ey);
+  matched = true;
+  const unsigned long long rel1 = relation8(cs, m, r, N, sy, sx, lane);
+  bool same = corr8_ok(rel1, Pm, Pr);
+  if (same && Pm <= Pr)
+    for (int p = 0; p < Pm; ++p) same = same && (((rel1 ^ rel0) >> (8 * p)) & 0xffull) == 0;
+  if (same && Pr <= Pm)
+    for (int q = 0; q < Pr; ++q) same = same && ((rel1 ^ rel0) & (0x0101010101010101ull << q)) == 0;
+  ok = same;
+}
+
+// 64 bits of a bit row starting at bit `start`, zero outside [0, N) (linear shift).
+__device__ __forceinline__ uint64_t row_bits_linear(const uint64_t* row, int wpr, int start) {
+  const int N = wpr * 64;
+  if (start <= -64 || start >= N) return 0ull;
+  if (start < 0) return row[0] << (-start);
+  const int ws = start >> 6, o = start & 63;
+  const uint64_t lo = row[ws];
+  if (o == 0) return lo;
+  const uint64_t hi = (ws + 1 < wpr) ? row[ws + 1] : 0ull;
+  return (lo >> o) | (hi << (64 - o));
+}
+
+// Does member m shifted by (dy, dx) overlap representative r (linear shift)?
+// Wave-wide.  Rows are first tried with a pigeonhole bound on the row sums:
+// r_rep[y] + r_mem[y + dy] > N + |dx| forces a common pixel; only if no row
+// proves it are the bit rows intersected.
+__device__ bool overlaps_any(const ClipsDev& cs, int m, int r, int N, int dy, int dx, int lane) {
+  const int y0 = max(0, -dy), y1 = min(N, N - dy);
+  if (y0 >= y1 || dx >= N || dx <= -N) return false;
+  const uint16_t* rs_m = cs.rowsum + cs.sig_off[m];
+  const uint16_t* rs_r = cs.rowsum + cs.sig_off[r];
+  const int lim = N + abs(dx);
+  bool hit = false;
+  for (int y = y0 + lane; y < y1; y += 64) hit = hit || ((int)rs_r[y] + (int)rs_m[y + dy] > lim);
+  if (__ballot(hit)) return true;
+  const int wpr = N >> 6;
+  const uint64_t* br = cs.bits + cs.bits_off[r];
+  const uint64_t* bm = cs.bits + cs.bits_off[m];
+  for (int y = y0 + lane; y < y1; y += 64) {
+    const uint64_t* rr = br + y * wpr;
+    const uint64_t* mr = bm + (y + dy) * wpr;
+    for (int k = 0; k < wpr && !hit; ++k) hit = (rr[k] & row_bits_linear(mr, wpr, 64 * k + dx)) != 0ull;
+  }
+  return __ballot(hit) != 0ull;
+}
+
+// One direction for single-polygon clips: each polygon's box is the global
+// box, so the Min-Max shift of the matched pair equals T0 and one overlap test
+// decides both the correspondence and its re-check.
+__device__ void edge_dir11(const ClipsDev& cs, int m, int r, int N, int lane, int& sy, int& sx, int& E,
+                           bool& matched, bool& ok) {
+  const int w = cs.w[m];
+  const int16_t* gm = cs.gbox + 4 * m;
+  const int16_t* gr = cs.gbox + 4 * r;
+  int ex, ey;
+  {
+    const int a = gm[0] - gr[0], b = gm[1] - gr[1];
+    minmax_axis(min(a, b), max(a, b), w, sx, ex);
+    const int c = gm[2] - gr[2], e = gm[3] - gr[3];
+    minmax_axis(min(c, e), max(c, e), w, sy, ey);
+  }
+  matched = overlaps_any(cs, m, r, N, sy, sx, lane);
+  ok = matched;
+  E = matched ? max(ex, ey) : -1;
+}
+
+constexpr int EDGE_PAIRS_PER_GROUP = 16;
+
+__global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, Threshold thr, int64_t block0) {
+  __shared__ unsigned long long relM[MAX_POLY], relR[MAX_POLY];
+  __shared__ unsigned long long relM0[MAX_POLY], relR0[MAX_POLY];
+  __shared__ int sflag;
+  __shared__ int red[4][64];
+  const int lane = threadIdx.x;
+  const int64_t k0 = (block0 + (int64_t)blockIdx.x) * EDGE_PAIRS_PER_GROUP;
+  const int64_t k1 = min(k0 + EDGE_PAIRS_PER_GROUP, io.n_pairs);
+  for (int64_t k = k0; k < k1; ++k) {
+    const int j = io.rep[k], i = io.mem[k];
+    const int N = cs.N[i];
+    const int Pi = cs.npoly[i], Pj = cs.npoly[j];
+    if (Pi > 8 || Pj > 8) {
+      edge_pair_lds(cs, io, thr, k, relM, relR, relM0, relR0, &sflag, red);
+      continue;
+    }
+    uint32_t fl = 0;
+    int sy[2], sx[2], E[2];
+    bool matched[2], ok[2];
+    const bool mirror = cs.w[i] == cs.w[j];
+    for (int d = 0; d < (mirror ? 1 : 2); ++d) {
+      const int m = d == 0 ? i : j, r = d == 0 ? j : i;
+      const int Pm = d == 0 ? Pi : Pj, Pr = d == 0 ? Pj : Pi;
+      if (Pm <= 0 || Pr <= 0) {
+        sy[d] = 0; sx[d] = 0; E[d] = -1; matched[d] = false; ok[d] = false;
+        fl |= CA_FLAG_EMPTY;
+        continue;
+      }
+      if (Pm == 1 && Pr == 1) edge_dir11(cs, m, r, N, lane, sy[d], sx[d], E[d], matched[d], ok[d]);
+      else edge_dir8(cs, m, r, N, Pm, Pr, lane, sy[d], sx[d], E[d], matched[d], ok[d]);
+    }
+    if (mirror) {  // equal windows: the reverse direction is the exact mirror
+      sy[1] = -sy[0]; sx[1] = -sx[0]; E[1] = E[0]; matched[1] = matched[0]; ok[1] = ok[0];
+    }
+    if (lane == 0) {
+      uint8_t bits = 0;
+      for (int d = 0; d < 2; ++d) {
+        io.shift[k * 4 + 2 * d] = (int16_t)sy[d];
+        io.shift[k * 4 + 2 * d + 1] = (int16_t)sx[d];
+        io.count[k * 2 + d] = E[d];
+        io.score[k * 2 + d] = 0.0;
+        if (!matched[d]) fl |= d == 0 ? CA_FLAG_NO_MATCH_FWD : CA_FLAG_NO_MATCH_REV;
+        else if (!ok[d]) fl |= d == 0 ? CA_FLAG_RECHECK_FWD : CA_FLAG_RECHECK_REV;
+        if (ok[d] && (int64_t)E[d] <= thr.p) bits |= (uint8_t)(1u << d);
+      }
+      io.bits[k] = bits;
+      io.flags[k] = fl;
+    }
+  }
+}
+
 }  // namespace ca
 
 namespace ca {
 
 hipError_t launch_edge(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s) {
   if (io.n_pairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(edge_kernel, dim3((unsigned)io.n_pairs), dim3(64), 0, s, cs, io, thr);
-  return hipGetLastError();
+  const int64_t groups = (io.n_pairs + EDGE_PAIRS_PER_GROUP - 1) / EDGE_PAIRS_PER_GROUP;
+  for (int64_t b0 = 0; b0 < groups; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, groups - b0);
+    hipLaunchKernelGGL(edge_batch_kernel, dim3(nb), dim3(64), 0, s, cs, io, thr, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ca

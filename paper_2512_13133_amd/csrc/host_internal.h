@@ -1,0 +1,21 @@
+// Host-side structures shared by the runtime translation units.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+namespace capriv {
+
+// Result of the last cosine bounds pass of ca_prune on 128 x 128 sets, kept
+// on the context so that a sizing call and the following writing call share it.
+struct PruneCache {
+  uint64_t gen = 0;              // clip-set generation (0 = empty)
+  int64_t kind = 0, p = 0, q = 0;
+  int64_t na = 0, total = 0;
+  void* dev = nullptr;           // order | hi | range_off | counts/offsets | mask
+  size_t bytes = 0;
+  std::vector<int64_t> counts;
+};
+
+}  // namespace capriv

@@ -30,6 +30,8 @@ struct ClipsDev {
   const int64_t* sig_off;    // [n] element offset into rowsum/colsum (N each)
   uint16_t* rowsum;
   uint16_t* colsum;
+  uint16_t* winrow;          // sum of rowsum over rows t .. t+7 (mod N), N each
+  uint16_t* wincol;          // same for columns
   int32_t* nruns;            // [n] total runs
   int32_t* npoly;            // [n] polygon count, -1 over the cap
   int16_t* boxes;            // [n][MAX_POLY][4] (x0, x1, y0, y1)
@@ -71,6 +73,23 @@ struct RescoreQueue {
   unsigned long long* len;            // number of queued pairs
   float* r1_low;                      // [n_pairs][2] low-precision normalised peak value
   unsigned long long* peak_err_bits;  // max |r1_low - r1_fp64| as double bits
+};
+
+// Near-tie candidates of a queued direction: the window shifts whose
+// low-precision value lies within the band of the maximum.
+constexpr int MAX_CAND = 16;
+struct CandGroup {
+  int64_t pair;    // pair id
+  int64_t offset;  // first candidate in CandQueue::shifts
+  int32_t dir;     // direction 0 or 1
+  int32_t count;   // candidates (0: group unused)
+};
+struct CandQueue {
+  CandGroup* groups;
+  int16_t* shifts;                  // (dy << 8) | (dx & 0xff)
+  unsigned long long* n_groups;
+  unsigned long long* n_shifts;
+  int64_t cap_groups, cap_shifts;
 };
 
 // Candidate generation: anchors, their partner ranges and the output list.

@@ -23,10 +23,11 @@ __device__ __forceinline__ uint64_t span_mask(int a, int b) {
 
 __global__ void __launch_bounds__(256) pack_kernel(const int64_t* __restrict__ rect_ptr,
                                                    const int32_t* __restrict__ rects,
-                                                   ClipsDev cs) {
+                                                   ClipsDev cs, int64_t block0) {
   __shared__ uint64_t sb[256 * 4];
   __shared__ int red[256];
-  const int i = blockIdx.x;
+  __shared__ int srow[256], scol[256];
+  const int64_t i = block0 + (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
   const int N = cs.N[i];
   const int wpr = N / 64;
@@ -64,12 +65,26 @@ __global__ void __launch_bounds__(256) pack_kernel(const int64_t* __restrict__ r
       prev = (int)(wv >> 63);
     }
     rs[tid] = (uint16_t)c;
+    srow[tid] = c;
     cnt = c;
     // column sum of column tid
     int cc = 0;
     const int kk = tid >> 6, bb = tid & 63;
     for (int y = 0; y < N; ++y) cc += (int)((sb[y * wpr + kk] >> bb) & 1ull);
     cls[tid] = (uint16_t)cc;
+    scol[tid] = cc;
+  }
+  // sliding 8-row / 8-column sums for the coarse pruning bound
+  __syncthreads();
+  if (tid < N) {
+    int wr = 0, wc = 0;
+    for (int t = 0; t < 8; ++t) {
+      const int y = (tid + t) & (N - 1);
+      wr += srow[y];
+      wc += scol[y];
+    }
+    cs.winrow[cs.sig_off[i] + tid] = (uint16_t)wr;
+    cs.wincol[cs.sig_off[i] + tid] = (uint16_t)wc;
   }
   red[tid] = cnt;
   __syncthreads();
@@ -96,14 +111,14 @@ __device__ __forceinline__ int uf_find(int16_t* parent, int x) {
   return x;
 }
 
-__global__ void __launch_bounds__(256) label_kernel(ClipsDev cs) {
+__global__ void __launch_bounds__(256) label_kernel(ClipsDev cs, int64_t block0) {
   __shared__ uint32_t srun[MAX_RUNS];   // x0 | x1 << 9
   __shared__ int16_t parent[MAX_RUNS];
   __shared__ int16_t slabel[MAX_RUNS];
   __shared__ uint16_t rowp[257];
   __shared__ int16_t box[MAX_POLY][4];
   __shared__ int s_npoly;
-  const int i = blockIdx.x;
+  const int64_t i = block0 + (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
   const int N = cs.N[i];
   const int wpr = N / 64;
@@ -244,14 +259,24 @@ __global__ void validate_pairs_kernel(ClipsDev cs, int64_t n_pairs, const int32_
 hipError_t launch_pack(const int64_t* rect_ptr, const int32_t* rects, const ClipsDev& cs, int64_t n,
                        hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)n), dim3(256), 0, s, rect_ptr, rects, cs);
-  return hipGetLastError();
+  for (int64_t b0 = 0; b0 < n; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, n - b0);
+    hipLaunchKernelGGL(pack_kernel, dim3(nb), dim3(256), 0, s, rect_ptr, rects, cs, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_label(const ClipsDev& cs, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(label_kernel, dim3((unsigned)n), dim3(256), 0, s, cs);
-  return hipGetLastError();
+  for (int64_t b0 = 0; b0 < n; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, n - b0);
+    hipLaunchKernelGGL(label_kernel, dim3(nb), dim3(256), 0, s, cs, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_validate(const ClipsDev& cs, int64_t n_pairs, const int32_t* rep, const int32_t* mem,

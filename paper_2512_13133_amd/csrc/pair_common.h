@@ -104,4 +104,19 @@ __device__ __forceinline__ void write_direction(const PairIO& io, int64_t k, int
   io.bits[k] = bit ? (uint8_t)(io.bits[k] | m) : (uint8_t)(io.bits[k] & ~m);
 }
 
+// As write_direction, but the cover-bit byte is updated with a 32-bit atomic on
+// its aligned word (the word lies in the same page as the byte).
+__device__ __forceinline__ void write_direction_atomic(const PairIO& io, int64_t k, int d, int dy, int dx,
+                                                       int c, double score, bool bit) {
+  io.shift[k * 4 + d * 2 + 0] = (int16_t)dy;
+  io.shift[k * 4 + d * 2 + 1] = (int16_t)dx;
+  io.count[k * 2 + d] = c;
+  io.score[k * 2 + d] = score;
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(io.bits + k);
+  unsigned int* word = reinterpret_cast<unsigned int*>(addr & ~(uintptr_t)3);
+  const unsigned int m = (1u << d) << (8 * (addr & 3));
+  if (bit) atomicOr(word, m);
+  else atomicAnd(word, ~m);
+}
+
 }  // namespace ca

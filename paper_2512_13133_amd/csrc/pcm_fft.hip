@@ -26,7 +26,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 pcm_fft_kernel(ClipsDev cs, PairIO io, const int64_t* __restrict__ list, int mode, Threshold thr,
                double band, const typename cplx<T>::type* __restrict__ tw256, int CH, int LINES,
-               int Lmax, RescoreQueue q) {
+               int Lmax, RescoreQueue q, int64_t block0) {
   using C = typename cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int ired[256];
@@ -35,7 +35,8 @@ pcm_fft_kernel(ClipsDev cs, PairIO io, const int64_t* __restrict__ list, int mod
   __shared__ int idxred[256];
   __shared__ int candf[256];
 
-  const int64_t k = list ? list[blockIdx.x] : (int64_t)blockIdx.x;
+  const int64_t b = block0 + (int64_t)blockIdx.x;
+  const int64_t k = list ? list[b] : b;
   const int tid = threadIdx.x;
   const int j = io.rep[k], i = io.mem[k];
   const int N = cs.N[i];
@@ -300,9 +301,14 @@ static hipError_t launch_pcm_fft_t(const ClipsDev& cs, const PairIO& io, const i
   hipError_t e = hipFuncSetAttribute((const void*)pcm_fft_kernel<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pcm_fft_kernel<T>, dim3((unsigned)n_blocks), dim3(256), smem, s, cs, io, list, mode,
-                     thr, band, tw256, CH, LINES, Lmax, q);
-  return hipGetLastError();
+  for (int64_t b0 = 0; b0 < n_blocks; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, n_blocks - b0);
+    hipLaunchKernelGGL(pcm_fft_kernel<T>, dim3(nb), dim3(256), smem, s, cs, io, list, mode, thr, band, tw256,
+                       CH, LINES, Lmax, q, b0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_pcm_fft32(const ClipsDev& cs, const PairIO& io, const int64_t* list, int64_t n_blocks,

@@ -1,0 +1,399 @@
+// Batched mixed-precision phase-correlation surface on MFMA, raster 128,
+// half-windows up to 16 (paper Sec. 3.2.1(1), Eqs. 3-5).
+//
+// For a pair (member i, representative j) the window surface is
+//   K r(dy, dx) = Re sum_u sum_{v<=64} h(v) R(u, v) e^{2 pi i (u dy + v dx)/128},
+// R = W_i conj(W_j), h = 1 at v = 0, 64 and 2 elsewhere.  Restricted to the
+// 33 x 33 window it is two dense contractions, run on 16x16x32 FP16 MFMA with
+// FP32 accumulation:
+//   stage 1  T(u, dx)  = sum_{v<64} R(u, v) h(v) e^{2 pi i v dx/128}   (+ the v = 64
+//            term on the VALU): rows u, K = (v, re/im) = 128, columns dx; the
+//            real part uses the operand R, the imaginary part the operand -i R
+//            against the same twiddles (Im T = Re(-i T));
+//   stage 2  K r(dy, dx) = sum_u Tr(u, dx) cos(2 pi u dy/128) - Ti(u, dx) sin(...):
+//            rows dy, K = (u, re/im) = 256, columns dx.
+// R is formed with packed FP16 complex multiplies directly in the stage-1 A
+// operand layout; each 16-row stage-1 result block converts in registers into
+// the matching stage-2 B operand, so the intermediate never leaves the wave.
+//
+// Batching: a workgroup owns TILE consecutive pairs.  Consecutive pairs with
+// the same representative form a run; the run's representative spectrum and
+// bits are staged once in LDS and the four waves take its members.  The
+// stage-1 twiddles are held in registers through a pair's contractions, the
+// stage-2 twiddles in LDS.
+//
+// Each direction's peak is taken over its window with a wavefront shuffle
+// reduction that keeps the maximum and the runner-up.  A peak whose gap is
+// below `band` (normalised, with the conservative K_hi = N^2 - max(zero bins))
+// is queued for the FP64 re-decision together with its candidate shifts (all
+// within the band of the maximum); the others are final here, with the
+// overlap count c, the FP64 score and the exact-rational bit.
+#include "kernels.h"
+#include "pair_common.h"
+
+namespace ca {
+
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+constexpr int MF_N = 128;
+constexpr int MF_TILE = 64;
+constexpr int MF_ROW_H2 = 68;           // LDS row stride of the staged spectrum (half2), padded
+constexpr int MF_SPEC_H2 = MF_N * MF_ROW_H2 + MF_N;
+
+__device__ __forceinline__ h2_t as_h2(uint32_t x) { return __builtin_bit_cast(h2_t, x); }
+__device__ __forceinline__ uint32_t as_u32(h2_t x) { return __builtin_bit_cast(uint32_t, x); }
+
+// -i z on a packed FP16 (re, im) pair.
+__device__ __forceinline__ h2_t mul_neg_i(h2_t z) { return h2_t{z.y, -z.x}; }
+
+// m * conj(r) on packed FP16 (re, im) pairs.
+__device__ __forceinline__ h2_t cmulc_h2(h2_t m, h2_t r) {
+  const h2_t rr = {r.x, r.x};
+  const h2_t ri = {r.y, -r.y};
+  const h2_t ms = {m.y, m.x};
+  return m * rr + ms * ri;
+}
+
+// Top value, its position and the runner-up over the wave (positions break ties low).
+__device__ __forceinline__ void wave_top2(float& v1, int& i1, float& v2) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float o1 = __shfl_xor(v1, off);
+    const int oi = __shfl_xor(i1, off);
+    const float o2 = __shfl_xor(v2, off);
+    if (o1 > v1 || (o1 == v1 && oi < i1)) {
+      v2 = fmaxf(v1, o2);
+      v1 = o1;
+      i1 = oi;
+    } else {
+      v2 = fmaxf(v2, o1);
+    }
+  }
+}
+
+// Overlap count c(s) = sum_x rep(x) mem((x + s) mod 128) on one wave.
+__device__ __forceinline__ int wave_overlap128(const uint64_t* rep, const uint64_t* mem, int dy, int dx) {
+  int c = row_overlap(rep, mem, MF_N, threadIdx.x & 63, dy, dx) +
+          row_overlap(rep, mem, MF_N, (threadIdx.x & 63) + 64, dy, dx);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  return c;
+}
+
+// Queue an undecided direction: every window shift whose low-precision value
+// is at least `cutv` becomes a candidate of the FP64 re-decision; when there
+// are more than MAX_CAND of them (or no room) the direction falls back to the
+// full FP64 surface.  Wave-wide; kept out of line to spare the caller's registers.
+__device__ __noinline__ void queue_candidates(const float* sw, int d, int wd, float cutv, float r1, int64_t k,
+                                              int lane, RescoreQueue q, CandQueue cq) {
+  int m = 0;
+  for (int t0 = 0; t0 < 33 * 33; t0 += 64) {
+    const int t = t0 + lane;
+    bool ok = false;
+    if (t < 33 * 33) {
+      const int ty = t / 33 - 16, tx = t - (t / 33) * 33 - 16;
+      ok = ty >= -wd && ty <= wd && tx >= -wd && tx <= wd && sw[d == 0 ? t : 33 * 33 - 1 - t] >= cutv;
+    }
+    m += __popcll(__ballot(ok));
+  }
+  unsigned long long slot = 0, off = 0;
+  if (lane == 0) {
+    slot = atomicAdd(cq.n_groups, 1ull);
+    off = m <= MAX_CAND ? atomicAdd(cq.n_shifts, (unsigned long long)m) : 0ull;
+  }
+  slot = __shfl(slot, 0);
+  off = __shfl(off, 0);
+  const bool fits = m <= MAX_CAND && (int64_t)slot < cq.cap_groups && (int64_t)(off + m) <= cq.cap_shifts;
+  if (fits) {
+    int written = 0;
+    for (int t0 = 0; t0 < 33 * 33; t0 += 64) {
+      const int t = t0 + lane;
+      bool ok = false;
+      int ty = 0, tx = 0;
+      if (t < 33 * 33) {
+        ty = t / 33 - 16;
+        tx = t - (t / 33) * 33 - 16;
+        ok = ty >= -wd && ty <= wd && tx >= -wd && tx <= wd && sw[d == 0 ? t : 33 * 33 - 1 - t] >= cutv;
+      }
+      const unsigned long long bm = __ballot(ok);
+      if (ok) {
+        const int idx = written + __popcll(bm & ((1ull << lane) - 1ull));
+        cq.shifts[off + idx] = (int16_t)((ty << 8) | (tx & 0xff));
+      }
+      written += __popcll(bm);
+    }
+  }
+  if (lane == 0) {
+    if ((int64_t)slot < cq.cap_groups) {
+      CandGroup gr;
+      gr.pair = k;
+      gr.offset = (int64_t)off;
+      gr.dir = d;
+      gr.count = fits ? m : 0;
+      cq.groups[slot] = gr;
+    }
+    q.r1_low[k * 2 + d] = r1;
+    if (!fits) {
+      const uint8_t old = q.need[k];
+      q.need[k] = (uint8_t)(old | (1u << d));
+      if (old == 0) {
+        const unsigned long long qs = atomicAdd(q.len, 1ull);
+        q.list[qs] = k;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256, 2)
+pcm_mfma128_kernel(ClipsDev cs, PairIO io, Threshold thr, float band, RescoreQueue q, CandQueue cq,
+                   const h8_t* b1frag, const h8_t* a2frag, float* surf_out, int64_t block0) {
+  __shared__ __align__(16) uint32_t s_spec[MF_SPEC_H2];   // representative W (half2)
+  __shared__ __align__(16) h8_t s_a2[8 * 3 * 64];          // stage-2 twiddles
+  __shared__ uint64_t s_bits[MF_N * 2];                   // representative bits
+  __shared__ int s_rep[MF_TILE];
+  __shared__ int s_seg_end;
+  __shared__ float s_surf[4][33 * 33];                    // per-wave window surface
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 4;      // k-group of the lane
+  const int col = lane & 15;    // row (A) / column (B, C) of the lane in a 16x16 block
+  const int64_t base = (block0 + (int64_t)blockIdx.x) * MF_TILE;
+  const int cnt = (int)min((int64_t)MF_TILE, io.n_pairs - base);
+
+  for (int t = tid; t < 8 * 3 * 64; t += 256) s_a2[t] = a2frag[t];
+  if (tid < cnt) s_rep[tid] = io.rep[base + tid];
+  __syncthreads();
+
+  int seg = 0;
+  while (seg < cnt) {
+    if (tid == 0) {
+      int e = seg + 1;
+      while (e < cnt && s_rep[e] == s_rep[seg]) ++e;
+      s_seg_end = e;
+    }
+    const int j = s_rep[seg];
+    // stage the representative's spectrum (rows padded) and bits
+    {
+      const uint4* src = reinterpret_cast<const uint4*>(cs.spec16 + cs.spec_off[j]);
+      for (int t = tid; t < MF_N * 16; t += 256) {  // 16 x 16 B per row
+        const int u = t >> 4, c4 = t & 15;
+        *reinterpret_cast<uint4*>(&s_spec[u * MF_ROW_H2 + c4 * 4]) = src[t];
+      }
+      const uint4* nyq = reinterpret_cast<const uint4*>(cs.spec16 + cs.spec_off[j] + MF_N * 64);
+      if (tid < 32) *reinterpret_cast<uint4*>(&s_spec[MF_N * MF_ROW_H2 + tid * 4]) = nyq[tid];
+      const uint64_t* bj = cs.bits + cs.bits_off[j];
+      s_bits[tid] = bj[tid];
+    }
+    __syncthreads();
+    const int seg_end = s_seg_end;
+    const int n_j = cs.npix[j], w_j = cs.w[j], z_j = cs.zero_bins[j];
+
+    for (int p = seg + wave; p < seg_end; p += 4) {
+      const int64_t k = base + p;
+      const int i = io.mem[k];
+      const int n_i = cs.npix[i], w_i = cs.w[i], z_i = cs.zero_bins[i];
+      if (n_i == 0 || n_j == 0) {
+        if (lane == 0) {
+          io.bits[k] = 0;
+          io.flags[k] = CA_FLAG_EMPTY;
+          if (q.need) q.need[k] = 0;
+          write_direction(io, k, 0, 0, 0, 0, 0.0, false);
+          write_direction(io, k, 1, 0, 0, 0, 0.0, false);
+        }
+        continue;
+      }
+      const uint32_t* mspec = reinterpret_cast<const uint32_t*>(cs.spec16 + cs.spec_off[i]);
+      // stage-1 twiddles (4 K-blocks x 3 dx-blocks) for this lane; cached, and
+      // not live across the peak search
+      h8_t B1[4][3];
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < 3; ++nb) B1[kb][nb] = b1frag[(kb * 3 + nb) * 64 + lane];
+      f4_t D2[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) D2[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll 1
+      for (int mb = 0; mb < 8; ++mb) {
+        const int u = mb * 16 + col;  // A-operand row of this lane
+        // D1[2 db] = Tr, D1[2 db + 1] = Ti for dx = 16 db - 16 + col
+        f4_t D1[6];
+#pragma unroll
+        for (int nb = 0; nb < 6; ++nb) D1[nb] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          const uint4 mv = *reinterpret_cast<const uint4*>(mspec + u * 64 + kb * 16 + g * 4);
+          const uint4 rv = *reinterpret_cast<const uint4*>(&s_spec[u * MF_ROW_H2 + kb * 16 + g * 4]);
+          const h2_t r0 = cmulc_h2(as_h2(mv.x), as_h2(rv.x));
+          const h2_t r1 = cmulc_h2(as_h2(mv.y), as_h2(rv.y));
+          const h2_t r2 = cmulc_h2(as_h2(mv.z), as_h2(rv.z));
+          const h2_t r3 = cmulc_h2(as_h2(mv.w), as_h2(rv.w));
+          const h8_t A1 = h8_t{r0.x, r0.y, r1.x, r1.y, r2.x, r2.y, r3.x, r3.y};
+          const h2_t q0 = mul_neg_i(r0), q1 = mul_neg_i(r1), q2 = mul_neg_i(r2), q3 = mul_neg_i(r3);
+          const h8_t A1n = h8_t{q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x, q3.y};
+#pragma unroll
+          for (int nb = 0; nb < 3; ++nb) {
+            D1[2 * nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B1[kb][nb], D1[2 * nb], 0, 0, 0);
+            D1[2 * nb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1n, B1[kb][nb], D1[2 * nb + 1], 0, 0, 0);
+          }
+        }
+        // Nyquist column v = 64: T(u, dx) += R(u, 64) (-1)^dx for the lane's 4 rows
+        {
+          const int u0 = mb * 16 + g * 4;
+          const uint4 mv = *reinterpret_cast<const uint4*>(mspec + MF_N * 64 + u0);
+          const uint4 rv = *reinterpret_cast<const uint4*>(&s_spec[MF_N * MF_ROW_H2 + u0]);
+          const h2_t n0 = cmulc_h2(as_h2(mv.x), as_h2(rv.x));
+          const h2_t n1 = cmulc_h2(as_h2(mv.y), as_h2(rv.y));
+          const h2_t n2 = cmulc_h2(as_h2(mv.z), as_h2(rv.z));
+          const h2_t n3 = cmulc_h2(as_h2(mv.w), as_h2(rv.w));
+          const float nr[4] = {(float)n0.x, (float)n1.x, (float)n2.x, (float)n3.x};
+          const float ni[4] = {(float)n0.y, (float)n1.y, (float)n2.y, (float)n3.y};
+          // column dx = -16 + col, col, 16 + col: parity of dx equals parity of col
+          const float sg = (col & 1) ? -1.f : 1.f;
+#pragma unroll
+          for (int db = 0; db < 3; ++db)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              D1[2 * db][t] += sg * nr[t];
+              D1[2 * db + 1][t] += sg * ni[t];
+            }
+        }
+        // stage 2: B operand (u, re/im) x dx straight from the stage-1 block
+#pragma unroll
+        for (int db = 0; db < 3; ++db) {
+          const h8_t B2 = h8_t{(_Float16)D1[2 * db][0], (_Float16)D1[2 * db][1], (_Float16)D1[2 * db][2],
+                               (_Float16)D1[2 * db][3], (_Float16)D1[2 * db + 1][0], (_Float16)D1[2 * db + 1][1],
+                               (_Float16)D1[2 * db + 1][2], (_Float16)D1[2 * db + 1][3]};
+#pragma unroll
+          for (int yb = 0; yb < 3; ++yb) {
+            const h8_t A2 = s_a2[(mb * 3 + yb) * 64 + lane];
+            D2[yb][db] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2, B2, D2[yb][db], 0, 0, 0);
+          }
+        }
+      }
+
+      // window surface to LDS: D2[yb][db][t] holds K r(dy, dx) at
+      // dy = 16 yb - 16 + 4 g + t, dx = 16 db - 16 + col (valid up to 16)
+      float* sw = s_surf[wave];
+#pragma unroll
+      for (int yb = 0; yb < 3; ++yb)
+#pragma unroll
+        for (int db = 0; db < 3; ++db)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const bool ok = (yb < 2 || (g == 0 && t == 0)) && (db < 2 || col == 0);
+            if (ok) sw[(4 * g + t) * 33 + col + (16 * yb * 33 + 16 * db)] = D2[yb][db][t];
+          }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int K_hi = MF_N * MF_N - max(z_i, z_j);
+      if (surf_out) {
+        float* so = surf_out + k * 33 * 33;
+        for (int t = lane; t < 33 * 33; t += 64) so[t] = sw[t] / (float)K_hi;
+      }
+      if (lane == 0) {
+        io.bits[k] = 0;
+        io.flags[k] = 0;
+        if (q.need) q.need[k] = 0;
+      }
+      for (int d = 0; d < 2; ++d) {
+        const int wd = d == 0 ? w_i : w_j;
+        float v1 = -3.0e38f, v2 = -3.0e38f;
+        int i1 = 0x7fffffff;
+        for (int t = lane; t < 33 * 33; t += 64) {
+          // direction-d shift s at window position t; the surface holds forward
+          // shifts, so the reverse direction reads the mirrored position
+          const int sy = t / 33 - 16, sx = t - (t / 33) * 33 - 16;
+          if (sy < -wd || sy > wd || sx < -wd || sx > wd) continue;
+          const float v = sw[d == 0 ? t : (33 * 33 - 1 - t)];
+          if (v > v1 || (v == v1 && t < i1)) {
+            v2 = v1;
+            v1 = v;
+            i1 = t;
+          } else {
+            v2 = fmaxf(v2, v);
+          }
+        }
+        wave_top2(v1, i1, v2);
+        const int sy = i1 / 33 - 16, sx = i1 % 33 - 16;
+        const uint64_t* brep = d == 0 ? s_bits : cs.bits + cs.bits_off[i];
+        const uint64_t* bmem = d == 0 ? cs.bits + cs.bits_off[i] : s_bits;
+        const int c = wave_overlap128(brep, bmem, sy, sx);
+        const int nm = d == 0 ? n_i : n_j, nr = d == 0 ? n_j : n_i;
+        const bool decided = (v1 - v2) >= band * (float)K_hi;
+        if (lane == 0)
+          write_direction(io, k, d, sy, sx, c, cosine_score(c, nm, nr), cosine_bit(c, nm, nr, thr));
+        if (!decided) queue_candidates(sw, d, wd, v1 - band * (float)K_hi, v1 / (float)K_hi, k, lane, q, cq);
+      }
+    }
+    __syncthreads();
+    seg = seg_end;
+  }
+}
+
+// Fragment tables, built on the host in double precision and rounded to FP16.
+//   b1[(kb * 3 + nb) * 64 + lane][t]: K index kk = 32 kb + 8 g + t <-> (v = 16 kb + 4 g + t/2,
+//     re/im = t % 2); column col of block nb <-> dx = 16 nb - 16 + col; entries
+//     h(v) cos(theta) for re, -h(v) sin(theta) for im, theta = 2 pi v dx / 128.
+//   a2[(mb * 3 + yb) * 64 + lane][t]: row col <-> dy = 16 yb - 16 + col; K index <->
+//     (u = 16 mb + 4 g + t % 4, re/im = t / 4): cos(2 pi u dy/128) or -sin(2 pi u dy/128).
+void build_mfma128_tables(_Float16* b1, _Float16* a2) {
+  const double tau = 2.0 * M_PI / 128.0;
+  for (int kb = 0; kb < 4; ++kb)
+    for (int nb = 0; nb < 3; ++nb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int gg = lane >> 4, cc = lane & 15;
+        const int dx = 16 * nb - 16 + cc;
+        for (int t = 0; t < 8; ++t) {
+          const int v = 16 * kb + 4 * gg + t / 2;
+          const int im = t % 2;
+          const double h = v == 0 ? 1.0 : 2.0;
+          double val = 0.0;
+          if (dx <= 16) {
+            const double th = tau * v * dx;
+            val = im ? -h * std::sin(th) : h * std::cos(th);
+          }
+          b1[((kb * 3 + nb) * 64 + lane) * 8 + t] = (_Float16)val;
+        }
+      }
+  for (int mb = 0; mb < 8; ++mb)
+    for (int yb = 0; yb < 3; ++yb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int gg = lane >> 4, cc = lane & 15;
+        const int dy = 16 * yb - 16 + cc;
+        for (int t = 0; t < 8; ++t) {
+          const int u = 16 * mb + 4 * gg + t % 4;
+          double val = 0.0;
+          if (dy <= 16) {
+            const double th = tau * u * dy;
+            val = (t / 4 == 0) ? std::cos(th) : -std::sin(th);
+          }
+          a2[((mb * 3 + yb) * 64 + lane) * 8 + t] = (_Float16)val;
+        }
+      }
+}
+
+hipError_t launch_pcm_mfma128(const ClipsDev& cs, const PairIO& io, Threshold thr, float band,
+                              const RescoreQueue& q, const CandQueue& cq, const void* b1frag,
+                              const void* a2frag, float* surf_out, hipStream_t s) {
+  if (io.n_pairs == 0) return hipSuccess;
+  const int64_t blocks = (io.n_pairs + MF_TILE - 1) / MF_TILE;
+  for (int64_t b0 = 0; b0 < blocks; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, blocks - b0);
+    hipLaunchKernelGGL(pcm_mfma128_kernel, dim3(nb), dim3(256), 0, s, cs, io, thr, band, q, cq,
+                       (const h8_t*)b1frag, (const h8_t*)a2frag, surf_out, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ca

@@ -16,7 +16,9 @@
 //
 // Both kernels run twice: once counting survivors per anchor, once writing
 // them at the anchor's exclusive-prefix offset in partner order, so the
-// output order is deterministic.
+// output order is deterministic.  The cosine kernel first applies a coarse
+// form of B2 over 8-row blocks (looser, eight times cheaper) and runs the
+// exact B2 only on pairs the coarse bound cannot reject.
 #include "kernels.h"
 #include "pair_common.h"
 
@@ -30,85 +32,141 @@ __device__ __forceinline__ bool bound_passes(int64_t b, int n1, int n2, Threshol
   return lhs > rhs;
 }
 
-// One 64-lane workgroup per anchor position a in `order`.
-__global__ void __launch_bounds__(64) cosine_prune_kernel(ClipsDev cs, PruneArgs pa, Threshold thr) {
-  __shared__ uint16_t ra[256], ca_[256], rb[256], cb[256];
-  __shared__ int red[64];
-  const int64_t a = blockIdx.x;
+// Lane-order prefix of a wave predicate and the wave total (ordered compaction).
+__device__ __forceinline__ int wave_prefix(bool pred, int lane, int* total) {
+  const unsigned long long m = __ballot(pred);
+  *total = __popcll(m);
+  return __popcll(m & ((1ull << lane) - 1ull));
+}
+
+// One wavefront per anchor position a in `order`; lanes take partners b in
+// [a+1, hi[a]), 64 at a time.
+//   coarse stage: per lane, the 8-row block bound
+//       U(d) <= sum_Y min(A_rep[Y], W_mem[(8 Y + d) mod N]),
+//     A = the anchor's 8-row block sums, W = the partner's sliding 8-row sums
+//     (held transposed in LDS so every lane reads its own column), maximised
+//     over the union of both windows; it bounds both directions at once;
+//   exact stage: for coarse survivors, one at a time, lanes own (rows or
+//     columns, shift) positions of the signature bound B2 and the wave takes
+//     the maxima of each direction's window with shuffles.
+__global__ void __launch_bounds__(64) cosine_prune_kernel(ClipsDev cs, PruneArgs pa, Threshold thr,
+                                                          int64_t block0) {
+  extern __shared__ uint16_t sT[];  // [2][N][64] partner sliding sums, transposed
+  __shared__ int ra[256], ca_[256], rb[256], cb[256];
+  __shared__ int Ar[32], Ac[32];
+  const int64_t a = block0 + (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
   const int ia = pa.order[a];
   const int N = cs.N[ia];
   const int na = cs.npix[ia];
   const int wa = cs.w[ia];
+  const int64_t so_a = cs.sig_off[ia];
   for (int y = lane; y < N; y += 64) {
-    ra[y] = cs.rowsum[cs.sig_off[ia] + y];
-    ca_[y] = cs.colsum[cs.sig_off[ia] + y];
+    ra[y] = cs.rowsum[so_a + y];
+    ca_[y] = cs.colsum[so_a + y];
   }
+  if (lane < N / 8) {
+    Ar[lane] = cs.winrow[so_a + 8 * lane];
+    Ac[lane] = cs.wincol[so_a + 8 * lane];
+  }
+  __syncthreads();
+  uint16_t* TR = sT;
+  uint16_t* TC = sT + N * 64;
   int64_t written = 0;
   const int64_t end = pa.hi[a];
-  for (int64_t b = a + 1; b < end; ++b) {
-    const int ib = pa.order[b];
+  for (int64_t b0 = a + 1; b0 < end; b0 += 64) {
+    const int64_t b = b0 + lane;
+    const bool valid = b < end;
+    const int ib = valid ? pa.order[b] : ia;
     const int nb = cs.npix[ib];
     const int wb = cs.w[ib];
-    __syncthreads();
-    for (int y = lane; y < N; y += 64) {
-      rb[y] = cs.rowsum[cs.sig_off[ib] + y];
-      cb[y] = cs.colsum[cs.sig_off[ib] + y];
+    const int64_t so_b = cs.sig_off[ib];
+    // partner sliding sums into this lane's LDS column
+    for (int t = 0; t < N; t += 8) {
+      const uint4 vr = *reinterpret_cast<const uint4*>(cs.winrow + so_b + t);
+      const uint4 vc = *reinterpret_cast<const uint4*>(cs.wincol + so_b + t);
+      const uint32_t r4[4] = {vr.x, vr.y, vr.z, vr.w};
+      const uint32_t c4[4] = {vc.x, vc.y, vc.z, vc.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        TR[(t + e) * 64 + lane] = (uint16_t)(r4[e >> 1] >> (16 * (e & 1)));
+        TC[(t + e) * 64 + lane] = (uint16_t)(c4[e >> 1] >> (16 * (e & 1)));
+      }
     }
-    __syncthreads();
-    // U(d) = sum_y min(sig_a[y], sig_b[(y + d) mod N]) for member b against rep a;
-    // the member-a direction sees U(-d).
     const Axis ax = make_axis(max(wa, wb), N);
-    int best_row_b = 0, best_col_b = 0, best_row_a = 0, best_col_a = 0;
-    for (int l = lane; l < ax.L; l += 64) {
-      const int dshift = l - ax.base;
-      int sd = dshift % N;
+    int best_r = 0, best_c = 0;
+    for (int l = 0; l < ax.L; ++l) {
+      int sd = (l - ax.base) % N;
       if (sd < 0) sd += N;
       int ur = 0, uc = 0;
-      for (int y = 0; y < N; ++y) {
-        int yy = y + sd;
-        if (yy >= N) yy -= N;
-        ur += min((int)ra[y], (int)rb[yy]);
-        uc += min((int)ca_[y], (int)cb[yy]);
+      for (int Y = 0; Y < N / 8; ++Y) {
+        const int t = (8 * Y + sd) & (N - 1);
+        ur += min(Ar[Y], (int)TR[t * 64 + lane]);
+        uc += min(Ac[Y], (int)TC[t * 64 + lane]);
       }
-      if (in_window(dshift, wb, N)) { best_row_b = max(best_row_b, ur); best_col_b = max(best_col_b, uc); }
-      const int nd = neg_rep(dshift, N);
-      if (in_window(nd, wa, N)) { best_row_a = max(best_row_a, ur); best_col_a = max(best_col_a, uc); }
+      best_r = max(best_r, ur);
+      best_c = max(best_c, uc);
     }
-    // wave maxima of the four values (LDS tree)
-    int vals[4] = {best_row_b, best_col_b, best_row_a, best_col_a};
-    int res[4];
-    for (int t = 0; t < 4; ++t) {
-      red[lane] = vals[t];
+    const bool pass_c = valid && na > 0 && nb > 0 && bound_passes(min(best_r, best_c), na, nb, thr);
+    bool pass = false;
+    unsigned long long todo = __ballot(pass_c);
+    while (todo) {
+      const int src = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1ull;
+      const int ibs = __shfl(ib, src), nbs = __shfl(nb, src), wbs = __shfl(wb, src);
+      const int64_t sob = cs.sig_off[ibs];
       __syncthreads();
-      for (int s = 32; s > 0; s >>= 1) {
-        if (lane < s) red[lane] = max(red[lane], red[lane + s]);
-        __syncthreads();
+      for (int y = lane; y < N; y += 64) {
+        rb[y] = cs.rowsum[sob + y];
+        cb[y] = cs.colsum[sob + y];
       }
-      res[t] = red[0];
       __syncthreads();
-    }
-    const int64_t bnd_b = min(res[0], res[1]);
-    const int64_t bnd_a = min(res[2], res[3]);
-    const bool pass = na > 0 && nb > 0 &&
-                      (bound_passes(bnd_b, na, nb, thr) || bound_passes(bnd_a, na, nb, thr));
-    if (pass) {
-      if (pa.offs && lane == 0) {
-        const int64_t o = pa.offs[a] + written;
-        pa.out_rep[o] = ia;
-        pa.out_mem[o] = ib;
+      // U(d) = sum_y min(sig_a[y], sig_b[(y + d) mod N]) serves member b against
+      // rep a at shift d, and member a against rep b at shift -d
+      const Axis axs = make_axis(max(wa, wbs), N);
+      int bb_r = 0, bb_c = 0, ba_r = 0, ba_c = 0;
+      for (int qpos = lane; qpos < 2 * axs.L; qpos += 64) {
+        const int dim = qpos >= axs.L;
+        const int d = qpos - dim * axs.L - axs.base;
+        int sd = d % N;
+        if (sd < 0) sd += N;
+        const int* sa = dim ? ca_ : ra;
+        const int* sbv = dim ? cb : rb;
+        int U = 0;
+        for (int y = 0; y < N; ++y) {
+          int yy = y + sd;
+          if (yy >= N) yy -= N;
+          U += min(sa[y], sbv[yy]);
+        }
+        if (in_window(d, wbs, N)) { if (dim) bb_c = max(bb_c, U); else bb_r = max(bb_r, U); }
+        if (in_window(neg_rep(d, N), wa, N)) { if (dim) ba_c = max(ba_c, U); else ba_r = max(ba_r, U); }
       }
-      ++written;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        bb_r = max(bb_r, __shfl_xor(bb_r, off));
+        bb_c = max(bb_c, __shfl_xor(bb_c, off));
+        ba_r = max(ba_r, __shfl_xor(ba_r, off));
+        ba_c = max(ba_c, __shfl_xor(ba_c, off));
+      }
+      const bool ok = bound_passes(min(bb_r, bb_c), na, nbs, thr) || bound_passes(min(ba_r, ba_c), na, nbs, thr);
+      if (lane == src) pass = ok;
     }
+    int total = 0;
+    const int before = wave_prefix(pass, lane, &total);
+    if (pass && pa.offs) {
+      const int64_t o = pa.offs[a] + written + before;
+      pa.out_rep[o] = ia;
+      pa.out_mem[o] = ib;
+    }
+    written += total;
   }
   if (!pa.offs && lane == 0) pa.counts[a] = written;
 }
 
 // Edge track: one 64-lane workgroup per anchor a; lanes take partners b in
 // [a+1, hi[a]) of the same raster size, 64 at a time.
-__global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs pa, Threshold thr) {
-  __shared__ int wsum[64];
-  const int64_t a = blockIdx.x;
+__global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs pa, Threshold thr, int64_t block0) {
+  const int64_t a = block0 + (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
   const int ia = pa.order[a];
   const int Pa = cs.npoly[ia];
@@ -146,13 +204,8 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
       }
     }
     // ordered compaction within the chunk
-    wsum[lane] = pass;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int t = 0; t < 64; ++t) {
-      before += (t < lane) ? wsum[t] : 0;
-      total += wsum[t];
-    }
+    int total = 0;
+    const int before = wave_prefix(pass != 0, lane, &total);
     if (pass && pa.offs) {
       const int64_t o = pa.offs[a] + written + before;
       const int x = min(ia, ib), y = max(ia, ib);
@@ -160,7 +213,6 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
       pa.out_mem[o] = y;
     }
     written += total;
-    __syncthreads();
   }
   if (!pa.offs && lane == 0) pa.counts[a] = written;
 }
@@ -169,16 +221,26 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
 
 namespace ca {
 
-hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, hipStream_t s) {
+hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, int maxN, hipStream_t s) {
   if (pa.n_anchor == 0) return hipSuccess;
-  hipLaunchKernelGGL(cosine_prune_kernel, dim3((unsigned)pa.n_anchor), dim3(64), 0, s, cs, pa, thr);
-  return hipGetLastError();
+  for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
+    hipLaunchKernelGGL(cosine_prune_kernel, dim3(nb), dim3(64), (size_t)256 * maxN, s, cs, pa, thr, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, hipStream_t s) {
   if (pa.n_anchor == 0) return hipSuccess;
-  hipLaunchKernelGGL(edge_prune_kernel, dim3((unsigned)pa.n_anchor), dim3(64), 0, s, cs, pa, thr);
-  return hipGetLastError();
+  for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
+    hipLaunchKernelGGL(edge_prune_kernel, dim3(nb), dim3(64), 0, s, cs, pa, thr, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ca

@@ -1,0 +1,226 @@
+// Cosine candidate generation for 128 x 128 clips with half-windows <= 16
+// (paper Sec. 3.1 stage 1; the safe bounds B1 and B2 of the library
+// documentation), specialised so that every operand of the signature bound
+// sits in registers.
+//
+// Anchors are clips in (n, id) order; B1 leaves each anchor a contiguous
+// range of larger partners (computed on the host).  One wavefront owns an
+// anchor; its lanes take 64 partners at a time.
+//   coarse stage   U(d) <= sum_Y min(A_rep[Y], W_mem[(8 Y + d) mod 128]) over the
+//                  16 row blocks Y, A = block sums of the anchor (uniform),
+//                  W = sliding 8-row sums of the partner (64 registers of packed
+//                  16-bit pairs); one v_pk_min_u16 / v_pk_add_u16 pair serves
+//                  the shifts d and d+1 at once.  Maximised over the union of
+//                  both windows, it bounds both directions.
+//   exact stage    U(d) = sum_y min(r_a[y], r_b[(y + d) mod 128]) for coarse
+//                  survivors, two rows per packed instruction (the partner's
+//                  sums held even- and odd-aligned in registers).  Survivors
+//                  of the coarse stage are queued in LDS so the exact stage
+//                  always runs on full waves.
+// Pass flags go to a bitmask over each anchor's partner range; a second
+// kernel writes the surviving pairs in (anchor order, partner order).
+#include "kernels.h"
+#include "pair_common.h"
+
+namespace ca {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t pk_u16(uint32_t lo, uint32_t hi) { return (lo & 0xffffu) | (hi << 16); }
+
+__device__ __forceinline__ bool passes128(int64_t b, int n1, int n2, Threshold t) {
+  const unsigned __int128 lhs = (unsigned __int128)((uint64_t)b * (uint64_t)b) *
+                                (unsigned __int128)((uint64_t)t.q * (uint64_t)t.q);
+  const unsigned __int128 rhs = (unsigned __int128)((uint64_t)t.p * (uint64_t)t.p) *
+                                (unsigned __int128)((uint64_t)n1 * (uint64_t)n2);
+  return lhs > rhs;
+}
+
+// Coarse bound of one dimension: max over |d| <= wmax of sum_Y min(A[Y], W[(8Y + d) mod 128]).
+// A: the anchor's 16 block sums (uniform, streamed); W: 64 packed pairs (W[2m], W[2m+1]).
+__device__ __forceinline__ int coarse_dim(const uint16_t* __restrict__ A, int stride, const uint32_t* W, int wmax) {
+  u16x2 acc[17];
+#pragma unroll
+  for (int e = 0; e < 17; ++e) acc[e] = u16x2{0, 0};
+#pragma unroll
+  for (int Y = 0; Y < 16; ++Y) {
+    const uint32_t ay = A[Y * stride];
+    const u16x2 a = as_u16x2(ay * 0x10001u);
+#pragma unroll
+    for (int e = 0; e < 17; ++e) {  // shift pair (d, d+1), d = -16 + 2 e
+      const int t = (8 * Y - 16 + 2 * e + 128) & 127;  // even
+      acc[e] += __builtin_elementwise_min(as_u16x2(W[t >> 1]), a);
+    }
+  }
+  int best = 0;
+#pragma unroll
+  for (int e = 0; e < 17; ++e) {
+    const int d = -16 + 2 * e;
+    if (d >= -wmax && d <= wmax) best = max(best, (int)acc[e].x);
+    if (d + 1 >= -wmax && d + 1 <= wmax) best = max(best, (int)acc[e].y);
+  }
+  return best;
+}
+
+// Exact bound of one dimension: per direction the max over the window of
+// U(d) = sum_y min(Ra[y], Rb[(y + d) mod 128]).
+// Ra: the anchor's packed pairs (uniform, streamed); Be/Bo: partner pairs aligned at even / odd rows.
+__device__ __forceinline__ void exact_dim(const uint32_t* __restrict__ Ra, const uint32_t* Be, const uint32_t* Bo,
+                                          int wb, int wa, int& best_b, int& best_a) {
+  u16x2 acc[33];
+#pragma unroll
+  for (int d = 0; d < 33; ++d) acc[d] = u16x2{0, 0};
+#pragma unroll
+  for (int m = 0; m < 64; ++m) {
+    const u16x2 ra = as_u16x2(Ra[m]);
+#pragma unroll
+    for (int d = -16; d <= 16; ++d) {
+      const int t = (2 * m + d + 128) & 127;
+      const uint32_t x = (t & 1) ? Bo[t >> 1] : Be[t >> 1];
+      acc[d + 16] += __builtin_elementwise_min(ra, as_u16x2(x));
+    }
+  }
+#pragma unroll
+  for (int d = -16; d <= 16; ++d) {
+    const int U = (int)acc[d + 16].x + (int)acc[d + 16].y;
+    if (d >= -wb && d <= wb) best_b = max(best_b, U);   // member b against rep a at shift d
+    if (-d >= -wa && -d <= wa) best_a = max(best_a, U); // member a against rep b at shift -d
+  }
+}
+
+__global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev cs, PruneArgs pa, Threshold thr,
+                                                             const int64_t* __restrict__ range_off,
+                                                             uint32_t* __restrict__ mask, int64_t block0) {
+  __shared__ int queue[128];
+  __shared__ int qlen;
+  const int64_t a = block0 + (int64_t)blockIdx.x;
+  const int lane = threadIdx.x;
+  const int ia = pa.order[a];
+  const int na = cs.npix[ia];
+  const int wa = cs.w[ia];
+  const int64_t so_a = cs.sig_off[ia];
+  const int64_t end = pa.hi[a];
+  const int64_t roff = range_off[a];
+  if (lane == 0) qlen = 0;
+  __syncthreads();
+  int64_t found = 0;
+
+  auto exact_flush = [&](int count) {
+    // lanes < count take queued partners; the rest idle through the same code
+    const int pos = lane < count ? queue[lane] : -1;
+    const int64_t b = pos >= 0 ? a + 1 + pos : a;
+    const int ib = pos >= 0 ? pa.order[b] : ia;
+    const int nb = cs.npix[ib];
+    const int wb = cs.w[ib];
+    const int64_t so_b = cs.sig_off[ib];
+    int bb_r = 0, ba_r = 0, bb_c = 0, ba_c = 0;
+    for (int dim = 0; dim < 2; ++dim) {
+      const uint16_t* sa = dim ? cs.colsum + so_a : cs.rowsum + so_a;
+      const uint16_t* sb = dim ? cs.colsum + so_b : cs.rowsum + so_b;
+      uint32_t Be[64], Bo[64];
+      const uint32_t* sa32 = reinterpret_cast<const uint32_t*>(sa);
+      const uint4* sb4 = reinterpret_cast<const uint4*>(sb);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const uint4 v = sb4[q];
+        Be[4 * q] = v.x; Be[4 * q + 1] = v.y; Be[4 * q + 2] = v.z; Be[4 * q + 3] = v.w;
+      }
+#pragma unroll
+      for (int m = 0; m < 64; ++m) Bo[m] = __builtin_amdgcn_alignbit(Be[(m + 1) & 63], Be[m], 16);
+      if (dim) exact_dim(sa32, Be, Bo, wb, wa, bb_c, ba_c);
+      else exact_dim(sa32, Be, Bo, wb, wa, bb_r, ba_r);
+    }
+    const bool ok = pos >= 0 && (passes128(min(bb_r, bb_c), na, nb, thr) || passes128(min(ba_r, ba_c), na, nb, thr));
+    if (ok) {
+      const int64_t bit = roff + pos;
+      atomicOr(mask + (bit >> 5), 1u << (bit & 31));
+    }
+    found += __popcll(__ballot(ok));
+  };
+
+  for (int64_t b0 = a + 1; b0 < end; b0 += 64) {
+    const int64_t b = b0 + lane;
+    const bool valid = b < end;
+    const int ib = valid ? pa.order[b] : ia;
+    const int nb = cs.npix[ib];
+    const int wb = cs.w[ib];
+    const int64_t so_b = cs.sig_off[ib];
+    uint32_t W[64];
+    const uint4* wr4 = reinterpret_cast<const uint4*>(cs.winrow + so_b);
+    const uint4* wc4 = reinterpret_cast<const uint4*>(cs.wincol + so_b);
+    const int wmax = max(wa, wb);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const uint4 v = wr4[q];
+      W[4 * q] = v.x; W[4 * q + 1] = v.y; W[4 * q + 2] = v.z; W[4 * q + 3] = v.w;
+    }
+    const int cr = coarse_dim(cs.winrow + so_a, 8, W, wmax);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const uint4 v = wc4[q];
+      W[4 * q] = v.x; W[4 * q + 1] = v.y; W[4 * q + 2] = v.z; W[4 * q + 3] = v.w;
+    }
+    const int cc = coarse_dim(cs.wincol + so_a, 8, W, wmax);
+    const bool keep = valid && na > 0 && nb > 0 && passes128(min(cr, cc), na, nb, thr);
+    const unsigned long long km = __ballot(keep);
+    const int qbase = qlen;
+    if (keep) queue[qbase + __popcll(km & ((1ull << lane) - 1ull))] = (int)(b - a - 1);
+    __syncthreads();
+    if (lane == 0) qlen = qbase + __popcll(km);
+    __syncthreads();
+    if (qlen >= 64) {
+      exact_flush(64);
+      __syncthreads();
+      const int rest = qlen - 64;
+      if (lane < rest) queue[lane] = queue[64 + lane];
+      __syncthreads();
+      if (lane == 0) qlen = rest;
+      __syncthreads();
+    }
+  }
+  if (qlen > 0) exact_flush(qlen);
+  if (lane == 0) pa.counts[a] = found;
+}
+
+// Ordered write of the surviving pairs of each anchor from the bitmask.
+__global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const int64_t* __restrict__ range_off,
+                                                            const uint32_t* __restrict__ mask, int64_t block0) {
+  const int64_t a = block0 + (int64_t)blockIdx.x;
+  const int lane = threadIdx.x;
+  const int ia = pa.order[a];
+  const int64_t len = pa.hi[a] - a - 1;
+  const int64_t roff = range_off[a];
+  int64_t o = pa.offs[a];
+  for (int64_t p0 = 0; p0 < len; p0 += 64) {
+    const int64_t p = p0 + lane;
+    bool on = false;
+    if (p < len) {
+      const int64_t bit = roff + p;
+      on = (mask[bit >> 5] >> (bit & 31)) & 1u;
+    }
+    const unsigned long long bm = __ballot(on);
+    if (on) {
+      const int64_t dst = o + __popcll(bm & ((1ull << lane) - 1ull));
+      pa.out_rep[dst] = ia;
+      pa.out_mem[dst] = pa.order[a + 1 + p];
+    }
+    o += __popcll(bm);
+  }
+}
+
+hipError_t launch_prune128(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
+                           uint32_t* mask, bool write, hipStream_t s) {
+  for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
+    if (write)
+      hipLaunchKernelGGL(prune128_write_kernel, dim3(nb), dim3(64), 0, s, pa, range_off, (const uint32_t*)mask, b0);
+    else
+      hipLaunchKernelGGL(prune128_bounds_kernel, dim3(nb), dim3(64), 0, s, cs, pa, thr, range_off, mask, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ca

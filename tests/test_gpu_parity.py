@@ -247,3 +247,131 @@ def test_error_paths(ctx):
         tiny.clips(clipgen.small(n_clips=64))
     assert e.value.status == ca.CA_ENOMEM
     h.close()
+
+
+# ------------------------------------------------------------------ mixed path
+
+
+def test_mixed_surface_within_band(ctx):
+    """Every window value of the FP16/MFMA surface is within a quarter of the
+    re-decision band of the FP64 surface, so an undecided peak is never final."""
+    import paper_2512_13133_amd as ca
+    cs = c128_subset(120, seed=11)
+    rep, mem = pairs_for(cs, 700, seed=5)
+    say(f"[surface] c128 pairs={rep.size}")
+    h = ctx.clips(cs)
+    got = ctx.surface(h, rep, mem).cpu().numpy().astype(np.float64)
+    band = ctx.stats()["tie_band_mixed"]
+    prep = cover.Prepared(cs)
+    z = {}
+    worst = 0.0
+    for k in range(rep.size):
+        i, j = int(mem[k]), int(rep[k])
+        for c in (i, j):
+            if c not in z:
+                z[c] = int((np.abs(cosine.spectrum(prep.a(c))) <= cosine.EPS).sum())
+        r, K = cosine.surface(prep.W(i), prep.W(j))
+        if K == 0:
+            continue
+        K_hi = 128 * 128 - max(z[i], z[j])
+        ax = np.arange(-16, 17) % 128
+        ref = r[np.ix_(ax, ax)] * K / K_hi
+        worst = max(worst, float(np.abs(got[k] - ref).max()))
+    say(f"[surface] max |mixed - fp64| = {worst:.3e}  band = {band:.1e}")
+    assert worst < band / 4
+    h.close()
+
+
+@pytest.mark.parametrize("seed", [2, 9])
+def test_cosine_c128_mixed(ctx, seed):
+    cs = c128_subset(200, seed=seed)
+    rep, mem = pairs_for(cs, 3000, seed=seed)
+    # group by representative, as candidate generation emits them, with a ragged tail
+    o = np.lexsort((mem, rep))
+    rep, mem = rep[o], mem[o]
+    say(f"[cosine] c128 path=mixed seed={seed} pairs={rep.size}")
+    h = ctx.clips(cs)
+    ctx.reset_stats()
+    got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "mixed"))
+    ref = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
+    check_cosine(got, ref, rep, mem, "c128/mixed")
+    st = ctx.stats()
+    say(f"[cosine] rescored {st['pairs_rescored']} of {st['pairs_aligned']}, max peak err {st['max_surface_err']:.2e}")
+    assert st["pairs_rescored"] < rep.size // 5
+    h.close()
+
+
+def test_mixed_rejects_other_shapes(ctx):
+    import paper_2512_13133_amd as ca
+    h = ctx.clips(small_set(8))
+    with pytest.raises(ca.ClipAlignError) as e:
+        ctx.align_pairs(h, [0], [1], "cosine", (19, 20), "mixed")
+    assert e.value.status == ca.CA_EUNSUPPORTED
+    h.close()
+
+
+# ------------------------------------------------------------------ launch limits
+
+
+@pytest.mark.parametrize("path,n_pairs", [("fp32", (1 << 24) + 77), ("edge", (1 << 26) + 77)])
+def test_launches_beyond_grid_limit(ctx, path, n_pairs):
+    """More pairs than one launch can hold (grid size in work-items < 2^32): every
+    replica of a pair must get the result of its first copy."""
+    import torch
+    cs = c128_subset(16, seed=4)
+    base_rep = np.array([0, 1, 2, 3, 4, 5, 6], np.int32)
+    base_mem = np.array([8, 9, 10, 11, 12, 13, 14], np.int32)
+    reps = np.resize(base_rep, n_pairs)
+    mems = np.resize(base_mem, n_pairs)
+    say(f"[launch] {path} pairs={n_pairs}")
+    h = ctx.clips(cs, fp32=True)
+    if path == "edge":
+        out = ctx.align_pairs(h, reps, mems, "edge", 3)
+    else:
+        out = ctx.align_pairs(h, reps, mems, "cosine", (19, 20), "fp32")
+    m = base_rep.size
+    for key in ("bits", "shift", "count", "flags"):
+        v = out[key]
+        first = v[:m]
+        reps_t = first.repeat((n_pairs + m - 1) // m, *([1] * (v.dim() - 1)))[:n_pairs]
+        assert torch.equal(v, reps_t), key
+    del out
+    torch.cuda.empty_cache()
+    h.close()
+
+
+def _oracle_prune_chunk(args):
+    cs, pairs = args
+    A = {}
+    out = []
+    for i, j in pairs:
+        for c in (i, j):
+            if c not in A:
+                A[c] = raster.clip_raster(cs, c)
+        if prune.cosine_pair_pass(A[i], A[j], int(cs.marker_w[i]), int(cs.marker_w[j]), 19, 20):
+            out.append((int(i), int(j)))
+    return out
+
+
+def test_prune128_matches_bounds(ctx):
+    """The register-resident 128 x 128 candidate generator against the oracle's bounds."""
+    import multiprocessing as mp
+    cs = c128_subset(360, seed=21)
+    say(f"[prune128] n={cs.n}")
+    h = ctx.clips(cs)
+    r, m = ctx.prune(h, "cosine", (19, 20))
+    r, m = r.cpu().numpy(), m.cpu().numpy()
+    got = {(min(a, b), max(a, b)) for a, b in zip(r.tolist(), m.tolist())}
+    assert len(got) == r.size
+    ii, jj = np.triu_indices(cs.n, 1)
+    chunks = np.array_split(np.arange(ii.size), 64)
+    with mp.get_context("fork").Pool(WORKERS) as pool:
+        res = pool.map(_oracle_prune_chunk, [(cs, list(zip(ii[c], jj[c]))) for c in chunks])
+    want = set(p for part in res for p in part)
+    say(f"[prune128] survivors got={len(got)} want={len(want)} of {ii.size}")
+    assert got == want
+    # grouping: pairs come grouped by representative (the anchor), anchors in (n, id) order
+    n_pix = np.array([raster.clip_raster(cs, i).sum() for i in range(cs.n)])
+    keys = [(n_pix[a], a) for a in r]
+    assert keys == sorted(keys)
+    h.close()
