@@ -227,6 +227,48 @@ ca_status ca_cluster(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_c
                      int32_t path, int32_t iterations, int32_t* rep_of, int16_t* center_shift,
                      int64_t* n_clusters);
 
+/* ---- serving: continuous batching against a device-resident library ---- */
+
+/* Serving applies the refinement step of the paper (Sec. 3.1, step 3: a
+ * pattern is aligned to fixed representatives and accepted under the strict
+ * threshold, Eqs. 2-5) to request batches that arrive over time.
+ *   library: a clip set on ctx (128 x 128 clips, half-windows <= 16) holding
+ *     the representatives; it must outlive the server.
+ *   con: the cosine constraint (CA_EUNSUPPORTED for the edge track).
+ *   slots: 1..32 concurrent requests; each slot has its own HIP stream and
+ *     worker thread, so requests on different slots overlap on the device.
+ *   hbm_budget_bytes: admission budget for the requests' own device memory
+ *     (0 = none); a request whose estimated footprint does not fit is refused
+ *     with CA_EBUSY and may be resubmitted later. */
+ca_status ca_server_create(ca_ctx* ctx, const ca_clipset* library, const ca_constraint* con, int32_t slots,
+                           uint64_t hbm_budget_bytes, ca_server** out);
+/* Stop the workers (queued requests still finish) and free the server. */
+ca_status ca_server_destroy(ca_server* srv);
+/* Submit a batch of n clips given as host arrays in the layout of
+ * ca_clips_create (128 x 128, half-windows <= 16).  The arrays are copied
+ * before return.  req_id (host) receives the request id.  Thread-safe. */
+ca_status ca_server_submit(ca_server* srv, int64_t n, const int64_t* rect_ptr, const int32_t* rects,
+                           const int16_t* raster_n, const int16_t* marker_w, uint64_t* req_id);
+/* Non-blocking poll.  *done = 0 while the request runs; when it has finished,
+ * *done = 1, the per-clip results are copied to the host arrays (any may be
+ * NULL) and the request is released:
+ *   best_rep [n] int32: library clip id of the best covering representative
+ *     (highest score, ties to the lowest id), -1 if none covers the clip;
+ *   shift [n][2] int16: the clip's shift (dy, dx) relative to that representative;
+ *   score [n] double: its cosine score; matched [n] uint8: 1 if covered.
+ * A failed request returns its error status with *done = 1.  Thread-safe. */
+ca_status ca_server_poll(ca_server* srv, uint64_t req_id, int32_t* best_rep, int16_t* shift, double* score,
+                         uint8_t* matched, int32_t* done);
+/* Block until the request has finished (timeout_ms < 0: no limit); CA_EBUSY
+ * on timeout.  Thread-safe. */
+ca_status ca_server_wait(ca_server* srv, uint64_t req_id, int32_t timeout_ms);
+/* Finished requests, candidate pairs aligned for them, and admitted bytes
+ * currently in flight.  Thread-safe. */
+ca_status ca_server_stats(ca_server* srv, int64_t* requests_done, int64_t* candidate_pairs,
+                          uint64_t* inflight_bytes);
+/* Last error message of the server (valid until its next failing call). */
+const char* ca_server_last_error(ca_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,6 +31,8 @@ SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
     "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect",
     "ca_align_pairs", "ca_surface", "ca_prune", "ca_cluster",
+    "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
+    "ca_server_stats", "ca_server_last_error",
 ]
 
 
@@ -84,8 +86,16 @@ def load():
     lib.ca_prune.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int64, P, P, C.POINTER(C.c_int64)]
     lib.ca_cluster.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int32, P, P,
                                C.POINTER(C.c_int64)]
+    lib.ca_server_create.argtypes = [P, P, C.POINTER(_Constraint), C.c_int32, C.c_uint64, C.POINTER(P)]
+    lib.ca_server_destroy.argtypes = [P]
+    lib.ca_server_submit.argtypes = [P, C.c_int64, P, P, P, P, C.POINTER(C.c_uint64)]
+    lib.ca_server_poll.argtypes = [P, C.c_uint64, P, P, P, P, C.POINTER(C.c_int32)]
+    lib.ca_server_wait.argtypes = [P, C.c_uint64, C.c_int32]
+    lib.ca_server_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
+    lib.ca_server_last_error.argtypes = [P]
+    lib.ca_server_last_error.restype = C.c_char_p
     for name in SYMBOLS:
-        if name != "ca_last_error":
+        if name not in ("ca_last_error", "ca_server_last_error"):
             getattr(lib, name).restype = C.c_int
     _LIB = lib
     return lib
@@ -240,3 +250,53 @@ class Context:
 
     def reset_stats(self):
         self._check(self.lib.ca_reset_stats(self.h))
+
+
+class Server:
+    """Continuous-batching matcher against a device-resident library (``ca_server_*``)."""
+
+    def __init__(self, ctx, library, thr=(19, 20), slots=4, hbm_budget_bytes=0):
+        self.ctx, self.lib = ctx, ctx.lib
+        self.library = library  # keep the library clip set alive
+        h = P()
+        con = constraint("cosine", thr)
+        ctx._check(self.lib.ca_server_create(ctx.h, library.handle, C.byref(con), int(slots),
+                                             int(hbm_budget_bytes), C.byref(h)))
+        self.h = h
+
+    def _check(self, st):
+        if st != CA_OK:
+            raise ClipAlignError(st, self.lib.ca_server_last_error(self.h).decode())
+
+    def submit(self, cs):
+        """Submit a ``clipgen.ClipSet`` batch; returns the request id (raises on refusal)."""
+        ptr = np.ascontiguousarray(cs.rect_ptr, dtype=np.int64)
+        rects = np.ascontiguousarray(cs.rects, dtype=np.int32).reshape(-1, 4)
+        rn = np.ascontiguousarray(cs.raster_n, dtype=np.int16)
+        mw = np.ascontiguousarray(cs.marker_w, dtype=np.int16)
+        rid = C.c_uint64(0)
+        self._check(self.lib.ca_server_submit(self.h, rn.size, _ptr(ptr), _ptr(rects) if rects.size else None,
+                                              _ptr(rn), _ptr(mw), C.byref(rid)))
+        return rid.value
+
+    def poll(self, rid, n):
+        """None while running, else dict(best_rep, shift, score, matched) as numpy arrays."""
+        out = dict(best_rep=np.zeros(n, np.int32), shift=np.zeros((n, 2), np.int16),
+                   score=np.zeros(n, np.float64), matched=np.zeros(n, np.uint8))
+        done = C.c_int32(0)
+        self._check(self.lib.ca_server_poll(self.h, C.c_uint64(rid), _ptr(out["best_rep"]), _ptr(out["shift"]),
+                                            _ptr(out["score"]), _ptr(out["matched"]), C.byref(done)))
+        return out if done.value else None
+
+    def wait(self, rid, timeout_ms=-1):
+        self._check(self.lib.ca_server_wait(self.h, C.c_uint64(rid), int(timeout_ms)))
+
+    def stats(self):
+        a, b, c = C.c_int64(0), C.c_int64(0), C.c_uint64(0)
+        self._check(self.lib.ca_server_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(requests_done=a.value, candidate_pairs=b.value, inflight_bytes=c.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._check(self.lib.ca_server_destroy(self.h))
+            self.h = None

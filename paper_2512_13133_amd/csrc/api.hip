@@ -421,14 +421,14 @@ ca_status ca_clips_inspect(const ca_clipset* cs, int64_t i, uint64_t* bits, int3
 
 namespace {
 
-ca_status validate_pairs(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, int64_t n_pairs,
-                         const int32_t* rep, const int32_t* mem, bool need_poly) {
+ca_status validate_pairs(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
+                         int64_t n_pairs, const int32_t* rep, const int32_t* mem, bool need_poly) {
   void* sc;
   ca_status st = scratch(ctx, 256, &sc);
   if (st) return st;
   int* bad = (int*)sc;
   HIP_OR_FAIL(ctx, hipMemsetAsync(bad, 0, sizeof(int), s));
-  HIP_OR_FAIL(ctx, launch_validate(cs->d, n_pairs, rep, mem, need_poly ? 1 : 0, bad, s));
+  HIP_OR_FAIL(ctx, launch_validate(crs->d, cms->d, n_pairs, rep, mem, need_poly ? 1 : 0, bad, s));
   int hbad = 0;
   HIP_OR_FAIL(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
@@ -438,8 +438,8 @@ ca_status validate_pairs(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, int64
 }
 
 // Algorithmic bytes of the FP32 per-pair kernel: both FP32 half-spectra and both bit rasters.
-double io_bytes_fp32(const ca_clipset* cs, int64_t n) {
-  const double N = cs->maxN;
+double io_bytes_fp32(int maxN, int64_t n) {
+  const double N = maxN;
   return (double)n * (2.0 * N * (N / 2 + 1) * 8.0 + 2.0 * N * N / 8.0);
 }
 
@@ -448,10 +448,9 @@ struct FftPlan {
   size_t smem;
 };
 
-FftPlan plan_fft(const ca_clipset* cs, int scalar_bytes) {
+FftPlan plan_fft(int N, int L, int scalar_bytes) {
   const size_t budget = 150 * 1024;
   FftPlan p;
-  const int N = cs->maxN, L = cs->Lmax;
   p.LINES = 8;
   const size_t c = 2 * (size_t)scalar_bytes;
   const size_t fixed = (size_t)p.LINES * N * c + (size_t)L * L * scalar_bytes;
@@ -464,18 +463,21 @@ FftPlan plan_fft(const ca_clipset* cs, int scalar_bytes) {
 }  // namespace
 
 // Cosine alignment of a device pair list with the chosen path (no validation).
-static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshold thr, int path,
-                              const PairIO& io) {
+static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
+                              Threshold thr, int path, const PairIO& io) {
+  const int maxN = std::max(crs->maxN, cms->maxN), Lmax = std::max(crs->Lmax, cms->Lmax);
+  const ClipsDev& cr = crs->d;
+  const ClipsDev& cm = cms->d;
   const int64_t n = io.n_pairs;
   const RescoreQueue none{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (path == CA_PATH_FP64) {
-    FftPlan pl = plan_fft(cs, 8);
-    HIP_OR_FAIL(ctx, launch_pcm_fft64(cs->d, io, nullptr, n, MODE_EXACT, thr, 0.0, ctx->tw64, pl.CH,
-                                      pl.LINES, cs->Lmax, cs->maxN, none, s));
+    FftPlan pl = plan_fft(maxN, Lmax, 8);
+    HIP_OR_FAIL(ctx, launch_pcm_fft64(cr, cm, io, nullptr, n, MODE_EXACT, thr, 0.0, ctx->tw64, pl.CH,
+                                      pl.LINES, Lmax, maxN, none, s));
     ctx->stats.pairs_aligned += n;
     return CA_OK;
   }
-  if (path == CA_PATH_FP32 && !cs->d.spec32)
+  if (path == CA_PATH_FP32 && (!cr.spec32 || !cm.spec32))
     return fail(ctx, CA_ESTATE, "CA_PATH_FP32 needs a clip set created with CA_CLIPS_FP32");
   // queue storage: need[n], list[n], r1_low[2n], counters, candidate groups and shifts
   const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
@@ -501,16 +503,16 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, 
   cq.cap_shifts = cap_s;
   HIP_OR_FAIL(ctx, hipMemsetAsync(counters, 0, 32, s));
   if (path == CA_PATH_FP32) {
-    FftPlan pl = plan_fft(cs, 4);
+    FftPlan pl = plan_fft(maxN, Lmax, 4);
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
-    HIP_OR_FAIL(ctx, launch_pcm_fft32(cs->d, io, nullptr, n, MODE_LOW, thr, BAND_FP32, ctx->tw32, pl.CH,
-                                      pl.LINES, cs->Lmax, cs->maxN, q, s));
+    HIP_OR_FAIL(ctx, launch_pcm_fft32(cr, cm, io, nullptr, n, MODE_LOW, thr, BAND_FP32, ctx->tw32, pl.CH,
+                                      pl.LINES, Lmax, maxN, q, s));
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
   } else {
-    if (!cs->mixed_ok)
+    if (!crs->mixed_ok || !cms->mixed_ok)
       return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
-    HIP_OR_FAIL(ctx, launch_pcm_mfma128(cs->d, io, thr, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
+    HIP_OR_FAIL(ctx, launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
                                         nullptr, s));
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
   }
@@ -522,16 +524,16 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, 
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     ctx->stats.t_main_ms += ms;
     ctx->stats.n_main_launch += 1;
-    ctx->stats.main_alg_bytes += path == CA_PATH_MIXED ? (double)n * (33280.0 + 2048.0) : io_bytes_fp32(cs, n);
+    ctx->stats.main_alg_bytes += path == CA_PATH_MIXED ? (double)n * (33280.0 + 2048.0) : io_bytes_fp32(maxN, n);
   }
   const int64_t n_groups = std::min<int64_t>((int64_t)h[2], cap_g);
   if (n_groups > 0)
-    HIP_OR_FAIL(ctx, launch_rescore_candidates(cs->d, io, thr, cq, n_groups, ctx->tw64, q.peak_err_bits,
+    HIP_OR_FAIL(ctx, launch_rescore_candidates(cr, cm, io, thr, cq, n_groups, ctx->tw64, q.peak_err_bits,
                                                q.r1_low, s));
   if (h[0] > 0) {
-    FftPlan pl = plan_fft(cs, 8);
-    HIP_OR_FAIL(ctx, launch_pcm_fft64(cs->d, io, q.list, (int64_t)h[0], MODE_RESCORE, thr, 0.0, ctx->tw64,
-                                      pl.CH, pl.LINES, cs->Lmax, cs->maxN, q, s));
+    FftPlan pl = plan_fft(maxN, Lmax, 8);
+    HIP_OR_FAIL(ctx, launch_pcm_fft64(cr, cm, io, q.list, (int64_t)h[0], MODE_RESCORE, thr, 0.0, ctx->tw64,
+                                      pl.CH, pl.LINES, Lmax, maxN, q, s));
   }
   if (n_groups > 0 || h[0] > 0) {
     HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, 16, hipMemcpyDeviceToHost, s));
@@ -544,6 +546,13 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, 
   ctx->stats.pairs_rescored += n_groups + (int64_t)h[0];
   return CA_OK;
 }
+
+namespace capriv {
+ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
+                            Threshold thr, int path, const PairIO& io) {
+  return align_cosine(ctx, crs, cms, s, thr, path, io);
+}
+}  // namespace capriv
 
 extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
                                     const ca_constraint* con, int32_t path, int64_t n_pairs,
@@ -560,7 +569,7 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
   if (path < CA_PATH_MIXED || path > CA_PATH_FP64) return fail(ctx, CA_EINVAL, "bad path");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  ca_status st = validate_pairs(ctx, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE);
+  ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE);
   if (st) return st;
   PairIO io{n_pairs, rep, mem, bits, shift, count, score, flags};
   if (con->kind == CA_EDGE) {
@@ -569,7 +578,7 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
     ctx->stats.pairs_edge += n_pairs;
     return CA_OK;
   }
-  return align_cosine(ctx, cs, s, Threshold{con->thr_num, con->thr_den}, path, io);
+  return align_cosine(ctx, cs, cs, s, Threshold{con->thr_num, con->thr_den}, path, io);
 }
 
 // Accessors used by api_cluster.hip.
@@ -605,7 +614,7 @@ extern "C" ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs,
   if (n_pairs == 0) return CA_OK;
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  ca_status st = validate_pairs(ctx, cs, s, n_pairs, rep, mem, false);
+  ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, false);
   if (st) return st;
   const size_t n = (size_t)n_pairs;
   const size_t b_bits = align_up(n), b_shift = align_up(8 * n), b_cnt = align_up(8 * n), b_sc = align_up(16 * n),
@@ -625,7 +634,7 @@ extern "C" ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs,
   q.peak_err_bits = q.len + 1;
   HIP_OR_FAIL(ctx, hipMemsetAsync(q.len, 0, 32, s));
   CandQueue cq{nullptr, nullptr, q.len + 2, q.len + 3, 0, 0};
-  HIP_OR_FAIL(ctx, launch_pcm_mfma128(cs->d, io, Threshold{1, 1}, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
+  HIP_OR_FAIL(ctx, launch_pcm_mfma128(cs->d, cs->d, io, Threshold{1, 1}, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
                                       surf, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
   return CA_OK;

@@ -126,7 +126,7 @@ static ca_status prune128_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* c
     HIP_TRY(ctx, hipMemcpyAsync(d_roff, range_off.data(), 8 * na, hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
     PruneArgs pa{d_order, d_hi, na, d_cnt, nullptr, nullptr, nullptr};
-    HIP_TRY(ctx, launch_prune128(dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff, d_mask, false, s));
+    HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff, d_mask, false, s));
     pc->counts.assign(na, 0);
     HIP_TRY(ctx, hipMemcpyAsync(pc->counts.data(), d_cnt, 8 * na, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -153,7 +153,7 @@ static ca_status prune128_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* c
   int64_t* d_off = (int64_t*)(base + 2 * b_ord + b_rng);  // reuses the count slots
   HIP_TRY(ctx, hipMemcpyAsync(d_off, off.data(), 8 * na, hipMemcpyHostToDevice, s));
   PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), na, nullptr, d_off, rep, mem};
-  HIP_TRY(ctx, launch_prune128(dev_of(cs), pa, Threshold{con->thr_num, con->thr_den},
+  HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, Threshold{con->thr_num, con->thr_den},
                                (int64_t*)(base + 2 * b_ord), (uint32_t*)(base + 2 * b_ord + 2 * b_rng), true, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return CA_OK;

@@ -93,14 +93,20 @@ struct CandQueue {
 };
 
 // Candidate generation: anchors, their partner ranges and the output list.
+// Within one clip set the anchors are the positions of `order` and each
+// anchor's partners start right after it; between two sets (a request batch
+// against a library) `anchor_ids` and `lo` give the anchors and range starts.
 struct PruneArgs {
-  const int32_t* order;  // clip ids, grouped by raster size (cosine: by (n, id) within a size)
+  const int32_t* order;  // partner clip ids, grouped by raster size (cosine: by (n, id) within a size)
   const int32_t* hi;     // [n_anchor] exclusive end of each anchor's partner range in `order`
   int64_t n_anchor;
   int64_t* counts;       // [n_anchor] survivors (count pass)
   const int64_t* offs;   // [n_anchor] write offsets (write pass), or null
   int32_t* out_rep;
   int32_t* out_mem;
+  const int32_t* anchor_ids = nullptr;  // [n_anchor] anchor clip ids (null: order[a])
+  const int32_t* lo = nullptr;          // [n_anchor] start of each range in `order` (null: a + 1)
+  int partner_is_rep = 0;               // write the partner as the representative
 };
 
 }  // namespace ca

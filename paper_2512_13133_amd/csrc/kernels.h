@@ -19,10 +19,10 @@ hipError_t launch_spectrum(const ClipsDev& cs, const int64_t* ids, int64_t n_ids
                            double2* scratch, const double2* tw256, hipStream_t s);
 // Shared-memory bytes of the per-pair FFT kernel for (scalar size, N, CH, LINES, Lmax).
 size_t pcm_fft_smem(int scalar_bytes, int N, int CH, int LINES, int Lmax);
-hipError_t launch_pcm_fft32(const ClipsDev& cs, const PairIO& io, const int64_t* list, int64_t n_blocks,
+hipError_t launch_pcm_fft32(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list, int64_t n_blocks,
                             int mode, Threshold thr, double band, const float2* tw256, int CH,
                             int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s);
-hipError_t launch_pcm_fft64(const ClipsDev& cs, const PairIO& io, const int64_t* list, int64_t n_blocks,
+hipError_t launch_pcm_fft64(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list, int64_t n_blocks,
                             int mode, Threshold thr, double band, const double2* tw256, int CH,
                             int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s);
 hipError_t launch_edge(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
@@ -31,19 +31,19 @@ hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold 
 // Batched MFMA surface for raster 128, half-windows <= 16 (fragment tables from
 // build_mfma128_tables: 4*3*64*8 and 8*3*64*8 halves).
 void build_mfma128_tables(_Float16* b1, _Float16* a2);
-hipError_t launch_pcm_mfma128(const ClipsDev& cs, const PairIO& io, Threshold thr, float band,
+hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr, float band,
                               const RescoreQueue& q, const CandQueue& cq, const void* b1frag,
                               const void* a2frag, float* surf_out, hipStream_t s);
 // FP64 re-decision of queued directions at their candidate shifts.
-hipError_t launch_rescore_candidates(const ClipsDev& cs, const PairIO& io, Threshold thr,
+hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                      const CandQueue& cq, int64_t n_groups, const double2* tw256,
                                      unsigned long long* peak_err_bits, const float* r1_low, hipStream_t s);
 // Cosine candidate generation for 128 x 128 clips with half-windows <= 16:
 // write = false runs the bounds pass (bitmask + counts), write = true the
 // ordered write of the survivors (needs pa.offs).
-hipError_t launch_prune128(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
-                           uint32_t* mask, bool write, hipStream_t s);
-hipError_t launch_validate(const ClipsDev& cs, int64_t n_pairs, const int32_t* rep, const int32_t* mem,
-                           int need_poly, int* bad, hipStream_t s);
+hipError_t launch_prune128(const ClipsDev& ca, const ClipsDev& cb, const PruneArgs& pa, Threshold thr,
+                           const int64_t* range_off, uint32_t* mask, bool write, hipStream_t s);
+hipError_t launch_validate(const ClipsDev& cr, const ClipsDev& cm, int64_t n_pairs, const int32_t* rep,
+                           const int32_t* mem, int need_poly, int* bad, hipStream_t s);
 
 }  // namespace ca

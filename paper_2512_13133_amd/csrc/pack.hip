@@ -244,16 +244,16 @@ namespace ca {
 
 // Pair validation: ids in range, equal raster sizes, and (for the edge track)
 // polygon tables within the cap.  Sets *bad to 1 (ids/sizes) or 2 (polygons).
-__global__ void validate_pairs_kernel(ClipsDev cs, int64_t n_pairs, const int32_t* __restrict__ rep,
+__global__ void validate_pairs_kernel(ClipsDev cr, ClipsDev cm, int64_t n_pairs, const int32_t* __restrict__ rep,
                                       const int32_t* __restrict__ mem, int need_poly, int* bad) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_pairs) return;
   const int a = rep[k], b = mem[k];
-  if (a < 0 || b < 0 || a >= cs.n || b >= cs.n || cs.N[a] != cs.N[b]) {
+  if (a < 0 || b < 0 || a >= cr.n || b >= cm.n || cr.N[a] != cm.N[b]) {
     atomicOr(bad, 1);
     return;
   }
-  if (need_poly && (cs.npoly[a] < 0 || cs.npoly[b] < 0)) atomicOr(bad, 2);
+  if (need_poly && (cr.npoly[a] < 0 || cm.npoly[b] < 0)) atomicOr(bad, 2);
 }
 
 hipError_t launch_pack(const int64_t* rect_ptr, const int32_t* rects, const ClipsDev& cs, int64_t n,
@@ -279,11 +279,11 @@ hipError_t launch_label(const ClipsDev& cs, int64_t n, hipStream_t s) {
   return hipSuccess;
 }
 
-hipError_t launch_validate(const ClipsDev& cs, int64_t n_pairs, const int32_t* rep, const int32_t* mem,
-                           int need_poly, int* bad, hipStream_t s) {
+hipError_t launch_validate(const ClipsDev& cr, const ClipsDev& cm, int64_t n_pairs, const int32_t* rep,
+                           const int32_t* mem, int need_poly, int* bad, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n_pairs + 255) / 256);
-  hipLaunchKernelGGL(validate_pairs_kernel, dim3(blocks), dim3(256), 0, s, cs, n_pairs, rep, mem,
+  hipLaunchKernelGGL(validate_pairs_kernel, dim3(blocks), dim3(256), 0, s, cr, cm, n_pairs, rep, mem,
                      need_poly, bad);
   return hipGetLastError();
 }

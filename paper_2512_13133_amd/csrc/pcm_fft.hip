@@ -24,7 +24,7 @@ namespace ca {
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-pcm_fft_kernel(ClipsDev cs, PairIO io, const int64_t* __restrict__ list, int mode, Threshold thr,
+pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ list, int mode, Threshold thr,
                double band, const typename cplx<T>::type* __restrict__ tw256, int CH, int LINES,
                int Lmax, RescoreQueue q, int64_t block0) {
   using C = typename cplx<T>::type;
@@ -39,11 +39,11 @@ pcm_fft_kernel(ClipsDev cs, PairIO io, const int64_t* __restrict__ list, int mod
   const int64_t k = list ? list[b] : b;
   const int tid = threadIdx.x;
   const int j = io.rep[k], i = io.mem[k];
-  const int N = cs.N[i];
+  const int N = cm.N[i];
   const int logN = ilog2(N);
   const int H = N / 2;
-  const int wf = cs.w[i], wr = cs.w[j];
-  const int n_i = cs.npix[i], n_j = cs.npix[j];
+  const int wf = cm.w[i], wr = cr.w[j];
+  const int n_i = cm.npix[i], n_j = cr.npix[j];
   const int dirs = (mode == MODE_RESCORE) ? (int)q.need[k] : 3;
 
   if (mode != MODE_RESCORE && tid == 0) {
@@ -70,11 +70,11 @@ pcm_fft_kernel(ClipsDev cs, PairIO io, const int64_t* __restrict__ list, int mod
   const C* Wi;
   const C* Wj;
   if constexpr (sizeof(T) == 4) {
-    Wi = reinterpret_cast<const C*>(cs.spec32 + cs.spec_off[i]);
-    Wj = reinterpret_cast<const C*>(cs.spec32 + cs.spec_off[j]);
+    Wi = reinterpret_cast<const C*>(cm.spec32 + cm.spec_off[i]);
+    Wj = reinterpret_cast<const C*>(cr.spec32 + cr.spec_off[j]);
   } else {
-    Wi = reinterpret_cast<const C*>(cs.spec64 + cs.spec_off[i]);
-    Wj = reinterpret_cast<const C*>(cs.spec64 + cs.spec_off[j]);
+    Wi = reinterpret_cast<const C*>(cm.spec64 + cm.spec_off[i]);
+    Wj = reinterpret_cast<const C*>(cr.spec64 + cr.spec_off[j]);
   }
   const int Hs = H + 1;  // stored half-spectrum columns
 
@@ -179,8 +179,8 @@ pcm_fft_kernel(ClipsDev cs, PairIO io, const int64_t* __restrict__ list, int mod
   const int K = ired[0];
   __syncthreads();
 
-  const uint64_t* bits_i = cs.bits + cs.bits_off[i];
-  const uint64_t* bits_j = cs.bits + cs.bits_off[j];
+  const uint64_t* bits_i = cm.bits + cm.bits_off[i];
+  const uint64_t* bits_j = cr.bits + cr.bits_off[j];
 
   for (int d = 0; d < 2; ++d) {
     if (!(dirs & (1 << d))) continue;
@@ -292,7 +292,7 @@ size_t pcm_fft_smem(int scalar_bytes, int N, int CH, int LINES, int Lmax) {
 }
 
 template <typename T>
-static hipError_t launch_pcm_fft_t(const ClipsDev& cs, const PairIO& io, const int64_t* list,
+static hipError_t launch_pcm_fft_t(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list,
                                    int64_t n_blocks, int mode, Threshold thr, double band,
                                    const typename cplx<T>::type* tw256, int CH, int LINES, int Lmax,
                                    int maxN, const RescoreQueue& q, hipStream_t s) {
@@ -303,7 +303,7 @@ static hipError_t launch_pcm_fft_t(const ClipsDev& cs, const PairIO& io, const i
   if (e != hipSuccess) return e;
   for (int64_t b0 = 0; b0 < n_blocks; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, n_blocks - b0);
-    hipLaunchKernelGGL(pcm_fft_kernel<T>, dim3(nb), dim3(256), smem, s, cs, io, list, mode, thr, band, tw256,
+    hipLaunchKernelGGL(pcm_fft_kernel<T>, dim3(nb), dim3(256), smem, s, cr, cm, io, list, mode, thr, band, tw256,
                        CH, LINES, Lmax, q, b0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -311,16 +311,16 @@ static hipError_t launch_pcm_fft_t(const ClipsDev& cs, const PairIO& io, const i
   return hipSuccess;
 }
 
-hipError_t launch_pcm_fft32(const ClipsDev& cs, const PairIO& io, const int64_t* list, int64_t n_blocks,
+hipError_t launch_pcm_fft32(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list, int64_t n_blocks,
                             int mode, Threshold thr, double band, const float2* tw256, int CH,
                             int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s) {
-  return launch_pcm_fft_t<float>(cs, io, list, n_blocks, mode, thr, band, tw256, CH, LINES, Lmax, maxN, q, s);
+  return launch_pcm_fft_t<float>(cr, cm, io, list, n_blocks, mode, thr, band, tw256, CH, LINES, Lmax, maxN, q, s);
 }
 
-hipError_t launch_pcm_fft64(const ClipsDev& cs, const PairIO& io, const int64_t* list, int64_t n_blocks,
+hipError_t launch_pcm_fft64(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list, int64_t n_blocks,
                             int mode, Threshold thr, double band, const double2* tw256, int CH,
                             int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s) {
-  return launch_pcm_fft_t<double>(cs, io, list, n_blocks, mode, thr, band, tw256, CH, LINES, Lmax, maxN, q, s);
+  return launch_pcm_fft_t<double>(cr, cm, io, list, n_blocks, mode, thr, band, tw256, CH, LINES, Lmax, maxN, q, s);
 }
 
 }  // namespace ca

@@ -16,6 +16,10 @@
 // operand layout; each 16-row stage-1 result block converts in registers into
 // the matching stage-2 B operand, so the intermediate never leaves the wave.
 //
+// Representatives come from the clip set `cr` and members from `cm` (the same
+// set for pairs within one set, a device-resident library and a request batch
+// when serving).
+//
 // Batching: a workgroup owns TILE consecutive pairs.  Consecutive pairs with
 // the same representative form a run; the run's representative spectrum and
 // bits are staged once in LDS and the four waves take its members.  The
@@ -147,7 +151,7 @@ __device__ __noinline__ void queue_candidates(const float* sw, int d, int wd, fl
 }
 
 __global__ void __launch_bounds__(256, 2)
-pcm_mfma128_kernel(ClipsDev cs, PairIO io, Threshold thr, float band, RescoreQueue q, CandQueue cq,
+pcm_mfma128_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, float band, RescoreQueue q, CandQueue cq,
                    const h8_t* b1frag, const h8_t* a2frag, float* surf_out, int64_t block0) {
   __shared__ __align__(16) uint32_t s_spec[MF_SPEC_H2];   // representative W (half2)
   __shared__ __align__(16) h8_t s_a2[8 * 3 * 64];          // stage-2 twiddles
@@ -178,24 +182,24 @@ pcm_mfma128_kernel(ClipsDev cs, PairIO io, Threshold thr, float band, RescoreQue
     const int j = s_rep[seg];
     // stage the representative's spectrum (rows padded) and bits
     {
-      const uint4* src = reinterpret_cast<const uint4*>(cs.spec16 + cs.spec_off[j]);
+      const uint4* src = reinterpret_cast<const uint4*>(cr.spec16 + cr.spec_off[j]);
       for (int t = tid; t < MF_N * 16; t += 256) {  // 16 x 16 B per row
         const int u = t >> 4, c4 = t & 15;
         *reinterpret_cast<uint4*>(&s_spec[u * MF_ROW_H2 + c4 * 4]) = src[t];
       }
-      const uint4* nyq = reinterpret_cast<const uint4*>(cs.spec16 + cs.spec_off[j] + MF_N * 64);
+      const uint4* nyq = reinterpret_cast<const uint4*>(cr.spec16 + cr.spec_off[j] + MF_N * 64);
       if (tid < 32) *reinterpret_cast<uint4*>(&s_spec[MF_N * MF_ROW_H2 + tid * 4]) = nyq[tid];
-      const uint64_t* bj = cs.bits + cs.bits_off[j];
+      const uint64_t* bj = cr.bits + cr.bits_off[j];
       s_bits[tid] = bj[tid];
     }
     __syncthreads();
     const int seg_end = s_seg_end;
-    const int n_j = cs.npix[j], w_j = cs.w[j], z_j = cs.zero_bins[j];
+    const int n_j = cr.npix[j], w_j = cr.w[j], z_j = cr.zero_bins[j];
 
     for (int p = seg + wave; p < seg_end; p += 4) {
       const int64_t k = base + p;
       const int i = io.mem[k];
-      const int n_i = cs.npix[i], w_i = cs.w[i], z_i = cs.zero_bins[i];
+      const int n_i = cm.npix[i], w_i = cm.w[i], z_i = cm.zero_bins[i];
       if (n_i == 0 || n_j == 0) {
         if (lane == 0) {
           io.bits[k] = 0;
@@ -206,7 +210,7 @@ pcm_mfma128_kernel(ClipsDev cs, PairIO io, Threshold thr, float band, RescoreQue
         }
         continue;
       }
-      const uint32_t* mspec = reinterpret_cast<const uint32_t*>(cs.spec16 + cs.spec_off[i]);
+      const uint32_t* mspec = reinterpret_cast<const uint32_t*>(cm.spec16 + cm.spec_off[i]);
       // stage-1 twiddles (4 K-blocks x 3 dx-blocks) for this lane; cached, and
       // not live across the peak search
       h8_t B1[4][3];
@@ -324,8 +328,8 @@ pcm_mfma128_kernel(ClipsDev cs, PairIO io, Threshold thr, float band, RescoreQue
         }
         wave_top2(v1, i1, v2);
         const int sy = i1 / 33 - 16, sx = i1 % 33 - 16;
-        const uint64_t* brep = d == 0 ? s_bits : cs.bits + cs.bits_off[i];
-        const uint64_t* bmem = d == 0 ? cs.bits + cs.bits_off[i] : s_bits;
+        const uint64_t* brep = d == 0 ? s_bits : cm.bits + cm.bits_off[i];
+        const uint64_t* bmem = d == 0 ? cm.bits + cm.bits_off[i] : s_bits;
         const int c = wave_overlap128(brep, bmem, sy, sx);
         const int nm = d == 0 ? n_i : n_j, nr = d == 0 ? n_j : n_i;
         const bool decided = (v1 - v2) >= band * (float)K_hi;
@@ -381,14 +385,14 @@ void build_mfma128_tables(_Float16* b1, _Float16* a2) {
       }
 }
 
-hipError_t launch_pcm_mfma128(const ClipsDev& cs, const PairIO& io, Threshold thr, float band,
+hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr, float band,
                               const RescoreQueue& q, const CandQueue& cq, const void* b1frag,
                               const void* a2frag, float* surf_out, hipStream_t s) {
   if (io.n_pairs == 0) return hipSuccess;
   const int64_t blocks = (io.n_pairs + MF_TILE - 1) / MF_TILE;
   for (int64_t b0 = 0; b0 < blocks; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, blocks - b0);
-    hipLaunchKernelGGL(pcm_mfma128_kernel, dim3(nb), dim3(256), 0, s, cs, io, thr, band, q, cq,
+    hipLaunchKernelGGL(pcm_mfma128_kernel, dim3(nb), dim3(256), 0, s, cr, cm, io, thr, band, q, cq,
                        (const h8_t*)b1frag, (const h8_t*)a2frag, surf_out, b0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

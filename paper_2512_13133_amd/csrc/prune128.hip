@@ -19,6 +19,8 @@
 //                  always runs on full waves.
 // Pass flags go to a bitmask over each anchor's partner range; a second
 // kernel writes the surviving pairs in (anchor order, partner order).
+// Anchors come from the clip set `ca` and partners from `cb` (the same set
+// within one clip set; a request batch and the library when serving).
 #include "kernels.h"
 #include "pair_common.h"
 
@@ -89,17 +91,18 @@ __device__ __forceinline__ void exact_dim(const uint32_t* __restrict__ Ra, const
   }
 }
 
-__global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev cs, PruneArgs pa, Threshold thr,
+__global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsDev cb, PruneArgs pa, Threshold thr,
                                                              const int64_t* __restrict__ range_off,
                                                              uint32_t* __restrict__ mask, int64_t block0) {
   __shared__ int queue[128];
   __shared__ int qlen;
   const int64_t a = block0 + (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
-  const int ia = pa.order[a];
-  const int na = cs.npix[ia];
-  const int wa = cs.w[ia];
-  const int64_t so_a = cs.sig_off[ia];
+  const int ia = pa.anchor_ids ? pa.anchor_ids[a] : pa.order[a];
+  const int na = ca.npix[ia];
+  const int wa = ca.w[ia];
+  const int64_t so_a = ca.sig_off[ia];
+  const int64_t start = pa.lo ? (int64_t)pa.lo[a] : a + 1;
   const int64_t end = pa.hi[a];
   const int64_t roff = range_off[a];
   if (lane == 0) qlen = 0;
@@ -109,15 +112,14 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev cs, PruneA
   auto exact_flush = [&](int count) {
     // lanes < count take queued partners; the rest idle through the same code
     const int pos = lane < count ? queue[lane] : -1;
-    const int64_t b = pos >= 0 ? a + 1 + pos : a;
-    const int ib = pos >= 0 ? pa.order[b] : ia;
-    const int nb = cs.npix[ib];
-    const int wb = cs.w[ib];
-    const int64_t so_b = cs.sig_off[ib];
+    const int ib = pos >= 0 ? pa.order[start + pos] : pa.order[start];
+    const int nb = cb.npix[ib];
+    const int wb = cb.w[ib];
+    const int64_t so_b = cb.sig_off[ib];
     int bb_r = 0, ba_r = 0, bb_c = 0, ba_c = 0;
     for (int dim = 0; dim < 2; ++dim) {
-      const uint16_t* sa = dim ? cs.colsum + so_a : cs.rowsum + so_a;
-      const uint16_t* sb = dim ? cs.colsum + so_b : cs.rowsum + so_b;
+      const uint16_t* sa = dim ? ca.colsum + so_a : ca.rowsum + so_a;
+      const uint16_t* sb = dim ? cb.colsum + so_b : cb.rowsum + so_b;
       uint32_t Be[64], Bo[64];
       const uint32_t* sa32 = reinterpret_cast<const uint32_t*>(sa);
       const uint4* sb4 = reinterpret_cast<const uint4*>(sb);
@@ -139,33 +141,33 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev cs, PruneA
     found += __popcll(__ballot(ok));
   };
 
-  for (int64_t b0 = a + 1; b0 < end; b0 += 64) {
+  for (int64_t b0 = start; b0 < end; b0 += 64) {
     const int64_t b = b0 + lane;
     const bool valid = b < end;
-    const int ib = valid ? pa.order[b] : ia;
-    const int nb = cs.npix[ib];
-    const int wb = cs.w[ib];
-    const int64_t so_b = cs.sig_off[ib];
+    const int ib = valid ? pa.order[b] : pa.order[start];
+    const int nb = cb.npix[ib];
+    const int wb = cb.w[ib];
+    const int64_t so_b = cb.sig_off[ib];
     uint32_t W[64];
-    const uint4* wr4 = reinterpret_cast<const uint4*>(cs.winrow + so_b);
-    const uint4* wc4 = reinterpret_cast<const uint4*>(cs.wincol + so_b);
+    const uint4* wr4 = reinterpret_cast<const uint4*>(cb.winrow + so_b);
+    const uint4* wc4 = reinterpret_cast<const uint4*>(cb.wincol + so_b);
     const int wmax = max(wa, wb);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const uint4 v = wr4[q];
       W[4 * q] = v.x; W[4 * q + 1] = v.y; W[4 * q + 2] = v.z; W[4 * q + 3] = v.w;
     }
-    const int cr = coarse_dim(cs.winrow + so_a, 8, W, wmax);
+    const int cr = coarse_dim(ca.winrow + so_a, 8, W, wmax);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const uint4 v = wc4[q];
       W[4 * q] = v.x; W[4 * q + 1] = v.y; W[4 * q + 2] = v.z; W[4 * q + 3] = v.w;
     }
-    const int cc = coarse_dim(cs.wincol + so_a, 8, W, wmax);
+    const int cc = coarse_dim(ca.wincol + so_a, 8, W, wmax);
     const bool keep = valid && na > 0 && nb > 0 && passes128(min(cr, cc), na, nb, thr);
     const unsigned long long km = __ballot(keep);
     const int qbase = qlen;
-    if (keep) queue[qbase + __popcll(km & ((1ull << lane) - 1ull))] = (int)(b - a - 1);
+    if (keep) queue[qbase + __popcll(km & ((1ull << lane) - 1ull))] = (int)(b - start);
     __syncthreads();
     if (lane == 0) qlen = qbase + __popcll(km);
     __syncthreads();
@@ -188,8 +190,9 @@ __global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const 
                                                             const uint32_t* __restrict__ mask, int64_t block0) {
   const int64_t a = block0 + (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
-  const int ia = pa.order[a];
-  const int64_t len = pa.hi[a] - a - 1;
+  const int ia = pa.anchor_ids ? pa.anchor_ids[a] : pa.order[a];
+  const int64_t start = pa.lo ? (int64_t)pa.lo[a] : a + 1;
+  const int64_t len = pa.hi[a] - start;
   const int64_t roff = range_off[a];
   int64_t o = pa.offs[a];
   for (int64_t p0 = 0; p0 < len; p0 += 64) {
@@ -202,21 +205,22 @@ __global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const 
     const unsigned long long bm = __ballot(on);
     if (on) {
       const int64_t dst = o + __popcll(bm & ((1ull << lane) - 1ull));
-      pa.out_rep[dst] = ia;
-      pa.out_mem[dst] = pa.order[a + 1 + p];
+      const int ib = pa.order[start + p];
+      pa.out_rep[dst] = pa.partner_is_rep ? ib : ia;
+      pa.out_mem[dst] = pa.partner_is_rep ? ia : ib;
     }
     o += __popcll(bm);
   }
 }
 
-hipError_t launch_prune128(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
-                           uint32_t* mask, bool write, hipStream_t s) {
+hipError_t launch_prune128(const ClipsDev& ca, const ClipsDev& cb, const PruneArgs& pa, Threshold thr,
+                           const int64_t* range_off, uint32_t* mask, bool write, hipStream_t s) {
   for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
     if (write)
       hipLaunchKernelGGL(prune128_write_kernel, dim3(nb), dim3(64), 0, s, pa, range_off, (const uint32_t*)mask, b0);
     else
-      hipLaunchKernelGGL(prune128_bounds_kernel, dim3(nb), dim3(64), 0, s, cs, pa, thr, range_off, mask, b0);
+      hipLaunchKernelGGL(prune128_bounds_kernel, dim3(nb), dim3(64), 0, s, ca, cb, pa, thr, range_off, mask, b0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

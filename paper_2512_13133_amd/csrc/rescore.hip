@@ -19,7 +19,7 @@ namespace ca {
 constexpr int RS_THREADS = 256;
 
 __global__ void __launch_bounds__(RS_THREADS)
-rescore_candidates_kernel(ClipsDev cs, PairIO io, Threshold thr, CandQueue cq,
+rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, CandQueue cq,
                           const double2* __restrict__ tw256, unsigned long long* peak_err_bits,
                           const float* __restrict__ r1_low) {
   __shared__ double red[RS_THREADS];
@@ -32,7 +32,7 @@ rescore_candidates_kernel(ClipsDev cs, PairIO io, Threshold thr, CandQueue cq,
   const int d = gr.dir;
   const int m = gr.count;
   const int j = io.rep[k], i = io.mem[k];
-  const int N = cs.N[i];
+  const int N = cm.N[i];
   const int H = N / 2;
   const int tws = 256 / N;
   if (m == 0) return;
@@ -43,8 +43,8 @@ rescore_candidates_kernel(ClipsDev cs, PairIO io, Threshold thr, CandQueue cq,
     tw[t] = second_half ? make_double2(-base.x, -base.y) : base;
   }
   __syncthreads();
-  const double2* Wi = cs.spec64 + cs.spec_off[i];
-  const double2* Wj = cs.spec64 + cs.spec_off[j];
+  const double2* Wi = cm.spec64 + cm.spec_off[i];
+  const double2* Wj = cr.spec64 + cr.spec_off[j];
   // forward shifts of the candidates (direction 1 reads the mirrored surface)
   int fy[MAX_CAND], fx[MAX_CAND];
   double acc[MAX_CAND];
@@ -96,8 +96,8 @@ rescore_candidates_kernel(ClipsDev cs, PairIO io, Threshold thr, CandQueue cq,
   double best = -1e300;
   for (int c = 0; c < m; ++c) best = fmax(best, s_acc[c]);
   const double cut = best - TAU * (double)K;
-  const uint64_t* bits_i = cs.bits + cs.bits_off[i];
-  const uint64_t* bits_j = cs.bits + cs.bits_off[j];
+  const uint64_t* bits_i = cm.bits + cm.bits_off[i];
+  const uint64_t* bits_j = cr.bits + cr.bits_off[j];
   const uint64_t* brep = d == 0 ? bits_j : bits_i;
   const uint64_t* bmem = d == 0 ? bits_i : bits_j;
   int best_c = -1, best_l1 = 0, best_dy = 0, best_dx = 0;
@@ -116,7 +116,7 @@ rescore_candidates_kernel(ClipsDev cs, PairIO io, Threshold thr, CandQueue cq,
     if (better) { best_c = cnt; best_l1 = l1; best_dy = dy; best_dx = dx; }
   }
   if (tid == 0) {
-    const int n_i = cs.npix[i], n_j = cs.npix[j];
+    const int n_i = cm.npix[i], n_j = cr.npix[j];
     const int nm = d == 0 ? n_i : n_j, nr = d == 0 ? n_j : n_i;
     // the other direction of the pair may be decided concurrently by another
     // workgroup, so the shared byte of cover bits is updated atomically
@@ -125,21 +125,21 @@ rescore_candidates_kernel(ClipsDev cs, PairIO io, Threshold thr, CandQueue cq,
     atomicOr(io.flags + k, d == 0 ? (uint32_t)CA_FLAG_RESCORED_FWD : (uint32_t)CA_FLAG_RESCORED_REV);
     if (peak_err_bits) {
       // compare like with like: both sides normalised by K_hi
-      const double K_hi = (double)(N * N - max(cs.zero_bins[i], cs.zero_bins[j]));
+      const double K_hi = (double)(N * N - max(cm.zero_bins[i], cr.zero_bins[j]));
       const double err = fabs(best / K_hi - (double)r1_low[k * 2 + d]);
       atomicMax(peak_err_bits, (unsigned long long)__double_as_longlong(err));
     }
   }
 }
 
-hipError_t launch_rescore_candidates(const ClipsDev& cs, const PairIO& io, Threshold thr,
+hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                      const CandQueue& cq, int64_t n_groups, const double2* tw256,
                                      unsigned long long* peak_err_bits, const float* r1_low, hipStream_t s) {
   for (int64_t b0 = 0; b0 < n_groups; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, n_groups - b0);
     CandQueue q2 = cq;
     q2.groups = cq.groups + b0;
-    hipLaunchKernelGGL(rescore_candidates_kernel, dim3(nb), dim3(RS_THREADS), 0, s, cs, io, thr, q2, tw256,
+    hipLaunchKernelGGL(rescore_candidates_kernel, dim3(nb), dim3(RS_THREADS), 0, s, cr, cm, io, thr, q2, tw256,
                        peak_err_bits, r1_low);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

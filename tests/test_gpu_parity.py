@@ -375,3 +375,73 @@ def test_prune128_matches_bounds(ctx):
     keys = [(n_pix[a], a) for a in r]
     assert keys == sorted(keys)
     h.close()
+
+
+# ------------------------------------------------------------------ a11 serving
+
+
+def _serving_case(n_library=120, n_requests=4, median=14, seed=77):
+    lib, reqs = clipgen.serving(seed=seed, n_library=n_library, n_requests=n_requests, median=median,
+                                sigma=0.5, max_size=40)
+    return lib, [cs for _, cs in reqs]
+
+
+def _oracle_best(lib, req):
+    both = clipgen.concat([lib, req])
+    nl = lib.n
+    rep = np.repeat(np.arange(nl, dtype=np.int32), req.n)
+    mem = np.tile(np.arange(nl, nl + req.n, dtype=np.int32), nl)
+    res = cover.align_pairs_cosine(both, rep, mem, 19, 20, workers=WORKERS)
+    best = np.full(req.n, -1, np.int32)
+    score = np.zeros(req.n)
+    shift = np.zeros((req.n, 2), np.int16)
+    for k in np.flatnonzero(res["bits"] & 1):
+        i, r, sc = int(mem[k]) - nl, int(rep[k]), res["score"][k, 0]
+        if best[i] < 0 or sc > score[i] or (sc == score[i] and r < best[i]):
+            best[i], score[i], shift[i] = r, sc, res["shift"][k, 0]
+    return best, score, shift
+
+
+def test_serving_matches_oracle_alone_and_in_mix(ctx):
+    import paper_2512_13133_amd as ca
+    lib, reqs = _serving_case()
+    say(f"[serve] library={lib.n} requests={[r.n for r in reqs]}")
+    hlib = ctx.clips(lib)
+    srv = ca.Server(ctx, hlib, (19, 20), slots=3)
+    alone = []
+    for r in reqs:
+        rid = srv.submit(r)
+        srv.wait(rid)
+        alone.append(srv.poll(rid, r.n))
+    ids = [srv.submit(r) for r in reqs]
+    mixed = []
+    for rid, r in zip(ids, reqs):
+        srv.wait(rid)
+        mixed.append(srv.poll(rid, r.n))
+    for a, m in zip(alone, mixed):
+        for key in a:
+            assert (a[key] == m[key]).all(), key
+    matched = 0
+    for r, got in zip(reqs, alone):
+        best, score, shift = _oracle_best(lib, r)
+        assert (got["best_rep"] == best).all()
+        assert (got["matched"] == (best >= 0)).all()
+        ok = best >= 0
+        assert (got["shift"][ok] == shift[ok]).all()
+        assert np.abs(got["score"] - score).max() <= 1e-12
+        matched += int(ok.sum())
+    say(f"[serve] matched {matched} of {sum(r.n for r in reqs)} clips; stats {srv.stats()}")
+    srv.close()
+    hlib.close()
+
+
+def test_serving_admission_budget(ctx):
+    import paper_2512_13133_amd as ca
+    lib, reqs = _serving_case(n_library=40, n_requests=2, median=30, seed=5)
+    hlib = ctx.clips(lib)
+    srv = ca.Server(ctx, hlib, (19, 20), slots=1, hbm_budget_bytes=1 << 20)
+    with pytest.raises(ca.ClipAlignError) as e:
+        srv.submit(reqs[0])
+    assert e.value.status == ca.CA_EBUSY
+    srv.close()
+    hlib.close()
