@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--no-edge", action="store_true", help="skip the edge track (diagnostics only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-library", type=int, default=100_000)
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -189,6 +192,9 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cs, rep.cpu().numpy(), mem.cpu().numpy(), args.cpu_seconds)
     h.close()
+    del out, rep, mem, last
+    torch.cuda.empty_cache()
+    serving = None if args.no_serving else serve_bench(ctx, args.serve_library, args.serve_seconds)
 
     line = {
         "metric": "aligned pairs/s at 128x128 +-16px (mixed-prec batched vs plain FP32); p99 latency",
@@ -206,8 +212,105 @@ def main():
         "plain_fp32": comparator,
         "stage_ms": stage_ms,
         "stats": stats_out,
+        "serving": serving,
     }
     print(json.dumps(line))
+
+
+def serve_bench(ctx, n_library, seconds, slots=4):
+    """Serving: a device-resident library of 128 x 128 representatives (one per
+    template); request batches of log-normal size (median 64, sigma 1, at most
+    10,000 clips) drawn from library templates with jitter 4 and offsets +-16,
+    arriving as a Poisson stream.  First the saturation rate with a full queue,
+    then latency at half of it."""
+    import threading
+
+    import numpy as np
+
+    import clipgen
+    import paper_2512_13133_amd as ca
+    t0 = time.time()
+    lib, _, tpl = clipgen.serving(n_library=n_library, n_requests=0, return_templates=True)
+    rng = np.random.default_rng(2026)
+
+    def make_request():
+        size = int(np.clip(np.rint(rng.lognormal(np.log(64), 1.0)), 1, 10_000))
+        return clipgen.make_clips(rng, tpl, 128, size, 4, 16)
+
+    hlib = ctx.clips(lib)
+    srv = ca.Server(ctx, hlib, (19, 20), slots=slots, hbm_budget_bytes=64 << 30)
+    log(f"[serve] library {lib.n} ready in {time.time() - t0:.1f}s")
+
+    def run(trace, pace):
+        """Submit (arrival_s, ClipSet) requests; return per-request latency (s) and wall time."""
+        lat = [None] * len(trace)
+        pending = {}
+        lock = threading.Lock()
+        finished = threading.Event()
+        start = time.perf_counter()
+
+        def collector():
+            while True:
+                with lock:
+                    items = list(pending.items())
+                for idx, (rid, n, arr) in items:
+                    if srv.poll(rid, n) is not None:
+                        lat[idx] = time.perf_counter() - start - arr
+                        with lock:
+                            del pending[idx]
+                if finished.is_set():
+                    with lock:
+                        if not pending:
+                            return
+                time.sleep(0.0003)
+
+        th = threading.Thread(target=collector)
+        th.start()
+        for idx, (arr, req) in enumerate(trace):
+            if pace:
+                delay = arr - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+            else:
+                arr = time.perf_counter() - start
+            while True:
+                try:
+                    rid = srv.submit(req)
+                    break
+                except ca.ClipAlignError as e:
+                    if e.status != ca.CA_EBUSY:
+                        raise
+                    time.sleep(0.0005)
+            with lock:
+                pending[idx] = (rid, req.n, arr)
+        finished.set()
+        th.join()
+        return np.array(lat), time.perf_counter() - start
+
+    # saturation: everything queued at once
+    warm = [(0.0, make_request()) for _ in range(8)]
+    run(warm, False)
+    sat_trace = [(0.0, make_request()) for _ in range(120)]
+    st0 = srv.stats()
+    lat_sat, wall_sat = run(sat_trace, False)
+    st1 = srv.stats()
+    sat_qps = len(sat_trace) / wall_sat
+    qps = 0.5 * sat_qps
+    n_req = max(20, int(qps * seconds))
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n_req))
+    trace = [(float(a), make_request()) for a in arrivals]
+    lat, wall = run(trace, True)
+    st2 = srv.stats()
+    srv.close()
+    hlib.close()
+    clips = sum(r.n for _, r in trace)
+    return {"library": lib.n, "slots": slots, "saturation_qps": round(sat_qps, 1),
+            "saturation_pairs_per_s": round((st1["candidate_pairs"] - st0["candidate_pairs"]) / wall_sat, 1),
+            "qps_target": round(qps, 1), "qps_achieved": round(n_req / wall, 1), "requests": n_req,
+            "clips": clips, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "pairs_per_s": round((st2["candidate_pairs"] - st1["candidate_pairs"]) / wall, 1),
+            "request_sizes": "round(LogNormal(ln 64, 1)) clipped to [1, 10000]"}
 
 
 def copy_probe(nbytes, reps=3):

@@ -252,7 +252,7 @@ def mixed(seed=SEED_BASE + 3, n_clips=200_000, sizes=(64, 128, 256), ratio=(4, 3
 
 
 def serving(seed=SEED_BASE + 5, n_library=100_000, N=128, jitter=4, w=16,
-            n_requests=200, qps=50.0, median=64, sigma=1.0, max_size=10_000):
+            n_requests=200, qps=50.0, median=64, sigma=1.0, max_size=10_000, return_templates=False):
     """A representative library (one clip per template) and a request trace.
 
     Returns ``(library, requests)`` where ``requests`` is a list of
@@ -271,6 +271,8 @@ def serving(seed=SEED_BASE + 5, n_library=100_000, N=128, jitter=4, w=16,
     for k in range(n_requests):
         cs = make_clips(rng, tpl, N, int(sizes[k]), jitter, w)
         reqs.append((float(t[k]), cs))
+    if return_templates:
+        return lib, reqs, tpl
     return lib, reqs
 
 

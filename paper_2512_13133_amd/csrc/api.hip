@@ -47,7 +47,8 @@ struct ca_clipset {
   int64_t n = 0;
   int flags = 0;
   ClipsDev d{};
-  std::vector<void*> owned;
+  std::vector<std::pair<void*, size_t>> owned;  // allocations freed by ca_clips_destroy
+  capriv::DevArena* arena = nullptr;             // region the set was carved from (not owned)
   std::vector<int16_t> hN, hw;
   std::vector<int32_t> hnpix, hnpoly;
   int maxN = 0, Lmax = 0;
@@ -85,6 +86,27 @@ ca_status dev_alloc(ca_ctx* ctx, void** p, size_t bytes, std::vector<void*>* own
   ctx->used += bytes;
   if (owner) owner->push_back(*p);
   return CA_OK;
+}
+
+// Allocation for a clip set: carved from its arena when it has one and the
+// request fits, else a device allocation the set owns.
+ca_status cs_alloc(ca_ctx* ctx, ca_clipset* cs, void** p, size_t bytes) {
+  if (bytes == 0) {
+    *p = nullptr;
+    return CA_OK;
+  }
+  if (cs->arena) {
+    const size_t at = (cs->arena->used + 255) & ~(size_t)255;
+    if (at + bytes <= cs->arena->cap) {
+      *p = cs->arena->base + at;
+      cs->arena->used = at + bytes;
+      return CA_OK;
+    }
+  }
+  std::vector<void*> tmp;
+  ca_status st = dev_alloc(ctx, p, bytes, &tmp);
+  if (st == CA_OK) cs->owned.emplace_back(*p, bytes);
+  return st;
 }
 
 // Per-call scratch, grown on demand and kept on the context.
@@ -211,7 +233,10 @@ ca_status ca_clips_destroy(ca_clipset* cs) {
   if (!cs) return CA_EINVAL;
   (void)hipSetDevice(cs->ctx->device);
   if (cs->ctx->prune_cache.gen == cs->gen) cs->ctx->prune_cache.gen = 0;
-  for (void* p : cs->owned) (void)hipFree(p);
+  for (auto& pb : cs->owned) {
+    (void)hipFree(pb.first);
+    cs->ctx->used -= pb.second;
+  }
   cs->ctx->live_clipsets--;
   delete cs;
   return CA_OK;
@@ -223,9 +248,9 @@ ca_status ca_clips_count(const ca_clipset* cs, int64_t* n) {
   return CA_OK;
 }
 
-ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr,
-                          const int32_t* rects, const int16_t* raster_n, const int16_t* marker_w,
-                          int32_t flags, ca_clipset** out) {
+static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr,
+                                   const int32_t* rects, const int16_t* raster_n, const int16_t* marker_w,
+                                   int32_t flags, capriv::DevArena* arena, ca_clipset** out) {
   if (!ctx) return CA_EINVAL;
   if (!out || !rect_ptr || !raster_n || !marker_w || n <= 0 || n > (1ll << 31) - 1)
     return fail(ctx, CA_EINVAL, "bad clip-set arguments");
@@ -258,6 +283,7 @@ ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
   ca_clipset* cs = new ca_clipset();
   cs->ctx = ctx;
   cs->gen = ctx->next_gen++;
+  cs->arena = arena;
   cs->n = n;
   cs->flags = flags | CA_CLIPS_FP64;  // FP64 spectra back the re-decision pass
   cs->hN = hN;
@@ -285,19 +311,19 @@ ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
   ca_status st;
 #define ALLOC(field, type, count)                                              \
   do {                                                                         \
-    st = dev_alloc(ctx, &p, sizeof(type) * (size_t)(count), &cs->owned);       \
+    st = cs_alloc(ctx, cs, &p, sizeof(type) * (size_t)(count));                \
     if (st != CA_OK) return bail(st);                                          \
     cs->d.field = (type*)p;                                                    \
   } while (0)
   int16_t *dN, *dw;
   int64_t *dbo, *dso, *dro, *dspo, *drun_off;
-  st = dev_alloc(ctx, &p, sizeof(int16_t) * n, &cs->owned); if (st) return bail(st); dN = (int16_t*)p;
-  st = dev_alloc(ctx, &p, sizeof(int16_t) * n, &cs->owned); if (st) return bail(st); dw = (int16_t*)p;
-  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); dbo = (int64_t*)p;
-  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); dso = (int64_t*)p;
-  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); dro = (int64_t*)p;
-  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); dspo = (int64_t*)p;
-  st = dev_alloc(ctx, &p, sizeof(int64_t) * n, &cs->owned); if (st) return bail(st); drun_off = (int64_t*)p;
+  st = cs_alloc(ctx, cs, &p, sizeof(int16_t) * n); if (st) return bail(st); dN = (int16_t*)p;
+  st = cs_alloc(ctx, cs, &p, sizeof(int16_t) * n); if (st) return bail(st); dw = (int16_t*)p;
+  st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); dbo = (int64_t*)p;
+  st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); dso = (int64_t*)p;
+  st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); dro = (int64_t*)p;
+  st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); dspo = (int64_t*)p;
+  st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); drun_off = (int64_t*)p;
   cs->d.n = n;
   cs->d.N = dN; cs->d.w = dw; cs->d.bits_off = dbo; cs->d.sig_off = dso;
   cs->d.rowptr_off = dro; cs->d.spec_off = dspo; cs->d.run_off = drun_off;
@@ -326,13 +352,12 @@ ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
   // inputs on the device
   const int64_t* d_ptr = rect_ptr;
   const int32_t* d_rects = rects;
-  std::vector<void*> temp;
-  if (!on_dev) {
-    st = dev_alloc(ctx, &p, sizeof(int64_t) * (n + 1), &temp); if (st) return bail(st);
+  if (!on_dev) {  // inputs copied into the set's own memory (kept with the set)
+    st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * (n + 1)); if (st) return bail(st);
     d_ptr = (const int64_t*)p;
     HIP_OR_FAIL(ctx, hipMemcpyAsync(p, rect_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
     if (m > 0) {
-      st = dev_alloc(ctx, &p, sizeof(int32_t) * 4 * m, &temp); if (st) return bail(st);
+      st = cs_alloc(ctx, cs, &p, sizeof(int32_t) * 4 * m); if (st) return bail(st);
       d_rects = (const int32_t*)p;
       HIP_OR_FAIL(ctx, hipMemcpyAsync(p, rects, sizeof(int32_t) * 4 * m, hipMemcpyHostToDevice, s));
     }
@@ -341,8 +366,6 @@ ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
   std::vector<int32_t> nruns(n);
   HIP_OR_FAIL(ctx, hipMemcpyAsync(nruns.data(), cs->d.nruns, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
-  for (void* t : temp) (void)hipFree(t);
-  if (!on_dev) ctx->used -= sizeof(int64_t) * (n + 1) + (m > 0 ? sizeof(int32_t) * 4 * m : 0);
   std::vector<int64_t> run_off(n);
   int64_t total_runs = 0;
   for (int64_t i = 0; i < n; ++i) {
@@ -380,6 +403,12 @@ ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
 #undef ALLOC
   *out = cs;
   return CA_OK;
+}
+
+ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr,
+                          const int32_t* rects, const int16_t* raster_n, const int16_t* marker_w,
+                          int32_t flags, ca_clipset** out) {
+  return clips_create_impl(ctx, stream, n, rect_ptr, rects, raster_n, marker_w, flags, nullptr, out);
 }
 
 ca_status ca_clips_inspect(const ca_clipset* cs, int64_t i, uint64_t* bits, int32_t* n_pix,
@@ -548,6 +577,10 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
 }
 
 namespace capriv {
+ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr, const int32_t* rects,
+                          const int16_t* raster_n, const int16_t* marker_w, DevArena* arena, ca_clipset** out) {
+  return clips_create_impl(ctx, stream, n, rect_ptr, rects, raster_n, marker_w, 0, arena, out);
+}
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
                             Threshold thr, int path, const PairIO& io) {
   return align_cosine(ctx, crs, cms, s, thr, path, io);

@@ -43,6 +43,8 @@ int64_t n_of(const ca_clipset* cs);
 bool mixed_ok_of(const ca_clipset* cs);
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
                             ca::Threshold thr, int path, const ca::PairIO& io);
+ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr, const int32_t* rects,
+                          const int16_t* raster_n, const int16_t* marker_w, DevArena* arena, ca_clipset** out);
 }  // namespace capriv
 
 using namespace ca;
@@ -68,9 +70,9 @@ struct Request {
 };
 
 // Per-request device footprint estimate: the batch clip set (bits, tables,
-// FP16 + FP64 spectra at 128 x 128) and up to 4096 candidates per clip with
-// their outputs and prune scratch.
-uint64_t estimate_bytes(int64_t n) { return (uint64_t)n * (180000ull + 4096ull * 64ull); }
+// runs, FP16 + FP64 spectra at 128 x 128) and up to 4096 candidates per clip
+// with their outputs and prune scratch.  It also sizes the slot's arena.
+uint64_t estimate_bytes(int64_t n) { return (uint64_t)n * (200000ull + 4096ull * 64ull) + (1ull << 20); }
 
 }  // namespace
 
@@ -85,6 +87,7 @@ struct ca_server {
   int32_t* d_order = nullptr;
   std::vector<ca_ctx*> slot_ctx;
   std::vector<hipStream_t> slot_stream;
+  std::vector<capriv::DevArena> slot_arena;
   std::vector<std::thread> workers;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -116,9 +119,24 @@ ca_status srv_fail(ca_server* srv, ca_status st, const std::string& msg) {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Carve from the slot arena, else allocate (the caller frees what it allocated).
+hipError_t slot_alloc(capriv::DevArena& ar, void** p, size_t bytes, std::vector<void*>& extra) {
+  const size_t at = al(ar.used);
+  if (at + bytes <= ar.cap) {
+    *p = ar.base + at;
+    ar.used = at + bytes;
+    return hipSuccess;
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) extra.push_back(*p);
+  return e;
+}
+
 void run_request(ca_server* srv, int slot, Request* req) {
   ca_ctx* ctx = srv->slot_ctx[slot];
   hipStream_t s = srv->slot_stream[slot];
+  capriv::DevArena& arena = srv->slot_arena[slot];
+  std::vector<void*> extra;  // allocations beyond the arena (rare)
   ca_clipset* rc = nullptr;
   void* buf = nullptr;
   const int64_t n = req->n;
@@ -130,8 +148,19 @@ void run_request(ca_server* srv, int slot, Request* req) {
   std::vector<uint8_t> h_bits;
   std::vector<int16_t> h_shift;
   std::vector<double> h_score;
-  req->status = ca_clips_create(ctx, s, n, req->rect_ptr.data(), req->rects.empty() ? nullptr : req->rects.data(),
-                                req->raster_n.data(), req->marker_w.data(), 0, &rc);
+  // grow the slot's arena (only when a larger request than any before arrives)
+  {
+    const size_t want = (size_t)req->est_bytes;
+    if (arena.cap < want) {
+      if (arena.base) (void)hipFree(arena.base);
+      arena.base = nullptr;
+      arena.cap = 0;
+      if (hipMalloc((void**)&arena.base, want) == hipSuccess) arena.cap = want;
+    }
+    arena.used = 0;
+  }
+  req->status = clips_create_in(ctx, s, n, req->rect_ptr.data(), req->rects.empty() ? nullptr : req->rects.data(),
+                                req->raster_n.data(), req->marker_w.data(), &arena, &rc);
   if (req->status != CA_OK) {
     req->error = ca_last_error(ctx);
     goto cleanup;
@@ -165,7 +194,7 @@ void run_request(ca_server* srv, int slot, Request* req) {
   {
     const size_t b_a = al(4 * (size_t)n), b_r = al(8 * (size_t)n), b_m = al(4 * (size_t)(bits / 32 + 1));
     const size_t bytes = 3 * b_a + 3 * b_r + b_m;
-    RUN_HIP(hipMalloc(&buf, bytes));
+    RUN_HIP(slot_alloc(arena, &buf, bytes, extra));
     char* c = (char*)buf;
     int32_t* d_anchor = (int32_t*)c; c += b_a;
     int32_t* d_lo = (int32_t*)c; c += b_a;
@@ -193,7 +222,7 @@ void run_request(ca_server* srv, int slot, Request* req) {
       void* out = nullptr;
       const size_t o4 = al(4 * (size_t)total), o1 = al((size_t)total), o8 = al(8 * (size_t)total),
                    o16 = al(16 * (size_t)total);
-      RUN_HIP(hipMalloc(&out, 2 * o4 + o1 + o8 + o8 + o16 + o4));
+      RUN_HIP(slot_alloc(arena, &out, 2 * o4 + o1 + o8 + o8 + o16 + o4, extra));
       char* o = (char*)out;
       int32_t* d_rep = (int32_t*)o; o += o4;
       int32_t* d_mem = (int32_t*)o; o += o4;
@@ -231,7 +260,6 @@ void run_request(ca_server* srv, int slot, Request* req) {
           req->error = hipGetErrorString(e1);
         }
       }
-      (void)hipFree(out);
       if (req->status != CA_OK) goto cleanup;
     }
   }
@@ -253,8 +281,8 @@ void run_request(ca_server* srv, int slot, Request* req) {
     }
   }
 cleanup:
-  if (buf) (void)hipFree(buf);
   if (rc) ca_clips_destroy(rc);
+  for (void* x : extra) (void)hipFree(x);
 }
 
 void worker_main(ca_server* srv, int slot) {
@@ -327,6 +355,7 @@ extern "C" ca_status ca_server_create(ca_ctx* ctx, const ca_clipset* library, co
     }
     srv->slot_ctx.push_back(sc);
     srv->slot_stream.push_back(st);
+    srv->slot_arena.emplace_back();
   }
   for (int sl = 0; sl < slots; ++sl) srv->workers.emplace_back(worker_main, srv, sl);
   *out = srv;
@@ -344,6 +373,7 @@ extern "C" ca_status ca_server_destroy(ca_server* srv) {
   for (size_t k = 0; k < srv->slot_ctx.size(); ++k) {
     ca_destroy(srv->slot_ctx[k]);
     (void)hipStreamDestroy(srv->slot_stream[k]);
+    if (srv->slot_arena[k].base) (void)hipFree(srv->slot_arena[k].base);
   }
   (void)hipFree(srv->d_order);
   for (auto& kv : srv->reqs) delete kv.second;

@@ -18,4 +18,13 @@ struct PruneCache {
   std::vector<int64_t> counts;
 };
 
+// Grow-only device region that a serving slot reuses for every request, so the
+// steady state makes no hipMalloc / hipFree calls (hipFree waits for the
+// device).  Allocations that do not fit fall back to hipMalloc.
+struct DevArena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+
 }  // namespace capriv

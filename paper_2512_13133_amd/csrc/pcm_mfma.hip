@@ -41,10 +41,27 @@ typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
+// The arrays of a clip set the kernel reads (a compact kernel argument).
+struct MfView {
+  const __half2* spec16;
+  const int64_t* spec_off;
+  const uint64_t* bits;
+  const int64_t* bits_off;
+  const int32_t* npix;
+  const int16_t* w;
+  const int32_t* zero_bins;
+};
+
+__host__ inline MfView mf_view(const ClipsDev& c) {
+  return MfView{c.spec16, c.spec_off, c.bits, c.bits_off, c.npix, c.w, c.zero_bins};
+}
+
 constexpr int MF_N = 128;
 constexpr int MF_TILE = 64;
 constexpr int MF_ROW_H2 = 68;           // LDS row stride of the staged spectrum (half2), padded
 constexpr int MF_SPEC_H2 = MF_N * MF_ROW_H2 + MF_N;
+constexpr int MF_SPEC_BYTES = (MF_N * 64 + MF_N) * 4;  // one clip's FP16 half-spectrum
+constexpr int MF_RSRC_WORD3 = 0x00020000;               // raw buffer, 32-bit data format
 
 __device__ __forceinline__ h2_t as_h2(uint32_t x) { return __builtin_bit_cast(h2_t, x); }
 __device__ __forceinline__ uint32_t as_u32(h2_t x) { return __builtin_bit_cast(uint32_t, x); }
@@ -58,6 +75,20 @@ __device__ __forceinline__ h2_t cmulc_h2(h2_t m, h2_t r) {
   const h2_t ri = {r.y, -r.y};
   const h2_t ms = {m.y, m.x};
   return m * rr + ms * ri;
+}
+
+// The lane's share of the member's 16-row block mb: four 16-byte K chunks of
+// row 16 mb + col, and the Nyquist column at rows 16 mb + 4 g .. + 3.  Buffer
+// loads (bounded by the spectrum's size) through a wave-uniform descriptor.
+__device__ __forceinline__ void load_member_block(__amdgpu_buffer_rsrc_t rs, int mb, int col, int g, uint4* out) {
+  const int u = mb * 16 + col;
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (u * 64 + kb * 16 + g * 4) * 4, 0, 0);
+    out[kb] = uint4{v[0], v[1], v[2], v[3]};
+  }
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (MF_N * 64 + mb * 16 + g * 4) * 4, 0, 0);
+  out[4] = uint4{v[0], v[1], v[2], v[3]};
 }
 
 // Top value, its position and the runner-up over the wave (positions break ties low).
@@ -151,7 +182,7 @@ __device__ __noinline__ void queue_candidates(const float* sw, int d, int wd, fl
 }
 
 __global__ void __launch_bounds__(256, 2)
-pcm_mfma128_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, float band, RescoreQueue q, CandQueue cq,
+pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, RescoreQueue q, CandQueue cq,
                    const h8_t* b1frag, const h8_t* a2frag, float* surf_out, int64_t block0) {
   __shared__ __align__(16) uint32_t s_spec[MF_SPEC_H2];   // representative W (half2)
   __shared__ __align__(16) h8_t s_a2[8 * 3 * 64];          // stage-2 twiddles
@@ -210,7 +241,10 @@ pcm_mfma128_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, float ban
         }
         continue;
       }
-      const uint32_t* mspec = reinterpret_cast<const uint32_t*>(cm.spec16 + cm.spec_off[i]);
+      const int64_t moff = (int64_t)__builtin_amdgcn_readfirstlane((int)(cm.spec_off[i] >> 32)) << 32 |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)cm.spec_off[i]);
+      const __amdgpu_buffer_rsrc_t mrs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(cm.spec16 + moff), (short)0, MF_SPEC_BYTES, MF_RSRC_WORD3);
       // stage-1 twiddles (4 K-blocks x 3 dx-blocks) for this lane; cached, and
       // not live across the peak search
       h8_t B1[4][3];
@@ -224,16 +258,23 @@ pcm_mfma128_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, float ban
 #pragma unroll
         for (int b = 0; b < 3; ++b) D2[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
 
+      // The member's 16-row block mb+1 is loaded while block mb is computed
+      // (register double buffer), so one block's HBM latency hides behind the
+      // previous block's matrix work.
+      uint4 mcur[5];
+      load_member_block(mrs, 0, col, g, mcur);
 #pragma unroll 1
       for (int mb = 0; mb < 8; ++mb) {
         const int u = mb * 16 + col;  // A-operand row of this lane
+        uint4 mnext[5];
+        load_member_block(mrs, min(mb + 1, 7), col, g, mnext);
         // D1[2 db] = Tr, D1[2 db + 1] = Ti for dx = 16 db - 16 + col
         f4_t D1[6];
 #pragma unroll
         for (int nb = 0; nb < 6; ++nb) D1[nb] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          const uint4 mv = *reinterpret_cast<const uint4*>(mspec + u * 64 + kb * 16 + g * 4);
+          const uint4 mv = mcur[kb];
           const uint4 rv = *reinterpret_cast<const uint4*>(&s_spec[u * MF_ROW_H2 + kb * 16 + g * 4]);
           const h2_t r0 = cmulc_h2(as_h2(mv.x), as_h2(rv.x));
           const h2_t r1 = cmulc_h2(as_h2(mv.y), as_h2(rv.y));
@@ -251,7 +292,7 @@ pcm_mfma128_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, float ban
         // Nyquist column v = 64: T(u, dx) += R(u, 64) (-1)^dx for the lane's 4 rows
         {
           const int u0 = mb * 16 + g * 4;
-          const uint4 mv = *reinterpret_cast<const uint4*>(mspec + MF_N * 64 + u0);
+          const uint4 mv = mcur[4];
           const uint4 rv = *reinterpret_cast<const uint4*>(&s_spec[MF_N * MF_ROW_H2 + u0]);
           const h2_t n0 = cmulc_h2(as_h2(mv.x), as_h2(rv.x));
           const h2_t n1 = cmulc_h2(as_h2(mv.y), as_h2(rv.y));
@@ -281,6 +322,8 @@ pcm_mfma128_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, float ban
             D2[yb][db] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2, B2, D2[yb][db], 0, 0, 0);
           }
         }
+#pragma unroll
+        for (int t = 0; t < 5; ++t) mcur[t] = mnext[t];
       }
 
       // window surface to LDS: D2[yb][db][t] holds K r(dy, dx) at
@@ -392,7 +435,7 @@ hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const Pair
   const int64_t blocks = (io.n_pairs + MF_TILE - 1) / MF_TILE;
   for (int64_t b0 = 0; b0 < blocks; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, blocks - b0);
-    hipLaunchKernelGGL(pcm_mfma128_kernel, dim3(nb), dim3(256), 0, s, cr, cm, io, thr, band, q, cq,
+    hipLaunchKernelGGL(pcm_mfma128_kernel, dim3(nb), dim3(256), 0, s, mf_view(cr), mf_view(cm), io, thr, band, q, cq,
                        (const h8_t*)b1frag, (const h8_t*)a2frag, surf_out, b0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
