@@ -69,6 +69,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP32 comparator")
     ap.add_argument("--serve-library", type=int, default=100_000)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -169,7 +170,7 @@ def main():
     kernel_rate = n_pairs / (main_ms * 1e-3) if main_ms > 0 else None
     # plain FP32 per-pair comparator on the identical pair list
     comparator = None
-    if args.path == "mixed":
+    if args.path == "mixed" and not args.no_comparator:
         h32 = make_clips(fp32=True)
         ctx.align_pairs(h32, rep, mem, "cosine", (19, 20), "fp32")  # warm
         ctx.reset_stats()

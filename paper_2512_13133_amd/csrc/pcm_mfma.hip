@@ -229,7 +229,7 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
 
     for (int p = seg + wave; p < seg_end; p += 4) {
       const int64_t k = base + p;
-      const int i = io.mem[k];
+      const int i = __builtin_amdgcn_readfirstlane(io.mem[k]);
       const int n_i = cm.npix[i], w_i = cm.w[i], z_i = cm.zero_bins[i];
       if (n_i == 0 || n_j == 0) {
         if (lane == 0) {
@@ -258,23 +258,16 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
 #pragma unroll
         for (int b = 0; b < 3; ++b) D2[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-      // The member's 16-row block mb+1 is loaded while block mb is computed
-      // (register double buffer), so one block's HBM latency hides behind the
-      // previous block's matrix work.
-      uint4 mcur[5];
-      load_member_block(mrs, 0, col, g, mcur);
-#pragma unroll 1
-      for (int mb = 0; mb < 8; ++mb) {
+      // One 16-row block of both stages from the member data mv[0..4] of block mb.
+      auto block = [&](int mb, const uint4* mv5) {
         const int u = mb * 16 + col;  // A-operand row of this lane
-        uint4 mnext[5];
-        load_member_block(mrs, min(mb + 1, 7), col, g, mnext);
         // D1[2 db] = Tr, D1[2 db + 1] = Ti for dx = 16 db - 16 + col
         f4_t D1[6];
 #pragma unroll
         for (int nb = 0; nb < 6; ++nb) D1[nb] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          const uint4 mv = mcur[kb];
+          const uint4 mv = mv5[kb];
           const uint4 rv = *reinterpret_cast<const uint4*>(&s_spec[u * MF_ROW_H2 + kb * 16 + g * 4]);
           const h2_t r0 = cmulc_h2(as_h2(mv.x), as_h2(rv.x));
           const h2_t r1 = cmulc_h2(as_h2(mv.y), as_h2(rv.y));
@@ -292,7 +285,7 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         // Nyquist column v = 64: T(u, dx) += R(u, 64) (-1)^dx for the lane's 4 rows
         {
           const int u0 = mb * 16 + g * 4;
-          const uint4 mv = mcur[4];
+          const uint4 mv = mv5[4];
           const uint4 rv = *reinterpret_cast<const uint4*>(&s_spec[MF_N * MF_ROW_H2 + u0]);
           const h2_t n0 = cmulc_h2(as_h2(mv.x), as_h2(rv.x));
           const h2_t n1 = cmulc_h2(as_h2(mv.y), as_h2(rv.y));
@@ -322,63 +315,114 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
             D2[yb][db] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2, B2, D2[yb][db], 0, 0, 0);
           }
         }
+      };
+      // The member's blocks are double-buffered in registers: block mb+1 loads
+      // while block mb computes, so one block's HBM latency hides behind the
+      // previous block's matrix work.
+      uint4 mcur[5];
+      load_member_block(mrs, 0, col, g, mcur);
+#pragma unroll 1
+      for (int mb = 0; mb < 8; ++mb) {
+        uint4 mnext[5];
+        load_member_block(mrs, min(mb + 1, 7), col, g, mnext);
+        block(mb, mcur);
 #pragma unroll
         for (int t = 0; t < 5; ++t) mcur[t] = mnext[t];
       }
 
-      // window surface to LDS: D2[yb][db][t] holds K r(dy, dx) at
-      // dy = 16 yb - 16 + 4 g + t, dx = 16 db - 16 + col (valid up to 16)
-      float* sw = s_surf[wave];
-#pragma unroll
-      for (int yb = 0; yb < 3; ++yb)
-#pragma unroll
-        for (int db = 0; db < 3; ++db)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const bool ok = (yb < 2 || (g == 0 && t == 0)) && (db < 2 || col == 0);
-            if (ok) sw[(4 * g + t) * 33 + col + (16 * yb * 33 + 16 * db)] = D2[yb][db][t];
-          }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // D2[yb][db][t] holds K r(dy, dx) at dy = 16 yb - 16 + 4 g + t,
+      // dx = 16 db - 16 + col (rows and columns valid up to 16).  Window
+      // position of a shift: (dy + 16) * 33 + (dx + 16).
       const int K_hi = MF_N * MF_N - max(z_i, z_j);
-      if (surf_out) {
-        float* so = surf_out + k * 33 * 33;
-        for (int t = lane; t < 33 * 33; t += 64) so[t] = sw[t] / (float)K_hi;
+      // The lane coordinates pass through an empty asm statement so that the
+      // positions and window tests derived from them are formed here, per
+      // pair, and are not hoisted to live across the matrix loop.
+      int gl = g, cl = col;
+      asm volatile("" : "+v"(gl), "+v"(cl));
+      // Top two values over the window |dy|, |dx| <= wd and the lowest position
+      // of the top one, straight from the registers (a lane visits its
+      // positions in increasing order).  The reverse direction's value at
+      // shift s is the forward value at -s and the window is symmetric, so the
+      // same search over the reverse window gives the reverse top two; its
+      // position mirrors.
+      auto top2 = [&](int wd, float& v1, int& i1, float& v2) {
+        v1 = -3.0e38f;
+        v2 = -3.0e38f;
+        i1 = 0x7fffffff;
+#pragma unroll
+        for (int yb = 0; yb < 3; ++yb)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int db = 0; db < 3; ++db) {
+              const int dy = 16 * yb - 16 + 4 * gl + t, dx = 16 * db - 16 + cl;
+              const bool ok = dy >= -wd && dy <= wd && dx >= -wd && dx <= wd;
+              const float v = ok ? D2[yb][db][t] : -3.0e38f;
+              v2 = fmaxf(v2, fminf(v, v1));
+              if (v > v1) {
+                v1 = v;
+                i1 = (dy + 16) * 33 + dx + 16;
+              }
+            }
+        wave_top2(v1, i1, v2);
+      };
+      float v1f, v2f, v1r, v2r;
+      int i1f, i1r;
+      top2(w_i, v1f, i1f, v2f);
+      if (w_j == w_i) {
+        v1r = v1f;
+        v2r = v2f;
+        i1r = i1f;
+      } else {
+        top2(w_j, v1r, i1r, v2r);
       }
+      // forward shift and the reverse one (mirror of the reverse top position)
+      const int sy0 = i1f / 33 - 16, sx0 = i1f % 33 - 16;
+      const int sy1 = 16 - i1r / 33, sx1 = 16 - i1r % 33;
+      const uint64_t* mbits = cm.bits + cm.bits_off[i];
+      // c(s) of the reverse direction at -s equals the forward c(s)
+      const int c0 = wave_overlap128(s_bits, mbits, sy0, sx0);
+      const int c1 = i1r == i1f ? c0 : wave_overlap128(mbits, s_bits, sy1, sx1);
+      const bool dec0 = (v1f - v2f) >= band * (float)K_hi;
+      const bool dec1 = (v1r - v2r) >= band * (float)K_hi;
       if (lane == 0) {
-        io.bits[k] = 0;
+        const bool b0 = cosine_bit(c0, n_i, n_j, thr), b1 = cosine_bit(c1, n_j, n_i, thr);
+        io.shift[k * 4 + 0] = (int16_t)sy0;
+        io.shift[k * 4 + 1] = (int16_t)sx0;
+        io.shift[k * 4 + 2] = (int16_t)sy1;
+        io.shift[k * 4 + 3] = (int16_t)sx1;
+        io.count[k * 2 + 0] = c0;
+        io.count[k * 2 + 1] = c1;
+        io.score[k * 2 + 0] = cosine_score(c0, n_i, n_j);
+        io.score[k * 2 + 1] = cosine_score(c1, n_j, n_i);
+        io.bits[k] = (uint8_t)((b0 ? 1u : 0u) | (b1 ? 2u : 0u));
         io.flags[k] = 0;
         if (q.need) q.need[k] = 0;
       }
-      for (int d = 0; d < 2; ++d) {
-        const int wd = d == 0 ? w_i : w_j;
-        float v1 = -3.0e38f, v2 = -3.0e38f;
-        int i1 = 0x7fffffff;
-        for (int t = lane; t < 33 * 33; t += 64) {
-          // direction-d shift s at window position t; the surface holds forward
-          // shifts, so the reverse direction reads the mirrored position
-          const int sy = t / 33 - 16, sx = t - (t / 33) * 33 - 16;
-          if (sy < -wd || sy > wd || sx < -wd || sx > wd) continue;
-          const float v = sw[d == 0 ? t : (33 * 33 - 1 - t)];
-          if (v > v1 || (v == v1 && t < i1)) {
-            v2 = v1;
-            v1 = v;
-            i1 = t;
-          } else {
-            v2 = fmaxf(v2, v);
-          }
+      if (!dec0 || !dec1 || surf_out) {
+        // the window surface goes to the wave's LDS tile for the candidate
+        // queue (and the surface output)
+        float* sw = s_surf[wave];
+#pragma unroll
+        for (int yb = 0; yb < 3; ++yb)
+#pragma unroll
+          for (int db = 0; db < 3; ++db)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const bool ok = (yb < 2 || (gl == 0 && t == 0)) && (db < 2 || cl == 0);
+              if (ok) sw[(4 * gl + t) * 33 + cl + (16 * yb * 33 + 16 * db)] = D2[yb][db][t];
+            }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (surf_out) {
+          float* so = surf_out + k * 33 * 33;
+          for (int t = lane; t < 33 * 33; t += 64) so[t] = sw[t] / (float)K_hi;
         }
-        wave_top2(v1, i1, v2);
-        const int sy = i1 / 33 - 16, sx = i1 % 33 - 16;
-        const uint64_t* brep = d == 0 ? s_bits : cm.bits + cm.bits_off[i];
-        const uint64_t* bmem = d == 0 ? cm.bits + cm.bits_off[i] : s_bits;
-        const int c = wave_overlap128(brep, bmem, sy, sx);
-        const int nm = d == 0 ? n_i : n_j, nr = d == 0 ? n_j : n_i;
-        const bool decided = (v1 - v2) >= band * (float)K_hi;
-        if (lane == 0)
-          write_direction(io, k, d, sy, sx, c, cosine_score(c, nm, nr), cosine_bit(c, nm, nr, thr));
-        if (!decided) queue_candidates(sw, d, wd, v1 - band * (float)K_hi, v1 / (float)K_hi, k, lane, q, cq);
+        if (!dec0) queue_candidates(sw, 0, w_i, v1f - band * (float)K_hi, v1f / (float)K_hi, k, lane, q, cq);
+        if (!dec1) queue_candidates(sw, 1, w_j, v1r - band * (float)K_hi, v1r / (float)K_hi, k, lane, q, cq);
+        // the tile is rewritten by the wave's next pair only after every lane is done reading
+        __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
