@@ -91,6 +91,13 @@ __device__ __forceinline__ void load_member_block(__amdgpu_buffer_rsrc_t rs, int
   out[4] = uint4{v[0], v[1], v[2], v[3]};
 }
 
+// A wave-uniform 64-bit value from lane l.
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Top value, its position and the runner-up over the wave (positions break ties low).
 __device__ __forceinline__ void wave_top2(float& v1, int& i1, float& v2) {
 #pragma unroll
@@ -193,12 +200,24 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar) pair indices
   const int g = lane >> 4;      // k-group of the lane
   const int col = lane & 15;    // row (A) / column (B, C) of the lane in a 16x16 block
   const int64_t base = (block0 + (int64_t)blockIdx.x) * MF_TILE;
   const int cnt = (int)min((int64_t)MF_TILE, io.n_pairs - base);
 
+  // Member metadata of the tile, pair base + l on lane l of every wave (read
+  // per pair with readlane), loaded once so no pair waits on a chain of
+  // dependent loads.  w in the low and the zero-bin count in the high half.
+  int t_i = 0, t_n = 0, t_wz = 0;
+  int64_t t_so = 0, t_bo = 0;
+  if (lane < cnt) {
+    t_i = io.mem[base + lane];
+    t_so = cm.spec_off[t_i];
+    t_bo = cm.bits_off[t_i];
+    t_n = cm.npix[t_i];
+    t_wz = ((int)cm.w[t_i] & 0xffff) | (cm.zero_bins[t_i] << 16);
+  }
   for (int t = tid; t < 8 * 3 * 64; t += 256) s_a2[t] = a2frag[t];
   if (tid < cnt) s_rep[tid] = io.rep[base + tid];
   __syncthreads();
@@ -227,11 +246,17 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
     const int seg_end = s_seg_end;
     const int n_j = cr.npix[j], w_j = cr.w[j], z_j = cr.zero_bins[j];
 
+    // block 0 of the wave's next pair in the segment is loaded during the
+    // current pair's last block; m_cur holds it when have0 is set
+    uint4 m_cur[5];
+    bool have0 = false;
     for (int p = seg + wave; p < seg_end; p += 4) {
       const int64_t k = base + p;
-      const int i = __builtin_amdgcn_readfirstlane(io.mem[k]);
-      const int n_i = cm.npix[i], w_i = cm.w[i], z_i = cm.zero_bins[i];
+      const int n_i = __builtin_amdgcn_readlane(t_n, p);
+      const int wz = __builtin_amdgcn_readlane(t_wz, p);
+      const int w_i = (int)(int16_t)(wz & 0xffff), z_i = wz >> 16;
       if (n_i == 0 || n_j == 0) {
+        have0 = false;
         if (lane == 0) {
           io.bits[k] = 0;
           io.flags[k] = CA_FLAG_EMPTY;
@@ -241,10 +266,25 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         }
         continue;
       }
-      const int64_t moff = (int64_t)__builtin_amdgcn_readfirstlane((int)(cm.spec_off[i] >> 32)) << 32 |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)cm.spec_off[i]);
-      const __amdgpu_buffer_rsrc_t mrs = __builtin_amdgcn_make_buffer_rsrc(
-          (void*)(cm.spec16 + moff), (short)0, MF_SPEC_BYTES, MF_RSRC_WORD3);
+      // this pair's spectrum, and the next pair's or an empty range (its loads
+      // read nothing) at the segment's end; wave-uniform, so the buffer
+      // descriptors are scalar
+      const __half2* mptr = cm.spec16 + readlane64(t_so, p);
+      const bool has_next = p + 4 < seg_end;
+      const __half2* nptr = cm.spec16 + readlane64(t_so, has_next ? p + 4 : p);
+      const int nbytes = has_next ? MF_SPEC_BYTES : 0;
+      const __amdgpu_buffer_rsrc_t mrs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)mptr, (short)0, MF_SPEC_BYTES, MF_RSRC_WORD3);
+      // The member's bit raster (2 KB) goes to the wave's LDS tile by direct
+      // global-to-LDS loads, which complete during the matrix loop; the overlap
+      // count reads it there.
+      uint64_t* mtile = reinterpret_cast<uint64_t*>(s_surf[wave]);
+      {
+        const uint64_t* mb_src = cm.bits + readlane64(t_bo, p) + 2 * lane;
+        __builtin_amdgcn_global_load_lds((const void*)mb_src, (__attribute__((address_space(3))) void*)mtile, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void*)(mb_src + 128),
+                                         (__attribute__((address_space(3))) void*)(mtile + 128), 16, 0, 0);
+      }
       // stage-1 twiddles (4 K-blocks x 3 dx-blocks) for this lane; cached, and
       // not live across the peak search
       h8_t B1[4][3];
@@ -316,19 +356,22 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
           }
         }
       };
-      // The member's blocks are double-buffered in registers: block mb+1 loads
-      // while block mb computes, so one block's HBM latency hides behind the
-      // previous block's matrix work.
-      uint4 mcur[5];
-      load_member_block(mrs, 0, col, g, mcur);
+      // The member's blocks are double-buffered in registers: block mb+1 (or
+      // the next pair's block 0) loads while block mb computes, so the HBM
+      // latency hides behind the previous block's matrix work.
+      if (!have0) load_member_block(mrs, 0, col, g, m_cur);
 #pragma unroll 1
       for (int mb = 0; mb < 8; ++mb) {
         uint4 mnext[5];
-        load_member_block(mrs, min(mb + 1, 7), col, g, mnext);
-        block(mb, mcur);
+        const bool last = mb == 7;
+        load_member_block(__builtin_amdgcn_make_buffer_rsrc((void*)(last ? nptr : mptr), (short)0,
+                                                            last ? nbytes : MF_SPEC_BYTES, MF_RSRC_WORD3),
+                          last ? 0 : mb + 1, col, g, mnext);
+        block(mb, m_cur);
 #pragma unroll
-        for (int t = 0; t < 5; ++t) mcur[t] = mnext[t];
+        for (int t = 0; t < 5; ++t) m_cur[t] = mnext[t];
       }
+      have0 = has_next;
 
       // D2[yb][db][t] holds K r(dy, dx) at dy = 16 yb - 16 + 4 g + t,
       // dx = 16 db - 16 + col (rows and columns valid up to 16).  Window
@@ -366,10 +409,48 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
             }
         wave_top2(v1, i1, v2);
       };
+      // Both windows cover the whole tile (half-window 16): no window tests,
+      // only the tile's partial row dy = 16 (lanes g == 0, t == 0) and
+      // column dx = 16 (lanes col == 0).  Four operations a value: the
+      // runner-up is the median of (value, top, runner-up).  The top one is
+      // tracked by its element number e (small integers are free operands)
+      // and turned into a position once: e = 3 (4 yb + t) + db for yb < 2,
+      // 24 + db for the row dy = 16.
+      auto top2_full = [&](float& v1, int& i1, float& v2) {
+        v1 = -3.0e38f;
+        v2 = -3.0e38f;
+        int e1 = 0;
+        const bool row16 = gl == 0, col16 = cl == 0;
+        auto upd = [&](float v, int e) {
+          const bool gt = v > v1;
+          v2 = __builtin_amdgcn_fmed3f(v, v1, v2);
+          v1 = gt ? v : v1;
+          e1 = gt ? e : e1;
+        };
+#pragma unroll
+        for (int yb = 0; yb < 2; ++yb)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int r = 4 * yb + t;
+            upd(D2[yb][0][t], 3 * r);
+            upd(D2[yb][1][t], 3 * r + 1);
+            upd(col16 ? D2[yb][2][t] : -3.0e38f, 3 * r + 2);
+          }
+        upd(row16 ? D2[2][0][0] : -3.0e38f, 24);
+        upd(row16 ? D2[2][1][0] : -3.0e38f, 25);
+        upd(row16 && col16 ? D2[2][2][0] : -3.0e38f, 26);
+        // every lane holds valid values (yb, db < 2), so v1 is a real value
+        const int r = e1 / 3, db = e1 - 3 * r;
+        const int dy16 = r < 8 ? 16 * (r >> 2) + (r & 3) + 4 * gl : 32;  // dy + 16
+        i1 = dy16 * 33 + 16 * db + cl;
+        wave_top2(v1, i1, v2);
+      };
       float v1f, v2f, v1r, v2r;
       int i1f, i1r;
-      top2(w_i, v1f, i1f, v2f);
-      if (w_j == w_i) {
+      const bool full = w_i >= 16 && w_j >= 16;
+      if (full) top2_full(v1f, i1f, v2f);
+      else top2(w_i, v1f, i1f, v2f);
+      if (full || w_j == w_i) {
         v1r = v1f;
         v2r = v2f;
         i1r = i1f;
@@ -379,7 +460,7 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
       // forward shift and the reverse one (mirror of the reverse top position)
       const int sy0 = i1f / 33 - 16, sx0 = i1f % 33 - 16;
       const int sy1 = 16 - i1r / 33, sx1 = 16 - i1r % 33;
-      const uint64_t* mbits = cm.bits + cm.bits_off[i];
+      const uint64_t* mbits = mtile;
       // c(s) of the reverse direction at -s equals the forward c(s)
       const int c0 = wave_overlap128(s_bits, mbits, sy0, sx0);
       const int c1 = i1r == i1f ? c0 : wave_overlap128(mbits, s_bits, sy1, sx1);
@@ -400,8 +481,8 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         if (q.need) q.need[k] = 0;
       }
       if (!dec0 || !dec1 || surf_out) {
-        // the window surface goes to the wave's LDS tile for the candidate
-        // queue (and the surface output)
+        // the window surface goes to the wave's LDS tile (over the member
+        // bits, no longer needed) for the candidate queue and the surface output
         float* sw = s_surf[wave];
 #pragma unroll
         for (int yb = 0; yb < 3; ++yb)

@@ -301,6 +301,25 @@ def test_cosine_c128_mixed(ctx, seed):
     h.close()
 
 
+def test_cosine_c128_mixed_small_windows(ctx):
+    """Half-windows below 16, equal and unequal within a pair, on the batched
+    MFMA path (its general window search and the reverse-direction search)."""
+    import dataclasses
+    cs = c128_subset(160, seed=21)
+    rng = np.random.default_rng(21)
+    w = rng.choice(np.array([0, 1, 5, 9, 15, 16], np.int16), size=cs.n)
+    cs = dataclasses.replace(cs, marker_w=w)
+    rep, mem = pairs_for(cs, 2500, seed=21)
+    o = np.lexsort((mem, rep))
+    rep, mem = rep[o], mem[o]
+    say(f"[cosine] c128 small windows path=mixed pairs={rep.size}")
+    h = ctx.clips(cs)
+    got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "mixed"))
+    ref = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
+    check_cosine(got, ref, rep, mem, "c128/mixed/windows")
+    h.close()
+
+
 def test_mixed_rejects_other_shapes(ctx):
     import paper_2512_13133_amd as ca
     h = ctx.clips(small_set(8))
