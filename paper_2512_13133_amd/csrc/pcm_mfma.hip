@@ -98,30 +98,75 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Top value, its position and the runner-up over the wave (positions break ties low).
+// Cross-lane reads for wave reductions: DPP within 16-lane rows (quad
+// permutes, half-row and row mirrors).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, x)));
+}
+
+// Merge a top-two state with another lane's: larger value wins, ties to the
+// lower position; commutative, so both lanes of a swap end up equal.
+__device__ __forceinline__ void top2_merge(float& v1, int& i1, float& v2, float o1, int oi, float o2) {
+  const bool take = o1 > v1 || (o1 == v1 && oi < i1);
+  const float a = take ? v1 : o1;  // the loser's top
+  const float b = take ? o2 : v2;  // the winner's runner-up
+  v2 = a > b ? a : b;
+  v1 = take ? o1 : v1;
+  i1 = take ? oi : i1;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void top2_step(float& v1, int& i1, float& v2) {
+  top2_merge(v1, i1, v2, dpp_f<CTRL>(v1), dpp_i<CTRL>(i1), dpp_f<CTRL>(v2));
+}
+
+// Top value, its position and the runner-up over the wave (positions break
+// ties low): DPP steps reduce each 16-lane row, then the four row results are
+// read as wave-uniform values and merged.
 __device__ __forceinline__ void wave_top2(float& v1, int& i1, float& v2) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const float o1 = __shfl_xor(v1, off);
-    const int oi = __shfl_xor(i1, off);
-    const float o2 = __shfl_xor(v2, off);
-    if (o1 > v1 || (o1 == v1 && oi < i1)) {
-      v2 = fmaxf(v1, o2);
-      v1 = o1;
-      i1 = oi;
-    } else {
-      v2 = fmaxf(v2, o1);
-    }
-  }
+  top2_step<0xB1>(v1, i1, v2);   // quad_perm [1,0,3,2]
+  top2_step<0x4E>(v1, i1, v2);   // quad_perm [2,3,0,1]
+  top2_step<0x141>(v1, i1, v2);  // row_half_mirror
+  top2_step<0x140>(v1, i1, v2);  // row_mirror
+  auto rd = [&](int l, float& a1, int& ai, float& a2) {
+    a1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v1), l));
+    ai = __builtin_amdgcn_readlane(i1, l);
+    a2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v2), l));
+  };
+  float r1, r2, o1, o2;
+  int ri, oi;
+  rd(0, r1, ri, r2);
+  rd(16, o1, oi, o2);
+  top2_merge(r1, ri, r2, o1, oi, o2);
+  rd(32, o1, oi, o2);
+  top2_merge(r1, ri, r2, o1, oi, o2);
+  rd(48, o1, oi, o2);
+  top2_merge(r1, ri, r2, o1, oi, o2);
+  v1 = r1;
+  i1 = ri;
+  v2 = r2;
+}
+
+// Sum over the wave (wave-uniform result).
+__device__ __forceinline__ int wave_sum(int c) {
+  c += dpp_i<0xB1>(c);
+  c += dpp_i<0x4E>(c);
+  c += dpp_i<0x141>(c);
+  c += dpp_i<0x140>(c);
+  return __builtin_amdgcn_readlane(c, 0) + __builtin_amdgcn_readlane(c, 16) + __builtin_amdgcn_readlane(c, 32) +
+         __builtin_amdgcn_readlane(c, 48);
 }
 
 // Overlap count c(s) = sum_x rep(x) mem((x + s) mod 128) on one wave.
 __device__ __forceinline__ int wave_overlap128(const uint64_t* rep, const uint64_t* mem, int dy, int dx) {
-  int c = row_overlap(rep, mem, MF_N, threadIdx.x & 63, dy, dx) +
-          row_overlap(rep, mem, MF_N, (threadIdx.x & 63) + 64, dy, dx);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  return c;
+  const int c = row_overlap(rep, mem, MF_N, threadIdx.x & 63, dy, dx) +
+                row_overlap(rep, mem, MF_N, (threadIdx.x & 63) + 64, dy, dx);
+  return wave_sum(c);
 }
 
 // Queue an undecided direction: every window shift whose low-precision value
@@ -218,6 +263,12 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
     t_n = cm.npix[t_i];
     t_wz = ((int)cm.w[t_i] & 0xffff) | (cm.zero_bins[t_i] << 16);
   }
+  // stage-1 twiddles (4 K-blocks x 3 dx-blocks) of this lane, held for the tile
+  h8_t B1[4][3];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int nb = 0; nb < 3; ++nb) B1[kb][nb] = b1frag[(kb * 3 + nb) * 64 + lane];
   for (int t = tid; t < 8 * 3 * 64; t += 256) s_a2[t] = a2frag[t];
   if (tid < cnt) s_rep[tid] = io.rep[base + tid];
   __syncthreads();
@@ -285,13 +336,6 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         __builtin_amdgcn_global_load_lds((const void*)(mb_src + 128),
                                          (__attribute__((address_space(3))) void*)(mtile + 128), 16, 0, 0);
       }
-      // stage-1 twiddles (4 K-blocks x 3 dx-blocks) for this lane; cached, and
-      // not live across the peak search
-      h8_t B1[4][3];
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-        for (int nb = 0; nb < 3; ++nb) B1[kb][nb] = b1frag[(kb * 3 + nb) * 64 + lane];
       f4_t D2[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -367,6 +411,9 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         load_member_block(__builtin_amdgcn_make_buffer_rsrc((void*)(last ? nptr : mptr), (short)0,
                                                             last ? nbytes : MF_SPEC_BYTES, MF_RSRC_WORD3),
                           last ? 0 : mb + 1, col, g, mnext);
+        // keep the loads at the top: sunk to where registers free up, their
+        // latency would surface at the next block
+        __builtin_amdgcn_sched_barrier(0);
         block(mb, m_cur);
 #pragma unroll
         for (int t = 0; t < 5; ++t) m_cur[t] = mnext[t];
