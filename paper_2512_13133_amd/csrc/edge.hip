@@ -273,51 +273,34 @@ __device__ __forceinline__ uint64_t row_bits_linear(const uint64_t* row, int wpr
   return (lo >> o) | (hi << (64 - o));
 }
 
-// Does member m shifted by (dy, dx) overlap representative r (linear shift)?
-// Wave-wide.  Rows are first tried with a pigeonhole bound on the row sums:
-// r_rep[y] + r_mem[y + dy] > N + |dx| forces a common pixel; only if no row
-// proves it are the bit rows intersected.
-__device__ bool overlaps_any(const ClipsDev& cs, int m, int r, int N, int dy, int dx, int lane) {
+// Does a member shifted by (dy, dx) overlap a representative (linear shift)?
+// Wave-wide; rs_* are row sums and b_* bit rasters.  Rows are first tried with
+// a pigeonhole bound on the row sums: r_rep[y] + r_mem[y + dy] > N + |dx|
+// forces a common pixel; only if no row proves it are the bit rows intersected.
+__device__ bool overlap11(const uint16_t* rs_m, const uint16_t* rs_r, const uint64_t* b_m, const uint64_t* b_r,
+                          int N, int dy, int dx, int lane) {
   const int y0 = max(0, -dy), y1 = min(N, N - dy);
   if (y0 >= y1 || dx >= N || dx <= -N) return false;
-  const uint16_t* rs_m = cs.rowsum + cs.sig_off[m];
-  const uint16_t* rs_r = cs.rowsum + cs.sig_off[r];
   const int lim = N + abs(dx);
   bool hit = false;
-  for (int y = y0 + lane; y < y1; y += 64) hit = hit || ((int)rs_r[y] + (int)rs_m[y + dy] > lim);
+  for (int y = y0 + lane; y < y1; y += 64) hit |= (int)rs_r[y] + (int)rs_m[y + dy] > lim;
   if (__ballot(hit)) return true;
   const int wpr = N >> 6;
-  const uint64_t* br = cs.bits + cs.bits_off[r];
-  const uint64_t* bm = cs.bits + cs.bits_off[m];
   for (int y = y0 + lane; y < y1; y += 64) {
-    const uint64_t* rr = br + y * wpr;
-    const uint64_t* mr = bm + (y + dy) * wpr;
-    for (int k = 0; k < wpr && !hit; ++k) hit = (rr[k] & row_bits_linear(mr, wpr, 64 * k + dx)) != 0ull;
+    const uint64_t* rr = b_r + y * wpr;
+    const uint64_t* mr = b_m + (y + dy) * wpr;
+    for (int k = 0; k < wpr; ++k) hit |= (rr[k] & row_bits_linear(mr, wpr, 64 * k + dx)) != 0ull;
   }
   return __ballot(hit) != 0ull;
 }
 
-// One direction for single-polygon clips: each polygon's box is the global
-// box, so the Min-Max shift of the matched pair equals T0 and one overlap test
-// decides both the correspondence and its re-check.
-__device__ void edge_dir11(const ClipsDev& cs, int m, int r, int N, int lane, int& sy, int& sx, int& E,
-                           bool& matched, bool& ok) {
-  const int w = cs.w[m];
-  const int16_t* gm = cs.gbox + 4 * m;
-  const int16_t* gr = cs.gbox + 4 * r;
-  int ex, ey;
-  {
-    const int a = gm[0] - gr[0], b = gm[1] - gr[1];
-    minmax_axis(min(a, b), max(a, b), w, sx, ex);
-    const int c = gm[2] - gr[2], e = gm[3] - gr[3];
-    minmax_axis(min(c, e), max(c, e), w, sy, ey);
-  }
-  matched = overlaps_any(cs, m, r, N, sy, sx, lane);
-  ok = matched;
-  E = matched ? max(ex, ey) : -1;
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-constexpr int EDGE_PAIRS_PER_GROUP = 16;
+constexpr int EDGE_PAIRS_PER_GROUP = 64;  // pairs per wave: one per lane
 
 __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, Threshold thr, int64_t block0) {
   __shared__ unsigned long long relM[MAX_POLY], relR[MAX_POLY];
@@ -326,10 +309,80 @@ __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, 
   __shared__ int red[4][64];
   const int lane = threadIdx.x;
   const int64_t k0 = (block0 + (int64_t)blockIdx.x) * EDGE_PAIRS_PER_GROUP;
-  const int64_t k1 = min(k0 + EDGE_PAIRS_PER_GROUP, io.n_pairs);
-  for (int64_t k = k0; k < k1; ++k) {
+  const int cnt = (int)min((int64_t)EDGE_PAIRS_PER_GROUP, io.n_pairs - k0);
+
+  // Pairs of single-polygon clips, one per lane: the shift, residual and
+  // outputs are per-lane arithmetic; the wave shares only the overlap test of
+  // each pair, whose answers collect in a bit mask.
+  bool single = false;
+  int sy0 = 0, sx0 = 0, E0 = 0, sy1 = 0, sx1 = 0, E1 = 0, N = 0;
+  bool mirror = true;
+  int64_t a_rs_i = 0, a_rs_j = 0, a_b_i = 0, a_b_j = 0;  // row-sum and bit addresses
+  if (lane < cnt) {
+    const int64_t k = k0 + lane;
+    const int i = io.mem[k], j = io.rep[k];
+    single = cs.npoly[i] == 1 && cs.npoly[j] == 1;
+    if (single) {
+      N = cs.N[i];
+      const int wi = cs.w[i], wj = cs.w[j];
+      mirror = wi == wj;
+      const int16_t* gi = cs.gbox + 4 * i;
+      const int16_t* gj = cs.gbox + 4 * j;
+      const int dx0 = gi[0] - gj[0], dx1 = gi[1] - gj[1], dy0 = gi[2] - gj[2], dy1 = gi[3] - gj[3];
+      int ex, ey;
+      // member i against rep j, then member j against rep i (negated displacements)
+      minmax_axis(min(dx0, dx1), max(dx0, dx1), wi, sx0, ex);
+      minmax_axis(min(dy0, dy1), max(dy0, dy1), wi, sy0, ey);
+      E0 = max(ex, ey);
+      minmax_axis(min(-dx0, -dx1), max(-dx0, -dx1), wj, sx1, ex);
+      minmax_axis(min(-dy0, -dy1), max(-dy0, -dy1), wj, sy1, ey);
+      E1 = max(ex, ey);
+      a_rs_i = (int64_t)(cs.rowsum + cs.sig_off[i]);
+      a_rs_j = (int64_t)(cs.rowsum + cs.sig_off[j]);
+      a_b_i = (int64_t)(cs.bits + cs.bits_off[i]);
+      a_b_j = (int64_t)(cs.bits + cs.bits_off[j]);
+    }
+  }
+  unsigned long long hit0 = 0ull, hit1 = 0ull;
+  for (unsigned long long m = __ballot(single); m; m &= m - 1ull) {
+    const int t = __ffsll(m) - 1;
+    const uint16_t* rs_i = (const uint16_t*)readlane64(a_rs_i, t);
+    const uint16_t* rs_j = (const uint16_t*)readlane64(a_rs_j, t);
+    const uint64_t* b_i = (const uint64_t*)readlane64(a_b_i, t);
+    const uint64_t* b_j = (const uint64_t*)readlane64(a_b_j, t);
+    const int Nt = __builtin_amdgcn_readlane(N, t);
+    if (overlap11(rs_i, rs_j, b_i, b_j, Nt, __builtin_amdgcn_readlane(sy0, t), __builtin_amdgcn_readlane(sx0, t),
+                  lane))
+      hit0 |= 1ull << t;
+    if (!__builtin_amdgcn_readlane((int)mirror, t) &&
+        overlap11(rs_j, rs_i, b_j, b_i, Nt, __builtin_amdgcn_readlane(sy1, t), __builtin_amdgcn_readlane(sx1, t),
+                  lane))
+      hit1 |= 1ull << t;
+  }
+  if (single) {
+    const int64_t k = k0 + lane;
+    const bool m0 = (hit0 >> lane) & 1ull;
+    bool m1 = (hit1 >> lane) & 1ull;
+    if (mirror) {  // equal windows: the reverse direction is the exact mirror
+      sy1 = -sy0; sx1 = -sx0; E1 = E0; m1 = m0;
+    }
+    io.shift[k * 4 + 0] = (int16_t)sy0;
+    io.shift[k * 4 + 1] = (int16_t)sx0;
+    io.shift[k * 4 + 2] = (int16_t)sy1;
+    io.shift[k * 4 + 3] = (int16_t)sx1;
+    io.count[k * 2 + 0] = m0 ? E0 : -1;
+    io.count[k * 2 + 1] = m1 ? E1 : -1;
+    io.score[k * 2 + 0] = 0.0;
+    io.score[k * 2 + 1] = 0.0;
+    io.bits[k] = (uint8_t)((m0 && (int64_t)E0 <= thr.p ? 1u : 0u) | (m1 && (int64_t)E1 <= thr.p ? 2u : 0u));
+    io.flags[k] = (m0 ? 0u : (uint32_t)CA_FLAG_NO_MATCH_FWD) | (m1 ? 0u : (uint32_t)CA_FLAG_NO_MATCH_REV);
+  }
+
+  // the other pairs one at a time, the wave together
+  for (unsigned long long m = __ballot(lane < cnt && !single); m; m &= m - 1ull) {
+    const int64_t k = k0 + (__ffsll(m) - 1);
     const int j = io.rep[k], i = io.mem[k];
-    const int N = cs.N[i];
+    const int Nk = cs.N[i];
     const int Pi = cs.npoly[i], Pj = cs.npoly[j];
     if (Pi > 8 || Pj > 8) {
       edge_pair_lds(cs, io, thr, k, relM, relR, relM0, relR0, &sflag, red);
@@ -338,19 +391,18 @@ __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, 
     uint32_t fl = 0;
     int sy[2], sx[2], E[2];
     bool matched[2], ok[2];
-    const bool mirror = cs.w[i] == cs.w[j];
-    for (int d = 0; d < (mirror ? 1 : 2); ++d) {
-      const int m = d == 0 ? i : j, r = d == 0 ? j : i;
+    const bool mir = cs.w[i] == cs.w[j];
+    for (int d = 0; d < (mir ? 1 : 2); ++d) {
+      const int mm = d == 0 ? i : j, r = d == 0 ? j : i;
       const int Pm = d == 0 ? Pi : Pj, Pr = d == 0 ? Pj : Pi;
       if (Pm <= 0 || Pr <= 0) {
         sy[d] = 0; sx[d] = 0; E[d] = -1; matched[d] = false; ok[d] = false;
         fl |= CA_FLAG_EMPTY;
         continue;
       }
-      if (Pm == 1 && Pr == 1) edge_dir11(cs, m, r, N, lane, sy[d], sx[d], E[d], matched[d], ok[d]);
-      else edge_dir8(cs, m, r, N, Pm, Pr, lane, sy[d], sx[d], E[d], matched[d], ok[d]);
+      edge_dir8(cs, mm, r, Nk, Pm, Pr, lane, sy[d], sx[d], E[d], matched[d], ok[d]);
     }
-    if (mirror) {  // equal windows: the reverse direction is the exact mirror
+    if (mir) {  // equal windows: the reverse direction is the exact mirror
       sy[1] = -sy[0]; sx[1] = -sx[0]; E[1] = E[0]; matched[1] = matched[0]; ok[1] = ok[0];
     }
     if (lane == 0) {

@@ -76,6 +76,17 @@ def check_cosine(got, ref, rep, mem, label):
     assert np.abs(got["score"] - ref["score"]).max() <= 1e-12
 
 
+def check_edge(got, ref, rep, mem, label):
+    bad = np.flatnonzero((got["bits"] != ref["bits"]) | np.any(got["shift"] != ref["shift"], axis=(1, 2)) |
+                         np.any(got["count"] != ref["E"], axis=1))
+    if bad.size:
+        k = bad[0]
+        raise AssertionError(f"{label}: {bad.size} pairs differ; first k={k} rep={rep[k]} mem={mem[k]} "
+                             f"got bits={got['bits'][k]} shift={got['shift'][k].tolist()} E={got['count'][k].tolist()} "
+                             f"ref bits={ref['bits'][k]} shift={ref['shift'][k].tolist()} E={ref['E'][k].tolist()}")
+    assert (got["score"] == 0).all()
+
+
 # ------------------------------------------------------------------ a1, a2
 
 
@@ -160,14 +171,27 @@ def test_edge_track(ctx, which):
     h = ctx.clips(cs)
     got = to_np(ctx.align_pairs(h, rep, mem, "edge", t))
     ref = cover.align_pairs_edge(cs, rep, mem, t, workers=WORKERS)
-    bad = np.flatnonzero((got["bits"] != ref["bits"]) | np.any(got["shift"] != ref["shift"], axis=(1, 2)) |
-                         np.any(got["count"] != ref["E"], axis=1))
-    assert bad.size == 0, (bad[:5], got["shift"][bad[:1]], ref["shift"][bad[:1]], got["count"][bad[:1]], ref["E"][bad[:1]])
-    assert (got["score"] == 0).all()
+    check_edge(got, ref, rep, mem, which)
     h.close()
 
 
 # ------------------------------------------------------------------ a3 pruning
+
+
+def test_edge_track_c128(ctx):
+    """128 x 128 clips with one to several polygons (single-polygon fast path
+    and the polygon-plane relation), in 64-pair groups with a ragged tail."""
+    cs = c128_subset(160, seed=17)
+    rep, mem = pairs_for(cs, 3001, seed=17)
+    say(f"[edge] c128 pairs={rep.size}")
+    h = ctx.clips(cs)
+    got = to_np(ctx.align_pairs(h, rep, mem, "edge", 3))
+    ref = cover.align_pairs_edge(cs, rep, mem, 3, workers=WORKERS)
+    npoly = np.array([len(raster.components(raster.clip_raster(cs, i))[1]) for i in range(cs.n)])
+    say(f"[edge] polygons per clip: {np.bincount(npoly).tolist()}")
+    assert (npoly >= 2).sum() >= 10
+    check_edge(got, ref, rep, mem, "c128")
+    h.close()
 
 
 def test_prune_is_safe_and_matches_bounds(ctx):
