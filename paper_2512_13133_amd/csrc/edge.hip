@@ -176,29 +176,6 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
   return x;
 }
 
-__device__ unsigned long long relation8(const ClipsDev& cs, int m, int r, int N, int dy, int dx, int lane) {
-  const uint16_t* rp_m = cs.run_rowptr + cs.rowptr_off[m];
-  const uint16_t* rp_r = cs.run_rowptr + cs.rowptr_off[r];
-  const uint32_t* ru_m = cs.runs + cs.run_off[m];
-  const uint32_t* ru_r = cs.runs + cs.run_off[r];
-  const int y0 = max(0, -dy), y1 = min(N, N - dy);
-  unsigned long long rel = 0ull;
-  for (int y = y0 + lane; y < y1; y += 64) {
-    const int ym = y + dy;
-    int a = rp_r[y], ae = rp_r[y + 1];
-    int b = rp_m[ym], be = rp_m[ym + 1];
-    while (a < ae && b < be) {
-      const uint32_t ra = ru_r[a], rb = ru_m[b];
-      const int a0 = ra & 511, a1 = (ra >> 9) & 511, qa = (ra >> 18) & 63;
-      const int b0 = (int)(rb & 511) - dx, b1 = (int)((rb >> 9) & 511) - dx, pb = (rb >> 18) & 63;
-      if (max(a0, b0) < min(a1, b1)) rel |= 1ull << (8 * pb + qa);
-      if (a1 < b1) ++a;
-      else ++b;
-    }
-  }
-  return wave_or64(rel);
-}
-
 // Exactly-one rule on an 8 x 8 relation word (uniform).
 __device__ __forceinline__ bool corr8_ok(unsigned long long rel, int Pm, int Pr) {
   if (Pm <= Pr)
@@ -208,57 +185,6 @@ __device__ __forceinline__ bool corr8_ok(unsigned long long rel, int Pm, int Pr)
     for (int q = 0; q < Pr; ++q)
       if (__popcll(rel & (0x0101010101010101ull << q)) != 1) return false;
   return true;
-}
-
-// One direction (member m against rep r) on the register path.
-__device__ void edge_dir8(const ClipsDev& cs, int m, int r, int N, int Pm, int Pr, int lane, int& sy, int& sx,
-                          int& E, bool& matched, bool& ok) {
-  const int w = cs.w[m];
-  const int16_t* gm = cs.gbox + 4 * m;
-  const int16_t* gr = cs.gbox + 4 * r;
-  int s0x, s0y, eu;
-  {
-    const int a = gm[0] - gr[0], b = gm[1] - gr[1];
-    minmax_axis(min(a, b), max(a, b), w, s0x, eu);
-    const int c = gm[2] - gr[2], e = gm[3] - gr[3];
-    minmax_axis(min(c, e), max(c, e), w, s0y, eu);
-  }
-  const unsigned long long rel0 = relation8(cs, m, r, N, s0y, s0x, lane);
-  if (!corr8_ok(rel0, Pm, Pr)) {
-    sy = s0y; sx = s0x; E = -1; matched = false; ok = false;
-    return;
-  }
-  const int16_t* bm = cs.boxes + (int64_t)m * MAX_POLY * 4;
-  const int16_t* br = cs.boxes + (int64_t)r * MAX_POLY * 4;
-  int xlo = 1 << 20, xhi = -(1 << 20), ylo = 1 << 20, yhi = -(1 << 20);
-  const bool from_member = Pm <= Pr;
-  const int P = from_member ? Pm : Pr;
-  for (int t = 0; t < P; ++t) {
-    int p, q;
-    if (from_member) { p = t; q = __ffsll((unsigned long long)((rel0 >> (8 * t)) & 0xffull)) - 1; }
-    else {
-      q = t;
-      const unsigned long long col = rel0 & (0x0101010101010101ull << t);
-      p = (__ffsll(col) - 1) >> 3;
-    }
-    const int16_t* a = bm + 4 * p;
-    const int16_t* b = br + 4 * q;
-    const int d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2], d3 = a[3] - b[3];
-    xlo = min(xlo, min(d0, d1)); xhi = max(xhi, max(d0, d1));
-    ylo = min(ylo, min(d2, d3)); yhi = max(yhi, max(d2, d3));
-  }
-  int ex, ey;
-  minmax_axis(xlo, xhi, w, sx, ex);
-  minmax_axis(ylo, yhi, w, sy, ey);
-  E = max(ex, ey);
-  matched = true;
-  const unsigned long long rel1 = relation8(cs, m, r, N, sy, sx, lane);
-  bool same = corr8_ok(rel1, Pm, Pr);
-  if (same && Pm <= Pr)
-    for (int p = 0; p < Pm; ++p) same = same && (((rel1 ^ rel0) >> (8 * p)) & 0xffull) == 0;
-  if (same && Pr <= Pm)
-    for (int q = 0; q < Pr; ++q) same = same && ((rel1 ^ rel0) & (0x0101010101010101ull << q)) == 0;
-  ok = same;
 }
 
 // 64 bits of a bit row starting at bit `start`, zero outside [0, N) (linear shift).
@@ -300,8 +226,73 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Relation of a member (row pointers rp_m, runs ru_m) shifted by (dy, dx)
+// against a representative (rp_r, ru_r): bit 8 p + q when member polygon p
+// overlaps rep polygon q (linear shift, zero fill).  Wave-wide, uniform result.
+__device__ unsigned long long relation_runs(const uint16_t* rp_m, const uint32_t* ru_m, const uint16_t* rp_r,
+                                            const uint32_t* ru_r, int N, int dy, int dx, int lane) {
+  const int y0 = max(0, -dy), y1 = min(N, N - dy);
+  unsigned long long rel = 0ull;
+  for (int y = y0 + lane; y < y1; y += 64) {
+    const int ym = y + dy;
+    int a = rp_r[y], ae = rp_r[y + 1];
+    int b = rp_m[ym], be = rp_m[ym + 1];
+    while (a < ae && b < be) {
+      const uint32_t ra = ru_r[a], rb = ru_m[b];
+      const int a0 = ra & 511, a1 = (ra >> 9) & 511, qa = (ra >> 18) & 63;
+      const int b0 = (int)(rb & 511) - dx, b1 = (int)((rb >> 9) & 511) - dx, pb = (rb >> 18) & 63;
+      if (max(a0, b0) < min(a1, b1)) rel |= 1ull << (8 * pb + qa);
+      if (a1 < b1) ++a;
+      else ++b;
+    }
+  }
+  return wave_or64(rel);
+}
+
+// Min-Max shift and residual of the correspondence in rel (member polygons
+// p, rep polygons q, from the fewer side), over the polygon boxes.
+__device__ void matched_shift(unsigned long long rel, int Pm, int Pr, const int16_t* bm, const int16_t* br, int w,
+                              int& sy, int& sx, int& E) {
+  int xlo = 1 << 20, xhi = -(1 << 20), ylo = 1 << 20, yhi = -(1 << 20);
+  const bool from_member = Pm <= Pr;
+  const int P = from_member ? Pm : Pr;
+  for (int t = 0; t < P; ++t) {
+    int p, q;
+    if (from_member) { p = t; q = __ffsll((unsigned long long)((rel >> (8 * t)) & 0xffull)) - 1; }
+    else {
+      q = t;
+      const unsigned long long col = rel & (0x0101010101010101ull << t);
+      p = (__ffsll(col) - 1) >> 3;
+    }
+    const int16_t* a = bm + 4 * p;
+    const int16_t* b = br + 4 * q;
+    const int d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2], d3 = a[3] - b[3];
+    xlo = min(xlo, min(d0, d1)); xhi = max(xhi, max(d0, d1));
+    ylo = min(ylo, min(d2, d3)); yhi = max(yhi, max(d2, d3));
+  }
+  int ex, ey;
+  minmax_axis(xlo, xhi, w, sx, ex);
+  minmax_axis(ylo, yhi, w, sy, ey);
+  E = max(ex, ey);
+}
+
+// The relation at the solved shift keeps the matching of the fewer side(s).
+__device__ __forceinline__ bool same_matching(unsigned long long rel1, unsigned long long rel0, int Pm, int Pr) {
+  bool same = corr8_ok(rel1, Pm, Pr);
+  if (Pm <= Pr)
+    for (int p = 0; p < Pm; ++p) same = same && (((rel1 ^ rel0) >> (8 * p)) & 0xffull) == 0;
+  if (Pr <= Pm)
+    for (int q = 0; q < Pr; ++q) same = same && ((rel1 ^ rel0) & (0x0101010101010101ull << q)) == 0;
+  return same;
+}
+
 constexpr int EDGE_PAIRS_PER_GROUP = 64;  // pairs per wave: one per lane
 
+// Pairs are held one per lane: shifts, residuals, correspondences and outputs
+// are per-lane arithmetic over 64 pairs at once, and the wave shares only the
+// pixel work of each pair (the single-polygon overlap test, the polygon
+// relation), whose answers return to the pair's lane.  Clips with more than 8
+// polygons take the LDS path, one pair at a time.
 __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, Threshold thr, int64_t block0) {
   __shared__ unsigned long long relM[MAX_POLY], relR[MAX_POLY];
   __shared__ unsigned long long relM0[MAX_POLY], relR0[MAX_POLY];
@@ -310,116 +301,161 @@ __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, 
   const int lane = threadIdx.x;
   const int64_t k0 = (block0 + (int64_t)blockIdx.x) * EDGE_PAIRS_PER_GROUP;
   const int cnt = (int)min((int64_t)EDGE_PAIRS_PER_GROUP, io.n_pairs - k0);
+  const int64_t k = k0 + lane;
 
-  // Pairs of single-polygon clips, one per lane: the shift, residual and
-  // outputs are per-lane arithmetic; the wave shares only the overlap test of
-  // each pair, whose answers collect in a bit mask.
-  bool single = false;
-  int sy0 = 0, sx0 = 0, E0 = 0, sy1 = 0, sx1 = 0, E1 = 0, N = 0;
-  bool mirror = true;
-  int64_t a_rs_i = 0, a_rs_j = 0, a_b_i = 0, a_b_j = 0;  // row-sum and bit addresses
+  int i = 0, j = 0, N = 0, Pi = 0, Pj = 0, wi = 0, wj = 0;
+  bool big = false, empty = false, single = false, multi = false, mirror = true;
+  int T0y[2] = {0, 0}, T0x[2] = {0, 0}, E0[2] = {0, 0};
   if (lane < cnt) {
-    const int64_t k = k0 + lane;
-    const int i = io.mem[k], j = io.rep[k];
-    single = cs.npoly[i] == 1 && cs.npoly[j] == 1;
-    if (single) {
+    i = io.mem[k];
+    j = io.rep[k];
+    Pi = cs.npoly[i];
+    Pj = cs.npoly[j];
+    big = Pi > 8 || Pj > 8 || Pi < 0 || Pj < 0;
+    empty = !big && (Pi == 0 || Pj == 0);
+    single = !big && Pi == 1 && Pj == 1;
+    multi = !big && !empty && !single;
+    if (single || multi) {
       N = cs.N[i];
-      const int wi = cs.w[i], wj = cs.w[j];
+      wi = cs.w[i];
+      wj = cs.w[j];
       mirror = wi == wj;
       const int16_t* gi = cs.gbox + 4 * i;
       const int16_t* gj = cs.gbox + 4 * j;
       const int dx0 = gi[0] - gj[0], dx1 = gi[1] - gj[1], dy0 = gi[2] - gj[2], dy1 = gi[3] - gj[3];
       int ex, ey;
-      // member i against rep j, then member j against rep i (negated displacements)
-      minmax_axis(min(dx0, dx1), max(dx0, dx1), wi, sx0, ex);
-      minmax_axis(min(dy0, dy1), max(dy0, dy1), wi, sy0, ey);
-      E0 = max(ex, ey);
-      minmax_axis(min(-dx0, -dx1), max(-dx0, -dx1), wj, sx1, ex);
-      minmax_axis(min(-dy0, -dy1), max(-dy0, -dy1), wj, sy1, ey);
-      E1 = max(ex, ey);
+      // T0 of member i against rep j, then of member j against rep i
+      minmax_axis(min(dx0, dx1), max(dx0, dx1), wi, T0x[0], ex);
+      minmax_axis(min(dy0, dy1), max(dy0, dy1), wi, T0y[0], ey);
+      E0[0] = max(ex, ey);
+      minmax_axis(min(-dx0, -dx1), max(-dx0, -dx1), wj, T0x[1], ex);
+      minmax_axis(min(-dy0, -dy1), max(-dy0, -dy1), wj, T0y[1], ey);
+      E0[1] = max(ex, ey);
+    }
+  }
+  int sy[2] = {0, 0}, sx[2] = {0, 0}, E[2] = {-1, -1};
+  bool matched[2] = {false, false}, ok[2] = {false, false};
+
+  // single-polygon pairs: one overlap test decides the correspondence and its
+  // re-check (each polygon's box is the global box, so the shift stays T0)
+  {
+    int64_t a_rs_i = 0, a_rs_j = 0, a_b_i = 0, a_b_j = 0;
+    if (single) {
       a_rs_i = (int64_t)(cs.rowsum + cs.sig_off[i]);
       a_rs_j = (int64_t)(cs.rowsum + cs.sig_off[j]);
       a_b_i = (int64_t)(cs.bits + cs.bits_off[i]);
       a_b_j = (int64_t)(cs.bits + cs.bits_off[j]);
     }
-  }
-  unsigned long long hit0 = 0ull, hit1 = 0ull;
-  for (unsigned long long m = __ballot(single); m; m &= m - 1ull) {
-    const int t = __ffsll(m) - 1;
-    const uint16_t* rs_i = (const uint16_t*)readlane64(a_rs_i, t);
-    const uint16_t* rs_j = (const uint16_t*)readlane64(a_rs_j, t);
-    const uint64_t* b_i = (const uint64_t*)readlane64(a_b_i, t);
-    const uint64_t* b_j = (const uint64_t*)readlane64(a_b_j, t);
-    const int Nt = __builtin_amdgcn_readlane(N, t);
-    if (overlap11(rs_i, rs_j, b_i, b_j, Nt, __builtin_amdgcn_readlane(sy0, t), __builtin_amdgcn_readlane(sx0, t),
-                  lane))
-      hit0 |= 1ull << t;
-    if (!__builtin_amdgcn_readlane((int)mirror, t) &&
-        overlap11(rs_j, rs_i, b_j, b_i, Nt, __builtin_amdgcn_readlane(sy1, t), __builtin_amdgcn_readlane(sx1, t),
-                  lane))
-      hit1 |= 1ull << t;
-  }
-  if (single) {
-    const int64_t k = k0 + lane;
-    const bool m0 = (hit0 >> lane) & 1ull;
-    bool m1 = (hit1 >> lane) & 1ull;
-    if (mirror) {  // equal windows: the reverse direction is the exact mirror
-      sy1 = -sy0; sx1 = -sx0; E1 = E0; m1 = m0;
+    unsigned long long hit0 = 0ull, hit1 = 0ull;
+    for (unsigned long long m = __ballot(single); m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const uint16_t* rs_i = (const uint16_t*)readlane64(a_rs_i, t);
+      const uint16_t* rs_j = (const uint16_t*)readlane64(a_rs_j, t);
+      const uint64_t* b_i = (const uint64_t*)readlane64(a_b_i, t);
+      const uint64_t* b_j = (const uint64_t*)readlane64(a_b_j, t);
+      const int Nt = __builtin_amdgcn_readlane(N, t);
+      if (overlap11(rs_i, rs_j, b_i, b_j, Nt, __builtin_amdgcn_readlane(T0y[0], t),
+                    __builtin_amdgcn_readlane(T0x[0], t), lane))
+        hit0 |= 1ull << t;
+      if (!__builtin_amdgcn_readlane((int)mirror, t) &&
+          overlap11(rs_j, rs_i, b_j, b_i, Nt, __builtin_amdgcn_readlane(T0y[1], t),
+                    __builtin_amdgcn_readlane(T0x[1], t), lane))
+        hit1 |= 1ull << t;
     }
-    io.shift[k * 4 + 0] = (int16_t)sy0;
-    io.shift[k * 4 + 1] = (int16_t)sx0;
-    io.shift[k * 4 + 2] = (int16_t)sy1;
-    io.shift[k * 4 + 3] = (int16_t)sx1;
-    io.count[k * 2 + 0] = m0 ? E0 : -1;
-    io.count[k * 2 + 1] = m1 ? E1 : -1;
-    io.score[k * 2 + 0] = 0.0;
-    io.score[k * 2 + 1] = 0.0;
-    io.bits[k] = (uint8_t)((m0 && (int64_t)E0 <= thr.p ? 1u : 0u) | (m1 && (int64_t)E1 <= thr.p ? 2u : 0u));
-    io.flags[k] = (m0 ? 0u : (uint32_t)CA_FLAG_NO_MATCH_FWD) | (m1 ? 0u : (uint32_t)CA_FLAG_NO_MATCH_REV);
+    if (single) {
+      matched[0] = ok[0] = (hit0 >> lane) & 1ull;
+      matched[1] = ok[1] = (hit1 >> lane) & 1ull;
+      for (int d = 0; d < 2; ++d) {
+        sy[d] = T0y[d];
+        sx[d] = T0x[d];
+        E[d] = matched[d] ? E0[d] : -1;
+      }
+    }
   }
 
-  // the other pairs one at a time, the wave together
-  for (unsigned long long m = __ballot(lane < cnt && !single); m; m &= m - 1ull) {
-    const int64_t k = k0 + (__ffsll(m) - 1);
-    const int j = io.rep[k], i = io.mem[k];
-    const int Nk = cs.N[i];
-    const int Pi = cs.npoly[i], Pj = cs.npoly[j];
-    if (Pi > 8 || Pj > 8) {
-      edge_pair_lds(cs, io, thr, k, relM, relR, relM0, relR0, &sflag, red);
-      continue;
+  // pairs with 2..8 polygons on a side: relation at T0, per-lane matching and
+  // Min-Max shift, relation at the shift, per-lane re-check
+  {
+    int64_t a_rp_i = 0, a_rp_j = 0, a_ru_i = 0, a_ru_j = 0;
+    if (multi) {
+      a_rp_i = (int64_t)(cs.run_rowptr + cs.rowptr_off[i]);
+      a_rp_j = (int64_t)(cs.run_rowptr + cs.rowptr_off[j]);
+      a_ru_i = (int64_t)(cs.runs + cs.run_off[i]);
+      a_ru_j = (int64_t)(cs.runs + cs.run_off[j]);
     }
-    uint32_t fl = 0;
-    int sy[2], sx[2], E[2];
-    bool matched[2], ok[2];
-    const bool mir = cs.w[i] == cs.w[j];
-    for (int d = 0; d < (mir ? 1 : 2); ++d) {
-      const int mm = d == 0 ? i : j, r = d == 0 ? j : i;
-      const int Pm = d == 0 ? Pi : Pj, Pr = d == 0 ? Pj : Pi;
-      if (Pm <= 0 || Pr <= 0) {
-        sy[d] = 0; sx[d] = 0; E[d] = -1; matched[d] = false; ok[d] = false;
-        fl |= CA_FLAG_EMPTY;
-        continue;
+    unsigned long long rel0[2] = {0ull, 0ull}, rel1[2] = {0ull, 0ull};
+    auto relation_of = [&](int t, int d, int dy, int dx) {
+      const uint16_t* rp_i = (const uint16_t*)readlane64(a_rp_i, t);
+      const uint16_t* rp_j = (const uint16_t*)readlane64(a_rp_j, t);
+      const uint32_t* ru_i = (const uint32_t*)readlane64(a_ru_i, t);
+      const uint32_t* ru_j = (const uint32_t*)readlane64(a_ru_j, t);
+      const int Nt = __builtin_amdgcn_readlane(N, t);
+      return d == 0 ? relation_runs(rp_i, ru_i, rp_j, ru_j, Nt, dy, dx, lane)
+                    : relation_runs(rp_j, ru_j, rp_i, ru_i, Nt, dy, dx, lane);
+    };
+    const unsigned long long mm = __ballot(multi);
+    for (unsigned long long m = mm; m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const int nd = __builtin_amdgcn_readlane((int)mirror, t) ? 1 : 2;
+      for (int d = 0; d < nd; ++d) {
+        const unsigned long long r =
+            relation_of(t, d, __builtin_amdgcn_readlane(T0y[d], t), __builtin_amdgcn_readlane(T0x[d], t));
+        if (lane == t) rel0[d] = r;
       }
-      edge_dir8(cs, mm, r, Nk, Pm, Pr, lane, sy[d], sx[d], E[d], matched[d], ok[d]);
     }
-    if (mir) {  // equal windows: the reverse direction is the exact mirror
+    if (multi) {
+      for (int d = 0; d < 2; ++d) {
+        const int Pm = d == 0 ? Pi : Pj, Pr = d == 0 ? Pj : Pi;
+        matched[d] = corr8_ok(rel0[d], Pm, Pr);
+        sy[d] = T0y[d];
+        sx[d] = T0x[d];
+        E[d] = -1;
+        if (matched[d]) {
+          const int mc = d == 0 ? i : j, rc = d == 0 ? j : i;
+          matched_shift(rel0[d], Pm, Pr, cs.boxes + (int64_t)mc * MAX_POLY * 4, cs.boxes + (int64_t)rc * MAX_POLY * 4,
+                        d == 0 ? wi : wj, sy[d], sx[d], E[d]);
+        }
+      }
+    }
+    for (unsigned long long m = __ballot(multi && matched[0]); m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const unsigned long long r =
+          relation_of(t, 0, __builtin_amdgcn_readlane(sy[0], t), __builtin_amdgcn_readlane(sx[0], t));
+      if (lane == t) rel1[0] = r;
+    }
+    for (unsigned long long m = __ballot(multi && !mirror && matched[1]); m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const unsigned long long r =
+          relation_of(t, 1, __builtin_amdgcn_readlane(sy[1], t), __builtin_amdgcn_readlane(sx[1], t));
+      if (lane == t) rel1[1] = r;
+    }
+    if (multi)
+      for (int d = 0; d < 2; ++d)
+        ok[d] = matched[d] && same_matching(rel1[d], rel0[d], d == 0 ? Pi : Pj, d == 0 ? Pj : Pi);
+  }
+
+  if (single || multi || empty) {
+    uint32_t fl = empty ? (uint32_t)CA_FLAG_EMPTY : 0u;
+    if (mirror && !empty) {  // equal windows: the reverse direction is the exact mirror
       sy[1] = -sy[0]; sx[1] = -sx[0]; E[1] = E[0]; matched[1] = matched[0]; ok[1] = ok[0];
     }
-    if (lane == 0) {
-      uint8_t bits = 0;
-      for (int d = 0; d < 2; ++d) {
-        io.shift[k * 4 + 2 * d] = (int16_t)sy[d];
-        io.shift[k * 4 + 2 * d + 1] = (int16_t)sx[d];
-        io.count[k * 2 + d] = E[d];
-        io.score[k * 2 + d] = 0.0;
-        if (!matched[d]) fl |= d == 0 ? CA_FLAG_NO_MATCH_FWD : CA_FLAG_NO_MATCH_REV;
-        else if (!ok[d]) fl |= d == 0 ? CA_FLAG_RECHECK_FWD : CA_FLAG_RECHECK_REV;
-        if (ok[d] && (int64_t)E[d] <= thr.p) bits |= (uint8_t)(1u << d);
-      }
-      io.bits[k] = bits;
-      io.flags[k] = fl;
+    uint8_t bits = 0;
+    for (int d = 0; d < 2; ++d) {
+      io.shift[k * 4 + 2 * d] = (int16_t)sy[d];
+      io.shift[k * 4 + 2 * d + 1] = (int16_t)sx[d];
+      io.count[k * 2 + d] = E[d];
+      io.score[k * 2 + d] = 0.0;
+      if (!matched[d]) fl |= d == 0 ? CA_FLAG_NO_MATCH_FWD : CA_FLAG_NO_MATCH_REV;
+      else if (!ok[d]) fl |= d == 0 ? CA_FLAG_RECHECK_FWD : CA_FLAG_RECHECK_REV;
+      if (ok[d] && (int64_t)E[d] <= thr.p) bits |= (uint8_t)(1u << d);
     }
+    io.bits[k] = bits;
+    io.flags[k] = fl;
   }
+
+  // clips with more than 8 polygons, one pair at a time on the LDS path
+  for (unsigned long long m = __ballot(big); m; m &= m - 1ull)
+    edge_pair_lds(cs, io, thr, k0 + (__ffsll(m) - 1), relM, relR, relM0, relR0, &sflag, red);
 }
 
 }  // namespace ca
