@@ -400,31 +400,6 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
   HIP_OR_FAIL(ctx, hipMemcpyAsync(cs->hnpix.data(), cs->d.npix, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(cs->hnpoly.data(), cs->d.npoly, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
-  // polygon planes for clips with 2..8 polygons (the edge track's relation)
-  {
-    std::vector<int64_t> plane_off(n, -1), pids;
-    int64_t words = 0;
-    for (int64_t i = 0; i < n; ++i) {
-      const int P = cs->hnpoly[i];
-      if (P >= 2 && P <= 8) {
-        plane_off[i] = words;
-        words += (int64_t)P * hN[i] * (hN[i] / 64);
-        pids.push_back(i);
-      }
-    }
-    int64_t* dpo;
-    st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); dpo = (int64_t*)p;
-    cs->d.plane_off = dpo;
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(dpo, plane_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
-    ALLOC(planes, uint64_t, std::max<int64_t>(words, 1));
-    if (!pids.empty()) {
-      int64_t* dids;
-      st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * pids.size()); if (st) return bail(st); dids = (int64_t*)p;
-      HIP_OR_FAIL(ctx, hipMemcpyAsync(dids, pids.data(), sizeof(int64_t) * pids.size(), hipMemcpyHostToDevice, s));
-      HIP_OR_FAIL(ctx, launch_planes(cs->d, dids, (int64_t)pids.size(), s));
-    }
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(s));  // host vectors above are copied from
-  }
 #undef ALLOC
   *out = cs;
   return CA_OK;

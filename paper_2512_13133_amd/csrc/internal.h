@@ -40,8 +40,6 @@ struct ClipsDev {
   uint16_t* run_rowptr;      // per clip: first run of each row, relative
   const int64_t* run_off;    // [n] offset into runs
   uint32_t* runs;            // x0 | x1 << 9 | label << 18 (label 0..63)
-  const int64_t* plane_off;  // [n] word offset of the clip's polygon planes, -1 if none
-  uint64_t* planes;          // per clip with 2..8 polygons: npoly bit rasters (N*N/64 words each)
   int32_t* zero_bins;        // [n] full-grid bins with |F| <= EPS
   const int64_t* spec_off;   // [n] offset in bins: N*(N/2+1) per clip
   __half2* spec16;           // per clip: [u][v < N/2] then Nyquist column [u]

@@ -15,8 +15,6 @@ constexpr int64_t LAUNCH_CHUNK = 1 << 22;
 hipError_t launch_pack(const int64_t* rect_ptr, const int32_t* rects, const ClipsDev& cs, int64_t n,
                        hipStream_t s);
 hipError_t launch_label(const ClipsDev& cs, int64_t n, hipStream_t s);
-// Polygon planes of the listed clips (each with 2..8 polygons, plane_off set).
-hipError_t launch_planes(const ClipsDev& cs, const int64_t* ids, int64_t n_ids, hipStream_t s);
 hipError_t launch_spectrum(const ClipsDev& cs, const int64_t* ids, int64_t n_ids, int N,
                            double2* scratch, const double2* tw256, hipStream_t s);
 // Shared-memory bytes of the per-pair FFT kernel for (scalar size, N, CH, LINES, Lmax).

@@ -279,44 +279,6 @@ hipError_t launch_label(const ClipsDev& cs, int64_t n, hipStream_t s) {
   return hipSuccess;
 }
 
-// Polygon planes: for a clip with 2..8 polygons, one bit raster per polygon
-// (plane p holds the pixels labelled p), built from the labelled row runs.
-// One workgroup per listed clip; one thread per (plane, row).
-__global__ void __launch_bounds__(256) planes_kernel(ClipsDev cs, const int64_t* __restrict__ ids, int64_t block0) {
-  const int64_t i = ids[block0 + (int64_t)blockIdx.x];
-  const int N = cs.N[i];
-  const int wpr = N / 64;
-  const int P = cs.npoly[i];
-  uint64_t* planes = cs.planes + cs.plane_off[i];
-  const uint16_t* rp = cs.run_rowptr + cs.rowptr_off[i];
-  const uint32_t* ru = cs.runs + cs.run_off[i];
-  for (int t = threadIdx.x; t < P * N; t += blockDim.x) {
-    const int p = t / N, y = t - p * N;
-    uint64_t w[4] = {0ull, 0ull, 0ull, 0ull};
-    for (int r = rp[y]; r < rp[y + 1]; ++r) {
-      const uint32_t run = ru[r];
-      if ((int)((run >> 18) & 63) != p) continue;
-      const int x0 = run & 511, x1 = (run >> 9) & 511;
-      for (int k = 0; k < wpr; ++k) {
-        const int a = max(x0, 64 * k), b = min(x1, 64 * k + 64);
-        if (a < b) w[k] |= span_mask(a - 64 * k, b - 64 * k);
-      }
-    }
-    uint64_t* row = planes + (int64_t)p * N * wpr + (int64_t)y * wpr;
-    for (int k = 0; k < wpr; ++k) row[k] = w[k];
-  }
-}
-
-hipError_t launch_planes(const ClipsDev& cs, const int64_t* ids, int64_t n_ids, hipStream_t s) {
-  for (int64_t b0 = 0; b0 < n_ids; b0 += LAUNCH_CHUNK) {
-    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, n_ids - b0);
-    hipLaunchKernelGGL(planes_kernel, dim3(nb), dim3(256), 0, s, cs, ids, b0);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
 hipError_t launch_validate(const ClipsDev& cr, const ClipsDev& cm, int64_t n_pairs, const int32_t* rep,
                            const int32_t* mem, int need_poly, int* bad, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
