@@ -85,11 +85,14 @@ void build_ranges(const ca_clipset* cs, const ca_constraint* con, std::vector<in
 
 }  // namespace
 
-// Specialised path (all clips 128 x 128, half-windows <= 16, cosine): the
-// bounds pass runs once per (clip set, threshold); its bitmask and counts are
-// cached on the context, so sizing and writing calls share it.
-static ca_status prune128_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
-                                 int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
+// Bounds pass with a survivor bitmask (cosine on 128 x 128 clips with
+// half-windows <= 16, and the edge track): the pass runs once per (clip set,
+// constraint); its bitmask and counts are cached on the context, so sizing and
+// writing calls share it.  Edge ranges start on 64-bit words (the edge pass
+// stores whole chunk words); edge pairs are written as (smaller, larger) id.
+static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
+                                     int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
+  const bool edge = con->kind == CA_EDGE;
   PruneCache* pc = prune_cache_of(ctx);
   const bool hit = pc->gen == gen_of(cs) && pc->kind == con->kind && pc->p == con->thr_num && pc->q == con->thr_den;
   std::vector<int32_t> order, hi;
@@ -100,9 +103,10 @@ static ca_status prune128_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* c
   int64_t bits = 0;
   for (int64_t a = 0; a < na; ++a) {
     range_off[a] = bits;
-    bits += hi[a] - a - 1;
+    const int64_t len = hi[a] - a - 1;
+    bits += edge ? (len + 63) / 64 * 64 : len;
   }
-  const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na), b_mask = aup(4 * (size_t)(bits / 32 + 1));
+  const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na), b_mask = aup(8 * (size_t)(bits / 64 + 1));
   const size_t need = 2 * b_ord + 2 * b_rng + b_mask;
   char* base;
   if (!hit) {
@@ -124,9 +128,15 @@ static ca_status prune128_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* c
     HIP_TRY(ctx, hipMemcpyAsync(d_order, order.data(), 4 * na, hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemcpyAsync(d_hi, hi.data(), 4 * na, hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipMemcpyAsync(d_roff, range_off.data(), 8 * na, hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
     PruneArgs pa{d_order, d_hi, na, d_cnt, nullptr, nullptr, nullptr};
-    HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff, d_mask, false, s));
+    if (edge) {
+      HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff,
+                                     (unsigned long long*)d_mask, s));
+    } else {
+      HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
+      HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff, d_mask,
+                                   false, s));
+    }
     pc->counts.assign(na, 0);
     HIP_TRY(ctx, hipMemcpyAsync(pc->counts.data(), d_cnt, 8 * na, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -153,6 +163,7 @@ static ca_status prune128_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* c
   int64_t* d_off = (int64_t*)(base + 2 * b_ord + b_rng);  // reuses the count slots
   HIP_TRY(ctx, hipMemcpyAsync(d_off, off.data(), 8 * na, hipMemcpyHostToDevice, s));
   PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), na, nullptr, d_off, rep, mem};
+  pa.order_ids = edge ? 1 : 0;
   HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, Threshold{con->thr_num, con->thr_den},
                                (int64_t*)(base + 2 * b_ord), (uint32_t*)(base + 2 * b_ord + 2 * b_rng), true, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -162,7 +173,7 @@ static ca_status prune128_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* c
 // Device candidate generation into caller buffers (or sizing only when rep is null).
 static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
                               int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
-  if (con->kind == CA_COSINE && mixed_ok_of(cs)) return prune128_device(ctx, s, cs, con, cap, rep, mem, n_out);
+  if (con->kind == CA_EDGE || mixed_ok_of(cs)) return prune_cached_device(ctx, s, cs, con, cap, rep, mem, n_out);
   std::vector<int32_t> order, hi;
   int64_t screened = 0;
   build_ranges(cs, con, order, hi, screened);
@@ -180,8 +191,7 @@ static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, 
   HIP_TRY(ctx, hipMemcpyAsync(d_hi, hi.data(), 4 * na, hipMemcpyHostToDevice, s));
   PruneArgs pa{d_order, d_hi, na, d_cnt, nullptr, nullptr, nullptr};
   const Threshold thr{con->thr_num, con->thr_den};
-  if (con->kind == CA_COSINE) HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, maxN_of(cs), s));
-  else HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, thr, s));
+  HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, maxN_of(cs), s));
   std::vector<int64_t> cnt(na), off(na);
   HIP_TRY(ctx, hipMemcpyAsync(cnt.data(), d_cnt, 8 * na, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -199,8 +209,7 @@ static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, 
   pa.offs = d_off;
   pa.out_rep = rep;
   pa.out_mem = mem;
-  if (con->kind == CA_COSINE) HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, maxN_of(cs), s));
-  else HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, thr, s));
+  HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, maxN_of(cs), s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return CA_OK;
 }

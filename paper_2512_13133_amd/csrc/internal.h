@@ -107,6 +107,7 @@ struct PruneArgs {
   const int32_t* anchor_ids = nullptr;  // [n_anchor] anchor clip ids (null: order[a])
   const int32_t* lo = nullptr;          // [n_anchor] start of each range in `order` (null: a + 1)
   int partner_is_rep = 0;               // write the partner as the representative
+  int order_ids = 0;                    // write each pair as (smaller id, larger id)
 };
 
 }  // namespace ca

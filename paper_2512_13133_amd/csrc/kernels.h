@@ -27,7 +27,11 @@ hipError_t launch_pcm_fft64(const ClipsDev& cr, const ClipsDev& cm, const PairIO
                             int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s);
 hipError_t launch_edge(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
 hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, int maxN, hipStream_t s);
-hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, hipStream_t s);
+// Edge bounds pass: 64-bit chunk words of the survivor mask (ranges start on
+// words, range_off in bits) and survivor counts; the pairs are written by
+// launch_prune128(..., write = true) with order_ids set.
+hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
+                             unsigned long long* mask, hipStream_t s);
 // Batched MFMA surface for raster 128, half-windows <= 16 (fragment tables from
 // build_mfma128_tables: 4*3*64*8 and 8*3*64*8 halves).
 void build_mfma128_tables(_Float16* b1, _Float16* a2);

@@ -164,8 +164,12 @@ __global__ void __launch_bounds__(64) cosine_prune_kernel(ClipsDev cs, PruneArgs
 }
 
 // Edge track: one 64-lane workgroup per anchor a; lanes take partners b in
-// [a+1, hi[a]) of the same raster size, 64 at a time.
-__global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs pa, Threshold thr, int64_t block0) {
+// [a+1, hi[a]) of the same raster size, 64 at a time.  Each chunk's pass flags
+// are one 64-bit word of the survivor mask (the anchor's range starts on a
+// word, range_off[a] in bits); counts[a] gets the survivors.
+__global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs pa, Threshold thr,
+                                                        const int64_t* __restrict__ range_off,
+                                                        unsigned long long* __restrict__ mask, int64_t block0) {
   const int64_t a = block0 + (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
   const int ia = pa.order[a];
@@ -173,17 +177,17 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
   const int16_t* ba = cs.boxes + (int64_t)ia * MAX_POLY * 4;
   const int64_t end = pa.hi[a];
   const int tol = (int)(2 * thr.p);
-  int64_t written = 0;
+  unsigned long long* m = mask + (range_off[a] >> 6);
+  int64_t found = 0;
   for (int64_t b0 = a + 1; b0 < end; b0 += 64) {
     const int64_t b = b0 + lane;
-    int pass = 0;
-    int ib = -1;
+    bool pass = false;
     if (b < end) {
-      ib = pa.order[b];
+      const int ib = pa.order[b];
       const int Pb = cs.npoly[ib];
       if (Pa > 0 && Pb > 0) {
         const int16_t* bb = cs.boxes + (int64_t)ib * MAX_POLY * 4;
-        pass = 1;
+        pass = true;
         // polygons of the fewer side each need a size-compatible partner
         for (int side = 0; side < 2 && pass; ++side) {
           const bool check = side == 0 ? (Pa <= Pb) : (Pb <= Pa);
@@ -193,28 +197,21 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
           const int PX = side == 0 ? Pa : Pb, PY = side == 0 ? Pb : Pa;
           for (int p = 0; p < PX && pass; ++p) {
             const int wx = X[4 * p + 1] - X[4 * p], hx = X[4 * p + 3] - X[4 * p + 2];
-            bool found = false;
-            for (int qq = 0; qq < PY && !found; ++qq) {
+            bool hit = false;
+            for (int qq = 0; qq < PY && !hit; ++qq) {
               const int wy = Y[4 * qq + 1] - Y[4 * qq], hy = Y[4 * qq + 3] - Y[4 * qq + 2];
-              found = abs(wx - wy) <= tol && abs(hx - hy) <= tol;
+              hit = abs(wx - wy) <= tol && abs(hx - hy) <= tol;
             }
-            if (!found) pass = 0;
+            if (!hit) pass = false;
           }
         }
       }
     }
-    // ordered compaction within the chunk
-    int total = 0;
-    const int before = wave_prefix(pass != 0, lane, &total);
-    if (pass && pa.offs) {
-      const int64_t o = pa.offs[a] + written + before;
-      const int x = min(ia, ib), y = max(ia, ib);
-      pa.out_rep[o] = x;
-      pa.out_mem[o] = y;
-    }
-    written += total;
+    const unsigned long long bm = __ballot(pass);
+    if (lane == 0) m[(b0 - a - 1) >> 6] = bm;
+    found += __popcll(bm);
   }
-  if (!pa.offs && lane == 0) pa.counts[a] = written;
+  if (lane == 0) pa.counts[a] = found;
 }
 
 }  // namespace ca
@@ -232,11 +229,12 @@ hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshol
   return hipSuccess;
 }
 
-hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, hipStream_t s) {
+hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
+                             unsigned long long* mask, hipStream_t s) {
   if (pa.n_anchor == 0) return hipSuccess;
   for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
-    hipLaunchKernelGGL(edge_prune_kernel, dim3(nb), dim3(64), 0, s, cs, pa, thr, b0);
+    hipLaunchKernelGGL(edge_prune_kernel, dim3(nb), dim3(64), 0, s, cs, pa, thr, range_off, mask, b0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

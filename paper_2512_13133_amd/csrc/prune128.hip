@@ -206,8 +206,13 @@ __global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const 
     if (on) {
       const int64_t dst = o + __popcll(bm & ((1ull << lane) - 1ull));
       const int ib = pa.order[start + p];
-      pa.out_rep[dst] = pa.partner_is_rep ? ib : ia;
-      pa.out_mem[dst] = pa.partner_is_rep ? ia : ib;
+      if (pa.order_ids) {
+        pa.out_rep[dst] = min(ia, ib);
+        pa.out_mem[dst] = max(ia, ib);
+      } else {
+        pa.out_rep[dst] = pa.partner_is_rep ? ib : ia;
+        pa.out_mem[dst] = pa.partner_is_rep ? ia : ib;
+      }
     }
     o += __popcll(bm);
   }
