@@ -81,7 +81,7 @@ constexpr int MAX_CAND = 16;
 struct CandGroup {
   int64_t pair;    // pair id
   int64_t offset;  // first candidate in CandQueue::shifts
-  int32_t dir;     // direction 0 or 1
+  int32_t dir;     // direction 0 or 1; 2: both (equal windows, candidates in forward shifts)
   int32_t count;   // candidates (0: group unused)
 };
 struct CandQueue {

@@ -172,7 +172,9 @@ __device__ __forceinline__ int wave_overlap128(const uint64_t* rep, const uint64
 // Queue an undecided direction: every window shift whose low-precision value
 // is at least `cutv` becomes a candidate of the FP64 re-decision; when there
 // are more than MAX_CAND of them (or no room) the direction falls back to the
-// full FP64 surface.  Wave-wide; kept out of line to spare the caller's registers.
+// full FP64 surface.  d == 2 queues both directions of a pair with equal
+// windows at once (candidates in forward shifts; the reverse ones mirror).
+// Wave-wide; kept out of line to spare the caller's registers.
 __device__ __noinline__ void queue_candidates(const float* sw, int d, int wd, float cutv, float r1, int64_t k,
                                               int lane, RescoreQueue q, CandQueue cq) {
   int m = 0;
@@ -181,7 +183,7 @@ __device__ __noinline__ void queue_candidates(const float* sw, int d, int wd, fl
     bool ok = false;
     if (t < 33 * 33) {
       const int ty = t / 33 - 16, tx = t - (t / 33) * 33 - 16;
-      ok = ty >= -wd && ty <= wd && tx >= -wd && tx <= wd && sw[d == 0 ? t : 33 * 33 - 1 - t] >= cutv;
+      ok = ty >= -wd && ty <= wd && tx >= -wd && tx <= wd && sw[d == 1 ? 33 * 33 - 1 - t : t] >= cutv;
     }
     m += __popcll(__ballot(ok));
   }
@@ -202,7 +204,7 @@ __device__ __noinline__ void queue_candidates(const float* sw, int d, int wd, fl
       if (t < 33 * 33) {
         ty = t / 33 - 16;
         tx = t - (t / 33) * 33 - 16;
-        ok = ty >= -wd && ty <= wd && tx >= -wd && tx <= wd && sw[d == 0 ? t : 33 * 33 - 1 - t] >= cutv;
+        ok = ty >= -wd && ty <= wd && tx >= -wd && tx <= wd && sw[d == 1 ? 33 * 33 - 1 - t : t] >= cutv;
       }
       const unsigned long long bm = __ballot(ok);
       if (ok) {
@@ -221,10 +223,12 @@ __device__ __noinline__ void queue_candidates(const float* sw, int d, int wd, fl
       gr.count = fits ? m : 0;
       cq.groups[slot] = gr;
     }
-    q.r1_low[k * 2 + d] = r1;
+    const uint8_t dirs = d == 2 ? 3u : (uint8_t)(1u << d);
+    if (dirs & 1u) q.r1_low[k * 2 + 0] = r1;
+    if (dirs & 2u) q.r1_low[k * 2 + 1] = r1;
     if (!fits) {
       const uint8_t old = q.need[k];
-      q.need[k] = (uint8_t)(old | (1u << d));
+      q.need[k] = (uint8_t)(old | dirs);
       if (old == 0) {
         const unsigned long long qs = atomicAdd(q.len, 1ull);
         q.list[qs] = k;
@@ -547,8 +551,12 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
           float* so = surf_out + k * 33 * 33;
           for (int t = lane; t < 33 * 33; t += 64) so[t] = sw[t] / (float)K_hi;
         }
-        if (!dec0) queue_candidates(sw, 0, w_i, v1f - band * (float)K_hi, v1f / (float)K_hi, k, lane, q, cq);
-        if (!dec1) queue_candidates(sw, 1, w_j, v1r - band * (float)K_hi, v1r / (float)K_hi, k, lane, q, cq);
+        if (w_i == w_j) {  // one group settles both (mirrored) directions
+          if (!dec0) queue_candidates(sw, 2, w_i, v1f - band * (float)K_hi, v1f / (float)K_hi, k, lane, q, cq);
+        } else {
+          if (!dec0) queue_candidates(sw, 0, w_i, v1f - band * (float)K_hi, v1f / (float)K_hi, k, lane, q, cq);
+          if (!dec1) queue_candidates(sw, 1, w_j, v1r - band * (float)K_hi, v1r / (float)K_hi, k, lane, q, cq);
+        }
         // the tile is rewritten by the wave's next pair only after every lane is done reading
         __builtin_amdgcn_wave_barrier();
       }

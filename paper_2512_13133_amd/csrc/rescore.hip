@@ -11,6 +11,11 @@
 // bins where both spectra are non-zero.  Shifts within TAU of the best are
 // tied; the larger overlap count c wins, then the smaller |dy|+|dx|, then the
 // lexicographically smaller (dy, dx).
+//
+// A group of both directions (equal windows) holds forward shifts.  The
+// reverse direction's value and overlap count at -s equal the forward ones at
+// s, so the sums and counts serve both; only the lexicographic tie-break is
+// taken in each direction's own coordinates.
 #include "kernels.h"
 #include "pair_common.h"
 
@@ -52,8 +57,8 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
   for (int c = 0; c < MAX_CAND; ++c) {
     const int16_t sh = c < m ? cq.shifts[gr.offset + c] : (int16_t)0;
     const int sy = (int8_t)(sh >> 8), sx = (int8_t)(sh & 0xff);
-    fy[c] = d == 0 ? sy : -sy;
-    fx[c] = d == 0 ? sx : -sx;
+    fy[c] = d == 1 ? -sy : sy;
+    fx[c] = d == 1 ? -sx : sx;
     acc[c] = 0.0;
   }
   int kc = 0;
@@ -70,7 +75,7 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
     for (int c = 0; c < MAX_CAND; ++c) {
       if (c >= m) break;
       // e^{+2 pi i (u dy + v dx)/N} = conj(tw[(u dy + v dx) mod N])
-      const int e = ((u * fy[c] + v * fx[c]) % N + N) % N;
+      const int e = (u * fy[c] + v * fx[c]) & (N - 1);  // N is a power of two
       const double2 t = tw[e];
       acc[c] += rr * t.x + ri * t.y;  // Re((rr + i ri)(t.x - i t.y))
     }
@@ -98,36 +103,44 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
   const double cut = best - TAU * (double)K;
   const uint64_t* bits_i = cm.bits + cm.bits_off[i];
   const uint64_t* bits_j = cr.bits + cr.bits_off[j];
-  const uint64_t* brep = d == 0 ? bits_j : bits_i;
-  const uint64_t* bmem = d == 0 ? bits_i : bits_j;
-  int best_c = -1, best_l1 = 0, best_dy = 0, best_dx = 0;
+  // candidate shifts are in the group's coordinates: forward for d = 0 and 2
+  const uint64_t* brep = d == 1 ? bits_i : bits_j;
+  const uint64_t* bmem = d == 1 ? bits_j : bits_i;
+  // best per direction of the group: [0] in the stored coordinates, [1] mirrored (d == 2)
+  int best_c[2] = {-1, -1}, best_l1[2] = {0, 0}, best_dy[2] = {0, 0}, best_dx[2] = {0, 0};
   for (int c = 0; c < m; ++c) {
     if (s_acc[c] < cut) continue;
     const int16_t sh = cq.shifts[gr.offset + c];
     const int dy = (int8_t)(sh >> 8), dx = (int8_t)(sh & 0xff);
     const int cnt = block_overlap(brep, bmem, N, dy, dx, ired);
     const int l1 = abs(dy) + abs(dx);
-    bool better = false;
-    if (best_c < 0 || cnt > best_c) better = true;
-    else if (cnt == best_c) {
-      if (l1 < best_l1) better = true;
-      else if (l1 == best_l1 && (dy < best_dy || (dy == best_dy && dx < best_dx))) better = true;
+    for (int h = 0; h < (d == 2 ? 2 : 1); ++h) {
+      const int ey = h == 0 ? dy : -dy, ex = h == 0 ? dx : -dx;
+      bool better = false;
+      if (best_c[h] < 0 || cnt > best_c[h]) better = true;
+      else if (cnt == best_c[h]) {
+        if (l1 < best_l1[h]) better = true;
+        else if (l1 == best_l1[h] && (ey < best_dy[h] || (ey == best_dy[h] && ex < best_dx[h]))) better = true;
+      }
+      if (better) { best_c[h] = cnt; best_l1[h] = l1; best_dy[h] = ey; best_dx[h] = ex; }
     }
-    if (better) { best_c = cnt; best_l1 = l1; best_dy = dy; best_dx = dx; }
   }
   if (tid == 0) {
     const int n_i = cm.npix[i], n_j = cr.npix[j];
-    const int nm = d == 0 ? n_i : n_j, nr = d == 0 ? n_j : n_i;
-    // the other direction of the pair may be decided concurrently by another
-    // workgroup, so the shared byte of cover bits is updated atomically
-    write_direction_atomic(io, k, d, best_dy, best_dx, best_c, cosine_score(best_c, nm, nr),
-                           cosine_bit(best_c, nm, nr, thr));
-    atomicOr(io.flags + k, d == 0 ? (uint32_t)CA_FLAG_RESCORED_FWD : (uint32_t)CA_FLAG_RESCORED_REV);
-    if (peak_err_bits) {
-      // compare like with like: both sides normalised by K_hi
-      const double K_hi = (double)(N * N - max(cm.zero_bins[i], cr.zero_bins[j]));
-      const double err = fabs(best / K_hi - (double)r1_low[k * 2 + d]);
-      atomicMax(peak_err_bits, (unsigned long long)__double_as_longlong(err));
+    const double K_hi = (double)(N * N - max(cm.zero_bins[i], cr.zero_bins[j]));
+    for (int h = 0; h < (d == 2 ? 2 : 1); ++h) {
+      const int dd = d == 2 ? h : d;  // the pair direction written
+      const int nm = dd == 0 ? n_i : n_j, nr = dd == 0 ? n_j : n_i;
+      // the other direction of the pair may be decided concurrently by another
+      // workgroup, so the shared byte of cover bits is updated atomically
+      write_direction_atomic(io, k, dd, best_dy[h], best_dx[h], best_c[h], cosine_score(best_c[h], nm, nr),
+                             cosine_bit(best_c[h], nm, nr, thr));
+      atomicOr(io.flags + k, dd == 0 ? (uint32_t)CA_FLAG_RESCORED_FWD : (uint32_t)CA_FLAG_RESCORED_REV);
+      if (peak_err_bits) {
+        // compare like with like: both sides normalised by K_hi
+        const double err = fabs(best / K_hi - (double)r1_low[k * 2 + dd]);
+        atomicMax(peak_err_bits, (unsigned long long)__double_as_longlong(err));
+      }
     }
   }
 }
