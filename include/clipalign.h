@@ -82,8 +82,17 @@ typedef struct {
  *     workgroup per pair, inverse transform by FFT on the vector ALUs; near
  *     ties re-decided in FP64.  All raster sizes and windows.
  *   CA_PATH_FP64: the FP64 surface and exact tie rule for every pair.
- * All three return identical shifts, counts, scores and bits. */
-enum { CA_PATH_MIXED = 0, CA_PATH_FP32 = 1, CA_PATH_FP64 = 2 };
+ *   CA_PATH_AUTO: pairs of any raster size and window in one call.  The pairs
+ *     are partitioned (stably) into buckets by raster size and window class
+ *     (the larger half-window: <= 4, <= 8, <= 15, 16, <= 23, <= 31, more);
+ *     each bucket runs the path the context's tuning table names for it.  A
+ *     bucket met for the first time is tuned on up to 4,096 of its pairs
+ *     (repeated to at least 1,024 when the bucket is smaller):
+ *     every applicable path is timed, a path is admitted only if its results
+ *     equal CA_PATH_FP64's bit for bit, and the fastest admitted one is kept
+ *     (see ca_autotune_*).  Results return in the caller's order.
+ * All of them return identical shifts, counts, scores and bits. */
+enum { CA_PATH_MIXED = 0, CA_PATH_FP32 = 1, CA_PATH_FP64 = 2, CA_PATH_AUTO = 3 };
 
 /* Per-pair flag bits written by the alignment calls. */
 enum {
@@ -185,7 +194,8 @@ ca_status ca_clips_inspect(const ca_clipset* cs, int64_t i, uint64_t* bits, int3
  * bounding-box edges, re-check at the final shift, bit iff E <= thr_num;
  * `path` is ignored.
  * Asynchronous on `stream` for CA_PATH_FP64 and the edge track; the other
- * paths synchronise once to size the FP64 re-decision pass. */
+ * paths synchronise once to size the FP64 re-decision pass, and
+ * CA_PATH_AUTO allocates its work space and synchronises per bucket. */
 ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
                          const ca_constraint* con, int32_t path, int64_t n_pairs,
                          const int32_t* rep, const int32_t* mem, uint8_t* bits,
@@ -201,6 +211,22 @@ ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
  * Synchronises. */
 ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs, int32_t path, int64_t n_pairs,
                      const int32_t* rep, const int32_t* mem, float* surf);
+
+/* Autotuner table of CA_PATH_AUTO (paper Sec. 3.2, the alignment of each
+ * candidate pair; the choice only affects speed, never results).
+ *   ca_autotune_report: one text line per tuned bucket (raster size, window
+ *     class bound, chosen path, measured microseconds per 1,000 pairs of each
+ *     path, -1 when not applicable or not admitted, sample size) into buf
+ *     (NUL-terminated, at most cap bytes); *len gets the full length, and
+ *     CA_ETRUNC is returned when cap is too small.
+ *   ca_autotune_save / ca_autotune_load: the table as a text file (path is a
+ *     host string); load replaces the table and rejects files of other
+ *     formats with CA_EINVAL.
+ *   ca_autotune_clear: empties the table (buckets are tuned again on use). */
+ca_status ca_autotune_report(ca_ctx* ctx, char* buf, int64_t cap, int64_t* len);
+ca_status ca_autotune_save(ca_ctx* ctx, const char* path);
+ca_status ca_autotune_load(ca_ctx* ctx, const char* path);
+ca_status ca_autotune_clear(ca_ctx* ctx);
 
 /* ---- multi-stage pruning (paper Sec. 3.1 stage 1, Table 2) --------------- */
 

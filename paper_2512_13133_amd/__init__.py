@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libclipalign.so")
 
 CA_OK, CA_EINVAL, CA_ENOMEM, CA_EDEVICE, CA_EBUSY, CA_ETRUNC, CA_ESTATE, CA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 CA_COSINE, CA_EDGE = 1, 2
-PATHS = {"mixed": 0, "fp32": 1, "fp64": 2}
+PATHS = {"mixed": 0, "fp32": 1, "fp64": 2, "auto": 3}
 CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64 = 1, 2, 4
 FLAG_RESCORED_FWD, FLAG_RESCORED_REV, FLAG_EMPTY = 1, 2, 4
 FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16, 32, 64
@@ -33,6 +33,7 @@ SYMBOLS = [
     "ca_align_pairs", "ca_surface", "ca_prune", "ca_cluster",
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
     "ca_server_stats", "ca_server_last_error",
+    "ca_autotune_report", "ca_autotune_save", "ca_autotune_load", "ca_autotune_clear",
 ]
 
 
@@ -94,6 +95,10 @@ def load():
     lib.ca_server_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
     lib.ca_server_last_error.argtypes = [P]
     lib.ca_server_last_error.restype = C.c_char_p
+    lib.ca_autotune_report.argtypes = [P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)]
+    lib.ca_autotune_save.argtypes = [P, C.c_char_p]
+    lib.ca_autotune_load.argtypes = [P, C.c_char_p]
+    lib.ca_autotune_clear.argtypes = [P]
     for name in SYMBOLS:
         if name not in ("ca_last_error", "ca_server_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -242,6 +247,23 @@ class Context:
         self._check(self.lib.ca_cluster(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path],
                                         int(iterations), _ptr(rep_of), _ptr(shift), C.byref(k)))
         return dict(rep_of=rep_of, center_shift=shift, n_clusters=int(k.value))
+
+    def autotune_report(self):
+        """Tuned buckets of CA_PATH_AUTO, one text line each."""
+        n = C.c_int64(0)
+        self._check(self.lib.ca_autotune_report(self.h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value + 1)
+        self._check(self.lib.ca_autotune_report(self.h, buf, n.value + 1, C.byref(n)))
+        return buf.value.decode()
+
+    def autotune_save(self, path):
+        self._check(self.lib.ca_autotune_save(self.h, str(path).encode()))
+
+    def autotune_load(self, path):
+        self._check(self.lib.ca_autotune_load(self.h, str(path).encode()))
+
+    def autotune_clear(self):
+        self._check(self.lib.ca_autotune_clear(self.h))
 
     def stats(self):
         s = _Stats()

@@ -40,6 +40,7 @@ struct ca_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   capriv::PruneCache prune_cache;
   uint64_t next_gen = 1;
+  std::map<int, capriv::TuneEntry> tune;  // autotuner choices by bucket key
 };
 
 struct ca_clipset {
@@ -492,8 +493,10 @@ FftPlan plan_fft(int N, int L, int scalar_bytes) {
 }  // namespace
 
 // Cosine alignment of a device pair list with the chosen path (no validation).
+// `checked`: the caller guarantees that every pair suits the path (the
+// autotuner's buckets), so the set-wide shape test of CA_PATH_MIXED is skipped.
 static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                              Threshold thr, int path, const PairIO& io) {
+                              Threshold thr, int path, const PairIO& io, bool checked = false) {
   const int maxN = std::max(crs->maxN, cms->maxN), Lmax = std::max(crs->Lmax, cms->Lmax);
   const ClipsDev& cr = crs->d;
   const ClipsDev& cm = cms->d;
@@ -538,7 +541,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
                                       pl.LINES, Lmax, maxN, q, s));
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
   } else {
-    if (!crs->mixed_ok || !cms->mixed_ok)
+    if (!checked && (!crs->mixed_ok || !cms->mixed_ok))
       return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
     HIP_OR_FAIL(ctx, launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
@@ -582,9 +585,14 @@ ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
   return clips_create_impl(ctx, stream, n, rect_ptr, rects, raster_n, marker_w, 0, arena, out);
 }
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                            Threshold thr, int path, const PairIO& io) {
-  return align_cosine(ctx, crs, cms, s, thr, path, io);
+                            Threshold thr, int path, const PairIO& io, bool checked) {
+  return align_cosine(ctx, crs, cms, s, thr, path, io, checked);
 }
+}  // namespace capriv
+
+namespace capriv {
+// Bucketed, autotuned alignment (api_auto.hip).
+ca_status align_auto(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshold thr, const PairIO& io);
 }  // namespace capriv
 
 extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
@@ -599,7 +607,7 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
   if (!rep || !mem || !bits || !shift || !count || !score || !flags)
     return fail(ctx, CA_EINVAL, "null output or pair pointer");
   if (n_pairs > (1ll << 31) - 1) return fail(ctx, CA_EINVAL, "pair list longer than 2^31 - 1");
-  if (path < CA_PATH_MIXED || path > CA_PATH_FP64) return fail(ctx, CA_EINVAL, "bad path");
+  if (path < CA_PATH_MIXED || path > CA_PATH_AUTO) return fail(ctx, CA_EINVAL, "bad path");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE);
@@ -611,6 +619,7 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
     ctx->stats.pairs_edge += n_pairs;
     return CA_OK;
   }
+  if (path == CA_PATH_AUTO) return capriv::align_auto(ctx, cs, s, Threshold{con->thr_num, con->thr_den}, io);
   return align_cosine(ctx, cs, cs, s, Threshold{con->thr_num, con->thr_den}, path, io);
 }
 
@@ -633,6 +642,10 @@ const std::vector<int32_t>& hnpix_of(const ca_clipset* cs) { return cs->hnpix; }
 int64_t n_of(const ca_clipset* cs) { return cs->n; }
 int maxN_of(const ca_clipset* cs) { return cs->maxN; }
 bool mixed_ok_of(const ca_clipset* cs) { return cs->mixed_ok; }
+bool has_fp32_of(const ca_clipset* cs) { return cs->d.spec32 != nullptr; }
+const std::vector<int16_t>& hw_of(const ca_clipset* cs) { return cs->hw; }
+std::map<int, TuneEntry>& tune_of(ca_ctx* ctx) { return ctx->tune; }
+void set_stats(ca_ctx* ctx, const ca_run_stats& st) { ctx->stats = st; }
 uint64_t gen_of(const ca_clipset* cs) { return cs->gen; }
 PruneCache* prune_cache_of(ca_ctx* ctx) { return &ctx->prune_cache; }
 }  // namespace capriv

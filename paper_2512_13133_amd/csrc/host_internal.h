@@ -3,11 +3,21 @@
 
 #include <stdint.h>
 
+#include <map>
 #include <vector>
 
 namespace capriv {
 
-// Result of the last cosine bounds pass of ca_prune on 128 x 128 sets, kept
+// Path chosen by the autotuner for one (raster size, window class) bucket,
+// with the measured time of every path tried on the calibration sample
+// (microseconds per 1,000 pairs; negative when not applicable or not valid).
+struct TuneEntry {
+  int path = -1;
+  double us_per_kpair[4] = {-1.0, -1.0, -1.0, -1.0};  // indexed by CA_PATH_*
+  int64_t sample = 0;
+};
+
+// Result of the last bounds pass of ca_prune (cosine on 128 x 128 sets, edge), kept
 // on the context so that a sizing call and the following writing call share it.
 struct PruneCache {
   uint64_t gen = 0;              // clip-set generation (0 = empty)

@@ -147,6 +147,55 @@ def test_cosine_mixed_sizes_and_windows(ctx, path):
     h.close()
 
 
+def test_cosine_auto_buckets(ctx, tmp_path):
+    """CA_PATH_AUTO over mixed raster sizes and windows (64/128/256, half-windows
+    0..32, empty clips): one call, buckets tuned on first use (each admitted
+    path equal to FP64 on its sample), results in the caller's order equal to
+    the oracle's; the tuning table survives a save/load round trip."""
+    cs = mixed_set()
+    rep, mem = pairs_for(cs, 1200, seed=8)
+    perm = np.random.default_rng(8).permutation(rep.size)  # buckets interleaved in the input
+    rep, mem = rep[perm], mem[perm]
+    h = ctx.clips(cs, fp32=True)
+    ctx.autotune_clear()
+    got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (97, 100), "auto"))
+    ref = cover.align_pairs_cosine(cs, rep, mem, 97, 100, workers=WORKERS)
+    check_cosine(got, ref, rep, mem, "mixed/auto")
+    report = ctx.autotune_report()
+    say("[auto]\n" + report)
+    lines = [ln for ln in report.splitlines() if ln]
+    sizes = {int(ln.split()[0][2:]) for ln in lines}
+    assert sizes == {64, 128, 256}
+    f = tmp_path / "tune.txt"
+    ctx.autotune_save(f)
+    ctx.autotune_clear()
+    assert ctx.autotune_report() == ""
+    ctx.autotune_load(f)
+    assert ctx.autotune_report() == report
+    again = to_np(ctx.align_pairs(h, rep, mem, "cosine", (97, 100), "auto"))
+    check_cosine(again, ref, rep, mem, "mixed/auto/loaded")
+    h.close()
+
+
+def test_cosine_auto_c128_picks_mfma(ctx):
+    """On 128 x 128 pairs with half-window 16 the tuner admits and picks the
+    batched MFMA path (it is exact after the re-decision and fastest)."""
+    cs = c128_subset(200, seed=4)
+    rep, mem = pairs_for(cs, 6000, seed=4)
+    o = np.lexsort((mem, rep))
+    rep, mem = rep[o], mem[o]
+    h = ctx.clips(cs, fp32=True)
+    ctx.autotune_clear()
+    got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "auto"))
+    ref = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
+    check_cosine(got, ref, rep, mem, "c128/auto")
+    report = ctx.autotune_report()
+    say("[auto]\n" + report)
+    line = [ln for ln in report.splitlines() if ln.startswith("N=128 w<=16")]
+    assert line and "path=mixed" in line[0], report
+    h.close()
+
+
 @pytest.mark.parametrize("path", ["fp32", "fp64"])
 def test_cosine_c128(ctx, path):
     cs = c128_subset(160)
