@@ -545,7 +545,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
       return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
     HIP_OR_FAIL(ctx, launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
-                                        nullptr, s));
+                                        nullptr, counters + 4, s));
     HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
   }
   unsigned long long h[4] = {0, 0, 0, 0};
@@ -681,7 +681,7 @@ extern "C" ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs,
   HIP_OR_FAIL(ctx, hipMemsetAsync(q.len, 0, 32, s));
   CandQueue cq{nullptr, nullptr, q.len + 2, q.len + 3, 0, 0};
   HIP_OR_FAIL(ctx, launch_pcm_mfma128(cs->d, cs->d, io, Threshold{1, 1}, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
-                                      surf, s));
+                                      surf, q.len + 4, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
   return CA_OK;
 }

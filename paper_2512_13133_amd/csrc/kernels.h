@@ -35,9 +35,11 @@ hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold 
 // Batched MFMA surface for raster 128, half-windows <= 16 (fragment tables from
 // build_mfma128_tables: 4*3*64*8 and 8*3*64*8 halves).
 void build_mfma128_tables(_Float16* b1, _Float16* a2);
+// Persistent launch: `tiles` is device memory for the tile counter (cleared
+// here on the stream).
 hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr, float band,
                               const RescoreQueue& q, const CandQueue& cq, const void* b1frag,
-                              const void* a2frag, float* surf_out, hipStream_t s);
+                              const void* a2frag, float* surf_out, unsigned long long* tiles, hipStream_t s);
 // FP64 re-decision of queued directions at their candidate shifts.
 hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                      const CandQueue& cq, int64_t n_groups, const double2* tw256,
