@@ -189,6 +189,7 @@ def main():
                                     "pairs_survived")}
     stage_ms = {k: round(v * 1000.0 / args.steps, 2) for k, v in stage_t.items()}
 
+    graph = graph_bench(ctx, h, rep, mem)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cs, rep.cpu().numpy(), mem.cpu().numpy(), args.cpu_seconds)
@@ -214,8 +215,37 @@ def main():
         "stage_ms": stage_ms,
         "stats": stats_out,
         "serving": serving,
+        "graph": graph,
     }
     print(json.dumps(line))
+
+
+def graph_bench(ctx, h, rep, mem, n=4096, reps=50):
+    """Small batches: the mixed alignment of n pairs as one captured graph
+    launch against the eager call (launches plus its host round trips)."""
+    import torch
+    r, m = rep[:n].clone(), mem[:n].clone()
+    g = ctx.graph(h, n, (19, 20))
+    g.set_pairs(r, m)
+    for _ in range(3):
+        g.launch()
+        ctx.align_pairs(h, r, m, "cosine", (19, 20), "mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.launch()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.align_pairs(h, r, m, "cosine", (19, 20), "mixed")
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / reps
+    same = all(bool(torch.equal(g.out[k], v)) for k, v in
+               ctx.align_pairs(h, r, m, "cosine", (19, 20), "mixed").items() if k != "flags")
+    g.close()
+    return {"pairs": n, "graph_ms": round(t_graph * 1e3, 3), "eager_ms": round(t_eager * 1e3, 3),
+            "identical_results": same}
 
 
 def serve_bench(ctx, n_library, seconds, slots=4):

@@ -102,7 +102,8 @@ enum {
   CA_FLAG_NO_MATCH_FWD = 1u << 3, /* edge: no polygon correspondence (forward) */
   CA_FLAG_NO_MATCH_REV = 1u << 4, /* edge: no polygon correspondence (reverse) */
   CA_FLAG_RECHECK_FWD = 1u << 5,  /* edge: correspondence changed at final shift */
-  CA_FLAG_RECHECK_REV = 1u << 6
+  CA_FLAG_RECHECK_REV = 1u << 6,
+  CA_FLAG_INVALID = 1u << 7       /* graph replay: a pair id out of range (no result) */
 };
 
 /* Run statistics accumulated on a context since creation or the last reset. */
@@ -227,6 +228,35 @@ ca_status ca_autotune_report(ca_ctx* ctx, char* buf, int64_t cap, int64_t* len);
 ca_status ca_autotune_save(ca_ctx* ctx, const char* path);
 ca_status ca_autotune_load(ca_ctx* ctx, const char* path);
 ca_status ca_autotune_clear(ca_ctx* ctx);
+
+/* ---- captured alignment (hipGraph) ---------------------------------------- */
+
+/* A HIP graph of the whole CA_PATH_MIXED cosine alignment (paper Eqs. 2-5) of
+ * a fixed device pair buffer: counters cleared by a kernel, the pair ids
+ * copied and range-checked, the batched MFMA surface kernel, the FP64
+ * re-decision sized on the device, and a fix-up of rejected pairs, with no
+ * host synchronisation, so a replay is one graph launch.
+ *   ca_graph_create: rep, mem, bits, shift, count, score, flags are device
+ *     buffers of n_pairs entries (layouts as ca_align_pairs) that the graph
+ *     reads and writes at every launch; the caller may change the pair ids
+ *     between launches.  The clip set must be one CA_PATH_MIXED accepts
+ *     (CA_EUNSUPPORTED otherwise) and must outlive the graph; cosine only.
+ *     The graph owns its work space (allocated here, counted against the
+ *     context's budget).  Captures on `stream`.
+ *   ca_graph_launch: replays on `stream` (asynchronous).  A pair whose ids are
+ *     out of range gets bits 0, shifts 0, counts -1, scores 0 and flags
+ *     CA_FLAG_INVALID; every other pair gets exactly ca_align_pairs' result.
+ *   ca_graph_invalid: synchronises `stream` and returns the number of pairs
+ *     rejected by the last launch.
+ *   ca_graph_destroy: releases the graph and its work space.
+ * Launches of one graph must not overlap (they share the work space). */
+typedef struct ca_graph ca_graph;
+ca_status ca_graph_create(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                          int64_t n_pairs, const int32_t* rep, const int32_t* mem, uint8_t* bits,
+                          int16_t* shift, int32_t* count, double* score, uint32_t* flags, ca_graph** out);
+ca_status ca_graph_launch(ca_graph* g, void* stream);
+ca_status ca_graph_invalid(ca_graph* g, void* stream, int64_t* n_invalid);
+ca_status ca_graph_destroy(ca_graph* g);
 
 /* ---- multi-stage pruning (paper Sec. 3.1 stage 1, Table 2) --------------- */
 

@@ -26,6 +26,7 @@ PATHS = {"mixed": 0, "fp32": 1, "fp64": 2, "auto": 3}
 CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64 = 1, 2, 4
 FLAG_RESCORED_FWD, FLAG_RESCORED_REV, FLAG_EMPTY = 1, 2, 4
 FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16, 32, 64
+FLAG_INVALID = 128
 
 SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
@@ -34,6 +35,7 @@ SYMBOLS = [
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
     "ca_server_stats", "ca_server_last_error",
     "ca_autotune_report", "ca_autotune_save", "ca_autotune_load", "ca_autotune_clear",
+    "ca_graph_create", "ca_graph_launch", "ca_graph_invalid", "ca_graph_destroy",
 ]
 
 
@@ -99,6 +101,10 @@ def load():
     lib.ca_autotune_save.argtypes = [P, C.c_char_p]
     lib.ca_autotune_load.argtypes = [P, C.c_char_p]
     lib.ca_autotune_clear.argtypes = [P]
+    lib.ca_graph_create.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int64, P, P, P, P, P, P, P, C.POINTER(P)]
+    lib.ca_graph_launch.argtypes = [P, P]
+    lib.ca_graph_invalid.argtypes = [P, P, C.POINTER(C.c_int64)]
+    lib.ca_graph_destroy.argtypes = [P]
     for name in SYMBOLS:
         if name not in ("ca_last_error", "ca_server_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -248,6 +254,10 @@ class Context:
                                         int(iterations), _ptr(rep_of), _ptr(shift), C.byref(k)))
         return dict(rep_of=rep_of, center_shift=shift, n_clusters=int(k.value))
 
+    def graph(self, clips, n_pairs, thr=(19, 20)):
+        """A captured CA_PATH_MIXED cosine alignment of a fixed pair buffer (``ca_graph_*``)."""
+        return Graph(self, clips, n_pairs, thr)
+
     def autotune_report(self):
         """Tuned buckets of CA_PATH_AUTO, one text line each."""
         n = C.c_int64(0)
@@ -272,6 +282,54 @@ class Context:
 
     def reset_stats(self):
         self._check(self.lib.ca_reset_stats(self.h))
+
+
+class Graph:
+    """Replayable alignment of ``n_pairs`` pairs: write ids with ``set_pairs``,
+    then ``launch``; results live in ``out`` (CUDA tensors)."""
+
+    def __init__(self, ctx, clips, n_pairs, thr=(19, 20)):
+        torch = ctx.torch
+        self.ctx, self.lib, self.clips, self.n = ctx, ctx.lib, clips, int(n_pairs)
+        self.rep = torch.zeros(self.n, dtype=torch.int32, device=ctx.dev)
+        self.mem = torch.zeros(self.n, dtype=torch.int32, device=ctx.dev)
+        self.out = dict(
+            bits=torch.empty(self.n, dtype=torch.uint8, device=ctx.dev),
+            shift=torch.empty((self.n, 2, 2), dtype=torch.int16, device=ctx.dev),
+            count=torch.empty((self.n, 2), dtype=torch.int32, device=ctx.dev),
+            score=torch.empty((self.n, 2), dtype=torch.float64, device=ctx.dev),
+            flags=torch.empty(self.n, dtype=torch.int32, device=ctx.dev),
+        )
+        con = constraint("cosine", thr)
+        self.h = P()
+        ctx._check(self.lib.ca_graph_create(ctx.h, ctx._stream(), clips.handle, C.byref(con), self.n,
+                                            _ptr(self.rep), _ptr(self.mem), _ptr(self.out["bits"]),
+                                            _ptr(self.out["shift"]), _ptr(self.out["count"]),
+                                            _ptr(self.out["score"]), _ptr(self.out["flags"]), C.byref(self.h)))
+
+    def set_pairs(self, rep, mem):
+        torch = self.ctx.torch
+        self.rep.copy_(torch.as_tensor(rep, dtype=torch.int32))
+        self.mem.copy_(torch.as_tensor(mem, dtype=torch.int32))
+
+    def launch(self):
+        self.ctx._check(self.lib.ca_graph_launch(self.h, self.ctx._stream()))
+
+    def invalid(self):
+        n = C.c_int64(0)
+        self.ctx._check(self.lib.ca_graph_invalid(self.h, self.ctx._stream(), C.byref(n)))
+        return int(n.value)
+
+    def close(self):
+        if self.h:
+            self.lib.ca_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -492,6 +492,69 @@ FftPlan plan_fft(int N, int L, int scalar_bytes) {
 
 }  // namespace
 
+// Queue storage of the low-precision paths for n pairs: need[n], list[n],
+// r1_low[2n], 32 counters (0 queued pairs, 1 max error bits, 2 candidate
+// groups, 3 candidate shifts, 4 tile counter, rest spare), candidate groups
+// and their shifts.
+struct QueueMem {
+  RescoreQueue q;
+  CandQueue cq;
+  unsigned long long* counters;
+};
+static size_t queue_bytes(int64_t n) {
+  const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
+  return align_up(n) + 2 * align_up(8 * (size_t)n) + 256 + align_up(sizeof(CandGroup) * (size_t)cap_g) +
+         align_up(2 * (size_t)cap_s);
+}
+static QueueMem queue_carve(char* base, int64_t n) {
+  const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
+  const size_t b_need = align_up(n), b_list = align_up(8 * (size_t)n), b_r1 = align_up(8 * (size_t)n);
+  const size_t b_cnt = 256, b_grp = align_up(sizeof(CandGroup) * (size_t)cap_g);
+  QueueMem m;
+  m.q.need = (uint8_t*)base;
+  m.q.list = (int64_t*)(base + b_need);
+  m.q.r1_low = (float*)(base + b_need + b_list);
+  m.counters = (unsigned long long*)(base + b_need + b_list + b_r1);
+  m.q.len = m.counters;
+  m.q.peak_err_bits = m.counters + 1;
+  m.cq.n_groups = m.counters + 2;
+  m.cq.n_shifts = m.counters + 3;
+  m.cq.groups = (CandGroup*)(base + b_need + b_list + b_r1 + b_cnt);
+  m.cq.shifts = (int16_t*)(base + b_need + b_list + b_r1 + b_cnt + b_grp);
+  m.cq.cap_groups = cap_g;
+  m.cq.cap_shifts = cap_s;
+  return m;
+}
+
+// The device sequence of a low-precision path (CA_PATH_FP32 or CA_PATH_MIXED):
+// counters cleared by a kernel, the main surface kernel (bracketed by the
+// context's events when `events`), then the FP64 re-decision sized on the
+// device.  No host synchronisation, so it can be captured in a graph.
+static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev& cm, int maxN, int Lmax, int path,
+                                 Threshold thr, const PairIO& io, const QueueMem& m, hipStream_t s, bool events) {
+  const int64_t n = io.n_pairs;
+  hipError_t e = launch_zero_u64(m.counters, 32, s);
+  if (e != hipSuccess) return e;
+  if (events && (e = hipEventRecord(ctx->ev0, s)) != hipSuccess) return e;
+  if (path == CA_PATH_FP32) {
+    FftPlan pl = plan_fft(maxN, Lmax, 4);
+    e = launch_pcm_fft32(cr, cm, io, nullptr, n, MODE_LOW, thr, BAND_FP32, ctx->tw32, pl.CH, pl.LINES, Lmax, maxN,
+                         m.q, s);
+  } else {
+    e = launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, m.q, m.cq, ctx->mf_b1, ctx->mf_a2, nullptr,
+                           m.counters + 4, s);
+  }
+  if (e != hipSuccess) return e;
+  if (events && (e = hipEventRecord(ctx->ev1, s)) != hipSuccess) return e;
+  // FP64 re-decision: the candidate groups, then the full FP64 surface of the
+  // pairs queued for it
+  e = launch_rescore_candidates(cr, cm, io, thr, m.cq, ctx->tw64, m.q.peak_err_bits, m.q.r1_low, s);
+  if (e != hipSuccess) return e;
+  FftPlan pl = plan_fft(maxN, Lmax, 8);
+  return launch_pcm_fft64(cr, cm, io, m.q.list, n, MODE_RESCORE, thr, 0.0, ctx->tw64, pl.CH, pl.LINES, Lmax, maxN,
+                          m.q, s, m.q.len);
+}
+
 // Cosine alignment of a device pair list with the chosen path (no validation).
 // `checked`: the caller guarantees that every pair suits the path (the
 // autotuner's buckets), so the set-wide shape test of CA_PATH_MIXED is skipped.
@@ -511,43 +574,15 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   }
   if (path == CA_PATH_FP32 && (!cr.spec32 || !cm.spec32))
     return fail(ctx, CA_ESTATE, "CA_PATH_FP32 needs a clip set created with CA_CLIPS_FP32");
-  // queue storage: need[n], list[n], r1_low[2n], counters, candidate groups and shifts
-  const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
-  const size_t b_need = align_up(n), b_list = align_up(8 * (size_t)n), b_r1 = align_up(8 * (size_t)n);
-  const size_t b_cnt = 256, b_grp = align_up(sizeof(CandGroup) * (size_t)cap_g), b_sh = align_up(2 * (size_t)cap_s);
+  if (path == CA_PATH_MIXED && !checked && (!crs->mixed_ok || !cms->mixed_ok))
+    return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
   void* sc;
-  ca_status st = scratch(ctx, b_need + b_list + b_r1 + b_cnt + b_grp + b_sh, &sc);
+  ca_status st = scratch(ctx, queue_bytes(n), &sc);
   if (st) return st;
-  RescoreQueue q;
-  char* base = (char*)sc;
-  q.need = (uint8_t*)base;
-  q.list = (int64_t*)(base + b_need);
-  q.r1_low = (float*)(base + b_need + b_list);
-  unsigned long long* counters = (unsigned long long*)(base + b_need + b_list + b_r1);
-  q.len = counters;
-  q.peak_err_bits = counters + 1;
-  CandQueue cq;
-  cq.n_groups = counters + 2;
-  cq.n_shifts = counters + 3;
-  cq.groups = (CandGroup*)(base + b_need + b_list + b_r1 + b_cnt);
-  cq.shifts = (int16_t*)(base + b_need + b_list + b_r1 + b_cnt + b_grp);
-  cq.cap_groups = cap_g;
-  cq.cap_shifts = cap_s;
-  HIP_OR_FAIL(ctx, hipMemsetAsync(counters, 0, 32, s));
-  if (path == CA_PATH_FP32) {
-    FftPlan pl = plan_fft(maxN, Lmax, 4);
-    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
-    HIP_OR_FAIL(ctx, launch_pcm_fft32(cr, cm, io, nullptr, n, MODE_LOW, thr, BAND_FP32, ctx->tw32, pl.CH,
-                                      pl.LINES, Lmax, maxN, q, s));
-    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
-  } else {
-    if (!checked && (!crs->mixed_ok || !cms->mixed_ok))
-      return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
-    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
-    HIP_OR_FAIL(ctx, launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
-                                        nullptr, counters + 4, s));
-    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
-  }
+  const QueueMem qm = queue_carve((char*)sc, n);
+  unsigned long long* counters = qm.counters;
+  const int64_t cap_g = qm.cq.cap_groups;
+  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true));
   unsigned long long h[4] = {0, 0, 0, 0};
   HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, 32, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
@@ -559,17 +594,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
     ctx->stats.main_alg_bytes += path == CA_PATH_MIXED ? (double)n * (33280.0 + 2048.0) : io_bytes_fp32(maxN, n);
   }
   const int64_t n_groups = std::min<int64_t>((int64_t)h[2], cap_g);
-  if (n_groups > 0)
-    HIP_OR_FAIL(ctx, launch_rescore_candidates(cr, cm, io, thr, cq, n_groups, ctx->tw64, q.peak_err_bits,
-                                               q.r1_low, s));
-  if (h[0] > 0) {
-    FftPlan pl = plan_fft(maxN, Lmax, 8);
-    HIP_OR_FAIL(ctx, launch_pcm_fft64(cr, cm, io, q.list, (int64_t)h[0], MODE_RESCORE, thr, 0.0, ctx->tw64,
-                                      pl.CH, pl.LINES, Lmax, maxN, q, s));
-  }
   if (n_groups > 0 || h[0] > 0) {
-    HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, 16, hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
     double err;
     std::memcpy(&err, &h[1], 8);
     ctx->stats.max_surface_err = std::max(ctx->stats.max_surface_err, err);
@@ -621,6 +646,112 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
   }
   if (path == CA_PATH_AUTO) return capriv::align_auto(ctx, cs, s, Threshold{con->thr_num, con->thr_den}, io);
   return align_cosine(ctx, cs, cs, s, Threshold{con->thr_num, con->thr_den}, path, io);
+}
+
+// ---- captured alignment ------------------------------------------------------
+
+struct ca_graph {
+  ca_ctx* ctx = nullptr;
+  int64_t n = 0;
+  void* mem = nullptr;
+  size_t bytes = 0;
+  unsigned long long* n_bad = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" ca_status ca_graph_destroy(ca_graph* g) {
+  if (!g) return CA_EINVAL;
+  (void)hipSetDevice(g->ctx->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->mem) {
+    (void)hipFree(g->mem);
+    g->ctx->used -= g->bytes;
+  }
+  delete g;
+  return CA_OK;
+}
+
+extern "C" ca_status ca_graph_create(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                                     int64_t n_pairs, const int32_t* rep, const int32_t* mem, uint8_t* bits,
+                                     int16_t* shift, int32_t* count, double* score, uint32_t* flags,
+                                     ca_graph** out) {
+  if (!ctx) return CA_EINVAL;
+  if (!out || !cs || cs->ctx != ctx) return fail(ctx, CA_EINVAL, "bad arguments");
+  if (!valid_constraint(con) || con->kind != CA_COSINE) return fail(ctx, CA_EINVAL, "graphs capture the cosine track");
+  if (n_pairs <= 0 || n_pairs > (1ll << 31) - 1) return fail(ctx, CA_EINVAL, "bad pair count");
+  if (!rep || !mem || !bits || !shift || !count || !score || !flags)
+    return fail(ctx, CA_EINVAL, "null output or pair pointer");
+  if (!cs->mixed_ok)
+    return fail(ctx, CA_EUNSUPPORTED, "graphs capture CA_PATH_MIXED: 128 x 128 clips with half-windows <= 16");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = n_pairs;
+  ca_graph* g = new ca_graph();
+  g->ctx = ctx;
+  g->n = n;
+  const size_t b_q = queue_bytes(n), b_ids = align_up(4 * (size_t)n), b_bad = align_up(n);
+  g->bytes = b_q + 2 * b_ids + b_bad + 256;
+  ca_status st = dev_alloc(ctx, &g->mem, g->bytes, nullptr);
+  if (st) {
+    g->bytes = 0;
+    ca_graph_destroy(g);
+    return st;
+  }
+  char* p = (char*)g->mem;
+  const QueueMem qm = queue_carve(p, n);
+  int32_t* p_rep = (int32_t*)(p + b_q);
+  int32_t* p_mem = (int32_t*)(p + b_q + b_ids);
+  uint8_t* bad = (uint8_t*)(p + b_q + 2 * b_ids);
+  g->n_bad = (unsigned long long*)(p + b_q + 2 * b_ids + b_bad);
+  const PairIO io{n, p_rep, p_mem, bits, shift, count, score, flags};
+  const Threshold thr{con->thr_num, con->thr_den};
+  auto sequence = [&](hipStream_t q) -> hipError_t {
+    hipError_t e = launch_zero_u64(g->n_bad, 1, q);
+    if (e == hipSuccess) e = launch_sanitize_pairs(n, rep, mem, cs->n, cs->n, p_rep, p_mem, bad, g->n_bad, q);
+    if (e == hipSuccess) e = enqueue_cosine(ctx, cs->d, cs->d, cs->maxN, cs->Lmax, CA_PATH_MIXED, thr, io, qm, q, false);
+    if (e == hipSuccess) e = launch_reject_pairs(n, bad, io, q);
+    return e;
+  };
+  // one eager run first (function attributes, first-use set-up), then the
+  // capture on a private stream (the caller's may be the legacy null stream,
+  // which cannot be captured)
+  hipError_t e = sequence(s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipStream_t cap = nullptr;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t ec = sequence(cap);
+    const hipError_t ee = hipStreamEndCapture(cap, &g->graph);
+    e = ec != hipSuccess ? ec : ee;
+  }
+  if (cap) (void)hipStreamDestroy(cap);
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    ca_graph_destroy(g);
+    return fail(ctx, CA_EDEVICE, hipGetErrorString(e));
+  }
+  *out = g;
+  return CA_OK;
+}
+
+extern "C" ca_status ca_graph_launch(ca_graph* g, void* stream) {
+  if (!g) return CA_EINVAL;
+  HIP_OR_FAIL(g->ctx, hipSetDevice(g->ctx->device));
+  HIP_OR_FAIL(g->ctx, hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return CA_OK;
+}
+
+extern "C" ca_status ca_graph_invalid(ca_graph* g, void* stream, int64_t* n_invalid) {
+  if (!g || !n_invalid) return CA_EINVAL;
+  HIP_OR_FAIL(g->ctx, hipSetDevice(g->ctx->device));
+  unsigned long long h = 0;
+  HIP_OR_FAIL(g->ctx, hipMemcpyAsync(&h, g->n_bad, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_OR_FAIL(g->ctx, hipStreamSynchronize((hipStream_t)stream));
+  *n_invalid = (int64_t)h;
+  return CA_OK;
 }
 
 // Accessors used by api_cluster.hip.

@@ -15,16 +15,29 @@ constexpr int64_t LAUNCH_CHUNK = 1 << 22;
 hipError_t launch_pack(const int64_t* rect_ptr, const int32_t* rects, const ClipsDev& cs, int64_t n,
                        hipStream_t s);
 hipError_t launch_label(const ClipsDev& cs, int64_t n, hipStream_t s);
+// Zero n 64-bit words with a kernel (no memset node under graph capture).
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+// Range check of a pair list into a copy (out-of-range pairs become (0, 0)
+// and are marked), and the no-result outputs of the marked pairs.
+hipError_t launch_sanitize_pairs(int64_t n, const int32_t* rep, const int32_t* mem, int64_t n_r, int64_t n_m,
+                                 int32_t* rep_o, int32_t* mem_o, uint8_t* bad, unsigned long long* n_bad,
+                                 hipStream_t s);
+hipError_t launch_reject_pairs(int64_t n, const uint8_t* bad, const PairIO& io, hipStream_t s);
 hipError_t launch_spectrum(const ClipsDev& cs, const int64_t* ids, int64_t n_ids, int N,
                            double2* scratch, const double2* tw256, hipStream_t s);
 // Shared-memory bytes of the per-pair FFT kernel for (scalar size, N, CH, LINES, Lmax).
 size_t pcm_fft_smem(int scalar_bytes, int N, int CH, int LINES, int Lmax);
+// Per-pair FFT surface over n_blocks pairs (list[b] when list is given); with
+// n_dev the count is read on the device (at most n_blocks), so the launch
+// needs no host synchronisation.
 hipError_t launch_pcm_fft32(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list, int64_t n_blocks,
                             int mode, Threshold thr, double band, const float2* tw256, int CH,
-                            int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s);
+                            int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s,
+                            const unsigned long long* n_dev = nullptr);
 hipError_t launch_pcm_fft64(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list, int64_t n_blocks,
                             int mode, Threshold thr, double band, const double2* tw256, int CH,
-                            int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s);
+                            int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s,
+                            const unsigned long long* n_dev = nullptr);
 hipError_t launch_edge(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
 hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, int maxN, hipStream_t s);
 // Edge bounds pass: 64-bit chunk words of the survivor mask (ranges start on
@@ -40,9 +53,10 @@ void build_mfma128_tables(_Float16* b1, _Float16* a2);
 hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr, float band,
                               const RescoreQueue& q, const CandQueue& cq, const void* b1frag,
                               const void* a2frag, float* surf_out, unsigned long long* tiles, hipStream_t s);
-// FP64 re-decision of queued directions at their candidate shifts.
+// FP64 re-decision of queued directions at their candidate shifts: the group
+// count is read on the device (*cq.n_groups, at most cq.cap_groups).
 hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
-                                     const CandQueue& cq, int64_t n_groups, const double2* tw256,
+                                     const CandQueue& cq, const double2* tw256,
                                      unsigned long long* peak_err_bits, const float* r1_low, hipStream_t s);
 // Cosine candidate generation for 128 x 128 clips with half-windows <= 16:
 // write = false runs the bounds pass (bitmask + counts), write = true the

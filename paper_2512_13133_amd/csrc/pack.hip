@@ -279,6 +279,63 @@ hipError_t launch_label(const ClipsDev& cs, int64_t n, hipStream_t s) {
   return hipSuccess;
 }
 
+// Clears device counters with a kernel (usable under graph capture, where
+// memset nodes are avoided).
+__global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = 0ull;
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// Copy of a pair list with every pair whose ids fall outside [0, n_r) x
+// [0, n_m) replaced by (0, 0) and marked (bad[k] = 1; *n_bad counts them).
+__global__ void sanitize_pairs_kernel(int64_t n, const int32_t* __restrict__ rep, const int32_t* __restrict__ mem,
+                                      int64_t n_r, int64_t n_m, int32_t* __restrict__ rep_o,
+                                      int32_t* __restrict__ mem_o, uint8_t* __restrict__ bad,
+                                      unsigned long long* n_bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int a = rep[k], b = mem[k];
+  const bool ok = a >= 0 && b >= 0 && a < n_r && b < n_m;
+  rep_o[k] = ok ? a : 0;
+  mem_o[k] = ok ? b : 0;
+  bad[k] = ok ? 0 : 1;
+  if (!ok) atomicAdd(n_bad, 1ull);
+}
+
+// Results of the marked pairs: no result (bits 0, shifts 0, counts -1, scores 0, CA_FLAG_INVALID).
+__global__ void reject_pairs_kernel(int64_t n, const uint8_t* __restrict__ bad, PairIO io) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n || !bad[k]) return;
+  io.bits[k] = 0;
+  io.flags[k] = CA_FLAG_INVALID;
+  for (int e = 0; e < 4; ++e) io.shift[4 * k + e] = 0;
+  for (int e = 0; e < 2; ++e) {
+    io.count[2 * k + e] = -1;
+    io.score[2 * k + e] = 0.0;
+  }
+}
+
+hipError_t launch_sanitize_pairs(int64_t n, const int32_t* rep, const int32_t* mem, int64_t n_r, int64_t n_m,
+                                 int32_t* rep_o, int32_t* mem_o, uint8_t* bad, unsigned long long* n_bad,
+                                 hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(sanitize_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, rep, mem, n_r, n_m,
+                     rep_o, mem_o, bad, n_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_reject_pairs(int64_t n, const uint8_t* bad, const PairIO& io, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(reject_pairs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, bad, io);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const ClipsDev& cr, const ClipsDev& cm, int64_t n_pairs, const int32_t* rep,
                            const int32_t* mem, int need_poly, int* bad, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;

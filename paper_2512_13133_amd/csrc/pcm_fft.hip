@@ -26,7 +26,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ list, int mode, Threshold thr,
                double band, const typename cplx<T>::type* __restrict__ tw256, int CH, int LINES,
-               int Lmax, RescoreQueue q, int64_t block0) {
+               int Lmax, RescoreQueue q, int64_t n_blocks, const unsigned long long* __restrict__ n_dev) {
   using C = typename cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int ired[256];
@@ -35,7 +35,10 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
   __shared__ int idxred[256];
   __shared__ int candf[256];
 
-  const int64_t b = block0 + (int64_t)blockIdx.x;
+  // grid-stride over the pairs (or listed pairs); the count comes from the
+  // host, or from device memory (capped by n_blocks) when n_dev is given
+  const int64_t nb_eff = n_dev ? min((int64_t)*n_dev, n_blocks) : n_blocks;
+  for (int64_t b = blockIdx.x; b < nb_eff; b += gridDim.x) {
   const int64_t k = list ? list[b] : b;
   const int tid = threadIdx.x;
   const int j = io.rep[k], i = io.mem[k];
@@ -57,7 +60,7 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
       write_direction(io, k, 1, 0, 0, 0, 0.0, false);
       io.flags[k] |= CA_FLAG_EMPTY;
     }
-    return;
+    continue;
   }
 
   C* Tbuf = reinterpret_cast<C*>(smem);
@@ -284,6 +287,7 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
     }
     __syncthreads();
   }
+  }
 }
 
 size_t pcm_fft_smem(int scalar_bytes, int N, int CH, int LINES, int Lmax) {
@@ -295,32 +299,38 @@ template <typename T>
 static hipError_t launch_pcm_fft_t(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list,
                                    int64_t n_blocks, int mode, Threshold thr, double band,
                                    const typename cplx<T>::type* tw256, int CH, int LINES, int Lmax,
-                                   int maxN, const RescoreQueue& q, hipStream_t s) {
+                                   int maxN, const RescoreQueue& q, const unsigned long long* n_dev,
+                                   hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
   const size_t smem = pcm_fft_smem((int)sizeof(T), maxN, CH, LINES, Lmax);
-  hipError_t e = hipFuncSetAttribute((const void*)pcm_fft_kernel<T>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  for (int64_t b0 = 0; b0 < n_blocks; b0 += LAUNCH_CHUNK) {
-    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, n_blocks - b0);
-    hipLaunchKernelGGL(pcm_fft_kernel<T>, dim3(nb), dim3(256), smem, s, cr, cm, io, list, mode, thr, band, tw256,
-                       CH, LINES, Lmax, q, b0);
-    e = hipGetLastError();
+  // the dynamic LDS limit is raised once to the largest size seen (not a
+  // stream operation, so it stays out of captured sequences once set)
+  static size_t smem_set = 0;
+  if (smem > smem_set) {
+    const hipError_t e = hipFuncSetAttribute((const void*)pcm_fft_kernel<T>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
+    smem_set = smem;
   }
-  return hipSuccess;
+  // a device-side count is a rare queue: a small grid strides over it
+  const unsigned grid = (unsigned)std::min<int64_t>(n_blocks, n_dev ? 2048 : LAUNCH_CHUNK);
+  hipLaunchKernelGGL(pcm_fft_kernel<T>, dim3(grid), dim3(256), smem, s, cr, cm, io, list, mode, thr, band, tw256,
+                     CH, LINES, Lmax, q, n_blocks, n_dev);
+  return hipGetLastError();
 }
 
 hipError_t launch_pcm_fft32(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list, int64_t n_blocks,
                             int mode, Threshold thr, double band, const float2* tw256, int CH,
-                            int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s) {
-  return launch_pcm_fft_t<float>(cr, cm, io, list, n_blocks, mode, thr, band, tw256, CH, LINES, Lmax, maxN, q, s);
+                            int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s,
+                            const unsigned long long* n_dev) {
+  return launch_pcm_fft_t<float>(cr, cm, io, list, n_blocks, mode, thr, band, tw256, CH, LINES, Lmax, maxN, q, n_dev, s);
 }
 
 hipError_t launch_pcm_fft64(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, const int64_t* list, int64_t n_blocks,
                             int mode, Threshold thr, double band, const double2* tw256, int CH,
-                            int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s) {
-  return launch_pcm_fft_t<double>(cr, cm, io, list, n_blocks, mode, thr, band, tw256, CH, LINES, Lmax, maxN, q, s);
+                            int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s,
+                            const unsigned long long* n_dev) {
+  return launch_pcm_fft_t<double>(cr, cm, io, list, n_blocks, mode, thr, band, tw256, CH, LINES, Lmax, maxN, q, n_dev, s);
 }
 
 }  // namespace ca

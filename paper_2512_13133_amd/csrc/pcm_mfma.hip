@@ -642,7 +642,7 @@ hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const Pair
       cus = 256;
   }
   const unsigned grid = (unsigned)std::min<int64_t>(n_tiles, 2 * (int64_t)cus);
-  hipError_t e = hipMemsetAsync(tiles, 0, sizeof(unsigned long long), s);
+  hipError_t e = launch_zero_u64(tiles, 1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(pcm_mfma128_kernel, dim3(grid), dim3(256), 0, s, mf_view(cr), mf_view(cm), io, thr, band, q, cq,
                      (const h8_t*)b1frag, (const h8_t*)a2frag, surf_out, tiles, n_tiles);

@@ -32,7 +32,10 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
   __shared__ int ired[RS_THREADS];
   __shared__ double2 tw[256];
   const int tid = threadIdx.x;
-  const CandGroup gr = cq.groups[blockIdx.x];
+  // grid-stride over the queued groups (count read on the device)
+  const int64_t n_groups = min((int64_t)*cq.n_groups, cq.cap_groups);
+  for (int64_t gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
+  const CandGroup gr = cq.groups[gi];
   const int64_t k = gr.pair;
   const int d = gr.dir;
   const int m = gr.count;
@@ -40,7 +43,8 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
   const int N = cm.N[i];
   const int H = N / 2;
   const int tws = 256 / N;
-  if (m == 0) return;
+  if (m == 0) continue;
+  __syncthreads();  // the previous group's last reads of tw / ired are done
   // tw[t] = exp(-2 pi i t / N) from the half-circle table exp(-2 pi i m / 256), m < 128
   for (int t = tid; t < N; t += RS_THREADS) {
     const double2 base = tw256[((t * tws) & 127)];
@@ -143,21 +147,17 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
       }
     }
   }
+  }
 }
 
 hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
-                                     const CandQueue& cq, int64_t n_groups, const double2* tw256,
+                                     const CandQueue& cq, const double2* tw256,
                                      unsigned long long* peak_err_bits, const float* r1_low, hipStream_t s) {
-  for (int64_t b0 = 0; b0 < n_groups; b0 += LAUNCH_CHUNK) {
-    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, n_groups - b0);
-    CandQueue q2 = cq;
-    q2.groups = cq.groups + b0;
-    hipLaunchKernelGGL(rescore_candidates_kernel, dim3(nb), dim3(RS_THREADS), 0, s, cr, cm, io, thr, q2, tw256,
-                       peak_err_bits, r1_low);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  if (cq.cap_groups <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(cq.cap_groups, 8192);
+  hipLaunchKernelGGL(rescore_candidates_kernel, dim3(grid), dim3(RS_THREADS), 0, s, cr, cm, io, thr, cq, tw256,
+                     peak_err_bits, r1_low);
+  return hipGetLastError();
 }
 
 }  // namespace ca

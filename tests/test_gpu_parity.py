@@ -393,6 +393,45 @@ def test_cosine_c128_mixed_small_windows(ctx):
     h.close()
 
 
+def test_graph_replays_match_eager(ctx):
+    """The captured mixed alignment, replayed with new pair ids each time (one
+    list with out-of-range ids) and eager work between replays: every replay
+    equals the eager call on the same pairs; rejected pairs carry the invalid
+    flag and no result."""
+    import paper_2512_13133_amd as ca
+    cs = c128_subset(200, seed=12)
+    h = ctx.clips(cs)
+    n = 3000
+    g = ctx.graph(h, n, (19, 20))
+    rng = np.random.default_rng(12)
+    for it in range(3):
+        rep = rng.integers(0, cs.n, n).astype(np.int32)
+        mem = rng.integers(0, cs.n, n).astype(np.int32)
+        o = np.lexsort((mem, rep))
+        rep, mem = rep[o], mem[o]
+        bad = np.zeros(n, bool)
+        if it == 1:
+            pos = rng.choice(n, 7, replace=False)
+            rep[pos[:3]] = -1
+            mem[pos[3:]] = cs.n + 5
+            bad[pos] = True
+        g.set_pairs(rep, mem)
+        g.launch()
+        assert g.invalid() == int(bad.sum())
+        got = to_np(g.out)
+        good = ~bad
+        want = to_np(ctx.align_pairs(h, rep[good], mem[good], "cosine", (19, 20), "mixed"))
+        for key in ("bits", "shift", "count", "score"):
+            assert np.array_equal(got[key][good], want[key]), (it, key)
+        mask = ca.FLAG_INVALID
+        assert np.array_equal((got["flags"][good] & ~mask), want["flags"] & ~mask)
+        assert ((got["flags"][bad] & mask) != 0).all()
+        assert (got["bits"][bad] == 0).all() and (got["count"][bad] == -1).all()
+        say(f"[graph] replay {it}: {good.sum()} pairs equal to eager, {bad.sum()} rejected")
+    g.close()
+    h.close()
+
+
 def test_mixed_rejects_other_shapes(ctx):
     import paper_2512_13133_amd as ca
     h = ctx.clips(small_set(8))
