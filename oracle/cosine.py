@@ -102,6 +102,30 @@ def surface_at(W_mem, W_rep, shifts):
     return np.array(out)
 
 
+def whitened_image(W: np.ndarray) -> np.ndarray:
+    """img = N * w with w the inverse DFT of the whitened spectrum (Eq. 4).
+
+    W is Hermitian (the raster is real and the whitening keeps |F| symmetric),
+    so w is real; ifft2 includes 1/N^2.  sum img^2 = number of non-zero bins
+    (Parseval), so the values are of order one.
+    """
+    N = W.shape[0]
+    return np.fft.ifft2(W).real * N
+
+
+def correlate_images(img_mem: np.ndarray, img_rep: np.ndarray, shifts) -> np.ndarray:
+    """sum_x img_rep(x) img_mem((x + s) mod N) at each shift s = (dy, dx).
+
+    By Parseval this equals K r(s) of Eq. 5 (the surface before division by
+    K): the spatial form of the same correlation.
+    """
+    out = []
+    for dy, dx in np.asarray(shifts).reshape(-1, 2):
+        moved = np.roll(img_mem, (-int(dy), -int(dx)), axis=(0, 1))  # moved[x] = img_mem[x + s]
+        out.append(float((img_rep * moved).sum()))
+    return np.array(out)
+
+
 def overlap(a_rep: np.ndarray, a_mem: np.ndarray, dy: int, dx: int) -> int:
     """c(s) = sum_x a_rep(x) a_mem((x + s) mod N), an integer."""
     shifted = np.roll(a_mem, shift=(-int(dy), -int(dx)), axis=(0, 1))

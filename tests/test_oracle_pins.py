@@ -148,6 +148,57 @@ def test_surface_equals_spatial_correlation_of_whitened_images(N):
         assert np.allclose(cosine.surface_at(Wa, Wb, sh), [r[dy % N, dx % N] for dy, dx in sh], atol=1e-12)
 
 
+def test_whitened_image_closed_forms():
+    """A single set pixel has |F| = 1 at every bin, so W = F and the image is
+    N at that pixel and 0 elsewhere; energy equals the non-zero bin count
+    (Parseval); and the image equals the explicit inverse DFT sum."""
+    for N in (8, 16, 64):
+        a = np.zeros((N, N))
+        a[3, N - 2] = 1
+        img = cosine.whitened_image(cosine.whiten(cosine.spectrum(a)))
+        ref = np.zeros((N, N))
+        ref[3, N - 2] = N
+        assert np.abs(img - ref).max() < 1e-12
+    rng = np.random.default_rng(5)
+    N = 8
+    for _ in range(4):
+        a = rand_clip(rng, N)
+        W = cosine.whiten(cosine.spectrum(a))
+        img = cosine.whitened_image(W)
+        assert abs((img ** 2).sum() - np.count_nonzero(W)) < 1e-9
+        for y, x in [(0, 0), (2, 5), (7, 1)]:
+            acc = 0j
+            for u in range(N):
+                for v in range(N):
+                    acc += W[u, v] * complex(math.cos(2 * math.pi * (u * y + v * x) / N),
+                                             math.sin(2 * math.pi * (u * y + v * x) / N))
+            assert abs(acc.imag) < 1e-9
+            assert abs(acc.real / N - img[y, x]) < 1e-12
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_image_correlation_is_the_surface(N):
+    """sum_x img_rep(x) img_mem(x + s) = K r(s) at every shift, against an
+    explicit quadruple loop (no array rolls)."""
+    rng = np.random.default_rng(17 + N)
+    for _ in range(3):
+        a, b = rand_clip(rng, N), rand_clip(rng, N)
+        if a.sum() == 0 or b.sum() == 0:
+            continue
+        Wa, Wb = (cosine.whiten(cosine.spectrum(x)) for x in (a, b))
+        r, K = cosine.surface(Wa, Wb)  # member a, rep b
+        ia, ib = cosine.whitened_image(Wa), cosine.whitened_image(Wb)
+        shifts = [(dy, dx) for dy in range(-3, 4) for dx in range(-3, 4)]
+        got = cosine.correlate_images(ia, ib, shifts)
+        for (dy, dx), g in zip(shifts, got):
+            acc = 0.0
+            for y in range(N):
+                for x in range(N):
+                    acc += ib[y, x] * ia[(y + dy) % N, (x + dx) % N]
+            assert abs(g - acc) < 1e-9
+            assert abs(g / K - r[dy % N, dx % N]) < 1e-12
+
+
 def test_surface_reverse_is_mirror():
     rng = np.random.default_rng(11)
     N = 32
