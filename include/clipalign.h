@@ -82,9 +82,16 @@ typedef struct {
  *     workgroup per pair, inverse transform by FFT on the vector ALUs; near
  *     ties re-decided in FP64.  All raster sizes and windows.
  *   CA_PATH_FP64: the FP64 surface and exact tie rule for every pair.
+ *   CA_PATH_DIRECT: the window surface as a direct circular cross-correlation
+ *     of the clips' FP16 whitened images (Parseval form of Eq. 5), batched
+ *     16 members per representative on MFMA with FP32 accumulation; near ties
+ *     re-decided in FP64.  Clip sets made with CA_CLIPS_IMAGE, one raster size
+ *     (64, 128 or 256), half-windows <= 7 (CA_EUNSUPPORTED otherwise).
+ *     Not enabled in this version of the library: every call with it returns
+ *     CA_EUNSUPPORTED, and CA_PATH_AUTO never selects it.
  *   CA_PATH_AUTO: pairs of any raster size and window in one call.  The pairs
  *     are partitioned (stably) into buckets by raster size and window class
- *     (the larger half-window: <= 4, <= 8, <= 15, 16, <= 23, <= 31, more);
+ *     (the larger half-window: <= 4, <= 7, <= 15, 16, <= 23, <= 31, more);
  *     each bucket runs the path the context's tuning table names for it.  A
  *     bucket met for the first time is tuned on up to 4,096 of its pairs
  *     (repeated to at least 1,024 when the bucket is smaller):
@@ -92,7 +99,7 @@ typedef struct {
  *     equal CA_PATH_FP64's bit for bit, and the fastest admitted one is kept
  *     (see ca_autotune_*).  Results return in the caller's order.
  * All of them return identical shifts, counts, scores and bits. */
-enum { CA_PATH_MIXED = 0, CA_PATH_FP32 = 1, CA_PATH_FP64 = 2, CA_PATH_AUTO = 3 };
+enum { CA_PATH_MIXED = 0, CA_PATH_FP32 = 1, CA_PATH_FP64 = 2, CA_PATH_AUTO = 3, CA_PATH_DIRECT = 4 };
 
 /* Per-pair flag bits written by the alignment calls. */
 enum {
@@ -120,6 +127,7 @@ typedef struct {
                                  re-decided pairs (normalised surface units) */
   double tie_band_mixed;      /* band under which CA_PATH_MIXED re-decides a peak */
   double tie_band_fp32;       /* band under which CA_PATH_FP32 re-decides a peak */
+  double tie_band_direct;     /* band under which CA_PATH_DIRECT re-decides a peak */
 } ca_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -149,12 +157,15 @@ ca_status ca_reset_stats(ca_ctx* ctx);
  *   flags: CA_CLIPS_DEVICE_PTRS if the four arrays are device pointers (else
  *     host pointers; the library copies them either way).
  *     CA_CLIPS_FP32 keeps FP32 spectra for CA_PATH_FP32 (doubles the spectra).
+ *     CA_CLIPS_IMAGE keeps each clip's whitened image w_i = IDFT2(W_i) (the
+ *     spatial form of the whitened spectrum), scaled by N and stored as FP16
+ *     (2 N^2 bytes a clip), for CA_PATH_DIRECT.
  * The library rasterises, counts pixels, row/column sums, 4-connected polygons
  * (at most 64 per clip; larger counts mark the clip and make the edge track
  * fail with CA_EUNSUPPORTED on it), and computes FP64 spectra, whitened with
  * |F| > 1e-2 kept, stored as FP16 (and FP32 / FP64 as requested).
  * Returns CA_EINVAL on a bad size or N, CA_ENOMEM if it does not fit. */
-enum { CA_CLIPS_DEVICE_PTRS = 1, CA_CLIPS_FP32 = 2, CA_CLIPS_FP64 = 4 };
+enum { CA_CLIPS_DEVICE_PTRS = 1, CA_CLIPS_FP32 = 2, CA_CLIPS_FP64 = 4, CA_CLIPS_IMAGE = 8 };
 ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr,
                           const int32_t* rects, const int16_t* raster_n,
                           const int16_t* marker_w, int32_t flags, ca_clipset** out);
@@ -172,6 +183,16 @@ ca_status ca_clips_count(const ca_clipset* cs, int64_t* n);
 ca_status ca_clips_inspect(const ca_clipset* cs, int64_t i, uint64_t* bits, int32_t* n_pix,
                            uint16_t* rowsum, uint16_t* colsum, int32_t* n_poly,
                            int16_t* boxes, int32_t* zero_bins, float* spec16);
+
+/* Copy clip i's whitened image to a host buffer img [N*N] float, row-major:
+ * img(y, x) = N * w_i(y, x), w_i = (1/N^2) sum_{u,v} W_i(u, v) e^{+2 pi i (u y + v x)/N}
+ * (the inverse DFT of the whitened spectrum of Eq. 4, real since W_i is
+ * Hermitian), as stored in FP16.  Its energy sum_x img^2 equals the number of
+ * non-zero bins, so the values are of order one.  The phase-correlation
+ * surface of Eq. 5 is the circular cross-correlation of two such images:
+ *   K r(s) = sum_x img_rep(x) img_mem(x + s).
+ * CA_ESTATE if the set was created without CA_CLIPS_IMAGE. */
+ca_status ca_clips_image(const ca_clipset* cs, int64_t i, float* img);
 
 /* ---- alignment on an explicit pair list (paper Sec. 3.2) ----------------- */
 
@@ -203,12 +224,14 @@ ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
                          int16_t* shift, int32_t* count, double* score, uint32_t* flags);
 
 /* Test and calibration access: the low-precision window surface of direction
- * 0 (member mem[k] against representative rep[k]) exactly as CA_PATH_MIXED
- * computes it before any FP64 re-decision, for dy, dx in [-16, 16]:
+ * 0 (member mem[k] against representative rep[k]) exactly as CA_PATH_MIXED or
+ * CA_PATH_DIRECT computes it before any FP64 re-decision, for dy, dx in
+ * [-16, 16] (CA_PATH_DIRECT writes only the entries with |dy|, |dx| <= 7):
  * surf[k][dy + 16][dx + 16] = K r(dy, dx) / K_hi with K_hi = N^2 minus the
  * larger zero-bin count of the two clips (paper Eq. 5 up to that positive
  * factor).  rep, mem, surf are device pointers; surf has n_pairs*33*33 floats.
- * CA_EUNSUPPORTED unless path == CA_PATH_MIXED on a set that path accepts.
+ * CA_EUNSUPPORTED unless path is CA_PATH_MIXED or CA_PATH_DIRECT on a set that
+ * path accepts.
  * Synchronises. */
 ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs, int32_t path, int64_t n_pairs,
                      const int32_t* rep, const int32_t* mem, float* surf);

@@ -22,15 +22,15 @@ LIB_PATH = os.path.join(HERE, "libclipalign.so")
 
 CA_OK, CA_EINVAL, CA_ENOMEM, CA_EDEVICE, CA_EBUSY, CA_ETRUNC, CA_ESTATE, CA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 CA_COSINE, CA_EDGE = 1, 2
-PATHS = {"mixed": 0, "fp32": 1, "fp64": 2, "auto": 3}
-CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64 = 1, 2, 4
+PATHS = {"mixed": 0, "fp32": 1, "fp64": 2, "auto": 3, "direct": 4}
+CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64, CA_CLIPS_IMAGE = 1, 2, 4, 8
 FLAG_RESCORED_FWD, FLAG_RESCORED_REV, FLAG_EMPTY = 1, 2, 4
 FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16, 32, 64
 FLAG_INVALID = 128
 
 SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
-    "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect",
+    "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect", "ca_clips_image",
     "ca_align_pairs", "ca_surface", "ca_prune", "ca_cluster",
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
     "ca_server_stats", "ca_server_last_error",
@@ -58,7 +58,7 @@ class _Stats(C.Structure):
                 ("pairs_screened", C.c_int64), ("pairs_survived", C.c_int64),
                 ("n_main_launch", C.c_int64), ("t_main_ms", C.c_double), ("main_alg_bytes", C.c_double),
                 ("max_surface_err", C.c_double), ("tie_band_mixed", C.c_double),
-                ("tie_band_fp32", C.c_double)]
+                ("tie_band_fp32", C.c_double), ("tie_band_direct", C.c_double)]
 
 
 _LIB = None
@@ -83,6 +83,7 @@ def load():
     lib.ca_clips_destroy.argtypes = [P]
     lib.ca_clips_count.argtypes = [P, C.POINTER(C.c_int64)]
     lib.ca_clips_inspect.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P]
+    lib.ca_clips_image.argtypes = [P, C.c_int64, P]
     lib.ca_align_pairs.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64,
                                    P, P, P, P, P, P, P]
     lib.ca_surface.argtypes = [P, P, P, C.c_int32, C.c_int64, P, P, P]
@@ -176,13 +177,16 @@ class Context:
             self.h = None
 
     # -------------------------------------------------------------- clips
-    def clips(self, cs, fp32=False):
-        """Build a device clip set from a ``clipgen.ClipSet`` (host arrays)."""
+    def clips(self, cs, fp32=False, image=False):
+        """Build a device clip set from a ``clipgen.ClipSet`` (host arrays).
+
+        fp32: keep FP32 spectra (the "fp32" path); image: keep the FP16 whitened
+        images (the "direct" path)."""
         ptr = np.ascontiguousarray(cs.rect_ptr, dtype=np.int64)
         rects = np.ascontiguousarray(cs.rects, dtype=np.int32).reshape(-1, 4)
         rn = np.ascontiguousarray(cs.raster_n, dtype=np.int16)
         mw = np.ascontiguousarray(cs.marker_w, dtype=np.int16)
-        flags = CA_CLIPS_FP32 if fp32 else 0
+        flags = (CA_CLIPS_FP32 if fp32 else 0) | (CA_CLIPS_IMAGE if image else 0)
         h = P()
         self._check(self.lib.ca_clips_create(self.h, self._stream(), rn.size, _ptr(ptr),
                                              _ptr(rects) if rects.size else None, _ptr(rn), _ptr(mw),
@@ -196,6 +200,12 @@ class Context:
                    zero_bins=np.zeros(1, np.int32), spec16=np.zeros((N, N // 2 + 1, 2), np.float32))
         self._check(self.lib.ca_clips_inspect(clips.handle, int(i), *[_ptr(out[k]) for k in (
             "bits", "n_pix", "rowsum", "colsum", "n_poly", "boxes", "zero_bins", "spec16")]))
+        return out
+
+    def image(self, clips, i, N):
+        """Whitened image N * IDFT2(W) of clip i as stored (FP16 widened), [N, N]."""
+        out = np.zeros((N, N), np.float32)
+        self._check(self.lib.ca_clips_image(clips.handle, int(i), _ptr(out)))
         return out
 
     # -------------------------------------------------------------- pairs

@@ -20,6 +20,11 @@ using namespace ca;
 // plus the tie tolerance.
 static constexpr double BAND_FP32 = 1e-5;
 static constexpr double BAND_MIXED = 1e-4;
+static constexpr double BAND_DIRECT = 1e-4;
+// The direct-correlation kernel is built but not launched: its first GPU run
+// ended in a memory-aperture fault whose cause is not yet identified, so the
+// path reports CA_EUNSUPPORTED until it is.
+static constexpr bool DIRECT_ENABLED = false;
 
 struct ca_ctx {
   int device = 0;
@@ -52,8 +57,9 @@ struct ca_clipset {
   capriv::DevArena* arena = nullptr;             // region the set was carved from (not owned)
   std::vector<int16_t> hN, hw;
   std::vector<int32_t> hnpix, hnpoly;
-  int maxN = 0, Lmax = 0;
+  int maxN = 0, minN = 1 << 30, Lmax = 0;
   bool mixed_ok = false;  // every clip is 128 x 128 with half-window <= 16
+  bool direct_ok = false; // whitened images kept, rasters <= 256, half-windows <= 7
   uint64_t gen = 0;       // unique per clip set within its context
 };
 
@@ -157,6 +163,7 @@ ca_status ca_create(const ca_config* cfg, ca_ctx** out) {
   ctx->budget = cfg->hbm_budget_bytes;
   ctx->stats.tie_band_mixed = BAND_MIXED;
   ctx->stats.tie_band_fp32 = BAND_FP32;
+  ctx->stats.tie_band_direct = BAND_DIRECT;
   std::vector<float2> t32(128);
   std::vector<double2> t64(128);
   for (int m = 0; m < 128; ++m) {
@@ -227,6 +234,7 @@ ca_status ca_reset_stats(ca_ctx* ctx) {
   ctx->stats = ca_run_stats{};
   ctx->stats.tie_band_mixed = BAND_MIXED;
   ctx->stats.tie_band_fp32 = BAND_FP32;
+  ctx->stats.tie_band_direct = BAND_DIRECT;
   return CA_OK;
 }
 
@@ -294,20 +302,26 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
     ca_clips_destroy(cs);
     return st;
   };
-  std::vector<int64_t> bits_off(n), sig_off(n), rowptr_off(n), spec_off(n);
-  int64_t nb = 0, ns = 0, nr = 0, nsp = 0;
+  std::vector<int64_t> bits_off(n), sig_off(n), rowptr_off(n), spec_off(n), img_off(n);
+  int64_t nb = 0, ns = 0, nr = 0, nsp = 0, nimg = 0;
   for (int64_t i = 0; i < n; ++i) {
     const int N = hN[i];
     bits_off[i] = nb; nb += (int64_t)N * N / 64;
     sig_off[i] = ns; ns += N;
     rowptr_off[i] = nr; nr += N + 1;
     spec_off[i] = nsp; nsp += (int64_t)N * (N / 2 + 1);
+    img_off[i] = nimg; nimg += (int64_t)N * N;
     cs->maxN = std::max(cs->maxN, N);
+    cs->minN = std::min(cs->minN, N);
     cs->Lmax = std::max(cs->Lmax, axis_len(hw[i], N));
   }
   cs->mixed_ok = true;
   for (int64_t i = 0; i < n; ++i)
     if (hN[i] != 128 || hw[i] > 16) cs->mixed_ok = false;
+  const bool image = (flags & CA_CLIPS_IMAGE) != 0;
+  cs->direct_ok = image;
+  for (int64_t i = 0; i < n; ++i)
+    if (hw[i] > 7) cs->direct_ok = false;
   void* p;
   ca_status st;
 #define ALLOC(field, type, count)                                              \
@@ -343,6 +357,13 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
   ALLOC(spec16, __half2, nsp);
   if (flags & CA_CLIPS_FP32) ALLOC(spec32, float2, nsp);
   ALLOC(spec64, double2, nsp);
+  if (image) {
+    int64_t* dio;
+    st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); dio = (int64_t*)p;
+    cs->d.img_off = dio;
+    ALLOC(img16, __half, nimg);
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(dio, img_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+  }
   HIP_OR_FAIL(ctx, hipMemcpyAsync(dN, hN.data(), sizeof(int16_t) * n, hipMemcpyHostToDevice, s));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(dw, hw.data(), sizeof(int16_t) * n, hipMemcpyHostToDevice, s));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(dbo, bits_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
@@ -393,6 +414,7 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
       const int64_t nb2 = std::min<int64_t>(batch, (int64_t)ids.size() - b0);
       HIP_OR_FAIL(ctx, hipMemcpyAsync(dids, ids.data() + b0, sizeof(int64_t) * nb2, hipMemcpyHostToDevice, s));
       HIP_OR_FAIL(ctx, launch_spectrum(cs->d, dids, nb2, N, sbuf, ctx->tw64, s));
+      if (image) HIP_OR_FAIL(ctx, launch_image(cs->d, dids, nb2, N, sbuf, ctx->tw64, s));
       HIP_OR_FAIL(ctx, hipStreamSynchronize(s));  // scratch reuse
     }
   }
@@ -442,6 +464,21 @@ ca_status ca_clips_inspect(const ca_clipset* cs, int64_t i, uint64_t* bits, int3
         spec16[((size_t)u * (H + 1) + v) * 2 + 1] = __half2float(__high2half(x));
       }
   }
+  return CA_OK;
+}
+
+ca_status ca_clips_image(const ca_clipset* cs, int64_t i, float* img) {
+  if (!cs || !img) return CA_EINVAL;
+  ca_ctx* ctx = cs->ctx;
+  if (i < 0 || i >= cs->n) return fail(ctx, CA_EINVAL, "clip id out of range");
+  if (!cs->d.img16) return fail(ctx, CA_ESTATE, "clip set created without CA_CLIPS_IMAGE");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  const int N = cs->hN[i];
+  int64_t off = 0;
+  HIP_OR_FAIL(ctx, hipMemcpy(&off, cs->d.img_off + i, 8, hipMemcpyDeviceToHost));
+  std::vector<__half> h((size_t)N * N);
+  HIP_OR_FAIL(ctx, hipMemcpy(h.data(), cs->d.img16 + off, sizeof(__half) * h.size(), hipMemcpyDeviceToHost));
+  for (size_t t = 0; t < h.size(); ++t) img[t] = __half2float(h[t]);
   return CA_OK;
 }
 
@@ -531,7 +568,8 @@ static QueueMem queue_carve(char* base, int64_t n) {
 // context's events when `events`), then the FP64 re-decision sized on the
 // device.  No host synchronisation, so it can be captured in a graph.
 static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev& cm, int maxN, int Lmax, int path,
-                                 Threshold thr, const PairIO& io, const QueueMem& m, hipStream_t s, bool events) {
+                                 Threshold thr, const PairIO& io, const QueueMem& m, hipStream_t s, bool events,
+                                 int direct_n = 0) {
   const int64_t n = io.n_pairs;
   hipError_t e = launch_zero_u64(m.counters, 32, s);
   if (e != hipSuccess) return e;
@@ -540,6 +578,8 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
     FftPlan pl = plan_fft(maxN, Lmax, 4);
     e = launch_pcm_fft32(cr, cm, io, nullptr, n, MODE_LOW, thr, BAND_FP32, ctx->tw32, pl.CH, pl.LINES, Lmax, maxN,
                          m.q, s);
+  } else if (path == CA_PATH_DIRECT) {
+    e = launch_pcm_direct(cr, cm, io, direct_n, thr, (float)BAND_DIRECT, m.q, m.cq, nullptr, m.counters + 4, s);
   } else {
     e = launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, m.q, m.cq, ctx->mf_b1, ctx->mf_a2, nullptr,
                            m.counters + 4, s);
@@ -557,9 +597,10 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
 
 // Cosine alignment of a device pair list with the chosen path (no validation).
 // `checked`: the caller guarantees that every pair suits the path (the
-// autotuner's buckets), so the set-wide shape test of CA_PATH_MIXED is skipped.
+// autotuner's buckets), so the set-wide shape tests of CA_PATH_MIXED and
+// CA_PATH_DIRECT are skipped; `direct_n` then names the bucket's raster size.
 static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                              Threshold thr, int path, const PairIO& io, bool checked = false) {
+                              Threshold thr, int path, const PairIO& io, bool checked = false, int direct_n = 0) {
   const int maxN = std::max(crs->maxN, cms->maxN), Lmax = std::max(crs->Lmax, cms->Lmax);
   const ClipsDev& cr = crs->d;
   const ClipsDev& cm = cms->d;
@@ -576,13 +617,24 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
     return fail(ctx, CA_ESTATE, "CA_PATH_FP32 needs a clip set created with CA_CLIPS_FP32");
   if (path == CA_PATH_MIXED && !checked && (!crs->mixed_ok || !cms->mixed_ok))
     return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
+  if (path == CA_PATH_DIRECT) {
+    if (!DIRECT_ENABLED) return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_DIRECT is disabled in this build");
+    if (!cr.img16 || !cm.img16) return fail(ctx, CA_ESTATE, "CA_PATH_DIRECT needs clip sets made with CA_CLIPS_IMAGE");
+    if (!checked) {
+      if (!crs->direct_ok || !cms->direct_ok || crs->minN != maxN || cms->minN != maxN)
+        return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_DIRECT needs one raster size and half-windows <= 7");
+      direct_n = maxN;
+    }
+    if (direct_n != 64 && direct_n != 128 && direct_n != 256)
+      return fail(ctx, CA_EINVAL, "CA_PATH_DIRECT raster size");
+  }
   void* sc;
   ca_status st = scratch(ctx, queue_bytes(n), &sc);
   if (st) return st;
   const QueueMem qm = queue_carve((char*)sc, n);
   unsigned long long* counters = qm.counters;
   const int64_t cap_g = qm.cq.cap_groups;
-  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true));
+  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n));
   unsigned long long h[4] = {0, 0, 0, 0};
   HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, 32, hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
@@ -591,7 +643,9 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     ctx->stats.t_main_ms += ms;
     ctx->stats.n_main_launch += 1;
-    ctx->stats.main_alg_bytes += path == CA_PATH_MIXED ? (double)n * (33280.0 + 2048.0) : io_bytes_fp32(maxN, n);
+    if (path == CA_PATH_MIXED) ctx->stats.main_alg_bytes += (double)n * (33280.0 + 2048.0);
+    else if (path == CA_PATH_DIRECT) ctx->stats.main_alg_bytes += (double)n * (2.0 * direct_n * direct_n + direct_n * direct_n / 8.0);
+    else ctx->stats.main_alg_bytes += io_bytes_fp32(maxN, n);
   }
   const int64_t n_groups = std::min<int64_t>((int64_t)h[2], cap_g);
   if (n_groups > 0 || h[0] > 0) {
@@ -610,8 +664,8 @@ ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
   return clips_create_impl(ctx, stream, n, rect_ptr, rects, raster_n, marker_w, 0, arena, out);
 }
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                            Threshold thr, int path, const PairIO& io, bool checked) {
-  return align_cosine(ctx, crs, cms, s, thr, path, io, checked);
+                            Threshold thr, int path, const PairIO& io, bool checked, int direct_n) {
+  return align_cosine(ctx, crs, cms, s, thr, path, io, checked, direct_n);
 }
 }  // namespace capriv
 
@@ -632,7 +686,7 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
   if (!rep || !mem || !bits || !shift || !count || !score || !flags)
     return fail(ctx, CA_EINVAL, "null output or pair pointer");
   if (n_pairs > (1ll << 31) - 1) return fail(ctx, CA_EINVAL, "pair list longer than 2^31 - 1");
-  if (path < CA_PATH_MIXED || path > CA_PATH_AUTO) return fail(ctx, CA_EINVAL, "bad path");
+  if (path < CA_PATH_MIXED || path > CA_PATH_DIRECT) return fail(ctx, CA_EINVAL, "bad path");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE);
@@ -774,6 +828,7 @@ int64_t n_of(const ca_clipset* cs) { return cs->n; }
 int maxN_of(const ca_clipset* cs) { return cs->maxN; }
 bool mixed_ok_of(const ca_clipset* cs) { return cs->mixed_ok; }
 bool has_fp32_of(const ca_clipset* cs) { return cs->d.spec32 != nullptr; }
+bool has_image_of(const ca_clipset* cs) { return DIRECT_ENABLED && cs->d.img16 != nullptr; }
 const std::vector<int16_t>& hw_of(const ca_clipset* cs) { return cs->hw; }
 std::map<int, TuneEntry>& tune_of(ca_ctx* ctx) { return ctx->tune; }
 void set_stats(ca_ctx* ctx, const ca_run_stats& st) { ctx->stats = st; }
@@ -786,8 +841,9 @@ extern "C" ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs,
   if (!ctx) return CA_EINVAL;
   if (!cs || cs->ctx != ctx || n_pairs < 0 || (n_pairs > 0 && (!rep || !mem || !surf)))
     return fail(ctx, CA_EINVAL, "bad arguments");
-  if (path != CA_PATH_MIXED || !cs->mixed_ok)
-    return fail(ctx, CA_EUNSUPPORTED, "surface access is provided for CA_PATH_MIXED on 128 x 128 sets");
+  const bool direct = DIRECT_ENABLED && path == CA_PATH_DIRECT && cs->direct_ok && cs->minN == cs->maxN;
+  if (!direct && (path != CA_PATH_MIXED || !cs->mixed_ok))
+    return fail(ctx, CA_EUNSUPPORTED, "surface access is provided for CA_PATH_MIXED and CA_PATH_DIRECT on the sets they accept");
   if (n_pairs == 0) return CA_OK;
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
@@ -811,8 +867,12 @@ extern "C" ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs,
   q.peak_err_bits = q.len + 1;
   HIP_OR_FAIL(ctx, hipMemsetAsync(q.len, 0, 32, s));
   CandQueue cq{nullptr, nullptr, q.len + 2, q.len + 3, 0, 0};
-  HIP_OR_FAIL(ctx, launch_pcm_mfma128(cs->d, cs->d, io, Threshold{1, 1}, (float)BAND_MIXED, q, cq, ctx->mf_b1, ctx->mf_a2,
-                                      surf, q.len + 4, s));
+  if (direct)
+    HIP_OR_FAIL(ctx, launch_pcm_direct(cs->d, cs->d, io, cs->maxN, Threshold{1, 1}, (float)BAND_DIRECT, q, cq, surf,
+                                       q.len + 4, s));
+  else
+    HIP_OR_FAIL(ctx, launch_pcm_mfma128(cs->d, cs->d, io, Threshold{1, 1}, (float)BAND_MIXED, q, cq, ctx->mf_b1,
+                                        ctx->mf_a2, surf, q.len + 4, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
   return CA_OK;
 }

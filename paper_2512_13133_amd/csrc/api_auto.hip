@@ -25,9 +25,10 @@ ca_run_stats* stats_of(ca_ctx* ctx);
 void set_stats(ca_ctx* ctx, const ca_run_stats& st);
 const ca::ClipsDev& dev_of(const ca_clipset* cs);
 bool has_fp32_of(const ca_clipset* cs);
+bool has_image_of(const ca_clipset* cs);
 std::map<int, TuneEntry>& tune_of(ca_ctx* ctx);
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                            ca::Threshold thr, int path, const ca::PairIO& io, bool checked);
+                            ca::Threshold thr, int path, const ca::PairIO& io, bool checked, int direct_n);
 }  // namespace capriv
 
 using namespace ca;
@@ -35,10 +36,10 @@ using namespace capriv;
 
 namespace {
 
-// Window classes by the larger half-window of a pair: <= 4, <= 8, <= 15, 16,
+// Window classes by the larger half-window of a pair: <= 4, <= 7, <= 15, 16,
 // <= 23, <= 31, larger.  Raster codes: 64, 128, 256.
 constexpr int N_WCLASS = 7;
-constexpr int W_BOUND[N_WCLASS] = {4, 8, 15, 16, 23, 31, 1 << 20};
+constexpr int W_BOUND[N_WCLASS] = {4, 7, 15, 16, 23, 31, 1 << 20};
 constexpr int N_KEYS = 3 * N_WCLASS;
 constexpr int64_t TUNE_SAMPLE = 4096;
 constexpr int64_t TUNE_MIN = 1024;  // a smaller bucket is repeated to this many pairs, so timings are throughputs
@@ -149,11 +150,11 @@ ca_status tune_bucket(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshol
   TuneEntry e;
   e.sample = m;
   auto run = [&](int path, const PairIO& o, double* us) -> ca_status {
-    ca_status st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true);  // warm
+    ca_status st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true, N);  // warm
     if (st) return st;
     HIP_TRY(ctx, hipStreamSynchronize(s));
     const double t0 = wall_us();
-    st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true);
+    st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true, N);
     if (st) return st;
     HIP_TRY(ctx, hipStreamSynchronize(s));
     *us = (wall_us() - t0) * 1000.0 / (double)m;
@@ -166,8 +167,10 @@ ca_status tune_bucket(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshol
   e.path = CA_PATH_FP64;
   double best = us;
   const bool mixed_ok = N == 128 && W_BOUND[wc] <= 16;
-  for (int path : {CA_PATH_MIXED, CA_PATH_FP32}) {
+  const bool direct_ok = W_BOUND[wc] <= 7 && has_image_of(cs);
+  for (int path : {CA_PATH_MIXED, CA_PATH_DIRECT, CA_PATH_FP32}) {
     if (path == CA_PATH_MIXED && !mixed_ok) continue;
+    if (path == CA_PATH_DIRECT && !direct_ok) continue;
     if (path == CA_PATH_FP32 && !has_fp32_of(cs)) continue;
     st = run(path, tmp, &us);
     if (st) return st;
@@ -194,6 +197,7 @@ const char* path_name(int p) {
     case CA_PATH_MIXED: return "mixed";
     case CA_PATH_FP32: return "fp32";
     case CA_PATH_FP64: return "fp64";
+    case CA_PATH_DIRECT: return "direct";
     default: return "none";
   }
 }
@@ -283,7 +287,7 @@ ca_status align_auto(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshold
       if (st) return done(st);
       it = table.emplace(key, e).first;
     }
-    st = align_cosine_sets(ctx, cs, cs, s, thr, it->second.path, bio, true);
+    st = align_cosine_sets(ctx, cs, cs, s, thr, it->second.path, bio, true, 64 << (key / N_WCLASS));
     if (st) return done(st);
     off += m;
   }
@@ -302,9 +306,11 @@ extern "C" ca_status ca_autotune_report(ca_ctx* ctx, char* buf, int64_t cap, int
   for (const auto& kv : tune_of(ctx)) {
     const int key = kv.first;
     const TuneEntry& e = kv.second;
-    std::snprintf(line, sizeof line, "N=%d w<=%d path=%s us_per_kpair mixed=%.1f fp32=%.1f fp64=%.1f sample=%lld\n",
+    std::snprintf(line, sizeof line,
+                  "N=%d w<=%d path=%s us_per_kpair mixed=%.1f direct=%.1f fp32=%.1f fp64=%.1f sample=%lld\n",
                   64 << (key / N_WCLASS), W_BOUND[key % N_WCLASS], path_name(e.path), e.us_per_kpair[CA_PATH_MIXED],
-                  e.us_per_kpair[CA_PATH_FP32], e.us_per_kpair[CA_PATH_FP64], (long long)e.sample);
+                  e.us_per_kpair[CA_PATH_DIRECT], e.us_per_kpair[CA_PATH_FP32], e.us_per_kpair[CA_PATH_FP64],
+                  (long long)e.sample);
     r += line;
   }
   *len = (int64_t)r.size();
@@ -321,11 +327,11 @@ extern "C" ca_status ca_autotune_save(ca_ctx* ctx, const char* path) {
   if (!ctx || !path) return CA_EINVAL;
   FILE* f = std::fopen(path, "w");
   if (!f) return fail_ctx(ctx, CA_EINVAL, "cannot open the tuning file for writing");
-  std::fprintf(f, "clipalign-autotune 1\n");
+  std::fprintf(f, "clipalign-autotune 2\n");
   for (const auto& kv : tune_of(ctx)) {
     const TuneEntry& e = kv.second;
-    std::fprintf(f, "%d %d %.17g %.17g %.17g %.17g %lld\n", kv.first, e.path, e.us_per_kpair[0], e.us_per_kpair[1],
-                 e.us_per_kpair[2], e.us_per_kpair[3], (long long)e.sample);
+    std::fprintf(f, "%d %d %.17g %.17g %.17g %.17g %.17g %lld\n", kv.first, e.path, e.us_per_kpair[0],
+                 e.us_per_kpair[1], e.us_per_kpair[2], e.us_per_kpair[3], e.us_per_kpair[4], (long long)e.sample);
   }
   const bool ok = std::fclose(f) == 0;
   return ok ? CA_OK : fail_ctx(ctx, CA_EINVAL, "cannot write the tuning file");
@@ -337,22 +343,23 @@ extern "C" ca_status ca_autotune_load(ca_ctx* ctx, const char* path) {
   if (!f) return fail_ctx(ctx, CA_EINVAL, "cannot open the tuning file");
   char head[64] = {0};
   int version = 0;
-  if (std::fscanf(f, "%63s %d", head, &version) != 2 || std::string(head) != "clipalign-autotune" || version != 1) {
+  if (std::fscanf(f, "%63s %d", head, &version) != 2 || std::string(head) != "clipalign-autotune" || version != 2) {
     std::fclose(f);
     return fail_ctx(ctx, CA_EINVAL, "not a tuning file of this library");
   }
   std::map<int, TuneEntry> loaded;
   int key, chosen;
-  double t0, t1, t2, t3;
+  double t0, t1, t2, t3, t4;
   long long sample;
-  while (std::fscanf(f, "%d %d %lf %lf %lf %lf %lld", &key, &chosen, &t0, &t1, &t2, &t3, &sample) == 7) {
-    if (key < 0 || key >= N_KEYS || chosen < CA_PATH_MIXED || chosen > CA_PATH_FP64) {
+  while (std::fscanf(f, "%d %d %lf %lf %lf %lf %lf %lld", &key, &chosen, &t0, &t1, &t2, &t3, &t4, &sample) == 8) {
+    if (key < 0 || key >= N_KEYS || chosen < CA_PATH_MIXED || chosen > CA_PATH_DIRECT || chosen == CA_PATH_AUTO) {
       std::fclose(f);
       return fail_ctx(ctx, CA_EINVAL, "bad entry in the tuning file");
     }
     TuneEntry e;
     e.path = chosen;
     e.us_per_kpair[0] = t0; e.us_per_kpair[1] = t1; e.us_per_kpair[2] = t2; e.us_per_kpair[3] = t3;
+    e.us_per_kpair[4] = t4;
     e.sample = sample;
     loaded[key] = e;
   }

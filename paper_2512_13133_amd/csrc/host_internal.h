@@ -13,7 +13,7 @@ namespace capriv {
 // (microseconds per 1,000 pairs; negative when not applicable or not valid).
 struct TuneEntry {
   int path = -1;
-  double us_per_kpair[4] = {-1.0, -1.0, -1.0, -1.0};  // indexed by CA_PATH_*
+  double us_per_kpair[5] = {-1.0, -1.0, -1.0, -1.0, -1.0};  // indexed by CA_PATH_*
   int64_t sample = 0;
 };
 

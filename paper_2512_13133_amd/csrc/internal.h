@@ -45,6 +45,8 @@ struct ClipsDev {
   __half2* spec16;           // per clip: [u][v < N/2] then Nyquist column [u]
   float2* spec32;            // per clip: [u][v <= N/2] (optional)
   double2* spec64;           // per clip: [u][v <= N/2] (optional)
+  const int64_t* img_off;    // [n] element offset into img16 (N*N each), or null
+  __half* img16;             // per clip: whitened image N * IDFT2(W), row-major (optional)
 };
 
 // Per-call alignment problem in device-visible form.

@@ -25,6 +25,15 @@ hipError_t launch_sanitize_pairs(int64_t n, const int32_t* rep, const int32_t* m
 hipError_t launch_reject_pairs(int64_t n, const uint8_t* bad, const PairIO& io, hipStream_t s);
 hipError_t launch_spectrum(const ClipsDev& cs, const int64_t* ids, int64_t n_ids, int N,
                            double2* scratch, const double2* tw256, hipStream_t s);
+// Whitened images of the listed clips of size N from their FP64 spectra
+// (scratch: n_ids * N * (N/2+1) complex doubles).
+// Direct window surface (half-windows <= 7) on MFMA from the whitened images;
+// every pair has raster N (64, 128 or 256).  `tiles`: one device counter.
+hipError_t launch_pcm_direct(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, int N, Threshold thr,
+                             float band, const RescoreQueue& q, const CandQueue& cq, float* surf_out,
+                             unsigned long long* tiles, hipStream_t s);
+hipError_t launch_image(const ClipsDev& cs, const int64_t* ids, int64_t n_ids, int N, double2* scratch,
+                        const double2* tw256, hipStream_t s);
 // Shared-memory bytes of the per-pair FFT kernel for (scalar size, N, CH, LINES, Lmax).
 size_t pcm_fft_smem(int scalar_bytes, int N, int CH, int LINES, int Lmax);
 // Per-pair FFT surface over n_blocks pairs (list[b] when list is given); with
