@@ -123,11 +123,12 @@ typedef struct {
   int64_t n_main_launch;      /* launches of the main cosine alignment kernel */
   double t_main_ms;           /* their summed duration (HIP events on the launch stream) */
   double main_alg_bytes;      /* their algorithmic HBM bytes (spectra and bit rasters read) */
-  double max_surface_err;     /* max |low-precision - FP64| surface value seen on
-                                 re-decided pairs (normalised surface units) */
-  double tie_band_mixed;      /* band under which CA_PATH_MIXED re-decides a peak */
-  double tie_band_fp32;       /* band under which CA_PATH_FP32 re-decides a peak */
-  double tie_band_direct;     /* band under which CA_PATH_DIRECT re-decides a peak */
+  double max_surface_err;     /* max |low-precision - FP64| peak value seen on
+                                 re-decided pairs, both as K r / K_hi */
+  double tie_band_mixed;      /* CA_PATH_MIXED re-decides a peak whose top-2 gap of K r is below
+                                 tie_band_mixed * sqrt(K_hi), K_hi = N^2 - max(zero bins) */
+  double tie_band_fp32;       /* CA_PATH_FP32 re-decides a peak whose normalised gap is below this */
+  double tie_band_direct;     /* as tie_band_mixed, for CA_PATH_DIRECT */
 } ca_run_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -385,8 +385,9 @@ pcm_direct_kernel(DView cr, DView cm, PairIO io, Threshold thr, float band, Resc
             const int c0 = wave_overlap<N>(bits_j, bits_i, sy0, sx0, lane);
             const int c1 = pr == pf ? c0 : wave_overlap<N>(bits_i, bits_j, sy1, sx1, lane);
             const int K_hi = N * N - max(z_i, z_j);
-            const bool dec0 = (f1 - f2) >= band * (float)K_hi;
-            const bool dec1 = (r1 - r2) >= band * (float)K_hi;
+            const float band_k = band * sqrtf((float)K_hi);  // in units of K r
+            const bool dec0 = (f1 - f2) >= band_k;
+            const bool dec1 = (r1 - r2) >= band_k;
             if (lane == 0) {
               const bool b0 = cosine_bit(c0, n_i, n_j, thr), b1 = cosine_bit(c1, n_j, n_i, thr);
               io.shift[k * 4 + 0] = (int16_t)sy0;
@@ -418,10 +419,10 @@ pcm_direct_kernel(DView cr, DView cm, PairIO io, Threshold thr, float band, Resc
                 }
               }
               if (w_i == w_j) {
-                if (!dec0) queue_direct(sw, 2, w_i, f1 - band * (float)K_hi, f1 / (float)K_hi, k, lane, q, cq);
+                if (!dec0) queue_direct(sw, 2, w_i, f1 - band_k, f1 / (float)K_hi, k, lane, q, cq);
               } else {
-                if (!dec0) queue_direct(sw, 0, w_i, f1 - band * (float)K_hi, f1 / (float)K_hi, k, lane, q, cq);
-                if (!dec1) queue_direct(sw, 1, w_j, r1 - band * (float)K_hi, r1 / (float)K_hi, k, lane, q, cq);
+                if (!dec0) queue_direct(sw, 0, w_i, f1 - band_k, f1 / (float)K_hi, k, lane, q, cq);
+                if (!dec1) queue_direct(sw, 1, w_j, r1 - band_k, r1 / (float)K_hi, k, lane, q, cq);
               }
               __builtin_amdgcn_wave_barrier();
             }

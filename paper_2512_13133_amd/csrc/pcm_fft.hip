@@ -181,6 +181,9 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
   }
   const int K = ired[0];
   __syncthreads();
+  // peak values are recorded and compared normalised by the same K_hi as the
+  // batched path uses, so the reported error compares like with like
+  const double K_hi = (double)(N * N - max(cm.zero_bins[i], cr.zero_bins[j]));
 
   const uint64_t* bits_i = cm.bits + cm.bits_off[i];
   const uint64_t* bits_j = cr.bits + cr.bits_off[j];
@@ -240,7 +243,7 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
         if (!decided && q.need) {
           const uint8_t old = q.need[k];
           q.need[k] = (uint8_t)(old | (1u << d));
-          q.r1_low[k * 2 + d] = (float)top / (float)K;
+          q.r1_low[k * 2 + d] = (float)((double)top / K_hi);
           if (old == 0) {
             const unsigned long long pos = atomicAdd(q.len, 1ull);
             q.list[pos] = k;
@@ -281,7 +284,7 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
                       cosine_bit(best_c, nm, nr, thr));
       if (mode == MODE_RESCORE) {
         io.flags[k] |= (d == 0) ? CA_FLAG_RESCORED_FWD : CA_FLAG_RESCORED_REV;
-        const double err = fabs((double)top / (double)K - (double)q.r1_low[k * 2 + d]);
+        const double err = fabs((double)top / K_hi - (double)q.r1_low[k * 2 + d]);
         atomicMax(q.peak_err_bits, (unsigned long long)__double_as_longlong(err));
       }
     }

@@ -11,7 +11,9 @@
 //            real part uses the operand R, the imaginary part the operand -i R
 //            against the same twiddles (Im T = Re(-i T));
 //   stage 2  K r(dy, dx) = sum_u Tr(u, dx) cos(2 pi u dy/128) - Ti(u, dx) sin(...):
-//            rows dy, K = (u, re/im) = 256, columns dx.
+//            rows dy, K = (u, re/im) = 256, columns dx.  T enters as two FP16
+//            operands, its rounding and the remainder (T - fp16(T)), so that
+//            its conversion adds no error of FP16 size.
 // R is formed with packed FP16 complex multiplies directly in the stage-1 A
 // operand layout; each 16-row stage-1 result block converts in registers into
 // the matching stage-2 B operand, so the intermediate never leaves the wave.
@@ -27,11 +29,13 @@
 // stage-2 twiddles in LDS.
 //
 // Each direction's peak is taken over its window with a wavefront shuffle
-// reduction that keeps the maximum and the runner-up.  A peak whose gap is
-// below `band` (normalised, with the conservative K_hi = N^2 - max(zero bins))
-// is queued for the FP64 re-decision together with its candidate shifts (all
-// within the band of the maximum); the others are final here, with the
-// overlap count c, the FP64 score and the exact-rational bit.
+// reduction that keeps the maximum and the runner-up.  A peak whose gap (in
+// units of K r) is below band * sqrt(K_hi), K_hi = N^2 - max(zero bins), is
+// queued for the FP64 re-decision together with its candidate shifts (all
+// within that band of the maximum); the others are final here, with the
+// overlap count c, the FP64 score and the exact-rational bit.  The error of
+// the surface grows like the square root of the number of non-zero bins, so
+// the band scales with it.
 #include "kernels.h"
 #include "pair_common.h"
 
@@ -413,10 +417,17 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
             const h8_t B2 = h8_t{(_Float16)D1[2 * db][0], (_Float16)D1[2 * db][1], (_Float16)D1[2 * db][2],
                                  (_Float16)D1[2 * db][3], (_Float16)D1[2 * db + 1][0], (_Float16)D1[2 * db + 1][1],
                                  (_Float16)D1[2 * db + 1][2], (_Float16)D1[2 * db + 1][3]};
+            h8_t B2lo;
+  #pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              B2lo[t] = (_Float16)(D1[2 * db][t] - (float)B2[t]);
+              B2lo[4 + t] = (_Float16)(D1[2 * db + 1][t] - (float)B2[4 + t]);
+            }
   #pragma unroll
             for (int yb = 0; yb < 3; ++yb) {
               const h8_t A2 = s_a2[(mb * 3 + yb) * 64 + lane];
               D2[yb][db] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2, B2, D2[yb][db], 0, 0, 0);
+              D2[yb][db] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2, B2lo, D2[yb][db], 0, 0, 0);
             }
           }
         };
@@ -531,8 +542,9 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         // c(s) of the reverse direction at -s equals the forward c(s)
         const int c0 = wave_overlap128(s_bits, mbits, sy0, sx0);
         const int c1 = i1r == i1f ? c0 : wave_overlap128(mbits, s_bits, sy1, sx1);
-        const bool dec0 = (v1f - v2f) >= band * (float)K_hi;
-        const bool dec1 = (v1r - v2r) >= band * (float)K_hi;
+        const float band_k = band * sqrtf((float)K_hi);  // in units of K r
+        const bool dec0 = (v1f - v2f) >= band_k;
+        const bool dec1 = (v1r - v2r) >= band_k;
         if (lane == 0) {
           const bool b0 = cosine_bit(c0, n_i, n_j, thr), b1 = cosine_bit(c1, n_j, n_i, thr);
           io.shift[k * 4 + 0] = (int16_t)sy0;
@@ -568,10 +580,10 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
             for (int t = lane; t < 33 * 33; t += 64) so[t] = sw[t] / (float)K_hi;
           }
           if (w_i == w_j) {  // one group settles both (mirrored) directions
-            if (!dec0) queue_candidates(sw, 2, w_i, v1f - band * (float)K_hi, v1f / (float)K_hi, k, lane, q, cq);
+            if (!dec0) queue_candidates(sw, 2, w_i, v1f - band_k, v1f / (float)K_hi, k, lane, q, cq);
           } else {
-            if (!dec0) queue_candidates(sw, 0, w_i, v1f - band * (float)K_hi, v1f / (float)K_hi, k, lane, q, cq);
-            if (!dec1) queue_candidates(sw, 1, w_j, v1r - band * (float)K_hi, v1r / (float)K_hi, k, lane, q, cq);
+            if (!dec0) queue_candidates(sw, 0, w_i, v1f - band_k, v1f / (float)K_hi, k, lane, q, cq);
+            if (!dec1) queue_candidates(sw, 1, w_j, v1r - band_k, v1r / (float)K_hi, k, lane, q, cq);
           }
           // the tile is rewritten by the wave's next pair only after every lane is done reading
           __builtin_amdgcn_wave_barrier();
