@@ -78,6 +78,20 @@ __device__ __forceinline__ int block_overlap(const uint64_t* rep, const uint64_t
   return out;
 }
 
+// Tie rule of the peak as one total order: a larger key wins (larger overlap
+// count c >= 0, then smaller |dy|+|dx|, then smaller dy, then smaller dx;
+// shift components in [-128, 127]).
+__device__ __forceinline__ uint64_t tie_key(int c, int dy, int dx) {
+  const uint64_t l1 = (uint64_t)(abs(dy) + abs(dx));  // 0 .. 256
+  return ((uint64_t)c << 32) | ((511u - l1) << 16) | ((uint64_t)(255 - (dy + 128)) << 8) |
+         (uint64_t)(255 - (dx + 128));
+}
+__device__ __forceinline__ void tie_decode(uint64_t key, int& c, int& dy, int& dx) {
+  c = (int)(key >> 32);
+  dy = 255 - (int)((key >> 8) & 0xff) - 128;
+  dx = 255 - (int)(key & 0xff) - 128;
+}
+
 // Eq. 2 as an exact integer test: c / sqrt(n_m n_r) > p / q.
 __device__ __forceinline__ bool cosine_bit(int c, int n_m, int n_r, Threshold t) {
   if (n_m <= 0 || n_r <= 0) return false;

@@ -255,9 +255,11 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
     }
 
     // exact tie rule: every shift within TAU of the maximum, then larger c,
-    // smaller |dy|+|dx|, lexicographically smaller (dy, dx)
+    // smaller |dy|+|dx|, lexicographically smaller (dy, dx) -- one integer key
+    // per candidate whose maximum is the winner (a running comparison with
+    // nested branches is a pattern the compiler has mistranslated here)
     const T cut = top - (T)(TAU * (double)K);
-    int best_c = -1, best_l1 = 0, best_dy = 0, best_dx = 0;
+    uint64_t best_key = 0;
     for (int p0 = 0; p0 < P; p0 += blockDim.x) {
       int dyc = 0, dxc = 0;
       const int p = p0 + tid;
@@ -268,17 +270,12 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
         int dy, dx;
         (void)value(p0 + t, dy, dx);
         const int c = block_overlap(brep, bmem, N, dy, dx, ired);
-        const int l1 = abs(dy) + abs(dx);
-        bool better = false;
-        if (best_c < 0 || c > best_c) better = true;
-        else if (c == best_c) {
-          if (l1 < best_l1) better = true;
-          else if (l1 == best_l1 && (dy < best_dy || (dy == best_dy && dx < best_dx))) better = true;
-        }
-        if (better) { best_c = c; best_l1 = l1; best_dy = dy; best_dx = dx; }
+        best_key = max(best_key, tie_key(c, dy, dx));
       }
       __syncthreads();
     }
+    int best_c, best_dy, best_dx;
+    tie_decode(best_key, best_c, best_dy, best_dx);
     if (tid == 0) {
       write_direction(io, k, d, best_dy, best_dx, best_c, cosine_score(best_c, nm, nr),
                       cosine_bit(best_c, nm, nr, thr));

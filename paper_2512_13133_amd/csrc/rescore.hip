@@ -23,18 +23,6 @@ namespace ca {
 
 constexpr int RS_THREADS = 256;
 
-// Tie-rule order of a candidate (overlap count c >= 0, shift components in
-// [-128, 127]) as an integer: a larger key wins.
-__device__ __forceinline__ uint64_t tie_key(int c, int dy, int dx) {
-  const uint64_t l1 = (uint64_t)(abs(dy) + abs(dx));              // 0 .. 256
-  return ((uint64_t)c << 32) | ((511u - l1) << 16) | ((uint64_t)(255 - (dy + 128)) << 8) |
-         (uint64_t)(255 - (dx + 128));
-}
-__device__ __forceinline__ void tie_decode(uint64_t key, int& c, int& dy, int& dx) {
-  c = (int)(key >> 32);
-  dy = 255 - (int)((key >> 8) & 0xff) - 128;
-  dx = 255 - (int)(key & 0xff) - 128;
-}
 
 // Sum over the wave, by a butterfly whose partial sums are the same in every
 // lane (fixed order, so the result is deterministic).
