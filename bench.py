@@ -185,7 +185,7 @@ def main():
                       "call_pairs_per_s": n_pairs / call_s, "identical_results": same,
                       "kernel_ms": st32["t_main_ms"], "rescored": st32["pairs_rescored"]}
         h32.close()
-    stats_out = {k: st[k] for k in ("pairs_rescored", "max_surface_err", "tie_band_mixed", "pairs_screened",
+    stats_out = {k: st[k] for k in ("pairs_rescored", "max_surface_err", "max_peak_err_sqrt", "tie_band_mixed", "pairs_screened",
                                     "pairs_survived")}
     stage_ms = {k: round(v * 1000.0 / args.steps, 2) for k, v in stage_t.items()}
 

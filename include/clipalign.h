@@ -129,6 +129,8 @@ typedef struct {
                                  tie_band_mixed * sqrt(K_hi), K_hi = N^2 - max(zero bins) */
   double tie_band_fp32;       /* CA_PATH_FP32 re-decides a peak whose normalised gap is below this */
   double tie_band_direct;     /* as tie_band_mixed, for CA_PATH_DIRECT */
+  double max_peak_err_sqrt;   /* max_surface_err in the band's units: |low - FP64| peak difference
+                                 of K r divided by sqrt(K_hi); stays below tie_band_mixed / 2 */
 } ca_run_stats;
 
 /* ---- context ------------------------------------------------------------ */

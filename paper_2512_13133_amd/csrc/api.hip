@@ -19,12 +19,12 @@ using namespace ca;
 // must exceed twice the path's worst surface error plus the tie tolerance.
 // FP32: normalised surface units.  Mixed and direct (FP16 data): the error of
 // K r grows like sqrt(K_hi), so the band is a coefficient of sqrt(K_hi) in
-// units of K r; 0.04 is 2.5 times twice the worst error seen (0.0158 sqrt(K_hi)
-// before the split of T, 0.0072 after it, over 17.2M workload pairs and 500k
-// emulated ones).
+// units of K r.  With the split of T the worst error seen is 0.0065 sqrt(K_hi)
+// (1.5M emulated workload candidate pairs and the worst of all 17.2M), so
+// 0.03 covers twice it with a factor 2.3.
 static constexpr double BAND_FP32 = 1e-5;
-static constexpr double BAND_MIXED = 0.04;
-static constexpr double BAND_DIRECT = 0.04;
+static constexpr double BAND_MIXED = 0.03;
+static constexpr double BAND_DIRECT = 0.03;
 // The direct-correlation kernel is built but not launched: its first GPU run
 // ended in a memory-aperture fault whose cause is not yet identified, so the
 // path reports CA_EUNSUPPORTED until it is.
@@ -558,6 +558,7 @@ static QueueMem queue_carve(char* base, int64_t n) {
   m.counters = (unsigned long long*)(base + b_need + b_list + b_r1);
   m.q.len = m.counters;
   m.q.peak_err_bits = m.counters + 1;
+  m.q.peak_ratio_bits = m.counters + 5;
   m.cq.n_groups = m.counters + 2;
   m.cq.n_shifts = m.counters + 3;
   m.cq.groups = (CandGroup*)(base + b_need + b_list + b_r1 + b_cnt);
@@ -592,7 +593,8 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
   if (events && (e = hipEventRecord(ctx->ev1, s)) != hipSuccess) return e;
   // FP64 re-decision: the candidate groups, then the full FP64 surface of the
   // pairs queued for it
-  e = launch_rescore_candidates(cr, cm, io, thr, m.cq, ctx->tw64, m.q.peak_err_bits, m.q.r1_low, s);
+  e = launch_rescore_candidates(cr, cm, io, thr, m.cq, ctx->tw64, m.q.peak_err_bits, m.q.peak_ratio_bits,
+                                m.q.r1_low, s);
   if (e != hipSuccess) return e;
   FftPlan pl = plan_fft(maxN, Lmax, 8);
   return launch_pcm_fft64(cr, cm, io, m.q.list, n, MODE_RESCORE, thr, 0.0, ctx->tw64, pl.CH, pl.LINES, Lmax, maxN,
@@ -639,8 +641,8 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   unsigned long long* counters = qm.counters;
   const int64_t cap_g = qm.cq.cap_groups;
   HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n));
-  unsigned long long h[4] = {0, 0, 0, 0};
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, 32, hipMemcpyDeviceToHost, s));
+  unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
   {
     float ms = 0.f;
@@ -656,6 +658,8 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
     double err;
     std::memcpy(&err, &h[1], 8);
     ctx->stats.max_surface_err = std::max(ctx->stats.max_surface_err, err);
+    std::memcpy(&err, &h[5], 8);
+    ctx->stats.max_peak_err_sqrt = std::max(ctx->stats.max_peak_err_sqrt, err);
   }
   ctx->stats.pairs_aligned += n;
   ctx->stats.pairs_rescored += n_groups + (int64_t)h[0];
@@ -869,6 +873,7 @@ extern "C" ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs,
   q.r1_low = (float*)(p + b_need + b_list);
   q.len = (unsigned long long*)(p + b_need + b_list + b_r1);
   q.peak_err_bits = q.len + 1;
+  q.peak_ratio_bits = q.len + 5;
   HIP_OR_FAIL(ctx, hipMemsetAsync(q.len, 0, 32, s));
   CandQueue cq{nullptr, nullptr, q.len + 2, q.len + 3, 0, 0};
   if (direct)

@@ -74,7 +74,8 @@ struct RescoreQueue {
   int64_t* list;                      // queued pair ids
   unsigned long long* len;            // number of queued pairs
   float* r1_low;                      // [n_pairs][2] low-precision normalised peak value
-  unsigned long long* peak_err_bits;  // max |r1_low - r1_fp64| as double bits
+  unsigned long long* peak_err_bits;  // max |r1_low - r1_fp64| as double bits (both K r / K_hi)
+  unsigned long long* peak_ratio_bits = nullptr;  // the same difference in K r units / sqrt(K_hi)
 };
 
 // Near-tie candidates of a queued direction: the window shifts whose

@@ -66,7 +66,8 @@ hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const Pair
 // count is read on the device (*cq.n_groups, at most cq.cap_groups).
 hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                      const CandQueue& cq, const double2* tw256,
-                                     unsigned long long* peak_err_bits, const float* r1_low, hipStream_t s);
+                                     unsigned long long* peak_err_bits, unsigned long long* peak_ratio_bits,
+                                     const float* r1_low, hipStream_t s);
 // Cosine candidate generation for 128 x 128 clips with half-windows <= 16:
 // write = false runs the bounds pass (bitmask + counts), write = true the
 // ordered write of the survivors (needs pa.offs).

@@ -283,6 +283,8 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
         io.flags[k] |= (d == 0) ? CA_FLAG_RESCORED_FWD : CA_FLAG_RESCORED_REV;
         const double err = fabs((double)top / K_hi - (double)q.r1_low[k * 2 + d]);
         atomicMax(q.peak_err_bits, (unsigned long long)__double_as_longlong(err));
+        if (q.peak_ratio_bits)
+          atomicMax(q.peak_ratio_bits, (unsigned long long)__double_as_longlong(err * sqrt(K_hi)));
       }
     }
     __syncthreads();

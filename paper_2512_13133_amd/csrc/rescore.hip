@@ -45,7 +45,7 @@ __device__ __forceinline__ int wave_sum_i32(int x) {
 __global__ void __launch_bounds__(RS_THREADS)
 rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, CandQueue cq,
                           const double2* __restrict__ tw256, unsigned long long* peak_err_bits,
-                          const float* __restrict__ r1_low) {
+                          unsigned long long* peak_ratio_bits, const float* __restrict__ r1_low) {
   constexpr int WAVES = RS_THREADS / 64;
   __shared__ double s_part[WAVES][MAX_CAND];
   __shared__ int s_kpart[WAVES];
@@ -180,6 +180,8 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
           // compare like with like: both sides normalised by K_hi
           const double err = fabs(best / K_hi - (double)r1_low[k * 2 + dd]);
           atomicMax(peak_err_bits, (unsigned long long)__double_as_longlong(err));
+          if (peak_ratio_bits)
+            atomicMax(peak_ratio_bits, (unsigned long long)__double_as_longlong(err * sqrt(K_hi)));
         }
       }
     }
@@ -188,11 +190,12 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
 
 hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                      const CandQueue& cq, const double2* tw256,
-                                     unsigned long long* peak_err_bits, const float* r1_low, hipStream_t s) {
+                                     unsigned long long* peak_err_bits, unsigned long long* peak_ratio_bits,
+                                     const float* r1_low, hipStream_t s) {
   if (cq.cap_groups <= 0) return hipSuccess;
   const unsigned grid = (unsigned)std::min<int64_t>(cq.cap_groups, 8192);
   hipLaunchKernelGGL(rescore_candidates_kernel, dim3(grid), dim3(RS_THREADS), 0, s, cr, cm, io, thr, cq, tw256,
-                     peak_err_bits, r1_low);
+                     peak_err_bits, peak_ratio_bits, r1_low);
   return hipGetLastError();
 }
 

@@ -427,7 +427,12 @@ def test_mixed_equals_fp32_on_full_workload(ctx):
     h = ctx.clips(cs, fp32=True)
     rep, mem = ctx.prune(h, "cosine", (19, 20))
     say(f"[full] pairs={rep.numel()}")
+    ctx.reset_stats()
     om = ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "mixed")
+    st = ctx.stats()
+    say(f"[full] mixed re-decided {st['pairs_rescored']} pairs; max peak error / sqrt(K_hi) "
+        f"{st['max_peak_err_sqrt']:.4f} against band {st['tie_band_mixed']}")
+    assert st["max_peak_err_sqrt"] < st["tie_band_mixed"] / 2
     of = ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "fp32")
     torch.cuda.synchronize()
     diff = torch.zeros(rep.numel(), dtype=torch.bool, device=rep.device)
