@@ -70,8 +70,14 @@ constexpr int MF_RSRC_WORD3 = 0x00020000;               // raw buffer, 32-bit da
 __device__ __forceinline__ h2_t as_h2(uint32_t x) { return __builtin_bit_cast(h2_t, x); }
 __device__ __forceinline__ uint32_t as_u32(h2_t x) { return __builtin_bit_cast(uint32_t, x); }
 
-// -i z on a packed FP16 (re, im) pair.
-__device__ __forceinline__ h2_t mul_neg_i(h2_t z) { return h2_t{z.y, -z.x}; }
+// -i z on a packed FP16 (re, im) pair: (im, -re) in one packed multiply by
+// 1.0 whose operand selects swap the halves and negate the new high half
+// (the compiler otherwise spends a swap and a sign flip).
+__device__ __forceinline__ h2_t mul_neg_i(h2_t z) {
+  uint32_t r;
+  asm("v_pk_mul_f16 %0, %1, 1.0 op_sel:[1,0] op_sel_hi:[0,0] neg_hi:[1,0]" : "=v"(r) : "v"(as_u32(z)));
+  return as_h2(r);
+}
 
 // m * conj(r) on packed FP16 (re, im) pairs.
 __device__ __forceinline__ h2_t cmulc_h2(h2_t m, h2_t r) {
@@ -93,6 +99,19 @@ __device__ __forceinline__ void load_member_block(__amdgpu_buffer_rsrc_t rs, int
   }
   const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (MF_N * 64 + mb * 16 + g * 4) * 4, 0, 0);
   out[4] = uint4{v[0], v[1], v[2], v[3]};
+}
+
+// Two FP32 values as FP16 pairs: their rounding (hi) and the remainder
+// (lo = value - hi, rounded).  value - hi is exact in FP32 (the two are
+// close), and a dot product of hi with (-1, 0) or (0, -1) plus the value
+// forms it in one instruction.
+// Both roundings truncate (one packing instruction each); the remainder
+// keeps what the first drops, so the pair carries the value to about 2^-22.
+__device__ __forceinline__ void split_f16(float a, float b, h2_t& hi, h2_t& lo) {
+  hi = __builtin_bit_cast(h2_t, __builtin_amdgcn_cvt_pkrtz(a, b));
+  const float la = __builtin_amdgcn_fdot2(hi, h2_t{(_Float16)-1.0f, (_Float16)0.0f}, a, false);
+  const float lb = __builtin_amdgcn_fdot2(hi, h2_t{(_Float16)0.0f, (_Float16)-1.0f}, b, false);
+  lo = __builtin_bit_cast(h2_t, __builtin_amdgcn_cvt_pkrtz(la, lb));
 }
 
 // A wave-uniform 64-bit value from lane l.
@@ -369,10 +388,29 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         // One 16-row block of both stages from the member data mv[0..4] of block mb.
         auto block = [&](int mb, const uint4* mv5) {
           const int u = mb * 16 + col;  // A-operand row of this lane
+          // Nyquist column v = 64: T(u, dx) gets R(u, 64) (-1)^dx for the lane's
+          // 4 rows; the parity of dx (-16 + col, col, 16 + col) is that of col,
+          // so one pair of vectors starts the accumulation of all three blocks.
+          f4_t N_re, N_im;
+          {
+            const int u0 = mb * 16 + g * 4;
+            const uint4 mv = mv5[4];
+            const uint4 rv = *reinterpret_cast<const uint4*>(&s_spec[MF_N * MF_ROW_H2 + u0]);
+            const h2_t n0 = cmulc_h2(as_h2(mv.x), as_h2(rv.x));
+            const h2_t n1 = cmulc_h2(as_h2(mv.y), as_h2(rv.y));
+            const h2_t n2 = cmulc_h2(as_h2(mv.z), as_h2(rv.z));
+            const h2_t n3 = cmulc_h2(as_h2(mv.w), as_h2(rv.w));
+            const float sg = (col & 1) ? -1.f : 1.f;
+            N_re = f4_t{sg * (float)n0.x, sg * (float)n1.x, sg * (float)n2.x, sg * (float)n3.x};
+            N_im = f4_t{sg * (float)n0.y, sg * (float)n1.y, sg * (float)n2.y, sg * (float)n3.y};
+          }
           // D1[2 db] = Tr, D1[2 db + 1] = Ti for dx = 16 db - 16 + col
           f4_t D1[6];
   #pragma unroll
-          for (int nb = 0; nb < 6; ++nb) D1[nb] = f4_t{0.f, 0.f, 0.f, 0.f};
+          for (int nb = 0; nb < 3; ++nb) {
+            D1[2 * nb] = N_re;
+            D1[2 * nb + 1] = N_im;
+          }
   #pragma unroll
           for (int kb = 0; kb < 4; ++kb) {
             const uint4 mv = mv5[kb];
@@ -390,39 +428,16 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
               D1[2 * nb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1n, B1[kb][nb], D1[2 * nb + 1], 0, 0, 0);
             }
           }
-          // Nyquist column v = 64: T(u, dx) += R(u, 64) (-1)^dx for the lane's 4 rows
-          {
-            const int u0 = mb * 16 + g * 4;
-            const uint4 mv = mv5[4];
-            const uint4 rv = *reinterpret_cast<const uint4*>(&s_spec[MF_N * MF_ROW_H2 + u0]);
-            const h2_t n0 = cmulc_h2(as_h2(mv.x), as_h2(rv.x));
-            const h2_t n1 = cmulc_h2(as_h2(mv.y), as_h2(rv.y));
-            const h2_t n2 = cmulc_h2(as_h2(mv.z), as_h2(rv.z));
-            const h2_t n3 = cmulc_h2(as_h2(mv.w), as_h2(rv.w));
-            const float nr[4] = {(float)n0.x, (float)n1.x, (float)n2.x, (float)n3.x};
-            const float ni[4] = {(float)n0.y, (float)n1.y, (float)n2.y, (float)n3.y};
-            // column dx = -16 + col, col, 16 + col: parity of dx equals parity of col
-            const float sg = (col & 1) ? -1.f : 1.f;
-  #pragma unroll
-            for (int db = 0; db < 3; ++db)
-  #pragma unroll
-              for (int t = 0; t < 4; ++t) {
-                D1[2 * db][t] += sg * nr[t];
-                D1[2 * db + 1][t] += sg * ni[t];
-              }
-          }
           // stage 2: B operand (u, re/im) x dx straight from the stage-1 block
   #pragma unroll
           for (int db = 0; db < 3; ++db) {
-            const h8_t B2 = h8_t{(_Float16)D1[2 * db][0], (_Float16)D1[2 * db][1], (_Float16)D1[2 * db][2],
-                                 (_Float16)D1[2 * db][3], (_Float16)D1[2 * db + 1][0], (_Float16)D1[2 * db + 1][1],
-                                 (_Float16)D1[2 * db + 1][2], (_Float16)D1[2 * db + 1][3]};
-            h8_t B2lo;
-  #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              B2lo[t] = (_Float16)(D1[2 * db][t] - (float)B2[t]);
-              B2lo[4 + t] = (_Float16)(D1[2 * db + 1][t] - (float)B2[4 + t]);
-            }
+            h2_t hi[4], lo[4];
+            split_f16(D1[2 * db][0], D1[2 * db][1], hi[0], lo[0]);
+            split_f16(D1[2 * db][2], D1[2 * db][3], hi[1], lo[1]);
+            split_f16(D1[2 * db + 1][0], D1[2 * db + 1][1], hi[2], lo[2]);
+            split_f16(D1[2 * db + 1][2], D1[2 * db + 1][3], hi[3], lo[3]);
+            const h8_t B2 = h8_t{hi[0].x, hi[0].y, hi[1].x, hi[1].y, hi[2].x, hi[2].y, hi[3].x, hi[3].y};
+            const h8_t B2lo = h8_t{lo[0].x, lo[0].y, lo[1].x, lo[1].y, lo[2].x, lo[2].y, lo[3].x, lo[3].y};
   #pragma unroll
             for (int yb = 0; yb < 3; ++yb) {
               const h8_t A2 = s_a2[(mb * 3 + yb) * 64 + lane];
@@ -434,20 +449,23 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         // The member's blocks are double-buffered in registers: block mb+1 (or
         // the next pair's block 0) loads while block mb computes, so the HBM
         // latency hides behind the previous block's matrix work.
+        // Two buffers alternate (blocks mb and mb+1), so no registers are
+        // copied between blocks; the next pair's block 0 ends in m_cur.
         if (!have0) load_member_block(mrs, 0, col, g, m_cur);
   #pragma unroll 1
-        for (int mb = 0; mb < 8; ++mb) {
-          uint4 mnext[5];
-          const bool last = mb == 7;
-          load_member_block(__builtin_amdgcn_make_buffer_rsrc((void*)(last ? nptr : mptr), (short)0,
-                                                              last ? nbytes : MF_SPEC_BYTES, MF_RSRC_WORD3),
-                            last ? 0 : mb + 1, col, g, mnext);
+        for (int mb = 0; mb < 8; mb += 2) {
+          uint4 m_odd[5];
+          load_member_block(mrs, mb + 1, col, g, m_odd);
           // keep the loads at the top: sunk to where registers free up, their
           // latency would surface at the next block
           __builtin_amdgcn_sched_barrier(0);
           block(mb, m_cur);
-  #pragma unroll
-          for (int t = 0; t < 5; ++t) m_cur[t] = mnext[t];
+          const bool last = mb == 6;
+          load_member_block(__builtin_amdgcn_make_buffer_rsrc((void*)(last ? nptr : mptr), (short)0,
+                                                              last ? nbytes : MF_SPEC_BYTES, MF_RSRC_WORD3),
+                            last ? 0 : mb + 2, col, g, m_cur);
+          __builtin_amdgcn_sched_barrier(0);
+          block(mb + 1, m_odd);
         }
         have0 = has_next;
 
