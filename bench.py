@@ -120,7 +120,8 @@ def main():
         return r
 
     def step(keep=False):
-        h = timed("clips", lambda: make_clips(args.path == "fp32"))
+        # FP32 spectra serve the FP32 path and the FP32 screen of the mixed path's re-decision
+        h = timed("clips", lambda: make_clips(args.path != "fp64"))
         rep, mem = timed("prune_cosine", lambda: ctx.prune(h, "cosine", (19, 20)))
         out = timed("align_cosine", lambda: ctx.align_pairs(h, rep, mem, "cosine", (19, 20), args.path))
         n_e = 0
@@ -171,7 +172,7 @@ def main():
     # plain FP32 per-pair comparator on the identical pair list
     comparator = None
     if args.path == "mixed" and not args.no_comparator:
-        h32 = make_clips(fp32=True)
+        h32 = h  # the step's clip set holds FP32 spectra
         ctx.align_pairs(h32, rep, mem, "cosine", (19, 20), "fp32")  # warm
         ctx.reset_stats()
         torch.cuda.synchronize()
@@ -184,8 +185,7 @@ def main():
         comparator = {"path": "fp32 per-pair FFT", "kernel_pairs_per_s": n_pairs / (st32["t_main_ms"] * 1e-3),
                       "call_pairs_per_s": n_pairs / call_s, "identical_results": same,
                       "kernel_ms": st32["t_main_ms"], "rescored": st32["pairs_rescored"]}
-        h32.close()
-    stats_out = {k: st[k] for k in ("pairs_rescored", "max_surface_err", "max_peak_err_sqrt", "tie_band_mixed", "pairs_screened",
+    stats_out = {k: st[k] for k in ("pairs_rescored", "groups_exact", "max_surface_err", "max_peak_err_sqrt", "tie_band_mixed", "pairs_screened",
                                     "pairs_survived")}
     stage_ms = {k: round(v * 1000.0 / args.steps, 2) for k, v in stage_t.items()}
 

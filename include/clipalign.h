@@ -131,6 +131,8 @@ typedef struct {
   double tie_band_direct;     /* as tie_band_mixed, for CA_PATH_DIRECT */
   double max_peak_err_sqrt;   /* max_surface_err in the band's units: |low - FP64| peak difference
                                  of K r divided by sqrt(K_hi); stays below tie_band_mixed / 2 */
+  int64_t groups_exact;       /* candidate groups the FP32 screen (clip sets with CA_CLIPS_FP32)
+                                 left to the FP64 re-decision; without FP32 spectra, all groups */
 } ca_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -159,7 +161,10 @@ ca_status ca_reset_stats(ca_ctx* ctx);
  *     [-w_i, w_i]^2 (mod N_i on the cosine track, every residue once).
  *   flags: CA_CLIPS_DEVICE_PTRS if the four arrays are device pointers (else
  *     host pointers; the library copies them either way).
- *     CA_CLIPS_FP32 keeps FP32 spectra for CA_PATH_FP32 (doubles the spectra).
+ *     CA_CLIPS_FP32 keeps FP32 spectra (8 (N/2+1) N bytes a clip) for
+ *     CA_PATH_FP32; the FP64 re-decision of CA_PATH_MIXED then also screens
+ *     its candidates on them first (same results, half the bytes read for
+ *     the groups the screen settles).
  *     CA_CLIPS_IMAGE keeps each clip's whitened image w_i = IDFT2(W_i) (the
  *     spatial form of the whitened spectrum), scaled by N and stored as FP16
  *     (2 N^2 bytes a clip), for CA_PATH_DIRECT.

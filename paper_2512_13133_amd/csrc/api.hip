@@ -535,16 +535,18 @@ FftPlan plan_fft(int N, int L, int scalar_bytes) {
 
 // Queue storage of the low-precision paths for n pairs: need[n], list[n],
 // r1_low[2n], 32 counters (0 queued pairs, 1 max error bits, 2 candidate
-// groups, 3 candidate shifts, 4 tile counter, rest spare), candidate groups
-// and their shifts.
+// groups, 3 candidate shifts, 4 tile counter, 5 error ratio bits, 8 groups
+// left by the FP32 screen, rest spare), candidate groups, their shifts, and
+// the groups left by the screen.
 struct QueueMem {
   RescoreQueue q;
   CandQueue cq;
+  CandQueue exact;  // groups the FP32 screen leaves to the FP64 pass (cq's shifts)
   unsigned long long* counters;
 };
 static size_t queue_bytes(int64_t n) {
   const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
-  return align_up(n) + 2 * align_up(8 * (size_t)n) + 256 + align_up(sizeof(CandGroup) * (size_t)cap_g) +
+  return align_up(n) + 2 * align_up(8 * (size_t)n) + 256 + 2 * align_up(sizeof(CandGroup) * (size_t)cap_g) +
          align_up(2 * (size_t)cap_s);
 }
 static QueueMem queue_carve(char* base, int64_t n) {
@@ -565,6 +567,10 @@ static QueueMem queue_carve(char* base, int64_t n) {
   m.cq.shifts = (int16_t*)(base + b_need + b_list + b_r1 + b_cnt + b_grp);
   m.cq.cap_groups = cap_g;
   m.cq.cap_shifts = cap_s;
+  m.exact = m.cq;
+  m.exact.groups = (CandGroup*)(base + b_need + b_list + b_r1 + b_cnt + b_grp + align_up(2 * (size_t)cap_s));
+  m.exact.n_groups = m.counters + 8;
+  m.exact.n_shifts = nullptr;
   return m;
 }
 
@@ -593,7 +599,7 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
   if (events && (e = hipEventRecord(ctx->ev1, s)) != hipSuccess) return e;
   // FP64 re-decision: the candidate groups, then the full FP64 surface of the
   // pairs queued for it
-  e = launch_rescore_candidates(cr, cm, io, thr, m.cq, ctx->tw64, m.q.peak_err_bits, m.q.peak_ratio_bits,
+  e = launch_rescore_candidates(cr, cm, io, thr, m.cq, m.exact, ctx->tw64, m.q.peak_err_bits, m.q.peak_ratio_bits,
                                 m.q.r1_low, s);
   if (e != hipSuccess) return e;
   FftPlan pl = plan_fft(maxN, Lmax, 8);
@@ -641,7 +647,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   unsigned long long* counters = qm.counters;
   const int64_t cap_g = qm.cq.cap_groups;
   HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n));
-  unsigned long long h[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
   {
@@ -663,6 +669,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   }
   ctx->stats.pairs_aligned += n;
   ctx->stats.pairs_rescored += n_groups + (int64_t)h[0];
+  ctx->stats.groups_exact += (cr.spec32 && cm.spec32) ? (int64_t)h[8] : n_groups;
   return CA_OK;
 }
 

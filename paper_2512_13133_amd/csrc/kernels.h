@@ -63,9 +63,12 @@ hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const Pair
                               const RescoreQueue& q, const CandQueue& cq, const void* b1frag,
                               const void* a2frag, float* surf_out, unsigned long long* tiles, hipStream_t s);
 // FP64 re-decision of queued directions at their candidate shifts: the group
-// count is read on the device (*cq.n_groups, at most cq.cap_groups).
+// count is read on the device (*cq.n_groups, at most cq.cap_groups).  With
+// FP32 spectra on both sides and `exact.groups` set, a screen over the FP32
+// spectra settles what it can and appends the rest to `exact` (its own group
+// array and counter, cq's shifts and capacity), which the FP64 pass then takes.
 hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
-                                     const CandQueue& cq, const double2* tw256,
+                                     const CandQueue& cq, const CandQueue& exact, const double2* tw256,
                                      unsigned long long* peak_err_bits, unsigned long long* peak_ratio_bits,
                                      const float* r1_low, hipStream_t s);
 // Cosine candidate generation for 128 x 128 clips with half-windows <= 16:

@@ -357,23 +357,52 @@ def test_mixed_surface_within_band(ctx):
     h.close()
 
 
-@pytest.mark.parametrize("seed", [2, 9])
-def test_cosine_c128_mixed(ctx, seed):
+@pytest.mark.parametrize("seed,fp32", [(2, False), (9, False), (2, True)])
+def test_cosine_c128_mixed(ctx, seed, fp32):
+    """The mixed path equals the oracle; with FP32 spectra its re-decision
+    first screens the candidate groups on them and settles most there."""
     cs = c128_subset(200, seed=seed)
     rep, mem = pairs_for(cs, 3000, seed=seed)
     # group by representative, as candidate generation emits them, with a ragged tail
     o = np.lexsort((mem, rep))
     rep, mem = rep[o], mem[o]
-    say(f"[cosine] c128 path=mixed seed={seed} pairs={rep.size}")
-    h = ctx.clips(cs)
+    say(f"[cosine] c128 path=mixed seed={seed} fp32={fp32} pairs={rep.size}")
+    h = ctx.clips(cs, fp32=fp32)
     ctx.reset_stats()
     got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "mixed"))
     ref = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
     check_cosine(got, ref, rep, mem, "c128/mixed")
     st = ctx.stats()
-    say(f"[cosine] rescored {st['pairs_rescored']} of {st['pairs_aligned']}, max peak err {st['max_surface_err']:.2e}")
+    say(f"[cosine] rescored {st['pairs_rescored']} of {st['pairs_aligned']} ({st['groups_exact']} in FP64), "
+        f"max peak err {st['max_surface_err']:.2e}")
     assert st["pairs_rescored"] < rep.size // 5
+    if fp32:
+        assert st["groups_exact"] < st["pairs_rescored"] // 2
     h.close()
+
+
+def test_fp32_screen_equals_fp64_redecision(ctx):
+    """The FP32 screen of the re-decision changes no result: the same pairs
+    through clip sets with and without FP32 spectra give identical outputs,
+    flags included (2,000 clips of the benchmark generator, 120k pairs)."""
+    cs = clipgen.c128(n_clips=2_000, n_templates=60)
+    h64 = ctx.clips(cs)
+    h32 = ctx.clips(cs, fp32=True)
+    rep, mem = ctx.prune(h64, "cosine", (19, 20))
+    rep, mem = rep[:120_000], mem[:120_000]
+    say(f"[screen] pairs={rep.numel()}")
+    ctx.reset_stats()
+    a = to_np(ctx.align_pairs(h64, rep, mem, "cosine", (19, 20), "mixed"))
+    st64 = ctx.stats()
+    ctx.reset_stats()
+    b = to_np(ctx.align_pairs(h32, rep, mem, "cosine", (19, 20), "mixed"))
+    st32 = ctx.stats()
+    say(f"[screen] groups {st64['groups_exact']} -> {st32['groups_exact']} in FP64")
+    for k in ("bits", "shift", "count", "score", "flags"):
+        assert (a[k] == b[k]).all(), k
+    assert st64["groups_exact"] > 0 and st32["groups_exact"] < st64["groups_exact"]
+    h64.close()
+    h32.close()
 
 
 def periodic_set(n, seed):
@@ -396,20 +425,24 @@ def periodic_set(n, seed):
                            np.zeros((n, 2), np.int16))
 
 
-def test_mixed_exact_ties_both_directions(ctx):
+@pytest.mark.parametrize("fp32", [False, True])
+def test_mixed_exact_ties_both_directions(ctx, fp32):
     """Exactly tied peaks (periodic clips): the FP64 re-decision of a pair
     with equal windows settles both directions with the tie rule in each
-    direction's own coordinates, equal to the oracle."""
+    direction's own coordinates, equal to the oracle.  With FP32 spectra the
+    screen must pass every exactly tied group on to FP64."""
     cs = periodic_set(48, seed=5)
     rep, mem = pairs_for(cs, None, seed=5)
     o = np.lexsort((mem, rep))
     rep, mem = rep[o], mem[o]
-    say(f"[ties] periodic pairs={rep.size}")
-    h = ctx.clips(cs)
+    say(f"[ties] periodic pairs={rep.size} fp32={fp32}")
+    h = ctx.clips(cs, fp32=fp32)
+    ctx.reset_stats()
     got = to_np(ctx.align_pairs(h, rep, mem, "cosine", (1, 2), "mixed"))
     ref = cover.align_pairs_cosine(cs, rep, mem, 1, 2, workers=WORKERS)
     check_cosine(got, ref, rep, mem, "periodic/mixed")
     assert (got["flags"] & 3).any()
+    assert ctx.stats()["groups_exact"] > 0
     h.close()
 
 
