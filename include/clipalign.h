@@ -202,6 +202,13 @@ ca_status ca_clips_inspect(const ca_clipset* cs, int64_t i, uint64_t* bits, int3
  * CA_ESTATE if the set was created without CA_CLIPS_IMAGE. */
 ca_status ca_clips_image(const ca_clipset* cs, int64_t i, float* img);
 
+/* Copy clip i's stored whitened half-spectrum W(u, v) = F/|F| (Eq. 4 with
+ * each clip whitened on its own; 0 where |F| <= 1e-2), u < N, v <= N/2, into
+ * host memory out[N][N/2 + 1][2] (real, imaginary) as doubles, read from the
+ * copy of the given precision (16, 32 or 64 bits).  CA_ESTATE if that copy is
+ * not kept (32: the set was made without CA_CLIPS_FP32). */
+ca_status ca_clips_spectrum(const ca_clipset* cs, int64_t i, int32_t precision, double* out);
+
 /* ---- alignment on an explicit pair list (paper Sec. 3.2) ----------------- */
 
 /* Align n_pairs unordered pairs (rep[k], mem[k]) in both directions.

@@ -30,7 +30,7 @@ FLAG_INVALID = 128
 
 SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
-    "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect", "ca_clips_image",
+    "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect", "ca_clips_image", "ca_clips_spectrum",
     "ca_align_pairs", "ca_surface", "ca_prune", "ca_cluster",
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
     "ca_server_stats", "ca_server_last_error",
@@ -85,6 +85,7 @@ def load():
     lib.ca_clips_count.argtypes = [P, C.POINTER(C.c_int64)]
     lib.ca_clips_inspect.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P]
     lib.ca_clips_image.argtypes = [P, C.c_int64, P]
+    lib.ca_clips_spectrum.argtypes = [P, C.c_int64, C.c_int32, P]
     lib.ca_align_pairs.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64,
                                    P, P, P, P, P, P, P]
     lib.ca_surface.argtypes = [P, P, P, C.c_int32, C.c_int64, P, P, P]
@@ -208,6 +209,12 @@ class Context:
         out = np.zeros((N, N), np.float32)
         self._check(self.lib.ca_clips_image(clips.handle, int(i), _ptr(out)))
         return out
+
+    def spectrum(self, clips, i, N, precision=64):
+        """Stored whitened half-spectrum of clip i, complex128 [N, N/2 + 1]."""
+        out = np.zeros((N, N // 2 + 1, 2), np.float64)
+        self._check(self.lib.ca_clips_spectrum(clips.handle, int(i), int(precision), _ptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
 
     # -------------------------------------------------------------- pairs
     def align_pairs(self, clips, rep, mem, kind="cosine", thr=(19, 20), path="mixed"):

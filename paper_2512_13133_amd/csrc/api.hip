@@ -407,6 +407,16 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
     for (int64_t i = 0; i < n; ++i)
       if (hN[i] == N) ids.push_back(i);
     if (ids.empty()) continue;
+    if (N == 128 && !image) {
+      // whole transform per workgroup, no scratch: one launch for all clips
+      void* sc;
+      st = scratch(ctx, align_up(sizeof(int64_t) * ids.size()), &sc);
+      if (st) return bail(st);
+      HIP_OR_FAIL(ctx, hipMemcpyAsync(sc, ids.data(), sizeof(int64_t) * ids.size(), hipMemcpyHostToDevice, s));
+      HIP_OR_FAIL(ctx, launch_spectrum128(cs->d, (const int64_t*)sc, (int64_t)ids.size(), ctx->tw64, s));
+      HIP_OR_FAIL(ctx, hipStreamSynchronize(s));  // scratch reuse
+      continue;
+    }
     const size_t per = (size_t)N * (N / 2 + 1) * sizeof(double2);
     const int64_t batch = std::max<int64_t>(1, std::min<int64_t>((int64_t)ids.size(), (512ll << 20) / (int64_t)per));
     void* sc;
@@ -483,6 +493,41 @@ ca_status ca_clips_image(const ca_clipset* cs, int64_t i, float* img) {
   std::vector<__half> h((size_t)N * N);
   HIP_OR_FAIL(ctx, hipMemcpy(h.data(), cs->d.img16 + off, sizeof(__half) * h.size(), hipMemcpyDeviceToHost));
   for (size_t t = 0; t < h.size(); ++t) img[t] = __half2float(h[t]);
+  return CA_OK;
+}
+
+ca_status ca_clips_spectrum(const ca_clipset* cs, int64_t i, int32_t precision, double* out) {
+  if (!cs || !out) return CA_EINVAL;
+  ca_ctx* ctx = cs->ctx;
+  if (i < 0 || i >= cs->n) return fail(ctx, CA_EINVAL, "clip id out of range");
+  if (precision != 16 && precision != 32 && precision != 64) return fail(ctx, CA_EINVAL, "precision 16, 32 or 64");
+  if (precision == 32 && !cs->d.spec32) return fail(ctx, CA_ESTATE, "clip set created without CA_CLIPS_FP32");
+  if (precision == 64 && !cs->d.spec64) return fail(ctx, CA_ESTATE, "clip set without FP64 spectra");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  const int N = cs->hN[i], H = N / 2 + 1;
+  int64_t off = 0;
+  HIP_OR_FAIL(ctx, hipMemcpy(&off, cs->d.spec_off + i, 8, hipMemcpyDeviceToHost));
+  const size_t nb = (size_t)N * H;
+  if (precision == 64) {
+    HIP_OR_FAIL(ctx, hipMemcpy(out, cs->d.spec64 + off, sizeof(double2) * nb, hipMemcpyDeviceToHost));
+  } else if (precision == 32) {
+    std::vector<float2> h(nb);
+    HIP_OR_FAIL(ctx, hipMemcpy(h.data(), cs->d.spec32 + off, sizeof(float2) * nb, hipMemcpyDeviceToHost));
+    for (size_t t = 0; t < nb; ++t) {
+      out[2 * t] = h[t].x;
+      out[2 * t + 1] = h[t].y;
+    }
+  } else {
+    // FP16 layout: [u][v < N/2], then the Nyquist column [u]
+    std::vector<__half2> h(nb);
+    HIP_OR_FAIL(ctx, hipMemcpy(h.data(), cs->d.spec16 + off, sizeof(__half2) * nb, hipMemcpyDeviceToHost));
+    for (int u = 0; u < N; ++u)
+      for (int v = 0; v < H; ++v) {
+        const __half2 z = v < N / 2 ? h[(size_t)u * (N / 2) + v] : h[(size_t)N * (N / 2) + u];
+        out[2 * ((size_t)u * H + v)] = __low2float(z);
+        out[2 * ((size_t)u * H + v) + 1] = __high2float(z);
+      }
+  }
   return CA_OK;
 }
 

@@ -23,6 +23,9 @@ hipError_t launch_sanitize_pairs(int64_t n, const int32_t* rep, const int32_t* m
                                  int32_t* rep_o, int32_t* mem_o, uint8_t* bad, unsigned long long* n_bad,
                                  hipStream_t s);
 hipError_t launch_reject_pairs(int64_t n, const uint8_t* bad, const PairIO& io, hipStream_t s);
+// 128 x 128 clips only: the same spectra from one fused kernel (no scratch).
+hipError_t launch_spectrum128(const ClipsDev& cs, const int64_t* ids, int64_t n_ids, const double2* tw256,
+                              hipStream_t s);
 hipError_t launch_spectrum(const ClipsDev& cs, const int64_t* ids, int64_t n_ids, int N,
                            double2* scratch, const double2* tw256, hipStream_t s);
 // Whitened images of the listed clips of size N from their FP64 spectra

@@ -118,6 +118,31 @@ def test_pack_and_spectrum_match_oracle(ctx, which):
     h.close()
 
 
+def test_stored_spectra_all_precisions(ctx):
+    """The FP64, FP32 and FP16 copies of every clip's whitened half-spectrum
+    equal the oracle's FP64 one to their rounding (FP64: 1e-10, room for the
+    two FFTs' rounding divided by |F| >= 1e-2): 128 x 128 clips through the
+    fused one-workgroup transform, 64 and 256 through the two-pass one, with
+    dense, sparse, empty and fully set rasters."""
+    cs = mixed_set(seed=11, per=(6, 10, 3))
+    rng = np.random.default_rng(5)
+    extra = clipgen.ClipSet(np.array([0, 0, 1, 2], np.int64),
+                            np.array([[0, 128, 0, 128], [5, 6, 7, 8]], np.int32),
+                            np.array([128, 128, 128], np.int16), np.array([4, 4, 4], np.int16),
+                            np.array([-1, -1, -1], np.int32), np.zeros((3, 2), np.int16))
+    cs = clipgen.concat([cs, extra, c128_subset(12, seed=int(rng.integers(100)))])
+    h = ctx.clips(cs, fp32=True)
+    for i in range(cs.n):
+        N = int(cs.raster_n[i])
+        W = cosine.whiten(cosine.spectrum(raster.clip_raster(cs, i)))[:, :N // 2 + 1]
+        for prec, tol in ((64, 1e-10), (32, 2.0 ** -24 + 1e-10), (16, 2.0 ** -11 + 1e-7)):
+            got = ctx.spectrum(h, i, N, prec)
+            err = max(np.abs(got.real - W.real).max(), np.abs(got.imag - W.imag).max())
+            assert err <= tol, f"clip {i} N={N} precision {prec}: error {err:.3e}"
+            assert ((got == 0) == (W == 0)).all(), f"clip {i} precision {prec}: zero bins"
+    h.close()
+
+
 # ------------------------------------------------------------------ a4-a6 cosine
 
 
