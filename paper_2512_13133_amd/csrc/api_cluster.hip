@@ -63,9 +63,13 @@ void build_ranges(const ca_clipset* cs, const ca_constraint* con, std::vector<in
     const int64_t m = (int64_t)ids.size();
     screened += m * (m - 1) / 2;
     if (con->kind == CA_COSINE) {
-      std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
-        return np[a] != np[b] ? np[a] < np[b] : a < b;
-      });
+      // (n, id) order by a stable counting sort on n <= N^2 (ids ascend already)
+      std::vector<int32_t> start((size_t)N * N + 2, 0);
+      for (int32_t i : ids) ++start[(size_t)np[i] + 1];
+      for (size_t v = 1; v < start.size(); ++v) start[v] += start[v - 1];
+      std::vector<int32_t> sorted(ids.size());
+      for (int32_t i : ids) sorted[start[(size_t)np[i]]++] = i;
+      ids.swap(sorted);
       const unsigned __int128 p2 = (unsigned __int128)(con->thr_num * con->thr_num);
       const unsigned __int128 q2 = (unsigned __int128)(con->thr_den * con->thr_den);
       int64_t e = 0;
@@ -95,21 +99,25 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
   const bool edge = con->kind == CA_EDGE;
   PruneCache* pc = prune_cache_of(ctx);
   const bool hit = pc->gen == gen_of(cs) && pc->kind == con->kind && pc->p == con->thr_num && pc->q == con->thr_den;
-  std::vector<int32_t> order, hi;
-  int64_t screened = 0;
-  build_ranges(cs, con, order, hi, screened);
-  const int64_t na = (int64_t)order.size();
-  std::vector<int64_t> range_off(na);
-  int64_t bits = 0;
-  for (int64_t a = 0; a < na; ++a) {
-    range_off[a] = bits;
-    const int64_t len = hi[a] - a - 1;
-    bits += edge ? (len + 63) / 64 * 64 : len;
-  }
-  const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na), b_mask = aup(8 * (size_t)(bits / 64 + 1));
-  const size_t need = 2 * b_ord + 2 * b_rng + b_mask;
+  // a hit (the writing call after a sizing call) reuses the device copies of
+  // the anchor order, ranges and bitmask
+  int64_t na = pc->na;
   char* base;
   if (!hit) {
+    std::vector<int32_t> order, hi;
+    int64_t screened = 0;
+    build_ranges(cs, con, order, hi, screened);
+    na = (int64_t)order.size();
+    std::vector<int64_t> range_off(na);
+    int64_t bits = 0;
+    for (int64_t a = 0; a < na; ++a) {
+      range_off[a] = bits;
+      const int64_t len = hi[a] - a - 1;
+      bits += edge ? (len + 63) / 64 * 64 : len;
+    }
+    const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na);
+    const size_t b_mask = aup(8 * (size_t)(bits / 64 + 1));
+    const size_t need = 2 * b_ord + 2 * b_rng + b_mask;
     if (pc->bytes < need) {
       free_ctx(ctx, pc->dev, pc->bytes);
       pc->dev = nullptr;
@@ -147,9 +155,11 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     pc->p = con->thr_num;
     pc->q = con->thr_den;
     pc->na = na;
+    pc->b_mask = b_mask;
     stats_of(ctx)->pairs_screened += screened;
     stats_of(ctx)->pairs_survived += pc->total;
   }
+  const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na);
   base = (char*)pc->dev;
   *n_out = pc->total;
   if (!rep) return CA_OK;

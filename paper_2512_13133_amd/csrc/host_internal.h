@@ -23,6 +23,7 @@ struct PruneCache {
   uint64_t gen = 0;              // clip-set generation (0 = empty)
   int64_t kind = 0, p = 0, q = 0;
   int64_t na = 0, total = 0;
+  size_t b_mask = 0;             // bytes of the survivor bitmask
   void* dev = nullptr;           // order | hi | range_off | counts/offsets | mask
   size_t bytes = 0;
   std::vector<int64_t> counts;
