@@ -7,8 +7,8 @@
 // the number of row runs.
 //
 // label_kernel: one workgroup per clip.  Row runs are extracted in parallel,
-// then the 4-connected polygons are labelled by union-find over runs of
-// adjacent rows (one thread; runs are few), giving each polygon its
+// then the 4-connected polygons are labelled by a lock-free union-find over
+// runs of adjacent rows (one thread per row pair), giving each polygon its
 // bounding box, and each run its polygon label.
 #include "kernels.h"
 
@@ -103,23 +103,50 @@ __global__ void __launch_bounds__(256) pack_kernel(const int64_t* __restrict__ r
   if (tid == 0) cs.nruns[i] = red[0];
 }
 
-__device__ __forceinline__ int uf_find(int16_t* parent, int x) {
-  while (parent[x] != x) {
-    parent[x] = parent[parent[x]];
-    x = parent[x];
+// Root of x in a forest whose links only point to smaller indices
+// (parent[x] <= x); reads may race with links made by other threads, which
+// only move a root further up.
+__device__ __forceinline__ int uf_root(volatile int* parent, int x) {
+  int p = parent[x];
+  while (p != x) {
+    x = p;
+    p = parent[x];
   }
   return x;
 }
 
+// Join the sets of a and b: the larger root is linked under the smaller one
+// by a compare-and-swap that succeeds only while it is still a root.
+__device__ __forceinline__ void uf_unite(int* parent, int a, int b) {
+  while (true) {
+    a = uf_root(parent, a);
+    b = uf_root(parent, b);
+    if (a == b) return;
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    if (atomicCAS(parent + a, a, b) == a) return;
+  }
+}
+
+// Polygons are the 4-connected components of the row runs.  Rows are merged
+// with their predecessor in parallel (one thread per row pair); each
+// component's root is its smallest run index, i.e. its first run in raster
+// order, and labels number the roots in that order (an exclusive scan).
 __global__ void __launch_bounds__(256) label_kernel(ClipsDev cs, int64_t block0) {
-  __shared__ uint32_t srun[MAX_RUNS];   // x0 | x1 << 9
-  __shared__ int16_t parent[MAX_RUNS];
+  __shared__ uint32_t srun[MAX_RUNS];   // x0 | x1 << 9 | y << 18
+  __shared__ int parent[MAX_RUNS];
   __shared__ int16_t slabel[MAX_RUNS];
   __shared__ uint16_t rowp[257];
-  __shared__ int16_t box[MAX_POLY][4];
-  __shared__ int s_npoly;
+  __shared__ uint16_t rcount[256];
+  __shared__ int box[MAX_POLY][4];
+  __shared__ int wsum[4];
+  __shared__ int gbx[4];
   const int64_t i = block0 + (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int N = cs.N[i];
   const int wpr = N / 64;
   const int total = cs.nruns[i];
@@ -134,7 +161,6 @@ __global__ void __launch_bounds__(256) label_kernel(ClipsDev cs, int64_t block0)
   }
   const uint64_t* bits = cs.bits + cs.bits_off[i];
   // per-row run counts -> exclusive prefix in rowp (serial over <= 256 rows)
-  __shared__ uint16_t rcount[256];
   if (tid < N) {
     int runs = 0;
     int prev = 0;
@@ -145,6 +171,11 @@ __global__ void __launch_bounds__(256) label_kernel(ClipsDev cs, int64_t block0)
     }
     rcount[tid] = (uint16_t)runs;
   }
+  if (tid < MAX_POLY) {
+    box[tid][0] = box[tid][2] = 1 << 20;
+    box[tid][1] = box[tid][3] = -1;
+  }
+  if (tid < 4) gbx[tid] = (tid & 1) ? -1 : (1 << 20);
   __syncthreads();
   if (tid == 0) {
     int acc = 0;
@@ -171,69 +202,72 @@ __global__ void __launch_bounds__(256) label_kernel(ClipsDev cs, int64_t block0)
       uint64_t nv = ~bits[tid * wpr + k2] & (~0ull << (a & 63));
       while (nv == 0 && ++k2 < wpr) nv = ~bits[tid * wpr + k2];
       int b = (k2 >= wpr) ? N : 64 * k2 + __ffsll((unsigned long long)nv) - 1;
-      srun[o++] = (uint32_t)a | ((uint32_t)b << 9);
+      srun[o++] = (uint32_t)a | ((uint32_t)b << 9) | ((uint32_t)tid << 18);
       x = b;
     }
   }
-  for (int t = tid; t < total; t += blockDim.x) parent[t] = (int16_t)t;
+  for (int t = tid; t < total; t += blockDim.x) parent[t] = t;
   __syncthreads();
-  if (tid == 0) {
-    // union runs of row y-1 and row y that share a column (4-connectivity)
-    for (int y = 1; y < N; ++y) {
-      int a = rowp[y - 1], ae = rowp[y];
-      int b = rowp[y], be = rowp[y + 1];
-      while (a < ae && b < be) {
-        int a0 = srun[a] & 511, a1 = (srun[a] >> 9) & 511;
-        int b0 = srun[b] & 511, b1 = (srun[b] >> 9) & 511;
-        if (a0 < b1 && b0 < a1) {
-          int ra = uf_find(parent, a), rb = uf_find(parent, b);
-          if (ra != rb) {
-            if (ra < rb) parent[rb] = (int16_t)ra;
-            else parent[ra] = (int16_t)rb;
-          }
-        }
-        if (a1 < b1) ++a;
-        else ++b;
-      }
+  // union runs of row y-1 and row y that share a column (4-connectivity)
+  for (int y = 1 + tid; y < N; y += blockDim.x) {
+    int a = rowp[y - 1], ae = rowp[y];
+    int b = rowp[y], be = rowp[y + 1];
+    while (a < ae && b < be) {
+      const int a0 = srun[a] & 511, a1 = (srun[a] >> 9) & 511;
+      const int b0 = srun[b] & 511, b1 = (srun[b] >> 9) & 511;
+      if (a0 < b1 && b0 < a1) uf_unite(parent, a, b);
+      if (a1 < b1) ++a;
+      else ++b;
     }
-    // labels in order of each polygon's first run (raster order)
-    int np = 0;
-    int gx0 = N, gx1 = 0, gy0 = N, gy1 = 0;
-    int y = 0;
-    for (int r = 0; r < total; ++r) {
-      while (rowp[y + 1] <= r) ++y;
-      int root = uf_find(parent, r);
-      int lab;
-      if (root == r) {
-        lab = np++;
-        if (lab < MAX_POLY) {
-          box[lab][0] = N; box[lab][1] = 0; box[lab][2] = N; box[lab][3] = 0;
-        }
-      } else {
-        lab = slabel[root];
-      }
-      slabel[r] = (int16_t)lab;
-      int x0 = srun[r] & 511, x1 = (srun[r] >> 9) & 511;
-      if (lab < MAX_POLY) {
-        box[lab][0] = (int16_t)min((int)box[lab][0], x0);
-        box[lab][1] = (int16_t)max((int)box[lab][1], x1);
-        box[lab][2] = (int16_t)min((int)box[lab][2], y);
-        box[lab][3] = (int16_t)max((int)box[lab][3], y + 1);
-      }
-      gx0 = min(gx0, x0); gx1 = max(gx1, x1);
-      gy0 = min(gy0, y); gy1 = max(gy1, y + 1);
-    }
-    s_npoly = np;
-    if (total == 0) { gx0 = gx1 = gy0 = gy1 = 0; }
-    gb[0] = (int16_t)gx0; gb[1] = (int16_t)gx1; gb[2] = (int16_t)gy0; gb[3] = (int16_t)gy1;
-    cs.npoly[i] = np > MAX_POLY ? -1 : np;
   }
   __syncthreads();
-  const int np = min(s_npoly, MAX_POLY);
-  for (int t = tid; t < np * 4; t += blockDim.x) bx[t] = box[t >> 2][t & 3];
+  // labels of the roots: exclusive count of roots before them, in chunks of
+  // the workgroup size
+  int base = 0;
+  for (int c0 = 0; c0 < total; c0 += blockDim.x) {
+    const int r = c0 + tid;
+    const bool root = r < total && parent[r] == r;
+    const unsigned long long m = __ballot(root);
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int before = base;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (root) slabel[r] = (int16_t)(before + __popcll(m & ((1ull << lane) - 1ull)));
+    base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+  const int np = base;
+  // every run takes its root's label; boxes by LDS atomics
+  for (int r = tid; r < total; r += blockDim.x) {
+    const int root = uf_root(parent, r);
+    const int lab = slabel[root];
+    if (root != r) slabel[r] = (int16_t)lab;
+    const uint32_t w = srun[r];
+    const int x0 = w & 511, x1 = (w >> 9) & 511, y = (w >> 18) & 511;
+    if (lab < MAX_POLY) {
+      atomicMin(&box[lab][0], x0);
+      atomicMax(&box[lab][1], x1);
+      atomicMin(&box[lab][2], y);
+      atomicMax(&box[lab][3], y + 1);
+    }
+    atomicMin(&gbx[0], x0);
+    atomicMax(&gbx[1], x1);
+    atomicMin(&gbx[2], y);
+    atomicMax(&gbx[3], y + 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (total == 0) gb[0] = gb[1] = gb[2] = gb[3] = 0;
+    else {
+      gb[0] = (int16_t)gbx[0]; gb[1] = (int16_t)gbx[1]; gb[2] = (int16_t)gbx[2]; gb[3] = (int16_t)gbx[3];
+    }
+    cs.npoly[i] = np > MAX_POLY ? -1 : np;
+  }
+  const int npb = min(np, MAX_POLY);
+  for (int t = tid; t < npb * 4; t += blockDim.x) bx[t] = (int16_t)box[t >> 2][t & 3];
   uint32_t* gr = cs.runs + cs.run_off[i];
   for (int t = tid; t < total; t += blockDim.x)
-    gr[t] = srun[t] | ((uint32_t)min((int)slabel[t], MAX_POLY - 1) << 18);
+    gr[t] = (srun[t] & 0x3ffffu) | ((uint32_t)min((int)slabel[t], MAX_POLY - 1) << 18);
   uint16_t* grp = cs.run_rowptr + cs.rowptr_off[i];
   for (int t = tid; t <= N; t += blockDim.x) grp[t] = rowp[t];
 }

@@ -118,6 +118,53 @@ def test_pack_and_spectrum_match_oracle(ctx, which):
     h.close()
 
 
+def _labeller_set():
+    """Shapes that stress the parallel labeller: U and comb shapes whose arms
+    join far below their first rows, a spiral, diagonal neighbours (separate
+    under 4-connectivity), a checkerboard beyond the 64-polygon cap, random
+    dense rasters, an empty and a full raster; sizes 64, 128 and 256."""
+    rng = np.random.default_rng(17)
+    clips = []
+    def add(rects, N=128):
+        clips.append((np.array(rects, np.int32).reshape(-1, 4), N))
+    add([(10, 14, 10, 100), (40, 44, 10, 100), (10, 44, 96, 100)])             # U
+    add([(x, x + 2, 5, 120) for x in range(4, 120, 6)] + [(4, 120, 118, 122)])  # comb joined at the bottom
+    add([(10, 110, 10, 12), (108, 110, 10, 110), (20, 110, 108, 110), (20, 22, 30, 110),
+         (20, 90, 30, 32), (88, 90, 30, 90), (40, 90, 88, 90), (40, 42, 50, 90)])  # spiral
+    add([(x, x + 1, x, x + 1) for x in range(0, 60, 1)])                          # diagonal: 60 polygons
+    add([(x, x + 1, y, y + 1) for x in range(0, 24, 2) for y in range(0, 24, 2)])  # 144 polygons: over the cap
+    add([(0, 128, 0, 128)])
+    add([], 64)
+    for N in (64, 128, 256):
+        for _ in range(3):
+            m = int(rng.integers(20, 60))
+            x0 = rng.integers(0, N, m); y0 = rng.integers(0, N, m)
+            add(np.stack([x0, x0 + rng.integers(1, 12, m), y0, y0 + rng.integers(1, 12, m)], 1), N)
+    ptr = np.cumsum([0] + [c[0].shape[0] for c in clips]).astype(np.int64)
+    rects = np.concatenate([c[0] for c in clips]).astype(np.int32)
+    n = len(clips)
+    return clipgen.ClipSet(ptr, rects, np.array([c[1] for c in clips], np.int16), np.full(n, 4, np.int16),
+                           np.full(n, -1, np.int32), np.zeros((n, 2), np.int16))
+
+
+def test_labeller_matches_oracle_components(ctx):
+    """Polygon counts (or -1 past the 64-polygon cap) and polygon boxes equal
+    the oracle's 4-connected components on shapes whose runs merge late."""
+    cs = _labeller_set()
+    h = ctx.clips(cs)
+    for i in range(cs.n):
+        N = int(cs.raster_n[i])
+        got = ctx.inspect(h, i, N)
+        lab, boxes = raster.components(raster.clip_raster(cs, i))
+        P = boxes.shape[0]
+        if P > 64:
+            assert got["n_poly"][0] == -1, f"clip {i}: {P} polygons"
+            continue
+        assert got["n_poly"][0] == P, f"polygons of clip {i}"
+        assert sorted(map(tuple, got["boxes"][:P].tolist())) == sorted(map(tuple, boxes.tolist())), f"clip {i}"
+    h.close()
+
+
 def test_stored_spectra_all_precisions(ctx):
     """The FP64, FP32 and FP16 copies of every clip's whitened half-spectrum
     equal the oracle's FP64 one to their rounding (FP64: 1e-10, room for the
