@@ -101,17 +101,31 @@ __device__ __forceinline__ void load_member_block(__amdgpu_buffer_rsrc_t rs, int
   out[4] = uint4{v[0], v[1], v[2], v[3]};
 }
 
-// Two FP32 values as FP16 pairs: their rounding (hi) and the remainder
-// (lo = value - hi, rounded).  value - hi is exact in FP32 (the two are
-// close), and a dot product of hi with (-1, 0) or (0, -1) plus the value
-// forms it in one instruction.
-// Both roundings truncate (one packing instruction each); the remainder
-// keeps what the first drops, so the pair carries the value to about 2^-22.
+// Two FP32 values as FP16 pairs: their truncation (hi, one packing
+// instruction) and the remainder lo = value - hi rounded to nearest.  One
+// mixed-precision FMA per value forms value - hi exactly (the two are close)
+// and rounds it into its half of lo, so the pair carries the value to about
+// 2^-22.
 __device__ __forceinline__ void split_f16(float a, float b, h2_t& hi, h2_t& lo) {
-  hi = __builtin_bit_cast(h2_t, __builtin_amdgcn_cvt_pkrtz(a, b));
-  const float la = __builtin_amdgcn_fdot2(hi, h2_t{(_Float16)-1.0f, (_Float16)0.0f}, a, false);
-  const float lb = __builtin_amdgcn_fdot2(hi, h2_t{(_Float16)0.0f, (_Float16)-1.0f}, b, false);
-  lo = __builtin_bit_cast(h2_t, __builtin_amdgcn_cvt_pkrtz(la, lb));
+  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
+  hi = __builtin_bit_cast(h2_t, h);
+  uint32_t l;
+  asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=&v"(l) : "v"(h), "v"(a));
+  asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(l) : "v"(h), "v"(b));
+  lo = __builtin_bit_cast(h2_t, l);
+}
+
+// s times the low / high FP16 half of z, as FP32, in one mixed-precision
+// multiply-add each (the conversion is exact).
+__device__ __forceinline__ float sgn_lo(h2_t z, float s) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, %2, 0 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(as_u32(z)), "v"(s));
+  return r;
+}
+__device__ __forceinline__ float sgn_hi(h2_t z, float s) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, %2, 0 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(as_u32(z)), "v"(s));
+  return r;
 }
 
 // A wave-uniform 64-bit value from lane l.
@@ -401,8 +415,8 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
             const h2_t n2 = cmulc_h2(as_h2(mv.z), as_h2(rv.z));
             const h2_t n3 = cmulc_h2(as_h2(mv.w), as_h2(rv.w));
             const float sg = (col & 1) ? -1.f : 1.f;
-            N_re = f4_t{sg * (float)n0.x, sg * (float)n1.x, sg * (float)n2.x, sg * (float)n3.x};
-            N_im = f4_t{sg * (float)n0.y, sg * (float)n1.y, sg * (float)n2.y, sg * (float)n3.y};
+            N_re = f4_t{sgn_lo(n0, sg), sgn_lo(n1, sg), sgn_lo(n2, sg), sgn_lo(n3, sg)};
+            N_im = f4_t{sgn_hi(n0, sg), sgn_hi(n1, sg), sgn_hi(n2, sg), sgn_hi(n3, sg)};
           }
           // D1[2 db] = Tr, D1[2 db + 1] = Ti for dx = 16 db - 16 + col
           f4_t D1[6];
