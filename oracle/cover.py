@@ -18,7 +18,7 @@ import os
 
 import numpy as np
 
-from . import cosine, edge, loop, raster
+from . import cosine, edge, loop, raster, xcorr
 
 _SHARED = {}
 
@@ -67,6 +67,25 @@ def _cosine_chunk(args):
     return bits, shift, c, sc, r1
 
 
+def _xcorr_chunk(args):
+    rep, mem, p, q = args
+    prep = _SHARED["prep"]
+    n = rep.size
+    bits = np.zeros(n, np.uint8)
+    shift = np.zeros((n, 2, 2), np.int16)
+    c = np.zeros((n, 2), np.int32)
+    sc = np.zeros((n, 2), np.float64)
+    for k in range(n):
+        j, i = int(rep[k]), int(mem[k])
+        for d, (m, r) in enumerate(((i, j), (j, i))):
+            res = xcorr.align(prep.a(m), prep.a(r), prep.w(m), p, q)
+            bits[k] |= np.uint8(res["bit"]) << d
+            shift[k, d] = res["s"]
+            c[k, d] = res["c"]
+            sc[k, d] = res["score"]
+    return bits, shift, c, sc
+
+
 def _edge_chunk(args):
     rep, mem, t_edge = args
     prep = _SHARED["prep"]
@@ -107,6 +126,12 @@ def align_pairs_cosine(clips, rep, mem, p, q, workers=None):
     """Cosine track on a pair list: dict(bits, shift, c, score, r1)."""
     bits, shift, c, sc, r1 = _run(_cosine_chunk, clips, rep, mem, (p, q), workers)
     return dict(bits=bits, shift=shift, c=c, score=sc, r1=r1)
+
+
+def align_pairs_xcorr(clips, rep, mem, p, q, workers=None):
+    """Exact-objective alignment on a pair list: dict(bits, shift, c, score)."""
+    bits, shift, c, sc = _run(_xcorr_chunk, clips, rep, mem, (p, q), workers)
+    return dict(bits=bits, shift=shift, c=c, score=sc)
 
 
 def align_pairs_edge(clips, rep, mem, t_edge, workers=None):

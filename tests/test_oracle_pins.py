@@ -16,7 +16,7 @@ import pytest
 from scipy.fft import dctn
 
 import clipgen
-from oracle import cosine, cover, edge, loop, prune, raster, scp
+from oracle import cosine, cover, edge, loop, prune, raster, scp, xcorr
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -530,3 +530,68 @@ def test_small_workload_symmetry_and_cover():
     assert ((er["bits"] & 1) == (er["bits"] >> 1)).all()
     cl = cover.cluster_cosine(cs, 19, 20, K=1, rep=rep, mem=mem, res=res)
     assert 1 <= cl["n_clusters"] <= cs.n
+
+
+# ------------------------------------------------------------------ exact objective (NEXT f1)
+
+
+@pytest.mark.parametrize("N,w", [(32, 5), (64, 16)])
+def test_xcorr_counts_equal_fft_correlation(N, w):
+    """c(s) from the definition equals the circular cross-correlation of the
+    two rasters computed through numpy's FFT (rounded to integers) at every
+    shift of the window."""
+    rng = np.random.default_rng(N + w)
+    for _ in range(3):
+        a_m = rand_clip(rng, N, k=5)
+        a_r = rand_clip(rng, N, k=5)
+        shifts, counts = xcorr.overlap_surface(a_m, a_r, w)
+        corr = np.fft.ifft2(np.conj(np.fft.fft2(a_r.astype(float))) * np.fft.fft2(a_m.astype(float))).real
+        ref = np.rint(corr[shifts[:, 0] % N, shifts[:, 1] % N]).astype(np.int64)
+        assert (counts == ref).all()
+
+
+def test_xcorr_recovers_cyclic_shift_exactly():
+    """A member that is the representative moved by s0 (inside the window)
+    aligns at s0 with c = n: no other shift can reach all n pixels of a dense
+    random pattern."""
+    rng = np.random.default_rng(9)
+    N, w = 64, 12
+    for s0 in [(0, 0), (3, -7), (-12, 12), (5, 0)]:
+        a_r = rng.random((N, N)) < 0.4
+        a_m = np.roll(a_r, s0, axis=(0, 1))
+        res = xcorr.align(a_m, a_r, w, 19, 20)
+        assert res["s"] == s0 and res["c"] == int(a_r.sum()) and res["bit"]
+
+
+def test_xcorr_tie_rule_on_constructed_ties():
+    """One representative pixel against two member pixels: c = 1 at exactly
+    two shifts, and the rule picks the smaller |dy|+|dx|, then the smaller
+    (dy, dx)."""
+    N, w = 32, 6
+    a_r = np.zeros((N, N), bool)
+    a_r[10, 10] = True
+    for pix, want in [(((10, 13), (10, 7)), (0, -3)),   # equal |s|: smaller dx
+                      (((13, 10), (10, 7)), (0, -3)),   # equal |s|: smaller dy first
+                      (((12, 10), (10, 7)), (2, 0))]:   # smaller |dy| + |dx|
+        a_m = np.zeros((N, N), bool)
+        for y, x in pix:
+            a_m[y, x] = True
+        res = xcorr.align(a_m, a_r, w, 1, 2)
+        assert res["s"] == want and res["c"] == 1
+
+
+def test_xcorr_mirror_and_dominance():
+    """c of (member, rep) at s equals c of (rep, member) at -s; the chosen
+    overlap is never below the one phase correlation picks (same window)."""
+    rng = np.random.default_rng(4)
+    N, w = 32, 6
+    for _ in range(4):
+        a = rand_clip(rng, N, k=6)
+        b = rand_clip(rng, N, k=6)
+        s1, c1 = xcorr.overlap_surface(a, b, w)
+        s2, c2 = xcorr.overlap_surface(b, a, w)
+        m2 = {(int(dy), int(dx)): int(c) for (dy, dx), c in zip(s2, c2)}
+        assert all(m2[(-int(dy), -int(dx))] == int(c) for (dy, dx), c in zip(s1, c1))
+        if a.any() and b.any():
+            pcm = cosine.align(a, b, cosine.whiten(cosine.spectrum(a)), cosine.whiten(cosine.spectrum(b)), w, 1, 2)
+            assert xcorr.align(a, b, w, 1, 2)["c"] >= pcm["c"]
