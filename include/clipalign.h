@@ -98,8 +98,19 @@ typedef struct {
  *     every applicable path is timed, a path is admitted only if its results
  *     equal CA_PATH_FP64's bit for bit, and the fastest admitted one is kept
  *     (see ca_autotune_*).  Results return in the caller's order.
- * All of them return identical shifts, counts, scores and bits. */
-enum { CA_PATH_MIXED = 0, CA_PATH_FP32 = 1, CA_PATH_FP64 = 2, CA_PATH_AUTO = 3, CA_PATH_DIRECT = 4 };
+ * All of them return identical shifts, counts, scores and bits.
+ *   CA_PATH_XCORR: a different objective, the one Sec. 3.2 states for
+ *     alignment: per direction, the shift of the member's window with the
+ *     largest overlap count c(s) = sum_x a_rep(x) a_mem((x + s) mod N), ties to
+ *     the smaller |dy| + |dx|, then the smaller (dy, dx); score and bit of
+ *     Eq. 2 there; empty clips as on the other paths.  Integer bit counts on
+ *     the vector ALUs, one workgroup per pair, so the result is exact.  It can
+ *     differ from the phase-correlation paths (their peak is the objective's
+ *     maximiser only for pure translations); the count it returns is never
+ *     smaller.  Rasters of 64 or 128 and half-windows <= 16 (CA_EUNSUPPORTED
+ *     otherwise); CA_PATH_AUTO never selects it. */
+enum { CA_PATH_MIXED = 0, CA_PATH_FP32 = 1, CA_PATH_FP64 = 2, CA_PATH_AUTO = 3, CA_PATH_DIRECT = 4,
+       CA_PATH_XCORR = 5 };
 
 /* Per-pair flag bits written by the alignment calls. */
 enum {

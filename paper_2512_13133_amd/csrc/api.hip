@@ -670,6 +670,21 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
     ctx->stats.pairs_aligned += n;
     return CA_OK;
   }
+  if (path == CA_PATH_XCORR) {
+    if (maxN > 128 || Lmax > 33)
+      return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_XCORR needs rasters of 64 or 128 and half-windows <= 16");
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
+    for (int N : {64, 128})
+      if (std::min(crs->minN, cms->minN) <= N && N <= maxN) HIP_OR_FAIL(ctx, launch_xcorr(cr, cm, io, N, thr, s));
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
+    HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->stats.t_main_ms += ms;
+    ctx->stats.n_main_launch += 1;
+    ctx->stats.pairs_aligned += n;
+    return CA_OK;
+  }
   if (path == CA_PATH_FP32 && (!cr.spec32 || !cm.spec32))
     return fail(ctx, CA_ESTATE, "CA_PATH_FP32 needs a clip set created with CA_CLIPS_FP32");
   if (path == CA_PATH_MIXED && !checked && (!crs->mixed_ok || !cms->mixed_ok))
@@ -746,7 +761,7 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
   if (!rep || !mem || !bits || !shift || !count || !score || !flags)
     return fail(ctx, CA_EINVAL, "null output or pair pointer");
   if (n_pairs > (1ll << 31) - 1) return fail(ctx, CA_EINVAL, "pair list longer than 2^31 - 1");
-  if (path < CA_PATH_MIXED || path > CA_PATH_DIRECT) return fail(ctx, CA_EINVAL, "bad path");
+  if (path < CA_PATH_MIXED || path > CA_PATH_XCORR) return fail(ctx, CA_EINVAL, "bad path");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE);

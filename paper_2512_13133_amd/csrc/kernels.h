@@ -74,6 +74,11 @@ hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, con
                                      const CandQueue& cq, const CandQueue& exact, const double2* tw256,
                                      unsigned long long* peak_err_bits, unsigned long long* peak_ratio_bits,
                                      const float* r1_low, hipStream_t s);
+// Exact-objective alignment: per pair the window shift of the largest overlap
+// count (tie rule as in the re-decision), both directions; rasters of 64 or
+// 128 (pairs of the other size are skipped), half-windows <= 16.
+hipError_t launch_xcorr(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, int N, Threshold thr,
+                        hipStream_t s);
 // Cosine candidate generation for 128 x 128 clips with half-windows <= 16:
 // write = false runs the bounds pass (bitmask + counts), write = true the
 // ordered write of the survivors (needs pa.offs).
