@@ -220,6 +220,29 @@ __device__ bool overlap11(const uint16_t* rs_m, const uint16_t* rs_r, const uint
   return __ballot(hit) != 0ull;
 }
 
+// One row of the same test, on one lane: row y of the representative against
+// row y + dy of the member shifted by dx (pigeonhole bound, then bit rows).
+__device__ __forceinline__ bool overlap_row(const uint16_t* rs_m, const uint16_t* rs_r, const uint64_t* b_m,
+                                            const uint64_t* b_r, int N, int dy, int dx, int y) {
+  if ((int)rs_r[y] + (int)rs_m[y + dy] > N + abs(dx)) return true;
+  const int wpr = N >> 6;
+  const uint64_t* rr = b_r + y * wpr;
+  const uint64_t* mr = b_m + (y + dy) * wpr;
+  bool hit = false;
+  for (int k = 0; k < wpr; ++k) hit |= (rr[k] & row_bits_linear(mr, wpr, 64 * k + dx)) != 0ull;
+  return hit;
+}
+
+// Quick per-lane proof of overlap from the middle row of the rows the shift
+// keeps (for two single polygons whose boxes are centred on each other at T0
+// it almost always overlaps); false means "not proven", not "no overlap".
+__device__ __forceinline__ bool overlap11_quick(const uint16_t* rs_m, const uint16_t* rs_r, const uint64_t* b_m,
+                                                const uint64_t* b_r, int N, int dy, int dx) {
+  const int y0 = max(0, -dy), y1 = min(N, N - dy);
+  if (y0 >= y1 || dx >= N || dx <= -N) return false;
+  return overlap_row(rs_m, rs_r, b_m, b_r, N, dy, dx, (y0 + y1) >> 1);
+}
+
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)v >> 32), l);
@@ -346,19 +369,35 @@ __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, 
       a_b_i = (int64_t)(cs.bits + cs.bits_off[i]);
       a_b_j = (int64_t)(cs.bits + cs.bits_off[j]);
     }
-    unsigned long long hit0 = 0ull, hit1 = 0ull;
-    for (unsigned long long m = __ballot(single); m; m &= m - 1ull) {
+    // each lane first tries its own pair's middle row; the wave-wide test of
+    // all rows runs only for the directions that row does not settle
+    bool q0 = false, q1 = false;
+    if (single) {
+      const uint16_t* rs_i = (const uint16_t*)a_rs_i;
+      const uint16_t* rs_j = (const uint16_t*)a_rs_j;
+      const uint64_t* b_i = (const uint64_t*)a_b_i;
+      const uint64_t* b_j = (const uint64_t*)a_b_j;
+      q0 = overlap11_quick(rs_i, rs_j, b_i, b_j, N, T0y[0], T0x[0]);
+      if (!mirror) q1 = overlap11_quick(rs_j, rs_i, b_j, b_i, N, T0y[1], T0x[1]);
+    }
+    unsigned long long hit0 = __ballot(q0), hit1 = __ballot(q1);
+    for (unsigned long long m = __ballot(single && !q0); m; m &= m - 1ull) {
       const int t = __ffsll(m) - 1;
       const uint16_t* rs_i = (const uint16_t*)readlane64(a_rs_i, t);
       const uint16_t* rs_j = (const uint16_t*)readlane64(a_rs_j, t);
       const uint64_t* b_i = (const uint64_t*)readlane64(a_b_i, t);
       const uint64_t* b_j = (const uint64_t*)readlane64(a_b_j, t);
-      const int Nt = __builtin_amdgcn_readlane(N, t);
-      if (overlap11(rs_i, rs_j, b_i, b_j, Nt, __builtin_amdgcn_readlane(T0y[0], t),
+      if (overlap11(rs_i, rs_j, b_i, b_j, __builtin_amdgcn_readlane(N, t), __builtin_amdgcn_readlane(T0y[0], t),
                     __builtin_amdgcn_readlane(T0x[0], t), lane))
         hit0 |= 1ull << t;
-      if (!__builtin_amdgcn_readlane((int)mirror, t) &&
-          overlap11(rs_j, rs_i, b_j, b_i, Nt, __builtin_amdgcn_readlane(T0y[1], t),
+    }
+    for (unsigned long long m = __ballot(single && !mirror && !q1); m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const uint16_t* rs_i = (const uint16_t*)readlane64(a_rs_i, t);
+      const uint16_t* rs_j = (const uint16_t*)readlane64(a_rs_j, t);
+      const uint64_t* b_i = (const uint64_t*)readlane64(a_b_i, t);
+      const uint64_t* b_j = (const uint64_t*)readlane64(a_b_j, t);
+      if (overlap11(rs_j, rs_i, b_j, b_i, __builtin_amdgcn_readlane(N, t), __builtin_amdgcn_readlane(T0y[1], t),
                     __builtin_amdgcn_readlane(T0x[1], t), lane))
         hit1 |= 1ull << t;
     }
