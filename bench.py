@@ -294,7 +294,7 @@ def serve_bench(ctx, n_library, seconds, slots=4):
         size = int(np.clip(np.rint(rng.lognormal(np.log(64), 1.0)), 1, 10_000))
         return clipgen.make_clips(rng, tpl, 128, size, 4, 16)
 
-    hlib = ctx.clips(lib)
+    hlib = ctx.clips(lib, fp32=True)
     srv = ca.Server(ctx, hlib, (19, 20), slots=slots, hbm_budget_bytes=64 << 30)
     log(f"[serve] library {lib.n} ready in {time.time() - t0:.1f}s")
 

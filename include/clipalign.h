@@ -338,7 +338,9 @@ ca_status ca_cluster(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_c
  * pattern is aligned to fixed representatives and accepted under the strict
  * threshold, Eqs. 2-5) to request batches that arrive over time.
  *   library: a clip set on ctx (128 x 128 clips, half-windows <= 16) holding
- *     the representatives; it must outlive the server.
+ *     the representatives; it must outlive the server.  If it was created
+ *     with CA_CLIPS_FP32, request batches get FP32 spectra too and the
+ *     exact re-decision of near-tied peaks runs behind the FP32 screen.
  *   con: the cosine constraint (CA_EUNSUPPORTED for the edge track).
  *   slots: 1..32 concurrent requests; each slot has its own HIP stream and
  *     worker thread, so requests on different slots overlap on the device.

@@ -735,8 +735,9 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
 
 namespace capriv {
 ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr, const int32_t* rects,
-                          const int16_t* raster_n, const int16_t* marker_w, DevArena* arena, ca_clipset** out) {
-  return clips_create_impl(ctx, stream, n, rect_ptr, rects, raster_n, marker_w, 0, arena, out);
+                          const int16_t* raster_n, const int16_t* marker_w, uint32_t flags, DevArena* arena,
+                          ca_clipset** out) {
+  return clips_create_impl(ctx, stream, n, rect_ptr, rects, raster_n, marker_w, flags, arena, out);
 }
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
                             Threshold thr, int path, const PairIO& io, bool checked, int direct_n) {

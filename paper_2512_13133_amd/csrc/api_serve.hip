@@ -45,7 +45,9 @@ ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset
                             ca::Threshold thr, int path, const ca::PairIO& io, bool checked = false,
                             int direct_n = 0);
 ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr, const int32_t* rects,
-                          const int16_t* raster_n, const int16_t* marker_w, DevArena* arena, ca_clipset** out);
+                          const int16_t* raster_n, const int16_t* marker_w, uint32_t flags, DevArena* arena,
+                          ca_clipset** out);
+bool has_fp32_of(const ca_clipset* cs);
 }  // namespace capriv
 
 using namespace ca;
@@ -71,9 +73,12 @@ struct Request {
 };
 
 // Per-request device footprint estimate: the batch clip set (bits, tables,
-// runs, FP16 + FP64 spectra at 128 x 128) and up to 4096 candidates per clip
-// with their outputs and prune scratch.  It also sizes the slot's arena.
-uint64_t estimate_bytes(int64_t n) { return (uint64_t)n * (200000ull + 4096ull * 64ull) + (1ull << 20); }
+// runs, FP16 + FP64 spectra at 128 x 128, FP32 spectra too when the library
+// keeps them) and up to 4096 candidates per clip with their outputs and prune
+// scratch.  It also sizes the slot's arena.
+uint64_t estimate_bytes(int64_t n, bool fp32) {
+  return (uint64_t)n * (200000ull + (fp32 ? 70000ull : 0ull) + 4096ull * 64ull) + (1ull << 20);
+}
 
 }  // namespace
 
@@ -161,7 +166,8 @@ void run_request(ca_server* srv, int slot, Request* req) {
     arena.used = 0;
   }
   req->status = clips_create_in(ctx, s, n, req->rect_ptr.data(), req->rects.empty() ? nullptr : req->rects.data(),
-                                req->raster_n.data(), req->marker_w.data(), &arena, &rc);
+                                req->raster_n.data(), req->marker_w.data(),
+                                has_fp32_of(srv->lib) ? CA_CLIPS_FP32 : 0u, &arena, &rc);
   if (req->status != CA_OK) {
     req->error = ca_last_error(ctx);
     goto cleanup;
@@ -209,7 +215,21 @@ void run_request(ca_server* srv, int slot, Request* req) {
     RUN_HIP(hipMemcpyAsync(d_hi, hi.data(), 4 * n, hipMemcpyHostToDevice, s));
     RUN_HIP(hipMemcpyAsync(d_roff, roff.data(), 8 * n, hipMemcpyHostToDevice, s));
     RUN_HIP(hipMemsetAsync(d_mask, 0, b_m, s));
-    PruneArgs pa{srv->d_order, d_hi, n, d_cnt, nullptr, nullptr, nullptr, d_anchor, d_lo, 1};
+    RUN_HIP(hipMemsetAsync(d_cnt, 0, 8 * n, s));
+    // pairs are written as (batch clip, library clip): each batch clip's
+    // candidates are consecutive, so the alignment kernel stages that clip once
+    // as the fixed side and streams the library clips; direction 1 of a pair
+    // is then the batch clip aligned to the library representative
+    PruneArgs pa{srv->d_order, d_hi, n, d_cnt, nullptr, nullptr, nullptr, d_anchor, d_lo};
+    // a batch has few anchors and each a long library range: split the ranges
+    // into segments of 64-partner chunks, about 2048 segments in all
+    {
+      int64_t longest = 0;
+      for (int64_t i = 0; i < n; ++i) longest = std::max<int64_t>(longest, (int64_t)hi[i] - lo[i]);
+      const int64_t seg = std::min<int64_t>(4096, std::max<int64_t>(64, (bits / 2048 + 63) / 64 * 64));
+      pa.seg = (int)seg;
+      pa.n_seg = (int)std::max<int64_t>(1, (longest + seg - 1) / seg);
+    }
     const Threshold thr{p, q};
     RUN_HIP(launch_prune128(dev_of(rc), dev_of(srv->lib), pa, thr, d_roff, d_mask, false, s));
     RUN_HIP(hipMemcpyAsync(cnt.data(), d_cnt, 8 * n, hipMemcpyDeviceToHost, s));
@@ -235,13 +255,15 @@ void run_request(ca_server* srv, int slot, Request* req) {
       RUN_HIP(hipMemcpyAsync(d_off, off.data(), 8 * n, hipMemcpyHostToDevice, s));
       PruneArgs pw = pa;
       pw.counts = nullptr;
+      pw.seg = 0;
+      pw.n_seg = 1;
       pw.offs = d_off;
       pw.out_rep = d_rep;
       pw.out_mem = d_mem;
       hipError_t e = launch_prune128(dev_of(rc), dev_of(srv->lib), pw, thr, d_roff, d_mask, true, s);
       if (e == hipSuccess) {
         PairIO io{total, d_rep, d_mem, d_bits, d_shift, d_count, d_score, d_flags};
-        req->status = align_cosine_sets(ctx, srv->lib, rc, s, thr, CA_PATH_MIXED, io);
+        req->status = align_cosine_sets(ctx, rc, srv->lib, s, thr, CA_PATH_MIXED, io);
         if (req->status != CA_OK) req->error = ca_last_error(ctx);
       } else {
         req->status = CA_EDEVICE;
@@ -264,21 +286,22 @@ void run_request(ca_server* srv, int slot, Request* req) {
       if (req->status != CA_OK) goto cleanup;
     }
   }
-  // best covering representative per batch clip (direction 0: rep covers member)
+  // best covering representative per batch clip: pair k = (batch clip h_rep[k],
+  // library clip h_mem[k]); direction 1 aligns the batch clip to the library clip
   req->best_rep.assign(n, -1);
   req->shift.assign(2 * n, 0);
   req->score.assign(n, 0.0);
   req->matched.assign(n, 0);
   for (int64_t k = 0; k < total; ++k) {
-    if (!(h_bits[k] & 1)) continue;
-    const int32_t i = h_mem[k], r = h_rep[k];
-    const double sc = h_score[2 * k];
+    if (!(h_bits[k] & 2)) continue;
+    const int32_t i = h_rep[k], r = h_mem[k];
+    const double sc = h_score[2 * k + 1];
     if (!req->matched[i] || sc > req->score[i] || (sc == req->score[i] && r < req->best_rep[i])) {
       req->matched[i] = 1;
       req->best_rep[i] = r;
       req->score[i] = sc;
-      req->shift[2 * i] = h_shift[4 * k];
-      req->shift[2 * i + 1] = h_shift[4 * k + 1];
+      req->shift[2 * i] = h_shift[4 * k + 2];
+      req->shift[2 * i + 1] = h_shift[4 * k + 3];
     }
   }
 cleanup:
@@ -396,7 +419,7 @@ extern "C" ca_status ca_server_submit(ca_server* srv, int64_t n, const int64_t* 
   if (rect_ptr[n] > 0 && !rects) return srv_fail(srv, CA_EINVAL, "null rects");
   Request* req = new Request();
   req->n = n;
-  req->est_bytes = estimate_bytes(n);
+  req->est_bytes = estimate_bytes(n, has_fp32_of(srv->lib));
   {
     std::lock_guard<std::mutex> g(srv->mu);
     if (srv->budget && srv->inflight + req->est_bytes > srv->budget) {

@@ -17,6 +17,9 @@
 //                  sums held even- and odd-aligned in registers).  Survivors
 //                  of the coarse stage are queued in LDS so the exact stage
 //                  always runs on full waves.
+// When anchors are few (a request batch against a large library), each
+// anchor's range is split over several workgroups (grid y) that add their
+// survivor counts atomically, so the chip still fills.
 // Pass flags go to a bitmask over each anchor's partner range; a second
 // kernel writes the surviving pairs in (anchor order, partner order).
 // Anchors come from the clip set `ca` and partners from `cb` (the same set
@@ -103,7 +106,13 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
   const int wa = ca.w[ia];
   const int64_t so_a = ca.sig_off[ia];
   const int64_t start = pa.lo ? (int64_t)pa.lo[a] : a + 1;
-  const int64_t end = pa.hi[a];
+  int64_t end = pa.hi[a];
+  int64_t first = start;
+  if (pa.seg > 0) {  // this workgroup's segment of the range (uniform exit)
+    first = start + (int64_t)blockIdx.y * pa.seg;
+    end = min(end, first + (int64_t)pa.seg);
+    if (first >= end) return;
+  }
   const int64_t roff = range_off[a];
   if (lane == 0) qlen = 0;
   __syncthreads();
@@ -141,7 +150,7 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
     found += __popcll(__ballot(ok));
   };
 
-  for (int64_t b0 = start; b0 < end; b0 += 64) {
+  for (int64_t b0 = first; b0 < end; b0 += 64) {
     const int64_t b = b0 + lane;
     const bool valid = b < end;
     const int ib = valid ? pa.order[b] : pa.order[start];
@@ -182,7 +191,10 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
     }
   }
   if (qlen > 0) exact_flush(qlen);
-  if (lane == 0) pa.counts[a] = found;
+  if (lane == 0) {
+    if (pa.seg == 0) pa.counts[a] = found;
+    else if (found > 0) atomicAdd(reinterpret_cast<unsigned long long*>(pa.counts + a), (unsigned long long)found);
+  }
 }
 
 // Ordered write of the surviving pairs of each anchor from the bitmask.
@@ -210,8 +222,8 @@ __global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const 
         pa.out_rep[dst] = min(ia, ib);
         pa.out_mem[dst] = max(ia, ib);
       } else {
-        pa.out_rep[dst] = pa.partner_is_rep ? ib : ia;
-        pa.out_mem[dst] = pa.partner_is_rep ? ia : ib;
+        pa.out_rep[dst] = ia;
+        pa.out_mem[dst] = ib;
       }
     }
     o += __popcll(bm);
@@ -225,7 +237,8 @@ hipError_t launch_prune128(const ClipsDev& ca, const ClipsDev& cb, const PruneAr
     if (write)
       hipLaunchKernelGGL(prune128_write_kernel, dim3(nb), dim3(64), 0, s, pa, range_off, (const uint32_t*)mask, b0);
     else
-      hipLaunchKernelGGL(prune128_bounds_kernel, dim3(nb), dim3(64), 0, s, ca, cb, pa, thr, range_off, mask, b0);
+      hipLaunchKernelGGL(prune128_bounds_kernel, dim3(nb, pa.seg > 0 ? pa.n_seg : 1), dim3(64), 0, s, ca, cb, pa,
+                         thr, range_off, mask, b0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
