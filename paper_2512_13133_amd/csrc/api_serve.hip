@@ -148,12 +148,13 @@ void run_request(ca_server* srv, int slot, Request* req) {
   const int64_t n = req->n;
   const int64_t p = srv->con.thr_num, q = srv->con.thr_den;
   std::vector<int32_t> lo(n), hi(n), anchors(n);
-  std::vector<int64_t> roff(n), cnt(n), off(n);
+  std::vector<int64_t> roff(n), cnt, off;
   int64_t bits = 0, total = 0;
-  std::vector<int32_t> h_rep, h_mem;
-  std::vector<uint8_t> h_bits;
-  std::vector<int16_t> h_shift;
-  std::vector<double> h_score;
+  std::vector<char> h_out;  // the pairs' result arrays, as laid out on the device
+  const int32_t *h_rep = nullptr, *h_mem = nullptr;
+  const uint8_t* h_bits = nullptr;
+  const int16_t* h_shift = nullptr;
+  const double* h_score = nullptr;
   // grow the slot's arena (only when a larger request than any before arrives)
   {
     const size_t want = (size_t)req->est_bytes;
@@ -199,42 +200,47 @@ void run_request(ca_server* srv, int slot, Request* req) {
     }
   }
   {
-    const size_t b_a = al(4 * (size_t)n), b_r = al(8 * (size_t)n), b_m = al(4 * (size_t)(bits / 32 + 1));
-    const size_t bytes = 3 * b_a + 3 * b_r + b_m;
-    RUN_HIP(slot_alloc(arena, &buf, bytes, extra));
+    // a batch has few anchors and each a long library range: split the ranges
+    // into segments of 64-partner chunks, about 2048 segments in all; counts
+    // and write offsets are kept per (anchor, segment)
+    int64_t longest = 0;
+    for (int64_t i = 0; i < n; ++i) longest = std::max<int64_t>(longest, (int64_t)hi[i] - lo[i]);
+    const int64_t seg = std::min<int64_t>(4096, std::max<int64_t>(64, (bits / 2048 + 63) / 64 * 64));
+    const int64_t n_seg = std::max<int64_t>(1, (longest + seg - 1) / seg);
+    const int64_t ns = n * n_seg;
+    const size_t b_a = al(4 * (size_t)n), b_r = al(8 * (size_t)n), b_s = al(8 * (size_t)ns),
+                 b_m = al(4 * (size_t)(bits / 32 + 1));
+    RUN_HIP(slot_alloc(arena, &buf, 3 * b_a + b_r + 2 * b_s + b_m, extra));
+    // the four range tables go over in one copy, laid out as on the device
+    std::vector<char> stage(3 * b_a + b_r);
+    std::memcpy(stage.data(), anchors.data(), 4 * n);
+    std::memcpy(stage.data() + b_a, lo.data(), 4 * n);
+    std::memcpy(stage.data() + 2 * b_a, hi.data(), 4 * n);
+    std::memcpy(stage.data() + 3 * b_a, roff.data(), 8 * n);
     char* c = (char*)buf;
     int32_t* d_anchor = (int32_t*)c; c += b_a;
     int32_t* d_lo = (int32_t*)c; c += b_a;
     int32_t* d_hi = (int32_t*)c; c += b_a;
     int64_t* d_roff = (int64_t*)c; c += b_r;
-    int64_t* d_cnt = (int64_t*)c; c += b_r;
-    int64_t* d_off = (int64_t*)c; c += b_r;
+    int64_t* d_cnt = (int64_t*)c; c += b_s;
+    int64_t* d_off = (int64_t*)c; c += b_s;
     uint32_t* d_mask = (uint32_t*)c;
-    RUN_HIP(hipMemcpyAsync(d_anchor, anchors.data(), 4 * n, hipMemcpyHostToDevice, s));
-    RUN_HIP(hipMemcpyAsync(d_lo, lo.data(), 4 * n, hipMemcpyHostToDevice, s));
-    RUN_HIP(hipMemcpyAsync(d_hi, hi.data(), 4 * n, hipMemcpyHostToDevice, s));
-    RUN_HIP(hipMemcpyAsync(d_roff, roff.data(), 8 * n, hipMemcpyHostToDevice, s));
+    RUN_HIP(hipMemcpyAsync(buf, stage.data(), stage.size(), hipMemcpyHostToDevice, s));
     RUN_HIP(hipMemsetAsync(d_mask, 0, b_m, s));
-    RUN_HIP(hipMemsetAsync(d_cnt, 0, 8 * n, s));
     // pairs are written as (batch clip, library clip): each batch clip's
     // candidates are consecutive, so the alignment kernel stages that clip once
     // as the fixed side and streams the library clips; direction 1 of a pair
     // is then the batch clip aligned to the library representative
     PruneArgs pa{srv->d_order, d_hi, n, d_cnt, nullptr, nullptr, nullptr, d_anchor, d_lo};
-    // a batch has few anchors and each a long library range: split the ranges
-    // into segments of 64-partner chunks, about 2048 segments in all
-    {
-      int64_t longest = 0;
-      for (int64_t i = 0; i < n; ++i) longest = std::max<int64_t>(longest, (int64_t)hi[i] - lo[i]);
-      const int64_t seg = std::min<int64_t>(4096, std::max<int64_t>(64, (bits / 2048 + 63) / 64 * 64));
-      pa.seg = (int)seg;
-      pa.n_seg = (int)std::max<int64_t>(1, (longest + seg - 1) / seg);
-    }
+    pa.seg = (int)seg;
+    pa.n_seg = (int)n_seg;
     const Threshold thr{p, q};
     RUN_HIP(launch_prune128(dev_of(rc), dev_of(srv->lib), pa, thr, d_roff, d_mask, false, s));
-    RUN_HIP(hipMemcpyAsync(cnt.data(), d_cnt, 8 * n, hipMemcpyDeviceToHost, s));
+    cnt.resize(ns);
+    off.resize(ns);
+    RUN_HIP(hipMemcpyAsync(cnt.data(), d_cnt, 8 * ns, hipMemcpyDeviceToHost, s));
     RUN_HIP(hipStreamSynchronize(s));
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < ns; ++i) {
       off[i] = total;
       total += cnt[i];
     }
@@ -252,11 +258,9 @@ void run_request(ca_server* srv, int slot, Request* req) {
       int32_t* d_count = (int32_t*)o; o += o8;
       double* d_score = (double*)o; o += o16;
       uint32_t* d_flags = (uint32_t*)o;
-      RUN_HIP(hipMemcpyAsync(d_off, off.data(), 8 * n, hipMemcpyHostToDevice, s));
+      RUN_HIP(hipMemcpyAsync(d_off, off.data(), 8 * ns, hipMemcpyHostToDevice, s));
       PruneArgs pw = pa;
       pw.counts = nullptr;
-      pw.seg = 0;
-      pw.n_seg = 1;
       pw.offs = d_off;
       pw.out_rep = d_rep;
       pw.out_mem = d_mem;
@@ -270,18 +274,19 @@ void run_request(ca_server* srv, int slot, Request* req) {
         req->error = hipGetErrorString(e);
       }
       if (req->status == CA_OK) {
-        h_rep.resize(total); h_mem.resize(total); h_bits.resize(total); h_shift.resize(4 * total);
-        h_score.resize(2 * total);
-        hipError_t e1 = hipMemcpyAsync(h_rep.data(), d_rep, 4 * total, hipMemcpyDeviceToHost, s);
-        if (e1 == hipSuccess) e1 = hipMemcpyAsync(h_mem.data(), d_mem, 4 * total, hipMemcpyDeviceToHost, s);
-        if (e1 == hipSuccess) e1 = hipMemcpyAsync(h_bits.data(), d_bits, total, hipMemcpyDeviceToHost, s);
-        if (e1 == hipSuccess) e1 = hipMemcpyAsync(h_shift.data(), d_shift, 8 * total, hipMemcpyDeviceToHost, s);
-        if (e1 == hipSuccess) e1 = hipMemcpyAsync(h_score.data(), d_score, 16 * total, hipMemcpyDeviceToHost, s);
+        // the result arrays (rep .. score) are contiguous: one copy back
+        h_out.resize(2 * o4 + o1 + 2 * o8 + o16);
+        hipError_t e1 = hipMemcpyAsync(h_out.data(), out, h_out.size(), hipMemcpyDeviceToHost, s);
         if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
         if (e1 != hipSuccess) {
           req->status = CA_EDEVICE;
           req->error = hipGetErrorString(e1);
         }
+        h_rep = (const int32_t*)h_out.data();
+        h_mem = (const int32_t*)(h_out.data() + o4);
+        h_bits = (const uint8_t*)(h_out.data() + 2 * o4);
+        h_shift = (const int16_t*)(h_out.data() + 2 * o4 + o1);
+        h_score = (const double*)(h_out.data() + 2 * o4 + o1 + 2 * o8);
       }
       if (req->status != CA_OK) goto cleanup;
     }

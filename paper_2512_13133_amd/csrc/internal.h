@@ -110,8 +110,8 @@ struct PruneArgs {
   const int32_t* anchor_ids = nullptr;  // [n_anchor] anchor clip ids (null: order[a])
   const int32_t* lo = nullptr;          // [n_anchor] start of each range in `order` (null: a + 1)
   int order_ids = 0;                    // write each pair as (smaller id, larger id)
-  int seg = 0;      // bounds pass: partners per workgroup (0: one workgroup per anchor range;
-                    // > 0: n_seg workgroups per anchor add into counts, which start at zero)
+  int seg = 0;      // partners per workgroup (0: one workgroup per anchor range; > 0: n_seg
+                    // segments per anchor, counts and offs indexed [a * n_seg + segment])
   int n_seg = 1;
 };
 

@@ -18,8 +18,8 @@
 //                  of the coarse stage are queued in LDS so the exact stage
 //                  always runs on full waves.
 // When anchors are few (a request batch against a large library), each
-// anchor's range is split over several workgroups (grid y) that add their
-// survivor counts atomically, so the chip still fills.
+// anchor's range is split into segments (grid y) so the chip still fills;
+// both passes then count and write per (anchor, segment).
 // Pass flags go to a bitmask over each anchor's partner range; a second
 // kernel writes the surviving pairs in (anchor order, partner order).
 // Anchors come from the clip set `ca` and partners from `cb` (the same set
@@ -111,7 +111,10 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
   if (pa.seg > 0) {  // this workgroup's segment of the range (uniform exit)
     first = start + (int64_t)blockIdx.y * pa.seg;
     end = min(end, first + (int64_t)pa.seg);
-    if (first >= end) return;
+    if (first >= end) {
+      if (threadIdx.x == 0) pa.counts[a * pa.n_seg + blockIdx.y] = 0;
+      return;
+    }
   }
   const int64_t roff = range_off[a];
   if (lane == 0) qlen = 0;
@@ -191,10 +194,7 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
     }
   }
   if (qlen > 0) exact_flush(qlen);
-  if (lane == 0) {
-    if (pa.seg == 0) pa.counts[a] = found;
-    else if (found > 0) atomicAdd(reinterpret_cast<unsigned long long*>(pa.counts + a), (unsigned long long)found);
-  }
+  if (lane == 0) pa.counts[pa.seg > 0 ? a * pa.n_seg + blockIdx.y : a] = found;
 }
 
 // Ordered write of the surviving pairs of each anchor from the bitmask.
@@ -204,10 +204,16 @@ __global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const 
   const int lane = threadIdx.x;
   const int ia = pa.anchor_ids ? pa.anchor_ids[a] : pa.order[a];
   const int64_t start = pa.lo ? (int64_t)pa.lo[a] : a + 1;
-  const int64_t len = pa.hi[a] - start;
+  int64_t len = pa.hi[a] - start;
+  int64_t p_first = 0;
+  if (pa.seg > 0) {  // this workgroup's segment (uniform exit)
+    p_first = (int64_t)blockIdx.y * pa.seg;
+    len = min(len, p_first + (int64_t)pa.seg);
+    if (p_first >= len) return;
+  }
   const int64_t roff = range_off[a];
-  int64_t o = pa.offs[a];
-  for (int64_t p0 = 0; p0 < len; p0 += 64) {
+  int64_t o = pa.offs[pa.seg > 0 ? a * pa.n_seg + blockIdx.y : a];
+  for (int64_t p0 = p_first; p0 < len; p0 += 64) {
     const int64_t p = p0 + lane;
     bool on = false;
     if (p < len) {
@@ -234,11 +240,11 @@ hipError_t launch_prune128(const ClipsDev& ca, const ClipsDev& cb, const PruneAr
                            const int64_t* range_off, uint32_t* mask, bool write, hipStream_t s) {
   for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
+    const dim3 grid(nb, pa.seg > 0 ? pa.n_seg : 1);
     if (write)
-      hipLaunchKernelGGL(prune128_write_kernel, dim3(nb), dim3(64), 0, s, pa, range_off, (const uint32_t*)mask, b0);
+      hipLaunchKernelGGL(prune128_write_kernel, grid, dim3(64), 0, s, pa, range_off, (const uint32_t*)mask, b0);
     else
-      hipLaunchKernelGGL(prune128_bounds_kernel, dim3(nb, pa.seg > 0 ? pa.n_seg : 1), dim3(64), 0, s, ca, cb, pa,
-                         thr, range_off, mask, b0);
+      hipLaunchKernelGGL(prune128_bounds_kernel, grid, dim3(64), 0, s, ca, cb, pa, thr, range_off, mask, b0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
