@@ -210,7 +210,7 @@ def main():
                               "frac": round(ops / (xms * 1e-3) / 1e12 / INT_PEAK_TOPS, 4),
                               "ops_per_pair": 33 * 33 * 128 * 4 * 2}}
         del ox
-    stats_out = {k: st[k] for k in ("pairs_rescored", "groups_exact", "max_surface_err", "max_peak_err_sqrt", "tie_band_mixed", "pairs_screened",
+    stats_out = {k: st[k] for k in ("pairs_rescored", "pairs_full_fp64", "groups_exact", "max_surface_err", "max_peak_err_sqrt", "tie_band_mixed", "pairs_screened",
                                     "pairs_survived")}
     stage_ms = {k: round(v * 1000.0 / args.steps, 2) for k, v in stage_t.items()}
 

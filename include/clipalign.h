@@ -144,6 +144,8 @@ typedef struct {
                                  of K r divided by sqrt(K_hi); stays below tie_band_mixed / 2 */
   int64_t groups_exact;       /* candidate groups the FP32 screen (clip sets with CA_CLIPS_FP32)
                                  left to the FP64 re-decision; without FP32 spectra, all groups */
+  int64_t pairs_full_fp64;    /* of pairs_rescored, pairs whose whole window was re-evaluated in
+                                 FP64 (their near-tied candidates overflowed the candidate list) */
 } ca_run_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -59,7 +59,8 @@ class _Stats(C.Structure):
                 ("n_main_launch", C.c_int64), ("t_main_ms", C.c_double), ("main_alg_bytes", C.c_double),
                 ("max_surface_err", C.c_double), ("tie_band_mixed", C.c_double),
                 ("tie_band_fp32", C.c_double), ("tie_band_direct", C.c_double),
-                ("max_peak_err_sqrt", C.c_double), ("groups_exact", C.c_int64)]
+                ("max_peak_err_sqrt", C.c_double), ("groups_exact", C.c_int64),
+                ("pairs_full_fp64", C.c_int64)]
 
 
 _LIB = None

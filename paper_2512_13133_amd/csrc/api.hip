@@ -730,6 +730,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   ctx->stats.pairs_aligned += n;
   ctx->stats.pairs_rescored += n_groups + (int64_t)h[0];
   ctx->stats.groups_exact += (cr.spec32 && cm.spec32) ? (int64_t)h[8] : n_groups;
+  ctx->stats.pairs_full_fp64 += (int64_t)h[0];
   return CA_OK;
 }
 

@@ -61,6 +61,13 @@ __device__ __forceinline__ int row_overlap(const uint64_t* rep, const uint64_t* 
   return c;
 }
 
+// c(s) = sum_x rep(x) mem((x + s) mod N) on one thread (all rows).
+__device__ __forceinline__ int thread_overlap(const uint64_t* rep, const uint64_t* mem, int N, int dy, int dx) {
+  int c = 0;
+  for (int y = 0; y < N; ++y) c += row_overlap(rep, mem, N, y, dy, dx);
+  return c;
+}
+
 // Block-wide c(s) = sum_x rep(x) mem((x + s) mod N).  All threads must call;
 // `red` is a block-sized int scratch in LDS.  Returns the count on every thread.
 __device__ __forceinline__ int block_overlap(const uint64_t* rep, const uint64_t* mem, int N, int dy,

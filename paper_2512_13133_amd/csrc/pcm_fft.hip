@@ -33,7 +33,7 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
   __shared__ T vred1[256];
   __shared__ T vred2[256];
   __shared__ int idxred[256];
-  __shared__ int candf[256];
+  __shared__ uint64_t keyred[256];
 
   // grid-stride over the pairs (or listed pairs); the count comes from the
   // host, or from device memory (capped by n_blocks) when n_dev is given
@@ -257,23 +257,23 @@ pcm_fft_kernel(ClipsDev cr, ClipsDev cm, PairIO io, const int64_t* __restrict__ 
     // exact tie rule: every shift within TAU of the maximum, then larger c,
     // smaller |dy|+|dx|, lexicographically smaller (dy, dx) -- one integer key
     // per candidate whose maximum is the winner (a running comparison with
-    // nested branches is a pattern the compiler has mistranslated here)
+    // nested branches is a pattern the compiler has mistranslated here).
+    // Each thread counts the overlap of its own window positions, so pairs
+    // with many near-tied shifts (periodic patterns) evaluate them in parallel.
     const T cut = top - (T)(TAU * (double)K);
     uint64_t best_key = 0;
-    for (int p0 = 0; p0 < P; p0 += blockDim.x) {
-      int dyc = 0, dxc = 0;
-      const int p = p0 + tid;
-      candf[tid] = (p < P && value(p, dyc, dxc) >= cut) ? 1 : 0;
-      __syncthreads();
-      for (int t = 0; t < (int)blockDim.x; ++t) {
-        if (!candf[t]) continue;
-        int dy, dx;
-        (void)value(p0 + t, dy, dx);
-        const int c = block_overlap(brep, bmem, N, dy, dx, ired);
-        best_key = max(best_key, tie_key(c, dy, dx));
-      }
+    for (int p = tid; p < P; p += blockDim.x) {
+      int dy, dx;
+      if (value(p, dy, dx) >= cut) best_key = max(best_key, tie_key(thread_overlap(brep, bmem, N, dy, dx), dy, dx));
+    }
+    keyred[tid] = best_key;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) keyred[tid] = max(keyred[tid], keyred[tid + s]);
       __syncthreads();
     }
+    best_key = keyred[0];
+    __syncthreads();
     int best_c, best_dy, best_dx;
     tie_decode(best_key, best_c, best_dy, best_dx);
     if (tid == 0) {
