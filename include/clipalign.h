@@ -181,12 +181,18 @@ ca_status ca_reset_stats(ca_ctx* ctx);
  *     CA_CLIPS_IMAGE keeps each clip's whitened image w_i = IDFT2(W_i) (the
  *     spatial form of the whitened spectrum), scaled by N and stored as FP16
  *     (2 N^2 bytes a clip), for CA_PATH_DIRECT.
+ *     CA_CLIPS_NO_FP64 keeps no FP64 spectra (16 (N/2+1) N bytes a clip
+ *     saved; 128 x 128 sets without CA_CLIPS_IMAGE only, CA_EUNSUPPORTED
+ *     otherwise), so that millions of clips fit in HBM: the FP64
+ *     re-decision of CA_PATH_MIXED / CA_PATH_FP32 then computes the FP64
+ *     spectra of just the clips it needs (same results).  CA_PATH_FP64,
+ *     CA_PATH_AUTO and ca_graph_create return CA_EUNSUPPORTED on such sets.
  * The library rasterises, counts pixels, row/column sums, 4-connected polygons
  * (at most 64 per clip; larger counts mark the clip and make the edge track
  * fail with CA_EUNSUPPORTED on it), and computes FP64 spectra, whitened with
  * |F| > 1e-2 kept, stored as FP16 (and FP32 / FP64 as requested).
  * Returns CA_EINVAL on a bad size or N, CA_ENOMEM if it does not fit. */
-enum { CA_CLIPS_DEVICE_PTRS = 1, CA_CLIPS_FP32 = 2, CA_CLIPS_FP64 = 4, CA_CLIPS_IMAGE = 8 };
+enum { CA_CLIPS_DEVICE_PTRS = 1, CA_CLIPS_FP32 = 2, CA_CLIPS_FP64 = 4, CA_CLIPS_IMAGE = 8, CA_CLIPS_NO_FP64 = 16 };
 ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr,
                           const int32_t* rects, const int16_t* raster_n,
                           const int16_t* marker_w, int32_t flags, ca_clipset** out);
@@ -342,7 +348,8 @@ ca_status ca_cluster(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_c
  *   library: a clip set on ctx (128 x 128 clips, half-windows <= 16) holding
  *     the representatives; it must outlive the server.  If it was created
  *     with CA_CLIPS_FP32, request batches get FP32 spectra too and the
- *     exact re-decision of near-tied peaks runs behind the FP32 screen.
+ *     exact re-decision of near-tied peaks runs behind the FP32 screen; if
+ *     it was created with CA_CLIPS_NO_FP64, so are the batches.
  *   con: the cosine constraint (CA_EUNSUPPORTED for the edge track).
  *   slots: 1..32 concurrent requests; each slot has its own HIP stream and
  *     worker thread, so requests on different slots overlap on the device.

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libclipalign.so")
 CA_OK, CA_EINVAL, CA_ENOMEM, CA_EDEVICE, CA_EBUSY, CA_ETRUNC, CA_ESTATE, CA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 CA_COSINE, CA_EDGE = 1, 2
 PATHS = {"mixed": 0, "fp32": 1, "fp64": 2, "auto": 3, "direct": 4, "xcorr": 5}
-CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64, CA_CLIPS_IMAGE = 1, 2, 4, 8
+CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64, CA_CLIPS_IMAGE, CA_CLIPS_NO_FP64 = 1, 2, 4, 8, 16
 FLAG_RESCORED_FWD, FLAG_RESCORED_REV, FLAG_EMPTY = 1, 2, 4
 FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16, 32, 64
 FLAG_INVALID = 128
@@ -180,16 +180,17 @@ class Context:
             self.h = None
 
     # -------------------------------------------------------------- clips
-    def clips(self, cs, fp32=False, image=False):
+    def clips(self, cs, fp32=False, image=False, fp64=True):
         """Build a device clip set from a ``clipgen.ClipSet`` (host arrays).
 
         fp32: keep FP32 spectra (the "fp32" path); image: keep the FP16 whitened
-        images (the "direct" path)."""
+        images (the "direct" path); fp64=False: keep no FP64 spectra (128 x 128
+        sets; the re-decision computes the ones it needs)."""
         ptr = np.ascontiguousarray(cs.rect_ptr, dtype=np.int64)
         rects = np.ascontiguousarray(cs.rects, dtype=np.int32).reshape(-1, 4)
         rn = np.ascontiguousarray(cs.raster_n, dtype=np.int16)
         mw = np.ascontiguousarray(cs.marker_w, dtype=np.int16)
-        flags = (CA_CLIPS_FP32 if fp32 else 0) | (CA_CLIPS_IMAGE if image else 0)
+        flags = (CA_CLIPS_FP32 if fp32 else 0) | (CA_CLIPS_IMAGE if image else 0) | (0 if fp64 else CA_CLIPS_NO_FP64)
         h = P()
         self._check(self.lib.ca_clips_create(self.h, self._stream(), rn.size, _ptr(ptr),
                                              _ptr(rects) if rects.size else None, _ptr(rn), _ptr(mw),

@@ -42,6 +42,11 @@ struct ca_ctx {
   // reusable per-call scratch
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  // on-demand FP64 spectra of sets without them: remap tables, then spectra
+  void* fp64_tab = nullptr;
+  size_t fp64_tab_bytes = 0;
+  void* fp64_spec = nullptr;
+  size_t fp64_spec_bytes = 0;
   // MFMA fragment tables of the mixed path (raster 128)
   void* mf_b1 = nullptr;
   void* mf_a2 = nullptr;
@@ -121,6 +126,23 @@ ca_status cs_alloc(ca_ctx* ctx, ca_clipset* cs, void** p, size_t bytes) {
 }
 
 // Per-call scratch, grown on demand and kept on the context.
+// Grow-only device buffer kept on the context.
+ca_status grow_buffer(ca_ctx* ctx, void** buf, size_t* have, size_t bytes) {
+  if (*have < bytes) {
+    if (*buf) {
+      (void)hipFree(*buf);
+      ctx->used -= *have;
+      *buf = nullptr;
+      *have = 0;
+    }
+    const size_t want = std::max(bytes, (size_t)1 << 20);
+    ca_status st = dev_alloc(ctx, buf, want, nullptr);
+    if (st != CA_OK) return st;
+    *have = want;
+  }
+  return CA_OK;
+}
+
 ca_status scratch(ca_ctx* ctx, size_t bytes, void** out) {
   if (ctx->scratch_bytes < bytes) {
     if (ctx->scratch) {
@@ -216,6 +238,8 @@ ca_status ca_destroy(ca_ctx* ctx) {
   (void)hipFree(ctx->tw32);
   (void)hipFree(ctx->tw64);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->fp64_tab) (void)hipFree(ctx->fp64_tab);
+  if (ctx->fp64_spec) (void)hipFree(ctx->fp64_spec);
   if (ctx->mf_b1) (void)hipFree(ctx->mf_b1);
   if (ctx->mf_a2) (void)hipFree(ctx->mf_a2);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -292,13 +316,19 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
   }
   const int64_t m = hptr[n];
   if (m > 0 && !rects) return fail(ctx, CA_EINVAL, "null rects");
+  const bool no_fp64 = (flags & CA_CLIPS_NO_FP64) != 0;
+  if (no_fp64) {
+    if (flags & CA_CLIPS_IMAGE) return fail(ctx, CA_EUNSUPPORTED, "CA_CLIPS_NO_FP64 with CA_CLIPS_IMAGE");
+    for (int64_t i = 0; i < n; ++i)
+      if (hN[i] != 128) return fail(ctx, CA_EUNSUPPORTED, "CA_CLIPS_NO_FP64 needs 128 x 128 clips");
+  }
 
   ca_clipset* cs = new ca_clipset();
   cs->ctx = ctx;
   cs->gen = ctx->next_gen++;
   cs->arena = arena;
   cs->n = n;
-  cs->flags = flags | CA_CLIPS_FP64;  // FP64 spectra back the re-decision pass
+  cs->flags = no_fp64 ? flags : (flags | CA_CLIPS_FP64);  // FP64 spectra back the re-decision pass
   cs->hN = hN;
   cs->hw = hw;
   ctx->live_clipsets++;
@@ -360,7 +390,7 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
   ALLOC(zero_bins, int32_t, n);
   ALLOC(spec16, __half2, nsp);
   if (flags & CA_CLIPS_FP32) ALLOC(spec32, float2, nsp);
-  ALLOC(spec64, double2, nsp);
+  if (!no_fp64) ALLOC(spec64, double2, nsp);
   if (image) {
     int64_t* dio;
     st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); dio = (int64_t*)p;
@@ -625,7 +655,7 @@ static QueueMem queue_carve(char* base, int64_t n) {
 // device.  No host synchronisation, so it can be captured in a graph.
 static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev& cm, int maxN, int Lmax, int path,
                                  Threshold thr, const PairIO& io, const QueueMem& m, hipStream_t s, bool events,
-                                 int direct_n = 0) {
+                                 int direct_n = 0, bool fp64_pass = true) {
   const int64_t n = io.n_pairs;
   hipError_t e = launch_zero_u64(m.counters, 32, s);
   if (e != hipSuccess) return e;
@@ -642,6 +672,14 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
   }
   if (e != hipSuccess) return e;
   if (events && (e = hipEventRecord(ctx->ev1, s)) != hipSuccess) return e;
+  if (!fp64_pass) {
+    // sets without FP64 spectra: only the FP32 screen here; the rest runs on
+    // demand once the host knows which clips it needs
+    if (cr.spec32 && cm.spec32)
+      return launch_rescore_screen(cr, cm, io, thr, m.cq, m.exact, ctx->tw64, m.q.peak_err_bits,
+                                   m.q.peak_ratio_bits, m.q.r1_low, s);
+    return hipSuccess;
+  }
   // FP64 re-decision: the candidate groups, then the full FP64 surface of the
   // pairs queued for it
   e = launch_rescore_candidates(cr, cm, io, thr, m.cq, m.exact, ctx->tw64, m.q.peak_err_bits, m.q.peak_ratio_bits,
@@ -650,6 +688,72 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
   FftPlan pl = plan_fft(maxN, Lmax, 8);
   return launch_pcm_fft64(cr, cm, io, m.q.list, n, MODE_RESCORE, thr, 0.0, ctx->tw64, pl.CH, pl.LINES, Lmax, maxN,
                           m.q, s, m.q.len);
+}
+
+// FP64 re-decision for clip sets without stored FP64 spectra: after the main
+// kernel (and the FP32 screen) the groups and pairs still to re-decide are
+// known; their clips are collected on the device (each once, in a per-set
+// table mapping clip -> slot), their FP64 spectra computed into a buffer on
+// the context, and the FP64 passes run on views whose FP64 spectra and offsets
+// point there.  h: the queue counters already read back.
+static ca_status fp64_on_demand(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
+                                Threshold thr, const PairIO& io, const QueueMem& qm, const unsigned long long* h,
+                                int maxN, int Lmax) {
+  const ClipsDev& cr = crs->d;
+  const ClipsDev& cm = cms->d;
+  const bool screened = cr.spec32 && cm.spec32;
+  const CandQueue& groups = screened ? qm.exact : qm.cq;
+  const int64_t n_groups = std::min<int64_t>((int64_t)(screened ? h[8] : h[2]), groups.cap_groups);
+  const int64_t n_full = (int64_t)h[0];
+  if (n_groups == 0 && n_full == 0) return CA_OK;
+  const bool same = crs == cms;
+  const int64_t nr = crs->n, nm = same ? 0 : cms->n;
+  const size_t b_r = align_up(8 * (size_t)nr), b_m = align_up(8 * (size_t)nm);
+  ca_status st = grow_buffer(ctx, &ctx->fp64_tab, &ctx->fp64_tab_bytes, 2 * b_r + 2 * b_m + 256);
+  if (st) return st;
+  char* t = (char*)ctx->fp64_tab;
+  int64_t* remap_r = (int64_t*)t;
+  int64_t* ids_r = (int64_t*)(t + b_r);
+  int64_t* remap_m = same ? remap_r : (int64_t*)(t + 2 * b_r);
+  int64_t* ids_m = same ? ids_r : (int64_t*)(t + 2 * b_r + b_m);
+  unsigned long long* cnt = (unsigned long long*)(t + 2 * b_r + 2 * b_m);
+  constexpr int64_t PER = 128 * 65;  // FP64 half-spectrum of a 128 x 128 clip, in double2
+  HIP_OR_FAIL(ctx, hipMemsetAsync(remap_r, 0xff, 8 * (size_t)nr, s));
+  if (!same) HIP_OR_FAIL(ctx, hipMemsetAsync(remap_m, 0xff, 8 * (size_t)nm, s));
+  HIP_OR_FAIL(ctx, launch_zero_u64(cnt, 2, s));
+  HIP_OR_FAIL(ctx, launch_mark_fp64(io, groups.groups, n_groups, qm.q.list, n_full, remap_r, ids_r, cnt, remap_m,
+                                    ids_m, same ? cnt : cnt + 1, PER, s));
+  unsigned long long hc[2] = {0, 0};
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  const int64_t kr = (int64_t)hc[0], km = same ? 0 : (int64_t)hc[1];
+  st = grow_buffer(ctx, &ctx->fp64_spec, &ctx->fp64_spec_bytes, sizeof(double2) * (size_t)PER * (size_t)(kr + km));
+  if (st) return st;
+  double2* spec_r = (double2*)ctx->fp64_spec;
+  double2* spec_m = same ? spec_r : spec_r + PER * kr;
+  // views for the spectrum writes (FP64 only, at the remapped offsets) and for the FP64 passes
+  auto write_view = [](ClipsDev v, double2* spec, const int64_t* remap) {
+    v.spec16 = nullptr;
+    v.spec32 = nullptr;
+    v.spec64 = spec;
+    v.spec_off = remap;
+    v.zero_bins = nullptr;
+    return v;
+  };
+  auto read_view = [](ClipsDev v, double2* spec, const int64_t* remap) {
+    v.spec64 = spec;
+    v.spec_off = remap;
+    return v;
+  };
+  HIP_OR_FAIL(ctx, launch_spectrum128(write_view(cr, spec_r, remap_r), ids_r, kr, ctx->tw64, s));
+  if (!same) HIP_OR_FAIL(ctx, launch_spectrum128(write_view(cm, spec_m, remap_m), ids_m, km, ctx->tw64, s));
+  const ClipsDev vr = read_view(cr, spec_r, remap_r), vm = read_view(cm, spec_m, remap_m);
+  HIP_OR_FAIL(ctx, launch_rescore_exact(vr, vm, io, thr, groups, ctx->tw64, qm.q.peak_err_bits, qm.q.peak_ratio_bits,
+                                        qm.q.r1_low, s));
+  FftPlan pl = plan_fft(maxN, Lmax, 8);
+  HIP_OR_FAIL(ctx, launch_pcm_fft64(vr, vm, io, qm.q.list, io.n_pairs, MODE_RESCORE, thr, 0.0, ctx->tw64, pl.CH,
+                                    pl.LINES, Lmax, maxN, qm.q, s, qm.q.len));
+  return CA_OK;
 }
 
 // Cosine alignment of a device pair list with the chosen path (no validation).
@@ -663,6 +767,9 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   const ClipsDev& cm = cms->d;
   const int64_t n = io.n_pairs;
   const RescoreQueue none{nullptr, nullptr, nullptr, nullptr, nullptr};
+  const bool on_demand = !cr.spec64 || !cm.spec64;
+  if (on_demand && path != CA_PATH_MIXED && path != CA_PATH_FP32)
+    return fail(ctx, CA_EUNSUPPORTED, "this path needs FP64 spectra (clip set made with CA_CLIPS_NO_FP64)");
   if (path == CA_PATH_FP64) {
     FftPlan pl = plan_fft(maxN, Lmax, 8);
     HIP_OR_FAIL(ctx, launch_pcm_fft64(cr, cm, io, nullptr, n, MODE_EXACT, thr, 0.0, ctx->tw64, pl.CH,
@@ -706,10 +813,17 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   const QueueMem qm = queue_carve((char*)sc, n);
   unsigned long long* counters = qm.counters;
   const int64_t cap_g = qm.cq.cap_groups;
-  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n));
+  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n, !on_demand));
   unsigned long long h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  if (on_demand) {
+    st = fp64_on_demand(ctx, crs, cms, s, thr, io, qm, h, maxN, Lmax);
+    if (st) return st;
+    // the FP64 passes raised the error maxima
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+  }
   {
     float ms = 0.f;
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
@@ -775,7 +889,11 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
     ctx->stats.pairs_edge += n_pairs;
     return CA_OK;
   }
-  if (path == CA_PATH_AUTO) return capriv::align_auto(ctx, cs, s, Threshold{con->thr_num, con->thr_den}, io);
+  if (path == CA_PATH_AUTO) {
+    if (!cs->d.spec64)
+      return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_AUTO verifies against FP64 spectra (clip set made with CA_CLIPS_NO_FP64)");
+    return capriv::align_auto(ctx, cs, s, Threshold{con->thr_num, con->thr_den}, io);
+  }
   return align_cosine(ctx, cs, cs, s, Threshold{con->thr_num, con->thr_den}, path, io);
 }
 
@@ -811,6 +929,8 @@ extern "C" ca_status ca_graph_create(ca_ctx* ctx, void* stream, const ca_clipset
   if (!ctx) return CA_EINVAL;
   if (!out || !cs || cs->ctx != ctx) return fail(ctx, CA_EINVAL, "bad arguments");
   if (!valid_constraint(con) || con->kind != CA_COSINE) return fail(ctx, CA_EINVAL, "graphs capture the cosine track");
+  if (!cs->d.spec64)
+    return fail(ctx, CA_EUNSUPPORTED, "a captured sequence needs stored FP64 spectra (clip set made with CA_CLIPS_NO_FP64)");
   if (n_pairs <= 0 || n_pairs > (1ll << 31) - 1) return fail(ctx, CA_EINVAL, "bad pair count");
   if (!rep || !mem || !bits || !shift || !count || !score || !flags)
     return fail(ctx, CA_EINVAL, "null output or pair pointer");
@@ -905,6 +1025,7 @@ int64_t n_of(const ca_clipset* cs) { return cs->n; }
 int maxN_of(const ca_clipset* cs) { return cs->maxN; }
 bool mixed_ok_of(const ca_clipset* cs) { return cs->mixed_ok; }
 bool has_fp32_of(const ca_clipset* cs) { return cs->d.spec32 != nullptr; }
+bool has_fp64_of(const ca_clipset* cs) { return cs->d.spec64 != nullptr; }
 bool has_image_of(const ca_clipset* cs) { return DIRECT_ENABLED && cs->d.img16 != nullptr; }
 const std::vector<int16_t>& hw_of(const ca_clipset* cs) { return cs->hw; }
 std::map<int, TuneEntry>& tune_of(ca_ctx* ctx) { return ctx->tune; }

@@ -48,6 +48,7 @@ ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
                           const int16_t* raster_n, const int16_t* marker_w, uint32_t flags, DevArena* arena,
                           ca_clipset** out);
 bool has_fp32_of(const ca_clipset* cs);
+bool has_fp64_of(const ca_clipset* cs);
 }  // namespace capriv
 
 using namespace ca;
@@ -168,7 +169,9 @@ void run_request(ca_server* srv, int slot, Request* req) {
   }
   req->status = clips_create_in(ctx, s, n, req->rect_ptr.data(), req->rects.empty() ? nullptr : req->rects.data(),
                                 req->raster_n.data(), req->marker_w.data(),
-                                has_fp32_of(srv->lib) ? CA_CLIPS_FP32 : 0u, &arena, &rc);
+                                (has_fp32_of(srv->lib) ? CA_CLIPS_FP32 : 0u) |
+                                    (has_fp64_of(srv->lib) ? 0u : CA_CLIPS_NO_FP64),
+                                &arena, &rc);
   if (req->status != CA_OK) {
     req->error = ca_last_error(ctx);
     goto cleanup;

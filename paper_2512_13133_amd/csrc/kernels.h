@@ -74,6 +74,20 @@ hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, con
                                      const CandQueue& cq, const CandQueue& exact, const double2* tw256,
                                      unsigned long long* peak_err_bits, unsigned long long* peak_ratio_bits,
                                      const float* r1_low, hipStream_t s);
+// The FP32 screen alone (groups it cannot settle go to `exact`), and the FP64
+// pass alone over a group queue.
+hipError_t launch_rescore_screen(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
+                                 const CandQueue& cq, const CandQueue& exact, const double2* tw256,
+                                 unsigned long long* peak_err_bits, unsigned long long* peak_ratio_bits,
+                                 const float* r1_low, hipStream_t s);
+hipError_t launch_rescore_exact(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
+                                const CandQueue& groups, const double2* tw256, unsigned long long* peak_err_bits,
+                                unsigned long long* peak_ratio_bits, const float* r1_low, hipStream_t s);
+// Collect the clips whose FP64 spectra the re-decision needs: the pairs of the
+// first n_groups groups and of list[0 .. n_list); remap tables start at -1.
+hipError_t launch_mark_fp64(const PairIO& io, const CandGroup* groups, int64_t n_groups, const int64_t* list,
+                            int64_t n_list, int64_t* remap_r, int64_t* ids_r, unsigned long long* cnt_r,
+                            int64_t* remap_m, int64_t* ids_m, unsigned long long* cnt_m, int64_t per, hipStream_t s);
 // Exact-objective alignment: per pair the window shift of the largest overlap
 // count (tie rule as in the re-decision), both directions; rasters of 64 or
 // 128 (pairs of the other size are skipped), half-windows <= 16.

@@ -290,6 +290,61 @@ rescore_candidates_kernel(ClipsDev cr, ClipsDev cm, PairIO io, Threshold thr, Ca
   }
 }
 
+hipError_t launch_rescore_screen(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
+                                 const CandQueue& cq, const CandQueue& exact, const double2* tw256,
+                                 unsigned long long* peak_err_bits, unsigned long long* peak_ratio_bits,
+                                 const float* r1_low, hipStream_t s) {
+  if (cq.cap_groups <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((cq.cap_groups + RS_WAVES - 1) / RS_WAVES, 2048);
+  hipLaunchKernelGGL(rescore_candidates_kernel<true>, dim3(grid), dim3(RS_THREADS), 0, s, cr, cm, io, thr, cq, exact,
+                     tw256, peak_err_bits, peak_ratio_bits, r1_low);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescore_exact(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
+                                const CandQueue& groups, const double2* tw256, unsigned long long* peak_err_bits,
+                                unsigned long long* peak_ratio_bits, const float* r1_low, hipStream_t s) {
+  if (groups.cap_groups <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((groups.cap_groups + RS_WAVES - 1) / RS_WAVES, 2048);
+  hipLaunchKernelGGL(rescore_candidates_kernel<false>, dim3(grid), dim3(RS_THREADS), 0, s, cr, cm, io, thr, groups,
+                     groups, tw256, peak_err_bits, peak_ratio_bits, r1_low);
+  return hipGetLastError();
+}
+
+// Claim clip c in a set's table: the first claimant takes the next slot and
+// records the clip's FP64 spectrum offset (slot * per); later ones see it taken.
+__device__ __forceinline__ void claim_clip(int c, int64_t* remap, int64_t* ids, unsigned long long* cnt, int64_t per) {
+  unsigned long long* r = reinterpret_cast<unsigned long long*>(remap + c);
+  if (atomicCAS(r, ~0ull, ~1ull) == ~0ull) {
+    const unsigned long long slot = atomicAdd(cnt, 1ull);
+    ids[slot] = c;
+    atomicExch(r, (unsigned long long)((int64_t)slot * per));
+  }
+}
+
+// The clips of the queued groups and of the pairs queued for the full FP64
+// surface (representatives in table r, members in table m).
+__global__ void mark_fp64_kernel(PairIO io, const CandGroup* __restrict__ groups, int64_t n_groups,
+                                 const int64_t* __restrict__ list, int64_t n_list, int64_t* remap_r, int64_t* ids_r,
+                                 unsigned long long* cnt_r, int64_t* remap_m, int64_t* ids_m,
+                                 unsigned long long* cnt_m, int64_t per) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_groups + n_list) return;
+  const int64_t k = t < n_groups ? groups[t].pair : list[t - n_groups];
+  claim_clip(io.rep[k], remap_r, ids_r, cnt_r, per);
+  claim_clip(io.mem[k], remap_m, ids_m, cnt_m, per);
+}
+
+hipError_t launch_mark_fp64(const PairIO& io, const CandGroup* groups, int64_t n_groups, const int64_t* list,
+                            int64_t n_list, int64_t* remap_r, int64_t* ids_r, unsigned long long* cnt_r,
+                            int64_t* remap_m, int64_t* ids_m, unsigned long long* cnt_m, int64_t per, hipStream_t s) {
+  const int64_t n = n_groups + n_list;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(mark_fp64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, io, groups, n_groups, list,
+                     n_list, remap_r, ids_r, cnt_r, remap_m, ids_m, cnt_m, per);
+  return hipGetLastError();
+}
+
 hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                      const CandQueue& cq, const CandQueue& exact, const double2* tw256,
                                      unsigned long long* peak_err_bits, unsigned long long* peak_ratio_bits,

@@ -334,8 +334,10 @@ __global__ void __launch_bounds__(S128_THREADS) spectrum128_kernel(ClipsDev cs,
         zeros += (v == 0 || v == 64) ? 1 : 2;  // full-grid bins represented
       }
       const __half2 h = __halves2half2(__float2half_rn((float)W.x), __float2half_rn((float)W.y));
-      if (v < 64) cs.spec16[so + (int64_t)u * 64 + v] = h;
-      else cs.spec16[so + 128 * 64 + u] = h;
+      if (cs.spec16) {
+        if (v < 64) cs.spec16[so + (int64_t)u * 64 + v] = h;
+        else cs.spec16[so + 128 * 64 + u] = h;
+      }
       if (cs.spec32) cs.spec32[so + (int64_t)u * 65 + v] = make_float2((float)W.x, (float)W.y);
       if (cs.spec64) cs.spec64[so + (int64_t)u * 65 + v] = W;
     }
@@ -346,7 +348,7 @@ __global__ void __launch_bounds__(S128_THREADS) spectrum128_kernel(ClipsDev cs,
     if (tid == 0) {
       int z = 0;
       for (int w = 0; w < S128_THREADS / 64; ++w) z += zred[w];
-      cs.zero_bins[clip] = z;
+      if (cs.zero_bins) cs.zero_bins[clip] = z;
     }
   }
 }

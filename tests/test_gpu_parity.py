@@ -722,15 +722,16 @@ def _oracle_best(lib, req):
     return best, score, shift
 
 
-@pytest.mark.parametrize("fp32", [False, True])
-def test_serving_matches_oracle_alone_and_in_mix(ctx, fp32):
+@pytest.mark.parametrize("fp32,fp64", [(False, True), (True, True), (True, False)])
+def test_serving_matches_oracle_alone_and_in_mix(ctx, fp32, fp64):
     # library ranges of ~130 partners are split into 64-partner segments, so
     # the per-segment survivor counts are summed across workgroups here; with
-    # an FP32 library the near-tie re-decision runs behind the FP32 screen
+    # an FP32 library the near-tie re-decision runs behind the FP32 screen, and
+    # without FP64 spectra (library and batches) it computes the ones it needs
     import paper_2512_13133_amd as ca
     lib, reqs = _serving_case(n_library=300)
-    say(f"[serve] library={lib.n} requests={[r.n for r in reqs]} fp32={fp32}")
-    hlib = ctx.clips(lib, fp32=fp32)
+    say(f"[serve] library={lib.n} requests={[r.n for r in reqs]} fp32={fp32} fp64={fp64}")
+    hlib = ctx.clips(lib, fp32=fp32, fp64=fp64)
     srv = ca.Server(ctx, hlib, (19, 20), slots=3)
     alone = []
     for r in reqs:
