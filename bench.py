@@ -279,7 +279,7 @@ def serve_bench(ctx, n_library, seconds, slots=4):
     template); request batches of log-normal size (median 64, sigma 1, at most
     10,000 clips) drawn from library templates with jitter 4 and offsets +-16,
     arriving as a Poisson stream.  First the saturation rate with a full queue,
-    then latency at half of it."""
+    then latency at half of it and at 80% of it."""
     import threading
 
     import numpy as np
@@ -358,6 +358,11 @@ def serve_bench(ctx, n_library, seconds, slots=4):
     trace = [(float(a), make_request()) for a in arrivals]
     lat, wall = run(trace, True)
     st2 = srv.stats()
+    # and at 80% of saturation
+    qps80 = 0.8 * sat_qps
+    n80 = max(20, int(qps80 * seconds))
+    arr80 = np.cumsum(rng.exponential(1.0 / qps80, size=n80))
+    lat80, wall80 = run([(float(a), make_request()) for a in arr80], True)
     srv.close()
     hlib.close()
     clips = sum(r.n for _, r in trace)
@@ -367,6 +372,9 @@ def serve_bench(ctx, n_library, seconds, slots=4):
             "clips": clips, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
             "pairs_per_s": round((st2["candidate_pairs"] - st1["candidate_pairs"]) / wall, 1),
+            "at_80pct": {"qps_target": round(qps80, 1), "qps_achieved": round(n80 / wall80, 1), "requests": n80,
+                         "p50_ms": round(float(np.percentile(lat80, 50)) * 1e3, 2),
+                         "p99_ms": round(float(np.percentile(lat80, 99)) * 1e3, 2)},
             "request_sizes": "round(LogNormal(ln 64, 1)) clipped to [1, 10000]"}
 
 
