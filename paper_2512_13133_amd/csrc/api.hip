@@ -597,7 +597,7 @@ struct FftPlan {
 FftPlan plan_fft(int N, int L, int scalar_bytes) {
   const size_t budget = 150 * 1024;
   FftPlan p;
-  p.LINES = 8;
+  p.LINES = N <= 64 ? 16 : 8;  // at least 512 butterflies between barriers
   const size_t c = 2 * (size_t)scalar_bytes;
   const size_t fixed = (size_t)p.LINES * N * c + (size_t)L * L * scalar_bytes;
   int ch = (int)((budget - fixed) / ((size_t)N * c));
@@ -759,10 +759,17 @@ static ca_status fp64_on_demand(ca_ctx* ctx, const ca_clipset* crs, const ca_cli
 // Cosine alignment of a device pair list with the chosen path (no validation).
 // `checked`: the caller guarantees that every pair suits the path (the
 // autotuner's buckets), so the set-wide shape tests of CA_PATH_MIXED and
-// CA_PATH_DIRECT are skipped; `direct_n` then names the bucket's raster size.
+// CA_PATH_DIRECT are skipped; `direct_n` then names the bucket's raster size
+// and `bucket_w` bounds its half-windows, so the per-pair FFT kernels are
+// planned (LDS per workgroup) for the bucket rather than for the whole set.
 static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                              Threshold thr, int path, const PairIO& io, bool checked = false, int direct_n = 0) {
-  const int maxN = std::max(crs->maxN, cms->maxN), Lmax = std::max(crs->Lmax, cms->Lmax);
+                              Threshold thr, int path, const PairIO& io, bool checked = false, int direct_n = 0,
+                              int bucket_w = 1 << 20) {
+  int maxN = std::max(crs->maxN, cms->maxN), Lmax = std::max(crs->Lmax, cms->Lmax);
+  if (checked && direct_n > 0) {
+    maxN = direct_n;
+    Lmax = std::min(Lmax, axis_len(bucket_w, direct_n));
+  }
   const ClipsDev& cr = crs->d;
   const ClipsDev& cm = cms->d;
   const int64_t n = io.n_pairs;
@@ -855,8 +862,8 @@ ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
   return clips_create_impl(ctx, stream, n, rect_ptr, rects, raster_n, marker_w, flags, arena, out);
 }
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                            Threshold thr, int path, const PairIO& io, bool checked, int direct_n) {
-  return align_cosine(ctx, crs, cms, s, thr, path, io, checked, direct_n);
+                            Threshold thr, int path, const PairIO& io, bool checked, int direct_n, int bucket_w) {
+  return align_cosine(ctx, crs, cms, s, thr, path, io, checked, direct_n, bucket_w);
 }
 }  // namespace capriv
 

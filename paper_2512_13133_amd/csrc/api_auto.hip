@@ -28,7 +28,8 @@ bool has_fp32_of(const ca_clipset* cs);
 bool has_image_of(const ca_clipset* cs);
 std::map<int, TuneEntry>& tune_of(ca_ctx* ctx);
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                            ca::Threshold thr, int path, const ca::PairIO& io, bool checked, int direct_n);
+                            ca::Threshold thr, int path, const ca::PairIO& io, bool checked, int direct_n,
+                            int bucket_w);
 }  // namespace capriv
 
 using namespace ca;
@@ -150,11 +151,11 @@ ca_status tune_bucket(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshol
   TuneEntry e;
   e.sample = m;
   auto run = [&](int path, const PairIO& o, double* us) -> ca_status {
-    ca_status st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true, N);  // warm
+    ca_status st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true, N, W_BOUND[wc]);  // warm
     if (st) return st;
     HIP_TRY(ctx, hipStreamSynchronize(s));
     const double t0 = wall_us();
-    st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true, N);
+    st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true, N, W_BOUND[wc]);
     if (st) return st;
     HIP_TRY(ctx, hipStreamSynchronize(s));
     *us = (wall_us() - t0) * 1000.0 / (double)m;
@@ -287,7 +288,8 @@ ca_status align_auto(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshold
       if (st) return done(st);
       it = table.emplace(key, e).first;
     }
-    st = align_cosine_sets(ctx, cs, cs, s, thr, it->second.path, bio, true, 64 << (key / N_WCLASS));
+    st = align_cosine_sets(ctx, cs, cs, s, thr, it->second.path, bio, true, 64 << (key / N_WCLASS),
+                           W_BOUND[key % N_WCLASS]);
     if (st) return done(st);
     off += m;
   }

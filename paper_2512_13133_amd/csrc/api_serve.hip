@@ -43,7 +43,7 @@ int64_t n_of(const ca_clipset* cs);
 bool mixed_ok_of(const ca_clipset* cs);
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
                             ca::Threshold thr, int path, const ca::PairIO& io, bool checked = false,
-                            int direct_n = 0);
+                            int direct_n = 0, int bucket_w = 1 << 20);
 ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr, const int32_t* rects,
                           const int16_t* raster_n, const int16_t* marker_w, uint32_t flags, DevArena* arena,
                           ca_clipset** out);
