@@ -117,7 +117,8 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     }
     const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na);
     const size_t b_mask = aup(8 * (size_t)(bits / 64 + 1));
-    const size_t need = 2 * b_ord + 2 * b_rng + b_mask;
+    const size_t b_soa = edge ? 0 : aup(4 * 64 * (size_t)na);  // transposed sliding sums (rows, columns)
+    const size_t need = 2 * b_ord + 2 * b_rng + b_mask + 2 * b_soa;
     if (pc->bytes < need) {
       free_ctx(ctx, pc->dev, pc->bytes);
       pc->dev = nullptr;
@@ -142,6 +143,11 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
                                      (unsigned long long*)d_mask, s));
     } else {
       HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
+      uint32_t* d_soa = (uint32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask);
+      HIP_TRY(ctx, launch_prune128_soa(dev_of(cs), d_order, na, d_soa, d_soa + b_soa / 4, s));
+      pa.soa_row = d_soa;
+      pa.soa_col = d_soa + b_soa / 4;
+      pa.soa_n = na;
       HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff, d_mask,
                                    false, s));
     }

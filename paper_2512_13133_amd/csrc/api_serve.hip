@@ -92,6 +92,7 @@ struct ca_server {
   std::vector<int32_t> lib_order;  // library ids by (n, id)
   std::vector<int32_t> lib_n;      // their pixel counts
   int32_t* d_order = nullptr;
+  uint32_t* d_soa = nullptr;       // transposed library sliding sums: rows, then columns (64 x n each)
   std::vector<ca_ctx*> slot_ctx;
   std::vector<hipStream_t> slot_stream;
   std::vector<capriv::DevArena> slot_arena;
@@ -235,6 +236,10 @@ void run_request(ca_server* srv, int slot, Request* req) {
     // as the fixed side and streams the library clips; direction 1 of a pair
     // is then the batch clip aligned to the library representative
     PruneArgs pa{srv->d_order, d_hi, n, d_cnt, nullptr, nullptr, nullptr, d_anchor, d_lo};
+    const int64_t nl = (int64_t)srv->lib_order.size();
+    pa.soa_row = srv->d_soa;
+    pa.soa_col = srv->d_soa + 64 * nl;
+    pa.soa_n = nl;
     pa.seg = (int)seg;
     pa.n_seg = (int)n_seg;
     const Threshold thr{p, q};
@@ -365,8 +370,13 @@ extern "C" ca_status ca_server_create(ca_ctx* ctx, const ca_clipset* library, co
             [&](int32_t a, int32_t b) { return np[a] != np[b] ? np[a] < np[b] : a < b; });
   srv->lib_n.resize(srv->lib_order.size());
   for (size_t k = 0; k < srv->lib_order.size(); ++k) srv->lib_n[k] = np[srv->lib_order[k]];
-  if (hipMalloc((void**)&srv->d_order, 4 * srv->lib_order.size() + 4) != hipSuccess ||
-      hipMemcpy(srv->d_order, srv->lib_order.data(), 4 * srv->lib_order.size(), hipMemcpyHostToDevice) != hipSuccess) {
+  const int64_t nl = (int64_t)srv->lib_order.size();
+  const size_t b_ord = (4 * (size_t)nl + 4 + 255) & ~(size_t)255;
+  if (hipMalloc((void**)&srv->d_order, b_ord + 2 * 256 * (size_t)nl) != hipSuccess ||
+      hipMemcpy(srv->d_order, srv->lib_order.data(), 4 * (size_t)nl, hipMemcpyHostToDevice) != hipSuccess ||
+      (srv->d_soa = (uint32_t*)((char*)srv->d_order + b_ord),
+       launch_prune128_soa(dev_of(library), srv->d_order, nl, srv->d_soa, srv->d_soa + 64 * nl, nullptr)) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess) {
     if (srv->d_order) (void)hipFree(srv->d_order);
     delete srv;
     return fail_ctx(ctx, CA_ENOMEM, "server library order upload failed");

@@ -110,6 +110,12 @@ struct PruneArgs {
   const int32_t* anchor_ids = nullptr;  // [n_anchor] anchor clip ids (null: order[a])
   const int32_t* lo = nullptr;          // [n_anchor] start of each range in `order` (null: a + 1)
   int order_ids = 0;                    // write each pair as (smaller id, larger id)
+  // partner sliding sums transposed (packed row pair q of the partner at
+  // position b of `order` at [q * soa_n + b]), so a wave's 64 partners read
+  // one contiguous run per pair; null: read each partner's own row
+  const uint32_t* soa_row = nullptr;
+  const uint32_t* soa_col = nullptr;
+  int64_t soa_n = 0;
   int seg = 0;      // partners per workgroup (0: one workgroup per anchor range; > 0: n_seg
                     // segments per anchor, counts and offs indexed [a * n_seg + segment])
   int n_seg = 1;

@@ -20,6 +20,9 @@
 // When anchors are few (a request batch against a large library), each
 // anchor's range is split into segments (grid y) so the chip still fills;
 // both passes then count and write per (anchor, segment).
+// The partners' sliding sums are read from a transposed copy (pair q of the
+// partner at order position b at [q n + b]), so each load of the coarse stage
+// is one contiguous run across the wave instead of 64 separate rows.
 // Pass flags go to a bitmask over each anchor's partner range; a second
 // kernel writes the surviving pairs in (anchor order, partner order).
 // Anchors come from the clip set `ca` and partners from `cb` (the same set
@@ -161,20 +164,13 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
     const int wb = cb.w[ib];
     const int64_t so_b = cb.sig_off[ib];
     uint32_t W[64];
-    const uint4* wr4 = reinterpret_cast<const uint4*>(cb.winrow + so_b);
-    const uint4* wc4 = reinterpret_cast<const uint4*>(cb.wincol + so_b);
     const int wmax = max(wa, wb);
+    const int64_t pos = valid ? b : start;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const uint4 v = wr4[q];
-      W[4 * q] = v.x; W[4 * q + 1] = v.y; W[4 * q + 2] = v.z; W[4 * q + 3] = v.w;
-    }
+    for (int q = 0; q < 64; ++q) W[q] = pa.soa_row[q * pa.soa_n + pos];
     const int cr = coarse_dim(ca.winrow + so_a, 8, W, wmax);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const uint4 v = wc4[q];
-      W[4 * q] = v.x; W[4 * q + 1] = v.y; W[4 * q + 2] = v.z; W[4 * q + 3] = v.w;
-    }
+    for (int q = 0; q < 64; ++q) W[q] = pa.soa_col[q * pa.soa_n + pos];
     const int cc = coarse_dim(ca.wincol + so_a, 8, W, wmax);
     const bool keep = valid && na > 0 && nb > 0 && passes128(min(cr, cc), na, nb, thr);
     const unsigned long long km = __ballot(keep);
@@ -236,8 +232,31 @@ __global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const 
   }
 }
 
+// Transposed partner sliding sums: pair q of the clip at position p of order
+// goes to [q * n + p] (threads take positions fastest, so the stores coalesce).
+__global__ void prune128_soa_kernel(ClipsDev cb, const int32_t* __restrict__ order, int64_t n,
+                                    uint32_t* __restrict__ soa_row, uint32_t* __restrict__ soa_col) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 64 * n) return;
+  const int q = (int)(t / n);
+  const int64_t p = t - (int64_t)q * n;
+  const int64_t so = cb.sig_off[order[p]];
+  soa_row[t] = reinterpret_cast<const uint32_t*>(cb.winrow + so)[q];
+  soa_col[t] = reinterpret_cast<const uint32_t*>(cb.wincol + so)[q];
+}
+
+hipError_t launch_prune128_soa(const ClipsDev& cb, const int32_t* order, int64_t n, uint32_t* soa_row,
+                               uint32_t* soa_col, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t total = 64 * n;
+  hipLaunchKernelGGL(prune128_soa_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, cb, order, n,
+                     soa_row, soa_col);
+  return hipGetLastError();
+}
+
 hipError_t launch_prune128(const ClipsDev& ca, const ClipsDev& cb, const PruneArgs& pa, Threshold thr,
                            const int64_t* range_off, uint32_t* mask, bool write, hipStream_t s) {
+  if (!write && (!pa.soa_row || !pa.soa_col || pa.soa_n <= 0)) return hipErrorInvalidValue;  // bounds pass reads them
   for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
     const dim3 grid(nb, pa.seg > 0 ? pa.n_seg : 1);
