@@ -117,7 +117,8 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     }
     const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na);
     const size_t b_mask = aup(8 * (size_t)(bits / 64 + 1));
-    const size_t b_soa = edge ? 0 : aup(4 * 64 * (size_t)na);  // transposed sliding sums (rows, columns)
+    // transposed sliding sums (rows, columns), or box sizes and polygon counts for the edge track
+    const size_t b_soa = aup(4 * 64 * (size_t)na);
     const size_t need = 2 * b_ord + 2 * b_rng + b_mask + 2 * b_soa;
     if (pc->bytes < need) {
       free_ctx(ctx, pc->dev, pc->bytes);
@@ -139,6 +140,12 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     HIP_TRY(ctx, hipMemcpyAsync(d_roff, range_off.data(), 8 * na, hipMemcpyHostToDevice, s));
     PruneArgs pa{d_order, d_hi, na, d_cnt, nullptr, nullptr, nullptr};
     if (edge) {
+      uint32_t* d_wh = (uint32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask);
+      int32_t* d_np = (int32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask + b_soa);
+      HIP_TRY(ctx, launch_edge_soa(dev_of(cs), d_order, na, d_wh, d_np, s));
+      pa.soa_wh = d_wh;
+      pa.soa_np = d_np;
+      pa.soa_n = na;
       HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff,
                                      (unsigned long long*)d_mask, s));
     } else {

@@ -116,6 +116,10 @@ struct PruneArgs {
   const uint32_t* soa_row = nullptr;
   const uint32_t* soa_col = nullptr;
   int64_t soa_n = 0;
+  // edge track: polygon box sizes (w | h << 16 of polygon q of the partner at
+  // position b at [q * soa_n + b]) and polygon counts by position
+  const uint32_t* soa_wh = nullptr;
+  const int32_t* soa_np = nullptr;
   int seg = 0;      // partners per workgroup (0: one workgroup per anchor range; > 0: n_seg
                     // segments per anchor, counts and offs indexed [a * n_seg + segment])
   int n_seg = 1;

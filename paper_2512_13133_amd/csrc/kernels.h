@@ -55,6 +55,9 @@ hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshol
 // Edge bounds pass: 64-bit chunk words of the survivor mask (ranges start on
 // words, range_off in bits) and survivor counts; the pairs are written by
 // launch_prune128(..., write = true) with order_ids set.
+// Transposed polygon box sizes (MAX_POLY x n words) and counts (n) of the clips in `order`.
+hipError_t launch_edge_soa(const ClipsDev& cs, const int32_t* order, int64_t n, uint32_t* soa_wh, int32_t* soa_np,
+                           hipStream_t s);
 hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
                              unsigned long long* mask, hipStream_t s);
 // Batched MFMA surface for raster 128, half-windows <= 16 (fragment tables from

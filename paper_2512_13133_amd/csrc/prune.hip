@@ -179,27 +179,30 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
   const int tol = (int)(2 * thr.p);
   unsigned long long* m = mask + (range_off[a] >> 6);
   int64_t found = 0;
+  // box size of polygon q: the anchor's from its own table (uniform reads), the
+  // partner's from the transposed table (one contiguous run across the wave)
+  auto wh_a = [&](int q) { return (uint32_t)(uint16_t)(ba[4 * q + 1] - ba[4 * q]) |
+                                  ((uint32_t)(uint16_t)(ba[4 * q + 3] - ba[4 * q + 2]) << 16); };
   for (int64_t b0 = a + 1; b0 < end; b0 += 64) {
     const int64_t b = b0 + lane;
     bool pass = false;
     if (b < end) {
-      const int ib = pa.order[b];
-      const int Pb = cs.npoly[ib];
+      const int Pb = pa.soa_np[b];
       if (Pa > 0 && Pb > 0) {
-        const int16_t* bb = cs.boxes + (int64_t)ib * MAX_POLY * 4;
+        auto wh_b = [&](int q) { return pa.soa_wh[(int64_t)q * pa.soa_n + b]; };
         pass = true;
         // polygons of the fewer side each need a size-compatible partner
         for (int side = 0; side < 2 && pass; ++side) {
           const bool check = side == 0 ? (Pa <= Pb) : (Pb <= Pa);
           if (!check) continue;
-          const int16_t* X = side == 0 ? ba : bb;
-          const int16_t* Y = side == 0 ? bb : ba;
           const int PX = side == 0 ? Pa : Pb, PY = side == 0 ? Pb : Pa;
           for (int p = 0; p < PX && pass; ++p) {
-            const int wx = X[4 * p + 1] - X[4 * p], hx = X[4 * p + 3] - X[4 * p + 2];
+            const uint32_t x = side == 0 ? wh_a(p) : wh_b(p);
+            const int wx = (int)(x & 0xffffu), hx = (int)(x >> 16);
             bool hit = false;
             for (int qq = 0; qq < PY && !hit; ++qq) {
-              const int wy = Y[4 * qq + 1] - Y[4 * qq], hy = Y[4 * qq + 3] - Y[4 * qq + 2];
+              const uint32_t y = side == 0 ? wh_b(qq) : wh_a(qq);
+              const int wy = (int)(y & 0xffffu), hy = (int)(y >> 16);
               hit = abs(wx - wy) <= tol && abs(hx - hy) <= tol;
             }
             if (!hit) pass = false;
@@ -229,9 +232,38 @@ hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshol
   return hipSuccess;
 }
 
+// Transposed polygon box sizes and counts of the clips in `order`: polygon q of
+// the clip at position p at [q * n + p] (threads take positions fastest).
+__global__ void edge_soa_kernel(ClipsDev cs, const int32_t* __restrict__ order, int64_t n,
+                                uint32_t* __restrict__ soa_wh, int32_t* __restrict__ soa_np) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)MAX_POLY * n) return;
+  const int q = (int)(t / n);
+  const int64_t p = t - (int64_t)q * n;
+  const int i = order[p];
+  const int np = cs.npoly[i];
+  uint32_t v = 0;
+  if (q < np) {
+    const int16_t* bx = cs.boxes + ((int64_t)i * MAX_POLY + q) * 4;
+    v = (uint32_t)(uint16_t)(bx[1] - bx[0]) | ((uint32_t)(uint16_t)(bx[3] - bx[2]) << 16);
+  }
+  soa_wh[t] = v;
+  if (q == 0) soa_np[p] = np;
+}
+
+hipError_t launch_edge_soa(const ClipsDev& cs, const int32_t* order, int64_t n, uint32_t* soa_wh, int32_t* soa_np,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t total = (int64_t)MAX_POLY * n;
+  hipLaunchKernelGGL(edge_soa_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, cs, order, n, soa_wh,
+                     soa_np);
+  return hipGetLastError();
+}
+
 hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
                              unsigned long long* mask, hipStream_t s) {
   if (pa.n_anchor == 0) return hipSuccess;
+  if (!pa.soa_wh || !pa.soa_np || pa.soa_n <= 0) return hipErrorInvalidValue;  // the kernel reads them
   for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
     hipLaunchKernelGGL(edge_prune_kernel, dim3(nb), dim3(64), 0, s, cs, pa, thr, range_off, mask, b0);
