@@ -82,8 +82,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU sharding is described in "
-                          "DESIGN.md and not launched", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; sharding across GPUs is not implemented",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

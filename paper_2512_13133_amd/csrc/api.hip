@@ -804,7 +804,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   if (path == CA_PATH_MIXED && !checked && (!crs->mixed_ok || !cms->mixed_ok))
     return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
   if (path == CA_PATH_DIRECT) {
-    if (!DIRECT_ENABLED) return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_DIRECT is disabled in this build");
+    if (!DIRECT_ENABLED) return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_DIRECT is switched off in this library");
     if (!cr.img16 || !cm.img16) return fail(ctx, CA_ESTATE, "CA_PATH_DIRECT needs clip sets made with CA_CLIPS_IMAGE");
     if (!checked) {
       if (!crs->direct_ok || !cms->direct_ok || crs->minN != maxN || cms->minN != maxN)
