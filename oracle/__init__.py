@@ -20,6 +20,8 @@ prune   -- safe pre-screening bounds (area, row/column signatures, polygon
            bounding-box sizes).
 scp     -- surprisal-based greedy set cover, eager and lazy (Eqs. 7-9).
 loop    -- coarse-to-fine closed loop with orphan re-injection (Sec. 3.1).
+serve   -- best covering representative per arriving clip (Sec. 3.1 step 3
+           applied to a fixed library).
 cover   -- drivers that run the above over pair lists.
 
 Readings of the paper where it is silent or ambiguous are fixed in the

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import clipgen
-from oracle import cosine, cover, edge, prune, raster
+from oracle import cosine, cover, edge, prune, raster, serve
 
 pytestmark = pytest.mark.gpu
 
@@ -707,18 +707,7 @@ _SERVE_ORACLE = {}  # oracle answers of the n_library=300 case, shared by both p
 
 
 def _oracle_best(lib, req):
-    both = clipgen.concat([lib, req])
-    nl = lib.n
-    rep = np.repeat(np.arange(nl, dtype=np.int32), req.n)
-    mem = np.tile(np.arange(nl, nl + req.n, dtype=np.int32), nl)
-    res = cover.align_pairs_cosine(both, rep, mem, 19, 20, workers=WORKERS)
-    best = np.full(req.n, -1, np.int32)
-    score = np.zeros(req.n)
-    shift = np.zeros((req.n, 2), np.int16)
-    for k in np.flatnonzero(res["bits"] & 1):
-        i, r, sc = int(mem[k]) - nl, int(rep[k]), res["score"][k, 0]
-        if best[i] < 0 or sc > score[i] or (sc == score[i] and r < best[i]):
-            best[i], score[i], shift[i] = r, sc, res["shift"][k, 0]
+    best, score, shift, _ = serve.serve_match(lib, req, 19, 20, workers=WORKERS)
     return best, score, shift
 
 

@@ -16,7 +16,7 @@ import pytest
 from scipy.fft import dctn
 
 import clipgen
-from oracle import cosine, cover, edge, loop, prune, raster, scp, xcorr
+from oracle import cosine, cover, edge, loop, prune, raster, scp, serve, xcorr
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -373,6 +373,54 @@ def test_edge_bit_brute_force_tiny():
     assert seen > 10
 
 
+def _bars(spans, N=64, y0=10, y1=14):
+    """A raster of full-height bars x[a, b) x y[y0, y1): one polygon per span."""
+    return raster.rasterize([(a, b, y0, y1) for a, b in spans], N)
+
+
+def test_edge_correspondence_is_taken_at_T0():
+    """Hand-worked (Sec. 2.2.2 with the T0 reading).  The member is the rep
+    moved 8 px right: rep bars x[2,8), x[10,16); member bars x[10,16), x[18,24).
+    Global boxes give d = (10-2, 24-16) = (8, 8), so T0 = (0, 8); there each
+    rep bar lands on exactly one member bar, the matched edges all move by 8,
+    so s = (0, 8) and E = 0.  Taken at s = 0 instead, rep bar x[2,8) meets no
+    member bar and the pair would have no correspondence."""
+    rep, mem = _bars([(2, 8), (10, 16)]), _bars([(10, 16), (18, 24)])
+    assert edge.align(mem, rep, 16, 0) == dict(s=(0, 8), E=0, bit=True, ok=True)
+    # the mirror direction: rep and member swap roles, the shift flips
+    assert edge.align(rep, mem, 16, 0) == dict(s=(0, -8), E=0, bit=True, ok=True)
+
+
+def test_edge_unmatched_polygon_moves_T0_but_not_E():
+    """Hand-worked.  Rep bars x[10,20), x[30,40); the member has the same two
+    bars plus an extra bar x[50,52) (3 > 2 polygons, so only the rep side must
+    match).  Global boxes: d = (10-10, 52-40) = (0, 12), T0 = (0, 6): rep bar
+    x[10,20) lands on x[16,26) (meets x[10,20) only), x[30,40) on x[36,46)
+    (meets x[30,40) only).  The matched pairs have all displacements 0, so
+    s = (0, 0) and E = 0: the extra bar moved T0 but enters no edge pair."""
+    rep, mem = _bars([(10, 20), (30, 40)]), _bars([(10, 20), (30, 40), (50, 52)])
+    assert edge.align(mem, rep, 16, 0) == dict(s=(0, 0), E=0, bit=True, ok=True)
+
+
+def test_edge_recheck_change_clears_the_bit():
+    """Hand-worked.  Rep bars q1 = x[20,30), q2 = x[40,53); member bars
+    p0 = x[1,2), p1 = x[20,30), p2 = x[40,50), p3 = x[51,53).
+    T0: d = (1-20, 53-53) = (-19, 0), half toward zero -> -9.  At T0 q1 lands
+    on x[11,21) (meets p1 only), q2 on x[31,44) (meets p2 only): matching
+    {(p1,q1), (p2,q2)}.  Edge displacements 0, 0 and 0, 50-53 = -3 give
+    s_x = -1 (-3/2 toward zero), E = max(0+1, -1+3) = 2.  At s = (0, -1) q2
+    lands on x[39,52) and meets p2 and p3, so the matching changed: no bit,
+    although E = 2 <= T_edge = 2."""
+    rep = _bars([(20, 30), (40, 53)])
+    mem = _bars([(1, 2), (20, 30), (40, 50), (51, 53)])
+    assert edge.align(mem, rep, 16, 2) == dict(s=(0, -1), E=2, bit=False, ok=False)
+    # with p3 one pixel further right (x[52,54)) T0 is still -9 (d = (-19, 1)),
+    # the matching and the solve are the same, q2 at x[39,52) now misses p3,
+    # and the bit is set
+    mem_ok = _bars([(1, 2), (20, 30), (40, 50), (52, 54)])
+    assert edge.align(mem_ok, rep, 16, 2) == dict(s=(0, -1), E=2, bit=True, ok=True)
+
+
 # ---------------------------------------------------------------- pruning
 
 
@@ -509,6 +557,31 @@ def test_loop_converges_and_members_pass_strict():
     assert len(set(rep_of.tolist())) == len(reps)
 
 
+def test_loop_reattaches_to_first_selected_representative():
+    """Hand-worked (Sec. 3.1 stages 3-4 with the re-attachment reading).
+    Ten nodes, K = 2.  Strict covers: 0 -> {4, 5, 6}, 2 -> {3, 7, 9},
+    1 -> {3, 8}; the relaxed graph adds 0 -> 3.
+    Iteration 1 (relaxed): in-degrees give f_3 = 4, f_4..f_9 = 2, f_0..f_2 = 1,
+    so Score_0 = 1 + 1/4 + 3/2 = 2.75 > Score_2 = 2.25 > Score_1 = 1.75: node 0
+    is selected and takes 3, 4, 5, 6; then Score_2 = 1 + 1/2 + 1/2 = 2 beats
+    Score_1 = 1.5.  Selection order [0, 2, 1].  Refinement: 0 does not cover 3
+    strictly, so 3 is the only orphan.
+    Iteration 2 (strict): 3 re-attaches to the first representative in
+    selection order that covers it strictly, 2 (not 1, the lower id and the
+    last one selected); skipping re-attachment would make 3 its own
+    representative."""
+    n = 10
+    strict = np.eye(n, dtype=bool)
+    for j, ks in {0: [4, 5, 6], 2: [3, 7, 9], 1: [3, 8]}.items():
+        strict[j, ks] = True
+    relaxed = strict.copy()
+    relaxed[0, 3] = True
+    rep_of, reps, log = loop.run(n, lambda tau: relaxed if tau == "relaxed" else strict, ["relaxed", "strict"])
+    assert reps == [0, 2, 1]
+    assert rep_of.tolist() == [0, 1, 2, 2, 0, 0, 0, 2, 1, 2]
+    assert [(g["pool"], g["selected"], g["orphans"]) for g in log] == [(10, 3, 1), (0, 0, 0)]
+
+
 def test_schedules():
     assert loop.cosine_schedule(19, 20, 3) == [(93, 100), (47, 50), (19, 20)]
     assert loop.cosine_schedule(19, 20, 1) == [(19, 20)]
@@ -595,3 +668,43 @@ def test_xcorr_mirror_and_dominance():
         if a.any() and b.any():
             pcm = cosine.align(a, b, cosine.whiten(cosine.spectrum(a)), cosine.whiten(cosine.spectrum(b)), w, 1, 2)
             assert xcorr.align(a, b, w, 1, 2)["c"] >= pcm["c"]
+
+
+
+# ---------------------------------------------------------------- serving rule
+
+
+def test_serve_best_match_rule_on_a_table():
+    """The rule on hand-made pair results: request 0 is covered by library
+    clips 5 (0.96) and 2 (0.97) -> 2; request 1 by 7 and 3 with equal scores
+    -> 3 (lowest id), while library clip 1 scores higher without covering;
+    request 2 is covered by nobody -> -1."""
+    req = [0, 0, 1, 1, 1, 2, 0]
+    lib = [5, 2, 7, 3, 1, 4, 9]
+    bits = [True, True, True, True, False, False, False]
+    score = [0.96, 0.97, 0.99, 0.99, 1.0, 0.5, 0.999]
+    shift = [(1, 1), (2, -1), (0, 3), (-3, 0), (5, 5), (0, 0), (7, 7)]
+    best, sc, sh, matched = serve.best_match(3, req, lib, bits, score, np.array(shift))
+    assert best.tolist() == [2, 3, -1]
+    assert sc.tolist() == [0.97, 0.99, 0.0]
+    assert sh.tolist() == [[2, -1], [-3, 0], [0, 0]]
+    assert matched.tolist() == [1, 1, 0]
+
+
+def test_serve_match_on_translated_copies():
+    """End to end on 32 x 32 clips: the request clip R is a 6 x 6 square;
+    library clip 1 is R moved by (+1, +1) and clip 2 is R moved by (-2, 0),
+    both cover R with score exactly 1, so the lower id 1 wins and R's shift
+    relative to it is (-1, -1); library clip 0 (a 2 x 2 square) covers
+    nothing.  A second request clip (a 1 x 1 dot) matches no library clip."""
+    def cs(rect_lists):
+        ptr = np.cumsum([0] + [len(r) for r in rect_lists]).astype(np.int64)
+        rects = np.array([r for rl in rect_lists for r in rl], np.int32).reshape(-1, 4)
+        n = len(rect_lists)
+        return clipgen.ClipSet(ptr, rects, np.full(n, 32, np.int16), np.full(n, 4, np.int16),
+                               np.zeros(n, np.int32), np.zeros((n, 2), np.int16))
+    library = cs([[(0, 2, 0, 2)], [(11, 17, 11, 17)], [(10, 16, 8, 14)]])
+    request = cs([[(10, 16, 10, 16)], [(25, 26, 25, 26)]])
+    best, sc, sh, matched = serve.serve_match(library, request, 19, 20)
+    assert best.tolist() == [1, -1] and matched.tolist() == [1, 0]
+    assert sc.tolist() == [1.0, 0.0] and sh.tolist() == [[-1, -1], [0, 0]]
