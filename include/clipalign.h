@@ -257,6 +257,28 @@ ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
                          const int32_t* rep, const int32_t* mem, uint8_t* bits,
                          int16_t* shift, int32_t* count, double* score, uint32_t* flags);
 
+/* Allocation-free variant of ca_align_pairs, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, layouts and results as
+ * ca_align_pairs (all arrays are caller-owned device pointers), with these
+ * limits:
+ *   - n_pairs <= CA_NOALLOC_MAX_PAIRS (CA_EINVAL above it);
+ *   - cosine track: path CA_PATH_MIXED or CA_PATH_FP32 only, on clip sets that
+ *     keep FP64 spectra (CA_EUNSUPPORTED otherwise); the edge track as in
+ *     ca_align_pairs.
+ * The call makes no device allocation: its work space (the FP64 re-decision
+ * queue, counters and a validation word, about 26 MB) is one static array per
+ * device, set up by ca_create and held until the process ends.  Every call on
+ * a device shares that array, so calls that overlap in time on one device
+ * (from several threads or contexts, or on streams that run concurrently)
+ * race and must be serialised by the caller.  Synchronises `stream` as
+ * ca_align_pairs does. */
+#define CA_NOALLOC_MAX_PAIRS 1048576
+ca_status ca_align_pairs_noalloc(ca_ctx* ctx, void* stream, const ca_clipset* cs,
+                                 const ca_constraint* con, int32_t path, int64_t n_pairs,
+                                 const int32_t* rep, const int32_t* mem, uint8_t* bits,
+                                 int16_t* shift, int32_t* count, double* score, uint32_t* flags);
+
 /* Test and calibration access: the low-precision window surface of direction
  * 0 (member mem[k] against representative rep[k]) exactly as CA_PATH_MIXED or
  * CA_PATH_DIRECT computes it before any FP64 re-decision, for dy, dx in

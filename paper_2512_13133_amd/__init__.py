@@ -27,11 +27,12 @@ CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64, CA_CLIPS_IMAGE, CA_CLIPS_NO_
 FLAG_RESCORED_FWD, FLAG_RESCORED_REV, FLAG_EMPTY = 1, 2, 4
 FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16, 32, 64
 FLAG_INVALID = 128
+NOALLOC_MAX_PAIRS = 1 << 20
 
 SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
     "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect", "ca_clips_image", "ca_clips_spectrum",
-    "ca_align_pairs", "ca_surface", "ca_prune", "ca_cluster",
+    "ca_align_pairs", "ca_align_pairs_noalloc", "ca_surface", "ca_prune", "ca_cluster",
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
     "ca_server_stats", "ca_server_last_error",
     "ca_autotune_report", "ca_autotune_save", "ca_autotune_load", "ca_autotune_clear",
@@ -89,6 +90,8 @@ def load():
     lib.ca_clips_spectrum.argtypes = [P, C.c_int64, C.c_int32, P]
     lib.ca_align_pairs.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64,
                                    P, P, P, P, P, P, P]
+    lib.ca_align_pairs_noalloc.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64,
+                                           P, P, P, P, P, P, P]
     lib.ca_surface.argtypes = [P, P, P, C.c_int32, C.c_int64, P, P, P]
     lib.ca_prune.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int64, P, P, C.POINTER(C.c_int64)]
     lib.ca_cluster.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int32, P, P,
@@ -219,8 +222,10 @@ class Context:
         return out[..., 0] + 1j * out[..., 1]
 
     # -------------------------------------------------------------- pairs
-    def align_pairs(self, clips, rep, mem, kind="cosine", thr=(19, 20), path="mixed"):
-        """Align unordered pairs on the GPU; returns a dict of CUDA tensors."""
+    def align_pairs(self, clips, rep, mem, kind="cosine", thr=(19, 20), path="mixed", noalloc=False):
+        """Align unordered pairs on the GPU; returns a dict of CUDA tensors.
+        noalloc=True calls ca_align_pairs_noalloc (no device allocation inside
+        the library; at most NOALLOC_MAX_PAIRS pairs)."""
         torch = self.torch
         rep = torch.as_tensor(rep, dtype=torch.int32, device=self.dev).contiguous()
         mem = torch.as_tensor(mem, dtype=torch.int32, device=self.dev).contiguous()
@@ -233,10 +238,10 @@ class Context:
             flags=torch.empty(n, dtype=torch.int32, device=self.dev),
         )
         con = constraint(kind, thr)
-        self._check(self.lib.ca_align_pairs(self.h, self._stream(), clips.handle, C.byref(con),
-                                            PATHS[path], n, _ptr(rep), _ptr(mem), _ptr(out["bits"]),
-                                            _ptr(out["shift"]), _ptr(out["count"]), _ptr(out["score"]),
-                                            _ptr(out["flags"])))
+        fn = self.lib.ca_align_pairs_noalloc if noalloc else self.lib.ca_align_pairs
+        self._check(fn(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path], n, _ptr(rep), _ptr(mem),
+                       _ptr(out["bits"]), _ptr(out["shift"]), _ptr(out["count"]), _ptr(out["score"]),
+                       _ptr(out["flags"])))
         return out
 
     def surface(self, clips, rep, mem, path="mixed"):

@@ -73,6 +73,7 @@ struct ca_clipset {
 };
 
 static thread_local std::string g_create_err;
+static hipError_t noalloc_setup(int device);  // allocation-free work array, per device
 
 namespace {
 
@@ -162,7 +163,7 @@ ca_status scratch(ca_ctx* ctx, size_t bytes, void** out) {
 
 int axis_len(int w, int N) { return (2 * w + 1 <= N) ? 2 * w + 1 : N; }
 
-size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool valid_constraint(const ca_constraint* c) {
   if (!c) return false;
@@ -224,6 +225,13 @@ ca_status ca_create(const ca_config* cfg, ca_ctx** out) {
         hipMemcpy(ctx->mf_a2, a2.data(), a2.size() * 2, hipMemcpyHostToDevice) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
       g_create_err = "context set-up failed";
+      return CA_EDEVICE;
+    }
+  }
+  {
+    const hipError_t e = noalloc_setup(cfg->device);
+    if (e != hipSuccess) {
+      g_create_err = std::string("hipGetSymbolAddress of the allocation-free work array: ") + hipGetErrorString(e);
       return CA_EDEVICE;
     }
   }
@@ -567,13 +575,19 @@ ca_status ca_clips_spectrum(const ca_clipset* cs, int64_t i, int32_t precision, 
 
 namespace {
 
+// flag: a device word for the result (null: the context's scratch), cleared
+// here by a kernel.
 ca_status validate_pairs(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                         int64_t n_pairs, const int32_t* rep, const int32_t* mem, bool need_poly) {
-  void* sc;
-  ca_status st = scratch(ctx, 256, &sc);
-  if (st) return st;
-  int* bad = (int*)sc;
-  HIP_OR_FAIL(ctx, hipMemsetAsync(bad, 0, sizeof(int), s));
+                         int64_t n_pairs, const int32_t* rep, const int32_t* mem, bool need_poly,
+                         unsigned long long* flag = nullptr) {
+  if (!flag) {
+    void* sc;
+    ca_status st = scratch(ctx, 256, &sc);
+    if (st) return st;
+    flag = (unsigned long long*)sc;
+  }
+  int* bad = (int*)flag;
+  HIP_OR_FAIL(ctx, launch_zero_u64(flag, 1, s));
   HIP_OR_FAIL(ctx, launch_validate(crs->d, cms->d, n_pairs, rep, mem, need_poly ? 1 : 0, bad, s));
   int hbad = 0;
   HIP_OR_FAIL(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -619,7 +633,7 @@ struct QueueMem {
   CandQueue exact;  // groups the FP32 screen leaves to the FP64 pass (cq's shifts)
   unsigned long long* counters;
 };
-static size_t queue_bytes(int64_t n) {
+static constexpr size_t queue_bytes(int64_t n) {
   const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
   return align_up(n) + 2 * align_up(8 * (size_t)n) + 256 + 2 * align_up(sizeof(CandGroup) * (size_t)cap_g) +
          align_up(2 * (size_t)cap_s);
@@ -647,6 +661,37 @@ static QueueMem queue_carve(char* base, int64_t n) {
   m.exact.n_groups = m.counters + 8;
   m.exact.n_shifts = nullptr;
   return m;
+}
+
+// Allocation-free alignment (ca_align_pairs_noalloc): the queue of up to
+// CA_NOALLOC_MAX_PAIRS pairs and a validation word live in one static device
+// array, which each device holds from the library's first use on it until the
+// process ends.  Host code never names the array in a kernel argument or a
+// copy: it uses the device address taken once per device at context creation.
+static constexpr size_t NOALLOC_QUEUE_BYTES = queue_bytes(CA_NOALLOC_MAX_PAIRS);
+static constexpr size_t NOALLOC_BYTES = NOALLOC_QUEUE_BYTES + 256;
+static __device__ __align__(256) char g_noalloc_scratch[NOALLOC_BYTES];
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_noalloc_mu;
+static char* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// With `device` current: look up the array's address on it (once per device).
+static hipError_t noalloc_setup(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_noalloc_scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_noalloc_ptr[device] = (char*)p;
+  return hipSuccess;
+}
+
+static char* noalloc_base(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  return g_noalloc_ptr[device];
 }
 
 // The device sequence of a low-precision path (CA_PATH_FP32 or CA_PATH_MIXED):
@@ -762,9 +807,11 @@ static ca_status fp64_on_demand(ca_ctx* ctx, const ca_clipset* crs, const ca_cli
 // CA_PATH_DIRECT are skipped; `direct_n` then names the bucket's raster size
 // and `bucket_w` bounds its half-windows, so the per-pair FFT kernels are
 // planned (LDS per workgroup) for the bucket rather than for the whole set.
+// `qmem`: queue memory of at least queue_bytes(n) bytes supplied by the caller
+// (null: the context's scratch, grown on demand).
 static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
                               Threshold thr, int path, const PairIO& io, bool checked = false, int direct_n = 0,
-                              int bucket_w = 1 << 20) {
+                              int bucket_w = 1 << 20, char* qmem = nullptr) {
   int maxN = std::max(crs->maxN, cms->maxN), Lmax = std::max(crs->Lmax, cms->Lmax);
   if (checked && direct_n > 0) {
     maxN = direct_n;
@@ -814,9 +861,9 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
     if (direct_n != 64 && direct_n != 128 && direct_n != 256)
       return fail(ctx, CA_EINVAL, "CA_PATH_DIRECT raster size");
   }
-  void* sc;
-  ca_status st = scratch(ctx, queue_bytes(n), &sc);
-  if (st) return st;
+  void* sc = qmem;
+  ca_status st = CA_OK;
+  if (!sc && (st = scratch(ctx, queue_bytes(n), &sc)) != CA_OK) return st;
   const QueueMem qm = queue_carve((char*)sc, n);
   unsigned long long* counters = qm.counters;
   const int64_t cap_g = qm.cq.cap_groups;
@@ -902,6 +949,48 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
     return capriv::align_auto(ctx, cs, s, Threshold{con->thr_num, con->thr_den}, io);
   }
   return align_cosine(ctx, cs, cs, s, Threshold{con->thr_num, con->thr_den}, path, io);
+}
+
+extern "C" ca_status ca_align_pairs_noalloc(ca_ctx* ctx, void* stream, const ca_clipset* cs,
+                                            const ca_constraint* con, int32_t path, int64_t n_pairs,
+                                            const int32_t* rep, const int32_t* mem, uint8_t* bits,
+                                            int16_t* shift, int32_t* count, double* score, uint32_t* flags) {
+  if (!ctx) return CA_EINVAL;
+  if (!cs || cs->ctx != ctx) return fail(ctx, CA_EINVAL, "clip set of another context");
+  if (!valid_constraint(con)) return fail(ctx, CA_EINVAL, "bad constraint");
+  if (n_pairs < 0) return fail(ctx, CA_EINVAL, "negative pair count");
+  if (n_pairs > CA_NOALLOC_MAX_PAIRS)
+    return fail(ctx, CA_EINVAL, "ca_align_pairs_noalloc takes at most CA_NOALLOC_MAX_PAIRS (1,048,576) pairs; got " +
+                                    std::to_string(n_pairs));
+  if (n_pairs == 0) return CA_OK;
+  if (!rep || !mem || !bits || !shift || !count || !score || !flags)
+    return fail(ctx, CA_EINVAL, "null output or pair pointer");
+  const bool cosine = con->kind == CA_COSINE;
+  if (cosine) {
+    if (path != CA_PATH_MIXED && path != CA_PATH_FP32)
+      return fail(ctx, CA_EUNSUPPORTED, "ca_align_pairs_noalloc runs CA_PATH_MIXED or CA_PATH_FP32");
+    if (!cs->d.spec64)
+      return fail(ctx, CA_EUNSUPPORTED, "ca_align_pairs_noalloc needs stored FP64 spectra (no CA_CLIPS_NO_FP64)");
+    if (path == CA_PATH_MIXED && !cs->mixed_ok)
+      return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
+    if (path == CA_PATH_FP32 && !cs->d.spec32)
+      return fail(ctx, CA_ESTATE, "CA_PATH_FP32 needs a clip set created with CA_CLIPS_FP32");
+  }
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  char* base = noalloc_base(ctx->device);
+  if (!base) return fail(ctx, CA_ESTATE, "allocation-free work array not set up on this device");
+  hipStream_t s = (hipStream_t)stream;
+  ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, !cosine,
+                                (unsigned long long*)(base + NOALLOC_QUEUE_BYTES));
+  if (st) return st;
+  PairIO io{n_pairs, rep, mem, bits, shift, count, score, flags};
+  if (!cosine) {
+    HIP_OR_FAIL(ctx, launch_zero_u64((unsigned long long*)score, 2 * n_pairs, s));
+    HIP_OR_FAIL(ctx, launch_edge(cs->d, io, Threshold{con->thr_num, 1}, s));
+    ctx->stats.pairs_edge += n_pairs;
+    return CA_OK;
+  }
+  return align_cosine(ctx, cs, cs, s, Threshold{con->thr_num, con->thr_den}, path, io, false, 0, 1 << 20, base);
 }
 
 // ---- captured alignment ------------------------------------------------------
