@@ -146,6 +146,9 @@ typedef struct {
                                  left to the FP64 re-decision; without FP32 spectra, all groups */
   int64_t pairs_full_fp64;    /* of pairs_rescored, pairs whose whole window was re-evaluated in
                                  FP64 (their near-tied candidates overflowed the candidate list) */
+  int64_t cover_nnz;          /* entries of the last cover relation built (ca_cover, ca_cluster) */
+  int64_t members_verified;   /* members checked at their centers (ca_verify_centers, ca_cluster) */
+  int64_t center_violations;  /* of those, members that failed the check (0 for ca_cluster's output) */
 } ca_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -340,21 +343,82 @@ ca_status ca_graph_destroy(ca_graph* g);
 /* ---- multi-stage pruning (paper Sec. 3.1 stage 1, Table 2) --------------- */
 
 /* Candidate generation over all same-size unordered pairs of the clip set,
- * with safe bounds: pixel-area (B1) and row/column signature (B2) bounds for
- * CA_COSINE, and B1 plus polygon bounding-box size (B3) for CA_EDGE.  A
- * rejected pair can never pass `con`, so pruned results equal unpruned ones.
- * Output (device pointers): rep[k] < mem[k], sorted by (rep, mem); capacity
- * `cap` pairs.  *n_out (host) receives the survivor count; if it exceeds cap,
+ * with safe bounds.  CA_COSINE: the pixel-area bound (B1: a pair whose smaller
+ * pixel count n_min has n_min q^2 <= p^2 n_max cannot pass) and the row/column
+ * signature bound over the window (B2).  CA_EDGE: every same-size pair is a
+ * candidate of the polygon bounding-box size bound only (B3: every polygon of
+ * the side with fewer polygons needs a partner whose box width and height
+ * differ by at most 2 thr_num).  A rejected pair can never pass `con`, so
+ * pruned results equal unpruned ones.
+ * Output (device pointers): candidate pairs (rep[k], mem[k]), both directions
+ * to be aligned; CA_EDGE writes rep[k] < mem[k] sorted by (rep, mem), CA_COSINE
+ * groups the pairs by the anchor of the smaller pixel count; capacity `cap`
+ * pairs.  *n_out (host) receives the survivor count; if it exceeds cap,
  * nothing is written past cap and CA_ETRUNC is returned.  Synchronises. */
 ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
                    int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out);
 
+/* ---- the cover relation (paper Sec. 3.1 stage 2, the sparse similarity
+ *      graph consumed by the set cover of Sec. 3.3) --------------------------- */
+
+/* Prune (ca_prune's bounds), align both directions of every candidate pair
+ * (`path` for CA_COSINE, ignored for CA_EDGE) and compact the directions that
+ * pass `con` into a CSR relation sorted by (representative, member):
+ *   row r, entries row_ptr[r] .. row_ptr[r+1]-1, lists the clips m != r that r
+ *   covers (cosine: Eq. 2 strictly above thr_num/thr_den at the aligned shift;
+ *   edge: correspondence and residual <= thr_num), members ascending.  The
+ *   diagonal (every clip covers itself) is implicit.
+ *   row_ptr [n+1] int64, col [cap] int32 (member id),
+ *   shift [cap][2] int16 (member's (dy, dx) relative to r),
+ *   value [cap] int32 (cosine: overlap count c; edge: residual E),
+ *   score [cap] double (cosine c / sqrt(n_m n_r); edge 0).
+ * All output arrays are device pointers; any of col, shift, value, score may
+ * be NULL to skip it.  *nnz (host) always receives the number of entries.
+ * row_ptr == NULL sizes only.  If nnz > cap nothing is written and CA_ETRUNC
+ * is returned.  The relation is compacted on the device and kept on the
+ * context: a following call with the same clip set, constraint and path (the
+ * copying call after a sizing call, or ca_cluster's loosest threshold) reuses
+ * it.  Synchronises. */
+ca_status ca_cover(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con, int32_t path,
+                   int64_t cap, int64_t* row_ptr, int32_t* col, int16_t* shift, int32_t* value, double* score,
+                   int64_t* nnz);
+
+/* The same relation as a dense bit matrix for small sets (n <= 65,536):
+ * bits [n][ceil(n/64)] uint64 (device pointer), bit m % 64 of word
+ * r * ceil(n/64) + m / 64 set iff r covers m; the diagonal is set.
+ * CA_EUNSUPPORTED above CA_COVER_DENSE_MAX clips.  Synchronises. */
+#define CA_COVER_DENSE_MAX 65536
+ca_status ca_cover_dense(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con, int32_t path,
+                         uint64_t* bits);
+
+/* Center verification (paper Sec. 2.3: center validity and cluster
+ * consistency) of an assignment given as host arrays of length n:
+ * rep_of [n] int32 and center_shift [n][2] int16 (as ca_cluster writes them).
+ * A clip i is a violation if rep_of[i] is out of range, if a representative
+ * (rep_of[i] == i) has a non-zero shift, if rep_of[rep_of[i]] != rep_of[i], or
+ * if the constraint does not hold for i at its center against rep_of[i],
+ * recomputed on the device from the clips' rasters:
+ *   CA_COSINE: the shift is a residue of i's window (as in ca_align_pairs) and
+ *     the overlap count c at it satisfies c^2 q^2 > p^2 n_i n_r exactly;
+ *   CA_EDGE: |dy|, |dx| <= i's half-window, the polygons of the side with
+ *     fewer polygons (both if equal) each overlap exactly one polygon of the
+ *     other clip at the shift, and over their matched bounding-box edges
+ *     max |d - s| per axis is at most thr_num.
+ * *n_violations (host) receives the count, *first_violation (host, may be
+ * NULL) the smallest violating clip id or -1.  Synchronises. */
+ca_status ca_verify_centers(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                            const int32_t* rep_of, const int16_t* center_shift, int64_t* n_violations,
+                            int64_t* first_violation);
+
 /* ---- clustering: set cover and closed loop (paper Secs. 3.1, 3.3) -------- */
 
-/* Full method on a clip set: prune, align (path), surprisal lazy-greedy set
- * cover (Eqs. 7-9) inside the coarse-to-fine loop with `iterations` >= 1
- * relaxed-to-strict thresholds (cosine T - 0.02 (K-t)/(K-1); edge
- * T + (K - t) px), orphans re-injected.  Outputs are host arrays of length n:
+/* Full method on a clip set: the cover relation at the loosest threshold of
+ * the schedule (ca_cover), surprisal lazy-greedy set cover (Eqs. 7-9) inside
+ * the coarse-to-fine loop with `iterations` >= 1 relaxed-to-strict thresholds
+ * (cosine T - 0.02 (K-t)/(K-1); edge T + (K - t) px), orphans re-attached to
+ * the first representative that covers them strictly, then every member
+ * verified at its center (ca_verify_centers; a violation returns CA_ESTATE).
+ * The host holds O(n + nnz) memory.  Outputs are host arrays of length n:
  *   rep_of [n] int32: representative of each clip (itself for representatives)
  *   center_shift [n][2] int16: the clip's shift relative to its representative
  *   n_clusters: number of representatives. */

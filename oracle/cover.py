@@ -216,3 +216,83 @@ def _center_shift(n, rep, mem, shift, rep_of):
 
 def default_workers():
     return max(1, len(os.sched_getaffinity(0)))
+
+
+def cover_csr(n, rep, mem, bits, shift, value, score):
+    """The directed cover relation (Sec. 3.1 stage 2, the sparse similarity
+    graph) from per-pair results of both directions: an entry (r, m) for every
+    set bit, "r covers m", with m's shift relative to r, the count or residual
+    and the score.  Rows r ascending, members ascending within a row; the
+    diagonal (every clip covers itself) is left implicit.  Returns dict of
+    row_ptr int64[n+1], col int32, shift int16[:, 2], value int32, score f64."""
+    rows = [[] for _ in range(n)]
+    for k in range(len(rep)):
+        for d, (r, m) in enumerate(((int(rep[k]), int(mem[k])), (int(mem[k]), int(rep[k])))):
+            if (int(bits[k]) >> d) & 1:
+                rows[r].append((m, int(shift[k][d][0]), int(shift[k][d][1]), int(value[k][d]), float(score[k][d])))
+    row_ptr = np.zeros(n + 1, np.int64)
+    ent = []
+    for r in range(n):
+        row = sorted(rows[r])
+        ent += row
+        row_ptr[r + 1] = row_ptr[r] + len(row)
+    return dict(row_ptr=row_ptr,
+                col=np.array([e[0] for e in ent], np.int32),
+                shift=np.array([(e[1], e[2]) for e in ent], np.int16).reshape(-1, 2),
+                value=np.array([e[3] for e in ent], np.int32),
+                score=np.array([e[4] for e in ent], np.float64))
+
+
+def verify_centers(clips, rep_of, center_shift, kind, thr):
+    """Center validity and cluster consistency (Sec. 2.3) of an assignment:
+    the list of clips that violate it.  A representative represents itself
+    with shift (0, 0); every other clip i with representative r = rep_of[i]
+    must meet the constraint at its center against r:
+    cosine (thr = (p, q)): the shift is a residue of i's window (C0 rule) and
+    Eq. 2 holds for the overlap count at it;
+    edge (thr = T): the shift lies in i's window, at it the fewer side's
+    polygons (both sides if equal) each overlap exactly one polygon of the
+    other clip, and over the matched bounding-box edges max |d - s| <= T."""
+    bad = []
+    n = clips.n
+    for i in range(n):
+        r = int(rep_of[i])
+        dy, dx = int(center_shift[i][0]), int(center_shift[i][1])
+        if r < 0 or r >= n:
+            bad.append(i)
+            continue
+        if r == i:
+            if dy or dx:
+                bad.append(i)
+            continue
+        if int(rep_of[r]) != r or clips.raster_n[i] != clips.raster_n[r]:
+            bad.append(i)
+            continue
+        a_m, a_r = raster.clip_raster(clips, i), raster.clip_raster(clips, r)
+        w, N = int(clips.marker_w[i]), int(clips.raster_n[i])
+        if kind == "cosine":
+            axis = cosine.window_axis(w, N)
+            ok = dy in axis and dx in axis
+            if ok:
+                c = cosine.overlap(a_r, a_m, dy, dx)
+                ok = cosine.bit(c, int(a_m.sum()), int(a_r.sum()), thr[0], thr[1])
+        else:
+            ok = abs(dy) <= w and abs(dx) <= w
+            if ok:
+                lab_m, box_m = raster.components(a_m)
+                lab_r, box_r = raster.components(a_r)
+                Pm, Pr = box_m.shape[0], box_r.shape[0]
+                pairs = None
+                if Pm and Pr:
+                    pairs = edge.correspondence(edge.overlap_relation(lab_m, lab_r, Pm, Pr, dy, dx), Pm, Pr)
+                ok = pairs is not None
+                if ok:
+                    E = 0
+                    for p_, q_ in pairs:
+                        bm, br = box_m[p_ - 1], box_r[q_ - 1]
+                        E = max(E, abs(int(bm[0] - br[0]) - dx), abs(int(bm[1] - br[1]) - dx),
+                                abs(int(bm[2] - br[2]) - dy), abs(int(bm[3] - br[3]) - dy))
+                    ok = E <= thr
+        if not ok:
+            bad.append(i)
+    return bad

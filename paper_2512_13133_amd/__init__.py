@@ -33,6 +33,7 @@ SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
     "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect", "ca_clips_image", "ca_clips_spectrum",
     "ca_align_pairs", "ca_align_pairs_noalloc", "ca_surface", "ca_prune", "ca_cluster",
+    "ca_cover", "ca_cover_dense", "ca_verify_centers",
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
     "ca_server_stats", "ca_server_last_error",
     "ca_autotune_report", "ca_autotune_save", "ca_autotune_load", "ca_autotune_clear",
@@ -61,7 +62,8 @@ class _Stats(C.Structure):
                 ("max_surface_err", C.c_double), ("tie_band_mixed", C.c_double),
                 ("tie_band_fp32", C.c_double), ("tie_band_direct", C.c_double),
                 ("max_peak_err_sqrt", C.c_double), ("groups_exact", C.c_int64),
-                ("pairs_full_fp64", C.c_int64)]
+                ("pairs_full_fp64", C.c_int64), ("cover_nnz", C.c_int64),
+                ("members_verified", C.c_int64), ("center_violations", C.c_int64)]
 
 
 _LIB = None
@@ -96,6 +98,11 @@ def load():
     lib.ca_prune.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int64, P, P, C.POINTER(C.c_int64)]
     lib.ca_cluster.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int32, P, P,
                                C.POINTER(C.c_int64)]
+    lib.ca_cover.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64, P, P, P, P, P,
+                             C.POINTER(C.c_int64)]
+    lib.ca_cover_dense.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, P]
+    lib.ca_verify_centers.argtypes = [P, P, P, C.POINTER(_Constraint), P, P, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]
     lib.ca_server_create.argtypes = [P, P, C.POINTER(_Constraint), C.c_int32, C.c_uint64, C.POINTER(P)]
     lib.ca_server_destroy.argtypes = [P]
     lib.ca_server_submit.argtypes = [P, C.c_int64, P, P, P, P, C.POINTER(C.c_uint64)]
@@ -278,6 +285,48 @@ class Context:
         self._check(self.lib.ca_cluster(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path],
                                         int(iterations), _ptr(rep_of), _ptr(shift), C.byref(k)))
         return dict(rep_of=rep_of, center_shift=shift, n_clusters=int(k.value))
+
+    def cover(self, clips, kind="cosine", thr=(19, 20), path="mixed"):
+        """The cover relation as a CSR (``ca_cover``): dict(row_ptr, col, shift,
+        value, score) of CUDA tensors, rows sorted by member."""
+        torch = self.torch
+        con = constraint(kind, thr)
+        z = C.c_int64(0)
+        self._check(self.lib.ca_cover(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path], 0,
+                                      None, None, None, None, None, C.byref(z)))
+        nnz = z.value
+        m = max(nnz, 1)
+        out = dict(row_ptr=torch.empty(clips.n + 1, dtype=torch.int64, device=self.dev),
+                   col=torch.empty(m, dtype=torch.int32, device=self.dev),
+                   shift=torch.empty((m, 2), dtype=torch.int16, device=self.dev),
+                   value=torch.empty(m, dtype=torch.int32, device=self.dev),
+                   score=torch.empty(m, dtype=torch.float64, device=self.dev))
+        self._check(self.lib.ca_cover(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path], nnz,
+                                      _ptr(out["row_ptr"]), _ptr(out["col"]), _ptr(out["shift"]),
+                                      _ptr(out["value"]), _ptr(out["score"]), C.byref(z)))
+        for k in ("col", "shift", "value", "score"):
+            out[k] = out[k][:nnz]
+        return out
+
+    def cover_dense(self, clips, kind="cosine", thr=(19, 20), path="mixed"):
+        """Dense cover bits (``ca_cover_dense``) as a uint64 CUDA tensor [n, ceil(n/64)]."""
+        torch = self.torch
+        con = constraint(kind, thr)
+        words = (clips.n + 63) // 64
+        out = torch.empty((clips.n, words), dtype=torch.int64, device=self.dev)
+        self._check(self.lib.ca_cover_dense(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path],
+                                            _ptr(out)))
+        return out
+
+    def verify_centers(self, clips, rep_of, center_shift, kind="cosine", thr=(19, 20)):
+        """(violations, first violating clip or -1) of an assignment (``ca_verify_centers``)."""
+        rep_of = np.ascontiguousarray(rep_of, dtype=np.int32)
+        center_shift = np.ascontiguousarray(center_shift, dtype=np.int16).reshape(-1, 2)
+        con = constraint(kind, thr)
+        v, f = C.c_int64(0), C.c_int64(0)
+        self._check(self.lib.ca_verify_centers(self.h, self._stream(), clips.handle, C.byref(con), _ptr(rep_of),
+                                               _ptr(center_shift), C.byref(v), C.byref(f)))
+        return int(v.value), int(f.value)
 
     def graph(self, clips, n_pairs, thr=(19, 20)):
         """A captured CA_PATH_MIXED cosine alignment of a fixed pair buffer (``ca_graph_*``)."""

@@ -53,6 +53,7 @@ struct ca_ctx {
   // HIP events bracketing the main alignment kernel
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   capriv::PruneCache prune_cache;
+  capriv::CoverCache cover_cache;
   uint64_t next_gen = 1;
   std::map<int, capriv::TuneEntry> tune;  // autotuner choices by bucket key
 };
@@ -253,6 +254,7 @@ ca_status ca_destroy(ca_ctx* ctx) {
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->prune_cache.dev) (void)hipFree(ctx->prune_cache.dev);
+  if (ctx->cover_cache.dev) (void)hipFree(ctx->cover_cache.dev);
   delete ctx;
   return CA_OK;
 }
@@ -278,6 +280,7 @@ ca_status ca_clips_destroy(ca_clipset* cs) {
   if (!cs) return CA_EINVAL;
   (void)hipSetDevice(cs->ctx->device);
   if (cs->ctx->prune_cache.gen == cs->gen) cs->ctx->prune_cache.gen = 0;
+  if (cs->ctx->cover_cache.gen == cs->gen) cs->ctx->cover_cache.gen = 0;
   for (auto& pb : cs->owned) {
     (void)hipFree(pb.first);
     cs->ctx->used -= pb.second;
@@ -1128,6 +1131,7 @@ std::map<int, TuneEntry>& tune_of(ca_ctx* ctx) { return ctx->tune; }
 void set_stats(ca_ctx* ctx, const ca_run_stats& st) { ctx->stats = st; }
 uint64_t gen_of(const ca_clipset* cs) { return cs->gen; }
 PruneCache* prune_cache_of(ca_ctx* ctx) { return &ctx->prune_cache; }
+CoverCache* cover_cache_of(ca_ctx* ctx) { return &ctx->cover_cache; }
 }  // namespace capriv
 
 extern "C" ca_status ca_surface(ca_ctx* ctx, void* stream, const ca_clipset* cs, int32_t path,

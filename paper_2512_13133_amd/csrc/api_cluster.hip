@@ -30,6 +30,7 @@ int maxN_of(const ca_clipset* cs);
 bool mixed_ok_of(const ca_clipset* cs);
 uint64_t gen_of(const ca_clipset* cs);
 PruneCache* prune_cache_of(ca_ctx* ctx);
+CoverCache* cover_cache_of(ca_ctx* ctx);
 }  // namespace capriv
 
 using namespace ca;
@@ -249,61 +250,319 @@ extern "C" ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, c
   return prune_device(ctx, (hipStream_t)stream, cs, con, cap, cap > 0 ? rep : nullptr, mem, n_out);
 }
 
+// ------------------------------------------------------------------ cover relation
+
+namespace {
+
+// Device memory released at scope exit.
+struct DevBuf {
+  ca_ctx* c = nullptr;
+  void* p = nullptr;
+  size_t b = 0;
+  ~DevBuf() { free_ctx(c, p, b); }
+  ca_status alloc(ca_ctx* ctx, size_t bytes) {
+    c = ctx;
+    b = std::max<size_t>(bytes, 256);
+    ca_status st = alloc_ctx(ctx, &p, b);
+    if (st) b = 0;
+    return st;
+  }
+};
+
+bool cover_hit(const CoverCache* cc, const ca_clipset* cs, const ca_constraint* con, int path) {
+  return cc->gen != 0 && cc->gen == gen_of(cs) && cc->kind == con->kind && cc->p == con->thr_num &&
+         cc->q == con->thr_den && cc->path == path;
+}
+
+}  // namespace
+
+// The cover relation of `con` on the clip set (Sec. 3.1 stage 2): candidate
+// pairs from the safe bounds, both directions aligned with `path` (cosine)
+// or the edge track, and the set directions compacted on the device into a
+// CSR sorted by (representative, member), kept in the context's cache.
+static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con, int path,
+                             CoverCache** out) {
+  CoverCache* cc = cover_cache_of(ctx);
+  const int pth = con->kind == CA_COSINE ? path : -1;
+  *out = cc;
+  if (cover_hit(cc, cs, con, pth)) return CA_OK;
+  const int64_t n = n_of(cs);
+  int64_t np = 0;
+  ca_status st = prune_device(ctx, s, cs, con, 0, nullptr, nullptr, &np);
+  if (st) return st;
+  // candidate pairs, their results, row counts and cursors
+  const size_t b4 = aup(4 * (size_t)np), b_bits = aup((size_t)np), b_sh = aup(8 * (size_t)np),
+               b_cnt = aup(8 * (size_t)np), b_sc = aup(16 * (size_t)np), b_row = aup(8 * (size_t)n);
+  DevBuf work;
+  st = work.alloc(ctx, 3 * b4 + b_bits + b_sh + b_cnt + b_sc + 2 * b_row);
+  if (st) return st;
+  char* w = (char*)work.p;
+  int32_t* d_rep = (int32_t*)w; w += b4;
+  int32_t* d_mem = (int32_t*)w; w += b4;
+  uint32_t* d_flags = (uint32_t*)w; w += b4;
+  uint8_t* d_bits = (uint8_t*)w; w += b_bits;
+  int16_t* d_shift = (int16_t*)w; w += b_sh;
+  int32_t* d_count = (int32_t*)w; w += b_cnt;
+  double* d_score = (double*)w; w += b_sc;
+  unsigned long long* d_rowcnt = (unsigned long long*)w; w += b_row;
+  unsigned long long* d_fill = (unsigned long long*)w;
+  if (np > 0) {
+    int64_t got = 0;
+    st = prune_device(ctx, s, cs, con, np, d_rep, d_mem, &got);
+    if (st) return st;
+    st = ca_align_pairs(ctx, s, cs, con, path, np, d_rep, d_mem, d_bits, d_shift, d_count, d_score, d_flags);
+    if (st) return st;
+  }
+  HIP_TRY(ctx, launch_zero_u64(d_rowcnt, n, s));
+  HIP_TRY(ctx, launch_cover_count(np, d_rep, d_mem, d_bits, d_rowcnt, s));
+  std::vector<int64_t> cnt(n);
+  HIP_TRY(ctx, hipMemcpyAsync(cnt.data(), d_rowcnt, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  std::vector<int64_t> row_ptr(n + 1, 0);
+  std::vector<int32_t> small_rows, large_rows;
+  int64_t longest = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    row_ptr[r + 1] = row_ptr[r] + cnt[r];
+    if (cnt[r] > 64) large_rows.push_back((int32_t)r);
+    else if (cnt[r] > 1) small_rows.push_back((int32_t)r);
+    longest = std::max(longest, cnt[r]);
+  }
+  const int64_t nnz = row_ptr[n];
+  // the cache's arrays
+  free_ctx(ctx, cc->dev, cc->bytes);
+  cc->dev = nullptr;
+  cc->bytes = 0;
+  cc->gen = 0;
+  const size_t c_rp = aup(8 * (size_t)(n + 1)), c_col = aup(4 * (size_t)nnz), c_sh = aup(4 * (size_t)nnz),
+               c_val = aup(4 * (size_t)nnz), c_sc = aup(8 * (size_t)nnz);
+  const size_t c_bytes = c_rp + c_col + c_sh + c_val + c_sc;
+  st = alloc_ctx(ctx, &cc->dev, c_bytes);
+  if (st) return st;
+  cc->bytes = c_bytes;
+  char* c = (char*)cc->dev;
+  cc->row_ptr = (int64_t*)c; c += c_rp;
+  cc->col = (int32_t*)c; c += c_col;
+  cc->shift = (int16_t*)c; c += c_sh;
+  cc->value = (int32_t*)c; c += c_val;
+  cc->score = (double*)c;
+  HIP_TRY(ctx, hipMemcpyAsync(cc->row_ptr, row_ptr.data(), 8 * (size_t)(n + 1), hipMemcpyHostToDevice, s));
+  if (nnz > 0) {
+    // keys, merge space for rows above the LDS sort, and the row lists
+    const size_t k_keys = aup(8 * (size_t)nnz), k_tmp = longest > 4096 ? k_keys : 0,
+                 k_small = aup(4 * small_rows.size()), k_large = aup(4 * large_rows.size());
+    DevBuf kb;
+    st = kb.alloc(ctx, k_keys + k_tmp + k_small + k_large);
+    if (st) return st;
+    char* k = (char*)kb.p;
+    uint64_t* d_keys = (uint64_t*)k;
+    uint64_t* d_tmp = k_tmp ? (uint64_t*)(k + k_keys) : nullptr;
+    int32_t* d_small = (int32_t*)(k + k_keys + k_tmp);
+    int32_t* d_large = (int32_t*)(k + k_keys + k_tmp + k_small);
+    if (!small_rows.empty())
+      HIP_TRY(ctx, hipMemcpyAsync(d_small, small_rows.data(), 4 * small_rows.size(), hipMemcpyHostToDevice, s));
+    if (!large_rows.empty())
+      HIP_TRY(ctx, hipMemcpyAsync(d_large, large_rows.data(), 4 * large_rows.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, launch_zero_u64(d_fill, n, s));
+    HIP_TRY(ctx, launch_cover_scatter(np, d_rep, d_mem, d_bits, cc->row_ptr, d_fill, d_keys, s));
+    HIP_TRY(ctx, launch_cover_sort(d_small, (int64_t)small_rows.size(), d_large, (int64_t)large_rows.size(),
+                                   cc->row_ptr, d_keys, d_tmp, s));
+    HIP_TRY(ctx, launch_cover_gather(nnz, d_keys, d_shift, d_count, d_score, cc->col, cc->shift, cc->value,
+                                     cc->score, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+  } else {
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+  }
+  cc->gen = gen_of(cs);
+  cc->kind = con->kind;
+  cc->p = con->thr_num;
+  cc->q = con->thr_den;
+  cc->path = pth;
+  cc->n = n;
+  cc->nnz = nnz;
+  cc->h_row_ptr.swap(row_ptr);
+  stats_of(ctx)->cover_nnz = nnz;
+  return CA_OK;
+}
+
+static bool valid_con(const ca_constraint* con) {
+  if (!con) return false;
+  if (con->kind == CA_COSINE)
+    return con->thr_num >= 0 && con->thr_den > 0 && con->thr_num <= con->thr_den && con->thr_den <= (1 << 24);
+  if (con->kind == CA_EDGE) return con->thr_num >= 0 && con->thr_den == 1 && con->thr_num < (1 << 20);
+  return false;
+}
+
+extern "C" ca_status ca_cover(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                              int32_t path, int64_t cap, int64_t* row_ptr, int32_t* col, int16_t* shift,
+                              int32_t* value, double* score, int64_t* nnz) {
+  if (!ctx) return CA_EINVAL;
+  if (!cs || ctx_of(cs) != ctx || !nnz || cap < 0) return fail_ctx(ctx, CA_EINVAL, "bad arguments");
+  if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (con->kind == CA_COSINE && (path < CA_PATH_MIXED || path > CA_PATH_AUTO))
+    return fail_ctx(ctx, CA_EINVAL, "cover path must be CA_PATH_MIXED, CA_PATH_FP32, CA_PATH_FP64 or CA_PATH_AUTO");
+  HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
+  hipStream_t s = (hipStream_t)stream;
+  CoverCache* cc = nullptr;
+  ca_status st = cover_build(ctx, s, cs, con, path, &cc);
+  if (st) return st;
+  *nnz = cc->nnz;
+  if (!row_ptr) return CA_OK;
+  if (cc->nnz > cap) return fail_ctx(ctx, CA_ETRUNC, "cover buffers smaller than the relation (see *nnz)");
+  const int64_t n = cc->n, z = cc->nnz;
+  HIP_TRY(ctx, hipMemcpyAsync(row_ptr, cc->row_ptr, 8 * (size_t)(n + 1), hipMemcpyDeviceToDevice, s));
+  if (z > 0) {
+    if (col) HIP_TRY(ctx, hipMemcpyAsync(col, cc->col, 4 * (size_t)z, hipMemcpyDeviceToDevice, s));
+    if (shift) HIP_TRY(ctx, hipMemcpyAsync(shift, cc->shift, 4 * (size_t)z, hipMemcpyDeviceToDevice, s));
+    if (value) HIP_TRY(ctx, hipMemcpyAsync(value, cc->value, 4 * (size_t)z, hipMemcpyDeviceToDevice, s));
+    if (score) HIP_TRY(ctx, hipMemcpyAsync(score, cc->score, 8 * (size_t)z, hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return CA_OK;
+}
+
+extern "C" ca_status ca_cover_dense(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                                    int32_t path, uint64_t* bits) {
+  if (!ctx) return CA_EINVAL;
+  if (!cs || ctx_of(cs) != ctx || !bits) return fail_ctx(ctx, CA_EINVAL, "bad arguments");
+  if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (con->kind == CA_COSINE && (path < CA_PATH_MIXED || path > CA_PATH_AUTO))
+    return fail_ctx(ctx, CA_EINVAL, "cover path must be CA_PATH_MIXED, CA_PATH_FP32, CA_PATH_FP64 or CA_PATH_AUTO");
+  if (n_of(cs) > CA_COVER_DENSE_MAX) return fail_ctx(ctx, CA_EUNSUPPORTED, "dense cover matrix above 65,536 clips");
+  HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
+  hipStream_t s = (hipStream_t)stream;
+  CoverCache* cc = nullptr;
+  ca_status st = cover_build(ctx, s, cs, con, path, &cc);
+  if (st) return st;
+  const int64_t n = cc->n, words = (n + 63) / 64;
+  HIP_TRY(ctx, launch_zero_u64((unsigned long long*)bits, n * words, s));
+  HIP_TRY(ctx, launch_cover_dense(n, words, cc->row_ptr, cc->col, (unsigned long long*)bits, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return CA_OK;
+}
+
+// Center verification of an assignment (host arrays) on the device.
+static ca_status verify_centers(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
+                                const int32_t* rep_of, const int16_t* center_shift, int64_t* n_viol,
+                                int64_t* first_viol) {
+  const int64_t n = n_of(cs);
+  int64_t viol = 0, first = -1;
+  auto note = [&](int64_t i) {
+    ++viol;
+    if (first < 0 || i < first) first = i;
+  };
+  std::vector<int32_t> mem, rep;
+  std::vector<int16_t> sh;
+  std::vector<int64_t> who;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t r = rep_of[i];
+    if (r < 0 || r >= n) { note(i); continue; }
+    if (r == i) {
+      if (center_shift[2 * i] != 0 || center_shift[2 * i + 1] != 0) note(i);
+      continue;
+    }
+    if (rep_of[r] != r) { note(i); continue; }  // a representative represents itself
+    mem.push_back((int32_t)i);
+    rep.push_back(r);
+    sh.push_back(center_shift[2 * i]);
+    sh.push_back(center_shift[2 * i + 1]);
+    who.push_back(i);
+  }
+  const int64_t m = (int64_t)mem.size();
+  if (m > 0) {
+    DevBuf buf;
+    const size_t b4 = aup(4 * (size_t)m);
+    ca_status st = buf.alloc(ctx, 3 * b4 + 256);
+    if (st) return st;
+    char* p = (char*)buf.p;
+    int32_t* d_mem = (int32_t*)p;
+    int32_t* d_rep = (int32_t*)(p + b4);
+    int16_t* d_sh = (int16_t*)(p + 2 * b4);
+    unsigned long long* d_out = (unsigned long long*)(p + 3 * b4);
+    HIP_TRY(ctx, hipMemcpyAsync(d_mem, mem.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(d_rep, rep.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(d_sh, sh.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
+    const unsigned long long init[2] = {0ull, ~0ull};
+    HIP_TRY(ctx, hipMemcpyAsync(d_out, init, sizeof(init), hipMemcpyHostToDevice, s));
+    const Threshold thr{con->thr_num, con->thr_den};
+    if (con->kind == CA_COSINE)
+      HIP_TRY(ctx, launch_verify_cosine(dev_of(cs), m, d_mem, d_rep, d_sh, thr, d_out, d_out + 1, s));
+    else
+      HIP_TRY(ctx, launch_verify_edge(dev_of(cs), m, d_mem, d_rep, d_sh, thr, d_out, d_out + 1, s));
+    unsigned long long h[2];
+    HIP_TRY(ctx, hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    viol += (int64_t)h[0];
+    if (h[0] > 0) {
+      const int64_t i = who[(size_t)h[1]];
+      if (first < 0 || i < first) first = i;
+    }
+  }
+  ca_run_stats* rs = stats_of(ctx);
+  rs->members_verified += m;
+  rs->center_violations += viol;
+  *n_viol = viol;
+  if (first_viol) *first_viol = first;
+  return CA_OK;
+}
+
+extern "C" ca_status ca_verify_centers(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                                       const int32_t* rep_of, const int16_t* center_shift, int64_t* n_violations,
+                                       int64_t* first_violation) {
+  if (!ctx) return CA_EINVAL;
+  if (!cs || ctx_of(cs) != ctx || !rep_of || !center_shift || !n_violations)
+    return fail_ctx(ctx, CA_EINVAL, "bad arguments");
+  if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
+  return verify_centers(ctx, (hipStream_t)stream, cs, con, rep_of, center_shift, n_violations, first_violation);
+}
+
 // ------------------------------------------------------------------ set cover
 
 namespace {
 
-struct Dir {
-  int32_t r, m;  // representative covers member
-  int32_t val;   // cosine: overlap count; edge: residual E
-  bool ok;       // edge: correspondence found and re-checked
-  int16_t sy, sx;
-};
-
+// The cover relation on the host: CSR rows of representatives, entries that
+// pass the loosest threshold; the bit at any stricter threshold is decided
+// from the stored count (cosine) or residual (edge).
 struct Cover {
   int64_t n;
   int kind;
-  std::vector<Dir> dirs;
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col, value;
+  std::vector<int16_t> shift;
   const std::vector<int32_t>* npix;
-  bool bit(const Dir& d, int64_t p, int64_t q) const {
+  bool bit(int64_t r, int64_t e, int64_t p, int64_t q) const {
     if (kind == CA_COSINE) {
-      const int64_t nm = (*npix)[d.m], nr = (*npix)[d.r];
+      const int64_t nm = (*npix)[col[e]], nr = (*npix)[r];
       if (nm <= 0 || nr <= 0) return false;
-      const unsigned __int128 lhs = (unsigned __int128)((uint64_t)d.val * (uint64_t)d.val) *
-                                    (unsigned __int128)((uint64_t)q * (uint64_t)q);
+      const uint64_t c = (uint64_t)value[e];
+      const unsigned __int128 lhs = (unsigned __int128)(c * c) * (unsigned __int128)((uint64_t)q * (uint64_t)q);
       const unsigned __int128 rhs = (unsigned __int128)((uint64_t)p * (uint64_t)p) *
                                     (unsigned __int128)((uint64_t)nm * (uint64_t)nr);
       return lhs > rhs;
     }
-    return d.ok && d.val >= 0 && d.val <= p;
+    return value[e] >= 0 && value[e] <= p;
   }
 };
 
 // Surprisal lazy greedy on `pool` (ascending ids) with threshold (p, q).
 // Returns reps in selection order and fills assign[i] for pool members.
 std::vector<int32_t> lazy_greedy(const Cover& cv, const std::vector<int32_t>& pool, int64_t p, int64_t q,
-                                 std::vector<int32_t>& assign) {
-  const int64_t n = cv.n;
-  std::vector<int32_t> pos(n, -1);
+                                 std::vector<int32_t>& pos, std::vector<int32_t>& assign) {
   for (size_t a = 0; a < pool.size(); ++a) pos[pool[a]] = (int32_t)a;
   const size_t P = pool.size();
+  // out-neighbours within the pool; rows list members in ascending id, and
+  // positions ascend with ids, so each list is sorted and duplicate-free
   std::vector<std::vector<int32_t>> out(P);
   std::vector<int64_t> indeg(P, 0);
-  for (const Dir& d : cv.dirs) {
-    const int32_t a = pos[d.r], b = pos[d.m];
-    if (a < 0 || b < 0 || a == b) continue;
-    if (!cv.bit(d, p, q)) continue;
-    out[a].push_back(b);
-    indeg[b]++;
+  for (size_t a = 0; a < P; ++a) {
+    const int64_t r = pool[a];
+    for (int64_t e = cv.row_ptr[r]; e < cv.row_ptr[r + 1]; ++e) {
+      const int32_t b = pos[cv.col[e]];
+      if (b < 0 || !cv.bit(r, e, p, q)) continue;
+      out[a].push_back(b);
+      indeg[b]++;
+    }
   }
-  for (auto& o : out) {
-    std::sort(o.begin(), o.end());
-    o.erase(std::unique(o.begin(), o.end()), o.end());
-  }
-  // in-degree counts distinct covering nodes
-  std::fill(indeg.begin(), indeg.end(), 0);
-  for (size_t a = 0; a < P; ++a)
-    for (int32_t b : out[a]) indeg[b]++;
   std::vector<double> S(P);
   for (size_t a = 0; a < P; ++a) S[a] = 1.0 / (double)(1 + indeg[a]);
   std::vector<char> unc(P, 1);
@@ -345,6 +604,7 @@ std::vector<int32_t> lazy_greedy(const Cover& cv, const std::vector<int32_t>& po
         assign[pool[k]] = pool[top.j];
       }
   }
+  for (int32_t i : pool) pos[i] = -1;
   return reps;
 }
 
@@ -375,90 +635,69 @@ static ca_status cluster_impl(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, 
   ca_constraint loose = *con;
   loose.thr_num = sched[0].first;
   loose.thr_den = sched[0].second;
-  int64_t np = 0;
-  ca_status st = prune_device(ctx, s, cs, &loose, 0, nullptr, nullptr, &np);
+  // the relation at the loosest threshold, compacted on the device; the host
+  // holds O(n + nnz)
+  CoverCache* cc = nullptr;
+  ca_status st = cover_build(ctx, s, cs, &loose, path, &cc);
   if (st) return st;
-  // device buffers for the candidate list and alignment outputs
-  const size_t b4 = aup(4 * (size_t)std::max<int64_t>(np, 1));
-  const size_t bytes = 2 * b4 + aup((size_t)np + 1) + aup(8 * (size_t)np + 8) + aup(8 * (size_t)np + 8) +
-                       aup(16 * (size_t)np + 16) + b4;
-  void* buf = nullptr;
-  st = alloc_ctx(ctx, &buf, bytes);
-  if (st) return st;
-  struct Guard {
-    ca_ctx* c; void* p; size_t b;
-    ~Guard() { free_ctx(c, p, b); }
-  } guard{ctx, buf, bytes};
-  char* b = (char*)buf;
-  int32_t* d_rep = (int32_t*)b; b += b4;
-  int32_t* d_mem = (int32_t*)b; b += b4;
-  uint8_t* d_bits = (uint8_t*)b; b += aup((size_t)np + 1);
-  int16_t* d_shift = (int16_t*)b; b += aup(8 * (size_t)np + 8);
-  int32_t* d_count = (int32_t*)b; b += aup(8 * (size_t)np + 8);
-  double* d_score = (double*)b; b += aup(16 * (size_t)np + 16);
-  uint32_t* d_flags = (uint32_t*)b;
-  int64_t got = 0;
-  if (np > 0) {
-    st = prune_device(ctx, s, cs, &loose, np, d_rep, d_mem, &got);
-    if (st) return st;
-    st = ca_align_pairs(ctx, s, cs, &loose, path, np, d_rep, d_mem, d_bits, d_shift, d_count, d_score, d_flags);
-    if (st) return st;
-  }
-  std::vector<int32_t> hrep(np), hmem(np), hcount(2 * np);
-  std::vector<int16_t> hshift(4 * np);
-  std::vector<uint32_t> hflags(np);
-  if (np > 0) {
-    HIP_TRY(ctx, hipMemcpyAsync(hrep.data(), d_rep, 4 * np, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hmem.data(), d_mem, 4 * np, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hcount.data(), d_count, 8 * np, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hshift.data(), d_shift, 8 * np, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipMemcpyAsync(hflags.data(), d_flags, 4 * np, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-  }
   Cover cv;
   cv.n = n;
   cv.kind = con->kind;
   cv.npix = &hnpix_of(cs);
-  cv.dirs.reserve(2 * np);
-  for (int64_t k = 0; k < np; ++k) {
-    for (int d = 0; d < 2; ++d) {
-      Dir x;
-      x.r = d == 0 ? hrep[k] : hmem[k];
-      x.m = d == 0 ? hmem[k] : hrep[k];
-      x.val = hcount[2 * k + d];
-      const uint32_t bad = d == 0 ? (CA_FLAG_NO_MATCH_FWD | CA_FLAG_RECHECK_FWD)
-                                  : (CA_FLAG_NO_MATCH_REV | CA_FLAG_RECHECK_REV);
-      x.ok = !(hflags[k] & bad);
-      x.sy = hshift[4 * k + 2 * d];
-      x.sx = hshift[4 * k + 2 * d + 1];
-      cv.dirs.push_back(x);
-    }
+  cv.row_ptr = cc->h_row_ptr;
+  const int64_t nnz = cc->nnz;
+  cv.col.resize(nnz);
+  cv.value.resize(nnz);
+  cv.shift.resize(2 * nnz);
+  if (nnz > 0) {
+    HIP_TRY(ctx, hipMemcpyAsync(cv.col.data(), cc->col, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(cv.value.data(), cc->value, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(cv.shift.data(), cc->shift, 4 * (size_t)nnz, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
   }
   // strict relation as per-member lists of covering representatives
   const auto [ps, qs] = sched.back();
-  std::vector<std::vector<int32_t>> strict_in(n);
-  for (const Dir& d : cv.dirs)
-    if (d.r != d.m && cv.bit(d, ps, qs)) strict_in[d.m].push_back(d.r);
+  std::vector<int64_t> in_ptr(n + 1, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t e = cv.row_ptr[r]; e < cv.row_ptr[r + 1]; ++e)
+      if (cv.bit(r, e, ps, qs)) in_ptr[cv.col[e] + 1]++;
+  for (int64_t i = 0; i < n; ++i) in_ptr[i + 1] += in_ptr[i];
+  std::vector<int32_t> strict_in(in_ptr[n]);
+  {
+    std::vector<int64_t> cur(in_ptr.begin(), in_ptr.end() - 1);
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t e = cv.row_ptr[r]; e < cv.row_ptr[r + 1]; ++e)
+        if (cv.bit(r, e, ps, qs)) strict_in[cur[cv.col[e]]++] = (int32_t)r;
+  }
+  // strict bit of (r covers i), r != i: binary search of i in row r
+  auto find = [&](int32_t r, int32_t i) -> int64_t {
+    const auto b = cv.col.begin() + cv.row_ptr[r], e = cv.col.begin() + cv.row_ptr[r + 1];
+    const auto it = std::lower_bound(b, e, i);
+    return (it != e && *it == i) ? (int64_t)(it - cv.col.begin()) : -1;
+  };
   auto strict = [&](int32_t r, int32_t i) {
     if (r == i) return true;
-    const auto& v = strict_in[i];
-    return std::find(v.begin(), v.end(), r) != v.end();
+    const int64_t e = find(r, i);
+    return e >= 0 && cv.bit(r, e, ps, qs);
   };
-  std::vector<int32_t> pool(n), reps, rank(n, -1), assign(n, -1);
+  std::vector<int32_t> pool(n), reps, rank(n, -1), assign(n, -1), pos(n, -1);
   std::iota(pool.begin(), pool.end(), 0);
   std::vector<int32_t> out_rep(n, -1);
   for (int t = 0; t < K; ++t) {
+    // re-attach to the first representative (selection order) covering strictly
     std::vector<int32_t> remaining;
     for (int32_t i : pool) {
       int32_t best = -1;
-      for (int32_t r : strict_in[i])
+      for (int64_t x = in_ptr[i]; x < in_ptr[i + 1]; ++x) {
+        const int32_t r = strict_in[x];
         if (rank[r] >= 0 && (best < 0 || rank[r] < rank[best])) best = r;
+      }
       if (best >= 0) out_rep[i] = best;
       else remaining.push_back(i);
     }
     pool.swap(remaining);
     if (pool.empty()) continue;
-    std::vector<int32_t> sel = lazy_greedy(cv, pool, sched[t].first, sched[t].second, assign);
+    std::vector<int32_t> sel = lazy_greedy(cv, pool, sched[t].first, sched[t].second, pos, assign);
     for (int32_t r : sel) {
       rank[r] = (int32_t)reps.size();
       reps.push_back(r);
@@ -473,22 +712,27 @@ static ca_status cluster_impl(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, 
   }
   if (!pool.empty()) return fail_ctx(ctx, CA_ESTATE, "closed loop ended with orphans");
   // centers: each member's shift relative to its representative
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> by_member(n);  // (rep, dir index)
-  for (size_t x = 0; x < cv.dirs.size(); ++x) by_member[cv.dirs[x].m].emplace_back(cv.dirs[x].r, (int32_t)x);
   for (int64_t i = 0; i < n; ++i) {
     rep_of[i] = out_rep[i];
     int16_t sy = 0, sx = 0;
-    if (out_rep[i] != i)
-      for (auto& pr : by_member[i])
-        if (pr.first == out_rep[i]) {
-          sy = cv.dirs[pr.second].sy;
-          sx = cv.dirs[pr.second].sx;
-          break;
-        }
+    if (out_rep[i] != i) {
+      const int64_t e = find(out_rep[i], (int32_t)i);
+      if (e < 0) return fail_ctx(ctx, CA_ESTATE, "member without a cover entry to its representative");
+      sy = cv.shift[2 * e];
+      sx = cv.shift[2 * e + 1];
+    }
     center_shift[2 * i] = sy;
     center_shift[2 * i + 1] = sx;
   }
   *n_clusters = (int64_t)reps.size();
+  // every member satisfies the strict constraint at its center (recomputed
+  // on the device from the clips' rasters, exact integer arithmetic)
+  int64_t viol = 0, first = -1;
+  st = verify_centers(ctx, s, cs, con, rep_of, center_shift, &viol, &first);
+  if (st) return st;
+  if (viol > 0)
+    return fail_ctx(ctx, CA_ESTATE, ("center verification failed for " + std::to_string(viol) +
+                                     " clips (first: " + std::to_string(first) + ")").c_str());
   return CA_OK;
 }
 
@@ -499,8 +743,7 @@ extern "C" ca_status ca_cluster(ca_ctx* ctx, void* stream, const ca_clipset* cs,
   if (!cs || ctx_of(cs) != ctx || !rep_of || !center_shift || !n_clusters)
     return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (iterations < 1 || iterations > 64) return fail_ctx(ctx, CA_EINVAL, "iterations must be in [1, 64]");
-  if (!con || (con->kind != CA_COSINE && con->kind != CA_EDGE))
-    return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
   HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
   return cluster_impl(ctx, (hipStream_t)stream, cs, con, path, iterations, rep_of, center_shift, n_clusters);
 }

@@ -501,6 +501,72 @@ __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, 
 
 namespace ca {
 
+// Center verification (edge track, Sec. 2.2.2 at the member's center): the
+// shift lies in the member's window, the fewer side's polygons (both sides if
+// the counts are equal) each overlap exactly one polygon of the other clip at
+// the shift, and over the matched bounding-box edges the residual
+// max |d - s| per axis is at most T.  One wave per member.
+__global__ void __launch_bounds__(64) edge_verify_kernel(ClipsDev cs, int64_t n, int64_t t0, const int32_t* mem,
+                                                         const int32_t* rep, const int16_t* shift, Threshold thr,
+                                                         unsigned long long* viol, unsigned long long* first) {
+  __shared__ unsigned long long relM[MAX_POLY], relR[MAX_POLY];
+  __shared__ int sflag;
+  __shared__ int red[4][64];
+  const int lane = threadIdx.x;
+  const int64_t t = t0 + blockIdx.x;
+  if (t >= n) return;  // block-uniform
+  const int m = mem[t], r = rep[t];
+  const int N = cs.N[m];
+  const int sy = shift[2 * t], sx = shift[2 * t + 1];
+  const int w = cs.w[m];
+  const int Pm = cs.npoly[m], Pr = cs.npoly[r];
+  bool ok = cs.N[r] == N && sy >= -w && sy <= w && sx >= -w && sx <= w && Pm > 0 && Pr > 0;
+  if (ok) {
+    overlap_relation(cs, m, r, N, sy, sx, relM, relR);
+    ok = correspondence_ok(relM, relR, Pm, Pr, &sflag);
+  }
+  if (ok) {
+    const int16_t* bm = cs.boxes + (int64_t)m * MAX_POLY * 4;
+    const int16_t* br = cs.boxes + (int64_t)r * MAX_POLY * 4;
+    const bool from_member = Pm <= Pr;
+    const int P = from_member ? Pm : Pr;
+    int ex = 0, ey = 0;  // residual of this lane's matched pair at the given shift
+    if (lane < P) {
+      int p, q;
+      if (from_member) { p = lane; q = __ffsll((unsigned long long)relM[lane]) - 1; }
+      else { q = lane; p = __ffsll((unsigned long long)relR[lane]) - 1; }
+      const int16_t* a = bm + 4 * p;
+      const int16_t* b = br + 4 * q;
+      ex = max(abs(a[0] - b[0] - sx), abs(a[1] - b[1] - sx));
+      ey = max(abs(a[2] - b[2] - sy), abs(a[3] - b[3] - sy));
+    }
+    red[0][lane] = max(ex, ey);
+    __syncthreads();
+    for (int st = 32; st > 0; st >>= 1) {
+      if (lane < st) red[0][lane] = max(red[0][lane], red[0][lane + st]);
+      __syncthreads();
+    }
+    ok = (int64_t)red[0][0] <= thr.p;
+  }
+  if (!ok && lane == 0) {
+    atomicAdd(viol, 1ull);
+    atomicMin(first, (unsigned long long)t);
+  }
+}
+
+hipError_t launch_verify_edge(const ClipsDev& cs, int64_t n, const int32_t* mem, const int32_t* rep,
+                              const int16_t* shift, Threshold thr, unsigned long long* viol, unsigned long long* first,
+                              hipStream_t s) {
+  for (int64_t t0 = 0; t0 < n; t0 += LAUNCH_CHUNK) {
+    const int64_t nt = std::min<int64_t>(LAUNCH_CHUNK, n - t0);
+    hipLaunchKernelGGL(edge_verify_kernel, dim3((unsigned)nt), dim3(64), 0, s, cs, n, t0, mem, rep, shift, thr, viol,
+                       first);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_edge(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s) {
   if (io.n_pairs == 0) return hipSuccess;
   const int64_t groups = (io.n_pairs + EDGE_PAIRS_PER_GROUP - 1) / EDGE_PAIRS_PER_GROUP;

@@ -29,6 +29,26 @@ struct PruneCache {
   std::vector<int64_t> counts;
 };
 
+// The last cover relation built by ca_cover / ca_cluster (CSR sorted by
+// (representative, member), directions passing the constraint), kept on the
+// context so that a sizing call and the following copying call, or a cluster
+// call after a cover call, share it.  Device arrays in one allocation; the
+// host keeps the row pointers.
+struct CoverCache {
+  uint64_t gen = 0;  // clip-set generation (0 = empty)
+  int64_t kind = 0, p = 0, q = 0;
+  int path = -1;
+  int64_t n = 0, nnz = 0;
+  void* dev = nullptr;
+  size_t bytes = 0;
+  int64_t* row_ptr = nullptr;  // [n + 1]
+  int32_t* col = nullptr;      // [nnz]
+  int16_t* shift = nullptr;    // [nnz][2]
+  int32_t* value = nullptr;    // [nnz] cosine overlap count / edge residual
+  double* score = nullptr;     // [nnz]
+  std::vector<int64_t> h_row_ptr;
+};
+
 // Grow-only device region that a serving slot reuses for every request, so the
 // steady state makes no hipMalloc / hipFree calls (hipFree waits for the
 // device).  Allocations that do not fit fall back to hipMalloc.

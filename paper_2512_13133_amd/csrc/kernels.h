@@ -107,4 +107,31 @@ hipError_t launch_prune128(const ClipsDev& ca, const ClipsDev& cb, const PruneAr
 hipError_t launch_validate(const ClipsDev& cr, const ClipsDev& cm, int64_t n_pairs, const int32_t* rep,
                            const int32_t* mem, int need_poly, int* bad, hipStream_t s);
 
+// Cover compaction (cover.hip): row counts of the set directions, the keys
+// (member << 32 | 2 k + d) scattered to their rows, the per-row sort (rows of
+// <= 64 keys in small_rows, longer ones in large_rows; tmp: nnz keys of
+// merge space, needed when a row exceeds 4,096 keys), and the gather of
+// column, shift, count and score per sorted key.
+hipError_t launch_cover_count(int64_t n_pairs, const int32_t* rep, const int32_t* mem, const uint8_t* bits,
+                              unsigned long long* rowcnt, hipStream_t s);
+hipError_t launch_cover_scatter(int64_t n_pairs, const int32_t* rep, const int32_t* mem, const uint8_t* bits,
+                                const int64_t* row_ptr, unsigned long long* fill, uint64_t* keys, hipStream_t s);
+hipError_t launch_cover_sort(const int32_t* small_rows, int64_t n_small, const int32_t* large_rows, int64_t n_large,
+                             const int64_t* row_ptr, uint64_t* keys, uint64_t* tmp, hipStream_t s);
+hipError_t launch_cover_gather(int64_t nnz, const uint64_t* keys, const int16_t* shift, const int32_t* count,
+                               const double* score, int32_t* col, int16_t* col_shift, int32_t* value,
+                               double* col_score, hipStream_t s);
+// Dense relation bits (out zeroed by the caller; n x words 64-bit words).
+hipError_t launch_cover_dense(int64_t n, int64_t words, const int64_t* row_ptr, const int32_t* col,
+                              unsigned long long* out, hipStream_t s);
+// Center verification of n (member, representative, shift) triples: counts
+// the violations into *viol and the smallest violating index into *first
+// (callers clear *viol to 0 and *first to all ones).
+hipError_t launch_verify_cosine(const ClipsDev& cs, int64_t n, const int32_t* mem, const int32_t* rep,
+                                const int16_t* shift, Threshold thr, unsigned long long* viol,
+                                unsigned long long* first, hipStream_t s);
+hipError_t launch_verify_edge(const ClipsDev& cs, int64_t n, const int32_t* mem, const int32_t* rep,
+                              const int16_t* shift, Threshold thr, unsigned long long* viol, unsigned long long* first,
+                              hipStream_t s);
+
 }  // namespace ca

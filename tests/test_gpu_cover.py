@@ -1,0 +1,174 @@
+"""GPU parity of the cover relation (ca_cover, ca_cover_dense), the center
+verification (ca_verify_centers) and clusters built on the compacted cover,
+against the FP64 oracle.
+
+Bar: row pointers, members, shifts and counts/residuals bit-exact; scores
+within 1e-12 (both sides divide the same integers); clusters and centers
+bit-exact; zero violations on every cluster the library returns.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import clipgen
+from oracle import cover
+
+pytestmark = pytest.mark.gpu
+
+WORKERS = 8
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2512_13133_amd as ca
+    c = ca.Context(0)
+    yield c
+
+
+def _np(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def _check_csr(got, ref, label):
+    assert (got["row_ptr"] == ref["row_ptr"]).all(), f"{label}: row pointers"
+    assert (got["col"] == ref["col"]).all(), f"{label}: members"
+    assert (got["shift"] == ref["shift"]).all(), f"{label}: shifts"
+    assert (got["value"] == ref["value"]).all(), f"{label}: counts"
+    if ref["score"].size:
+        assert np.abs(got["score"] - ref["score"]).max() <= 1e-12, f"{label}: scores"
+
+
+def _dense_ref(n, csr):
+    words = (n + 63) // 64
+    out = np.zeros((n, words), np.uint64)
+    for r in range(n):
+        out[r, r >> 6] |= np.uint64(1) << np.uint64(r & 63)
+        for e in range(csr["row_ptr"][r], csr["row_ptr"][r + 1]):
+            m = int(csr["col"][e])
+            out[r, m >> 6] |= np.uint64(1) << np.uint64(m & 63)
+    return out
+
+
+@pytest.fixture(scope="module")
+def small_case():
+    cs = clipgen.small(n_clips=96)
+    rep, mem = clipgen.all_pairs(cs.n)
+    res = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
+    er = cover.align_pairs_edge(cs, rep, mem, 2, workers=WORKERS)
+    return cs, rep, mem, res, er
+
+
+def test_cover_csr_and_dense_equal_oracle_small(ctx, small_case):
+    cs, rep, mem, res, er = small_case
+    say(f"[cover] small n={cs.n} pairs={rep.size}")
+    h = ctx.clips(cs, fp32=True)
+    ref_c = cover.cover_csr(cs.n, rep, mem, res["bits"], res["shift"], res["c"], res["score"])
+    for path in ("fp32", "fp64", "auto"):
+        _check_csr(_np(ctx.cover(h, "cosine", (19, 20), path)), ref_c, f"cosine {path}")
+    dense = ctx.cover_dense(h, "cosine", (19, 20), "fp32").cpu().numpy().view(np.uint64)
+    assert (dense == _dense_ref(cs.n, ref_c)).all()
+    zeros = np.zeros_like(er["E"], dtype=np.float64)
+    ref_e = cover.cover_csr(cs.n, rep, mem, er["bits"], er["shift"], er["E"], zeros)
+    _check_csr(_np(ctx.cover(h, "edge", 2)), ref_e, "edge")
+    dense = ctx.cover_dense(h, "edge", 2).cpu().numpy().view(np.uint64)
+    assert (dense == _dense_ref(cs.n, ref_e)).all()
+    say(f"[cover] small: cosine nnz={ref_c['col'].size} edge nnz={ref_e['col'].size}")
+    h.close()
+
+
+def test_cover_csr_equals_oracle_c128_mixed(ctx):
+    """128 x 128 clips, window +-16, six templates: the batched mixed path with
+    its FP64 re-decision feeds the compaction."""
+    cs = clipgen.c128(n_clips=300, n_templates=6)
+    rep, mem = clipgen.all_pairs(cs.n)
+    say(f"[cover] c128 subset n={cs.n} pairs={rep.size}")
+    res = cover.align_pairs_cosine(cs, rep, mem, 19, 20, workers=WORKERS)
+    ref = cover.cover_csr(cs.n, rep, mem, res["bits"], res["shift"], res["c"], res["score"])
+    h = ctx.clips(cs, fp32=True)
+    got = _np(ctx.cover(h, "cosine", (19, 20), "mixed"))
+    _check_csr(got, ref, "c128 mixed")
+    lens = np.diff(ref["row_ptr"])
+    say(f"[cover] c128: nnz={ref['col'].size} longest row={lens.max()}")
+    assert lens.max() > 1  # rows that the one-wave sort has to order
+    h.close()
+
+
+def _translated_copies(n, seed):
+    """n copies of one template moved by offsets in [-8, 8]^2 (rectangles kept
+    inside [10, 118) so nothing is clipped): every ordered pair is an exact
+    circular translation by the offset difference, within the +-16 window."""
+    rng = np.random.default_rng(seed)
+    base = []
+    for _ in range(5):
+        x0, y0 = rng.integers(10, 90, 2)
+        base.append((x0, x0 + int(rng.integers(4, 28)), y0, y0 + int(rng.integers(4, 28))))
+    off = rng.integers(-8, 9, size=(n, 2)).astype(np.int16)
+    rects = np.array([(x0 + o[1], x1 + o[1], y0 + o[0], y1 + o[0]) for o in off for (x0, x1, y0, y1) in base],
+                     np.int32)
+    ptr = np.arange(0, 5 * n + 1, 5, dtype=np.int64)
+    return clipgen.ClipSet(ptr, rects, np.full(n, 128, np.int16), np.full(n, 16, np.int16), np.zeros(n, np.int32),
+                           off), off
+
+
+@pytest.mark.parametrize("n", [300, 4400])
+def test_cover_long_rows_of_translated_copies(ctx, n):
+    """Closed form at any size: every clip covers every other with count n_pix,
+    score 1 and shift o_m - o_r, so each row lists all other clips (rows of 299
+    take the LDS sort, rows of 4,399 the chunked merge)."""
+    cs, off = _translated_copies(n, seed=n)
+    say(f"[cover] translated copies n={n}")
+    h = ctx.clips(cs, fp32=True)
+    got = _np(ctx.cover(h, "cosine", (19, 20), "mixed"))
+    npix = int(ctx.inspect(h, 0, 128)["n_pix"][0])
+    assert (got["row_ptr"] == np.arange(0, n * n, n - 1, dtype=np.int64)[: n + 1]).all()
+    r = np.repeat(np.arange(n), n - 1)
+    m = np.concatenate([np.delete(np.arange(n), i) for i in range(n)])
+    assert (got["col"] == m).all()
+    assert (got["shift"] == (off[m] - off[r])).all()
+    assert (got["value"] == npix).all() and (got["score"] == 1.0).all()
+    h.close()
+
+
+@pytest.mark.parametrize("kind,thr,K", [("cosine", (19, 20), 1), ("cosine", (19, 20), 3), ("edge", 3, 3)])
+def test_cluster_on_compacted_cover_c128_mixed(ctx, kind, thr, K):
+    """Clusters of the mixed path equal the oracle's; every member passes the
+    device center verification; planted errors are reported."""
+    cs = clipgen.c128(n_clips=300, n_templates=6)
+    rep, mem = clipgen.all_pairs(cs.n)
+    say(f"[cluster] c128 subset {kind} K={K}")
+    h = ctx.clips(cs, fp32=True)
+    ctx.reset_stats()
+    got = ctx.cluster(h, kind, thr, iterations=K, path="mixed")
+    st = ctx.stats()
+    assert st["members_verified"] == int((got["rep_of"] != np.arange(cs.n)).sum())
+    assert st["center_violations"] == 0
+    if kind == "cosine":
+        ref = cover.cluster_cosine(cs, thr[0], thr[1], K=K, rep=rep, mem=mem, workers=WORKERS)
+    else:
+        ref = cover.cluster_edge(cs, thr, K=K, rep=rep, mem=mem, workers=WORKERS)
+    assert got["n_clusters"] == ref["n_clusters"]
+    assert (got["rep_of"] == ref["rep_of"]).all()
+    assert (got["center_shift"] == ref["shift"]).all()
+    assert ctx.verify_centers(h, got["rep_of"], got["center_shift"], kind, thr) == (0, -1)
+    # a member moved off its center by a full window, and a representative
+    # that no longer represents itself, are both caught (same as the oracle)
+    members = np.flatnonzero(got["rep_of"] != np.arange(cs.n))
+    if members.size:
+        i = int(members[0])
+        sh = got["center_shift"].copy()
+        sh[i] = (17, 17)
+        assert ctx.verify_centers(h, got["rep_of"], sh, kind, thr) == (1, i)
+        assert cover.verify_centers(cs, got["rep_of"], sh, kind, thr) == [i]
+        chain = got["rep_of"].copy()
+        r = int(chain[i])
+        chain[r] = i
+        nv, first = ctx.verify_centers(h, chain, got["center_shift"], kind, thr)
+        ref_bad = cover.verify_centers(cs, chain, got["center_shift"], kind, thr)
+        assert nv == len(ref_bad) and first == ref_bad[0]
+    h.close()

@@ -708,3 +708,63 @@ def test_serve_match_on_translated_copies():
     best, sc, sh, matched = serve.serve_match(library, request, 19, 20)
     assert best.tolist() == [1, -1] and matched.tolist() == [1, 0]
     assert sc.tolist() == [1.0, 0.0] and sh.tolist() == [[-1, -1], [0, 0]]
+
+
+
+# ---------------------------------------------------------------- cover relation and centers
+
+
+def test_cover_csr_lists_each_set_direction_once_sorted():
+    """Hand-made results of three pairs on five clips: (0,3) both directions,
+    (4,1) only 4 covers 1, (2,0) only 0 covers 2."""
+    rep = [0, 4, 2]
+    mem = [3, 1, 0]
+    bits = [3, 1, 2]
+    shift = np.array([[[1, 2], [-1, -2]], [[0, 5], [0, -5]], [[7, 7], [3, -3]]])
+    value = [[10, 10], [8, 9], [1, 4]]
+    score = [[0.9, 0.9], [0.8, 0.7], [0.1, 0.4]]
+    out = cover.cover_csr(5, rep, mem, bits, shift, value, score)
+    assert out["row_ptr"].tolist() == [0, 2, 2, 2, 3, 4]
+    assert out["col"].tolist() == [2, 3, 0, 1]
+    assert out["shift"].tolist() == [[3, -3], [1, 2], [-1, -2], [0, 5]]
+    assert out["value"].tolist() == [4, 10, 10, 8]
+    assert out["score"].tolist() == [0.4, 0.9, 0.9, 0.8]
+
+
+def test_oracle_clusters_pass_center_verification_and_planted_errors_fail():
+    """Every assignment the closed loop produces satisfies the strict
+    constraint at its centers (K = 1 and 3, both tracks); moving a member to a
+    clip that does not cover it, shifting it off its center, or naming a
+    non-representative as representative is reported."""
+    cs = clipgen.small(n_clips=40)
+    rep, mem = clipgen.all_pairs(cs.n)
+    res = cover.align_pairs_cosine(cs, rep, mem, 19, 20)
+    er = cover.align_pairs_edge(cs, rep, mem, 2)
+    for K in (1, 3):
+        cl = cover.cluster_cosine(cs, 19, 20, K=K, rep=rep, mem=mem, res=res)
+        assert cover.verify_centers(cs, cl["rep_of"], cl["shift"], "cosine", (19, 20)) == []
+        ce = cover.cluster_edge(cs, 2, K=K, rep=rep, mem=mem, res=er)
+        assert cover.verify_centers(cs, ce["rep_of"], ce["shift"], "edge", 2) == []
+    cl = cover.cluster_cosine(cs, 19, 20, K=1, rep=rep, mem=mem, res=res)
+    rep_of, sh = cl["rep_of"].copy(), cl["shift"].copy()
+    members = [i for i in range(cs.n) if rep_of[i] != i]
+    assert members
+    i = members[0]
+    r = int(rep_of[i])
+    # a representative that does not cover i at any shift of its window
+    others = [j for j in range(cs.n) if rep_of[j] == j and j != r]
+    a_i = raster.clip_raster(cs, i)
+    far = next(j for j in others
+               if not any(cosine.bit(cosine.overlap(raster.clip_raster(cs, j), a_i, dy, dx), int(a_i.sum()),
+                                     int(raster.clip_raster(cs, j).sum()), 19, 20)
+                          for dy, dx in cosine.window(int(cs.marker_w[i]), 64)))
+    moved = rep_of.copy()
+    moved[i] = far
+    assert cover.verify_centers(cs, moved, sh, "cosine", (19, 20)) == [i]
+    off = sh.copy()
+    off[i] = (9, 9)  # outside the 17 x 17 window
+    assert cover.verify_centers(cs, rep_of, off, "cosine", (19, 20)) == [i]
+    chain = rep_of.copy()
+    chain[r] = i  # r no longer represents itself: r and its members fail
+    bad = cover.verify_centers(cs, chain, sh, "cosine", (19, 20))
+    assert r in bad and i in bad
