@@ -50,6 +50,9 @@ struct ca_ctx {
   // MFMA fragment tables of the mixed path (raster 128)
   void* mf_b1 = nullptr;
   void* mf_a2 = nullptr;
+  // MFMA fragment tables of the mixed path for other raster sizes and windows,
+  // by (raster code, window blocks): b1 then a2 in one allocation, made on first use
+  void* gen_tab[3][6] = {};
   // HIP events bracketing the main alignment kernel
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   capriv::PruneCache prune_cache;
@@ -69,6 +72,7 @@ struct ca_clipset {
   std::vector<int32_t> hnpix, hnpoly;
   int maxN = 0, minN = 1 << 30, Lmax = 0;
   bool mixed_ok = false;  // every clip is 128 x 128 with half-window <= 16
+  int wmax = 0;           // largest half-window
   bool direct_ok = false; // whitened images kept, rasters <= 256, half-windows <= 7
   uint64_t gen = 0;       // unique per clip set within its context
 };
@@ -251,6 +255,9 @@ ca_status ca_destroy(ca_ctx* ctx) {
   if (ctx->fp64_spec) (void)hipFree(ctx->fp64_spec);
   if (ctx->mf_b1) (void)hipFree(ctx->mf_b1);
   if (ctx->mf_a2) (void)hipFree(ctx->mf_a2);
+  for (auto& row : ctx->gen_tab)
+    for (void* t : row)
+      if (t) (void)hipFree(t);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->prune_cache.dev) (void)hipFree(ctx->prune_cache.dev);
@@ -361,8 +368,10 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
     cs->Lmax = std::max(cs->Lmax, axis_len(hw[i], N));
   }
   cs->mixed_ok = true;
-  for (int64_t i = 0; i < n; ++i)
+  for (int64_t i = 0; i < n; ++i) {
     if (hN[i] != 128 || hw[i] > 16) cs->mixed_ok = false;
+    cs->wmax = std::max<int>(cs->wmax, hw[i]);
+  }
   const bool image = (flags & CA_CLIPS_IMAGE) != 0;
   cs->direct_ok = image;
   for (int64_t i = 0; i < n; ++i)
@@ -701,9 +710,31 @@ static char* noalloc_base(int device) {
 // counters cleared by a kernel, the main surface kernel (bracketed by the
 // context's events when `events`), then the FP64 re-decision sized on the
 // device.  No host synchronisation, so it can be captured in a graph.
+// The fragment tables of the general MFMA kernel for (N, NB), built on the
+// host in FP64 and uploaded on first use (a few hundred KB at most).
+static ca_status ensure_gen_tables(ca_ctx* ctx, int N, int NB) {
+  void*& t = ctx->gen_tab[N == 64 ? 0 : (N == 128 ? 1 : 2)][NB];
+  if (t) return CA_OK;
+  std::vector<_Float16> tab(mfma_gen_table_halves(N, NB));
+  build_mfma_gen_tables(N, NB, tab.data(), tab.data() + (size_t)(N / 32) * NB * 64 * 8);
+  void* p = nullptr;
+  ca_status st = dev_alloc(ctx, &p, tab.size() * 2, nullptr);
+  if (st) return st;
+  const hipError_t e = hipMemcpy(p, tab.data(), tab.size() * 2, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    ctx->used -= tab.size() * 2;
+    return fail(ctx, CA_EDEVICE, std::string("fragment table upload: ") + hipGetErrorString(e));
+  }
+  t = p;
+  return CA_OK;
+}
+
+// gen_nb > 0: CA_PATH_MIXED runs the general MFMA kernel on raster maxN with
+// gen_nb x gen_nb window blocks (0: the 128 x 128 kernel for half-windows <= 16).
 static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev& cm, int maxN, int Lmax, int path,
                                  Threshold thr, const PairIO& io, const QueueMem& m, hipStream_t s, bool events,
-                                 int direct_n = 0, bool fp64_pass = true) {
+                                 int direct_n = 0, bool fp64_pass = true, int gen_nb = 0) {
   const int64_t n = io.n_pairs;
   hipError_t e = launch_zero_u64(m.counters, 32, s);
   if (e != hipSuccess) return e;
@@ -714,6 +745,11 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
                          m.q, s);
   } else if (path == CA_PATH_DIRECT) {
     e = launch_pcm_direct(cr, cm, io, direct_n, thr, (float)BAND_DIRECT, m.q, m.cq, nullptr, m.counters + 4, s);
+  } else if (gen_nb > 0) {
+    const _Float16* tab = (const _Float16*)ctx->gen_tab[maxN == 64 ? 0 : (maxN == 128 ? 1 : 2)][gen_nb];
+    if (!tab) return hipErrorNotInitialized;  // made by ensure_gen_tables before any launch
+    e = launch_pcm_mfma_gen(maxN, gen_nb, cr, cm, io, thr, (float)BAND_MIXED, m.q, m.cq, tab,
+                            tab + (size_t)(maxN / 32) * gen_nb * 64 * 8, m.counters + 4, s);
   } else {
     e = launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, m.q, m.cq, ctx->mf_b1, ctx->mf_a2, nullptr,
                            m.counters + 4, s);
@@ -851,8 +887,27 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   }
   if (path == CA_PATH_FP32 && (!cr.spec32 || !cm.spec32))
     return fail(ctx, CA_ESTATE, "CA_PATH_FP32 needs a clip set created with CA_CLIPS_FP32");
-  if (path == CA_PATH_MIXED && !checked && (!crs->mixed_ok || !cms->mixed_ok))
-    return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs 128 x 128 clips with half-windows <= 16");
+  // CA_PATH_MIXED: the 128 x 128 kernel for half-windows <= 16, else the
+  // general kernel with enough window blocks for the largest half-window
+  int gen_nb = 0;
+  if (path == CA_PATH_MIXED) {
+    int N = maxN, wb = std::max(crs->wmax, cms->wmax);
+    if (checked && direct_n > 0) {
+      N = direct_n;
+      wb = bucket_w;
+    } else if (!(crs->mixed_ok && cms->mixed_ok) &&
+               (crs->minN != crs->maxN || cms->minN != cms->maxN || crs->maxN != cms->maxN)) {
+      return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED needs clip sets of one raster size (CA_PATH_AUTO mixes sizes)");
+    }
+    if (N > 64) wb = std::min(wb, 32);
+    if (!(N == 128 && wb <= 16)) {
+      gen_nb = mfma_gen_blocks(N, wb);
+      if (gen_nb <= 0) return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_MIXED: half-window above 32");
+      maxN = N;
+      ca_status st = ensure_gen_tables(ctx, N, gen_nb);
+      if (st) return st;
+    }
+  }
   if (path == CA_PATH_DIRECT) {
     if (!DIRECT_ENABLED) return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_DIRECT is switched off in this library");
     if (!cr.img16 || !cm.img16) return fail(ctx, CA_ESTATE, "CA_PATH_DIRECT needs clip sets made with CA_CLIPS_IMAGE");
@@ -870,7 +925,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   const QueueMem qm = queue_carve((char*)sc, n);
   unsigned long long* counters = qm.counters;
   const int64_t cap_g = qm.cq.cap_groups;
-  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n, !on_demand));
+  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n, !on_demand, gen_nb));
   unsigned long long h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
@@ -886,7 +941,8 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
     HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     ctx->stats.t_main_ms += ms;
     ctx->stats.n_main_launch += 1;
-    if (path == CA_PATH_MIXED) ctx->stats.main_alg_bytes += (double)n * (33280.0 + 2048.0);
+    if (path == CA_PATH_MIXED)  // the member's FP16 half-spectrum and bit raster per pair
+      ctx->stats.main_alg_bytes += (double)n * (4.0 * maxN * (maxN / 2 + 1) + maxN * maxN / 8.0);
     else if (path == CA_PATH_DIRECT) ctx->stats.main_alg_bytes += (double)n * (2.0 * direct_n * direct_n + direct_n * direct_n / 8.0);
     else ctx->stats.main_alg_bytes += io_bytes_fp32(maxN, n);
   }

@@ -167,7 +167,7 @@ ca_status tune_bucket(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshol
   e.us_per_kpair[CA_PATH_FP64] = us;
   e.path = CA_PATH_FP64;
   double best = us;
-  const bool mixed_ok = N == 128 && W_BOUND[wc] <= 16;
+  const bool mixed_ok = true;  // the batched MFMA kernels cover every raster size and window class
   const bool direct_ok = W_BOUND[wc] <= 7 && has_image_of(cs);
   for (int path : {CA_PATH_MIXED, CA_PATH_DIRECT, CA_PATH_FP32}) {
     if (path == CA_PATH_MIXED && !mixed_ok) continue;

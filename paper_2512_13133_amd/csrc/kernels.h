@@ -68,6 +68,16 @@ void build_mfma128_tables(_Float16* b1, _Float16* a2);
 hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr, float band,
                               const RescoreQueue& q, const CandQueue& cq, const void* b1frag,
                               const void* a2frag, float* surf_out, unsigned long long* tiles, hipStream_t s);
+// Batched MFMA surface for rasters 64, 128 and 256 with NB x NB blocks of 16
+// window positions per axis (shifts [-8 NB, 8 NB - 1]); mfma_gen_blocks gives
+// the NB a half-window needs (0: unsupported), the fragment tables (b1 then
+// a2, mfma_gen_table_halves halves) come from build_mfma_gen_tables.
+int mfma_gen_blocks(int N, int half_window);
+size_t mfma_gen_table_halves(int N, int NB);
+void build_mfma_gen_tables(int N, int NB, _Float16* b1, _Float16* a2);
+hipError_t launch_pcm_mfma_gen(int N, int NB, const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
+                               float band, const RescoreQueue& q, const CandQueue& cq, const void* b1, const void* a2,
+                               unsigned long long* tiles, hipStream_t s);
 // FP64 re-decision of queued directions at their candidate shifts: the group
 // count is read on the device (*cq.n_groups, at most cq.cap_groups).  With
 // FP32 spectra on both sides and `exact.groups` set, a screen over the FP32

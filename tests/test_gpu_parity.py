@@ -618,9 +618,12 @@ def test_graph_replays_match_eager(ctx):
     h.close()
 
 
-def test_mixed_rejects_other_shapes(ctx):
+def test_mixed_rejects_mixed_raster_sizes(ctx):
+    """CA_PATH_MIXED takes clip sets of one raster size; sets that mix sizes
+    go through CA_PATH_AUTO."""
     import paper_2512_13133_amd as ca
-    h = ctx.clips(small_set(8))
+    cs = mixed_set()
+    h = ctx.clips(cs)
     with pytest.raises(ca.ClipAlignError) as e:
         ctx.align_pairs(h, [0], [1], "cosine", (19, 20), "mixed")
     assert e.value.status == ca.CA_EUNSUPPORTED
