@@ -78,8 +78,15 @@ __device__ __forceinline__ int wave_overlap_n(const uint64_t* rep, const uint64_
   return wave_sum(c);
 }
 
+// Waves per SIMD the register allocation is held to: two where that fits
+// without spilling (measured on the compiler's resource report), else one.
 template <int N, int NB>
-__global__ void __launch_bounds__(GEN_THREADS, 1)
+constexpr int gen_min_waves() {
+  return (N == 64 && NB <= 3) || (N == 128 && NB == 3) ? 2 : 1;
+}
+
+template <int N, int NB>
+__global__ void __launch_bounds__(GEN_THREADS, (gen_min_waves<N, NB>()))
 pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, RescoreQueue q, CandQueue cq,
                     const h8_t* b1frag, const h8_t* a2frag, unsigned long long* tiles, int64_t n_tiles) {
   using S = GenShape<N, NB>;
@@ -167,7 +174,9 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
 #pragma unroll
         for (int b = 0; b < NB; ++b) D2[a][b] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-      auto block = [&](int mb, const uint4* mv, const uint4* rv) {
+      // stage 1 of block mb: T(u, dx) for the block's 16 rows into D1
+      f4_t D1[2 * NB];  // D1[2 nb] = Tr, D1[2 nb + 1] = Ti at dx = 16 nb + col - C
+      auto stage1 = [&](const uint4* mv, const uint4* rv) {
         // Nyquist column v = N/2 for the lane's rows 16 mb + 4 g + t: R(u, N/2)
         // (-1)^dx starts the accumulation; dx has the parity of col in every block
         f4_t N_re, N_im;
@@ -180,7 +189,6 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
           N_re = f4_t{sgn_lo(n0, sg), sgn_lo(n1, sg), sgn_lo(n2, sg), sgn_lo(n3, sg)};
           N_im = f4_t{sgn_hi(n0, sg), sgn_hi(n1, sg), sgn_hi(n2, sg), sgn_hi(n3, sg)};
         }
-        f4_t D1[2 * NB];  // D1[2 nb] = Tr, D1[2 nb + 1] = Ti at dx = 16 nb + col - C
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           D1[2 * nb] = N_re;
@@ -202,7 +210,9 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
             D1[2 * nb + 1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1n, B1, D1[2 * nb + 1], 0, 0, 0);
           }
         }
-        // stage 2: the B operand (u, re/im) x dx straight from the stage-1 block
+      };
+      // stage 2 of block mb: the B operand (u, re/im) x dx straight from D1
+      auto stage2 = [&](int mb) {
 #pragma unroll
         for (int db = 0; db < NB; ++db) {
           h2_t hi[4], lo[4];
@@ -220,26 +230,35 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
           }
         }
       };
-      // blocks double-buffered in registers: block mb + 1 (or the next pair's
-      // block 0) loads while block mb computes
+      // The member's blocks are double-buffered in registers (block mb + 1, or
+      // the next pair's block 0, loads while block mb computes).  The
+      // representative's block, mostly a cache hit (consecutive pairs share it),
+      // has one buffer: the next block loads into it as soon as stage 1 has
+      // consumed it, and arrives during stage 2.
       if (!have0) {
         load_block<N>(mrs, 0, col, g, m_cur);
         load_block<N>(rrs, 0, col, g, r_cur);
       }
+      const __amdgpu_buffer_rsrc_t mrs_next =
+          __builtin_amdgcn_make_buffer_rsrc((void*)mnext, (short)0, nbytes, MF_RSRC_WORD3);
+      const __amdgpu_buffer_rsrc_t rrs_next =
+          __builtin_amdgcn_make_buffer_rsrc((void*)rnext, (short)0, nbytes, MF_RSRC_WORD3);
 #pragma unroll 1
       for (int mb = 0; mb < MB; mb += 2) {
-        uint4 m_odd[KB + 1], r_odd[KB + 1];
+        uint4 m_odd[KB + 1];
         load_block<N>(mrs, mb + 1, col, g, m_odd);
-        load_block<N>(rrs, mb + 1, col, g, r_odd);
         __builtin_amdgcn_sched_barrier(0);
-        block(mb, m_cur, r_cur);
+        stage1(m_cur, r_cur);
+        load_block<N>(rrs, mb + 1, col, g, r_cur);
+        __builtin_amdgcn_sched_barrier(0);
+        stage2(mb);
         const bool last = mb == MB - 2;
-        load_block<N>(last ? __builtin_amdgcn_make_buffer_rsrc((void*)mnext, (short)0, nbytes, MF_RSRC_WORD3) : mrs,
-                      last ? 0 : mb + 2, col, g, m_cur);
-        load_block<N>(last ? __builtin_amdgcn_make_buffer_rsrc((void*)rnext, (short)0, nbytes, MF_RSRC_WORD3) : rrs,
-                      last ? 0 : mb + 2, col, g, r_cur);
+        load_block<N>(last ? mrs_next : mrs, last ? 0 : mb + 2, col, g, m_cur);
         __builtin_amdgcn_sched_barrier(0);
-        block(mb + 1, m_odd, r_odd);
+        stage1(m_odd, r_cur);
+        load_block<N>(last ? rrs_next : rrs, last ? 0 : mb + 2, col, g, r_cur);
+        __builtin_amdgcn_sched_barrier(0);
+        stage2(mb + 1);
       }
       have0 = has_next;
 
