@@ -55,10 +55,17 @@ typedef struct ca_server ca_server;
 
 /* Context configuration.  device: HIP device ordinal.  hbm_budget_bytes: cap
  * on the library's own device allocations (0 = no cap); allocations that would
- * exceed it fail with CA_ENOMEM instead of exhausting HBM. */
+ * exceed it fail with CA_ENOMEM instead of exhausting HBM.
+ * check_sample: pairs per CA_PATH_MIXED alignment call that the low-precision
+ * pass decided (no FP64 re-decision) and that are nevertheless re-evaluated on
+ * the full FP64 surface, as a run-time check of the decision band: 0 = 1,024,
+ * negative = none, at most 4,096 and at most one pair in 256 of the call
+ * (spread evenly over the call's pairs, the same pairs for equal pair
+ * counts; the autotuner's timing runs check none).  A checked pair whose answer changes keeps the
+ * FP64 answer and is counted in ca_run_stats.check_changed. */
 typedef struct {
   int32_t device;
-  int32_t reserved;
+  int32_t check_sample;
   uint64_t hbm_budget_bytes;
 } ca_config;
 
@@ -76,8 +83,9 @@ typedef struct {
 /* Alignment paths for the cosine track (paper Sec. 3.2.1(1), Eqs. 3-5).
  *   CA_PATH_MIXED: FP16 whitened spectra, batched per representative, pruned
  *     inverse transform as dense contractions on MFMA with FP32 accumulation;
- *     near-tied peaks are re-decided in FP64.  Clip sets of 128 x 128 clips
- *     with half-windows <= 16 only (CA_EUNSUPPORTED otherwise).
+ *     near-tied peaks are re-decided in FP64.  Clip sets of one raster size
+ *     (64, 128 or 256) and half-windows up to 32 (CA_EUNSUPPORTED for sets
+ *     that mix raster sizes: CA_PATH_AUTO takes those).
  *   CA_PATH_FP32: FP32 whitened spectra of both clips read per pair, one
  *     workgroup per pair, inverse transform by FFT on the vector ALUs; near
  *     ties re-decided in FP64.  All raster sizes and windows.
@@ -149,6 +157,13 @@ typedef struct {
   int64_t cover_nnz;          /* entries of the last cover relation built (ca_cover, ca_cluster) */
   int64_t members_verified;   /* members checked at their centers (ca_verify_centers, ca_cluster) */
   int64_t center_violations;  /* of those, members that failed the check (0 for ca_cluster's output) */
+  int64_t check_pairs;        /* decided pairs re-evaluated on the full FP64 surface (check_sample) */
+  int64_t check_changed;      /* of those, pairs whose FP64 answer differed (the band failed; 0 expected) */
+  double check_peak_err_sqrt; /* max |low - FP64| peak value of K r / sqrt(K_hi) over the checked pairs,
+                                 in the units of tie_band_mixed */
+  double check_band_frac;     /* the same error as a fraction of the band the call used (tie_band_mixed
+                                 for rasters up to 128, tie_band_mixed * N / 128 above): a decision
+                                 is safe while it stays below 0.5 */
 } ca_run_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -468,6 +483,11 @@ ca_status ca_server_wait(ca_server* srv, uint64_t req_id, int32_t timeout_ms);
  * currently in flight.  Thread-safe. */
 ca_status ca_server_stats(ca_server* srv, int64_t* requests_done, int64_t* candidate_pairs,
                           uint64_t* inflight_bytes);
+/* Run statistics of the server's slots (ca_run_stats, summed over the slots,
+ * maxima for the error fields) as of each slot's last finished request: the
+ * requests' alignment counts and the FP64 check of decided pairs.
+ * Thread-safe. */
+ca_status ca_server_run_stats(ca_server* srv, ca_run_stats* out);
 /* Last error message of the server (valid until its next failing call). */
 const char* ca_server_last_error(ca_server* srv);
 

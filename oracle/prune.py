@@ -71,3 +71,51 @@ def edge_pair_pass(box_a, box_b, t_edge: int) -> bool:
     if Pb <= Pa and not ok.any(axis=0).all():
         return False
     return True
+
+
+# ---- the same bounds over many pairs at once (for whole clip sets) ----------
+
+
+def area_pairs(npix, p: int, q: int, ids=None):
+    """B1 over all unordered pairs of the clips ``ids`` (default: all): the
+    pairs (i, j), i < j, with min(n) q^2 > p^2 max(n), as two int64 arrays.
+    Sorting by pixel count makes each clip's admissible partners (equal or
+    larger counts) one contiguous run."""
+    npix = np.asarray(npix, dtype=np.int64)
+    ids = np.arange(npix.size) if ids is None else np.asarray(ids, dtype=np.int64)
+    order = ids[np.argsort(npix[ids], kind="stable")]
+    n_sorted = npix[order]
+    # partners after position a: counts n_b with n_a q^2 > p^2 n_b (n_b >= n_a)
+    end = np.searchsorted(n_sorted * (p * p), n_sorted * (q * q), side="left")
+    reps, mems = [], []
+    for a in range(order.size):
+        if n_sorted[a] == 0 or end[a] <= a + 1:
+            continue
+        part = order[a + 1:end[a]]
+        i = np.full(part.size, order[a], dtype=np.int64)
+        reps.append(np.minimum(i, part))
+        mems.append(np.maximum(i, part))
+    if not reps:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    return np.concatenate(reps), np.concatenate(mems)
+
+
+def signature_bound_many(r_mem, c_mem, r_rep, c_rep, w_mem: int):
+    """B2 bounds of many (member, representative) pairs with one half-window:
+    row / column sums as arrays [P, N]; returns int64 [P] with
+    min(max_dy U_row(dy), max_dx U_col(dx)) as in ``signature_bound``."""
+    N = r_mem.shape[1]
+    best_row = np.zeros(r_mem.shape[0], np.int64)
+    best_col = np.zeros(r_mem.shape[0], np.int64)
+    for d in window_axis(w_mem, N):
+        best_row = np.maximum(best_row, np.minimum(r_rep, np.roll(r_mem, -int(d), axis=1)).sum(axis=1))
+        best_col = np.maximum(best_col, np.minimum(c_rep, np.roll(c_mem, -int(d), axis=1)).sum(axis=1))
+    return np.minimum(best_row, best_col)
+
+
+def signature_pass_many(r_mem, c_mem, n_mem, r_rep, c_rep, n_rep, w_mem: int, p: int, q: int):
+    """B2 test of many directed pairs: bound^2 q^2 > p^2 n_mem n_rep (bool [P])."""
+    b = signature_bound_many(r_mem, c_mem, r_rep, c_rep, w_mem).astype(object)
+    nm, nr = np.asarray(n_mem).astype(object), np.asarray(n_rep).astype(object)
+    ok = (b * b * q * q > p * p * nm * nr) & (nm > 0) & (nr > 0)
+    return ok.astype(bool)

@@ -35,7 +35,7 @@ SYMBOLS = [
     "ca_align_pairs", "ca_align_pairs_noalloc", "ca_surface", "ca_prune", "ca_cluster",
     "ca_cover", "ca_cover_dense", "ca_verify_centers",
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
-    "ca_server_stats", "ca_server_last_error",
+    "ca_server_stats", "ca_server_run_stats", "ca_server_last_error",
     "ca_autotune_report", "ca_autotune_save", "ca_autotune_load", "ca_autotune_clear",
     "ca_graph_create", "ca_graph_launch", "ca_graph_invalid", "ca_graph_destroy",
 ]
@@ -48,7 +48,7 @@ class ClipAlignError(RuntimeError):
 
 
 class _Config(C.Structure):
-    _fields_ = [("device", C.c_int32), ("reserved", C.c_int32), ("hbm_budget_bytes", C.c_uint64)]
+    _fields_ = [("device", C.c_int32), ("check_sample", C.c_int32), ("hbm_budget_bytes", C.c_uint64)]
 
 
 class _Constraint(C.Structure):
@@ -63,7 +63,9 @@ class _Stats(C.Structure):
                 ("tie_band_fp32", C.c_double), ("tie_band_direct", C.c_double),
                 ("max_peak_err_sqrt", C.c_double), ("groups_exact", C.c_int64),
                 ("pairs_full_fp64", C.c_int64), ("cover_nnz", C.c_int64),
-                ("members_verified", C.c_int64), ("center_violations", C.c_int64)]
+                ("members_verified", C.c_int64), ("center_violations", C.c_int64),
+                ("check_pairs", C.c_int64), ("check_changed", C.c_int64), ("check_peak_err_sqrt", C.c_double),
+                ("check_band_frac", C.c_double)]
 
 
 _LIB = None
@@ -109,6 +111,7 @@ def load():
     lib.ca_server_poll.argtypes = [P, C.c_uint64, P, P, P, P, C.POINTER(C.c_int32)]
     lib.ca_server_wait.argtypes = [P, C.c_uint64, C.c_int32]
     lib.ca_server_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]
+    lib.ca_server_run_stats.argtypes = [P, C.POINTER(_Stats)]
     lib.ca_server_last_error.argtypes = [P]
     lib.ca_server_last_error.restype = C.c_char_p
     lib.ca_autotune_report.argtypes = [P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)]
@@ -164,14 +167,14 @@ class ClipSet:
 class Context:
     """A library context on one GPU (``ca_create``)."""
 
-    def __init__(self, device=0, hbm_budget_bytes=0):
+    def __init__(self, device=0, hbm_budget_bytes=0, check_sample=0):
         import torch  # device memory and streams come from torch
 
         self.torch = torch
         self.lib = load()
         self.device = device
         h = P()
-        st = self.lib.ca_create(C.byref(_Config(device, 0, hbm_budget_bytes)), C.byref(h))
+        st = self.lib.ca_create(C.byref(_Config(device, int(check_sample), hbm_budget_bytes)), C.byref(h))
         if st != CA_OK:
             raise ClipAlignError(st, self.lib.ca_last_error(None).decode())
         self.h = h
@@ -444,6 +447,12 @@ class Server:
 
     def wait(self, rid, timeout_ms=-1):
         self._check(self.lib.ca_server_wait(self.h, C.c_uint64(rid), int(timeout_ms)))
+
+    def run_stats(self):
+        """Summed run statistics of the slots (``ca_server_run_stats``)."""
+        s = _Stats()
+        self._check(self.lib.ca_server_run_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in _Stats._fields_}
 
     def stats(self):
         a, b, c = C.c_int64(0), C.c_int64(0), C.c_uint64(0)

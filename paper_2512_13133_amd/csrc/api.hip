@@ -25,6 +25,11 @@ using namespace ca;
 static constexpr double BAND_FP32 = 1e-5;
 static constexpr double BAND_MIXED = 0.03;
 static constexpr double BAND_DIRECT = 0.03;
+// The general MFMA kernel's surface error in these units grows with the raster
+// size (the FP16 twiddle roundings add up coherently along one axis, about
+// sqrt(N)): the FP64 check of decided 256 x 256 pairs saw peak errors up to
+// 0.019 sqrt(K_hi), so rasters above 128 take a band proportional to N.
+static double band_mixed(int N) { return N > 128 ? BAND_MIXED * N / 128.0 : BAND_MIXED; }
 // The direct-correlation kernel is built but not launched: its first GPU run
 // ended in a memory-aperture fault whose cause is not yet identified, so the
 // path reports CA_EUNSUPPORTED until it is.
@@ -33,6 +38,7 @@ static constexpr bool DIRECT_ENABLED = false;
 struct ca_ctx {
   int device = 0;
   uint64_t budget = 0;
+  int64_t check_sample = 1024;  // decided pairs per mixed call checked in FP64
   uint64_t used = 0;
   std::string err;
   ca_run_stats stats{};
@@ -78,6 +84,7 @@ struct ca_clipset {
 };
 
 static thread_local std::string g_create_err;
+static constexpr int64_t CHECK_MAX = 4096;  // decided pairs checked in FP64 per call, at most
 static hipError_t noalloc_setup(int device);  // allocation-free work array, per device
 
 namespace {
@@ -193,6 +200,7 @@ ca_status ca_create(const ca_config* cfg, ca_ctx** out) {
   ca_ctx* ctx = new ca_ctx();
   ctx->device = cfg->device;
   ctx->budget = cfg->hbm_budget_bytes;
+  ctx->check_sample = cfg->check_sample == 0 ? 1024 : (cfg->check_sample < 0 ? 0 : std::min<int64_t>(cfg->check_sample, CHECK_MAX));
   ctx->stats.tie_band_mixed = BAND_MIXED;
   ctx->stats.tie_band_fp32 = BAND_FP32;
   ctx->stats.tie_band_direct = BAND_DIRECT;
@@ -637,18 +645,22 @@ FftPlan plan_fft(int N, int L, int scalar_bytes) {
 // Queue storage of the low-precision paths for n pairs: need[n], list[n],
 // r1_low[2n], 32 counters (0 queued pairs, 1 max error bits, 2 candidate
 // groups, 3 candidate shifts, 4 tile counter, 5 error ratio bits, 8 groups
-// left by the FP32 screen, rest spare), candidate groups, their shifts, and
-// the groups left by the screen.
+// left by the FP32 screen, 10 checked decided pairs, 11 / 12 their peak error
+// bits (as 1 / 5), 13 their changed answers, rest spare), candidate groups,
+// their shifts, the groups left by the screen, and the list and saved results
+// of the decided pairs checked in FP64 (at most CHECK_MAX a call).
 struct QueueMem {
   RescoreQueue q;
   CandQueue cq;
   CandQueue exact;  // groups the FP32 screen leaves to the FP64 pass (cq's shifts)
   unsigned long long* counters;
+  RescoreQueue check;  // the sample of decided pairs: q's need and r1_low, its own list and counters
+  SampleSave* check_saved;
 };
 static constexpr size_t queue_bytes(int64_t n) {
   const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
   return align_up(n) + 2 * align_up(8 * (size_t)n) + 256 + 2 * align_up(sizeof(CandGroup) * (size_t)cap_g) +
-         align_up(2 * (size_t)cap_s);
+         align_up(2 * (size_t)cap_s) + align_up(8 * (size_t)CHECK_MAX) + align_up(sizeof(SampleSave) * (size_t)CHECK_MAX);
 }
 static QueueMem queue_carve(char* base, int64_t n) {
   const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
@@ -672,6 +684,13 @@ static QueueMem queue_carve(char* base, int64_t n) {
   m.exact.groups = (CandGroup*)(base + b_need + b_list + b_r1 + b_cnt + b_grp + align_up(2 * (size_t)cap_s));
   m.exact.n_groups = m.counters + 8;
   m.exact.n_shifts = nullptr;
+  char* chk = base + b_need + b_list + b_r1 + b_cnt + 2 * b_grp + align_up(2 * (size_t)cap_s);
+  m.check = m.q;
+  m.check.list = (int64_t*)chk;
+  m.check.len = m.counters + 10;
+  m.check.peak_err_bits = m.counters + 11;
+  m.check.peak_ratio_bits = m.counters + 12;
+  m.check_saved = (SampleSave*)(chk + align_up(8 * (size_t)CHECK_MAX));
   return m;
 }
 
@@ -732,9 +751,11 @@ static ca_status ensure_gen_tables(ca_ctx* ctx, int N, int NB) {
 
 // gen_nb > 0: CA_PATH_MIXED runs the general MFMA kernel on raster maxN with
 // gen_nb x gen_nb window blocks (0: the 128 x 128 kernel for half-windows <= 16).
+// check_n > 0: after the re-decision, up to check_n decided pairs are checked
+// against the full FP64 surface (QueueMem::check).
 static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev& cm, int maxN, int Lmax, int path,
                                  Threshold thr, const PairIO& io, const QueueMem& m, hipStream_t s, bool events,
-                                 int direct_n = 0, bool fp64_pass = true, int gen_nb = 0) {
+                                 int direct_n = 0, bool fp64_pass = true, int gen_nb = 0, int64_t check_n = 0) {
   const int64_t n = io.n_pairs;
   hipError_t e = launch_zero_u64(m.counters, 32, s);
   if (e != hipSuccess) return e;
@@ -748,7 +769,7 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
   } else if (gen_nb > 0) {
     const _Float16* tab = (const _Float16*)ctx->gen_tab[maxN == 64 ? 0 : (maxN == 128 ? 1 : 2)][gen_nb];
     if (!tab) return hipErrorNotInitialized;  // made by ensure_gen_tables before any launch
-    e = launch_pcm_mfma_gen(maxN, gen_nb, cr, cm, io, thr, (float)BAND_MIXED, m.q, m.cq, tab,
+    e = launch_pcm_mfma_gen(maxN, gen_nb, cr, cm, io, thr, (float)band_mixed(maxN), m.q, m.cq, tab,
                             tab + (size_t)(maxN / 32) * gen_nb * 64 * 8, m.counters + 4, s);
   } else {
     e = launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, m.q, m.cq, ctx->mf_b1, ctx->mf_a2, nullptr,
@@ -770,8 +791,17 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
                                 m.q.r1_low, s);
   if (e != hipSuccess) return e;
   FftPlan pl = plan_fft(maxN, Lmax, 8);
-  return launch_pcm_fft64(cr, cm, io, m.q.list, n, MODE_RESCORE, thr, 0.0, ctx->tw64, pl.CH, pl.LINES, Lmax, maxN,
-                          m.q, s, m.q.len);
+  e = launch_pcm_fft64(cr, cm, io, m.q.list, n, MODE_RESCORE, thr, 0.0, ctx->tw64, pl.CH, pl.LINES, Lmax, maxN, m.q,
+                       s, m.q.len);
+  if (e != hipSuccess || check_n <= 0) return e;
+  const int64_t cn = std::min(check_n, std::min(n, CHECK_MAX));
+  e = launch_sample_pick(n, cn, io, m.q.need, m.check.list, m.check.len, m.check_saved, s);
+  if (e == hipSuccess)
+    e = launch_pcm_fft64(cr, cm, io, m.check.list, cn, MODE_RESCORE, thr, 0.0, ctx->tw64, pl.CH, pl.LINES, Lmax, maxN,
+                         m.check, s, m.check.len);
+  if (e == hipSuccess)
+    e = launch_sample_compare(cn, m.check.list, m.check.len, m.check_saved, io, m.q.need, m.counters + 13, s);
+  return e;
 }
 
 // FP64 re-decision for clip sets without stored FP64 spectra: after the main
@@ -925,8 +955,12 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   const QueueMem qm = queue_carve((char*)sc, n);
   unsigned long long* counters = qm.counters;
   const int64_t cap_g = qm.cq.cap_groups;
-  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n, !on_demand, gen_nb));
-  unsigned long long h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // at most one pair in 256 of the call, so that small calls stay cheap
+  const int64_t check_n =
+      (path == CA_PATH_MIXED && !on_demand) ? std::min<int64_t>(ctx->check_sample, std::max<int64_t>(1, n / 256)) : 0;
+  HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n, !on_demand, gen_nb,
+                                  check_n));
+  unsigned long long h[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   HIP_OR_FAIL(ctx, hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
   if (on_demand) {
@@ -953,6 +987,17 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
     ctx->stats.max_surface_err = std::max(ctx->stats.max_surface_err, err);
     std::memcpy(&err, &h[5], 8);
     ctx->stats.max_peak_err_sqrt = std::max(ctx->stats.max_peak_err_sqrt, err);
+  }
+  if (check_n > 0) {
+    ctx->stats.check_pairs += (int64_t)h[10];
+    ctx->stats.check_changed += (int64_t)h[13];
+    double err;
+    std::memcpy(&err, &h[12], 8);
+    if (h[10] > 0) {
+      ctx->stats.check_peak_err_sqrt = std::max(ctx->stats.check_peak_err_sqrt, err);
+      const double band = gen_nb > 0 ? band_mixed(maxN) : BAND_MIXED;
+      ctx->stats.check_band_frac = std::max(ctx->stats.check_band_frac, err / band);
+    }
   }
   ctx->stats.pairs_aligned += n;
   ctx->stats.pairs_rescored += n_groups + (int64_t)h[0];
@@ -1116,7 +1161,9 @@ extern "C" ca_status ca_graph_create(ca_ctx* ctx, void* stream, const ca_clipset
   auto sequence = [&](hipStream_t q) -> hipError_t {
     hipError_t e = launch_zero_u64(g->n_bad, 1, q);
     if (e == hipSuccess) e = launch_sanitize_pairs(n, rep, mem, cs->n, cs->n, p_rep, p_mem, bad, g->n_bad, q);
-    if (e == hipSuccess) e = enqueue_cosine(ctx, cs->d, cs->d, cs->maxN, cs->Lmax, CA_PATH_MIXED, thr, io, qm, q, false);
+    if (e == hipSuccess)
+      e = enqueue_cosine(ctx, cs->d, cs->d, cs->maxN, cs->Lmax, CA_PATH_MIXED, thr, io, qm, q, false, 0, true, 0,
+                         ctx->check_sample);
     if (e == hipSuccess) e = launch_reject_pairs(n, bad, io, q);
     return e;
   };
@@ -1171,6 +1218,8 @@ void free_ctx(ca_ctx* ctx, void* p, size_t bytes) {
   ctx->used -= bytes;
 }
 int device_of(const ca_ctx* ctx) { return ctx->device; }
+int64_t check_sample_of(const ca_ctx* ctx) { return ctx->check_sample; }
+void set_check_sample(ca_ctx* ctx, int64_t v) { ctx->check_sample = v; }
 ca_run_stats* stats_of(ca_ctx* ctx) { return &ctx->stats; }
 const ca::ClipsDev& dev_of(const ca_clipset* cs) { return cs->d; }
 ca_ctx* ctx_of(const ca_clipset* cs) { return cs->ctx; }

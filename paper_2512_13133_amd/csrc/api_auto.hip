@@ -27,6 +27,8 @@ const ca::ClipsDev& dev_of(const ca_clipset* cs);
 bool has_fp32_of(const ca_clipset* cs);
 bool has_image_of(const ca_clipset* cs);
 std::map<int, TuneEntry>& tune_of(ca_ctx* ctx);
+int64_t check_sample_of(const ca_ctx* ctx);
+void set_check_sample(ca_ctx* ctx, int64_t v);
 ca_status align_cosine_sets(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
                             ca::Threshold thr, int path, const ca::PairIO& io, bool checked, int direct_n,
                             int bucket_w);
@@ -145,6 +147,14 @@ ca_status tune_bucket(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshol
   const int N = 64 << (key / N_WCLASS);
   const int wc = key % N_WCLASS;
   const ca_run_stats saved = *stats_of(ctx);
+  // the timed runs compare paths on equal terms: no FP64 check of decided pairs
+  const int64_t check = check_sample_of(ctx);
+  set_check_sample(ctx, 0);
+  struct Restore {
+    ca_ctx* c;
+    int64_t v;
+    ~Restore() { set_check_sample(c, v); }
+  } restore{ctx, check};
   const int64_t m = io.n_pairs;
   PairIO ref = result_view(ref_mem, m, io.rep, io.mem);
   PairIO tmp = result_view(tmp_mem, m, io.rep, io.mem);

@@ -49,6 +49,7 @@ ca_status clips_create_in(ca_ctx* ctx, void* stream, int64_t n, const int64_t* r
                           ca_clipset** out);
 bool has_fp32_of(const ca_clipset* cs);
 bool has_fp64_of(const ca_clipset* cs);
+int64_t check_sample_of(const ca_ctx* ctx);
 }  // namespace capriv
 
 using namespace ca;
@@ -104,6 +105,7 @@ struct ca_server {
   uint64_t next_id = 1;
   bool stop = false;
   int64_t done_requests = 0, done_pairs = 0;
+  std::vector<ca_run_stats> slot_stats;  // each slot context's statistics after its last request
   std::string err;
 };
 
@@ -335,8 +337,11 @@ void worker_main(ca_server* srv, int slot) {
       req->state = 1;
     }
     run_request(srv, slot, req);
+    ca_run_stats snap{};
+    (void)ca_get_stats(srv->slot_ctx[slot], &snap);  // this worker is the slot context's only user
     {
       std::lock_guard<std::mutex> g(srv->mu);
+      srv->slot_stats[slot] = snap;
       req->state = req->status == CA_OK ? 2 : 3;
       srv->inflight -= req->est_bytes;
       srv->done_requests += 1;
@@ -381,7 +386,11 @@ extern "C" ca_status ca_server_create(ca_ctx* ctx, const ca_clipset* library, co
     delete srv;
     return fail_ctx(ctx, CA_ENOMEM, "server library order upload failed");
   }
-  ca_config cfg{device_of(ctx), 0, 0};
+  // slot contexts check a small sample of decided pairs per request in FP64
+  // (at most 128, none if the server's context checks none), so the check
+  // adds little to a request's latency
+  const int64_t chk = check_sample_of(ctx);
+  ca_config cfg{device_of(ctx), chk <= 0 ? -1 : (int32_t)std::min<int64_t>(chk, 128), 0};
   for (int sl = 0; sl < slots; ++sl) {
     ca_ctx* sc = nullptr;
     hipStream_t st = nullptr;
@@ -396,6 +405,7 @@ extern "C" ca_status ca_server_create(ca_ctx* ctx, const ca_clipset* library, co
       return fail_ctx(ctx, CA_EDEVICE, "server slot set-up failed");
     }
     srv->slot_ctx.push_back(sc);
+    srv->slot_stats.emplace_back();
     srv->slot_stream.push_back(st);
     srv->slot_arena.emplace_back();
   }
@@ -514,6 +524,41 @@ extern "C" ca_status ca_server_stats(ca_server* srv, int64_t* requests_done, int
   if (requests_done) *requests_done = srv->done_requests;
   if (candidate_pairs) *candidate_pairs = srv->done_pairs;
   if (inflight_bytes) *inflight_bytes = srv->inflight;
+  return CA_OK;
+}
+
+extern "C" ca_status ca_server_run_stats(ca_server* srv, ca_run_stats* out) {
+  if (!srv || !out) return CA_EINVAL;
+  std::lock_guard<std::mutex> g(srv->mu);
+  ca_run_stats t{};
+  bool first = true;
+  for (const ca_run_stats& a : srv->slot_stats) {
+    if (first) {
+      t = a;  // bands and other constants
+      first = false;
+      continue;
+    }
+    t.pairs_aligned += a.pairs_aligned;
+    t.pairs_rescored += a.pairs_rescored;
+    t.pairs_edge += a.pairs_edge;
+    t.pairs_screened += a.pairs_screened;
+    t.pairs_survived += a.pairs_survived;
+    t.n_main_launch += a.n_main_launch;
+    t.t_main_ms += a.t_main_ms;
+    t.main_alg_bytes += a.main_alg_bytes;
+    t.max_surface_err = std::max(t.max_surface_err, a.max_surface_err);
+    t.max_peak_err_sqrt = std::max(t.max_peak_err_sqrt, a.max_peak_err_sqrt);
+    t.groups_exact += a.groups_exact;
+    t.pairs_full_fp64 += a.pairs_full_fp64;
+    t.cover_nnz += a.cover_nnz;
+    t.members_verified += a.members_verified;
+    t.center_violations += a.center_violations;
+    t.check_pairs += a.check_pairs;
+    t.check_changed += a.check_changed;
+    t.check_peak_err_sqrt = std::max(t.check_peak_err_sqrt, a.check_peak_err_sqrt);
+    t.check_band_frac = std::max(t.check_band_frac, a.check_band_frac);
+  }
+  *out = t;
   return CA_OK;
 }
 

@@ -95,6 +95,15 @@ struct CandQueue {
   int64_t cap_groups, cap_shifts;
 };
 
+// A decided pair's low-precision result, kept while the FP64 check of a
+// sample of decided pairs recomputes it.
+struct SampleSave {
+  int16_t shift[4];
+  int32_t count[2];
+  uint32_t flags;
+  uint8_t bits;
+};
+
 // Candidate generation: anchors, their partner ranges and the output list.
 // Within one clip set the anchors are the positions of `order` and each
 // anchor's partners start right after it; between two sets (a request batch

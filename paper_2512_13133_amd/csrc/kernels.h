@@ -96,6 +96,15 @@ hipError_t launch_rescore_screen(const ClipsDev& cr, const ClipsDev& cm, const P
 hipError_t launch_rescore_exact(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                 const CandQueue& groups, const double2* tw256, unsigned long long* peak_err_bits,
                                 unsigned long long* peak_ratio_bits, const float* r1_low, hipStream_t s);
+// FP64 check of a sample of decided pairs (up to `count` of n pairs, spread
+// evenly): the pick queues them (need = 3) in `list` / *len and saves their
+// results; after an FP64 pass over that list the compare counts changed
+// answers and restores the flags of the unchanged ones (cap: the pick's count).
+hipError_t launch_sample_pick(int64_t n, int64_t count, const PairIO& io, uint8_t* need, int64_t* list,
+                              unsigned long long* len, SampleSave* saved, hipStream_t s);
+hipError_t launch_sample_compare(int64_t cap, const int64_t* list, const unsigned long long* len,
+                                 const SampleSave* saved, const PairIO& io, uint8_t* need,
+                                 unsigned long long* mismatches, hipStream_t s);
 // Collect the clips whose FP64 spectra the re-decision needs: the pairs of the
 // first n_groups groups and of list[0 .. n_list); remap tables start at -1.
 hipError_t launch_mark_fp64(const PairIO& io, const CandGroup* groups, int64_t n_groups, const int64_t* list,

@@ -321,6 +321,10 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
         io.bits[k] = (uint8_t)((b0 ? 1u : 0u) | (b1 ? 2u : 0u));
         io.flags[k] = 0;
         if (q.need) q.need[k] = 0;
+        if (q.r1_low) {  // the low-precision peaks, read by the FP64 passes' error statistics
+          q.r1_low[k * 2 + 0] = v1f / (float)K_hi;
+          q.r1_low[k * 2 + 1] = v1r / (float)K_hi;
+        }
       }
       // An undecided direction queues every window shift whose value is within
       // the band of its maximum (d == 2: both directions of equal windows, in

@@ -366,4 +366,66 @@ hipError_t launch_rescore_candidates(const ClipsDev& cr, const ClipsDev& cm, con
   return hipGetLastError();
 }
 
+// ---- FP64 check of decided pairs ------------------------------------------
+//
+// A deterministic sample of the pairs that the low-precision pass decided in
+// both directions (no FP64 re-decision, no empty clip) goes through the full
+// FP64 surface as well: their results are saved, they are queued for both
+// directions, the FP64 pass rewrites them with the exact answer and records
+// |low - FP64| of the peak value, and the compare step counts the pairs whose
+// answer changed (a decision the band should have caught; the FP64 answer is
+// kept for them) and restores the flags of the others.
+
+__global__ void sample_pick_kernel(int64_t n, int64_t stride, int64_t offset, int64_t count, PairIO io, uint8_t* need,
+                                   int64_t* list, unsigned long long* len, SampleSave* saved) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t k = (offset + i * stride) % n;
+  const uint32_t f = io.flags[k];
+  if (need[k] != 0 || (f & (CA_FLAG_RESCORED_FWD | CA_FLAG_RESCORED_REV | CA_FLAG_EMPTY)) != 0) return;
+  const unsigned long long slot = atomicAdd(len, 1ull);
+  SampleSave v;
+  for (int e = 0; e < 4; ++e) v.shift[e] = io.shift[4 * k + e];
+  v.count[0] = io.count[2 * k];
+  v.count[1] = io.count[2 * k + 1];
+  v.flags = f;
+  v.bits = io.bits[k];
+  saved[slot] = v;
+  list[slot] = k;
+  need[k] = 3;
+}
+
+__global__ void sample_compare_kernel(const int64_t* list, const unsigned long long* len, const SampleSave* saved,
+                                      PairIO io, uint8_t* need, unsigned long long* mismatches) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)*len) return;
+  const int64_t k = list[t];
+  const SampleSave v = saved[t];
+  bool same = io.bits[k] == v.bits && io.count[2 * k] == v.count[0] && io.count[2 * k + 1] == v.count[1];
+  for (int e = 0; e < 4; ++e) same = same && io.shift[4 * k + e] == v.shift[e];
+  if (same) io.flags[k] = v.flags;
+  else atomicAdd(mismatches, 1ull);
+  need[k] = 0;
+}
+
+hipError_t launch_sample_pick(int64_t n, int64_t count, const PairIO& io, uint8_t* need, int64_t* list,
+                              unsigned long long* len, SampleSave* saved, hipStream_t s) {
+  if (n <= 0 || count <= 0) return hipSuccess;
+  count = std::min(count, n);
+  const int64_t stride = n / count;          // count * stride <= n: distinct pairs
+  const int64_t offset = (n * 7919) % stride;  // a fixed function of n: repeated calls check the same pairs
+  hipLaunchKernelGGL(sample_pick_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, n, stride, offset,
+                     count, io, need, list, len, saved);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_compare(int64_t cap, const int64_t* list, const unsigned long long* len,
+                                 const SampleSave* saved, const PairIO& io, uint8_t* need,
+                                 unsigned long long* mismatches, hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_compare_kernel, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, list, len, saved,
+                     io, need, mismatches);
+  return hipGetLastError();
+}
+
 }  // namespace ca

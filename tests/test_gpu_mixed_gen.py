@@ -85,8 +85,13 @@ def test_mixed_general_kernel_equals_oracle(ctx, N, wmax):
     check(got, ref, rep, mem, f"N={N} w<={wmax}")
     say(f"[mixed-gen] N={N} wmax={wmax}: {int((got['bits'] != 0).sum())} covering pairs, "
         f"rescored {st['pairs_rescored']}, full FP64 {st['pairs_full_fp64']}, "
-        f"peak error {st['max_peak_err_sqrt']:.4f} (band {st['tie_band_mixed']})")
-    assert st["max_peak_err_sqrt"] < st["tie_band_mixed"] / 2
+        f"peak error {st['max_peak_err_sqrt']:.4f}; FP64 check of {st['check_pairs']} decided pairs: "
+        f"{st['check_changed']} changed, error {st['check_band_frac']:.3f} of the band")
+    band = st["tie_band_mixed"] * max(1.0, N / 128)  # rasters above 128 take a band proportional to N
+    assert st["max_peak_err_sqrt"] < band / 2
+    # the decided pairs re-evaluated on the full FP64 surface (one in 256 here) kept their answers
+    assert st["check_changed"] == 0
+    assert st["check_band_frac"] < 0.5
     h.close()
 
 
@@ -112,3 +117,35 @@ def test_mixed_general_kernel_periodic_ties_all_residues(ctx):
     check(got, ref, rep, mem, "periodic 64 all residues")
     assert ((got["flags"] & 3) != 0).any()  # ties went to the FP64 re-decision
     h.close()
+
+
+def test_decided_pairs_checked_in_fp64_on_density_workload(ctx):
+    """Clips of the density workload (union densities 0.1-0.6), every pair of
+    600 clips (179,700) through the mixed path with the FP64 check at its
+    largest share (one pair in 256 re-evaluated on the full FP64 surface): no
+    decision changes and the peak error of the decided pairs stays below half
+    the band."""
+    import paper_2512_13133_amd as ca
+    c = ca.Context(0, check_sample=4096)
+    cs = clipgen.dense(n_clips=600, n_templates=6)
+    rep, mem = clipgen.all_pairs(cs.n)
+    h = c.clips(cs, fp32=True)
+    got = to_np(c.align_pairs(h, rep, mem, "cosine", (19, 20), "mixed"))
+    st = c.stats()
+    say(f"[check] density clips: {st['check_pairs']} decided pairs checked, {st['check_changed']} changed, "
+        f"peak error {st['check_peak_err_sqrt']:.4f} (band {st['tie_band_mixed']}); "
+        f"{int((got['bits'] != 0).sum())} covering pairs")
+    assert st["check_pairs"] >= 500 and st["check_changed"] == 0
+    assert st["check_band_frac"] < 0.5
+    # the checked pairs' flags are restored: a second call without the check
+    # returns the same results and flags
+    c2 = ca.Context(0, check_sample=-1)
+    h2 = c2.clips(cs, fp32=True)
+    again = to_np(c2.align_pairs(h2, rep, mem, "cosine", (19, 20), "mixed"))
+    assert c2.stats()["check_pairs"] == 0
+    for k in ("bits", "shift", "count", "score", "flags"):
+        assert (again[k] == got[k]).all(), k
+    h.close()
+    h2.close()
+    c.close()
+    c2.close()

@@ -536,8 +536,11 @@ def test_mixed_equals_fp32_on_full_workload(ctx):
     om = ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "mixed")
     st = ctx.stats()
     say(f"[full] mixed re-decided {st['pairs_rescored']} pairs; max peak error / sqrt(K_hi) "
-        f"{st['max_peak_err_sqrt']:.4f} against band {st['tie_band_mixed']}")
+        f"{st['max_peak_err_sqrt']:.4f} against band {st['tie_band_mixed']}; FP64 check of "
+        f"{st['check_pairs']} decided pairs: {st['check_changed']} changed, peak error {st['check_peak_err_sqrt']:.4f}")
     assert st["max_peak_err_sqrt"] < st["tie_band_mixed"] / 2
+    assert st["check_pairs"] > 0 and st["check_changed"] == 0
+    assert st["check_band_frac"] < 0.5
     of = ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "fp32")
     torch.cuda.synchronize()
     diff = torch.zeros(rep.numel(), dtype=torch.bool, device=rep.device)

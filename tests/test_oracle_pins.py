@@ -442,6 +442,29 @@ def test_pruning_bounds_are_safe():
                 assert prune.signature_pass(a, b, w, p, q)
 
 
+def test_bounds_over_many_pairs_equal_the_pairwise_bounds():
+    """area_pairs lists exactly the pairs area_pass admits, and the batched B2
+    bound equals the pairwise one, on random 16 x 16 clips."""
+    rng = np.random.default_rng(23)
+    N, w = 16, 3
+    clips = [rand_clip(rng, N, k=int(rng.integers(1, 5))) for _ in range(30)]
+    npix = np.array([int(c.sum()) for c in clips])
+    for p, q in [(19, 20), (93, 100), (1, 2)]:
+        r, m = prune.area_pairs(npix, p, q)
+        got = set(zip(r.tolist(), m.tolist()))
+        want = {(i, j) for i in range(30) for j in range(i + 1, 30) if prune.area_pass(npix[i], npix[j], p, q)}
+        assert got == want
+    a_idx, b_idx = rng.integers(0, 30, 80), rng.integers(0, 30, 80)
+    rows = np.array([c.sum(axis=1) for c in clips]).astype(np.int64)
+    cols = np.array([c.sum(axis=0) for c in clips]).astype(np.int64)
+    many = prune.signature_bound_many(rows[a_idx], cols[a_idx], rows[b_idx], cols[b_idx], w)
+    one = [prune.signature_bound(clips[i], clips[j], w) for i, j in zip(a_idx, b_idx)]
+    assert many.tolist() == one
+    ok = prune.signature_pass_many(rows[a_idx], cols[a_idx], npix[a_idx], rows[b_idx], cols[b_idx], npix[b_idx],
+                                   w, 19, 20)
+    assert ok.tolist() == [prune.signature_pass(clips[i], clips[j], w, 19, 20) for i, j in zip(a_idx, b_idx)]
+
+
 def test_edge_box_bound_is_safe():
     rng = np.random.default_rng(14)
     N = 16
