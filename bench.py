@@ -14,7 +14,9 @@ One step is one pass of the hot path over the clip set:
 `value` counts the unordered cosine pairs carried through alignment per second
 of the whole step.  Beside it the JSON line carries the roofline of the
 dominant kernel, the plain FP32 per-pair kernel on the same pair list, the
-edge track's rate and the FP64 oracle timed on this host's cores.
+edge track's rate, the run-time FP64 check of decided pairs, the mixed-size
+workload (200,000 clips of 64/128/256, windows 4..32, 41.3M pairs) in one
+autotuned call, serving, and the FP64 oracle timed on this host's cores.
 """
 import argparse
 import json
@@ -73,6 +75,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP32 comparator")
     ap.add_argument("--no-xcorr", action="store_true", help="skip the exact-objective alignment")
+    ap.add_argument("--no-mixed-sizes", action="store_true", help="skip the mixed-size workload")
     ap.add_argument("--serve-library", type=int, default=100_000)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -210,8 +213,19 @@ def main():
                               "frac": round(ops / (xms * 1e-3) / 1e12 / INT_PEAK_TOPS, 4),
                               "ops_per_pair": 33 * 33 * 128 * 4 * 2}}
         del ox
-    stats_out = {k: st[k] for k in ("pairs_rescored", "pairs_full_fp64", "groups_exact", "max_surface_err", "max_peak_err_sqrt", "tie_band_mixed", "pairs_screened",
-                                    "pairs_survived")}
+    stats_out = {k: st[k] for k in ("pairs_rescored", "pairs_full_fp64", "groups_exact", "max_surface_err",
+                                    "max_peak_err_sqrt", "tie_band_mixed", "pairs_screened", "pairs_survived",
+                                    "check_pairs", "check_changed", "check_peak_err_sqrt", "check_band_frac")}
+    # edge track: pairs per second of its alignment stage; algorithmic bytes are
+    # the two clips' polygon box tables (64 boxes x 8 bytes each), mostly served
+    # from the caches (the kernel is bound by instruction issue)
+    edge = None
+    if not args.no_edge and stage_t.get("align_edge"):
+        e_pairs = tot_e / args.steps
+        e_s = stage_t["align_edge"] / args.steps
+        edge = {"pairs_per_step": int(e_pairs), "stage_ms": round(e_s * 1e3, 2),
+                "pairs_per_s": round(e_pairs / e_s, 1), "alg_bytes_per_pair": 2 * 64 * 8,
+                "achieved_GBps": round(e_pairs * 2 * 64 * 8 / e_s / 1e9, 1)}
     stage_ms = {k: round(v * 1000.0 / args.steps, 2) for k, v in stage_t.items()}
 
     graph = graph_bench(ctx, h, rep, mem)
@@ -220,6 +234,8 @@ def main():
         cpu = cpu_baseline(cs, rep.cpu().numpy(), mem.cpu().numpy(), args.cpu_seconds)
     h.close()
     del out, rep, mem, last
+    torch.cuda.empty_cache()
+    mixed_sizes = None if args.no_mixed_sizes else mixed_sizes_bench(ctx)
     torch.cuda.empty_cache()
     serving = None if args.no_serving else serve_bench(ctx, args.serve_library, args.serve_seconds)
 
@@ -238,12 +254,60 @@ def main():
         "kernel_pairs_per_s": kernel_rate,
         "plain_fp32": comparator,
         "exact_objective": xcorr,
+        "edge": edge,
+        "mixed_sizes": mixed_sizes,
         "stage_ms": stage_ms,
         "stats": stats_out,
         "serving": serving,
         "graph": graph,
     }
     print(json.dumps(line))
+
+
+def mixed_sizes_bench(ctx):
+    """The mixed-size workload: 200,000 clips (64, 128, 256 in ratio 4:3:1),
+    half-windows 4..32, Zipf(1.2) candidate lists (41.3M directed pairs),
+    cosine 97/100, one CA_PATH_AUTO call over the whole list: first with an
+    empty tuning table (every bucket tuned on its own pairs), then tuned.  The
+    batched MFMA kernels' time and algorithmic bytes (member spectrum and bits
+    per pair) come from the library's events."""
+    import numpy as np
+    import torch
+
+    import clipgen
+    t0 = time.time()
+    cs, rep, mem = clipgen.mixed()
+    log(f"[mixed] generated {cs.n} clips, {rep.size} pairs in {time.time() - t0:.1f}s")
+    h = ctx.clips(cs, fp32=True)
+    d_rep = torch.from_numpy(rep.astype(np.int32)).cuda()
+    d_mem = torch.from_numpy(mem.astype(np.int32)).cuda()
+    ctx.autotune_clear()
+    times = []
+    for it in range(3):
+        ctx.reset_stats()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = ctx.align_pairs(h, d_rep, d_mem, "cosine", (97, 100), "auto")
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        del out
+    st = ctx.stats()
+    report = ctx.autotune_report()
+    h.close()
+    by_size = {}
+    for N in (64, 128, 256):
+        by_size[N] = int((cs.raster_n[rep] == N).sum())
+    kernel_gbs = st["main_alg_bytes"] / (st["t_main_ms"] * 1e-3) / 1e9
+    return {"workload": "200k clips 64/128/256 (4:3:1), windows 4..32, Zipf(1.2) lists, cosine 97/100",
+            "pairs": int(rep.size), "pairs_by_size": by_size,
+            "first_call_s": round(times[0], 3), "tuned_call_s": round(min(times[1:]), 3),
+            "pairs_per_s": round(rep.size / min(times[1:]), 1),
+            "mfma_kernels_ms": round(st["t_main_ms"], 1), "mfma_kernel_launches": st["n_main_launch"],
+            "mfma_alg_GBps": round(kernel_gbs, 1), "mfma_hbm_frac": round(kernel_gbs / HBM_PEAK_GBS, 4),
+            "rescored": st["pairs_rescored"], "full_fp64": st["pairs_full_fp64"],
+            "check_pairs": st["check_pairs"], "check_changed": st["check_changed"],
+            "check_band_frac": round(st["check_band_frac"], 4),
+            "tuned_paths": [ln.split(" us_per_kpair")[0] for ln in report.splitlines() if ln]}
 
 
 def graph_bench(ctx, h, rep, mem, n=4096, reps=50):
@@ -409,8 +473,10 @@ def cpu_baseline(cs, rep, mem, seconds):
     import multiprocessing as mp
 
     import numpy as np
-    cores = len(os.sched_getaffinity(0))
-    cores = max(1, min(cores, 16))
+    # one GPU's share of the host: 16 cores (the host may show more; worker
+    # pools beyond one GPU's share are not run)
+    visible = len(os.sched_getaffinity(0))
+    cores = max(1, min(visible, 16))
     # size the sample from a short single-core probe
     rng = np.random.default_rng(1234)
     probe = rng.choice(rep.size, size=min(200, rep.size), replace=False)
@@ -425,7 +491,8 @@ def cpu_baseline(cs, rep, mem, seconds):
         res = pool.map(_cpu_worker, [(cs, rep[c], mem[c]) for c in chunks])
     wall = time.perf_counter() - t
     done = sum(r[0] for r in res)
-    return {"value": round(done / wall, 1), "unit": "pairs/s", "cores": cores, "kind": "oracle",
+    return {"value": round(done / wall, 1), "unit": "pairs/s", "cores": cores, "cores_visible": visible,
+            "per_core": round(done / wall / cores, 1), "kind": "oracle",
             "sample": f"{done} cosine candidate pairs of the timed step, uniform sample, FP64 numpy oracle, "
                       f"both directions per pair"}
 

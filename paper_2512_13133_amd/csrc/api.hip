@@ -658,12 +658,12 @@ struct QueueMem {
   SampleSave* check_saved;
 };
 static constexpr size_t queue_bytes(int64_t n) {
-  const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
+  const int64_t cap_g = n / 4 + 65536, cap_s = 16 * cap_g;
   return align_up(n) + 2 * align_up(8 * (size_t)n) + 256 + 2 * align_up(sizeof(CandGroup) * (size_t)cap_g) +
          align_up(2 * (size_t)cap_s) + align_up(8 * (size_t)CHECK_MAX) + align_up(sizeof(SampleSave) * (size_t)CHECK_MAX);
 }
 static QueueMem queue_carve(char* base, int64_t n) {
-  const int64_t cap_g = n / 16 + 65536, cap_s = 8 * cap_g;
+  const int64_t cap_g = n / 4 + 65536, cap_s = 16 * cap_g;
   const size_t b_need = align_up(n), b_list = align_up(8 * (size_t)n), b_r1 = align_up(8 * (size_t)n);
   const size_t b_cnt = 256, b_grp = align_up(sizeof(CandGroup) * (size_t)cap_g);
   QueueMem m;

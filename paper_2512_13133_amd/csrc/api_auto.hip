@@ -60,16 +60,26 @@ __host__ __device__ inline int ncode_of(int N) { return N <= 64 ? 0 : (N <= 128 
     if (e_ != hipSuccess) return fail_ctx((ctx), CA_EDEVICE, hipGetErrorString(e_)); \
   } while (0)
 
+// Bucket key of every pair and the bucket sizes: a histogram per workgroup in
+// LDS, added to the global one with one atomic per bucket and workgroup (one
+// global atomic per pair serialised on a few counters).
 __global__ void bucket_keys_kernel(ClipsDev cs, int64_t n, const int32_t* __restrict__ rep,
                                    const int32_t* __restrict__ mem, uint8_t* __restrict__ keys,
                                    int32_t* __restrict__ idx, unsigned* __restrict__ hist) {
+  __shared__ unsigned s_hist[N_KEYS];
+  for (int t = threadIdx.x; t < N_KEYS; t += blockDim.x) s_hist[t] = 0u;
+  __syncthreads();
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int i = mem[k], j = rep[k];
-  const int key = ncode_of(cs.N[i]) * N_WCLASS + wclass_of(max((int)cs.w[i], (int)cs.w[j]));
-  keys[k] = (uint8_t)key;
-  idx[k] = (int32_t)k;
-  atomicAdd(hist + key, 1u);
+  if (k < n) {
+    const int i = mem[k], j = rep[k];
+    const int key = ncode_of(cs.N[i]) * N_WCLASS + wclass_of(max((int)cs.w[i], (int)cs.w[j]));
+    keys[k] = (uint8_t)key;
+    idx[k] = (int32_t)k;
+    atomicAdd(&s_hist[key], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < N_KEYS; t += blockDim.x)
+    if (s_hist[t]) atomicAdd(hist + t, s_hist[t]);
 }
 
 __global__ void gather_pairs_kernel(int64_t n, const int32_t* __restrict__ idx, const int32_t* __restrict__ rep,

@@ -80,7 +80,7 @@ struct RescoreQueue {
 
 // Near-tie candidates of a queued direction: the window shifts whose
 // low-precision value lies within the band of the maximum.
-constexpr int MAX_CAND = 16;
+constexpr int MAX_CAND = 64;
 struct CandGroup {
   int64_t pair;    // pair id
   int64_t offset;  // first candidate in CandQueue::shifts
