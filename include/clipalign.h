@@ -285,7 +285,7 @@ ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset* cs,
  *     keep FP64 spectra (CA_EUNSUPPORTED otherwise); the edge track as in
  *     ca_align_pairs.
  * The call makes no device allocation: its work space (the FP64 re-decision
- * queue, counters and a validation word, about 26 MB) is one static array per
+ * queue, counters and a validation word, about 45 MB) is one static array per
  * device, set up by ca_create and held until the process ends.  Every call on
  * a device shares that array, so calls that overlap in time on one device
  * (from several threads or contexts, or on streams that run concurrently)
