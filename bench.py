@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # 32-bit integer vector operations: 256 CUs x 4 SIMDs x 16 lanes a clock at 2.4 GHz
 INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 PROFILE = os.path.join(ROOT, "profiles", "c128_bench_hbm_counters.md")
-KERNEL_SOURCES = ["paper_2512_13133_amd/csrc/pcm_mfma.hip", "paper_2512_13133_amd/csrc/pair_common.h",
-                  "paper_2512_13133_amd/csrc/internal.h"]
+KERNEL_SOURCES = ["paper_2512_13133_amd/csrc/pcm_mfma.hip", "paper_2512_13133_amd/csrc/mfma_common.h",
+                  "paper_2512_13133_amd/csrc/pair_common.h", "paper_2512_13133_amd/csrc/internal.h"]
 
 
 def profiled_traffic(kernel):
@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-comparator", action="store_true", help="skip the plain FP32 comparator")
     ap.add_argument("--no-xcorr", action="store_true", help="skip the exact-objective alignment")
     ap.add_argument("--no-mixed-sizes", action="store_true", help="skip the mixed-size workload")
+    ap.add_argument("--mixed-sizes-only", action="store_true",
+                    help="only run the mixed-size workload (profiling) and print its object")
     ap.add_argument("--serve-library", type=int, default=100_000)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -83,6 +85,10 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.mixed_sizes_only:
+        import paper_2512_13133_amd as ca
+        print(json.dumps({"mixed_sizes": mixed_sizes_bench(ca.Context(0))}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; sharding across GPUs is not implemented",

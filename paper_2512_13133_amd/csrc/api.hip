@@ -749,6 +749,13 @@ static ca_status ensure_gen_tables(ca_ctx* ctx, int N, int NB) {
   return CA_OK;
 }
 
+// Decided pairs of an n-pair mixed call checked on the full FP64 surface: the
+// context's check_sample, at most one pair in 256 of the call (so that small
+// calls and graph replays stay cheap), none when switched off.
+static int64_t check_count(const ca_ctx* ctx, int64_t n) {
+  return ctx->check_sample > 0 ? std::min<int64_t>(ctx->check_sample, std::max<int64_t>(1, n / 256)) : 0;
+}
+
 // gen_nb > 0: CA_PATH_MIXED runs the general MFMA kernel on raster maxN with
 // gen_nb x gen_nb window blocks (0: the 128 x 128 kernel for half-windows <= 16).
 // check_n > 0: after the re-decision, up to check_n decided pairs are checked
@@ -955,9 +962,7 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   const QueueMem qm = queue_carve((char*)sc, n);
   unsigned long long* counters = qm.counters;
   const int64_t cap_g = qm.cq.cap_groups;
-  // at most one pair in 256 of the call, so that small calls stay cheap
-  const int64_t check_n =
-      (path == CA_PATH_MIXED && !on_demand) ? std::min<int64_t>(ctx->check_sample, std::max<int64_t>(1, n / 256)) : 0;
+  const int64_t check_n = (path == CA_PATH_MIXED && !on_demand) ? check_count(ctx, n) : 0;
   HIP_OR_FAIL(ctx, enqueue_cosine(ctx, cr, cm, maxN, Lmax, path, thr, io, qm, s, true, direct_n, !on_demand, gen_nb,
                                   check_n));
   unsigned long long h[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -1163,7 +1168,7 @@ extern "C" ca_status ca_graph_create(ca_ctx* ctx, void* stream, const ca_clipset
     if (e == hipSuccess) e = launch_sanitize_pairs(n, rep, mem, cs->n, cs->n, p_rep, p_mem, bad, g->n_bad, q);
     if (e == hipSuccess)
       e = enqueue_cosine(ctx, cs->d, cs->d, cs->maxN, cs->Lmax, CA_PATH_MIXED, thr, io, qm, q, false, 0, true, 0,
-                         ctx->check_sample);
+                         check_count(ctx, n));
     if (e == hipSuccess) e = launch_reject_pairs(n, bad, io, q);
     return e;
   };

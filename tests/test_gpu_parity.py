@@ -315,6 +315,55 @@ def test_edge_track_c128(ctx):
     h.close()
 
 
+def _edge_strata(cs, rep, mem, npoly):
+    """Stratum of each pair by the larger polygon count of its clips: 1,
+    2-4, 5-8 and more than 8 (the edge kernel's LDS path)."""
+    mx = np.maximum(npoly[rep], npoly[mem])
+    return np.select([mx <= 1, mx <= 4, mx <= 8], [0, 1, 2], 3)
+
+
+def test_edge_track_stratified_by_polygon_count(ctx):
+    """128 x 128 clips with up to about 20 polygons, pairs stratified by the
+    larger polygon count of the pair, half same-template pairs (polygon
+    correspondences and set bits) and half uniform: clips of the density
+    workload (edge 2 px), and clips of low-density many-rectangle templates
+    with 1 px jitter (edge 3 px), where correspondences of more than 8
+    polygons occur."""
+    rng = np.random.default_rng(23)
+    dens = rng.uniform(0.1, 0.3, size=40)
+    tpl = clipgen.make_templates(rng, 40, 128, 12, 24, density=dens)
+    tof = np.resize(np.arange(40), 800)
+    rng.shuffle(tof)
+    sets = [("density workload", clipgen.dense(n_clips=2000, n_templates=200), 2),
+            ("many polygons", clipgen.make_clips(rng, tpl, 128, 800, 1, 16, template_of=tof), 3)]
+    for label, cs, t in sets:
+        npoly = np.array([len(raster.components(raster.clip_raster(cs, i))[1]) for i in range(cs.n)])
+        by_tpl = {}
+        for i, tp in enumerate(cs.template.tolist()):
+            by_tpl.setdefault(tp, []).append(i)
+        reps, mems = [], []
+        for i in rng.choice(cs.n, size=min(cs.n, 800), replace=False).tolist():
+            mates = [j for j in by_tpl[int(cs.template[i])] if j != i]
+            for j in ([int(rng.choice(mates))] if mates else []) + [int(rng.integers(0, cs.n))]:
+                reps.append(i)
+                mems.append(j)
+        rep, mem = np.array(reps, np.int32), np.array(mems, np.int32)
+        strata = _edge_strata(cs, rep, mem, npoly)
+        say(f"[edge] {label}: {rep.size} pairs, per stratum {np.bincount(strata, minlength=4).tolist()}, "
+            f"max polygons {npoly.max()}")
+        h = ctx.clips(cs)
+        got = to_np(ctx.align_pairs(h, rep, mem, "edge", t))
+        ref = cover.align_pairs_edge(cs, rep, mem, t, workers=WORKERS)
+        check_edge(got, ref, rep, mem, label)
+        ok = [int(ref["ok"][strata == s].sum()) for s in range(4)]
+        set_bits = [int((ref["bits"][strata == s] != 0).sum()) for s in range(4)]
+        say(f"[edge] {label}: correspondences per stratum {ok}, set bits {set_bits}")
+        assert (strata == 3).sum() >= 100
+        if label == "many polygons":
+            assert ok[3] > 0 and set_bits[3] > 0
+        h.close()
+
+
 def test_prune_is_safe_and_matches_bounds(ctx):
     cs = small_set(96)
     say(f"[prune] cosine n={cs.n}")
