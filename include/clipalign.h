@@ -116,9 +116,23 @@ typedef struct {
  *     differ from the phase-correlation paths (their peak is the objective's
  *     maximiser only for pure translations); the count it returns is never
  *     smaller.  Rasters of 64 or 128 and half-windows <= 16 (CA_EUNSUPPORTED
- *     otherwise); CA_PATH_AUTO never selects it. */
+ *     otherwise); CA_PATH_AUTO never selects it.
+ *   CA_PATH_XYSEP: the geometric alternative of Sec. 3.2.1(2), "interval
+ *     competition", in place of phase correlation: the polygon correspondence
+ *     of the edge track at T0; per matched polygon pair the x and y intervals
+ *     [min, max] of its two box-edge displacements (member minus
+ *     representative); per axis the narrowest interval (ties: the first pair
+ *     in (member polygon, rep polygon) order, polygons numbered in raster
+ *     order) gives the shift as its midpoint, rounded half toward zero and
+ *     clamped to the member's window, named as the cosine window names it.
+ *     Without a correspondence (no polygon on a side, the exactly-one rule
+ *     fails, a clip with more than 64 polygons) the global bounding boxes give
+ *     the shift (T0).  Count, score and bit of Eq. 2 at the shift; empty clips
+ *     as on the other paths (CA_FLAG_EMPTY).  Integer arithmetic only; rasters
+ *     64, 128 and 256, any half-window; no spectra are read.  CA_PATH_AUTO
+ *     never selects it. */
 enum { CA_PATH_MIXED = 0, CA_PATH_FP32 = 1, CA_PATH_FP64 = 2, CA_PATH_AUTO = 3, CA_PATH_DIRECT = 4,
-       CA_PATH_XCORR = 5 };
+       CA_PATH_XCORR = 5, CA_PATH_XYSEP = 6 };
 
 /* Per-pair flag bits written by the alignment calls. */
 enum {
@@ -377,8 +391,9 @@ ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_con
  *      graph consumed by the set cover of Sec. 3.3) --------------------------- */
 
 /* Prune (ca_prune's bounds), align both directions of every candidate pair
- * (`path` for CA_COSINE, ignored for CA_EDGE) and compact the directions that
- * pass `con` into a CSR relation sorted by (representative, member):
+ * (`path` for CA_COSINE: any but CA_PATH_DIRECT; ignored for CA_EDGE) and
+ * compact the directions that pass `con` into a CSR relation sorted by
+ * (representative, member):
  *   row r, entries row_ptr[r] .. row_ptr[r+1]-1, lists the clips m != r that r
  *   covers (cosine: Eq. 2 strictly above thr_num/thr_den at the aligned shift;
  *   edge: correspondence and residual <= thr_num), members ascending.  The

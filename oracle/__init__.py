@@ -16,6 +16,10 @@ cosine  -- cosine track: spectra, whitening, phase-correlation surface
            thresholded bit (Eq. 2).
 edge    -- edge track: polygon correspondence (Sec. 2.2.2) and the separable
            L-infinity Min-Max midpoint solve (Eq. 6).
+xcorr   -- the exact objective: the window shift with the largest overlap
+           count (Sec. 3.2).
+xysep   -- cosine track aligned by XY-separation interval competition
+           (Sec. 3.2.1(2)) instead of phase correlation.
 prune   -- safe pre-screening bounds (area, row/column signatures, polygon
            bounding-box sizes).
 scp     -- surprisal-based greedy set cover, eager and lazy (Eqs. 7-9).

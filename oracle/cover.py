@@ -18,7 +18,7 @@ import os
 
 import numpy as np
 
-from . import cosine, edge, loop, raster, xcorr
+from . import cosine, edge, loop, raster, xcorr, xysep
 
 _SHARED = {}
 
@@ -86,6 +86,27 @@ def _xcorr_chunk(args):
     return bits, shift, c, sc
 
 
+def _xysep_chunk(args):
+    rep, mem, p, q = args
+    prep = _SHARED["prep"]
+    n = rep.size
+    bits = np.zeros(n, np.uint8)
+    shift = np.zeros((n, 2, 2), np.int16)
+    c = np.zeros((n, 2), np.int32)
+    sc = np.zeros((n, 2), np.float64)
+    matched = np.zeros((n, 2), bool)
+    for k in range(n):
+        j, i = int(rep[k]), int(mem[k])
+        for d, (m, r) in enumerate(((i, j), (j, i))):
+            res = xysep.align(prep.a(m), prep.a(r), prep.w(m), p, q)
+            bits[k] |= np.uint8(res["bit"]) << d
+            shift[k, d] = res["s"]
+            c[k, d] = res["c"]
+            sc[k, d] = res["score"]
+            matched[k, d] = res["matched"]
+    return bits, shift, c, sc, matched
+
+
 def _edge_chunk(args):
     rep, mem, t_edge = args
     prep = _SHARED["prep"]
@@ -132,6 +153,13 @@ def align_pairs_xcorr(clips, rep, mem, p, q, workers=None):
     """Exact-objective alignment on a pair list: dict(bits, shift, c, score)."""
     bits, shift, c, sc = _run(_xcorr_chunk, clips, rep, mem, (p, q), workers)
     return dict(bits=bits, shift=shift, c=c, score=sc)
+
+
+def align_pairs_xysep(clips, rep, mem, p, q, workers=None):
+    """Cosine track aligned by XY separation (Sec. 3.2.1(2)):
+    dict(bits, shift, c, score, matched)."""
+    bits, shift, c, sc, matched = _run(_xysep_chunk, clips, rep, mem, (p, q), workers)
+    return dict(bits=bits, shift=shift, c=c, score=sc, matched=matched)
 
 
 def align_pairs_edge(clips, rep, mem, t_edge, workers=None):

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libclipalign.so")
 
 CA_OK, CA_EINVAL, CA_ENOMEM, CA_EDEVICE, CA_EBUSY, CA_ETRUNC, CA_ESTATE, CA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 CA_COSINE, CA_EDGE = 1, 2
-PATHS = {"mixed": 0, "fp32": 1, "fp64": 2, "auto": 3, "direct": 4, "xcorr": 5}
+PATHS = {"mixed": 0, "fp32": 1, "fp64": 2, "auto": 3, "direct": 4, "xcorr": 5, "xysep": 6}
 CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64, CA_CLIPS_IMAGE, CA_CLIPS_NO_FP64 = 1, 2, 4, 8, 16
 FLAG_RESCORED_FWD, FLAG_RESCORED_REV, FLAG_EMPTY = 1, 2, 4
 FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16, 32, 64

@@ -897,6 +897,19 @@ static ca_status align_cosine(ca_ctx* ctx, const ca_clipset* crs, const ca_clips
   const ClipsDev& cm = cms->d;
   const int64_t n = io.n_pairs;
   const RescoreQueue none{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (path == CA_PATH_XYSEP) {
+    if (crs != cms) return fail(ctx, CA_EUNSUPPORTED, "CA_PATH_XYSEP aligns pairs within one clip set");
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0, s));
+    HIP_OR_FAIL(ctx, launch_xysep(cr, io, thr, s));
+    HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1, s));
+    HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->stats.t_main_ms += ms;
+    ctx->stats.n_main_launch += 1;
+    ctx->stats.pairs_aligned += n;
+    return CA_OK;
+  }
   const bool on_demand = !cr.spec64 || !cm.spec64;
   if (on_demand && path != CA_PATH_MIXED && path != CA_PATH_FP32)
     return fail(ctx, CA_EUNSUPPORTED, "this path needs FP64 spectra (clip set made with CA_CLIPS_NO_FP64)");
@@ -1040,7 +1053,7 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
   if (!rep || !mem || !bits || !shift || !count || !score || !flags)
     return fail(ctx, CA_EINVAL, "null output or pair pointer");
   if (n_pairs > (1ll << 31) - 1) return fail(ctx, CA_EINVAL, "pair list longer than 2^31 - 1");
-  if (path < CA_PATH_MIXED || path > CA_PATH_XCORR) return fail(ctx, CA_EINVAL, "bad path");
+  if (path < CA_PATH_MIXED || path > CA_PATH_XYSEP) return fail(ctx, CA_EINVAL, "bad path");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE);

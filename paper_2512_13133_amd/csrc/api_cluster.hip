@@ -384,6 +384,12 @@ static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, c
   return CA_OK;
 }
 
+// Cosine paths the cover relation and the clustering accept (every one but
+// the switched-off direct path).
+static bool cover_path_ok(int32_t path) {
+  return (path >= CA_PATH_MIXED && path <= CA_PATH_AUTO) || path == CA_PATH_XCORR || path == CA_PATH_XYSEP;
+}
+
 static bool valid_con(const ca_constraint* con) {
   if (!con) return false;
   if (con->kind == CA_COSINE)
@@ -398,8 +404,8 @@ extern "C" ca_status ca_cover(ca_ctx* ctx, void* stream, const ca_clipset* cs, c
   if (!ctx) return CA_EINVAL;
   if (!cs || ctx_of(cs) != ctx || !nnz || cap < 0) return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
-  if (con->kind == CA_COSINE && (path < CA_PATH_MIXED || path > CA_PATH_AUTO))
-    return fail_ctx(ctx, CA_EINVAL, "cover path must be CA_PATH_MIXED, CA_PATH_FP32, CA_PATH_FP64 or CA_PATH_AUTO");
+  if (con->kind == CA_COSINE && !cover_path_ok(path))
+    return fail_ctx(ctx, CA_EINVAL, "cover path must be CA_PATH_MIXED, CA_PATH_FP32, CA_PATH_FP64, CA_PATH_AUTO, CA_PATH_XCORR or CA_PATH_XYSEP");
   HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
   hipStream_t s = (hipStream_t)stream;
   CoverCache* cc = nullptr;
@@ -425,8 +431,8 @@ extern "C" ca_status ca_cover_dense(ca_ctx* ctx, void* stream, const ca_clipset*
   if (!ctx) return CA_EINVAL;
   if (!cs || ctx_of(cs) != ctx || !bits) return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
-  if (con->kind == CA_COSINE && (path < CA_PATH_MIXED || path > CA_PATH_AUTO))
-    return fail_ctx(ctx, CA_EINVAL, "cover path must be CA_PATH_MIXED, CA_PATH_FP32, CA_PATH_FP64 or CA_PATH_AUTO");
+  if (con->kind == CA_COSINE && !cover_path_ok(path))
+    return fail_ctx(ctx, CA_EINVAL, "cover path must be CA_PATH_MIXED, CA_PATH_FP32, CA_PATH_FP64, CA_PATH_AUTO, CA_PATH_XCORR or CA_PATH_XYSEP");
   if (n_of(cs) > CA_COVER_DENSE_MAX) return fail_ctx(ctx, CA_EUNSUPPORTED, "dense cover matrix above 65,536 clips");
   HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
   hipStream_t s = (hipStream_t)stream;

@@ -567,6 +567,279 @@ hipError_t launch_verify_edge(const ClipsDev& cs, int64_t n, const int32_t* mem,
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// XY-separation alignment of the cosine track (paper Sec. 3.2.1(2)).
+//
+// Per direction (member m against representative r) the polygon
+// correspondence of the edge track is taken at T0.  Every matched pair gives
+// an x interval and a y interval: [min, max] of the displacements (member
+// minus representative) of its two box edges on that axis.  Per axis the
+// narrowest interval wins (ties: the first pair in (member polygon, rep
+// polygon) order), and its midpoint, rounded half toward zero and clamped to
+// the member's window, is the shift on that axis.  Without a correspondence
+// (no polygon on a side, the exactly-one rule fails, more than 64 polygons)
+// the pair of global boxes gives the shift, which is T0.  Shifts are then
+// named as the cosine window names them (every residue in [-N/2, N/2 - 1]
+// when 2 w + 1 > N).  xysep_count_kernel evaluates Eq. 2 at the shifts.
+
+// A clamped shift named as the cosine window names it (N a power of two).
+__device__ __forceinline__ int cos_residue(int s, int w, int N) {
+  return (2 * w + 1 > N) ? ((s + N / 2) & (N - 1)) - N / 2 : s;
+}
+
+// 8 x 8 bit matrix transpose: bit 8 r + c -> bit 8 c + r.
+__device__ __forceinline__ unsigned long long transpose8(unsigned long long x) {
+  unsigned long long t;
+  t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+  x = x ^ t ^ (t << 7);
+  t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+  x = x ^ t ^ (t << 14);
+  t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+  x = x ^ t ^ (t << 28);
+  return x;
+}
+
+// Interval of one matched pair on one axis: the key orders pairs by width,
+// then by (p, q); the smaller key wins.
+__device__ __forceinline__ void xy_interval(int d0, int d1, int p, int q, int& key, int& lo, int& hi) {
+  lo = min(d0, d1);
+  hi = max(d0, d1);
+  key = ((hi - lo) << 12) | (p << 6) | q;
+}
+
+// The shift from the winning intervals (x: [xlo, xhi], y: [ylo, yhi]).
+__device__ __forceinline__ void xy_shift(int xlo, int xhi, int ylo, int yhi, int w, int N, int& sy, int& sx) {
+  int e;
+  minmax_axis(xlo, xhi, w, sx, e);
+  minmax_axis(ylo, yhi, w, sy, e);
+  sx = cos_residue(sx, w, N);
+  sy = cos_residue(sy, w, N);
+}
+
+// Winning intervals over the correspondence in an 8 x 8 relation word
+// (member polygons p, rep polygons q), on one lane.
+__device__ void xy_select8(unsigned long long rel, int Pm, int Pr, const int16_t* bm, const int16_t* br, int w,
+                           int N, int& sy, int& sx) {
+  int kx = 1 << 30, xlo = 0, xhi = 0, ky = 1 << 30, ylo = 0, yhi = 0;
+  const bool from_member = Pm <= Pr;
+  const int P = from_member ? Pm : Pr;
+  for (int t = 0; t < P; ++t) {
+    int p, q;
+    if (from_member) {
+      p = t;
+      q = __ffsll((unsigned long long)((rel >> (8 * t)) & 0xffull)) - 1;
+    } else {
+      q = t;
+      p = (__ffsll(rel & (0x0101010101010101ull << t)) - 1) >> 3;
+    }
+    const int16_t* a = bm + 4 * p;
+    const int16_t* b = br + 4 * q;
+    int k, lo, hi;
+    xy_interval(a[0] - b[0], a[1] - b[1], p, q, k, lo, hi);
+    if (k < kx) { kx = k; xlo = lo; xhi = hi; }
+    xy_interval(a[2] - b[2], a[3] - b[3], p, q, k, lo, hi);
+    if (k < ky) { ky = k; ylo = lo; yhi = hi; }
+  }
+  xy_shift(xlo, xhi, ylo, yhi, w, N, sy, sx);
+}
+
+// Clips with more than 8 polygons on a side (at most 64): one direction of
+// one pair on the whole wave, relation masks in LDS.  Returns the shift in
+// (sy, sx) on every lane.
+__device__ void xy_pair_lds(const ClipsDev& cs, int m, int r, int N, int w, int t0y, int t0x,
+                            unsigned long long* relM, unsigned long long* relR, int* sflag, int& sy, int& sx) {
+  const int lane = threadIdx.x;
+  const int Pm = cs.npoly[m], Pr = cs.npoly[r];
+  overlap_relation(cs, m, r, N, t0y, t0x, relM, relR);
+  if (!correspondence_ok(relM, relR, Pm, Pr, sflag)) {
+    sy = cos_residue(t0y, w, N);
+    sx = cos_residue(t0x, w, N);
+    return;
+  }
+  const bool from_member = Pm <= Pr;
+  const int P = from_member ? Pm : Pr;
+  int kx = 1 << 30, ky = 1 << 30, xlo = 0, xhi = 0, ylo = 0, yhi = 0;
+  if (lane < P) {
+    int p, q;
+    if (from_member) { p = lane; q = __ffsll((unsigned long long)relM[lane]) - 1; }
+    else { q = lane; p = __ffsll((unsigned long long)relR[lane]) - 1; }
+    const int16_t* a = cs.boxes + (int64_t)m * MAX_POLY * 4 + 4 * p;
+    const int16_t* b = cs.boxes + (int64_t)r * MAX_POLY * 4 + 4 * q;
+    xy_interval(a[0] - b[0], a[1] - b[1], p, q, kx, xlo, xhi);
+    xy_interval(a[2] - b[2], a[3] - b[3], p, q, ky, ylo, yhi);
+  }
+  int mx = kx, my = ky;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = min(mx, __shfl_xor(mx, off));
+    my = min(my, __shfl_xor(my, off));
+  }
+  // keys are distinct (they carry (p, q)), so exactly one lane holds each minimum
+  const int lx = __ffsll(__ballot(kx == mx)) - 1, ly = __ffsll(__ballot(ky == my)) - 1;
+  xy_shift(__shfl(xlo, lx), __shfl(xhi, lx), __shfl(ylo, ly), __shfl(yhi, ly), w, N, sy, sx);
+}
+
+// Shifts of both directions of 64 pairs per one-wave workgroup, one pair per
+// lane; the wave shares the relation work of each multi-polygon pair.
+// Writes io.shift and io.flags (CA_FLAG_EMPTY for an empty clip).
+__global__ void __launch_bounds__(64) xysep_shift_kernel(ClipsDev cs, PairIO io, int64_t block0) {
+  __shared__ unsigned long long relM[MAX_POLY], relR[MAX_POLY];
+  __shared__ int sflag;
+  const int lane = threadIdx.x;
+  const int64_t k0 = (block0 + (int64_t)blockIdx.x) * EDGE_PAIRS_PER_GROUP;
+  const int cnt = (int)min((int64_t)EDGE_PAIRS_PER_GROUP, io.n_pairs - k0);
+  const int64_t k = k0 + lane;
+
+  int i = 0, j = 0, N = 0, Pi = 0, Pj = 0, wi = 0, wj = 0;
+  bool big = false, empty = false, multi = false, mirror = true;
+  int sy[2] = {0, 0}, sx[2] = {0, 0}, T0y[2] = {0, 0}, T0x[2] = {0, 0};
+  if (lane < cnt) {
+    i = io.mem[k];
+    j = io.rep[k];
+    N = cs.N[i];
+    Pi = cs.npoly[i];
+    Pj = cs.npoly[j];
+    empty = Pi == 0 || Pj == 0;
+    const bool capped = Pi < 0 || Pj < 0;
+    big = !empty && !capped && (Pi > 8 || Pj > 8);
+    multi = !empty && !capped && !big && !(Pi == 1 && Pj == 1);
+    if (!empty) {
+      wi = cs.w[i];
+      wj = cs.w[j];
+      mirror = wi == wj;
+      const int16_t* gi = cs.gbox + 4 * i;
+      const int16_t* gj = cs.gbox + 4 * j;
+      const int dx0 = gi[0] - gj[0], dx1 = gi[1] - gj[1], dy0 = gi[2] - gj[2], dy1 = gi[3] - gj[3];
+      int e;
+      minmax_axis(min(dx0, dx1), max(dx0, dx1), wi, T0x[0], e);
+      minmax_axis(min(dy0, dy1), max(dy0, dy1), wi, T0y[0], e);
+      minmax_axis(min(-dx0, -dx1), max(-dx0, -dx1), wj, T0x[1], e);
+      minmax_axis(min(-dy0, -dy1), max(-dy0, -dy1), wj, T0y[1], e);
+      // single polygons, more than 64 polygons, or no correspondence: T0
+      sy[0] = cos_residue(T0y[0], wi, N);
+      sx[0] = cos_residue(T0x[0], wi, N);
+      sy[1] = cos_residue(T0y[1], wj, N);
+      sx[1] = cos_residue(T0x[1], wj, N);
+    }
+  }
+
+  // 2..8 polygons a side: relation at T0 (wave-shared), then per lane
+  {
+    int64_t a_rp_i = 0, a_rp_j = 0, a_ru_i = 0, a_ru_j = 0;
+    if (multi) {
+      a_rp_i = (int64_t)(cs.run_rowptr + cs.rowptr_off[i]);
+      a_rp_j = (int64_t)(cs.run_rowptr + cs.rowptr_off[j]);
+      a_ru_i = (int64_t)(cs.runs + cs.run_off[i]);
+      a_ru_j = (int64_t)(cs.runs + cs.run_off[j]);
+    }
+    unsigned long long rel0[2] = {0ull, 0ull};
+    for (unsigned long long m = __ballot(multi); m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const uint16_t* rp_i = (const uint16_t*)readlane64(a_rp_i, t);
+      const uint16_t* rp_j = (const uint16_t*)readlane64(a_rp_j, t);
+      const uint32_t* ru_i = (const uint32_t*)readlane64(a_ru_i, t);
+      const uint32_t* ru_j = (const uint32_t*)readlane64(a_ru_j, t);
+      const int Nt = __builtin_amdgcn_readlane(N, t);
+      const unsigned long long r0 = relation_runs(rp_i, ru_i, rp_j, ru_j, Nt, __builtin_amdgcn_readlane(T0y[0], t),
+                                                  __builtin_amdgcn_readlane(T0x[0], t), lane);
+      // equal windows: T0 of the reverse direction is the mirror, and its
+      // relation the transpose
+      unsigned long long r1 = transpose8(r0);
+      if (!__builtin_amdgcn_readlane((int)mirror, t))
+        r1 = relation_runs(rp_j, ru_j, rp_i, ru_i, Nt, __builtin_amdgcn_readlane(T0y[1], t),
+                           __builtin_amdgcn_readlane(T0x[1], t), lane);
+      if (lane == t) {
+        rel0[0] = r0;
+        rel0[1] = r1;
+      }
+    }
+    if (multi) {
+      for (int d = 0; d < 2; ++d) {
+        const int Pm = d == 0 ? Pi : Pj, Pr = d == 0 ? Pj : Pi;
+        if (corr8_ok(rel0[d], Pm, Pr)) {
+          const int mc = d == 0 ? i : j, rc = d == 0 ? j : i;
+          xy_select8(rel0[d], Pm, Pr, cs.boxes + (int64_t)mc * MAX_POLY * 4, cs.boxes + (int64_t)rc * MAX_POLY * 4,
+                     d == 0 ? wi : wj, N, sy[d], sx[d]);
+        }
+      }
+    }
+  }
+
+  // more than 8 polygons on a side: one direction at a time on the LDS path
+  for (unsigned long long m = __ballot(big); m; m &= m - 1ull) {
+    const int t = __ffsll(m) - 1;
+    const int ti = __builtin_amdgcn_readlane(i, t), tj = __builtin_amdgcn_readlane(j, t);
+    const int Nt = __builtin_amdgcn_readlane(N, t);
+    for (int d = 0; d < 2; ++d) {
+      int y, x;
+      xy_pair_lds(cs, d == 0 ? ti : tj, d == 0 ? tj : ti, Nt, __builtin_amdgcn_readlane(d == 0 ? wi : wj, t),
+                  __builtin_amdgcn_readlane(T0y[d], t), __builtin_amdgcn_readlane(T0x[d], t), relM, relR, &sflag, y,
+                  x);
+      if (lane == t) {
+        sy[d] = y;
+        sx[d] = x;
+      }
+    }
+  }
+
+  if (lane < cnt) {
+    for (int d = 0; d < 2; ++d) {
+      io.shift[k * 4 + 2 * d] = (int16_t)sy[d];
+      io.shift[k * 4 + 2 * d + 1] = (int16_t)sx[d];
+    }
+    io.flags[k] = empty ? (uint32_t)CA_FLAG_EMPTY : 0u;
+  }
+}
+
+// Eq. 2 at the shifts of both directions: one wave per pair.
+__global__ void __launch_bounds__(256) xysep_count_kernel(ClipsDev cs, PairIO io, Threshold thr, int64_t k0) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t k = k0 + (int64_t)blockIdx.x * 4 + wave;
+  if (k >= io.n_pairs) return;
+  const int i = io.mem[k], j = io.rep[k];
+  const int N = cs.N[i];
+  const int sy0 = io.shift[k * 4 + 0], sx0 = io.shift[k * 4 + 1];
+  const int sy1 = io.shift[k * 4 + 2], sx1 = io.shift[k * 4 + 3];
+  const uint64_t* bi = cs.bits + cs.bits_off[i];
+  const uint64_t* bj = cs.bits + cs.bits_off[j];
+  int c0 = 0, c1 = 0;
+  for (int y = lane; y < N; y += 64) {
+    c0 += row_overlap(bj, bi, N, y, sy0, sx0);  // member i against rep j
+    c1 += row_overlap(bi, bj, N, y, sy1, sx1);  // member j against rep i
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c0 += __shfl_xor(c0, off);
+    c1 += __shfl_xor(c1, off);
+  }
+  if (lane == 0) {
+    const int ni = cs.npix[i], nj = cs.npix[j];
+    io.count[k * 2 + 0] = c0;
+    io.count[k * 2 + 1] = c1;
+    io.score[k * 2 + 0] = cosine_score(c0, ni, nj);
+    io.score[k * 2 + 1] = cosine_score(c1, nj, ni);
+    io.bits[k] = (uint8_t)((cosine_bit(c0, ni, nj, thr) ? 1u : 0u) | (cosine_bit(c1, nj, ni, thr) ? 2u : 0u));
+  }
+}
+
+hipError_t launch_xysep(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s) {
+  if (io.n_pairs == 0) return hipSuccess;
+  const int64_t groups = (io.n_pairs + EDGE_PAIRS_PER_GROUP - 1) / EDGE_PAIRS_PER_GROUP;
+  for (int64_t b0 = 0; b0 < groups; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, groups - b0);
+    hipLaunchKernelGGL(xysep_shift_kernel, dim3(nb), dim3(64), 0, s, cs, io, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  for (int64_t k0 = 0; k0 < io.n_pairs; k0 += LAUNCH_CHUNK * 4) {
+    const int64_t nk = std::min<int64_t>(LAUNCH_CHUNK * 4, io.n_pairs - k0);
+    hipLaunchKernelGGL(xysep_count_kernel, dim3((unsigned)((nk + 3) / 4)), dim3(256), 0, s, cs, io, thr, k0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_edge(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s) {
   if (io.n_pairs == 0) return hipSuccess;
   const int64_t groups = (io.n_pairs + EDGE_PAIRS_PER_GROUP - 1) / EDGE_PAIRS_PER_GROUP;

@@ -51,6 +51,9 @@ hipError_t launch_pcm_fft64(const ClipsDev& cr, const ClipsDev& cm, const PairIO
                             int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s,
                             const unsigned long long* n_dev = nullptr);
 hipError_t launch_edge(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
+// XY-separation alignment of the cosine track: shifts of both directions
+// (io.shift, io.flags), then count, score and bit at them.
+hipError_t launch_xysep(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
 hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, int maxN, hipStream_t s);
 // Edge bounds pass: 64-bit chunk words of the survivor mask (ranges start on
 // words, range_off in bits) and survivor counts; the pairs are written by

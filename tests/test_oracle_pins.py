@@ -16,7 +16,7 @@ import pytest
 from scipy.fft import dctn
 
 import clipgen
-from oracle import cosine, cover, edge, loop, prune, raster, scp, serve, xcorr
+from oracle import cosine, cover, edge, loop, prune, raster, scp, serve, xcorr, xysep
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -419,6 +419,83 @@ def test_edge_recheck_change_clears_the_bit():
     # and the bit is set
     mem_ok = _bars([(1, 2), (20, 30), (40, 50), (52, 54)])
     assert edge.align(mem_ok, rep, 16, 2) == dict(s=(0, -1), E=2, bit=True, ok=True)
+
+
+# ---------------------------------------------------------------- XY separation (cosine track)
+
+
+def test_xysep_picks_the_narrowest_interval_per_axis():
+    """Hand-worked (Sec. 3.2.1(2)).  Rep boxes A = x[10,20) y[10,20) and
+    B = x[40,60) y[40,50); member boxes A' = x[14,23) y[11,22) and
+    B' = x[42,62) y[43,53).  T0 from the global boxes (d_x = 4, 2 -> 3;
+    d_y = 1, 3 -> 2) puts A' on A and B' on B only.  Intervals: A' x [3, 4]
+    (Q 1), y [1, 2] (Q 1); B' x [2, 2] (Q 0), y [3, 3] (Q 0).  B' wins both
+    axes: s = (3, 2).  The edge track's Min-Max over all edges gives (2, 3)
+    instead, and so does T0."""
+    N = 64
+    rep = raster.rasterize([(10, 20, 10, 20), (40, 60, 40, 50)], N)
+    mem = raster.rasterize([(14, 23, 11, 22), (42, 62, 43, 53)], N)
+    (s, matched) = xysep.shift(mem, rep, 8)
+    assert s == (3, 2) and matched
+    assert edge.align(mem, rep, 8, 10)["s"] == (2, 3)
+    res = xysep.align(mem, rep, 8, 19, 20)
+    c = int(np.count_nonzero(rep & np.roll(mem, (-3, -2), axis=(0, 1))))
+    assert res["s"] == (3, 2) and res["c"] == c
+    assert res["score"] == c / math.sqrt(float(mem.sum()) * float(rep.sum()))
+
+
+def test_xysep_ties_go_to_the_first_pair_and_windows_clamp():
+    """Hand-worked.  Both pairs have x intervals of width 0 (A' d_x = 3,
+    B' d_x = 2): the first pair in polygon order (A', the first in raster
+    order) wins, s_x = 3; y: A' [1, 2] (Q 1) loses to B' [5, 5] (Q 0),
+    s_y = 5.  With a half-window of 4 the y shift clamps to 4."""
+    N = 64
+    rep = raster.rasterize([(10, 20, 10, 20), (40, 60, 40, 50)], N)
+    mem = raster.rasterize([(13, 23, 11, 22), (42, 62, 45, 55)], N)
+    assert xysep.shift(mem, rep, 8) == ((5, 3), True)
+    assert xysep.shift(mem, rep, 4) == ((4, 3), True)
+
+
+def test_xysep_without_correspondence_uses_T0():
+    """Hand-worked.  One rep bar x[10,30) against two member bars x[12,18)
+    and x[22,28) (the rep is the fewer side and overlaps two member polygons
+    at T0, so the exactly-one rule fails): the shift is T0 of the global
+    boxes, d_x = 12-10, 28-30 = (2, -2) -> 0, d_y = 0 -> (0, 0)."""
+    N = 64
+    rep = _bars([(10, 30)])
+    mem = _bars([(12, 18), (22, 28)])
+    assert xysep.shift(mem, rep, 8) == ((0, 0), False)
+    # an empty member: no shift, no count
+    assert xysep.align(np.zeros_like(rep), rep, 8, 19, 20) == dict(s=(0, 0), c=0, score=0.0, bit=False,
+                                                                     matched=False)
+
+
+def test_xysep_recovers_translations_exactly():
+    """Closed form: a clip translated by t inside its window (content away
+    from the border, so every box moves by t) gives every interval [t, t], the
+    shift t and c = n: a full match."""
+    rng = np.random.default_rng(31)
+    N, w = 64, 8
+    for _ in range(40):
+        rects = []
+        for _ in range(int(rng.integers(1, 5))):
+            x0, y0 = rng.integers(10, 40, 2)
+            rects.append((int(x0), int(x0 + rng.integers(2, 12)), int(y0), int(y0 + rng.integers(2, 12))))
+        rep = raster.rasterize(rects, N)
+        ty, tx = (int(v) for v in rng.integers(-w, w + 1, 2))
+        mem = np.roll(rep, (ty, tx), axis=(0, 1))
+        res = xysep.align(mem, rep, w, 19, 20)
+        assert res["s"] == (ty, tx) and res["c"] == int(rep.sum()) and res["bit"]
+
+
+def test_xysep_names_residues_when_the_window_wraps():
+    """C0 rule: with 2w + 1 > N every residue is named in [-N/2, N/2 - 1];
+    a box pair displaced by +8 on a 16-grid with w = 8 gives the shift -8."""
+    N = 16
+    rep = raster.rasterize([(0, 4, 0, 4)], N)
+    mem = raster.rasterize([(8, 12, 0, 4)], N)
+    assert xysep.shift(mem, rep, 8) == ((0, -8), True)
+    assert xysep.residue(8, 8, 16) == -8 and xysep.residue(7, 8, 16) == 7 and xysep.residue(8, 8, 64) == 8
 
 
 # ---------------------------------------------------------------- pruning
