@@ -246,16 +246,11 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         const int nbytes = has_next ? MF_SPEC_BYTES : 0;
         const __amdgpu_buffer_rsrc_t mrs =
             __builtin_amdgcn_make_buffer_rsrc((void*)mptr, (short)0, MF_SPEC_BYTES, MF_RSRC_WORD3);
-        // The member's bit raster (2 KB) goes to the wave's LDS tile by direct
-        // global-to-LDS loads, which complete during the matrix loop; the overlap
-        // count reads it there.
-        uint64_t* mtile = reinterpret_cast<uint64_t*>(s_surf[wave]);
-        {
-          const uint64_t* mb_src = cm.bits + readlane64(t_bo, p) + 2 * lane;
-          __builtin_amdgcn_global_load_lds((const void*)mb_src, (__attribute__((address_space(3))) void*)mtile, 16, 0, 0);
-          __builtin_amdgcn_global_load_lds((const void*)(mb_src + 128),
-                                           (__attribute__((address_space(3))) void*)(mtile + 128), 16, 0, 0);
-        }
+        // The member's bit raster is read from global memory by the overlap
+        // count after the matrix loop.  (Staging it in LDS with direct
+        // global-to-LDS loads made the compiler wait for every outstanding load
+        // before each block's LDS reads, which undid the double buffering.)
+        const uint64_t* mbits = cm.bits + readlane64(t_bo, p);
         f4_t D2[3][3];
   #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -433,7 +428,6 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         // forward shift and the reverse one (mirror of the reverse top position)
         const int sy0 = i1f / 33 - 16, sx0 = i1f % 33 - 16;
         const int sy1 = 16 - i1r / 33, sx1 = 16 - i1r % 33;
-        const uint64_t* mbits = mtile;
         // c(s) of the reverse direction at -s equals the forward c(s)
         const int c0 = wave_overlap128(s_bits, mbits, sy0, sx0);
         const int c1 = i1r == i1f ? c0 : wave_overlap128(mbits, s_bits, sy1, sx1);
