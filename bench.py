@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--no-xcorr", action="store_true", help="skip the exact-objective alignment")
     ap.add_argument("--no-xysep", action="store_true", help="skip the XY-separation alignment")
     ap.add_argument("--no-mixed-sizes", action="store_true", help="skip the mixed-size workload")
+    ap.add_argument("--no-schedule-study", action="store_true", help="skip the relaxation-schedule study")
     ap.add_argument("--mixed-sizes-only", action="store_true",
                     help="only run the mixed-size workload (profiling) and print its object")
     ap.add_argument("--serve-library", type=int, default=100_000)
@@ -270,6 +271,8 @@ def main():
     torch.cuda.empty_cache()
     mixed_sizes = None if args.no_mixed_sizes else mixed_sizes_bench(ctx)
     torch.cuda.empty_cache()
+    schedules = None if args.no_schedule_study else schedule_study(ctx)
+    torch.cuda.empty_cache()
     serving = None if args.no_serving else serve_bench(ctx, args.serve_library, args.serve_seconds)
 
     line = {
@@ -290,6 +293,7 @@ def main():
         "xy_separation": xysep,
         "edge": edge,
         "mixed_sizes": mixed_sizes,
+        "schedule_study": schedules,
         "stage_ms": stage_ms,
         "stats": stats_out,
         "serving": serving,
@@ -342,6 +346,34 @@ def mixed_sizes_bench(ctx):
             "check_pairs": st["check_pairs"], "check_changed": st["check_changed"],
             "check_band_frac": round(st["check_band_frac"], 4),
             "tuned_paths": [ln.split(" us_per_kpair")[0] for ln in report.splitlines() if ln]}
+
+
+def schedule_study(ctx):
+    """Clusters of the coarse-to-fine loop under different relaxation
+    schedules (Sec. 3.1: relaxed coarse stages, strict last stage) on the
+    128 x 128 workload at 1:10 (5,000 clips, 100 templates): cosine 19/20 with
+    K iterations and total relaxation R, edge 3 px with K iterations and a
+    relaxation step in pixels; each entry is one full ca_cluster_schedule call
+    (cover at the loosest threshold, set cover, loop, center verification)."""
+    import torch
+
+    import clipgen
+    cs = clipgen.c128(n_clips=5000, n_templates=100)
+    h = ctx.clips(cs, fp32=True)
+    out = {"workload": "c128 at 1:10: 5,000 clips, 100 templates", "cosine": [], "edge": []}
+    runs = [("cosine", (19, 20), 1, (0, 1))] + [("cosine", (19, 20), K, (r, 100)) for K in (2, 3, 4)
+                                                for r in (1, 2, 4)]
+    runs += [("edge", 3, 1, 0)] + [("edge", 3, K, st) for K in (2, 3) for st in (1, 2)]
+    for kind, thr, K, relax in runs:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        got = ctx.cluster(h, kind, thr, iterations=K, relax=relax)
+        ms = (time.perf_counter() - t) * 1e3
+        entry = {"K": K, "clusters": got["n_clusters"], "ms": round(ms, 1)}
+        entry["relax"] = f"{relax[0]}/{relax[1]}" if kind == "cosine" else f"{relax} px/step"
+        out[kind].append(entry)
+    h.close()
+    return out
 
 
 def graph_bench(ctx, h, rep, mem, n=4096, reps=50):

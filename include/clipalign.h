@@ -455,6 +455,16 @@ ca_status ca_verify_centers(ca_ctx* ctx, void* stream, const ca_clipset* cs, con
 ca_status ca_cluster(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
                      int32_t path, int32_t iterations, int32_t* rep_of, int16_t* center_shift,
                      int64_t* n_clusters);
+/* ca_cluster with the relaxation of the coarse-to-fine schedule (Sec. 3.1:
+ * coarse stages under relaxed constraints, the last one strict) as a
+ * parameter, for schedule studies.  CA_COSINE: the thresholds are
+ * T - R (K - t) / (K - 1) for t = 1..K with R = relax_num / relax_den an exact
+ * rational, 0 <= R < T (ca_cluster uses R = 2/100).  CA_EDGE: T + relax_num
+ * (K - t) pixels, relax_den = 1 (ca_cluster uses 1 px).  CA_EINVAL otherwise.
+ * Everything else as ca_cluster. */
+ca_status ca_cluster_schedule(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                              int32_t path, int32_t iterations, int64_t relax_num, int64_t relax_den,
+                              int32_t* rep_of, int16_t* center_shift, int64_t* n_clusters);
 
 /* ---- serving: continuous batching against a device-resident library ---- */
 

@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import multiprocessing as mp
 import os
+from fractions import Fraction
 
 import numpy as np
 
@@ -172,9 +173,10 @@ def pixel_counts(clips):
     return np.array([int(raster.clip_raster(clips, i).sum()) for i in range(clips.n)], np.int64)
 
 
-def cluster_cosine(clips, p, q, K=1, rep=None, mem=None, res=None, workers=None):
+def cluster_cosine(clips, p, q, K=1, rep=None, mem=None, res=None, workers=None, relax=Fraction(2, 100)):
     """Closed loop on the cosine track over a candidate pair list (default: all
-    same-size pairs).  Returns dict(rep_of, shift, n_clusters, reps, log)."""
+    same-size pairs), with the schedule's total relaxation `relax`.  Returns
+    dict(rep_of, shift, n_clusters, reps, log)."""
     n = clips.n
     if rep is None:
         from clipgen import same_size_pairs
@@ -197,14 +199,15 @@ def cluster_cosine(clips, p, q, K=1, rep=None, mem=None, res=None, workers=None)
             cov[r_[ok], m_[ok]] = True
         return cov
 
-    sched = loop.cosine_schedule(p, q, K)
+    sched = loop.cosine_schedule(p, q, K, relax)
     rep_of, reps, log = loop.run(n, bits_at, sched)
     return dict(rep_of=rep_of, shift=_center_shift(n, rep, mem, res["shift"], rep_of),
                 n_clusters=len(reps), reps=reps, log=log)
 
 
-def cluster_edge(clips, t_edge, K=1, rep=None, mem=None, res=None, workers=None):
-    """Closed loop on the edge track (see cluster_cosine)."""
+def cluster_edge(clips, t_edge, K=1, rep=None, mem=None, res=None, workers=None, step=1):
+    """Closed loop on the edge track (see cluster_cosine), `step` pixels of
+    relaxation per coarse iteration."""
     n = clips.n
     if rep is None:
         from clipgen import same_size_pairs
@@ -222,7 +225,7 @@ def cluster_edge(clips, t_edge, K=1, rep=None, mem=None, res=None, workers=None)
             cov[r_[ok], m_[ok]] = True
         return cov
 
-    sched = loop.edge_schedule(t_edge, K)
+    sched = loop.edge_schedule(t_edge, K, step)
     rep_of, reps, log = loop.run(n, bits_at, sched)
     return dict(rep_of=rep_of, shift=_center_shift(n, rep, mem, res["shift"], rep_of),
                 n_clusters=len(reps), reps=reps, log=log)

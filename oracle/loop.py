@@ -29,18 +29,21 @@ import numpy as np
 from . import scp
 
 
-def cosine_schedule(p: int, q: int, K: int):
-    """[(p_t, q_t)] for t = 1..K, exact."""
+def cosine_schedule(p: int, q: int, K: int, relax=Fraction(2, 100)):
+    """[(p_t, q_t)] for t = 1..K, exact: T - relax (K - t)/(K - 1), the total
+    relaxation `relax` spread evenly over the coarse iterations."""
     T = Fraction(p, q)
+    relax = Fraction(relax)
     out = []
     for t in range(1, K + 1):
-        tau = T if K == 1 else T - Fraction(2, 100) * Fraction(K - t, K - 1)
+        tau = T if K == 1 else T - relax * Fraction(K - t, K - 1)
         out.append((tau.numerator, tau.denominator))
     return out
 
 
-def edge_schedule(t_edge: int, K: int):
-    return [t_edge + (K - t) for t in range(1, K + 1)]
+def edge_schedule(t_edge: int, K: int, step: int = 1):
+    """T_edge + step (K - t) pixels for t = 1..K."""
+    return [t_edge + step * (K - t) for t in range(1, K + 1)]
 
 
 def run(n: int, bits_at, schedule):

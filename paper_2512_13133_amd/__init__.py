@@ -32,7 +32,7 @@ NOALLOC_MAX_PAIRS = 1 << 20
 SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
     "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect", "ca_clips_image", "ca_clips_spectrum",
-    "ca_align_pairs", "ca_align_pairs_noalloc", "ca_surface", "ca_prune", "ca_cluster",
+    "ca_align_pairs", "ca_align_pairs_noalloc", "ca_surface", "ca_prune", "ca_cluster", "ca_cluster_schedule",
     "ca_cover", "ca_cover_dense", "ca_verify_centers",
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
     "ca_server_stats", "ca_server_run_stats", "ca_server_last_error",
@@ -100,6 +100,8 @@ def load():
     lib.ca_prune.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int64, P, P, C.POINTER(C.c_int64)]
     lib.ca_cluster.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int32, P, P,
                                C.POINTER(C.c_int64)]
+    lib.ca_cluster_schedule.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int32, C.c_int64,
+                                        C.c_int64, P, P, C.POINTER(C.c_int64)]
     lib.ca_cover.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64, P, P, P, P, P,
                              C.POINTER(C.c_int64)]
     lib.ca_cover_dense.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, P]
@@ -279,14 +281,23 @@ class Context:
                                           _ptr(rep), _ptr(mem), C.byref(got)))
         return rep[:n.value], mem[:n.value]
 
-    def cluster(self, clips, kind="cosine", thr=(19, 20), iterations=1, path="mixed"):
-        """Full method; returns dict(rep_of, center_shift, n_clusters) as numpy."""
+    def cluster(self, clips, kind="cosine", thr=(19, 20), iterations=1, path="mixed", relax=None):
+        """Full method; returns dict(rep_of, center_shift, n_clusters) as numpy.
+        ``relax``: the schedule's relaxation ((num, den) for the cosine track,
+        pixels per step for the edge track; ``ca_cluster_schedule``), or None
+        for the default."""
         rep_of = np.zeros(clips.n, np.int32)
         shift = np.zeros((clips.n, 2), np.int16)
         k = C.c_int64(0)
         con = constraint(kind, thr)
-        self._check(self.lib.ca_cluster(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path],
-                                        int(iterations), _ptr(rep_of), _ptr(shift), C.byref(k)))
+        if relax is None:
+            self._check(self.lib.ca_cluster(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path],
+                                            int(iterations), _ptr(rep_of), _ptr(shift), C.byref(k)))
+        else:
+            rn, rd = relax if isinstance(relax, tuple) else (int(relax), 1)
+            self._check(self.lib.ca_cluster_schedule(self.h, self._stream(), clips.handle, C.byref(con), PATHS[path],
+                                                     int(iterations), int(rn), int(rd), _ptr(rep_of), _ptr(shift),
+                                                     C.byref(k)))
         return dict(rep_of=rep_of, center_shift=shift, n_clusters=int(k.value))
 
     def cover(self, clips, kind="cosine", thr=(19, 20), path="mixed"):

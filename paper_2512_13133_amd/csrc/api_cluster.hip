@@ -616,26 +616,29 @@ std::vector<int32_t> lazy_greedy(const Cover& cv, const std::vector<int32_t>& po
 
 }  // namespace
 
+// relax_num / relax_den: the cosine schedule's total relaxation (tau_t =
+// T - relax (K - t) / (K - 1)), or the edge schedule's step in pixels
+// (tau_t = T + relax_num (K - t)).
 static ca_status cluster_impl(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
-                              int32_t path, int32_t K, int32_t* rep_of, int16_t* center_shift,
-                              int64_t* n_clusters) {
+                              int32_t path, int32_t K, int64_t relax_num, int64_t relax_den, int32_t* rep_of,
+                              int16_t* center_shift, int64_t* n_clusters) {
   const int64_t n = n_of(cs);
   // thresholds t = 1..K (exact rationals), loosest first
   std::vector<std::pair<int64_t, int64_t>> sched;
   for (int t = 1; t <= K; ++t) {
     if (con->kind == CA_COSINE) {
-      // T - (K - t) / (50 (K - 1))
+      // p/q - (a/b) (K - t)/(K - 1) = (p b (K - 1) - a q (K - t)) / (q b (K - 1))
       int64_t p = con->thr_num, q = con->thr_den;
       if (K > 1) {
-        const int64_t num = p * 50 * (K - 1) - (int64_t)(K - t) * q;
-        const int64_t den = q * 50 * (K - 1);
+        const int64_t num = p * relax_den * (K - 1) - relax_num * q * (int64_t)(K - t);
+        const int64_t den = q * relax_den * (K - 1);
         const int64_t g = std::gcd(std::max<int64_t>(num, 0), den);
         p = std::max<int64_t>(num, 0) / (g ? g : 1);
         q = den / (g ? g : 1);
       }
       sched.emplace_back(p, q);
     } else {
-      sched.emplace_back(con->thr_num + (K - t), 1);
+      sched.emplace_back(con->thr_num + relax_num * (K - t), 1);
     }
   }
   ca_constraint loose = *con;
@@ -751,5 +754,27 @@ extern "C" ca_status ca_cluster(ca_ctx* ctx, void* stream, const ca_clipset* cs,
   if (iterations < 1 || iterations > 64) return fail_ctx(ctx, CA_EINVAL, "iterations must be in [1, 64]");
   if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
   HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
-  return cluster_impl(ctx, (hipStream_t)stream, cs, con, path, iterations, rep_of, center_shift, n_clusters);
+  return cluster_impl(ctx, (hipStream_t)stream, cs, con, path, iterations, con->kind == CA_COSINE ? 2 : 1,
+                      con->kind == CA_COSINE ? 100 : 1, rep_of, center_shift, n_clusters);
+}
+
+extern "C" ca_status ca_cluster_schedule(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
+                                         int32_t path, int32_t iterations, int64_t relax_num, int64_t relax_den,
+                                         int32_t* rep_of, int16_t* center_shift, int64_t* n_clusters) {
+  if (!ctx) return CA_EINVAL;
+  if (!cs || ctx_of(cs) != ctx || !rep_of || !center_shift || !n_clusters)
+    return fail_ctx(ctx, CA_EINVAL, "bad arguments");
+  if (iterations < 1 || iterations > 64) return fail_ctx(ctx, CA_EINVAL, "iterations must be in [1, 64]");
+  if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (con->kind == CA_COSINE) {
+    // 0 <= relax < T, exact; kept small enough for 64-bit products
+    if (relax_num < 0 || relax_den <= 0 || relax_den > (1 << 24) ||
+        (__int128)relax_num * con->thr_den >= (__int128)con->thr_num * relax_den)
+      return fail_ctx(ctx, CA_EINVAL, "cosine relaxation must satisfy 0 <= relax_num/relax_den < thr_num/thr_den");
+  } else if (relax_num < 0 || relax_num > 1024 || relax_den != 1) {
+    return fail_ctx(ctx, CA_EINVAL, "edge relaxation is relax_num pixels per step (0..1024) with relax_den = 1");
+  }
+  HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
+  return cluster_impl(ctx, (hipStream_t)stream, cs, con, path, iterations, relax_num, relax_den, rep_of, center_shift,
+                      n_clusters);
 }

@@ -33,6 +33,7 @@ cannot drop a covering pair, so every relation below is the full one):
 from __future__ import annotations
 
 import hashlib
+from fractions import Fraction
 import multiprocessing as mp
 import os
 import sys
@@ -176,6 +177,11 @@ def make_small():
         out[f"edge_csr_{k}"] = csr[k]
     for K in (1, 3):
         clusters_to(out, f"edge_K{K}", cover.cluster_edge(cs, 2, K=K, rep=rep, mem=mem, res=er))
+    # other relaxation schedules (the schedule study's parity cases)
+    for key, K, relax in (("cos_K3r1", 3, Fraction(1, 100)), ("cos_K3r4", 3, Fraction(4, 100)),
+                          ("cos_K4r3", 4, Fraction(3, 100)), ("cos_K3r0", 3, Fraction(0))):
+        clusters_to(out, key, cover.cluster_cosine(cs, 19, 20, K=K, rep=rep, mem=mem, res=res, relax=relax))
+    clusters_to(out, "edge_K3s2", cover.cluster_edge(cs, 2, K=3, rep=rep, mem=mem, res=er, step=2))
     return out
 
 

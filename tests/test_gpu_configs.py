@@ -88,6 +88,22 @@ def test_small_workload_all_pairs(ctx, path):
     h.close()
 
 
+@pytest.mark.parametrize("key,K,relax", [("cos_K3r1", 3, (1, 100)), ("cos_K3r4", 3, (4, 100)),
+                                         ("cos_K4r3", 4, (3, 100)), ("cos_K3r0", 3, (0, 1)),
+                                         ("edge_K3s2", 3, 2)])
+def test_small_workload_relaxation_schedules(ctx, key, K, relax):
+    """Coarse-to-fine schedules other than the default (ca_cluster_schedule)
+    on the 256-clip workload: clusters and centers equal the oracle loop's."""
+    g = golden("small")
+    cs = clipgen.small()
+    h = ctx.clips(cs, fp32=True)
+    kind, thr = ("edge", 2) if key.startswith("edge") else ("cosine", (19, 20))
+    got = ctx.cluster(h, kind, thr, iterations=K, relax=relax)
+    _check_clusters(got, g, key, key)
+    say(f"[small] {key}: {got['n_clusters']} clusters, equal to the oracle")
+    h.close()
+
+
 # ------------------------------------------------------------------ 128 x 128 workload at 1:10
 
 

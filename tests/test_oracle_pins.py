@@ -10,6 +10,7 @@ import json
 import math
 import os
 from collections import deque
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -686,6 +687,23 @@ def test_schedules():
     assert loop.cosine_schedule(19, 20, 3) == [(93, 100), (47, 50), (19, 20)]
     assert loop.cosine_schedule(19, 20, 1) == [(19, 20)]
     assert loop.edge_schedule(2, 3) == [4, 3, 2]
+    # other relaxations: 0.95 - 0.03 (4 - t)/3 = 0.92, 0.93, 0.94, 0.95; 2 px a step
+    assert loop.cosine_schedule(19, 20, 4, Fraction(3, 100)) == [(23, 25), (93, 100), (47, 50), (19, 20)]
+    assert loop.edge_schedule(2, 3, 2) == [6, 4, 2]
+    assert loop.cosine_schedule(19, 20, 3, 0) == [(19, 20)] * 3
+
+
+def test_loop_without_relaxation_is_one_set_cover():
+    """With no relaxation every iteration uses the strict threshold: the
+    first set cover places every node and the later iterations find an empty
+    pool, so K iterations give the K = 1 result."""
+    rng = np.random.default_rng(20)
+    n = 30
+    cov = _random_cover(rng, n, 0.2)
+    one = loop.run(n, lambda tau: cov, [None])
+    three = loop.run(n, lambda tau: cov, [None, None, None])
+    assert one[1] == three[1] and (one[0] == three[0]).all()
+    assert [g["pool"] for g in three[2]] == [n, 0, 0]
 
 
 # ---------------------------------------------------------------- drivers
