@@ -104,7 +104,9 @@ typedef struct {
  *     bucket met for the first time is tuned on up to 4,096 of its pairs
  *     (repeated to at least 1,024 when the bucket is smaller):
  *     every applicable path is timed, a path is admitted only if its results
- *     equal CA_PATH_FP64's bit for bit, and the fastest admitted one is kept
+ *     equal CA_PATH_FP64's bit for bit, the admitted ones are timed again on a
+ *     contiguous run of up to 32,768 (64 x 64), 16,384 (128 x 128) or 8,192
+ *     (256 x 256) of the bucket's pairs, and the fastest admitted one is kept
  *     (see ca_autotune_*).  Results return in the caller's order.
  * All of them return identical shifts, counts, scores and bits.
  *   CA_PATH_XCORR: a different objective, the one Sec. 3.2 states for

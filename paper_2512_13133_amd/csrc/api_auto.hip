@@ -46,6 +46,10 @@ constexpr int W_BOUND[N_WCLASS] = {4, 7, 15, 16, 23, 31, 1 << 20};
 constexpr int N_KEYS = 3 * N_WCLASS;
 constexpr int64_t TUNE_SAMPLE = 4096;
 constexpr int64_t TUNE_MIN = 1024;  // a smaller bucket is repeated to this many pairs, so timings are throughputs
+// Pairs the admitted paths are timed on (a contiguous run of the bucket, so
+// that candidate lists keep their representatives together): enough tiles for
+// the persistent batched kernels to fill the device, fewer for larger rasters.
+constexpr int64_t tune_time_pairs(int N) { return N <= 64 ? 32768 : (N <= 128 ? 16384 : 8192); }
 
 __host__ __device__ inline int wclass_of(int w) {
   int c = 0;
@@ -152,8 +156,11 @@ double wall_us() {
 
 // Tune one bucket on `io` (its first pairs): time each applicable path and keep
 // the fastest whose results equal the FP64 path's.
+// `timing`: a run of the bucket's own pairs (outputs in the bucket's result
+// slices, which the bucket's launch overwrites) on which the admitted paths
+// other than FP64 are timed again when it is longer than the sample.
 ca_status tune_bucket(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshold thr, int key, const PairIO& io,
-                      char* ref_mem, char* tmp_mem, unsigned* bad, TuneEntry* out) {
+                      const PairIO& timing, char* ref_mem, char* tmp_mem, unsigned* bad, TuneEntry* out) {
   const int N = 64 << (key / N_WCLASS);
   const int wc = key % N_WCLASS;
   const ca_run_stats saved = *stats_of(ctx);
@@ -178,7 +185,7 @@ ca_status tune_bucket(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshol
     st = align_cosine_sets(ctx, cs, cs, s, thr, path, o, true, N, W_BOUND[wc]);
     if (st) return st;
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    *us = (wall_us() - t0) * 1000.0 / (double)m;
+    *us = (wall_us() - t0) * 1000.0 / (double)o.n_pairs;
     return CA_OK;
   };
   double us = 0.0;
@@ -202,6 +209,10 @@ ca_status tune_bucket(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshol
     HIP_TRY(ctx, hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (hbad != 0) continue;  // not valid on this bucket: never chosen
+    if (timing.n_pairs > m) {
+      st = run(path, timing, &us);
+      if (st) return st;
+    }
     e.us_per_kpair[path] = us;
     if (us < best) {
       best = us;
@@ -303,8 +314,10 @@ ca_status align_auto(ca_ctx* ctx, const ca_clipset* cs, hipStream_t s, Threshold
       AUTO_TRY(hipGetLastError());
       sample.rep = rep_s;
       sample.mem = mem_s;
+      PairIO timing = bio;
+      timing.n_pairs = std::min<int64_t>(m, tune_time_pairs(64 << (key / N_WCLASS)));
       TuneEntry e;
-      st = tune_bucket(ctx, cs, s, thr, key, sample, cal_ref, cal_tmp, hist + 32, &e);
+      st = tune_bucket(ctx, cs, s, thr, key, sample, timing, cal_ref, cal_tmp, hist + 32, &e);
       if (st) return done(st);
       it = table.emplace(key, e).first;
     }
