@@ -246,10 +246,7 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         const int nbytes = has_next ? MF_SPEC_BYTES : 0;
         const __amdgpu_buffer_rsrc_t mrs =
             __builtin_amdgcn_make_buffer_rsrc((void*)mptr, (short)0, MF_SPEC_BYTES, MF_RSRC_WORD3);
-        // The member's bit raster is read from global memory by the overlap
-        // count after the matrix loop.  (Staging it in LDS with direct
-        // global-to-LDS loads made the compiler wait for every outstanding load
-        // before each block's LDS reads, which undid the double buffering.)
+        // the member's bit raster, staged in LDS after the matrix loop
         const uint64_t* mbits = cm.bits + readlane64(t_bo, p);
         f4_t D2[3][3];
   #pragma unroll
@@ -340,6 +337,17 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
           block(mb + 1, m_odd);
         }
         have0 = has_next;
+        // the member's bit raster goes to the wave's LDS tile by direct
+        // global-to-LDS loads now, after the matrix loop (issued inside it they
+        // would make every block wait for all outstanding loads); they land
+        // while the peak search runs from the registers
+        uint64_t* mtile = reinterpret_cast<uint64_t*>(s_surf[wave]);
+        {
+          const uint64_t* mb_src = mbits + 2 * lane;
+          __builtin_amdgcn_global_load_lds((const void*)mb_src, (__attribute__((address_space(3))) void*)mtile, 16, 0, 0);
+          __builtin_amdgcn_global_load_lds((const void*)(mb_src + 128),
+                                           (__attribute__((address_space(3))) void*)(mtile + 128), 16, 0, 0);
+        }
 
         // D2[yb][db][t] holds K r(dy, dx) at dy = 16 yb - 16 + 4 g + t,
         // dx = 16 db - 16 + col (rows and columns valid up to 16).  Window
@@ -429,8 +437,8 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         const int sy0 = i1f / 33 - 16, sx0 = i1f % 33 - 16;
         const int sy1 = 16 - i1r / 33, sx1 = 16 - i1r % 33;
         // c(s) of the reverse direction at -s equals the forward c(s)
-        const int c0 = wave_overlap128(s_bits, mbits, sy0, sx0);
-        const int c1 = i1r == i1f ? c0 : wave_overlap128(mbits, s_bits, sy1, sx1);
+        const int c0 = wave_overlap128(s_bits, mtile, sy0, sx0);
+        const int c1 = i1r == i1f ? c0 : wave_overlap128(mtile, s_bits, sy1, sx1);
         const float band_k = band * sqrtf((float)K_hi);  // in units of K r
         const bool dec0 = (v1f - v2f) >= band_k;
         const bool dec1 = (v1r - v2r) >= band_k;
