@@ -436,6 +436,11 @@ pcm_mfma128_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, R
         // forward shift and the reverse one (mirror of the reverse top position)
         const int sy0 = i1f / 33 - 16, sx0 = i1f % 33 - 16;
         const int sy1 = 16 - i1r / 33, sx1 = 16 - i1r % 33;
+        // The wait for the direct loads is explicit: the compiler places its
+        // own from alias information, which has been seen to let a read of such
+        // a tile go ahead of it; the memory clobber keeps every tile read after
+        // it.  The direct loads were the last vector loads issued.
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         // c(s) of the reverse direction at -s equals the forward c(s)
         const int c0 = wave_overlap128(s_bits, mtile, sy0, sx0);
         const int c1 = i1r == i1f ? c0 : wave_overlap128(mtile, s_bits, sy1, sx1);

@@ -94,6 +94,10 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
   __shared__ h8_t s_b1[KB * NB * 64];  // stage-1 twiddles
   __shared__ h8_t s_a2[MB * NB * 64];  // stage-2 twiddles
   __shared__ int64_t s_tile;
+  // per wave: the pair's two bit rasters (member, then representative) for
+  // the overlap counts, at rasters up to 128 x 128
+  constexpr int BW = N <= 128 ? N * N / 64 : 1;  // 64-bit words of one raster
+  __shared__ uint64_t s_pbits[4][2 * BW];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -261,6 +265,27 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
         stage2(mb + 1);
       }
       have0 = has_next;
+      // the two bit rasters go to the wave's LDS tile by direct global-to-LDS
+      // loads issued after the matrix loop (inside it they would make each
+      // block wait for every outstanding load); they land during the peak search
+      if constexpr (N <= 128) {
+        const uint64_t* src_i = cm.bits + readlane64(t_boi, p);
+        const uint64_t* src_j = cr.bits + readlane64(t_boj, p);
+        if constexpr (N == 64) {
+          // 16 bytes a lane: lanes 0-31 the member's 512 bytes, 32-63 the representative's
+          const uint64_t* src = lane < 32 ? src_i + 2 * lane : src_j + 2 * (lane - 32);
+          __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)s_pbits[wave],
+                                           16, 0, 0);
+        } else {
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const uint64_t* src = (h < 2 ? src_i : src_j) + 128 * (h & 1) + 2 * lane;
+            __builtin_amdgcn_global_load_lds((const void*)src,
+                                             (__attribute__((address_space(3))) void*)(s_pbits[wave] + 128 * h), 16, 0,
+                                             0);
+          }
+        }
+      }
 
       // D2[yb][db][t] = K r(dy, dx) at dy = 16 yb + 4 g + t - C, dx = 16 db + col - C;
       // tile position (dy + C) W + (dx + C) breaks value ties low.
@@ -301,8 +326,14 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
       // the reverse direction's value at shift s is the forward value at -s
       const int sy0 = i1f / W - C, sx0 = i1f % W - C;
       const int sy1 = neg_rep(i1r / W - C, N), sx1 = neg_rep(i1r % W - C, N);
-      const uint64_t* bits_i = cm.bits + readlane64(t_boi, p);
-      const uint64_t* bits_j = cr.bits + readlane64(t_boj, p);
+      const uint64_t* bits_i = N <= 128 ? s_pbits[wave] : cm.bits + readlane64(t_boi, p);
+      const uint64_t* bits_j = N <= 128 ? s_pbits[wave] + BW : cr.bits + readlane64(t_boj, p);
+      // The compiler's own wait for the direct loads is not placed before every
+      // read of the tile (at 128 it let the first read of the representative's
+      // half go ahead of it), so the wait is explicit; the memory clobber keeps
+      // every tile read after it.  The direct loads were the last vector loads
+      // issued, so this waits for nothing else.
+      if constexpr (N <= 128) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       const int c0 = wave_overlap_n<N>(bits_j, bits_i, sy0, sx0, lane);
       const int c1 = i1r == i1f ? c0 : wave_overlap_n<N>(bits_i, bits_j, sy1, sx1, lane);
       const float band_k = band * sqrtf((float)K_hi);  // in units of K r
