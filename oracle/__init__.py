@@ -16,6 +16,9 @@ cosine  -- cosine track: spectra, whitening, phase-correlation surface
            thresholded bit (Eq. 2).
 edge    -- edge track: polygon correspondence (Sec. 2.2.2) and the separable
            L-infinity Min-Max midpoint solve (Eq. 6).
+contour -- edge track over full boundary edges: contour tracing, canonical
+           edge order, descriptor equality, and the topological-hash
+           pre-filter (Sec. 2.2.2; Sec. 3.1 stage 1).
 xcorr   -- the exact objective: the window shift with the largest overlap
            count (Sec. 3.2).
 xysep   -- cosine track aligned by XY-separation interval competition

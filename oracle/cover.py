@@ -19,7 +19,7 @@ from fractions import Fraction
 
 import numpy as np
 
-from . import cosine, edge, loop, raster, xcorr, xysep
+from . import contour, cosine, edge, loop, raster, xcorr, xysep
 
 _SHARED = {}
 
@@ -29,7 +29,7 @@ class Prepared:
 
     def __init__(self, clips):
         self.clips = clips
-        self._a, self._W = {}, {}
+        self._a, self._W, self._P = {}, {}, {}
 
     def a(self, i):
         i = int(i)
@@ -45,6 +45,13 @@ class Prepared:
 
     def w(self, i):
         return int(self.clips.marker_w[int(i)])
+
+    def polys(self, i):
+        """Labels, boxes and full-edge polygons (`contour.clip_polygons`)."""
+        i = int(i)
+        if i not in self._P:
+            self._P[i] = contour.clip_polygons(self.a(i))
+        return self._P[i]
 
 
 def _cosine_chunk(args):
@@ -127,6 +134,27 @@ def _edge_chunk(args):
     return bits, shift, E, ok
 
 
+def _contour_chunk(args):
+    rep, mem, t_edge = args
+    prep = _SHARED["prep"]
+    n = rep.size
+    bits = np.zeros(n, np.uint8)
+    shift = np.zeros((n, 2, 2), np.int16)
+    E = np.zeros((n, 2), np.int32)
+    ok = np.zeros((n, 2), bool)
+    topo = np.zeros((n, 2), bool)
+    for k in range(n):
+        j, i = int(rep[k]), int(mem[k])
+        for d, (m, r) in enumerate(((i, j), (j, i))):
+            res = contour.align(prep.a(m), prep.a(r), prep.w(m), t_edge, prep.polys(m), prep.polys(r))
+            bits[k] |= np.uint8(res["bit"]) << d
+            shift[k, d] = res["s"]
+            E[k, d] = res["E"]
+            ok[k, d] = res["ok"]
+            topo[k, d] = res["topo"]
+    return bits, shift, E, ok, topo
+
+
 def _run(fn, clips, rep, mem, extra, workers):
     rep = np.asarray(rep, np.int64)
     mem = np.asarray(mem, np.int64)
@@ -169,6 +197,13 @@ def align_pairs_edge(clips, rep, mem, t_edge, workers=None):
     return dict(bits=bits, shift=shift, E=E, ok=ok)
 
 
+def align_pairs_contour(clips, rep, mem, t_edge, workers=None):
+    """Edge track over full boundary edges (`contour`) on a pair list:
+    dict(bits, shift, E, ok, topo)."""
+    bits, shift, E, ok, topo = _run(_contour_chunk, clips, rep, mem, (t_edge,), workers)
+    return dict(bits=bits, shift=shift, E=E, ok=ok, topo=topo)
+
+
 def pixel_counts(clips):
     return np.array([int(raster.clip_raster(clips, i).sum()) for i in range(clips.n)], np.int64)
 
@@ -205,15 +240,17 @@ def cluster_cosine(clips, p, q, K=1, rep=None, mem=None, res=None, workers=None,
                 n_clusters=len(reps), reps=reps, log=log)
 
 
-def cluster_edge(clips, t_edge, K=1, rep=None, mem=None, res=None, workers=None, step=1):
+def cluster_edge(clips, t_edge, K=1, rep=None, mem=None, res=None, workers=None, step=1, edges="box"):
     """Closed loop on the edge track (see cluster_cosine), `step` pixels of
-    relaxation per coarse iteration."""
+    relaxation per coarse iteration; `edges` names the corresponding edges:
+    "box" (bounding-box sides, `edge`) or "contour" (full boundary edges)."""
     n = clips.n
     if rep is None:
         from clipgen import same_size_pairs
         rep, mem = same_size_pairs(clips)
     if res is None:
-        res = align_pairs_edge(clips, rep, mem, t_edge, workers)
+        fn = align_pairs_contour if edges == "contour" else align_pairs_edge
+        res = fn(clips, rep, mem, t_edge, workers)
     rep = np.asarray(rep, np.int64)
     mem = np.asarray(mem, np.int64)
 
@@ -283,7 +320,9 @@ def verify_centers(clips, rep_of, center_shift, kind, thr):
     Eq. 2 holds for the overlap count at it;
     edge (thr = T): the shift lies in i's window, at it the fewer side's
     polygons (both sides if equal) each overlap exactly one polygon of the
-    other clip, and over the matched bounding-box edges max |d - s| <= T."""
+    other clip, and over the matched bounding-box edges max |d - s| <= T;
+    contour (thr = T): as edge, over the full boundary edges of the matched
+    polygons, whose descriptors must be equal (`contour.residual_at`)."""
     bad = []
     n = clips.n
     for i in range(n):
@@ -307,6 +346,11 @@ def verify_centers(clips, rep_of, center_shift, kind, thr):
             if ok:
                 c = cosine.overlap(a_r, a_m, dy, dx)
                 ok = cosine.bit(c, int(a_m.sum()), int(a_r.sum()), thr[0], thr[1])
+        elif kind == "contour":
+            ok = abs(dy) <= w and abs(dx) <= w
+            if ok:
+                E = contour.residual_at(a_m, a_r, dy, dx)
+                ok = E is not None and E <= thr
         else:
             ok = abs(dy) <= w and abs(dx) <= w
             if ok:
