@@ -71,11 +71,33 @@ typedef struct {
 
 /* Constraint (paper Sec. 2.2).  CA_COSINE: Eq. 2, cosine strictly greater than
  * thr_num/thr_den (an exact rational, e.g. 19/20).  CA_EDGE: Sec. 2.2.2,
- * residual edge displacement at most thr_num pixels (thr_den must be 1). */
+ * residual edge displacement at most thr_num pixels (thr_den must be 1).
+ * edges (CA_EDGE only; 0 for CA_COSINE) names the corresponding edges of two
+ * matched polygons:
+ *   CA_EDGES_BOX: the four sides of the polygons' bounding boxes;
+ *   CA_EDGES_CONTOUR: every edge of the polygon boundaries (Sec. 2.2.2 read
+ *     over the full boundary).  A polygon's boundary is traced into closed
+ *     contours with the polygon on the right (image coordinates, y down; a
+ *     contour turns right where two of its pixels meet only diagonally); an
+ *     edge is a maximal straight run.  Each contour starts at the least
+ *     rotation of its direction codes (E 0, S 1, W 2, N 3; unique, since the
+ *     sequence of a closed contour has no shorter period), the outer contour
+ *     first, then the holes in raster order of their first vertex.  Two
+ *     matched polygons correspond only if these code sequences are equal
+ *     (else the direction has no correspondence: count -1, shift T0,
+ *     CA_FLAG_NO_MATCH_*); then edge k corresponds to edge k, vertical edges
+ *     displaced along x and horizontal ones along y.  Needs a clip set made
+ *     with CA_CLIPS_CONTOURS (CA_ESTATE otherwise); pairs with a clip of more
+ *     than 4,096 boundary edges return CA_EUNSUPPORTED.  The candidate
+ *     generation (ca_prune) adds the topological hash: every polygon of the
+ *     fewer side must find a polygon of the other side with the same hash
+ *     (FNV-1a over its code sequences, see ca_clips_contours) as well as
+ *     box sizes within 2 thr_num. */
 enum { CA_COSINE = 1, CA_EDGE = 2 };
+enum { CA_EDGES_BOX = 0, CA_EDGES_CONTOUR = 1 };
 typedef struct {
   int32_t kind;
-  int32_t reserved;
+  int32_t edges;
   int64_t thr_num;
   int64_t thr_den;
 } ca_constraint;
@@ -221,12 +243,16 @@ ca_status ca_reset_stats(ca_ctx* ctx);
  *     re-decision of CA_PATH_MIXED / CA_PATH_FP32 then computes the FP64
  *     spectra of just the clips it needs (same results).  CA_PATH_FP64,
  *     CA_PATH_AUTO and ca_graph_create return CA_EUNSUPPORTED on such sets.
+ *     CA_CLIPS_CONTOURS also traces every polygon's boundary into contours
+ *     (2 bytes an edge, 388 bytes a clip of tables) for the edge track over
+ *     full boundary edges (CA_EDGES_CONTOUR; ca_clips_contours reads them).
  * The library rasterises, counts pixels, row/column sums, 4-connected polygons
  * (at most 64 per clip; larger counts mark the clip and make the edge track
  * fail with CA_EUNSUPPORTED on it), and computes FP64 spectra, whitened with
  * |F| > 1e-2 kept, stored as FP16 (and FP32 / FP64 as requested).
  * Returns CA_EINVAL on a bad size or N, CA_ENOMEM if it does not fit. */
-enum { CA_CLIPS_DEVICE_PTRS = 1, CA_CLIPS_FP32 = 2, CA_CLIPS_FP64 = 4, CA_CLIPS_IMAGE = 8, CA_CLIPS_NO_FP64 = 16 };
+enum { CA_CLIPS_DEVICE_PTRS = 1, CA_CLIPS_FP32 = 2, CA_CLIPS_FP64 = 4, CA_CLIPS_IMAGE = 8, CA_CLIPS_NO_FP64 = 16,
+       CA_CLIPS_CONTOURS = 32 };
 ca_status ca_clips_create(ca_ctx* ctx, void* stream, int64_t n, const int64_t* rect_ptr,
                           const int32_t* rects, const int16_t* raster_n,
                           const int16_t* marker_w, int32_t flags, ca_clipset** out);
@@ -262,6 +288,25 @@ ca_status ca_clips_image(const ca_clipset* cs, int64_t i, float* img);
  * not kept (32: the set was made without CA_CLIPS_FP32). */
 ca_status ca_clips_spectrum(const ca_clipset* cs, int64_t i, int32_t precision, double* out);
 
+/* Copy clip i's polygon contours (Sec. 2.2.2 over full boundary edges) to
+ * host buffers; any pointer may be NULL to skip it.
+ *   n_edges: edges of the clip, or -1 when it has no contour data (its
+ *     polygons were not kept, or it has more than 4,096 boundary edges).
+ *   edges [cap] uint16: the clip's edges, polygon 0, 1, ... in turn; a
+ *     polygon lists its outer contour, then its holes in raster order of their
+ *     first vertex, each contour from the start of its least rotation.  A word
+ *     is coordinate (y of an E/W edge, x of an S/N edge; 0..N) | direction
+ *     (E 0, S 1, W 2, N 3) << 9 | (first edge of a contour) << 11.
+ *     CA_ETRUNC (n_edges written) if cap < n_edges.
+ *   poly_ptr [65] uint16: first edge of polygon p; entries from n_poly on
+ *     hold n_edges.
+ *   hashes [64] uint32: per polygon, FNV-1a (64-bit offset basis and prime)
+ *     over the bytes of its direction codes, each contour followed by the
+ *     byte 4, low 32 bits; 0 past the last polygon.
+ * CA_ESTATE if the set was created without CA_CLIPS_CONTOURS. */
+ca_status ca_clips_contours(const ca_clipset* cs, int64_t i, int32_t* n_edges, uint16_t* edges, int64_t cap,
+                            uint16_t* poly_ptr, uint32_t* hashes);
+
 /* ---- alignment on an explicit pair list (paper Sec. 3.2) ----------------- */
 
 /* Align n_pairs unordered pairs (rep[k], mem[k]) in both directions.
@@ -280,9 +325,10 @@ ca_status ca_clips_spectrum(const ca_clipset* cs, int64_t i, int32_t precision, 
  * 1e-9 of the maximum are tied and resolved by the larger overlap count, then
  * the smaller |dy|+|dx|, then the lexicographically smaller (dy, dx).
  * Edge track (CA_EDGE, paper Sec. 2.2.2, Eq. 6): polygon correspondence at the
- * global-bounding-box Min-Max shift, per-axis Min-Max midpoint over matched
- * bounding-box edges, re-check at the final shift, bit iff E <= thr_num;
- * `path` is ignored.
+ * global-bounding-box Min-Max shift, per-axis Min-Max midpoint over the
+ * corresponding edges of the matched polygons (bounding-box sides, or every
+ * boundary edge with con->edges == CA_EDGES_CONTOUR), re-check at the final
+ * shift, bit iff E <= thr_num; `path` is ignored.
  * Asynchronous on `stream` for CA_PATH_FP64 and the edge track; the other
  * paths synchronise once to size the FP64 re-decision pass, and
  * CA_PATH_AUTO allocates its work space and synchronises per bucket. */

@@ -133,11 +133,16 @@ def turning(edges):
 
 def least_rotation(codes):
     """Start index of the lexicographically least rotation (unique)."""
+    codes = tuple(codes)
     n = len(codes)
-    rots = [tuple(codes[i:]) + tuple(codes[:i]) for i in range(n)]
-    best = min(rots)
-    assert rots.count(best) == 1, "direction sequence with a shorter period"
-    return rots.index(best)
+
+    def rot(i):
+        return codes[i:] + codes[:i]
+
+    best = min(range(n), key=rot)
+    least = rot(best)
+    assert sum(1 for i in range(n) if rot(i) == least) == 1, "direction sequence with a shorter period"
+    return best
 
 
 def coord(e):
@@ -149,7 +154,11 @@ def coord(e):
 def polygon(inside):
     """Edges of one polygon in its canonical order: list of contours, each a
     list of (direction, coordinate); contour 0 is the outer one."""
-    cons = contours(inside)
+    return canonical(contours(inside))
+
+
+def canonical(cons):
+    """The contours of one polygon in canonical order (see `polygon`)."""
     outer = [c for c in cons if turning(c) == 4]
     holes = [c for c in cons if turning(c) == -4]
     assert len(outer) == 1 and len(outer) + len(holes) == len(cons)
@@ -190,10 +199,10 @@ def clip_polygons(a):
     P = boxes.shape[0]
     if P > MAX_POLYGONS:
         return lab, boxes, None
-    polys = [polygon(lab == p) for p in range(1, P + 1)]
-    if sum(len(c) for poly in polys for c in poly) > MAX_EDGES:
+    cons = [contours(lab == p) for p in range(1, P + 1)]
+    if sum(len(c) for cc in cons for c in cc) > MAX_EDGES:
         return lab, boxes, None
-    return lab, boxes, polys
+    return lab, boxes, [canonical(cc) for cc in cons]
 
 
 def solve(polys_m, polys_r, pairs, w):

@@ -24,6 +24,8 @@ CA_OK, CA_EINVAL, CA_ENOMEM, CA_EDEVICE, CA_EBUSY, CA_ETRUNC, CA_ESTATE, CA_EUNS
 CA_COSINE, CA_EDGE = 1, 2
 PATHS = {"mixed": 0, "fp32": 1, "fp64": 2, "auto": 3, "direct": 4, "xcorr": 5, "xysep": 6}
 CA_CLIPS_DEVICE_PTRS, CA_CLIPS_FP32, CA_CLIPS_FP64, CA_CLIPS_IMAGE, CA_CLIPS_NO_FP64 = 1, 2, 4, 8, 16
+CA_CLIPS_CONTOURS = 32
+CA_EDGES_BOX, CA_EDGES_CONTOUR = 0, 1
 FLAG_RESCORED_FWD, FLAG_RESCORED_REV, FLAG_EMPTY = 1, 2, 4
 FLAG_NO_MATCH_FWD, FLAG_NO_MATCH_REV, FLAG_RECHECK_FWD, FLAG_RECHECK_REV = 8, 16, 32, 64
 FLAG_INVALID = 128
@@ -32,6 +34,7 @@ NOALLOC_MAX_PAIRS = 1 << 20
 SYMBOLS = [
     "ca_create", "ca_destroy", "ca_last_error", "ca_get_stats", "ca_reset_stats",
     "ca_clips_create", "ca_clips_destroy", "ca_clips_count", "ca_clips_inspect", "ca_clips_image", "ca_clips_spectrum",
+    "ca_clips_contours",
     "ca_align_pairs", "ca_align_pairs_noalloc", "ca_surface", "ca_prune", "ca_cluster", "ca_cluster_schedule",
     "ca_cover", "ca_cover_dense", "ca_verify_centers",
     "ca_server_create", "ca_server_destroy", "ca_server_submit", "ca_server_poll", "ca_server_wait",
@@ -52,7 +55,7 @@ class _Config(C.Structure):
 
 
 class _Constraint(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("thr_num", C.c_int64), ("thr_den", C.c_int64)]
+    _fields_ = [("kind", C.c_int32), ("edges", C.c_int32), ("thr_num", C.c_int64), ("thr_den", C.c_int64)]
 
 
 class _Stats(C.Structure):
@@ -92,6 +95,7 @@ def load():
     lib.ca_clips_inspect.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P]
     lib.ca_clips_image.argtypes = [P, C.c_int64, P]
     lib.ca_clips_spectrum.argtypes = [P, C.c_int64, C.c_int32, P]
+    lib.ca_clips_contours.argtypes = [P, C.c_int64, P, P, C.c_int64, P, P]
     lib.ca_align_pairs.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64,
                                    P, P, P, P, P, P, P]
     lib.ca_align_pairs_noalloc.argtypes = [P, P, P, C.POINTER(_Constraint), C.c_int32, C.c_int64,
@@ -141,12 +145,15 @@ def _ptr(a):
 
 
 def constraint(kind, thr):
-    """('cosine', (p, q)) or ('edge', t_px) -> ca_constraint."""
+    """('cosine', (p, q)), ('edge', t_px) (bounding-box edges) or ('contour',
+    t_px) (the edge track over full boundary edges) -> ca_constraint."""
     if kind == "cosine":
         p, q = thr
-        return _Constraint(CA_COSINE, 0, int(p), int(q))
+        return _Constraint(CA_COSINE, CA_EDGES_BOX, int(p), int(q))
     if kind == "edge":
-        return _Constraint(CA_EDGE, 0, int(thr), 1)
+        return _Constraint(CA_EDGE, CA_EDGES_BOX, int(thr), 1)
+    if kind == "contour":
+        return _Constraint(CA_EDGE, CA_EDGES_CONTOUR, int(thr), 1)
     raise ValueError(kind)
 
 
@@ -195,17 +202,19 @@ class Context:
             self.h = None
 
     # -------------------------------------------------------------- clips
-    def clips(self, cs, fp32=False, image=False, fp64=True):
+    def clips(self, cs, fp32=False, image=False, fp64=True, contours=False):
         """Build a device clip set from a ``clipgen.ClipSet`` (host arrays).
 
         fp32: keep FP32 spectra (the "fp32" path); image: keep the FP16 whitened
         images (the "direct" path); fp64=False: keep no FP64 spectra (128 x 128
-        sets; the re-decision computes the ones it needs)."""
+        sets; the re-decision computes the ones it needs); contours: trace the
+        polygon contours (the "contour" kind of the edge track)."""
         ptr = np.ascontiguousarray(cs.rect_ptr, dtype=np.int64)
         rects = np.ascontiguousarray(cs.rects, dtype=np.int32).reshape(-1, 4)
         rn = np.ascontiguousarray(cs.raster_n, dtype=np.int16)
         mw = np.ascontiguousarray(cs.marker_w, dtype=np.int16)
-        flags = (CA_CLIPS_FP32 if fp32 else 0) | (CA_CLIPS_IMAGE if image else 0) | (0 if fp64 else CA_CLIPS_NO_FP64)
+        flags = (CA_CLIPS_FP32 if fp32 else 0) | (CA_CLIPS_IMAGE if image else 0) | (0 if fp64 else CA_CLIPS_NO_FP64) | \
+            (CA_CLIPS_CONTOURS if contours else 0)
         h = P()
         self._check(self.lib.ca_clips_create(self.h, self._stream(), rn.size, _ptr(ptr),
                                              _ptr(rects) if rects.size else None, _ptr(rn), _ptr(mw),
@@ -232,6 +241,18 @@ class Context:
         out = np.zeros((N, N // 2 + 1, 2), np.float64)
         self._check(self.lib.ca_clips_spectrum(clips.handle, int(i), int(precision), _ptr(out)))
         return out[..., 0] + 1j * out[..., 1]
+
+    def contours(self, clips, i):
+        """Contour tables of clip i: dict(n_edges, edges uint16, poly_ptr
+        uint16[65], hashes uint32[64]); n_edges -1 without contour data."""
+        ne = C.c_int32(0)
+        pp = np.zeros(65, np.uint16)
+        hs = np.zeros(64, np.uint32)
+        self._check(self.lib.ca_clips_contours(clips.handle, int(i), C.byref(ne), None, 0, _ptr(pp), _ptr(hs)))
+        edges = np.zeros(max(ne.value, 0), np.uint16)
+        if ne.value > 0:
+            self._check(self.lib.ca_clips_contours(clips.handle, int(i), None, _ptr(edges), edges.size, None, None))
+        return dict(n_edges=ne.value, edges=edges, poly_ptr=pp, hashes=hs)
 
     # -------------------------------------------------------------- pairs
     def align_pairs(self, clips, rep, mem, kind="cosine", thr=(19, 20), path="mixed", noalloc=False):

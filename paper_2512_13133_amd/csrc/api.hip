@@ -179,9 +179,11 @@ constexpr size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool valid_constraint(const ca_constraint* c) {
   if (!c) return false;
-  if (c->kind == CA_COSINE) return c->thr_num >= 0 && c->thr_den > 0 && c->thr_num <= c->thr_den &&
+  if (c->kind == CA_COSINE) return c->edges == 0 && c->thr_num >= 0 && c->thr_den > 0 && c->thr_num <= c->thr_den &&
                                    c->thr_den <= (1 << 24);
-  if (c->kind == CA_EDGE) return c->thr_num >= 0 && c->thr_den == 1 && c->thr_num < (1 << 20);
+  if (c->kind == CA_EDGE)
+    return (c->edges == CA_EDGES_BOX || c->edges == CA_EDGES_CONTOUR) && c->thr_num >= 0 && c->thr_den == 1 &&
+           c->thr_num < (1 << 20);
   return false;
 }
 
@@ -459,6 +461,28 @@ static ca_status clips_create_impl(ca_ctx* ctx, void* stream, int64_t n, const i
   ALLOC(runs, uint32_t, std::max<int64_t>(total_runs, 1));
   HIP_OR_FAIL(ctx, hipMemcpyAsync(drun_off, run_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
   HIP_OR_FAIL(ctx, launch_label(cs->d, n, s));
+  if (flags & CA_CLIPS_CONTOURS) {
+    // contours: edges per clip, their offsets (host scan), then the walk
+    ALLOC(cstat, int32_t, n);
+    ALLOC(cpoly, uint16_t, n * (MAX_POLY + 1));
+    ALLOC(chash, uint32_t, n * MAX_POLY);
+    HIP_OR_FAIL(ctx, launch_contour_count(cs->d, cs->d.cstat, s));
+    std::vector<int32_t> ne(n);
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ne.data(), cs->d.cstat, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
+    std::vector<int64_t> eoff(n);
+    int64_t total_edges = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      eoff[i] = total_edges;
+      total_edges += std::max(ne[i], 0);
+    }
+    int64_t* deo;
+    st = cs_alloc(ctx, cs, &p, sizeof(int64_t) * n); if (st) return bail(st); deo = (int64_t*)p;
+    cs->d.cedge_off = deo;
+    ALLOC(cedges, uint16_t, std::max<int64_t>(total_edges, 1));
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(deo, eoff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(ctx, launch_contour_trace(cs->d, cs->maxN, s));
+  }
   // spectra per raster size, in batches through an FP64 scratch
   for (int N : {64, 128, 256}) {
     std::vector<int64_t> ids;
@@ -589,6 +613,29 @@ ca_status ca_clips_spectrum(const ca_clipset* cs, int64_t i, int32_t precision, 
   return CA_OK;
 }
 
+ca_status ca_clips_contours(const ca_clipset* cs, int64_t i, int32_t* n_edges, uint16_t* edges, int64_t cap,
+                            uint16_t* poly_ptr, uint32_t* hashes) {
+  if (!cs) return CA_EINVAL;
+  ca_ctx* ctx = cs->ctx;
+  if (i < 0 || i >= cs->n) return fail(ctx, CA_EINVAL, "clip id out of range");
+  if (!cs->d.cstat) return fail(ctx, CA_ESTATE, "clip set created without CA_CLIPS_CONTOURS");
+  if (cap < 0) return fail(ctx, CA_EINVAL, "negative capacity");
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  int32_t ne = 0;
+  int64_t off = 0;
+  HIP_OR_FAIL(ctx, hipMemcpy(&ne, cs->d.cstat + i, 4, hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(ctx, hipMemcpy(&off, cs->d.cedge_off + i, 8, hipMemcpyDeviceToHost));
+  if (n_edges) *n_edges = ne;
+  if (poly_ptr)
+    HIP_OR_FAIL(ctx, hipMemcpy(poly_ptr, cs->d.cpoly + i * (MAX_POLY + 1), 2 * (MAX_POLY + 1), hipMemcpyDeviceToHost));
+  if (hashes) HIP_OR_FAIL(ctx, hipMemcpy(hashes, cs->d.chash + i * MAX_POLY, 4 * MAX_POLY, hipMemcpyDeviceToHost));
+  if (edges && ne > 0) {
+    if (cap < ne) return fail(ctx, CA_ETRUNC, "edge buffer too small");
+    HIP_OR_FAIL(ctx, hipMemcpy(edges, cs->d.cedges + off, 2 * (size_t)ne, hipMemcpyDeviceToHost));
+  }
+  return CA_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ alignment
@@ -598,7 +645,7 @@ namespace {
 // flag: a device word for the result (null: the context's scratch), cleared
 // here by a kernel.
 ca_status validate_pairs(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* cms, hipStream_t s,
-                         int64_t n_pairs, const int32_t* rep, const int32_t* mem, bool need_poly,
+                         int64_t n_pairs, const int32_t* rep, const int32_t* mem, int need_poly,
                          unsigned long long* flag = nullptr) {
   if (!flag) {
     void* sc;
@@ -608,12 +655,14 @@ ca_status validate_pairs(ca_ctx* ctx, const ca_clipset* crs, const ca_clipset* c
   }
   int* bad = (int*)flag;
   HIP_OR_FAIL(ctx, launch_zero_u64(flag, 1, s));
-  HIP_OR_FAIL(ctx, launch_validate(crs->d, cms->d, n_pairs, rep, mem, need_poly ? 1 : 0, bad, s));
+  HIP_OR_FAIL(ctx, launch_validate(crs->d, cms->d, n_pairs, rep, mem, need_poly, bad, s));
   int hbad = 0;
   HIP_OR_FAIL(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_OR_FAIL(ctx, hipStreamSynchronize(s));
   if (hbad & 1) return fail(ctx, CA_EINVAL, "pair list has an out-of-range id or unequal raster sizes");
   if (hbad & 2) return fail(ctx, CA_EUNSUPPORTED, "edge track on a clip with more than 64 polygons");
+  if (hbad & 4)
+    return fail(ctx, CA_EUNSUPPORTED, "full-edge track on a clip with more than 4,096 boundary edges");
   return CA_OK;
 }
 
@@ -1056,12 +1105,16 @@ extern "C" ca_status ca_align_pairs(ca_ctx* ctx, void* stream, const ca_clipset*
   if (path < CA_PATH_MIXED || path > CA_PATH_XYSEP) return fail(ctx, CA_EINVAL, "bad path");
   HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE);
+  const bool contour = con->kind == CA_EDGE && con->edges == CA_EDGES_CONTOUR;
+  if (contour && !cs->d.cstat)
+    return fail(ctx, CA_ESTATE, "CA_EDGES_CONTOUR needs a clip set created with CA_CLIPS_CONTOURS");
+  ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, con->kind == CA_EDGE ? (contour ? 2 : 1) : 0);
   if (st) return st;
   PairIO io{n_pairs, rep, mem, bits, shift, count, score, flags};
   if (con->kind == CA_EDGE) {
     HIP_OR_FAIL(ctx, hipMemsetAsync(score, 0, sizeof(double) * 2 * n_pairs, s));
-    HIP_OR_FAIL(ctx, launch_edge(cs->d, io, Threshold{con->thr_num, 1}, s));
+    if (contour) HIP_OR_FAIL(ctx, launch_edge_contour(cs->d, io, Threshold{con->thr_num, 1}, s));
+    else HIP_OR_FAIL(ctx, launch_edge(cs->d, io, Threshold{con->thr_num, 1}, s));
     ctx->stats.pairs_edge += n_pairs;
     return CA_OK;
   }
@@ -1088,6 +1141,9 @@ extern "C" ca_status ca_align_pairs_noalloc(ca_ctx* ctx, void* stream, const ca_
   if (!rep || !mem || !bits || !shift || !count || !score || !flags)
     return fail(ctx, CA_EINVAL, "null output or pair pointer");
   const bool cosine = con->kind == CA_COSINE;
+  const bool contour = con->kind == CA_EDGE && con->edges == CA_EDGES_CONTOUR;
+  if (contour && !cs->d.cstat)
+    return fail(ctx, CA_ESTATE, "CA_EDGES_CONTOUR needs a clip set created with CA_CLIPS_CONTOURS");
   if (cosine) {
     if (path != CA_PATH_MIXED && path != CA_PATH_FP32)
       return fail(ctx, CA_EUNSUPPORTED, "ca_align_pairs_noalloc runs CA_PATH_MIXED or CA_PATH_FP32");
@@ -1102,13 +1158,14 @@ extern "C" ca_status ca_align_pairs_noalloc(ca_ctx* ctx, void* stream, const ca_
   char* base = noalloc_base(ctx->device);
   if (!base) return fail(ctx, CA_ESTATE, "allocation-free work array not set up on this device");
   hipStream_t s = (hipStream_t)stream;
-  ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, !cosine,
+  ca_status st = validate_pairs(ctx, cs, cs, s, n_pairs, rep, mem, cosine ? 0 : (contour ? 2 : 1),
                                 (unsigned long long*)(base + NOALLOC_QUEUE_BYTES));
   if (st) return st;
   PairIO io{n_pairs, rep, mem, bits, shift, count, score, flags};
   if (!cosine) {
     HIP_OR_FAIL(ctx, launch_zero_u64((unsigned long long*)score, 2 * n_pairs, s));
-    HIP_OR_FAIL(ctx, launch_edge(cs->d, io, Threshold{con->thr_num, 1}, s));
+    if (contour) HIP_OR_FAIL(ctx, launch_edge_contour(cs->d, io, Threshold{con->thr_num, 1}, s));
+    else HIP_OR_FAIL(ctx, launch_edge(cs->d, io, Threshold{con->thr_num, 1}, s));
     ctx->stats.pairs_edge += n_pairs;
     return CA_OK;
   }

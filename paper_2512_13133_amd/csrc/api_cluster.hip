@@ -46,6 +46,11 @@ namespace {
 
 size_t aup(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Cache key of a constraint's kind and edge set.
+int64_t con_key(const ca_constraint* con) { return con->kind | ((int64_t)con->edges << 8); }
+
+bool over_contours(const ca_constraint* con) { return con->kind == CA_EDGE && con->edges == CA_EDGES_CONTOUR; }
+
 // Anchor order and partner ranges for a constraint (host side, O(n log n)).
 void build_ranges(const ca_clipset* cs, const ca_constraint* con, std::vector<int32_t>& order,
                   std::vector<int32_t>& hi, int64_t& screened) {
@@ -99,7 +104,7 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
                                      int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
   const bool edge = con->kind == CA_EDGE;
   PruneCache* pc = prune_cache_of(ctx);
-  const bool hit = pc->gen == gen_of(cs) && pc->kind == con->kind && pc->p == con->thr_num && pc->q == con->thr_den;
+  const bool hit = pc->gen == gen_of(cs) && pc->kind == con_key(con) && pc->p == con->thr_num && pc->q == con->thr_den;
   // a hit (the writing call after a sizing call) reuses the device copies of
   // the anchor order, ranges and bitmask
   int64_t na = pc->na;
@@ -120,7 +125,8 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     const size_t b_mask = aup(8 * (size_t)(bits / 64 + 1));
     // transposed sliding sums (rows, columns), or box sizes and polygon counts for the edge track
     const size_t b_soa = aup(4 * 64 * (size_t)na);
-    const size_t need = 2 * b_ord + 2 * b_rng + b_mask + 2 * b_soa;
+    const bool topo = over_contours(con);  // polygon hashes as a third table
+    const size_t need = 2 * b_ord + 2 * b_rng + b_mask + (topo ? 3 : 2) * b_soa;
     if (pc->bytes < need) {
       free_ctx(ctx, pc->dev, pc->bytes);
       pc->dev = nullptr;
@@ -143,9 +149,11 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     if (edge) {
       uint32_t* d_wh = (uint32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask);
       int32_t* d_np = (int32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask + b_soa);
-      HIP_TRY(ctx, launch_edge_soa(dev_of(cs), d_order, na, d_wh, d_np, s));
+      uint32_t* d_hash = topo ? (uint32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask + 2 * b_soa) : nullptr;
+      HIP_TRY(ctx, launch_edge_soa(dev_of(cs), d_order, na, d_wh, d_np, s, d_hash));
       pa.soa_wh = d_wh;
       pa.soa_np = d_np;
+      pa.soa_hash = d_hash;
       pa.soa_n = na;
       HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff,
                                      (unsigned long long*)d_mask, s));
@@ -165,7 +173,7 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     pc->total = 0;
     for (int64_t a = 0; a < na; ++a) pc->total += pc->counts[a];
     pc->gen = gen_of(cs);
-    pc->kind = con->kind;
+    pc->kind = con_key(con);
     pc->p = con->thr_num;
     pc->q = con->thr_den;
     pc->na = na;
@@ -243,8 +251,11 @@ extern "C" ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, c
   if (!ctx) return CA_EINVAL;
   if (!cs || ctx_of(cs) != ctx || !n_out) return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (!con || (con->kind != CA_COSINE && con->kind != CA_EDGE) || con->thr_den <= 0 ||
-      con->thr_num < 0 || (con->kind == CA_COSINE && con->thr_num > con->thr_den))
+      con->thr_num < 0 || (con->kind == CA_COSINE && con->thr_num > con->thr_den) ||
+      (con->kind == CA_COSINE && con->edges != 0) || (con->edges != CA_EDGES_BOX && con->edges != CA_EDGES_CONTOUR))
     return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (over_contours(con) && !dev_of(cs).cstat)
+    return fail_ctx(ctx, CA_ESTATE, "CA_EDGES_CONTOUR needs a clip set created with CA_CLIPS_CONTOURS");
   if (cap < 0 || (cap > 0 && (!rep || !mem))) return fail_ctx(ctx, CA_EINVAL, "bad output buffers");
   HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
   return prune_device(ctx, (hipStream_t)stream, cs, con, cap, cap > 0 ? rep : nullptr, mem, n_out);
@@ -270,7 +281,7 @@ struct DevBuf {
 };
 
 bool cover_hit(const CoverCache* cc, const ca_clipset* cs, const ca_constraint* con, int path) {
-  return cc->gen != 0 && cc->gen == gen_of(cs) && cc->kind == con->kind && cc->p == con->thr_num &&
+  return cc->gen != 0 && cc->gen == gen_of(cs) && cc->kind == con_key(con) && cc->p == con->thr_num &&
          cc->q == con->thr_den && cc->path == path;
 }
 
@@ -373,7 +384,7 @@ static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, c
     HIP_TRY(ctx, hipStreamSynchronize(s));
   }
   cc->gen = gen_of(cs);
-  cc->kind = con->kind;
+  cc->kind = con_key(con);
   cc->p = con->thr_num;
   cc->q = con->thr_den;
   cc->path = pth;
@@ -393,9 +404,19 @@ static bool cover_path_ok(int32_t path) {
 static bool valid_con(const ca_constraint* con) {
   if (!con) return false;
   if (con->kind == CA_COSINE)
-    return con->thr_num >= 0 && con->thr_den > 0 && con->thr_num <= con->thr_den && con->thr_den <= (1 << 24);
-  if (con->kind == CA_EDGE) return con->thr_num >= 0 && con->thr_den == 1 && con->thr_num < (1 << 20);
+    return con->edges == 0 && con->thr_num >= 0 && con->thr_den > 0 && con->thr_num <= con->thr_den &&
+           con->thr_den <= (1 << 24);
+  if (con->kind == CA_EDGE)
+    return (con->edges == CA_EDGES_BOX || con->edges == CA_EDGES_CONTOUR) && con->thr_num >= 0 &&
+           con->thr_den == 1 && con->thr_num < (1 << 20);
   return false;
+}
+
+// CA_EDGES_CONTOUR reads the contour tables of the clip set.
+static ca_status contours_ok(ca_ctx* ctx, const ca_clipset* cs, const ca_constraint* con) {
+  if (over_contours(con) && !dev_of(cs).cstat)
+    return fail_ctx(ctx, CA_ESTATE, "CA_EDGES_CONTOUR needs a clip set created with CA_CLIPS_CONTOURS");
+  return CA_OK;
 }
 
 extern "C" ca_status ca_cover(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
@@ -404,6 +425,7 @@ extern "C" ca_status ca_cover(ca_ctx* ctx, void* stream, const ca_clipset* cs, c
   if (!ctx) return CA_EINVAL;
   if (!cs || ctx_of(cs) != ctx || !nnz || cap < 0) return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (contours_ok(ctx, cs, con)) return CA_ESTATE;
   if (con->kind == CA_COSINE && !cover_path_ok(path))
     return fail_ctx(ctx, CA_EINVAL, "cover path must be CA_PATH_MIXED, CA_PATH_FP32, CA_PATH_FP64, CA_PATH_AUTO, CA_PATH_XCORR or CA_PATH_XYSEP");
   HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
@@ -431,6 +453,7 @@ extern "C" ca_status ca_cover_dense(ca_ctx* ctx, void* stream, const ca_clipset*
   if (!ctx) return CA_EINVAL;
   if (!cs || ctx_of(cs) != ctx || !bits) return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (contours_ok(ctx, cs, con)) return CA_ESTATE;
   if (con->kind == CA_COSINE && !cover_path_ok(path))
     return fail_ctx(ctx, CA_EINVAL, "cover path must be CA_PATH_MIXED, CA_PATH_FP32, CA_PATH_FP64, CA_PATH_AUTO, CA_PATH_XCORR or CA_PATH_XYSEP");
   if (n_of(cs) > CA_COVER_DENSE_MAX) return fail_ctx(ctx, CA_EUNSUPPORTED, "dense cover matrix above 65,536 clips");
@@ -493,7 +516,8 @@ static ca_status verify_centers(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs
     if (con->kind == CA_COSINE)
       HIP_TRY(ctx, launch_verify_cosine(dev_of(cs), m, d_mem, d_rep, d_sh, thr, d_out, d_out + 1, s));
     else
-      HIP_TRY(ctx, launch_verify_edge(dev_of(cs), m, d_mem, d_rep, d_sh, thr, d_out, d_out + 1, s));
+      HIP_TRY(ctx, launch_verify_edge(dev_of(cs), m, d_mem, d_rep, d_sh, thr, d_out, d_out + 1, s,
+                                      over_contours(con)));
     unsigned long long h[2];
     HIP_TRY(ctx, hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -518,6 +542,7 @@ extern "C" ca_status ca_verify_centers(ca_ctx* ctx, void* stream, const ca_clips
   if (!cs || ctx_of(cs) != ctx || !rep_of || !center_shift || !n_violations)
     return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (contours_ok(ctx, cs, con)) return CA_ESTATE;
   HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
   return verify_centers(ctx, (hipStream_t)stream, cs, con, rep_of, center_shift, n_violations, first_violation);
 }
@@ -753,6 +778,7 @@ extern "C" ca_status ca_cluster(ca_ctx* ctx, void* stream, const ca_clipset* cs,
     return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (iterations < 1 || iterations > 64) return fail_ctx(ctx, CA_EINVAL, "iterations must be in [1, 64]");
   if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (contours_ok(ctx, cs, con)) return CA_ESTATE;
   HIP_TRY(ctx, hipSetDevice(device_of(ctx)));
   return cluster_impl(ctx, (hipStream_t)stream, cs, con, path, iterations, con->kind == CA_COSINE ? 2 : 1,
                       con->kind == CA_COSINE ? 100 : 1, rep_of, center_shift, n_clusters);
@@ -766,6 +792,7 @@ extern "C" ca_status ca_cluster_schedule(ca_ctx* ctx, void* stream, const ca_cli
     return fail_ctx(ctx, CA_EINVAL, "bad arguments");
   if (iterations < 1 || iterations > 64) return fail_ctx(ctx, CA_EINVAL, "iterations must be in [1, 64]");
   if (!valid_con(con)) return fail_ctx(ctx, CA_EINVAL, "bad constraint");
+  if (contours_ok(ctx, cs, con)) return CA_ESTATE;
   if (con->kind == CA_COSINE) {
     // 0 <= relax < T, exact; kept small enough for 64-bit products
     if (relax_num < 0 || relax_den <= 0 || relax_den > (1 << 24) ||

@@ -358,7 +358,7 @@ extern "C" ca_status ca_server_create(ca_ctx* ctx, const ca_clipset* library, co
   if (!ctx) return CA_EINVAL;
   if (!library || ctx_of(library) != ctx || !con || !out || slots < 1 || slots > 32)
     return fail_ctx(ctx, CA_EINVAL, "bad server arguments");
-  if (con->kind != CA_COSINE || con->thr_den <= 0 || con->thr_num < 0 || con->thr_num > con->thr_den)
+  if (con->kind != CA_COSINE || con->edges != 0 || con->thr_den <= 0 || con->thr_num < 0 || con->thr_num > con->thr_den)
     return fail_ctx(ctx, CA_EUNSUPPORTED, "serving supports the cosine constraint");
   if (!mixed_ok_of(library))
     return fail_ctx(ctx, CA_EUNSUPPORTED, "serving needs a 128 x 128 library with half-windows <= 16");

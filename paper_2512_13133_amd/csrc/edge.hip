@@ -72,7 +72,44 @@ __device__ bool correspondence_ok(const unsigned long long* relM, const unsigned
   return ok;
 }
 
-// LDS path: any polygon count up to the cap, relation masks in LDS.
+// Displacement extremes (member minus representative) over the contour edges
+// of member polygon p of clip m and representative polygon q of clip r, edge k
+// against edge k of the two canonical lists; false when the direction codes
+// or contour boundaries differ (the polygons have no edge correspondence).
+__device__ bool contour_pair(const ClipsDev& cs, int m, int r, int p, int q, int& xlo, int& xhi, int& ylo, int& yhi) {
+  const uint16_t* pm = cs.cpoly + (int64_t)m * (MAX_POLY + 1);
+  const uint16_t* pr = cs.cpoly + (int64_t)r * (MAX_POLY + 1);
+  const int a0 = pm[p], n = pm[p + 1] - a0, b0 = pr[q];
+  if (pr[q + 1] - b0 != n) return false;
+  const uint16_t* em = cs.cedges + cs.cedge_off[m] + a0;
+  const uint16_t* er = cs.cedges + cs.cedge_off[r] + b0;
+  for (int k = 0; k < n; ++k) {
+    const int u = em[k], v = er[k];
+    if ((u ^ v) >> 9) return false;
+    const int d = (u & 511) - (v & 511);
+    if (u & (1 << 9)) {  // S or N: a vertical edge, displaced along x
+      xlo = min(xlo, d);
+      xhi = max(xhi, d);
+    } else {
+      ylo = min(ylo, d);
+      yhi = max(yhi, d);
+    }
+  }
+  return true;
+}
+
+// Largest |d - s| over the same corresponding edges at shift (sy, sx); false
+// when the polygons have no edge correspondence.
+__device__ bool contour_residual(const ClipsDev& cs, int m, int r, int p, int q, int sy, int sx, int& res) {
+  int xlo = 1 << 20, xhi = -(1 << 20), ylo = 1 << 20, yhi = -(1 << 20);
+  if (!contour_pair(cs, m, r, p, q, xlo, xhi, ylo, yhi)) return false;
+  res = max(max(xhi - sx, sx - xlo), max(yhi - sy, sy - ylo));
+  return true;
+}
+
+// LDS path: any polygon count up to the cap, relation masks in LDS.  CONTOUR:
+// the Min-Max runs over the full boundary edges of the matched polygons.
+template <bool CONTOUR>
 __device__ void edge_pair_lds(const ClipsDev& cs, const PairIO& io, Threshold thr, int64_t k,
                               unsigned long long* relM, unsigned long long* relR, unsigned long long* relM0,
                               unsigned long long* relR0, int* sflag_p, int (*red)[64]) {
@@ -119,15 +156,28 @@ __device__ void edge_pair_lds(const ClipsDev& cs, const PairIO& io, Threshold th
     int xlo = 1 << 20, xhi = -(1 << 20), ylo = 1 << 20, yhi = -(1 << 20);
     const bool from_member = Pm <= Pr;
     const int P = from_member ? Pm : Pr;
+    bool same = true;
     if (lane < P) {
       int p, qq;
       if (from_member) { p = lane; qq = __ffsll((unsigned long long)relM0[lane]) - 1; }
       else { qq = lane; p = __ffsll((unsigned long long)relR0[lane]) - 1; }
-      const int16_t* a = bm + 4 * p;
-      const int16_t* b = br + 4 * qq;
-      const int d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2], d3 = a[3] - b[3];
-      xlo = min(d0, d1); xhi = max(d0, d1);
-      ylo = min(d2, d3); yhi = max(d2, d3);
+      if constexpr (CONTOUR) {
+        same = contour_pair(cs, m, r, p, qq, xlo, xhi, ylo, yhi);
+      } else {
+        const int16_t* a = bm + 4 * p;
+        const int16_t* b = br + 4 * qq;
+        const int d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2], d3 = a[3] - b[3];
+        xlo = min(d0, d1); xhi = max(d0, d1);
+        ylo = min(d2, d3); yhi = max(d2, d3);
+      }
+    }
+    if (CONTOUR && __ballot(!same)) {  // wave-uniform: no edge correspondence
+      if (lane == 0) {
+        write_direction(io, k, d, s0y, s0x, -1, 0.0, false);
+        io.flags[k] |= nomatch;
+      }
+      __syncthreads();
+      continue;
     }
     red[0][lane] = xlo; red[1][lane] = xhi; red[2][lane] = ylo; red[3][lane] = yhi;
     __syncthreads();
@@ -494,7 +544,162 @@ __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, 
 
   // clips with more than 8 polygons, one pair at a time on the LDS path
   for (unsigned long long m = __ballot(big); m; m &= m - 1ull)
-    edge_pair_lds(cs, io, thr, k0 + (__ffsll(m) - 1), relM, relR, relM0, relR0, &sflag, red);
+    edge_pair_lds<false>(cs, io, thr, k0 + (__ffsll(m) - 1), relM, relR, relM0, relR0, &sflag, red);
+}
+
+// ---------------------------------------------------------------------------
+// Edge track over full boundary edges (CA_EDGES_CONTOUR).  The correspondence
+// at T0, the exactly-one rule and the re-check at the solved shift are those
+// of the box track; the Min-Max solve runs over every edge of the matched
+// polygons (contour_pair: edge k against edge k of the canonical lists, no
+// correspondence when the code sequences differ).  One pair per lane for
+// clips of up to 8 polygons (the wave shares each pair's relation sweep), the
+// LDS path one pair at a time above that.
+
+// Min-Max shift and residual over the contour edges of the correspondence in
+// the 8 x 8 relation word rel; false when a matched pair has no edge
+// correspondence.
+__device__ bool contour_matched_shift(const ClipsDev& cs, int m, int r, unsigned long long rel, int Pm, int Pr, int w,
+                                      int& sy, int& sx, int& E) {
+  int xlo = 1 << 20, xhi = -(1 << 20), ylo = 1 << 20, yhi = -(1 << 20);
+  const bool from_member = Pm <= Pr;
+  const int P = from_member ? Pm : Pr;
+  for (int t = 0; t < P; ++t) {
+    int p, q;
+    if (from_member) { p = t; q = __ffsll((unsigned long long)((rel >> (8 * t)) & 0xffull)) - 1; }
+    else {
+      q = t;
+      const unsigned long long col = rel & (0x0101010101010101ull << t);
+      p = (__ffsll(col) - 1) >> 3;
+    }
+    if (!contour_pair(cs, m, r, p, q, xlo, xhi, ylo, yhi)) return false;
+  }
+  int ex, ey;
+  minmax_axis(xlo, xhi, w, sx, ex);
+  minmax_axis(ylo, yhi, w, sy, ey);
+  E = max(ex, ey);
+  return true;
+}
+
+__global__ void __launch_bounds__(64) edge_contour_kernel(ClipsDev cs, PairIO io, Threshold thr, int64_t block0) {
+  __shared__ unsigned long long relM[MAX_POLY], relR[MAX_POLY];
+  __shared__ unsigned long long relM0[MAX_POLY], relR0[MAX_POLY];
+  __shared__ int sflag;
+  __shared__ int red[4][64];
+  const int lane = threadIdx.x;
+  const int64_t k0 = (block0 + (int64_t)blockIdx.x) * EDGE_PAIRS_PER_GROUP;
+  const int cnt = (int)min((int64_t)EDGE_PAIRS_PER_GROUP, io.n_pairs - k0);
+  const int64_t k = k0 + lane;
+
+  int i = 0, j = 0, N = 0, Pi = 0, Pj = 0, wi = 0, wj = 0;
+  bool none = false, empty = false, small = false, big = false, mirror = true;
+  int T0y[2] = {0, 0}, T0x[2] = {0, 0};
+  if (lane < cnt) {
+    i = io.mem[k];
+    j = io.rep[k];
+    Pi = cs.npoly[i];
+    Pj = cs.npoly[j];
+    empty = Pi == 0 || Pj == 0;
+    none = empty || Pi < 0 || Pj < 0 || cs.cstat[i] < 0 || cs.cstat[j] < 0;
+    small = !none && Pi <= 8 && Pj <= 8;
+    big = !none && !small;
+    if (small) {
+      N = cs.N[i];
+      wi = cs.w[i];
+      wj = cs.w[j];
+      mirror = wi == wj;
+      const int16_t* gi = cs.gbox + 4 * i;
+      const int16_t* gj = cs.gbox + 4 * j;
+      const int dx0 = gi[0] - gj[0], dx1 = gi[1] - gj[1], dy0 = gi[2] - gj[2], dy1 = gi[3] - gj[3];
+      int e_unused;
+      minmax_axis(min(dx0, dx1), max(dx0, dx1), wi, T0x[0], e_unused);
+      minmax_axis(min(dy0, dy1), max(dy0, dy1), wi, T0y[0], e_unused);
+      minmax_axis(min(-dx0, -dx1), max(-dx0, -dx1), wj, T0x[1], e_unused);
+      minmax_axis(min(-dy0, -dy1), max(-dy0, -dy1), wj, T0y[1], e_unused);
+    }
+  }
+  int sy[2] = {0, 0}, sx[2] = {0, 0}, E[2] = {-1, -1};
+  bool matched[2] = {false, false}, ok[2] = {false, false};
+  {
+    int64_t a_rp_i = 0, a_rp_j = 0, a_ru_i = 0, a_ru_j = 0;
+    if (small) {
+      a_rp_i = (int64_t)(cs.run_rowptr + cs.rowptr_off[i]);
+      a_rp_j = (int64_t)(cs.run_rowptr + cs.rowptr_off[j]);
+      a_ru_i = (int64_t)(cs.runs + cs.run_off[i]);
+      a_ru_j = (int64_t)(cs.runs + cs.run_off[j]);
+    }
+    unsigned long long rel0[2] = {0ull, 0ull}, rel1[2] = {0ull, 0ull};
+    auto relation_of = [&](int t, int d, int dy, int dx) {
+      const uint16_t* rp_i = (const uint16_t*)readlane64(a_rp_i, t);
+      const uint16_t* rp_j = (const uint16_t*)readlane64(a_rp_j, t);
+      const uint32_t* ru_i = (const uint32_t*)readlane64(a_ru_i, t);
+      const uint32_t* ru_j = (const uint32_t*)readlane64(a_ru_j, t);
+      const int Nt = __builtin_amdgcn_readlane(N, t);
+      return d == 0 ? relation_runs(rp_i, ru_i, rp_j, ru_j, Nt, dy, dx, lane)
+                    : relation_runs(rp_j, ru_j, rp_i, ru_i, Nt, dy, dx, lane);
+    };
+    for (unsigned long long m = __ballot(small); m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const int nd = __builtin_amdgcn_readlane((int)mirror, t) ? 1 : 2;
+      for (int d = 0; d < nd; ++d) {
+        const unsigned long long r =
+            relation_of(t, d, __builtin_amdgcn_readlane(T0y[d], t), __builtin_amdgcn_readlane(T0x[d], t));
+        if (lane == t) rel0[d] = r;
+      }
+    }
+    if (small) {
+      for (int d = 0; d < (mirror ? 1 : 2); ++d) {
+        const int Pm = d == 0 ? Pi : Pj, Pr = d == 0 ? Pj : Pi;
+        sy[d] = T0y[d];
+        sx[d] = T0x[d];
+        matched[d] = corr8_ok(rel0[d], Pm, Pr) &&
+                     contour_matched_shift(cs, d == 0 ? i : j, d == 0 ? j : i, rel0[d], Pm, Pr, d == 0 ? wi : wj,
+                                           sy[d], sx[d], E[d]);
+        if (!matched[d]) {
+          sy[d] = T0y[d];
+          sx[d] = T0x[d];
+          E[d] = -1;
+        }
+      }
+    }
+    for (unsigned long long m = __ballot(small && matched[0]); m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const unsigned long long r =
+          relation_of(t, 0, __builtin_amdgcn_readlane(sy[0], t), __builtin_amdgcn_readlane(sx[0], t));
+      if (lane == t) rel1[0] = r;
+    }
+    for (unsigned long long m = __ballot(small && !mirror && matched[1]); m; m &= m - 1ull) {
+      const int t = __ffsll(m) - 1;
+      const unsigned long long r =
+          relation_of(t, 1, __builtin_amdgcn_readlane(sy[1], t), __builtin_amdgcn_readlane(sx[1], t));
+      if (lane == t) rel1[1] = r;
+    }
+    if (small)
+      for (int d = 0; d < (mirror ? 1 : 2); ++d)
+        ok[d] = matched[d] && same_matching(rel1[d], rel0[d], d == 0 ? Pi : Pj, d == 0 ? Pj : Pi);
+  }
+
+  if (small || none) {
+    uint32_t fl = empty ? (uint32_t)CA_FLAG_EMPTY : 0u;
+    if (mirror && small) {  // equal windows: the reverse direction is the exact mirror
+      sy[1] = -sy[0]; sx[1] = -sx[0]; E[1] = E[0]; matched[1] = matched[0]; ok[1] = ok[0];
+    }
+    uint8_t bits = 0;
+    for (int d = 0; d < 2; ++d) {
+      io.shift[k * 4 + 2 * d] = (int16_t)sy[d];
+      io.shift[k * 4 + 2 * d + 1] = (int16_t)sx[d];
+      io.count[k * 2 + d] = E[d];
+      io.score[k * 2 + d] = 0.0;
+      if (!matched[d]) fl |= d == 0 ? CA_FLAG_NO_MATCH_FWD : CA_FLAG_NO_MATCH_REV;
+      else if (!ok[d]) fl |= d == 0 ? CA_FLAG_RECHECK_FWD : CA_FLAG_RECHECK_REV;
+      if (ok[d] && (int64_t)E[d] <= thr.p) bits |= (uint8_t)(1u << d);
+    }
+    io.bits[k] = bits;
+    io.flags[k] = fl;
+  }
+
+  for (unsigned long long m = __ballot(big); m; m &= m - 1ull)
+    edge_pair_lds<true>(cs, io, thr, k0 + (__ffsll(m) - 1), relM, relR, relM0, relR0, &sflag, red);
 }
 
 }  // namespace ca
@@ -506,6 +711,7 @@ namespace ca {
 // the counts are equal) each overlap exactly one polygon of the other clip at
 // the shift, and over the matched bounding-box edges the residual
 // max |d - s| per axis is at most T.  One wave per member.
+template <bool CONTOUR>
 __global__ void __launch_bounds__(64) edge_verify_kernel(ClipsDev cs, int64_t n, int64_t t0, const int32_t* mem,
                                                          const int32_t* rep, const int16_t* shift, Threshold thr,
                                                          unsigned long long* viol, unsigned long long* first) {
@@ -535,10 +741,15 @@ __global__ void __launch_bounds__(64) edge_verify_kernel(ClipsDev cs, int64_t n,
       int p, q;
       if (from_member) { p = lane; q = __ffsll((unsigned long long)relM[lane]) - 1; }
       else { q = lane; p = __ffsll((unsigned long long)relR[lane]) - 1; }
-      const int16_t* a = bm + 4 * p;
-      const int16_t* b = br + 4 * q;
-      ex = max(abs(a[0] - b[0] - sx), abs(a[1] - b[1] - sx));
-      ey = max(abs(a[2] - b[2] - sy), abs(a[3] - b[3] - sy));
+      if constexpr (CONTOUR) {
+        // no edge correspondence: a residual above any threshold
+        if (!contour_residual(cs, m, r, p, q, sy, sx, ex)) ex = 1 << 30;
+      } else {
+        const int16_t* a = bm + 4 * p;
+        const int16_t* b = br + 4 * q;
+        ex = max(abs(a[0] - b[0] - sx), abs(a[1] - b[1] - sx));
+        ey = max(abs(a[2] - b[2] - sy), abs(a[3] - b[3] - sy));
+      }
     }
     red[0][lane] = max(ex, ey);
     __syncthreads();
@@ -556,11 +767,15 @@ __global__ void __launch_bounds__(64) edge_verify_kernel(ClipsDev cs, int64_t n,
 
 hipError_t launch_verify_edge(const ClipsDev& cs, int64_t n, const int32_t* mem, const int32_t* rep,
                               const int16_t* shift, Threshold thr, unsigned long long* viol, unsigned long long* first,
-                              hipStream_t s) {
+                              hipStream_t s, bool contour) {
   for (int64_t t0 = 0; t0 < n; t0 += LAUNCH_CHUNK) {
     const int64_t nt = std::min<int64_t>(LAUNCH_CHUNK, n - t0);
-    hipLaunchKernelGGL(edge_verify_kernel, dim3((unsigned)nt), dim3(64), 0, s, cs, n, t0, mem, rep, shift, thr, viol,
-                       first);
+    if (contour)
+      hipLaunchKernelGGL(edge_verify_kernel<true>, dim3((unsigned)nt), dim3(64), 0, s, cs, n, t0, mem, rep, shift, thr,
+                         viol, first);
+    else
+      hipLaunchKernelGGL(edge_verify_kernel<false>, dim3((unsigned)nt), dim3(64), 0, s, cs, n, t0, mem, rep, shift,
+                         thr, viol, first);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -834,6 +1049,19 @@ hipError_t launch_xysep(const ClipsDev& cs, const PairIO& io, Threshold thr, hip
   for (int64_t k0 = 0; k0 < io.n_pairs; k0 += LAUNCH_CHUNK * 4) {
     const int64_t nk = std::min<int64_t>(LAUNCH_CHUNK * 4, io.n_pairs - k0);
     hipLaunchKernelGGL(xysep_count_kernel, dim3((unsigned)((nk + 3) / 4)), dim3(256), 0, s, cs, io, thr, k0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_edge_contour(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s) {
+  if (io.n_pairs == 0) return hipSuccess;
+  if (!cs.cstat) return hipErrorInvalidValue;  // the kernel reads the contour tables
+  const int64_t groups = (io.n_pairs + EDGE_PAIRS_PER_GROUP - 1) / EDGE_PAIRS_PER_GROUP;
+  for (int64_t b0 = 0; b0 < groups; b0 += LAUNCH_CHUNK) {
+    const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, groups - b0);
+    hipLaunchKernelGGL(edge_contour_kernel, dim3(nb), dim3(64), 0, s, cs, io, thr, b0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -17,6 +17,7 @@ constexpr double EPS = 1e-2;
 constexpr int MAX_POLY = 64;       // polygons per clip kept for the edge track
 constexpr int MAX_RUNS = 4096;     // row runs per clip handled by the labeller
 constexpr int MAX_AXIS = 65;       // window positions per axis (half-window <= 32)
+constexpr int MAX_EDGES = 4096;    // boundary edges per clip kept for the full-edge track
 
 // Device-resident clip set.  Per-clip arrays are indexed by clip id; pools are
 // addressed through per-clip offsets that depend only on the raster size.
@@ -47,6 +48,16 @@ struct ClipsDev {
   double2* spec64;           // per clip: [u][v <= N/2] (optional)
   const int64_t* img_off;    // [n] element offset into img16 (N*N each), or null
   __half* img16;             // per clip: whitened image N * IDFT2(W), row-major (optional)
+  // Polygon contours (sets made with CA_CLIPS_CONTOURS; null otherwise).  The
+  // edges of a clip list polygon 0, 1, ... in turn, each polygon its outer
+  // contour and then its holes, each contour from the start of its least
+  // rotation: coordinate (y of E/W edges, x of S/N edges) | direction
+  // (E 0, S 1, W 2, N 3) << 9 | first edge of a contour << 11.
+  int32_t* cstat;            // [n] edges of the clip, or -1 without contour data
+  const int64_t* cedge_off;  // [n] offset into cedges
+  uint16_t* cedges;
+  uint16_t* cpoly;           // [n][MAX_POLY + 1] first edge of each polygon (relative), then the total
+  uint32_t* chash;           // [n][MAX_POLY] polygon hash (FNV-1a 64 over the codes, low 32 bits)
 };
 
 // Per-call alignment problem in device-visible form.
@@ -129,6 +140,9 @@ struct PruneArgs {
   // position b at [q * soa_n + b]) and polygon counts by position
   const uint32_t* soa_wh = nullptr;
   const int32_t* soa_np = nullptr;
+  // edge track over full boundary edges: polygon hashes in the layout of
+  // soa_wh, and polygons match only with equal hashes (null: box track)
+  const uint32_t* soa_hash = nullptr;
   int seg = 0;      // partners per workgroup (0: one workgroup per anchor range; > 0: n_seg
                     // segments per anchor, counts and offs indexed [a * n_seg + segment])
   int n_seg = 1;

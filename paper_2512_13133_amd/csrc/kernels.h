@@ -51,6 +51,12 @@ hipError_t launch_pcm_fft64(const ClipsDev& cr, const ClipsDev& cm, const PairIO
                             int LINES, int Lmax, int maxN, const RescoreQueue& q, hipStream_t s,
                             const unsigned long long* n_dev = nullptr);
 hipError_t launch_edge(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
+// Contours of every clip: the count pass writes edges per clip (or -1) into
+// counts; the trace pass (after cedge_off is set) writes cedges, cpoly, chash.
+hipError_t launch_contour_count(const ClipsDev& cs, int32_t* counts, hipStream_t s);
+hipError_t launch_contour_trace(const ClipsDev& cs, int maxN, hipStream_t s);
+// Edge track over full boundary edges (clip sets with contours).
+hipError_t launch_edge_contour(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
 // XY-separation alignment of the cosine track: shifts of both directions
 // (io.shift, io.flags), then count, score and bit at them.
 hipError_t launch_xysep(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
@@ -58,9 +64,10 @@ hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshol
 // Edge bounds pass: 64-bit chunk words of the survivor mask (ranges start on
 // words, range_off in bits) and survivor counts; the pairs are written by
 // launch_prune128(..., write = true) with order_ids set.
-// Transposed polygon box sizes (MAX_POLY x n words) and counts (n) of the clips in `order`.
+// Transposed polygon box sizes (MAX_POLY x n words) and counts (n) of the clips in `order`, and
+// with soa_hash the polygon hashes in the layout of the sizes (edge track over contours).
 hipError_t launch_edge_soa(const ClipsDev& cs, const int32_t* order, int64_t n, uint32_t* soa_wh, int32_t* soa_np,
-                           hipStream_t s);
+                           hipStream_t s, uint32_t* soa_hash = nullptr);
 hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
                              unsigned long long* mask, hipStream_t s);
 // Batched MFMA surface for raster 128, half-windows <= 16 (fragment tables from
@@ -154,6 +161,6 @@ hipError_t launch_verify_cosine(const ClipsDev& cs, int64_t n, const int32_t* me
                                 unsigned long long* first, hipStream_t s);
 hipError_t launch_verify_edge(const ClipsDev& cs, int64_t n, const int32_t* mem, const int32_t* rep,
                               const int16_t* shift, Threshold thr, unsigned long long* viol, unsigned long long* first,
-                              hipStream_t s);
+                              hipStream_t s, bool contour = false);
 
 }  // namespace ca

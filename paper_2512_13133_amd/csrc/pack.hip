@@ -277,7 +277,8 @@ __global__ void __launch_bounds__(256) label_kernel(ClipsDev cs, int64_t block0)
 namespace ca {
 
 // Pair validation: ids in range, equal raster sizes, and (for the edge track)
-// polygon tables within the cap.  Sets *bad to 1 (ids/sizes) or 2 (polygons).
+// polygon tables within the cap, and (need_poly 2: full boundary edges)
+// contour data.  Sets *bad to 1 (ids/sizes), 2 (polygons) or 4 (contours).
 __global__ void validate_pairs_kernel(ClipsDev cr, ClipsDev cm, int64_t n_pairs, const int32_t* __restrict__ rep,
                                       const int32_t* __restrict__ mem, int need_poly, int* bad) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -288,6 +289,7 @@ __global__ void validate_pairs_kernel(ClipsDev cr, ClipsDev cm, int64_t n_pairs,
     return;
   }
   if (need_poly && (cr.npoly[a] < 0 || cm.npoly[b] < 0)) atomicOr(bad, 2);
+  else if (need_poly == 2 && (cr.cstat[a] < 0 || cm.cstat[b] < 0)) atomicOr(bad, 4);
 }
 
 hipError_t launch_pack(const int64_t* rect_ptr, const int32_t* rects, const ClipsDev& cs, int64_t n,

@@ -173,8 +173,11 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
   const int64_t a = block0 + (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
   const int ia = pa.order[a];
-  const int Pa = cs.npoly[ia];
+  const bool topo = pa.soa_hash != nullptr;
+  // over contours, a clip without contour data matches nothing
+  const int Pa = (topo && cs.cstat[ia] < 0) ? -1 : cs.npoly[ia];
   const int16_t* ba = cs.boxes + (int64_t)ia * MAX_POLY * 4;
+  const uint32_t* ha = topo ? cs.chash + (int64_t)ia * MAX_POLY : nullptr;
   const int64_t end = pa.hi[a];
   const int tol = (int)(2 * thr.p);
   unsigned long long* m = mask + (range_off[a] >> 6);
@@ -199,11 +202,13 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
           for (int p = 0; p < PX && pass; ++p) {
             const uint32_t x = side == 0 ? wh_a(p) : wh_b(p);
             const int wx = (int)(x & 0xffffu), hx = (int)(x >> 16);
+            const uint32_t tx = !topo ? 0u : (side == 0 ? ha[p] : pa.soa_hash[(int64_t)p * pa.soa_n + b]);
             bool hit = false;
             for (int qq = 0; qq < PY && !hit; ++qq) {
               const uint32_t y = side == 0 ? wh_b(qq) : wh_a(qq);
               const int wy = (int)(y & 0xffffu), hy = (int)(y >> 16);
               hit = abs(wx - wy) <= tol && abs(hx - hy) <= tol;
+              if (hit && topo) hit = tx == (side == 0 ? pa.soa_hash[(int64_t)qq * pa.soa_n + b] : ha[qq]);
             }
             if (!hit) pass = false;
           }
@@ -235,28 +240,33 @@ hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshol
 // Transposed polygon box sizes and counts of the clips in `order`: polygon q of
 // the clip at position p at [q * n + p] (threads take positions fastest).
 __global__ void edge_soa_kernel(ClipsDev cs, const int32_t* __restrict__ order, int64_t n,
-                                uint32_t* __restrict__ soa_wh, int32_t* __restrict__ soa_np) {
+                                uint32_t* __restrict__ soa_wh, int32_t* __restrict__ soa_np,
+                                uint32_t* __restrict__ soa_hash) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)MAX_POLY * n) return;
   const int q = (int)(t / n);
   const int64_t p = t - (int64_t)q * n;
   const int i = order[p];
-  const int np = cs.npoly[i];
-  uint32_t v = 0;
+  // over contours (soa_hash given) a clip without contour data matches nothing
+  const int np = (soa_hash && cs.cstat[i] < 0) ? -1 : cs.npoly[i];
+  uint32_t v = 0, h = 0;
   if (q < np) {
     const int16_t* bx = cs.boxes + ((int64_t)i * MAX_POLY + q) * 4;
     v = (uint32_t)(uint16_t)(bx[1] - bx[0]) | ((uint32_t)(uint16_t)(bx[3] - bx[2]) << 16);
+    if (soa_hash) h = cs.chash[(int64_t)i * MAX_POLY + q];
   }
   soa_wh[t] = v;
+  if (soa_hash) soa_hash[t] = h;
   if (q == 0) soa_np[p] = np;
 }
 
 hipError_t launch_edge_soa(const ClipsDev& cs, const int32_t* order, int64_t n, uint32_t* soa_wh, int32_t* soa_np,
-                           hipStream_t s) {
+                           hipStream_t s, uint32_t* soa_hash) {
   if (n == 0) return hipSuccess;
+  if (soa_hash && !cs.cstat) return hipErrorInvalidValue;  // hashes need the contour tables
   const int64_t total = (int64_t)MAX_POLY * n;
   hipLaunchKernelGGL(edge_soa_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, cs, order, n, soa_wh,
-                     soa_np);
+                     soa_np, soa_hash);
   return hipGetLastError();
 }
 
