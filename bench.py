@@ -78,6 +78,7 @@ def main():
     ap.add_argument("--no-xysep", action="store_true", help="skip the XY-separation alignment")
     ap.add_argument("--no-mixed-sizes", action="store_true", help="skip the mixed-size workload")
     ap.add_argument("--no-schedule-study", action="store_true", help="skip the relaxation-schedule study")
+    ap.add_argument("--no-contour", action="store_true", help="skip the edge track over full boundary edges")
     ap.add_argument("--mixed-sizes-only", action="store_true",
                     help="only run the mixed-size workload (profiling) and print its object")
     ap.add_argument("--serve-library", type=int, default=100_000)
@@ -116,9 +117,9 @@ def main():
     P = ca.P
     import ctypes as C
 
-    def make_clips(fp32=False):
+    def make_clips(fp32=False, contours=False):
         h = P()
-        flags = ca.CA_CLIPS_DEVICE_PTRS | (ca.CA_CLIPS_FP32 if fp32 else 0)
+        flags = ca.CA_CLIPS_DEVICE_PTRS | (ca.CA_CLIPS_FP32 if fp32 else 0) | (ca.CA_CLIPS_CONTOURS if contours else 0)
         ctx._check(lib.ca_clips_create(ctx.h, ctx._stream(), cs.n, d_ptr.data_ptr(), d_rects.data_ptr(),
                                        d_n.data_ptr(), d_w.data_ptr(), flags, C.byref(h)))
         return ca.ClipSet(ctx, h, cs.n)
@@ -263,6 +264,9 @@ def main():
     stage_ms = {k: round(v * 1000.0 / args.steps, 2) for k, v in stage_t.items()}
 
     graph = graph_bench(ctx, h, rep, mem)
+    contour_obj = None
+    if not args.no_contour and not args.no_edge:
+        contour_obj = contour_bench(ctx, make_clips, timed, stage_t, args.steps)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cs, rep.cpu().numpy(), mem.cpu().numpy(), args.cpu_seconds)
@@ -292,6 +296,7 @@ def main():
         "exact_objective": xcorr,
         "xy_separation": xysep,
         "edge": edge,
+        "edge_contour": contour_obj,
         "mixed_sizes": mixed_sizes,
         "schedule_study": schedules,
         "stage_ms": stage_ms,
@@ -300,6 +305,66 @@ def main():
         "graph": graph,
     }
     print(json.dumps(line))
+
+
+def contour_bench(ctx, make_clips, timed, stage_t, steps, t_edge=3, reps=3):
+    """Edge track over full boundary edges on the step's clips: contour
+    tracing (clip set with CA_CLIPS_CONTOURS against one without), candidate
+    generation with the topological-hash test against box sizes alone, and
+    the alignment of the surviving pairs, set against the box track's cover."""
+    import time
+
+    import torch
+
+    def dirs(b):
+        return int((b & 1).sum().item() + ((b >> 1) & 1).sum().item())
+
+    t_plain, t_cont = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        h0 = make_clips()
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t)
+        h0.close()
+        t = time.perf_counter()
+        hc = make_clips(contours=True)
+        torch.cuda.synchronize()
+        t_cont.append(time.perf_counter() - t)
+        if _ < reps - 1:
+            hc.close()
+    rep_b, mem_b = ctx.prune(hc, "edge", t_edge)
+    ob = ctx.align_pairs(hc, rep_b, mem_b, "edge", t_edge)
+    # the first call runs the bounds pass (later calls with the same
+    # constraint reuse its survivor mask)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rep_c, mem_c = ctx.prune(hc, "contour", t_edge)
+    torch.cuda.synchronize()
+    prune_s = time.perf_counter() - t
+    ctx.align_pairs(hc, rep_c, mem_c, "contour", t_edge)  # warm
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        oc = ctx.align_pairs(hc, rep_c, mem_c, "contour", t_edge)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    al_s = min(ts)
+    # the box track on the same (hash-filtered) pairs, for the overlap of the covers
+    ob2 = ctx.align_pairs(hc, rep_c, mem_c, "edge", t_edge)
+    n_c = rep_c.numel()
+    out = {"t_edge_px": t_edge, "clips": int(hc.n),
+           "trace_ms": round((min(t_cont) - min(t_plain)) * 1e3, 2),
+           "clip_set_ms_without_contours": round(min(t_plain) * 1e3, 2),
+           "prune_ms": round(prune_s * 1e3, 2), "pairs": int(n_c), "pairs_box_sizes_only": int(rep_b.numel()),
+           "align_ms": round(al_s * 1e3, 2), "pairs_per_s": round(n_c / al_s, 1) if al_s > 0 else None,
+           "covering_directions": dirs(oc["bits"]), "covering_directions_box_track": dirs(ob["bits"]),
+           "covering_both": dirs(oc["bits"] & ob2["bits"]),
+           "no_edge_correspondence_directions": int(((oc["flags"] & (1 << 3)) != 0).sum().item() +
+                                                    ((oc["flags"] & (1 << 4)) != 0).sum().item())}
+    hc.close()
+    return out
 
 
 def mixed_sizes_bench(ctx):
