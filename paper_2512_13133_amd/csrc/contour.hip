@@ -104,8 +104,10 @@ template <int NMAX>
 struct TraceLds {
   static constexpr int CWM = NMAX / 64 + 1;
   uint64_t bits[NMAX * NMAX / 64];
-  uint64_t vtx[(NMAX + 1) * CWM];
+  uint64_t vtx[(NMAX + 1) * CWM];     // vertex rows: bit X of row Y
+  uint64_t vcol[(NMAX + 1) * CWM];    // the same bits by column: bit Y of column X
   uint64_t vis[2][(NMAX + 1) * CWM];  // passages leaving E or S / W or N
+  uint64_t busy[(NMAX + 64) / 64];    // corner rows holding a vertex
   uint16_t edge[MAX_EDGES];           // coordinate | direction << 9, in walk order
   uint16_t c_start[MAX_CONTOURS], c_len[MAX_CONTOURS], c_rot[MAX_CONTOURS];
   uint8_t c_label[MAX_CONTOURS];
@@ -119,13 +121,31 @@ __device__ void trace_clip(const ClipsDev& cs, int64_t i, TraceLds<NMAX>& L) {
   const uint64_t* gbits = cs.bits + cs.bits_off[i];
   for (int t = lane; t < N * WPR; t += 64) L.bits[t] = gbits[t];
   __syncthreads();
-  for (int Y = lane; Y <= N; Y += 64) {
-    vertex_row<N>(Y >= 1 ? L.bits + (Y - 1) * WPR : nullptr, Y < N ? L.bits + Y * WPR : nullptr, L.vtx + Y * CW,
-                  nullptr);
+  for (int Y0 = 0; Y0 <= N; Y0 += 64) {
+    const int Y = Y0 + lane;
+    uint64_t any = 0ull;
+    if (Y <= N) {
+      vertex_row<N>(Y >= 1 ? L.bits + (Y - 1) * WPR : nullptr, Y < N ? L.bits + Y * WPR : nullptr, L.vtx + Y * CW,
+                    nullptr);
 #pragma unroll
-    for (int w = 0; w < CW; ++w) {
-      L.vis[0][Y * CW + w] = 0ull;
-      L.vis[1][Y * CW + w] = 0ull;
+      for (int w = 0; w < CW; ++w) {
+        any |= L.vtx[Y * CW + w];
+        L.vis[0][Y * CW + w] = 0ull;
+        L.vis[1][Y * CW + w] = 0ull;
+      }
+    }
+    const unsigned long long rows = __ballot(any != 0ull);
+    if (lane == 0) L.busy[Y0 >> 6] = rows;
+  }
+  __syncthreads();
+  // column bitmaps, one column per lane at a time
+  for (int X = lane; X <= N; X += 64) {
+#pragma unroll
+    for (int wy = 0; wy < CW; ++wy) {
+      uint64_t col = 0ull;
+      const int y1 = min(N, 64 * wy + 63);
+      for (int Y = 64 * wy; Y <= y1; ++Y) col |= ((L.vtx[Y * CW + (X >> 6)] >> (X & 63)) & 1ull) << (Y & 63);
+      L.vcol[X * CW + wy] = col;
     }
   }
   __syncthreads();
@@ -137,7 +157,22 @@ __device__ void trace_clip(const ClipsDev& cs, int64_t i, TraceLds<NMAX>& L) {
       if (y < 0 || y >= N || x < 0 || x >= N) return 0;
       return (int)((L.bits[y * WPR + (x >> 6)] >> (x & 63)) & 1ull);
     };
-    auto vbit = [&](int y, int x) -> bool { return (L.vtx[y * CW + (x >> 6)] >> (x & 63)) & 1ull; };
+    // next set bit above `from` (or below it, down = true) in a bitmap of CW
+    // words; -1 when none
+    auto next_bit = [&](const uint64_t* words, int from, bool down) -> int {
+      if (!down) {
+        int t = from + 1, w = t >> 6;
+        if (w >= CW) return -1;
+        uint64_t m = words[w] & (~0ull << (t & 63));
+        while (!m && ++w < CW) m = words[w];
+        return m ? w * 64 + __builtin_ctzll(m) : -1;
+      }
+      int t = from - 1, w = t >> 6;
+      if (t < 0) return -1;
+      uint64_t m = words[w] & (~0ull >> (63 - (t & 63)));
+      while (!m && --w >= 0) m = words[w];
+      return m ? w * 64 + 63 - __builtin_clzll(m) : -1;
+    };
     auto visited = [&](int y, int x, int d) -> bool {
       return (L.vis[d == DIR_E || d == DIR_S ? 0 : 1][y * CW + (x >> 6)] >> (x & 63)) & 1ull;
     };
@@ -146,6 +181,7 @@ __device__ void trace_clip(const ClipsDev& cs, int64_t i, TraceLds<NMAX>& L) {
     };
     int ne = 0, nc = 0, bad = 0;
     for (int Y0 = 0; Y0 <= N && !bad; ++Y0) {
+      if (!((L.busy[Y0 >> 6] >> (Y0 & 63)) & 1ull)) continue;
       for (int w0 = 0; w0 < CW && !bad; ++w0) {
         uint64_t row = L.vtx[Y0 * CW + w0];
         while (row && !bad) {
@@ -166,23 +202,8 @@ __device__ void trace_clip(const ClipsDev& cs, int64_t i, TraceLds<NMAX>& L) {
               mark(Y, X, d);
               L.edge[ne++] = (uint16_t)(((d == DIR_E || d == DIR_W) ? Y : X) | (d << 9));
               // along d to the next vertex (one exists: the contour closes)
-              if (d == DIR_E) {
-                int x = X + 1;
-                while (x <= N && !vbit(Y, x)) ++x;
-                X = x;
-              } else if (d == DIR_W) {
-                int x = X - 1;
-                while (x >= 0 && !vbit(Y, x)) --x;
-                X = x;
-              } else if (d == DIR_S) {
-                int y = Y + 1;
-                while (y <= N && !vbit(y, X)) ++y;
-                Y = y;
-              } else {
-                int y = Y - 1;
-                while (y >= 0 && !vbit(y, X)) --y;
-                Y = y;
-              }
+              if (d == DIR_E || d == DIR_W) X = next_bit(L.vtx + Y * CW, X, d == DIR_W);
+              else Y = next_bit(L.vcol + X * CW, Y, d == DIR_N);
               if (X < 0 || X > N || Y < 0 || Y > N) { bad = 1; break; }
               const int a2 = pix(Y - 1, X - 1), b2 = pix(Y - 1, X), c2 = pix(Y, X - 1), d2 = pix(Y, X);
               if ((a2 && d2 && !b2 && !c2) || (b2 && c2 && !a2 && !d2)) d = (d + 1) & 3;
