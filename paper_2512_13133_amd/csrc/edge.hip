@@ -306,17 +306,40 @@ __device__ unsigned long long relation_runs(const uint16_t* rp_m, const uint32_t
                                             const uint32_t* ru_r, int N, int dy, int dx, int lane) {
   const int y0 = max(0, -dy), y1 = min(N, N - dy);
   unsigned long long rel = 0ull;
-  for (int y = y0 + lane; y < y1; y += 64) {
-    const int ym = y + dy;
-    int a = rp_r[y], ae = rp_r[y + 1];
-    int b = rp_m[ym], be = rp_m[ym + 1];
-    while (a < ae && b < be) {
-      const uint32_t ra = ru_r[a], rb = ru_m[b];
-      const int a0 = ra & 511, a1 = (ra >> 9) & 511, qa = (ra >> 18) & 63;
-      const int b0 = (int)(rb & 511) - dx, b1 = (int)((rb >> 9) & 511) - dx, pb = (rb >> 18) & 63;
-      if (max(a0, b0) < min(a1, b1)) rel |= 1ull << (8 * pb + qa);
-      if (a1 < b1) ++a;
-      else ++b;
+  // two rows of the lane at a time: their row pointers, then their first
+  // runs, are loaded together, so a row costs no round trip of its own unless
+  // it holds more than one run on a side
+  for (int yb = y0 + lane; yb < y1; yb += 128) {
+    int a[2], ae[2], b[2], be[2];
+    uint32_t ra[2], rb[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int y = yb + 64 * k;
+      const bool in = y < y1;
+      a[k] = in ? rp_r[y] : 0;
+      ae[k] = in ? rp_r[y + 1] : 0;
+      b[k] = in ? rp_m[y + dy] : 0;
+      be[k] = in ? rp_m[y + dy + 1] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      ra[k] = a[k] < ae[k] ? ru_r[a[k]] : 0u;
+      rb[k] = b[k] < be[k] ? ru_m[b[k]] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      int ia = a[k], ib = b[k];
+      uint32_t va = ra[k], vb = rb[k];
+      while (ia < ae[k] && ib < be[k]) {
+        const int a0 = va & 511, a1 = (va >> 9) & 511, qa = (va >> 18) & 63;
+        const int b0 = (int)(vb & 511) - dx, b1 = (int)((vb >> 9) & 511) - dx, pb = (vb >> 18) & 63;
+        if (max(a0, b0) < min(a1, b1)) rel |= 1ull << (8 * pb + qa);
+        if (a1 < b1) {
+          if (++ia < ae[k]) va = ru_r[ia];
+        } else {
+          if (++ib < be[k]) vb = ru_m[ib];
+        }
+      }
     }
   }
   return wave_or64(rel);
