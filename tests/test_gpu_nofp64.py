@@ -92,12 +92,13 @@ def test_no_fp64_refusals(ctx):
 def test_zz_scale_store_two_million_clips(ctx):
     """The scale workload at full size: 2,000,000 clips of 128 x 128 from
     20,000 templates with union densities uniform in 0.1-0.6, window +-16,
-    resident on one GPU without FP64 spectra.  Sampled pairs (a same-template
-    partner and a uniform partner for each of 400 clips) through the mixed
-    cosine path and the edge track equal the oracle."""
+    resident on one GPU without FP64 spectra, with polygon contours.  Sampled
+    pairs (a same-template partner and a uniform partner for each of 400
+    clips) through the mixed cosine path, the edge track and the edge track
+    over full boundary edges equal the oracle."""
     cs = clipgen.dense()
     say(f"[scale] clips={cs.n} rects={cs.rects.shape[0]}")
-    h = ctx.clips(cs, fp64=False)
+    h = ctx.clips(cs, fp64=False, contours=True)
     rng = np.random.default_rng(44)
     order = np.argsort(cs.template, kind="stable")
     tsorted = cs.template[order]
@@ -117,6 +118,7 @@ def test_zz_scale_store_two_million_clips(ctx):
     got_c = to_np(ctx.align_pairs(h, rep, mem, "cosine", (19, 20), "mixed"))
     st = ctx.stats()
     got_e = to_np(ctx.align_pairs(h, rep, mem, "edge", 2))
+    got_t = to_np(ctx.align_pairs(h, rep, mem, "contour", 2))
     # the oracle on the clips involved, pairs renumbered into that subset
     ids, inv = np.unique(np.concatenate([rep, mem]), return_inverse=True)
     sub = cs.subset(ids)
@@ -125,8 +127,12 @@ def test_zz_scale_store_two_million_clips(ctx):
     check_cosine(got_c, ref_c, rep, mem, "scale/cosine")
     ref_e = cover.align_pairs_edge(sub, srep, smem, 2, workers=WORKERS)
     check_edge(got_e, ref_e, rep, mem, "scale/edge")
+    ref_t = cover.align_pairs_contour(sub, srep, smem, 2, workers=WORKERS)
+    check_edge(got_t, ref_t, rep, mem, "scale/contour")
+    n_edges = [ctx.contours(h, int(i))["n_edges"] for i in ids[:200]]
     say(f"[scale] pairs={rep.size} cosine bits={int((got_c['bits'] > 0).sum())} edge bits={int((got_e['bits'] > 0).sum())} "
-        f"re-decided {st['pairs_rescored']}")
+        f"contour bits={int((got_t['bits'] > 0).sum())} (differing contours {int(((ref_t['E'] < 0) & ~ref_t['topo']).sum())} "
+        f"directions), edges per clip {min(n_edges)}-{max(n_edges)}, re-decided {st['pairs_rescored']}")
     # jittered copies of one template align far better than unrelated clips
     best = got_c["score"].max(axis=1)
     say(f"[scale] mean best cosine: same template {best[kind == 0].mean():.3f}, uniform {best[kind == 1].mean():.3f}")
