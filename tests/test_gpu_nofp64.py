@@ -138,3 +138,37 @@ def test_zz_scale_store_two_million_clips(ctx):
     say(f"[scale] mean best cosine: same template {best[kind == 0].mean():.3f}, uniform {best[kind == 1].mean():.3f}")
     assert best[kind == 0].mean() > best[kind == 1].mean() + 0.1
     h.close()
+
+
+def test_zz_scale_clusters_two_million_clips(ctx):
+    """The method end to end at full scale: cosine 19/20, K = 3 on the
+    2,000,000-clip workload.  The clusters are too many for the oracle's loop,
+    so their validity is checked instead: the library verifies every member at
+    its center on the device (any violation is an error), the assignment is a
+    partition onto representatives, and the oracle re-checks 300 sampled
+    members at their centers against their representatives."""
+    cs = clipgen.dense()
+    h = ctx.clips(cs, fp64=False)
+    ctx.reset_stats()
+    g = ctx.cluster(h, "cosine", (19, 20), iterations=3, path="mixed")
+    st = ctx.stats()
+    rep_of = g["rep_of"]
+    reps = rep_of == np.arange(cs.n)
+    assert (rep_of[rep_of] == rep_of).all() and g["n_clusters"] == int(reps.sum())
+    assert st["center_violations"] == 0 and st["members_verified"] == int((~reps).sum())
+    members = np.flatnonzero(~reps)
+    pick = np.random.default_rng(1).choice(members, size=min(300, members.size), replace=False)
+    ids = np.unique(np.concatenate([pick, rep_of[pick]]))
+    sub = cs.subset(ids)
+    pos = {int(c): k for k, c in enumerate(ids.tolist())}
+    sub_rep = np.arange(sub.n, dtype=np.int32)
+    sub_shift = np.zeros((sub.n, 2), np.int16)
+    for m in pick.tolist():
+        sub_rep[pos[m]] = pos[int(rep_of[m])]
+        sub_shift[pos[m]] = g["center_shift"][m]
+    bad = cover.verify_centers(sub, sub_rep, sub_shift, "cosine", (19, 20))
+    say(f"[scale] clusters K=3: {g['n_clusters']} of {cs.n} clips, {members.size} members verified on the device, "
+        f"{st['pairs_survived']} candidates of {st['pairs_screened']} at the loosest threshold; "
+        f"oracle re-check of {pick.size} members: {len(bad)} violations")
+    assert not bad
+    h.close()
