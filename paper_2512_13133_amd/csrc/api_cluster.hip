@@ -2,6 +2,7 @@
 // surprisal lazy-greedy set cover (paper Sec. 3.3, Eqs. 7-9) inside the
 // coarse-to-fine closed loop (Sec. 3.1), on the host over the device results.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <queue>
@@ -100,33 +101,84 @@ void build_ranges(const ca_clipset* cs, const ca_constraint* con, std::vector<in
 // constraint); its bitmask and counts are cached on the context, so sizing and
 // writing calls share it.  Edge ranges start on 64-bit words (the edge pass
 // stores whole chunk words); edge pairs are written as (smaller, larger) id.
+// Candidate mask held at once by the bounds pass, in bytes: larger clip sets
+// run the pass over chunks of consecutive anchors (CLIPALIGN_PRUNE_CHUNK_BYTES
+// overrides the 8 GiB default).
+static int64_t prune_chunk_bytes() {
+  if (const char* e = std::getenv("CLIPALIGN_PRUNE_CHUNK_BYTES")) {
+    const long long v = std::atoll(e);
+    if (v >= 8) return v;
+  }
+  return 8ll << 30;
+}
+
 static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
                                      int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
   const bool edge = con->kind == CA_EDGE;
+  const bool topo = over_contours(con);  // polygon hashes as a third table
+  const Threshold thr{con->thr_num, con->thr_den};
   PruneCache* pc = prune_cache_of(ctx);
   const bool hit = pc->gen == gen_of(cs) && pc->kind == con_key(con) && pc->p == con->thr_num && pc->q == con->thr_den;
   // a hit (the writing call after a sizing call) reuses the device copies of
-  // the anchor order, ranges and bitmask
+  // the anchor order, ranges, partner tables and (one chunk) bitmask
   int64_t na = pc->na;
-  char* base;
+  // layout: order | hi | range_off | counts | offsets | mask (largest chunk) | partner tables
+  auto b_ord_of = [](int64_t n) { return aup(4 * (size_t)n); };
+  auto b_rng_of = [](int64_t n) { return aup(8 * (size_t)n); };
+  auto b_soa_of = [](int64_t n) { return aup(4 * 64 * (size_t)n); };
+  // the bounds pass over anchors [cuts[c], cuts[c + 1]), mask bits from cut_bit0[c]
+  auto bounds_chunk = [&](char* base, size_t b_mask, int c) -> ca_status {
+    const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na), b_soa = b_soa_of(na);
+    PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), pc->cuts[c + 1], (int64_t*)(base + 2 * b_ord + b_rng),
+                 nullptr, nullptr, nullptr};
+    pa.a_begin = pc->cuts[c];
+    pa.mask_bit0 = pc->cut_bit0[c];
+    pa.soa_n = na;
+    const int64_t* d_roff = (const int64_t*)(base + 2 * b_ord);
+    char* tables = base + 2 * b_ord + 3 * b_rng + b_mask;
+    uint32_t* d_mask = (uint32_t*)(base + 2 * b_ord + 3 * b_rng);
+    if (edge) {
+      pa.soa_wh = (const uint32_t*)tables;
+      pa.soa_np = (const int32_t*)(tables + b_soa);
+      pa.soa_hash = topo ? (const uint32_t*)(tables + 2 * b_soa) : nullptr;
+      HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, thr, d_roff, (unsigned long long*)d_mask, s));
+    } else {
+      HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
+      pa.soa_row = (const uint32_t*)tables;
+      pa.soa_col = (const uint32_t*)(tables + b_soa);
+      HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, thr, d_roff, d_mask, false, s));
+    }
+    return CA_OK;
+  };
   if (!hit) {
     std::vector<int32_t> order, hi;
     int64_t screened = 0;
     build_ranges(cs, con, order, hi, screened);
     na = (int64_t)order.size();
-    std::vector<int64_t> range_off(na);
+    std::vector<int64_t> range_off(na + 1);
     int64_t bits = 0;
     for (int64_t a = 0; a < na; ++a) {
       range_off[a] = bits;
       const int64_t len = hi[a] - a - 1;
       bits += edge ? (len + 63) / 64 * 64 : len;
     }
-    const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na);
-    const size_t b_mask = aup(8 * (size_t)(bits / 64 + 1));
-    // transposed sliding sums (rows, columns), or box sizes and polygon counts for the edge track
-    const size_t b_soa = aup(4 * 64 * (size_t)na);
-    const bool topo = over_contours(con);  // polygon hashes as a third table
-    const size_t need = 2 * b_ord + 2 * b_rng + b_mask + (topo ? 3 : 2) * b_soa;
+    range_off[na] = bits;
+    // anchor chunks whose mask fits the budget (at least one anchor each);
+    // cosine chunks start on a 32-bit mask word, edge ranges on a 64-bit one
+    const int64_t cbits = prune_chunk_bytes() * 8;
+    std::vector<int64_t> cuts{0};
+    for (int64_t a = 1; a < na; ++a)
+      if (range_off[a + 1] - (range_off[cuts.back()] & ~(int64_t)63) > cbits) cuts.push_back(a);
+    cuts.push_back(na);
+    std::vector<int64_t> bit0(cuts.size() - 1);
+    int64_t max_bits = 0;
+    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+      bit0[c] = range_off[cuts[c]] & ~(int64_t)63;
+      max_bits = std::max(max_bits, range_off[cuts[c + 1]] - bit0[c]);
+    }
+    const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na), b_soa = b_soa_of(na);
+    const size_t b_mask = aup(8 * (size_t)(max_bits / 64 + 1));
+    const size_t need = 2 * b_ord + 3 * b_rng + b_mask + (topo ? 3 : 2) * b_soa;
     if (pc->bytes < need) {
       free_ctx(ctx, pc->dev, pc->bytes);
       pc->dev = nullptr;
@@ -136,39 +188,27 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
       if (st) return st;
       pc->bytes = need;
     }
-    base = (char*)pc->dev;
+    char* base = (char*)pc->dev;
     int32_t* d_order = (int32_t*)base;
-    int32_t* d_hi = (int32_t*)(base + b_ord);
-    int64_t* d_roff = (int64_t*)(base + 2 * b_ord);
-    int64_t* d_cnt = (int64_t*)(base + 2 * b_ord + b_rng);
-    uint32_t* d_mask = (uint32_t*)(base + 2 * b_ord + 2 * b_rng);
     HIP_TRY(ctx, hipMemcpyAsync(d_order, order.data(), 4 * na, hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, hipMemcpyAsync(d_hi, hi.data(), 4 * na, hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, hipMemcpyAsync(d_roff, range_off.data(), 8 * na, hipMemcpyHostToDevice, s));
-    PruneArgs pa{d_order, d_hi, na, d_cnt, nullptr, nullptr, nullptr};
-    if (edge) {
-      uint32_t* d_wh = (uint32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask);
-      int32_t* d_np = (int32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask + b_soa);
-      uint32_t* d_hash = topo ? (uint32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask + 2 * b_soa) : nullptr;
-      HIP_TRY(ctx, launch_edge_soa(dev_of(cs), d_order, na, d_wh, d_np, s, d_hash));
-      pa.soa_wh = d_wh;
-      pa.soa_np = d_np;
-      pa.soa_hash = d_hash;
-      pa.soa_n = na;
-      HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff,
-                                     (unsigned long long*)d_mask, s));
-    } else {
-      HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
-      uint32_t* d_soa = (uint32_t*)(base + 2 * b_ord + 2 * b_rng + b_mask);
-      HIP_TRY(ctx, launch_prune128_soa(dev_of(cs), d_order, na, d_soa, d_soa + b_soa / 4, s));
-      pa.soa_row = d_soa;
-      pa.soa_col = d_soa + b_soa / 4;
-      pa.soa_n = na;
-      HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, Threshold{con->thr_num, con->thr_den}, d_roff, d_mask,
-                                   false, s));
+    HIP_TRY(ctx, hipMemcpyAsync(base + b_ord, hi.data(), 4 * na, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipMemcpyAsync(base + 2 * b_ord, range_off.data(), 8 * na, hipMemcpyHostToDevice, s));
+    char* tables = base + 2 * b_ord + 3 * b_rng + b_mask;
+    if (edge)
+      HIP_TRY(ctx, launch_edge_soa(dev_of(cs), d_order, na, (uint32_t*)tables, (int32_t*)(tables + b_soa), s,
+                                   topo ? (uint32_t*)(tables + 2 * b_soa) : nullptr));
+    else
+      HIP_TRY(ctx, launch_prune128_soa(dev_of(cs), d_order, na, (uint32_t*)tables, (uint32_t*)(tables + b_soa), s));
+    pc->na = na;
+    pc->cuts = cuts;
+    pc->cut_bit0 = bit0;
+    pc->gen = 0;  // valid only once the counts are in
+    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+      ca_status st = bounds_chunk(base, b_mask, (int)c);
+      if (st) return st;
     }
     pc->counts.assign(na, 0);
-    HIP_TRY(ctx, hipMemcpyAsync(pc->counts.data(), d_cnt, 8 * na, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(pc->counts.data(), base + 2 * b_ord + b_rng, 8 * na, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     pc->total = 0;
     for (int64_t a = 0; a < na; ++a) pc->total += pc->counts[a];
@@ -176,13 +216,12 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     pc->kind = con_key(con);
     pc->p = con->thr_num;
     pc->q = con->thr_den;
-    pc->na = na;
     pc->b_mask = b_mask;
     stats_of(ctx)->pairs_screened += screened;
     stats_of(ctx)->pairs_survived += pc->total;
   }
-  const size_t b_ord = aup(4 * (size_t)na), b_rng = aup(8 * (size_t)na);
-  base = (char*)pc->dev;
+  const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na);
+  char* base = (char*)pc->dev;
   *n_out = pc->total;
   if (!rep) return CA_OK;
   if (pc->total > cap) return fail_ctx(ctx, CA_ETRUNC, "candidate buffer too small");
@@ -192,12 +231,23 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     off[a] = acc;
     acc += pc->counts[a];
   }
-  int64_t* d_off = (int64_t*)(base + 2 * b_ord + b_rng);  // reuses the count slots
+  int64_t* d_off = (int64_t*)(base + 2 * b_ord + 2 * b_rng);
   HIP_TRY(ctx, hipMemcpyAsync(d_off, off.data(), 8 * na, hipMemcpyHostToDevice, s));
-  PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), na, nullptr, d_off, rep, mem};
-  pa.order_ids = edge ? 1 : 0;
-  HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, Threshold{con->thr_num, con->thr_den},
-                               (int64_t*)(base + 2 * b_ord), (uint32_t*)(base + 2 * b_ord + 2 * b_rng), true, s));
+  const int n_chunks = (int)pc->cuts.size() - 1;
+  for (int c = 0; c < n_chunks; ++c) {
+    // one chunk: its mask is still in place from the counting pass; more: each
+    // chunk's mask is rebuilt before its pairs are written
+    if (n_chunks > 1) {
+      ca_status st = bounds_chunk(base, pc->b_mask, c);
+      if (st) return st;
+    }
+    PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), pc->cuts[c + 1], nullptr, d_off, rep, mem};
+    pa.a_begin = pc->cuts[c];
+    pa.mask_bit0 = pc->cut_bit0[c];
+    pa.order_ids = edge ? 1 : 0;
+    HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, thr, (int64_t*)(base + 2 * b_ord),
+                                 (uint32_t*)(base + 2 * b_ord + 3 * b_rng), true, s));
+  }
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return CA_OK;
 }

@@ -24,9 +24,11 @@ struct PruneCache {
   int64_t kind = 0, p = 0, q = 0;
   int64_t na = 0, total = 0;
   size_t b_mask = 0;             // bytes of the survivor bitmask
-  void* dev = nullptr;           // order | hi | range_off | counts/offsets | mask
+  void* dev = nullptr;           // order | hi | range_off | counts | offsets | mask | partner tables
   size_t bytes = 0;
   std::vector<int64_t> counts;
+  std::vector<int64_t> cuts;     // anchor chunks of the bounds pass: [cuts[c], cuts[c + 1])
+  std::vector<int64_t> cut_bit0; // first mask bit of each chunk (64-bit aligned)
 };
 
 // The last cover relation built by ca_cover / ca_cluster (CSR sorted by

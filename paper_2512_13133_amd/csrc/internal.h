@@ -130,6 +130,10 @@ struct PruneArgs {
   const int32_t* anchor_ids = nullptr;  // [n_anchor] anchor clip ids (null: order[a])
   const int32_t* lo = nullptr;          // [n_anchor] start of each range in `order` (null: a + 1)
   int order_ids = 0;                    // write each pair as (smaller id, larger id)
+  // a launch over anchors [a_begin, n_anchor) whose mask buffer starts at bit
+  // mask_bit0 of the range offsets (the bounds pass in anchor chunks)
+  int64_t a_begin = 0;
+  int64_t mask_bit0 = 0;
   // partner sliding sums transposed (packed row pair q of the partner at
   // position b of `order` at [q * soa_n + b]), so a wave's 64 partners read
   // one contiguous run per pair; null: read each partner's own row

@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
   const uint32_t* ha = topo ? cs.chash + (int64_t)ia * MAX_POLY : nullptr;
   const int64_t end = pa.hi[a];
   const int tol = (int)(2 * thr.p);
-  unsigned long long* m = mask + (range_off[a] >> 6);
+  unsigned long long* m = mask + ((range_off[a] - pa.mask_bit0) >> 6);
   int64_t found = 0;
   // box size of polygon q: the anchor's from its own table (uniform reads), the
   // partner's from the transposed table (one contiguous run across the wave)
@@ -274,7 +274,7 @@ hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold 
                              unsigned long long* mask, hipStream_t s) {
   if (pa.n_anchor == 0) return hipSuccess;
   if (!pa.soa_wh || !pa.soa_np || pa.soa_n <= 0) return hipErrorInvalidValue;  // the kernel reads them
-  for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
+  for (int64_t b0 = pa.a_begin; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
     hipLaunchKernelGGL(edge_prune_kernel, dim3(nb), dim3(64), 0, s, cs, pa, thr, range_off, mask, b0);
     const hipError_t e = hipGetLastError();

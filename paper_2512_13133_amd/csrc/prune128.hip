@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
       return;
     }
   }
-  const int64_t roff = range_off[a];
+  const int64_t roff = range_off[a] - pa.mask_bit0;
   if (lane == 0) qlen = 0;
   __syncthreads();
   int64_t found = 0;
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const 
     len = min(len, p_first + (int64_t)pa.seg);
     if (p_first >= len) return;
   }
-  const int64_t roff = range_off[a];
+  const int64_t roff = range_off[a] - pa.mask_bit0;
   int64_t o = pa.offs[pa.seg > 0 ? a * pa.n_seg + blockIdx.y : a];
   for (int64_t p0 = p_first; p0 < len; p0 += 64) {
     const int64_t p = p0 + lane;
@@ -257,7 +257,7 @@ hipError_t launch_prune128_soa(const ClipsDev& cb, const int32_t* order, int64_t
 hipError_t launch_prune128(const ClipsDev& ca, const ClipsDev& cb, const PruneArgs& pa, Threshold thr,
                            const int64_t* range_off, uint32_t* mask, bool write, hipStream_t s) {
   if (!write && (!pa.soa_row || !pa.soa_col || pa.soa_n <= 0)) return hipErrorInvalidValue;  // bounds pass reads them
-  for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
+  for (int64_t b0 = pa.a_begin; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
     const dim3 grid(nb, pa.seg > 0 ? pa.n_seg : 1);
     if (write)

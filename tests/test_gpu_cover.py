@@ -172,3 +172,25 @@ def test_cluster_on_compacted_cover_c128_mixed(ctx, kind, thr, K):
         ref_bad = cover.verify_centers(cs, chain, got["center_shift"], kind, thr)
         assert nv == len(ref_bad) and first == ref_bad[0]
     h.close()
+
+
+@pytest.mark.parametrize("kind,thr", [("cosine", (19, 20)), ("edge", 3), ("contour", 3)])
+def test_prune_in_anchor_chunks_equals_one_pass(ctx, kind, thr, monkeypatch):
+    """A bounds pass split into anchor chunks (a 4 KiB mask budget instead of
+    the default) returns the same candidate list, in the same order, and the
+    same cover relation."""
+    cs = clipgen.c128(n_clips=2000, n_templates=40)
+    h1 = ctx.clips(cs, contours=True)
+    rep1, mem1 = (x.cpu().numpy() for x in ctx.prune(h1, kind, thr))
+    cov1 = {k: v.cpu().numpy() for k, v in ctx.cover(h1, kind, thr).items()}
+    h1.close()
+    monkeypatch.setenv("CLIPALIGN_PRUNE_CHUNK_BYTES", "4096")
+    h2 = ctx.clips(cs, contours=True)
+    rep2, mem2 = (x.cpu().numpy() for x in ctx.prune(h2, kind, thr))
+    cov2 = {k: v.cpu().numpy() for k, v in ctx.cover(h2, kind, thr).items()}
+    h2.close()
+    say(f"[prune chunks] {kind}: {rep1.size} candidates, cover entries {cov1['col'].size}")
+    assert rep1.size > 0
+    assert (rep1 == rep2).all() and (mem1 == mem2).all()
+    for k in ("row_ptr", "col", "shift", "value"):
+        assert (cov1[k] == cov2[k]).all(), k
