@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--no-mixed-sizes", action="store_true", help="skip the mixed-size workload")
     ap.add_argument("--no-schedule-study", action="store_true", help="skip the relaxation-schedule study")
     ap.add_argument("--no-contour", action="store_true", help="skip the edge track over full boundary edges")
+    ap.add_argument("--scale-clusters", action="store_true",
+                    help="only run the method end to end on the 2M-clip workload (cosine 19/20 and the edge track "
+                         "over full boundary edges at 2 px, K = 3) and print its object (several minutes)")
     ap.add_argument("--mixed-sizes-only", action="store_true",
                     help="only run the mixed-size workload (profiling) and print its object")
     ap.add_argument("--serve-library", type=int, default=100_000)
@@ -88,6 +91,9 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.scale_clusters:
+        print(json.dumps({"scale_clusters": scale_clusters()}))
         return
     if args.mixed_sizes_only:
         import paper_2512_13133_amd as ca
@@ -373,6 +379,56 @@ def contour_bench(ctx, make_clips, timed, stage_t, steps, t_edge=3, reps=3):
            "no_edge_correspondence_directions": int(((oc["flags"] & (1 << 3)) != 0).sum().item() +
                                                     ((oc["flags"] & (1 << 4)) != 0).sum().item())}
     hc.close()
+    return out
+
+
+def scale_clusters():
+    """The method end to end on the 2,000,000-clip workload (128 x 128,
+    template densities 0.1-0.6, window +-16) on one GPU: the cosine track at
+    19/20 and the edge track over full boundary edges at 2 px, K = 3 each
+    (candidates at the loosest threshold, alignment, cover, loop, and the
+    verification of every member at its center)."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    import clipgen
+    import paper_2512_13133_amd as ca
+
+    cs = clipgen.dense()
+    ctx = ca.Context(0)
+    t = time.perf_counter()
+    h = ctx.clips(cs, fp64=False, contours=True)
+    torch.cuda.synchronize()
+    out = {"workload": "dense: 2,000,000 clips 128x128, 20,000 templates, densities 0.1-0.6, window +-16",
+           "clip_set_s": round(time.perf_counter() - t, 2)}
+    log(f"[scale] clip set with contours: {out['clip_set_s']} s")
+    for kind, thr, loose in (("cosine", (19, 20), (93, 100)), ("contour", 2, 4)):
+        # the loosest threshold of the K = 3 schedule, counted first (a step of its own)
+        con = ca.constraint(kind, loose)
+        n = C.c_int64(0)
+        ctx.reset_stats()
+        t = time.perf_counter()
+        ctx._check(ctx.lib.ca_prune(ctx.h, ctx._stream(), h.handle, C.byref(con), 0, None, None, C.byref(n)))
+        torch.cuda.synchronize()
+        prune_s = time.perf_counter() - t
+        screened = ctx.stats()["pairs_screened"]
+        log(f"[scale] {kind}: {n.value} candidates of {screened} at the loosest threshold in {prune_s:.1f} s")
+        ctx.reset_stats()
+        t = time.perf_counter()
+        g = ctx.cluster(h, kind, thr, iterations=3)
+        torch.cuda.synchronize()
+        st = ctx.stats()
+        cl_s = time.perf_counter() - t
+        members = int((g["rep_of"] != np.arange(cs.n)).sum())
+        out[kind] = {"threshold": list(thr) if isinstance(thr, tuple) else thr, "K": 3,
+                     "candidates_loosest": int(n.value), "pairs_screened": int(screened),
+                     "prune_count_s": round(prune_s, 1), "cluster_s": round(cl_s, 1),
+                     "clusters": int(g["n_clusters"]), "members": members,
+                     "members_verified": int(st["members_verified"]), "center_violations": int(st["center_violations"])}
+        log(f"[scale] {kind}: {g['n_clusters']} clusters in {cl_s:.1f} s, {st['center_violations']} violations")
+    h.close()
     return out
 
 

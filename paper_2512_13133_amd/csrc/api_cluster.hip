@@ -101,14 +101,18 @@ void build_ranges(const ca_clipset* cs, const ca_constraint* con, std::vector<in
 // constraint); its bitmask and counts are cached on the context, so sizing and
 // writing calls share it.  Edge ranges start on 64-bit words (the edge pass
 // stores whole chunk words); edge pairs are written as (smaller, larger) id.
-// Candidate mask held at once by the bounds pass, in bytes: larger clip sets
-// run the pass over chunks of consecutive anchors (CLIPALIGN_PRUNE_CHUNK_BYTES
-// overrides the 8 GiB default).
+// Candidate mask held at once by the bounds pass, in bytes: a quarter of the
+// free device memory (at least 1 GiB; CLIPALIGN_PRUNE_CHUNK_BYTES overrides).
+// Larger masks run the pass over chunks of consecutive anchors, and the
+// writing call then rebuilds each chunk's mask.
 static int64_t prune_chunk_bytes() {
   if (const char* e = std::getenv("CLIPALIGN_PRUNE_CHUNK_BYTES")) {
     const long long v = std::atoll(e);
     if (v >= 8) return v;
   }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+    return std::max<int64_t>(1ll << 30, (int64_t)(free_b / 4));
   return 8ll << 30;
 }
 
