@@ -705,11 +705,14 @@ struct QueueMem {
   unsigned long long* counters;
   RescoreQueue check;  // the sample of decided pairs: q's need and r1_low, its own list and counters
   SampleSave* check_saved;
+  int32_t* sel;              // pairs a queue-free first pass leaves undecided (batched kernel)
+  unsigned long long* n_sel;
 };
 static constexpr size_t queue_bytes(int64_t n) {
   const int64_t cap_g = n / 4 + 65536, cap_s = 16 * cap_g;
   return align_up(n) + 2 * align_up(8 * (size_t)n) + 256 + 2 * align_up(sizeof(CandGroup) * (size_t)cap_g) +
-         align_up(2 * (size_t)cap_s) + align_up(8 * (size_t)CHECK_MAX) + align_up(sizeof(SampleSave) * (size_t)CHECK_MAX);
+         align_up(2 * (size_t)cap_s) + align_up(8 * (size_t)CHECK_MAX) + align_up(sizeof(SampleSave) * (size_t)CHECK_MAX) +
+         align_up(4 * (size_t)n);
 }
 static QueueMem queue_carve(char* base, int64_t n) {
   const int64_t cap_g = n / 4 + 65536, cap_s = 16 * cap_g;
@@ -740,6 +743,8 @@ static QueueMem queue_carve(char* base, int64_t n) {
   m.check.peak_err_bits = m.counters + 11;
   m.check.peak_ratio_bits = m.counters + 12;
   m.check_saved = (SampleSave*)(chk + align_up(8 * (size_t)CHECK_MAX));
+  m.sel = (int32_t*)(chk + align_up(8 * (size_t)CHECK_MAX) + align_up(sizeof(SampleSave) * (size_t)CHECK_MAX));
+  m.n_sel = m.counters + 6;
   return m;
 }
 
@@ -826,7 +831,7 @@ static hipError_t enqueue_cosine(ca_ctx* ctx, const ClipsDev& cr, const ClipsDev
     const _Float16* tab = (const _Float16*)ctx->gen_tab[maxN == 64 ? 0 : (maxN == 128 ? 1 : 2)][gen_nb];
     if (!tab) return hipErrorNotInitialized;  // made by ensure_gen_tables before any launch
     e = launch_pcm_mfma_gen(maxN, gen_nb, cr, cm, io, thr, (float)band_mixed(maxN), m.q, m.cq, tab,
-                            tab + (size_t)(maxN / 32) * gen_nb * 64 * 8, m.counters + 4, s);
+                            tab + (size_t)(maxN / 32) * gen_nb * 64 * 8, m.counters + 4, m.sel, m.n_sel, s);
   } else {
     e = launch_pcm_mfma128(cr, cm, io, thr, (float)BAND_MIXED, m.q, m.cq, ctx->mf_b1, ctx->mf_a2, nullptr,
                            m.counters + 4, s);

@@ -85,9 +85,11 @@ hipError_t launch_pcm_mfma128(const ClipsDev& cr, const ClipsDev& cm, const Pair
 int mfma_gen_blocks(int N, int half_window);
 size_t mfma_gen_table_halves(int N, int NB);
 void build_mfma_gen_tables(int N, int NB, _Float16* b1, _Float16* a2);
+// sel (n_pairs int32) and n_sel (one counter): the list of pairs a queue-free
+// first pass leaves undecided, where an instance runs two passes (null: one).
 hipError_t launch_pcm_mfma_gen(int N, int NB, const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                float band, const RescoreQueue& q, const CandQueue& cq, const void* b1, const void* a2,
-                               unsigned long long* tiles, hipStream_t s);
+                               unsigned long long* tiles, int32_t* sel, unsigned long long* n_sel, hipStream_t s);
 // FP64 re-decision of queued directions at their candidate shifts: the group
 // count is read on the device (*cq.n_groups, at most cq.cap_groups).  With
 // FP32 spectra on both sides and `exact.groups` set, a screen over the FP32

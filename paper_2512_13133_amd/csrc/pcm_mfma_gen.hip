@@ -80,17 +80,26 @@ __device__ __forceinline__ int wave_overlap_n(const uint64_t* rep, const uint64_
 
 // Waves per SIMD the register allocation is held to: two where that fits
 // without spilling (measured on the compiler's resource report), else one.
-template <int N, int NB>
+// Without the candidate queue (QUEUE false) the 64 x 64 kernel of four
+// blocks fits two waves as well.
+template <int N, int NB, bool QUEUE = true>
 constexpr int gen_min_waves() {
-  return (N == 64 && NB <= 3) || (N == 128 && NB == 3) ? 2 : 1;
+  return (N == 64 && NB <= 3) || (N == 128 && NB == 3) || (N == 64 && NB == 4 && !QUEUE) ? 2 : 1;
 }
 
-template <int N, int NB>
-__global__ void __launch_bounds__(GEN_THREADS, (gen_min_waves<N, NB>()))
+// QUEUE true: every pair (sel null), or the pairs listed in sel[0, *n_sel),
+// with the candidate queue of undecided directions.  QUEUE false: every pair,
+// results as above, and each pair with an undecided direction appended to
+// sel (count in *n_sel) for a QUEUE pass over just those pairs.
+template <int N, int NB, bool QUEUE = true>
+__global__ void __launch_bounds__(GEN_THREADS, (gen_min_waves<N, NB, QUEUE>()))
 pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, RescoreQueue q, CandQueue cq,
-                    const h8_t* b1frag, const h8_t* a2frag, unsigned long long* tiles, int64_t n_tiles) {
+                    const h8_t* b1frag, const h8_t* a2frag, unsigned long long* tiles, int64_t n_tiles,
+                    int32_t* sel, unsigned long long* n_sel) {
   using S = GenShape<N, NB>;
   constexpr int KB = S::KB, MB = S::MB, C = S::C, W = S::W;
+  // only the instance that runs two passes reads a pair list
+  constexpr bool LIST = QUEUE && gen_min_waves<N, NB, false>() > gen_min_waves<N, NB, true>();
   __shared__ h8_t s_b1[KB * NB * 64];  // stage-1 twiddles
   __shared__ h8_t s_a2[MB * NB * 64];  // stage-2 twiddles
   __shared__ int64_t s_tile;
@@ -107,26 +116,33 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
   for (int t = tid; t < KB * NB * 64; t += GEN_THREADS) s_b1[t] = b1frag[t];
   for (int t = tid; t < MB * NB * 64; t += GEN_THREADS) s_a2[t] = a2frag[t];
 
+  // over a list, its length (written by the pass before this launch) sets the tiles
+  const int64_t n_pairs = (LIST && sel) ? (int64_t)*n_sel : io.n_pairs;
+  const int64_t tiles_end = (LIST && sel) ? (n_pairs + GEN_TILE - 1) / GEN_TILE : n_tiles;
   for (;;) {
     __syncthreads();  // every wave has read the previous tile number (and the tables are in place)
     if (tid == 0) {
       const int64_t got = (int64_t)atomicAdd(tiles, 1ull);
-      s_tile = got < n_tiles ? got : -1;
+      s_tile = got < tiles_end ? got : -1;
     }
     __syncthreads();
     const int64_t tile = s_tile;
     if (tile < 0) break;
     const int64_t base = tile * GEN_TILE;
-    const int cnt = (int)min((int64_t)GEN_TILE, io.n_pairs - base);
+    const int cnt = (int)min((int64_t)GEN_TILE, n_pairs - base);
 
     // Metadata of the tile's pairs, pair base + l on lane l (read per pair
     // with readlane): member and representative ids, spectrum and bit
     // offsets, pixel counts, half-window | zero bins << 16.
     int t_i = 0, t_j = 0, t_ni = 0, t_nj = 0, t_wzi = 0, t_wzj = 0;
     int64_t t_soi = 0, t_soj = 0, t_boi = 0, t_boj = 0;
+    // the lane's pair: the tile's base + lane, or (list pass) the listed one
+    int64_t t_k = 0;
+    if constexpr (LIST) t_k = sel ? (lane < cnt ? (int64_t)sel[base + lane] : 0) : base + lane;
     if (lane < cnt) {
-      t_i = io.mem[base + lane];
-      t_j = io.rep[base + lane];
+      const int64_t kk = LIST ? t_k : base + lane;
+      t_i = io.mem[kk];
+      t_j = io.rep[kk];
       t_soi = cm.spec_off[t_i];
       t_soj = cr.spec_off[t_j];
       t_boi = cm.bits_off[t_i];
@@ -140,7 +156,7 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
     uint4 m_cur[KB + 1], r_cur[KB + 1];
     bool have0 = false;
     for (int p = wave; p < cnt; p += 4) {
-      const int64_t k = base + p;
+      const int64_t k = LIST ? readlane64(t_k, p) : base + p;
       const int n_i = __builtin_amdgcn_readlane(t_ni, p);
       const int n_j = __builtin_amdgcn_readlane(t_nj, p);
       const int wzi = __builtin_amdgcn_readlane(t_wzi, p);
@@ -423,38 +439,69 @@ pcm_mfma_gen_kernel(MfView cr, MfView cm, PairIO io, Threshold thr, float band, 
           }
         }
       };
-      if (w_i == w_j) {
-        if (!dec0) queue(2, w_i, v1f - band_k, v1f / (float)K_hi);
+      if constexpr (QUEUE) {
+        if (w_i == w_j) {
+          if (!dec0) queue(2, w_i, v1f - band_k, v1f / (float)K_hi);
+        } else {
+          if (!dec0) queue(0, w_i, v1f - band_k, v1f / (float)K_hi);
+          if (!dec1) queue(1, w_j, v1r - band_k, v1r / (float)K_hi);
+        }
       } else {
-        if (!dec0) queue(0, w_i, v1f - band_k, v1f / (float)K_hi);
-        if (!dec1) queue(1, w_j, v1r - band_k, v1r / (float)K_hi);
+        if ((!dec0 || (w_i != w_j && !dec1)) && lane == 0) sel[atomicAdd(n_sel, 1ull)] = (int32_t)k;
       }
     }
   }
 }
 
-template <int N, int NB>
-hipError_t launch_nb(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr, float band,
-                     const RescoreQueue& q, const CandQueue& cq, const void* b1, const void* a2,
-                     unsigned long long* tiles, hipStream_t s) {
-  static int resident = 0;  // workgroups resident on the device at once
+// Workgroups of one kernel instance resident on the device at once.
+template <int N, int NB, bool QUEUE>
+int resident_groups() {
+  static int resident = 0;
   if (resident == 0) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcm_mfma_gen_kernel<N, NB>, GEN_THREADS, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcm_mfma_gen_kernel<N, NB, QUEUE>, GEN_THREADS, 0) !=
             hipSuccess ||
         per <= 0)
       per = 1;
     resident = cus * per;
   }
+  return resident;
+}
+
+// Where the queue-free kernel runs more waves than the queue kernel, the call
+// runs it over every pair and then the queue kernel over the pairs it left
+// undecided (their number stays on the device); elsewhere one queue pass.
+template <int N, int NB>
+hipError_t launch_nb(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr, float band,
+                     const RescoreQueue& q, const CandQueue& cq, const void* b1, const void* a2,
+                     unsigned long long* tiles, int32_t* sel, unsigned long long* n_sel, hipStream_t s) {
   const int64_t n_tiles = (io.n_pairs + GEN_TILE - 1) / GEN_TILE;
-  const unsigned grid = (unsigned)std::min<int64_t>(n_tiles, (int64_t)resident);
   hipError_t e = launch_zero_u64(tiles, 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((pcm_mfma_gen_kernel<N, NB>), dim3(grid), dim3(GEN_THREADS), 0, s, mf_view(cr), mf_view(cm), io,
-                     thr, band, q, cq, (const h8_t*)b1, (const h8_t*)a2, tiles, n_tiles);
+  if constexpr (gen_min_waves<N, NB, false>() > gen_min_waves<N, NB, true>()) {
+    if (sel && n_sel) {
+      if ((e = launch_zero_u64(n_sel, 1, s)) != hipSuccess) return e;
+      const unsigned g1 = (unsigned)std::min<int64_t>(n_tiles, (int64_t)resident_groups<N, NB, false>());
+      hipLaunchKernelGGL((pcm_mfma_gen_kernel<N, NB, false>), dim3(g1), dim3(GEN_THREADS), 0, s, mf_view(cr),
+                         mf_view(cm), io, thr, band, q, cq, (const h8_t*)b1, (const h8_t*)a2, tiles, n_tiles, sel,
+                         n_sel);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = launch_zero_u64(tiles, 1, s)) != hipSuccess) return e;
+      // the list is at most the whole call; groups without a tile exit at once
+      const unsigned g2 = (unsigned)std::min<int64_t>(n_tiles, (int64_t)resident_groups<N, NB, true>());
+      hipLaunchKernelGGL((pcm_mfma_gen_kernel<N, NB, true>), dim3(g2), dim3(GEN_THREADS), 0, s, mf_view(cr),
+                         mf_view(cm), io, thr, band, q, cq, (const h8_t*)b1, (const h8_t*)a2, tiles, n_tiles, sel,
+                         n_sel);
+      return hipGetLastError();
+    }
+  }
+  const unsigned grid = (unsigned)std::min<int64_t>(n_tiles, (int64_t)resident_groups<N, NB, true>());
+  hipLaunchKernelGGL((pcm_mfma_gen_kernel<N, NB, true>), dim3(grid), dim3(GEN_THREADS), 0, s, mf_view(cr),
+                     mf_view(cm), io, thr, band, q, cq, (const h8_t*)b1, (const h8_t*)a2, tiles, n_tiles,
+                     (int32_t*)nullptr, (unsigned long long*)nullptr);
   return hipGetLastError();
 }
 
@@ -501,21 +548,21 @@ void build_mfma_gen_tables(int N, int NB, _Float16* b1, _Float16* a2) {
 
 hipError_t launch_pcm_mfma_gen(int N, int NB, const ClipsDev& cr, const ClipsDev& cm, const PairIO& io, Threshold thr,
                                float band, const RescoreQueue& q, const CandQueue& cq, const void* b1, const void* a2,
-                               unsigned long long* tiles, hipStream_t s) {
+                               unsigned long long* tiles, int32_t* sel, unsigned long long* n_sel, hipStream_t s) {
   if (io.n_pairs == 0) return hipSuccess;
   switch (N * 8 + NB) {
-    case 64 * 8 + 1: return launch_nb<64, 1>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 64 * 8 + 2: return launch_nb<64, 2>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 64 * 8 + 3: return launch_nb<64, 3>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 64 * 8 + 4: return launch_nb<64, 4>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 128 * 8 + 3: return launch_nb<128, 3>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 128 * 8 + 4: return launch_nb<128, 4>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 128 * 8 + 5: return launch_nb<128, 5>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 256 * 8 + 1: return launch_nb<256, 1>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 256 * 8 + 2: return launch_nb<256, 2>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 256 * 8 + 3: return launch_nb<256, 3>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 256 * 8 + 4: return launch_nb<256, 4>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
-    case 256 * 8 + 5: return launch_nb<256, 5>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, s);
+    case 64 * 8 + 1: return launch_nb<64, 1>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 64 * 8 + 2: return launch_nb<64, 2>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 64 * 8 + 3: return launch_nb<64, 3>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 64 * 8 + 4: return launch_nb<64, 4>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 128 * 8 + 3: return launch_nb<128, 3>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 128 * 8 + 4: return launch_nb<128, 4>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 128 * 8 + 5: return launch_nb<128, 5>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 256 * 8 + 1: return launch_nb<256, 1>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 256 * 8 + 2: return launch_nb<256, 2>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 256 * 8 + 3: return launch_nb<256, 3>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 256 * 8 + 4: return launch_nb<256, 4>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
+    case 256 * 8 + 5: return launch_nb<256, 5>(cr, cm, io, thr, band, q, cq, b1, a2, tiles, sel, n_sel, s);
     default: return hipErrorInvalidValue;
   }
 }
