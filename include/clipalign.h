@@ -425,13 +425,21 @@ ca_status ca_graph_destroy(ca_graph* g);
  * signature bound over the window (B2).  CA_EDGE: every same-size pair is a
  * candidate of the polygon bounding-box size bound only (B3: every polygon of
  * the side with fewer polygons needs a partner whose box width and height
- * differ by at most 2 thr_num).  A rejected pair can never pass `con`, so
- * pruned results equal unpruned ones.
+ * differ by at most 2 thr_num; with con->edges == CA_EDGES_CONTOUR also the same
+ * polygon hash).  A rejected pair can never pass `con`, so pruned results
+ * equal unpruned ones.
  * Output (device pointers): candidate pairs (rep[k], mem[k]), both directions
  * to be aligned; CA_EDGE writes rep[k] < mem[k] sorted by (rep, mem), CA_COSINE
  * groups the pairs by the anchor of the smaller pixel count; capacity `cap`
  * pairs.  *n_out (host) receives the survivor count; if it exceeds cap,
- * nothing is written past cap and CA_ETRUNC is returned.  Synchronises. */
+ * nothing is written past cap and CA_ETRUNC is returned.  Synchronises.
+ * Call with cap = 0 to size, then again to write: the bounds pass of the
+ * sizing call is kept on the context for the writing call.  Its candidate
+ * mask (one bit per pair in each anchor's partner range) is held at most a
+ * quarter of the free device memory at a time (the environment variable
+ * CLIPALIGN_PRUNE_CHUNK_BYTES sets another limit, in bytes); a larger mask is
+ * built over chunks of consecutive anchors, and the writing call then rebuilds
+ * each chunk before writing its pairs (same results, twice the bounds work). */
 ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con,
                    int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out);
 
