@@ -91,13 +91,14 @@ __global__ void __launch_bounds__(64) contour_count_kernel(ClipsDev cs, int64_t 
   if (lane == 0) out[i] = cnt > MAX_EDGES ? -1 : cnt;
 }
 
-// Label of pixel (y, x), which is set: the run of row y that holds x.
+// Label of pixel (y, x), which is set: the run of row y that holds x (-1 if
+// no run holds it, which a consistent clip set never gives).
 __device__ int label_at(const uint16_t* rp, const uint32_t* ru, int y, int x) {
   for (int k = rp[y]; k < rp[y + 1]; ++k) {
     const uint32_t r = ru[k];
     if ((int)(r & 511) <= x && x < (int)((r >> 9) & 511)) return (int)((r >> 18) & 63);
   }
-  return 0;  // not reached for a set pixel
+  return -1;
 }
 
 template <int NMAX>
@@ -214,9 +215,11 @@ __device__ void trace_clip(const ClipsDev& cs, int64_t i, TraceLds<NMAX>& L) {
               if (X == X0 && Y == Y0 && d == d0) break;
             }
             if (bad) break;
+            const int label = label_at(rp, ru, py, px);
+            if (label < 0) { bad = 1; break; }  // the clip then has no contour data
             L.c_start[nc] = (uint16_t)start;
             L.c_len[nc] = (uint16_t)(ne - start);
-            L.c_label[nc] = (uint8_t)label_at(rp, ru, py, px);
+            L.c_label[nc] = (uint8_t)label;
             ++nc;
           }
         }
