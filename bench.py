@@ -644,14 +644,22 @@ def copy_probe(nbytes, reps=3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    dst.copy_(src)
+    src.sum()
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):
         dst.copy_(src)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    for _ in range(reps):
+        src.sum()
+    torch.cuda.synchronize()
+    dt_sum = (time.perf_counter() - t) / reps
     print(json.dumps({"copy_bytes": src.numel() * 4, "reps": reps, "ms": dt * 1e3,
-                      "GBps_read_plus_write": 2 * src.numel() * 4 / dt / 1e9}))
+                      "GBps_read_plus_write": 2 * src.numel() * 4 / dt / 1e9,
+                      "sum_ms": dt_sum * 1e3, "GBps_read_only_sum": src.numel() * 4 / dt_sum / 1e9}))
 
 
 def _cpu_worker(args):
