@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <queue>
 #include <string>
@@ -46,6 +47,21 @@ namespace {
   } while (0)
 
 size_t aup(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device memory released at scope exit.
+struct DevBuf {
+  ca_ctx* c = nullptr;
+  void* p = nullptr;
+  size_t b = 0;
+  ~DevBuf() { free_ctx(c, p, b); }
+  ca_status alloc(ca_ctx* ctx, size_t bytes) {
+    c = ctx;
+    b = std::max<size_t>(bytes, 256);
+    ca_status st = alloc_ctx(ctx, &p, b);
+    if (st) b = 0;
+    return st;
+  }
+};
 
 // Cache key of a constraint's kind and edge set.
 int64_t con_key(const ca_constraint* con) { return con->kind | ((int64_t)con->edges << 8); }
@@ -105,6 +121,23 @@ void build_ranges(const ca_clipset* cs, const ca_constraint* con, std::vector<in
 // free device memory (at least 1 GiB; CLIPALIGN_PRUNE_CHUNK_BYTES overrides).
 // Larger masks run the pass over chunks of consecutive anchors, and the
 // writing call then rebuilds each chunk's mask.
+// The writing call in pieces: consecutive anchors whose candidates total at
+// most `cap` pairs (cap >= the longest anchor range) are written to the start
+// of (rep, mem), then fn(piece size) runs on the same stream before the next
+// piece overwrites them.
+struct Pieces {
+  int64_t cap;
+  std::function<ca_status(int64_t)> fn;
+};
+
+// End of the piece of anchors that starts at a0 (at most `cap` pairs, before
+// a_end); a0 itself when one anchor alone exceeds cap.
+static int64_t piece_end(const std::vector<int64_t>& counts, int64_t a0, int64_t a_end, int64_t cap) {
+  int64_t a1 = a0, m = 0;
+  while (a1 < a_end && m + counts[a1] <= cap) m += counts[a1++];
+  return a1;
+}
+
 static int64_t prune_chunk_bytes() {
   if (const char* e = std::getenv("CLIPALIGN_PRUNE_CHUNK_BYTES")) {
     const long long v = std::atoll(e);
@@ -117,7 +150,8 @@ static int64_t prune_chunk_bytes() {
 }
 
 static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
-                                     int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
+                                     int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out,
+                                     const Pieces* pieces = nullptr) {
   const bool edge = con->kind == CA_EDGE;
   const bool topo = over_contours(con);  // polygon hashes as a third table
   const Threshold thr{con->thr_num, con->thr_den};
@@ -228,13 +262,14 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
   char* base = (char*)pc->dev;
   *n_out = pc->total;
   if (!rep) return CA_OK;
-  if (pc->total > cap) return fail_ctx(ctx, CA_ETRUNC, "candidate buffer too small");
-  std::vector<int64_t> off(na);
+  if (!pieces && pc->total > cap) return fail_ctx(ctx, CA_ETRUNC, "candidate buffer too small");
+  std::vector<int64_t> off(na + 1);
   int64_t acc = 0;
   for (int64_t a = 0; a < na; ++a) {
     off[a] = acc;
     acc += pc->counts[a];
   }
+  off[na] = acc;
   int64_t* d_off = (int64_t*)(base + 2 * b_ord + 2 * b_rng);
   HIP_TRY(ctx, hipMemcpyAsync(d_off, off.data(), 8 * na, hipMemcpyHostToDevice, s));
   const int n_chunks = (int)pc->cuts.size() - 1;
@@ -245,30 +280,46 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
       ca_status st = bounds_chunk(base, pc->b_mask, c);
       if (st) return st;
     }
-    PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), pc->cuts[c + 1], nullptr, d_off, rep, mem};
-    pa.a_begin = pc->cuts[c];
-    pa.mask_bit0 = pc->cut_bit0[c];
-    pa.order_ids = edge ? 1 : 0;
-    HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, thr, (int64_t*)(base + 2 * b_ord),
-                                 (uint32_t*)(base + 2 * b_ord + 3 * b_rng), true, s));
+    for (int64_t a0 = pc->cuts[c]; a0 < pc->cuts[c + 1];) {
+      const int64_t a1 = pieces ? piece_end(pc->counts, a0, pc->cuts[c + 1], pieces->cap) : pc->cuts[c + 1];
+      if (a1 == a0) return fail_ctx(ctx, CA_EINVAL, "internal: an anchor's candidates exceed the piece size");
+      PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), a1, nullptr, d_off, rep, mem};
+      pa.a_begin = a0;
+      pa.mask_bit0 = pc->cut_bit0[c];
+      pa.order_ids = edge ? 1 : 0;
+      pa.out_base = pieces ? off[a0] : 0;
+      HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, thr, (int64_t*)(base + 2 * b_ord),
+                                   (uint32_t*)(base + 2 * b_ord + 3 * b_rng), true, s));
+      if (pieces && off[a1] > off[a0]) {
+        ca_status st = pieces->fn(off[a1] - off[a0]);
+        if (st) return st;
+      }
+      a0 = a1;
+    }
   }
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return CA_OK;
 }
 
-// Device candidate generation into caller buffers (or sizing only when rep is null).
+// Device candidate generation into caller buffers (or sizing only when rep is
+// null), or in pieces (rep, mem: one piece).
 static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
-                              int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out) {
-  if (con->kind == CA_EDGE || mixed_ok_of(cs)) return prune_cached_device(ctx, s, cs, con, cap, rep, mem, n_out);
+                              int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out,
+                              const Pieces* pieces = nullptr) {
+  if (con->kind == CA_EDGE || mixed_ok_of(cs))
+    return prune_cached_device(ctx, s, cs, con, cap, rep, mem, n_out, pieces);
   std::vector<int32_t> order, hi;
   int64_t screened = 0;
   build_ranges(cs, con, order, hi, screened);
   const int64_t na = (int64_t)order.size();
   void* sc;
   const size_t b_ord = aup(4 * (size_t)na), b_hi = aup(4 * (size_t)na), b_cnt = aup(8 * (size_t)na);
-  ca_status st = scratch_ctx(ctx, b_ord + b_hi + 2 * b_cnt, &sc);
+  // pieces: the alignment between them uses the context's scratch, so the
+  // anchor tables get their own allocation
+  DevBuf own;
+  ca_status st = pieces ? own.alloc(ctx, b_ord + b_hi + 2 * b_cnt) : scratch_ctx(ctx, b_ord + b_hi + 2 * b_cnt, &sc);
   if (st) return st;
-  char* base = (char*)sc;
+  char* base = pieces ? (char*)own.p : (char*)sc;
   int32_t* d_order = (int32_t*)base;
   int32_t* d_hi = (int32_t*)(base + b_ord);
   int64_t* d_cnt = (int64_t*)(base + b_ord + b_hi);
@@ -290,12 +341,25 @@ static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, 
   stats_of(ctx)->pairs_screened += screened;
   stats_of(ctx)->pairs_survived += total;
   if (!rep) return CA_OK;
-  if (total > cap) return fail_ctx(ctx, CA_ETRUNC, "candidate buffer too small");
+  if (!pieces && total > cap) return fail_ctx(ctx, CA_ETRUNC, "candidate buffer too small");
   HIP_TRY(ctx, hipMemcpyAsync(d_off, off.data(), 8 * na, hipMemcpyHostToDevice, s));
   pa.offs = d_off;
   pa.out_rep = rep;
   pa.out_mem = mem;
-  HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, maxN_of(cs), s));
+  for (int64_t a0 = 0; a0 < na;) {
+    const int64_t a1 = pieces ? piece_end(cnt, a0, na, pieces->cap) : na;
+    if (a1 == a0) return fail_ctx(ctx, CA_EINVAL, "internal: an anchor's candidates exceed the piece size");
+    pa.a_begin = a0;
+    pa.n_anchor = a1;
+    pa.out_base = pieces ? off[a0] : 0;
+    HIP_TRY(ctx, launch_cosine_prune(dev_of(cs), pa, thr, maxN_of(cs), s));
+    const int64_t m = (a1 < na ? off[a1] : total) - off[a0];
+    if (pieces && m > 0) {
+      st = pieces->fn(m);
+      if (st) return st;
+    }
+    a0 = a1;
+  }
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return CA_OK;
 }
@@ -319,21 +383,6 @@ extern "C" ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, c
 
 namespace {
 
-// Device memory released at scope exit.
-struct DevBuf {
-  ca_ctx* c = nullptr;
-  void* p = nullptr;
-  size_t b = 0;
-  ~DevBuf() { free_ctx(c, p, b); }
-  ca_status alloc(ca_ctx* ctx, size_t bytes) {
-    c = ctx;
-    b = std::max<size_t>(bytes, 256);
-    ca_status st = alloc_ctx(ctx, &p, b);
-    if (st) b = 0;
-    return st;
-  }
-};
-
 bool cover_hit(const CoverCache* cc, const ca_clipset* cs, const ca_constraint* con, int path) {
   return cc->gen != 0 && cc->gen == gen_of(cs) && cc->kind == con_key(con) && cc->p == con->thr_num &&
          cc->q == con->thr_den && cc->path == path;
@@ -341,43 +390,84 @@ bool cover_hit(const CoverCache* cc, const ca_clipset* cs, const ca_constraint* 
 
 }  // namespace
 
-// The cover relation of `con` on the clip set (Sec. 3.1 stage 2): candidate
-// pairs from the safe bounds, both directions aligned with `path` (cosine)
-// or the edge track, and the set directions compacted on the device into a
-// CSR sorted by (representative, member), kept in the context's cache.
-static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con, int path,
-                             CoverCache** out) {
-  CoverCache* cc = cover_cache_of(ctx);
-  const int pth = con->kind == CA_COSINE ? path : -1;
-  *out = cc;
-  if (cover_hit(cc, cs, con, pth)) return CA_OK;
-  const int64_t n = n_of(cs);
-  int64_t np = 0;
-  ca_status st = prune_device(ctx, s, cs, con, 0, nullptr, nullptr, &np);
-  if (st) return st;
-  // candidate pairs, their results, row counts and cursors
-  const size_t b4 = aup(4 * (size_t)np), b_bits = aup((size_t)np), b_sh = aup(8 * (size_t)np),
-               b_cnt = aup(8 * (size_t)np), b_sc = aup(16 * (size_t)np), b_row = aup(8 * (size_t)n);
-  DevBuf work;
-  st = work.alloc(ctx, 3 * b4 + b_bits + b_sh + b_cnt + b_sc + 2 * b_row);
-  if (st) return st;
-  char* w = (char*)work.p;
-  int32_t* d_rep = (int32_t*)w; w += b4;
-  int32_t* d_mem = (int32_t*)w; w += b4;
-  uint32_t* d_flags = (uint32_t*)w; w += b4;
-  uint8_t* d_bits = (uint8_t*)w; w += b_bits;
-  int16_t* d_shift = (int16_t*)w; w += b_sh;
-  int32_t* d_count = (int32_t*)w; w += b_cnt;
-  double* d_score = (double*)w; w += b_sc;
-  unsigned long long* d_rowcnt = (unsigned long long*)w; w += b_row;
-  unsigned long long* d_fill = (unsigned long long*)w;
-  if (np > 0) {
-    int64_t got = 0;
-    st = prune_device(ctx, s, cs, con, np, d_rep, d_mem, &got);
-    if (st) return st;
-    st = ca_align_pairs(ctx, s, cs, con, path, np, d_rep, d_mem, d_bits, d_shift, d_count, d_score, d_flags);
-    if (st) return st;
+// Candidate pairs aligned at once by the cover relation: a list longer than
+// this is aligned in pieces of at most this many pairs (at least n, so one
+// anchor's partners always fit; at most 2^30, so the sort keys' pair indices
+// fit).  Default: an eighth of the free device memory at 45 bytes a pair;
+// CLIPALIGN_COVER_PIECE_PAIRS overrides.
+static int64_t cover_piece_pairs(int64_t n) {
+  int64_t v = 0;
+  if (const char* e = std::getenv("CLIPALIGN_COVER_PIECE_PAIRS")) v = std::atoll(e);
+  if (v <= 0) {
+    size_t free_b = 0, total_b = 0;
+    v = (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) ? (int64_t)(free_b / 8 / 45) : (1ll << 26);
   }
+  return std::max<int64_t>(std::min<int64_t>(v, 1ll << 30), std::max<int64_t>(n, 1));
+}
+
+// Pairs with a set direction and their results, kept from the pieces of a
+// long candidate list (grown as pieces arrive).
+struct Kept {
+  DevBuf buf;
+  int64_t cap = 0;
+  int32_t* rep = nullptr;
+  int32_t* mem = nullptr;
+  uint8_t* bits = nullptr;
+  int16_t* shift = nullptr;
+  int32_t* count = nullptr;
+  double* score = nullptr;
+
+  static size_t bytes(int64_t c) {
+    return 2 * aup(4 * (size_t)c) + aup((size_t)c) + 2 * aup(8 * (size_t)c) + aup(16 * (size_t)c);
+  }
+  // capacity `want`, the first `used` entries copied over
+  ca_status grow(ca_ctx* ctx, hipStream_t s, int64_t want, int64_t used) {
+    DevBuf nb;
+    ca_status st = nb.alloc(ctx, bytes(want));
+    if (st) return st;
+    char* w = (char*)nb.p;
+    int32_t* n_rep = (int32_t*)w; w += aup(4 * (size_t)want);
+    int32_t* n_mem = (int32_t*)w; w += aup(4 * (size_t)want);
+    uint8_t* n_bits = (uint8_t*)w; w += aup((size_t)want);
+    int16_t* n_shift = (int16_t*)w; w += aup(8 * (size_t)want);
+    int32_t* n_count = (int32_t*)w; w += aup(8 * (size_t)want);
+    double* n_score = (double*)w;
+    if (used > 0) {
+      HIP_TRY(ctx, hipMemcpyAsync(n_rep, rep, 4 * (size_t)used, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(n_mem, mem, 4 * (size_t)used, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(n_bits, bits, (size_t)used, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(n_shift, shift, 8 * (size_t)used, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(n_count, count, 8 * (size_t)used, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipMemcpyAsync(n_score, score, 16 * (size_t)used, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+    }
+    std::swap(buf.c, nb.c);
+    std::swap(buf.p, nb.p);
+    std::swap(buf.b, nb.b);
+    cap = want;
+    rep = n_rep;
+    mem = n_mem;
+    bits = n_bits;
+    shift = n_shift;
+    count = n_count;
+    score = n_score;
+    return CA_OK;
+  }
+};
+
+// Steps 1-5 of the compaction on np aligned pairs (both directions each):
+// row counts, row pointers, keys scattered to their rows, per-row sort and
+// the gather, into the cover cache's arrays.
+static ca_status cover_compact(ca_ctx* ctx, hipStream_t s, CoverCache* cc, int64_t n, int64_t np,
+                               const int32_t* d_rep, const int32_t* d_mem, const uint8_t* d_bits,
+                               const int16_t* d_shift, const int32_t* d_count, const double* d_score) {
+  if (np >= (1ll << 31))
+    return fail_ctx(ctx, CA_EUNSUPPORTED, "cover relation from 2^31 or more candidate pairs with a set direction");
+  DevBuf rows;
+  ca_status st = rows.alloc(ctx, 2 * aup(8 * (size_t)n));
+  if (st) return st;
+  unsigned long long* d_rowcnt = (unsigned long long*)rows.p;
+  unsigned long long* d_fill = (unsigned long long*)((char*)rows.p + aup(8 * (size_t)n));
   HIP_TRY(ctx, launch_zero_u64(d_rowcnt, n, s));
   HIP_TRY(ctx, launch_cover_count(np, d_rep, d_mem, d_bits, d_rowcnt, s));
   std::vector<int64_t> cnt(n);
@@ -394,10 +484,6 @@ static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, c
   }
   const int64_t nnz = row_ptr[n];
   // the cache's arrays
-  free_ctx(ctx, cc->dev, cc->bytes);
-  cc->dev = nullptr;
-  cc->bytes = 0;
-  cc->gen = 0;
   const size_t c_rp = aup(8 * (size_t)(n + 1)), c_col = aup(4 * (size_t)nnz), c_sh = aup(4 * (size_t)nnz),
                c_val = aup(4 * (size_t)nnz), c_sc = aup(8 * (size_t)nnz);
   const size_t c_bytes = c_rp + c_col + c_sh + c_val + c_sc;
@@ -433,19 +519,111 @@ static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, c
                                    cc->row_ptr, d_keys, d_tmp, s));
     HIP_TRY(ctx, launch_cover_gather(nnz, d_keys, d_shift, d_count, d_score, cc->col, cc->shift, cc->value,
                                      cc->score, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-  } else {
-    HIP_TRY(ctx, hipStreamSynchronize(s));
   }
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  cc->n = n;
+  cc->nnz = nnz;
+  cc->h_row_ptr.swap(row_ptr);
+  stats_of(ctx)->cover_nnz = nnz;
+  return CA_OK;
+}
+
+// The cover relation of `con` on the clip set (Sec. 3.1 stage 2): candidate
+// pairs from the safe bounds, both directions aligned with `path` (cosine)
+// or the edge track, and the set directions compacted on the device into a
+// CSR sorted by (representative, member), kept in the context's cache.  A
+// candidate list longer than the piece size is written, aligned and reduced
+// to its pairs with a set direction piece by piece, so its per-pair results
+// never exist all at once.
+static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con, int path,
+                             CoverCache** out) {
+  CoverCache* cc = cover_cache_of(ctx);
+  const int pth = con->kind == CA_COSINE ? path : -1;
+  *out = cc;
+  if (cover_hit(cc, cs, con, pth)) return CA_OK;
+  // the stale relation's memory goes before the new one is built
+  free_ctx(ctx, cc->dev, cc->bytes);
+  cc->dev = nullptr;
+  cc->bytes = 0;
+  cc->gen = 0;
+  const int64_t n = n_of(cs);
+  int64_t np = 0;
+  ca_status st = prune_device(ctx, s, cs, con, 0, nullptr, nullptr, &np);
+  if (st) return st;
+  const int64_t piece = cover_piece_pairs(n);
+  if (np <= piece) {
+    // candidate pairs and their results
+    const size_t b4 = aup(4 * (size_t)np), b_bits = aup((size_t)np), b_sh = aup(8 * (size_t)np),
+                 b_cnt = aup(8 * (size_t)np), b_sc = aup(16 * (size_t)np);
+    DevBuf work;
+    st = work.alloc(ctx, 3 * b4 + b_bits + b_sh + b_cnt + b_sc);
+    if (st) return st;
+    char* w = (char*)work.p;
+    int32_t* d_rep = (int32_t*)w; w += b4;
+    int32_t* d_mem = (int32_t*)w; w += b4;
+    uint32_t* d_flags = (uint32_t*)w; w += b4;
+    uint8_t* d_bits = (uint8_t*)w; w += b_bits;
+    int16_t* d_shift = (int16_t*)w; w += b_sh;
+    int32_t* d_count = (int32_t*)w; w += b_cnt;
+    double* d_score = (double*)w;
+    if (np > 0) {
+      int64_t got = 0;
+      st = prune_device(ctx, s, cs, con, np, d_rep, d_mem, &got);
+      if (st) return st;
+      st = ca_align_pairs(ctx, s, cs, con, path, np, d_rep, d_mem, d_bits, d_shift, d_count, d_score, d_flags);
+      if (st) return st;
+    }
+    st = cover_compact(ctx, s, cc, n, np, d_rep, d_mem, d_bits, d_shift, d_count, d_score);
+  } else {
+    Kept kept;
+    int64_t n_kept = 0;
+    {
+      const size_t p4 = aup(4 * (size_t)piece), p_bits = aup((size_t)piece), p8 = aup(8 * (size_t)piece),
+                   p_sc = aup(16 * (size_t)piece);
+      DevBuf work;
+      st = work.alloc(ctx, 3 * p4 + p_bits + 2 * p8 + p_sc + 256);
+      if (st) return st;
+      char* w = (char*)work.p;
+      int32_t* p_rep = (int32_t*)w; w += p4;
+      int32_t* p_mem = (int32_t*)w; w += p4;
+      uint32_t* p_flags = (uint32_t*)w; w += p4;
+      uint8_t* p_bitv = (uint8_t*)w; w += p_bits;
+      int16_t* p_shift = (int16_t*)w; w += p8;
+      int32_t* p_count = (int32_t*)w; w += p8;
+      double* p_score = (double*)w; w += p_sc;
+      unsigned long long* d_ctr = (unsigned long long*)w;  // [0] kept in the piece, [1] next slot
+      HIP_TRY(ctx, launch_zero_u64(d_ctr, 2, s));
+      Pieces pcs{piece, [&](int64_t m) -> ca_status {
+        ca_status e = ca_align_pairs(ctx, s, cs, con, path, m, p_rep, p_mem, p_bitv, p_shift, p_count, p_score,
+                                     p_flags);
+        if (e) return e;
+        HIP_TRY(ctx, launch_zero_u64(d_ctr, 1, s));
+        HIP_TRY(ctx, launch_cover_keep_count(m, p_bitv, d_ctr, s));
+        unsigned long long c = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(&c, d_ctr, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        if (c == 0) return CA_OK;
+        if (n_kept + (int64_t)c > kept.cap) {
+          e = kept.grow(ctx, s, std::max(n_kept + (int64_t)c, kept.cap + kept.cap / 2), n_kept);
+          if (e) return e;
+        }
+        HIP_TRY(ctx, launch_cover_keep(m, p_rep, p_mem, p_bitv, p_shift, p_count, p_score, d_ctr + 1, kept.rep,
+                                       kept.mem, kept.bits, kept.shift, kept.count, kept.score, s));
+        n_kept += (int64_t)c;
+        return CA_OK;
+      }};
+      int64_t got = 0;
+      st = prune_device(ctx, s, cs, con, 0, p_rep, p_mem, &got, &pcs);
+      if (st) return st;
+    }
+    st = cover_compact(ctx, s, cc, n, n_kept, kept.rep, kept.mem, kept.bits, kept.shift, kept.count, kept.score);
+  }
+  if (st) return st;
   cc->gen = gen_of(cs);
   cc->kind = con_key(con);
   cc->p = con->thr_num;
   cc->q = con->thr_den;
   cc->path = pth;
-  cc->n = n;
-  cc->nnz = nnz;
-  cc->h_row_ptr.swap(row_ptr);
-  stats_of(ctx)->cover_nnz = nnz;
   return CA_OK;
 }
 

@@ -18,6 +18,10 @@
 //      memory where each key's output position is its index in its run plus
 //      its rank in the sibling run (binary search);
 //   5. gather: column, shift, count and score of each sorted key.
+// A candidate list too long to align at once is aligned in pieces; each
+// piece keeps only its pairs with a set direction (with their results, in any
+// order: the row sort makes the relation unique), and steps 1-5 run on the
+// kept pairs.
 #include "kernels.h"
 #include "pair_common.h"
 
@@ -52,6 +56,47 @@ __global__ void cover_scatter_kernel(int64_t n_pairs, const int32_t* __restrict_
     const int64_t pos = row_ptr[m] + (int64_t)atomicAdd(&fill[m], 1ull);
     keys[pos] = ((uint64_t)(uint32_t)a << 32) | (uint64_t)(2 * k + 1);
   }
+}
+
+// Pairs of a piece with at least one set direction (keep_count: how many).
+__global__ void cover_keep_count_kernel(int64_t n_pairs, const uint8_t* __restrict__ bits,
+                                        unsigned long long* __restrict__ n_keep) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool on = k < n_pairs && (bits[k] & 3u) != 0;
+  const unsigned long long m = __ballot(on);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_keep, (unsigned long long)__popcll(m));
+}
+
+// Copies the kept pairs and both directions' results (shift: 4 int16, count:
+// 2 int32, score: 2 double per pair) to slots taken from *slot, one atomic
+// per wave.
+__global__ void cover_keep_kernel(int64_t n_pairs, const int32_t* __restrict__ rep, const int32_t* __restrict__ mem,
+                                  const uint8_t* __restrict__ bits, const uint64_t* __restrict__ shift,
+                                  const uint64_t* __restrict__ count, const double* __restrict__ score,
+                                  unsigned long long* __restrict__ slot, int32_t* __restrict__ k_rep,
+                                  int32_t* __restrict__ k_mem, uint8_t* __restrict__ k_bits,
+                                  uint64_t* __restrict__ k_shift, uint64_t* __restrict__ k_count,
+                                  double* __restrict__ k_score) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint8_t b = k < n_pairs ? bits[k] : 0;
+  const bool on = (b & 3u) != 0;
+  const unsigned long long m = __ballot(on);
+  if (!m) return;  // wave-uniform
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(slot, (unsigned long long)__popcll(m));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
+  if (!on) return;
+  const int64_t j = (int64_t)(((uint64_t)hi << 32) | lo) + __popcll(m & ((1ull << lane) - 1ull));
+  k_rep[j] = rep[k];
+  k_mem[j] = mem[k];
+  k_bits[j] = b;
+  k_shift[j] = shift[k];
+  k_count[j] = count[k];
+  k_score[2 * j] = score[2 * k];
+  k_score[2 * j + 1] = score[2 * k + 1];
 }
 
 // Rows of at most 64 keys, one wave per row (four rows per workgroup): each
@@ -225,6 +270,33 @@ hipError_t launch_cover_count(int64_t n_pairs, const int32_t* rep, const int32_t
     const int64_t nk = std::min<int64_t>(LAUNCH_CHUNK * 256, n_pairs - k0);
     hipLaunchKernelGGL(cover_count_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, nk, rep + k0,
                        mem + k0, bits + k0, rowcnt);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_cover_keep_count(int64_t n_pairs, const uint8_t* bits, unsigned long long* n_keep, hipStream_t s) {
+  for (int64_t k0 = 0; k0 < n_pairs; k0 += LAUNCH_CHUNK * 256) {
+    const int64_t nk = std::min<int64_t>(LAUNCH_CHUNK * 256, n_pairs - k0);
+    hipLaunchKernelGGL(cover_keep_count_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, nk, bits + k0,
+                       n_keep);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_cover_keep(int64_t n_pairs, const int32_t* rep, const int32_t* mem, const uint8_t* bits,
+                             const int16_t* shift, const int32_t* count, const double* score,
+                             unsigned long long* slot, int32_t* k_rep, int32_t* k_mem, uint8_t* k_bits,
+                             int16_t* k_shift, int32_t* k_count, double* k_score, hipStream_t s) {
+  for (int64_t k0 = 0; k0 < n_pairs; k0 += LAUNCH_CHUNK * 256) {
+    const int64_t nk = std::min<int64_t>(LAUNCH_CHUNK * 256, n_pairs - k0);
+    hipLaunchKernelGGL(cover_keep_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, nk, rep + k0,
+                       mem + k0, bits + k0, reinterpret_cast<const uint64_t*>(shift + 4 * k0),
+                       reinterpret_cast<const uint64_t*>(count + 2 * k0), score + 2 * k0, slot, k_rep, k_mem,
+                       k_bits, reinterpret_cast<uint64_t*>(k_shift), reinterpret_cast<uint64_t*>(k_count), k_score);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

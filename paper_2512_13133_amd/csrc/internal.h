@@ -134,6 +134,9 @@ struct PruneArgs {
   // mask_bit0 of the range offsets (the bounds pass in anchor chunks)
   int64_t a_begin = 0;
   int64_t mask_bit0 = 0;
+  // subtracted from every write offset, so a piece of anchors [a_begin,
+  // n_anchor) lands at the start of its own output buffer
+  int64_t out_base = 0;
   // partner sliding sums transposed (packed row pair q of the partner at
   // position b of `order` at [q * soa_n + b]), so a wave's 64 partners read
   // one contiguous run per pair; null: read each partner's own row

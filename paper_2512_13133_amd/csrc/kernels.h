@@ -145,6 +145,14 @@ hipError_t launch_validate(const ClipsDev& cr, const ClipsDev& cm, int64_t n_pai
 // column, shift, count and score per sorted key.
 hipError_t launch_cover_count(int64_t n_pairs, const int32_t* rep, const int32_t* mem, const uint8_t* bits,
                               unsigned long long* rowcnt, hipStream_t s);
+// A piece of a long candidate list: *n_keep += its pairs with a set direction
+// (keep_count), then those pairs and their results copied to the kept arrays
+// at slots taken from *slot (keep; the kept arrays hold *slot + that many).
+hipError_t launch_cover_keep_count(int64_t n_pairs, const uint8_t* bits, unsigned long long* n_keep, hipStream_t s);
+hipError_t launch_cover_keep(int64_t n_pairs, const int32_t* rep, const int32_t* mem, const uint8_t* bits,
+                             const int16_t* shift, const int32_t* count, const double* score,
+                             unsigned long long* slot, int32_t* k_rep, int32_t* k_mem, uint8_t* k_bits,
+                             int16_t* k_shift, int32_t* k_count, double* k_score, hipStream_t s);
 hipError_t launch_cover_scatter(int64_t n_pairs, const int32_t* rep, const int32_t* mem, const uint8_t* bits,
                                 const int64_t* row_ptr, unsigned long long* fill, uint64_t* keys, hipStream_t s);
 hipError_t launch_cover_sort(const int32_t* small_rows, int64_t n_small, const int32_t* large_rows, int64_t n_large,

@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(64) cosine_prune_kernel(ClipsDev cs, PruneArgs
     int total = 0;
     const int before = wave_prefix(pass, lane, &total);
     if (pass && pa.offs) {
-      const int64_t o = pa.offs[a] + written + before;
+      const int64_t o = pa.offs[a] - pa.out_base + written + before;
       pa.out_rep[o] = ia;
       pa.out_mem[o] = ib;
     }
@@ -227,8 +227,7 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
 namespace ca {
 
 hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, int maxN, hipStream_t s) {
-  if (pa.n_anchor == 0) return hipSuccess;
-  for (int64_t b0 = 0; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
+  for (int64_t b0 = pa.a_begin; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
     hipLaunchKernelGGL(cosine_prune_kernel, dim3(nb), dim3(64), (size_t)256 * maxN, s, cs, pa, thr, b0);
     const hipError_t e = hipGetLastError();

@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(64) prune128_write_kernel(PruneArgs pa, const 
     if (p_first >= len) return;
   }
   const int64_t roff = range_off[a] - pa.mask_bit0;
-  int64_t o = pa.offs[pa.seg > 0 ? a * pa.n_seg + blockIdx.y : a];
+  int64_t o = pa.offs[pa.seg > 0 ? a * pa.n_seg + blockIdx.y : a] - pa.out_base;
   for (int64_t p0 = p_first; p0 < len; p0 += 64) {
     const int64_t p = p0 + lane;
     bool on = false;

@@ -194,3 +194,54 @@ def test_prune_in_anchor_chunks_equals_one_pass(ctx, kind, thr, monkeypatch):
     assert (rep1 == rep2).all() and (mem1 == mem2).all()
     for k in ("row_ptr", "col", "shift", "value"):
         assert (cov1[k] == cov2[k]).all(), k
+
+
+def test_cover_in_pieces_equals_oracle_small(ctx, small_case, monkeypatch):
+    """64 x 64 clips (the generic cosine bounds pass) with the candidate list
+    aligned in pieces of at most n pairs: the relation still equals the
+    oracle's, on both tracks."""
+    cs, rep, mem, res, er = small_case
+    res = cover.align_pairs_cosine(cs, rep, mem, 1, 2, workers=WORKERS)  # enough candidates at 1/2
+    monkeypatch.setenv("CLIPALIGN_COVER_PIECE_PAIRS", "1")  # raised to n by the library
+    h = ctx.clips(cs, fp32=True)
+    n_cos = ctx.prune(h, "cosine", (1, 2))[0].numel()
+    n_edge = ctx.prune(h, "edge", 2)[0].numel()
+    say(f"[cover pieces] small n={cs.n}: cosine {n_cos} candidates, edge {n_edge}")
+    assert n_cos > cs.n and n_edge > cs.n  # more than one piece each
+    ref_c = cover.cover_csr(cs.n, rep, mem, res["bits"], res["shift"], res["c"], res["score"])
+    for path in ("fp32", "auto"):
+        _check_csr(_np(ctx.cover(h, "cosine", (1, 2), path)), ref_c, f"pieces cosine {path}")
+    zeros = np.zeros_like(er["E"], dtype=np.float64)
+    ref_e = cover.cover_csr(cs.n, rep, mem, er["bits"], er["shift"], er["E"], zeros)
+    _check_csr(_np(ctx.cover(h, "edge", 2)), ref_e, "pieces edge")
+    h.close()
+
+
+@pytest.mark.parametrize("kind,thr", [("cosine", (19, 20)), ("edge", 3), ("contour", 3)])
+def test_cover_in_pieces_equals_one_pass(ctx, kind, thr, monkeypatch):
+    """128 x 128 clips (the cached bounds pass): the candidate list aligned in
+    pieces of at most n pairs, with the bounds pass also in anchor chunks,
+    gives the relation and the K = 3 clusters of one pass."""
+    if kind == "contour":
+        cs = clipgen.c128(n_clips=600, n_templates=4, jitter=1)  # equal topology within a template
+    else:
+        cs = clipgen.c128(n_clips=1200, n_templates=12)
+    h1 = ctx.clips(cs, contours=True)
+    np1 = ctx.prune(h1, kind, thr)[0].numel()
+    cov1 = _np(ctx.cover(h1, kind, thr))
+    cl1 = ctx.cluster(h1, kind, thr, iterations=3)
+    h1.close()
+    monkeypatch.setenv("CLIPALIGN_COVER_PIECE_PAIRS", "1")
+    monkeypatch.setenv("CLIPALIGN_PRUNE_CHUNK_BYTES", "4096")
+    h2 = ctx.clips(cs, contours=True)
+    cov2 = _np(ctx.cover(h2, kind, thr))
+    cl2 = ctx.cluster(h2, kind, thr, iterations=3)
+    h2.close()
+    say(f"[cover pieces] {kind}: n={cs.n}, {np1} candidates, cover entries {cov1['col'].size}, "
+        f"clusters {cl1['n_clusters']}")
+    assert np1 > cs.n and cov1["col"].size > 0
+    for k in ("row_ptr", "col", "shift", "value"):
+        assert (cov1[k] == cov2[k]).all(), k
+    assert np.abs(cov1["score"] - cov2["score"]).max(initial=0.0) <= 1e-12
+    assert cl1["n_clusters"] == cl2["n_clusters"]
+    assert (cl1["rep_of"] == cl2["rep_of"]).all() and (cl1["center_shift"] == cl2["center_shift"]).all()
