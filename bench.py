@@ -81,7 +81,10 @@ def main():
     ap.add_argument("--no-contour", action="store_true", help="skip the edge track over full boundary edges")
     ap.add_argument("--scale-clusters", action="store_true",
                     help="only run the method end to end on the 2M-clip workload (cosine 19/20 and the edge track "
-                         "over full boundary edges at 2 px, K = 3) and print its object (several minutes)")
+                         "over full boundary edges at 2 px, K = 3; box edges at 2 px, K = 1) and print its object "
+                         "(several minutes)")
+    ap.add_argument("--scale-tracks", default="cosine,contour,edge",
+                    help="tracks of --scale-clusters, comma-separated (cosine, contour, edge)")
     ap.add_argument("--mixed-sizes-only", action="store_true",
                     help="only run the mixed-size workload (profiling) and print its object")
     ap.add_argument("--serve-library", type=int, default=100_000)
@@ -93,7 +96,7 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.scale_clusters:
-        print(json.dumps({"scale_clusters": scale_clusters()}))
+        print(json.dumps({"scale_clusters": scale_clusters(tuple(args.scale_tracks.split(",")))}))
         return
     if args.mixed_sizes_only:
         import paper_2512_13133_amd as ca
@@ -382,12 +385,15 @@ def contour_bench(ctx, make_clips, timed, stage_t, steps, t_edge=3, reps=3):
     return out
 
 
-def scale_clusters():
+def scale_clusters(tracks=("cosine", "contour", "edge")):
     """The method end to end on the 2,000,000-clip workload (128 x 128,
     template densities 0.1-0.6, window +-16) on one GPU: the cosine track at
-    19/20 and the edge track over full boundary edges at 2 px, K = 3 each
-    (candidates at the loosest threshold, alignment, cover, loop, and the
-    verification of every member at its center)."""
+    19/20 and the edge track over full boundary edges at 2 px with K = 3, and
+    the box edge track at 2 px with K = 1 (its K = 3 schedule starts from
+    4.0e10 candidates at 4 px, whose relation does not fit one GPU).  Each
+    track runs as printed steps: the candidates at the loosest threshold
+    counted, the cover relation there built and sized, then the loop on it
+    with the verification of every member at its center."""
     import ctypes as C
 
     import numpy as np
@@ -404,8 +410,9 @@ def scale_clusters():
     out = {"workload": "dense: 2,000,000 clips 128x128, 20,000 templates, densities 0.1-0.6, window +-16",
            "clip_set_s": round(time.perf_counter() - t, 2)}
     log(f"[scale] clip set with contours: {out['clip_set_s']} s")
-    for kind, thr, loose in (("cosine", (19, 20), (93, 100)), ("contour", 2, 4)):
-        # the loosest threshold of the K = 3 schedule, counted first (a step of its own)
+    runs = {"cosine": ((19, 20), (93, 100), 3), "contour": (2, 4, 3), "edge": (2, 2, 1)}
+    for kind in tracks:
+        thr, loose, K = runs[kind]
         con = ca.constraint(kind, loose)
         n = C.c_int64(0)
         ctx.reset_stats()
@@ -415,16 +422,24 @@ def scale_clusters():
         prune_s = time.perf_counter() - t
         screened = ctx.stats()["pairs_screened"]
         log(f"[scale] {kind}: {n.value} candidates of {screened} at the loosest threshold in {prune_s:.1f} s")
+        z = C.c_int64(0)
+        t = time.perf_counter()
+        ctx._check(ctx.lib.ca_cover(ctx.h, ctx._stream(), h.handle, C.byref(con), ca.PATHS["mixed"], 0, None, None,
+                                    None, None, None, C.byref(z)))
+        torch.cuda.synchronize()
+        cover_s = time.perf_counter() - t
+        log(f"[scale] {kind}: cover relation at the loosest threshold, {z.value} entries, in {cover_s:.1f} s")
         ctx.reset_stats()
         t = time.perf_counter()
-        g = ctx.cluster(h, kind, thr, iterations=3)
+        g = ctx.cluster(h, kind, thr, iterations=K)
         torch.cuda.synchronize()
         st = ctx.stats()
         cl_s = time.perf_counter() - t
         members = int((g["rep_of"] != np.arange(cs.n)).sum())
-        out[kind] = {"threshold": list(thr) if isinstance(thr, tuple) else thr, "K": 3,
+        out[kind] = {"threshold": list(thr) if isinstance(thr, tuple) else thr, "K": K,
                      "candidates_loosest": int(n.value), "pairs_screened": int(screened),
-                     "prune_count_s": round(prune_s, 1), "cluster_s": round(cl_s, 1),
+                     "prune_count_s": round(prune_s, 1), "cover_entries_loosest": int(z.value),
+                     "cover_s": round(cover_s, 1), "cluster_s": round(cl_s, 1),
                      "clusters": int(g["n_clusters"]), "members": members,
                      "members_verified": int(st["members_verified"]), "center_violations": int(st["center_violations"])}
         log(f"[scale] {kind}: {g['n_clusters']} clusters in {cl_s:.1f} s, {st['center_violations']} violations")

@@ -464,7 +464,13 @@ ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_con
  * is returned.  The relation is compacted on the device and kept on the
  * context: a following call with the same clip set, constraint and path (the
  * copying call after a sizing call, or ca_cluster's loosest threshold) reuses
- * it.  Synchronises. */
+ * it.  A candidate list longer than the piece size (45 bytes of per-pair
+ * results each: an eighth of the free device memory, at most 2^30 pairs and
+ * at least n; the environment variable CLIPALIGN_COVER_PIECE_PAIRS sets
+ * another size) is written, aligned and reduced to its pairs with a set
+ * direction one piece at a time, with the same result.  Returns
+ * CA_EUNSUPPORTED when 2^31 or more candidate pairs have a set direction.
+ * Synchronises. */
 ca_status ca_cover(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con, int32_t path,
                    int64_t cap, int64_t* row_ptr, int32_t* col, int16_t* shift, int32_t* value, double* score,
                    int64_t* nnz);

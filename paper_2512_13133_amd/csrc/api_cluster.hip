@@ -603,6 +603,9 @@ static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, c
         HIP_TRY(ctx, hipMemcpyAsync(&c, d_ctr, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
         if (c == 0) return CA_OK;
+        if (n_kept + (int64_t)c >= (1ll << 31))
+          return fail_ctx(ctx, CA_EUNSUPPORTED,
+                          "cover relation from 2^31 or more candidate pairs with a set direction");
         if (n_kept + (int64_t)c > kept.cap) {
           e = kept.grow(ctx, s, std::max(n_kept + (int64_t)c, kept.cap + kept.cap / 2), n_kept);
           if (e) return e;
