@@ -391,9 +391,11 @@ def scale_clusters(tracks=("cosine", "contour", "edge")):
     19/20 and the edge track over full boundary edges at 2 px with K = 3, and
     the box edge track at 2 px with K = 1 (its K = 3 schedule starts from
     4.0e10 candidates at 4 px, whose relation does not fit one GPU).  Each
-    track runs as printed steps: the candidates at the loosest threshold
-    counted, the cover relation there built and sized, then the loop on it
-    with the verification of every member at its center."""
+    track runs as printed steps: the cover relation at the loosest threshold
+    built and sized (the bounds pass, in anchor chunks where its candidate
+    mask does not fit, counting and writing the candidates in one sweep, and
+    their alignment and compaction), then the loop on it with the
+    verification of every member at its center."""
     import ctypes as C
 
     import numpy as np
@@ -414,21 +416,17 @@ def scale_clusters(tracks=("cosine", "contour", "edge")):
     for kind in tracks:
         thr, loose, K = runs[kind]
         con = ca.constraint(kind, loose)
-        n = C.c_int64(0)
-        ctx.reset_stats()
-        t = time.perf_counter()
-        ctx._check(ctx.lib.ca_prune(ctx.h, ctx._stream(), h.handle, C.byref(con), 0, None, None, C.byref(n)))
-        torch.cuda.synchronize()
-        prune_s = time.perf_counter() - t
-        screened = ctx.stats()["pairs_screened"]
-        log(f"[scale] {kind}: {n.value} candidates of {screened} at the loosest threshold in {prune_s:.1f} s")
         z = C.c_int64(0)
+        ctx.reset_stats()
         t = time.perf_counter()
         ctx._check(ctx.lib.ca_cover(ctx.h, ctx._stream(), h.handle, C.byref(con), ca.PATHS["mixed"], 0, None, None,
                                     None, None, None, C.byref(z)))
         torch.cuda.synchronize()
         cover_s = time.perf_counter() - t
-        log(f"[scale] {kind}: cover relation at the loosest threshold, {z.value} entries, in {cover_s:.1f} s")
+        st = ctx.stats()
+        cand, screened = st["pairs_survived"], st["pairs_screened"]
+        log(f"[scale] {kind}: {cand} candidates of {screened} at the loosest threshold, cover relation of "
+            f"{z.value} entries, in {cover_s:.1f} s")
         ctx.reset_stats()
         t = time.perf_counter()
         g = ctx.cluster(h, kind, thr, iterations=K)
@@ -437,8 +435,8 @@ def scale_clusters(tracks=("cosine", "contour", "edge")):
         cl_s = time.perf_counter() - t
         members = int((g["rep_of"] != np.arange(cs.n)).sum())
         out[kind] = {"threshold": list(thr) if isinstance(thr, tuple) else thr, "K": K,
-                     "candidates_loosest": int(n.value), "pairs_screened": int(screened),
-                     "prune_count_s": round(prune_s, 1), "cover_entries_loosest": int(z.value),
+                     "candidates_loosest": int(cand), "pairs_screened": int(screened),
+                     "cover_entries_loosest": int(z.value),
                      "cover_s": round(cover_s, 1), "cluster_s": round(cl_s, 1),
                      "clusters": int(g["n_clusters"]), "members": members,
                      "members_verified": int(st["members_verified"]), "center_violations": int(st["center_violations"])}

@@ -468,7 +468,9 @@ ca_status ca_prune(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_con
  * results each: an eighth of the free device memory, at most 2^30 pairs and
  * at least n; the environment variable CLIPALIGN_COVER_PIECE_PAIRS sets
  * another size) is written, aligned and reduced to its pairs with a set
- * direction one piece at a time, with the same result.  Returns
+ * direction one piece at a time, with the same result; when the bounds pass
+ * runs in anchor chunks (see ca_prune), one sweep counts and writes each
+ * chunk's candidates.  Returns
  * CA_EUNSUPPORTED when 2^31 or more candidate pairs have a set direction.
  * Synchronises. */
 ca_status ca_cover(ca_ctx* ctx, void* stream, const ca_clipset* cs, const ca_constraint* con, int32_t path,

@@ -151,12 +151,15 @@ static int64_t prune_chunk_bytes() {
 
 static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
                                      int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out,
-                                     const Pieces* pieces = nullptr) {
+                                     const Pieces* pieces = nullptr, bool defer = false,
+                                     int64_t* n_bound = nullptr) {
   const bool edge = con->kind == CA_EDGE;
   const bool topo = over_contours(con);  // polygon hashes as a third table
   const Threshold thr{con->thr_num, con->thr_den};
   PruneCache* pc = prune_cache_of(ctx);
   const bool hit = pc->gen == gen_of(cs) && pc->kind == con_key(con) && pc->p == con->thr_num && pc->q == con->thr_den;
+  const bool planned = pc->plan_gen == gen_of(cs) && pc->plan_kind == con_key(con) && pc->plan_p == con->thr_num &&
+                       pc->plan_q == con->thr_den;
   // a hit (the writing call after a sizing call) reuses the device copies of
   // the anchor order, ranges, partner tables and (one chunk) bitmask
   int64_t na = pc->na;
@@ -188,7 +191,42 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     }
     return CA_OK;
   };
-  if (!hit) {
+  // the pairs of anchors [a_lo, a_hi) of mask chunk c, written in pieces to
+  // the start of (rep, mem), each followed by pieces->fn; off: global offsets
+  auto write_pieces = [&](char* base, int c, int64_t a_lo, int64_t a_hi, const std::vector<int64_t>& counts,
+                          const std::vector<int64_t>& off) -> ca_status {
+    const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na);
+    int64_t* d_off = (int64_t*)(base + 2 * b_ord + 2 * b_rng);
+    for (int64_t a0 = a_lo; a0 < a_hi;) {
+      const int64_t a1 = pieces ? piece_end(counts, a0, a_hi, pieces->cap) : a_hi;
+      if (a1 == a0) return fail_ctx(ctx, CA_EINVAL, "internal: an anchor's candidates exceed the piece size");
+      PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), a1, nullptr, d_off, rep, mem};
+      pa.a_begin = a0;
+      pa.mask_bit0 = pc->cut_bit0[c];
+      pa.order_ids = edge ? 1 : 0;
+      pa.out_base = pieces ? off[a0] : 0;
+      HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, thr, (int64_t*)(base + 2 * b_ord),
+                                   (uint32_t*)(base + 2 * b_ord + 3 * b_rng), true, s));
+      if (pieces && off[a1] > off[a0]) {
+        ca_status st = pieces->fn(off[a1] - off[a0]);
+        if (st) return st;
+      }
+      a0 = a1;
+    }
+    return CA_OK;
+  };
+  // the counts are in: the cache is valid for this key
+  auto finish = [&]() {
+    pc->total = 0;
+    for (int64_t a = 0; a < na; ++a) pc->total += pc->counts[a];
+    pc->gen = gen_of(cs);
+    pc->kind = con_key(con);
+    pc->p = con->thr_num;
+    pc->q = con->thr_den;
+    stats_of(ctx)->pairs_screened += pc->plan_screened;
+    stats_of(ctx)->pairs_survived += pc->total;
+  };
+  if (!hit && !planned) {
     std::vector<int32_t> order, hi;
     int64_t screened = 0;
     build_ranges(cs, con, order, hi, screened);
@@ -201,6 +239,8 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
       bits += edge ? (len + 63) / 64 * 64 : len;
     }
     range_off[na] = bits;
+    int64_t pairs = 0;
+    for (int64_t a = 0; a < na; ++a) pairs += hi[a] - a - 1;
     // anchor chunks whose mask fits the budget (at least one anchor each);
     // cosine chunks start on a 32-bit mask word, edge ranges on a 64-bit one
     const int64_t cbits = prune_chunk_bytes() * 8;
@@ -217,11 +257,12 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na), b_soa = b_soa_of(na);
     const size_t b_mask = aup(8 * (size_t)(max_bits / 64 + 1));
     const size_t need = 2 * b_ord + 3 * b_rng + b_mask + (topo ? 3 : 2) * b_soa;
+    pc->gen = 0;  // valid only once the counts are in
+    pc->plan_gen = 0;
     if (pc->bytes < need) {
       free_ctx(ctx, pc->dev, pc->bytes);
       pc->dev = nullptr;
       pc->bytes = 0;
-      pc->gen = 0;
       ca_status st = alloc_ctx(ctx, &pc->dev, need);
       if (st) return st;
       pc->bytes = need;
@@ -237,26 +278,64 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
                                    topo ? (uint32_t*)(tables + 2 * b_soa) : nullptr));
     else
       HIP_TRY(ctx, launch_prune128_soa(dev_of(cs), d_order, na, (uint32_t*)tables, (uint32_t*)(tables + b_soa), s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));  // the host vectors above go out of scope
     pc->na = na;
     pc->cuts = cuts;
     pc->cut_bit0 = bit0;
-    pc->gen = 0;  // valid only once the counts are in
-    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
-      ca_status st = bounds_chunk(base, b_mask, (int)c);
-      if (st) return st;
+    pc->b_mask = b_mask;
+    pc->plan_gen = gen_of(cs);
+    pc->plan_kind = con_key(con);
+    pc->plan_p = con->thr_num;
+    pc->plan_q = con->thr_den;
+    pc->plan_screened = screened;
+    pc->plan_pairs = pairs;
+  }
+  if (!hit) {
+    const int n_chunks = (int)pc->cuts.size() - 1;
+    char* base = (char*)pc->dev;
+    const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na);
+    if (n_chunks > 1 && defer) {
+      // the caller writes in pieces next: one sweep then counts and writes
+      *n_out = -1;
+      if (n_bound) *n_bound = pc->plan_pairs;
+      return CA_OK;
     }
     pc->counts.assign(na, 0);
+    if (n_chunks > 1 && pieces && rep) {
+      // one sweep: each chunk's bounds pass, its counts, then its pairs in
+      // pieces while its mask is in place
+      std::vector<int64_t> off(na + 1, 0);
+      int64_t acc = 0;
+      int64_t* d_off = (int64_t*)(base + 2 * b_ord + 2 * b_rng);
+      for (int c = 0; c < n_chunks; ++c) {
+        ca_status st = bounds_chunk(base, pc->b_mask, c);
+        if (st) return st;
+        const int64_t a_lo = pc->cuts[c], a_hi = pc->cuts[c + 1];
+        HIP_TRY(ctx, hipMemcpyAsync(pc->counts.data() + a_lo, base + 2 * b_ord + b_rng + 8 * a_lo,
+                                    8 * (size_t)(a_hi - a_lo), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        for (int64_t a = a_lo; a < a_hi; ++a) {
+          off[a] = acc;
+          acc += pc->counts[a];
+        }
+        off[a_hi] = acc;
+        HIP_TRY(ctx, hipMemcpyAsync(d_off + a_lo, off.data() + a_lo, 8 * (size_t)(a_hi - a_lo),
+                                    hipMemcpyHostToDevice, s));
+        st = write_pieces(base, c, a_lo, a_hi, pc->counts, off);
+        if (st) return st;
+      }
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+      finish();
+      *n_out = pc->total;
+      return CA_OK;
+    }
+    for (int c = 0; c < n_chunks; ++c) {
+      ca_status st = bounds_chunk(base, pc->b_mask, c);
+      if (st) return st;
+    }
     HIP_TRY(ctx, hipMemcpyAsync(pc->counts.data(), base + 2 * b_ord + b_rng, 8 * na, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    pc->total = 0;
-    for (int64_t a = 0; a < na; ++a) pc->total += pc->counts[a];
-    pc->gen = gen_of(cs);
-    pc->kind = con_key(con);
-    pc->p = con->thr_num;
-    pc->q = con->thr_den;
-    pc->b_mask = b_mask;
-    stats_of(ctx)->pairs_screened += screened;
-    stats_of(ctx)->pairs_survived += pc->total;
+    finish();
   }
   const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na);
   char* base = (char*)pc->dev;
@@ -280,34 +359,23 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
       ca_status st = bounds_chunk(base, pc->b_mask, c);
       if (st) return st;
     }
-    for (int64_t a0 = pc->cuts[c]; a0 < pc->cuts[c + 1];) {
-      const int64_t a1 = pieces ? piece_end(pc->counts, a0, pc->cuts[c + 1], pieces->cap) : pc->cuts[c + 1];
-      if (a1 == a0) return fail_ctx(ctx, CA_EINVAL, "internal: an anchor's candidates exceed the piece size");
-      PruneArgs pa{(int32_t*)base, (int32_t*)(base + b_ord), a1, nullptr, d_off, rep, mem};
-      pa.a_begin = a0;
-      pa.mask_bit0 = pc->cut_bit0[c];
-      pa.order_ids = edge ? 1 : 0;
-      pa.out_base = pieces ? off[a0] : 0;
-      HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, thr, (int64_t*)(base + 2 * b_ord),
-                                   (uint32_t*)(base + 2 * b_ord + 3 * b_rng), true, s));
-      if (pieces && off[a1] > off[a0]) {
-        ca_status st = pieces->fn(off[a1] - off[a0]);
-        if (st) return st;
-      }
-      a0 = a1;
-    }
+    ca_status st = write_pieces(base, c, pc->cuts[c], pc->cuts[c + 1], pc->counts, off);
+    if (st) return st;
   }
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return CA_OK;
 }
 
 // Device candidate generation into caller buffers (or sizing only when rep is
-// null), or in pieces (rep, mem: one piece).
+// null), or in pieces (rep, mem: one piece).  defer: a sizing call whose
+// bounds pass would run in several chunks returns *n_out = -1 and, in
+// *n_bound, an upper bound of the candidates, without running it; the
+// writing call in pieces then counts and writes in one sweep.
 static ca_status prune_device(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, const ca_constraint* con,
                               int64_t cap, int32_t* rep, int32_t* mem, int64_t* n_out,
-                              const Pieces* pieces = nullptr) {
+                              const Pieces* pieces = nullptr, bool defer = false, int64_t* n_bound = nullptr) {
   if (con->kind == CA_EDGE || mixed_ok_of(cs))
-    return prune_cached_device(ctx, s, cs, con, cap, rep, mem, n_out, pieces);
+    return prune_cached_device(ctx, s, cs, con, cap, rep, mem, n_out, pieces, defer, n_bound);
   std::vector<int32_t> order, hi;
   int64_t screened = 0;
   build_ranges(cs, con, order, hi, screened);
@@ -547,11 +615,14 @@ static ca_status cover_build(ca_ctx* ctx, hipStream_t s, const ca_clipset* cs, c
   cc->bytes = 0;
   cc->gen = 0;
   const int64_t n = n_of(cs);
-  int64_t np = 0;
-  ca_status st = prune_device(ctx, s, cs, con, 0, nullptr, nullptr, &np);
+  int64_t np = 0, bound = 0;
+  ca_status st = prune_device(ctx, s, cs, con, 0, nullptr, nullptr, &np, nullptr, true, &bound);
   if (st) return st;
-  const int64_t piece = cover_piece_pairs(n);
-  if (np <= piece) {
+  // np < 0: the bounds pass runs in chunks and is left to the piece sweep;
+  // no piece needs to hold more than the bound of the candidates
+  const int64_t piece =
+      np >= 0 ? cover_piece_pairs(n) : std::min(cover_piece_pairs(n), std::max<int64_t>(bound, 1));
+  if (np >= 0 && np <= piece) {
     // candidate pairs and their results
     const size_t b4 = aup(4 * (size_t)np), b_bits = aup((size_t)np), b_sh = aup(8 * (size_t)np),
                  b_cnt = aup(8 * (size_t)np), b_sc = aup(16 * (size_t)np);

@@ -29,6 +29,11 @@ struct PruneCache {
   std::vector<int64_t> counts;
   std::vector<int64_t> cuts;     // anchor chunks of the bounds pass: [cuts[c], cuts[c + 1])
   std::vector<int64_t> cut_bit0; // first mask bit of each chunk (64-bit aligned)
+  // the plan (anchor order, ranges, chunks and partner tables on the device)
+  // of the key below, valid before the counts are in
+  uint64_t plan_gen = 0;
+  int64_t plan_kind = 0, plan_p = 0, plan_q = 0, plan_screened = 0;
+  int64_t plan_pairs = 0;        // pairs in the partner ranges (bounds the candidates)
 };
 
 // The last cover relation built by ca_cover / ca_cluster (CSR sorted by
