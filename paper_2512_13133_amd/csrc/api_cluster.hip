@@ -187,6 +187,7 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
       HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
       pa.soa_row = (const uint32_t*)tables;
       pa.soa_col = (const uint32_t*)(tables + b_soa);
+      pa.soa_grp = (const uint32_t*)(tables + 2 * b_soa);
       HIP_TRY(ctx, launch_prune128(dev_of(cs), dev_of(cs), pa, thr, d_roff, d_mask, false, s));
     }
     return CA_OK;
@@ -256,7 +257,9 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     }
     const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na), b_soa = b_soa_of(na);
     const size_t b_mask = aup(8 * (size_t)(max_bits / 64 + 1));
-    const size_t need = 2 * b_ord + 3 * b_rng + b_mask + (topo ? 3 : 2) * b_soa;
+    // partner tables: cosine rows, columns and shift-group maxima; edge box
+    // sizes, polygon counts (and hashes)
+    const size_t need = 2 * b_ord + 3 * b_rng + b_mask + (edge && !topo ? 2 : 3) * b_soa;
     pc->gen = 0;  // valid only once the counts are in
     pc->plan_gen = 0;
     if (pc->bytes < need) {
@@ -277,7 +280,8 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
       HIP_TRY(ctx, launch_edge_soa(dev_of(cs), d_order, na, (uint32_t*)tables, (int32_t*)(tables + b_soa), s,
                                    topo ? (uint32_t*)(tables + 2 * b_soa) : nullptr));
     else
-      HIP_TRY(ctx, launch_prune128_soa(dev_of(cs), d_order, na, (uint32_t*)tables, (uint32_t*)(tables + b_soa), s));
+      HIP_TRY(ctx, launch_prune128_soa(dev_of(cs), d_order, na, (uint32_t*)tables, (uint32_t*)(tables + b_soa),
+                                       (uint32_t*)(tables + 2 * b_soa), s));
     HIP_TRY(ctx, hipStreamSynchronize(s));  // the host vectors above go out of scope
     pc->na = na;
     pc->cuts = cuts;

@@ -93,7 +93,8 @@ struct ca_server {
   std::vector<int32_t> lib_order;  // library ids by (n, id)
   std::vector<int32_t> lib_n;      // their pixel counts
   int32_t* d_order = nullptr;
-  uint32_t* d_soa = nullptr;       // transposed library sliding sums: rows, then columns (64 x n each)
+  uint32_t* d_soa = nullptr;       // transposed library sliding sums: rows, columns (64 x n each), then
+                                   // their shift-group maxima (64 x n)
   std::vector<ca_ctx*> slot_ctx;
   std::vector<hipStream_t> slot_stream;
   std::vector<capriv::DevArena> slot_arena;
@@ -241,6 +242,7 @@ void run_request(ca_server* srv, int slot, Request* req) {
     const int64_t nl = (int64_t)srv->lib_order.size();
     pa.soa_row = srv->d_soa;
     pa.soa_col = srv->d_soa + 64 * nl;
+    pa.soa_grp = srv->d_soa + 128 * nl;
     pa.soa_n = nl;
     pa.seg = (int)seg;
     pa.n_seg = (int)n_seg;
@@ -377,10 +379,11 @@ extern "C" ca_status ca_server_create(ca_ctx* ctx, const ca_clipset* library, co
   for (size_t k = 0; k < srv->lib_order.size(); ++k) srv->lib_n[k] = np[srv->lib_order[k]];
   const int64_t nl = (int64_t)srv->lib_order.size();
   const size_t b_ord = (4 * (size_t)nl + 4 + 255) & ~(size_t)255;
-  if (hipMalloc((void**)&srv->d_order, b_ord + 2 * 256 * (size_t)nl) != hipSuccess ||
+  if (hipMalloc((void**)&srv->d_order, b_ord + 3 * 256 * (size_t)nl) != hipSuccess ||
       hipMemcpy(srv->d_order, srv->lib_order.data(), 4 * (size_t)nl, hipMemcpyHostToDevice) != hipSuccess ||
       (srv->d_soa = (uint32_t*)((char*)srv->d_order + b_ord),
-       launch_prune128_soa(dev_of(library), srv->d_order, nl, srv->d_soa, srv->d_soa + 64 * nl, nullptr)) != hipSuccess ||
+       launch_prune128_soa(dev_of(library), srv->d_order, nl, srv->d_soa, srv->d_soa + 64 * nl,
+                           srv->d_soa + 128 * nl, nullptr)) != hipSuccess ||
       hipStreamSynchronize(nullptr) != hipSuccess) {
     if (srv->d_order) (void)hipFree(srv->d_order);
     delete srv;

@@ -143,6 +143,9 @@ struct PruneArgs {
   const uint32_t* soa_row = nullptr;
   const uint32_t* soa_col = nullptr;
   int64_t soa_n = 0;
+  // the partners' shift-group maxima of the sliding sums (32 rows a
+  // dimension, rows then columns, stride soa_n); null: no group stage
+  const uint32_t* soa_grp = nullptr;
   // edge track: polygon box sizes (w | h << 16 of polygon q of the partner at
   // position b at [q * soa_n + b]) and polygon counts by position
   const uint32_t* soa_wh = nullptr;

@@ -132,7 +132,7 @@ hipError_t launch_xcorr(const ClipsDev& cr, const ClipsDev& cm, const PairIO& io
 // ordered write of the survivors (needs pa.offs).
 // Transposed copies of the partners' sliding sums in `order` (64 x n words each).
 hipError_t launch_prune128_soa(const ClipsDev& cb, const int32_t* order, int64_t n, uint32_t* soa_row,
-                               uint32_t* soa_col, hipStream_t s);
+                               uint32_t* soa_col, uint32_t* soa_grp, hipStream_t s);
 hipError_t launch_prune128(const ClipsDev& ca, const ClipsDev& cb, const PruneArgs& pa, Threshold thr,
                            const int64_t* range_off, uint32_t* mask, bool write, hipStream_t s);
 hipError_t launch_validate(const ClipsDev& cr, const ClipsDev& cm, int64_t n_pairs, const int32_t* rep,

@@ -6,6 +6,17 @@
 // Anchors are clips in (n, id) order; B1 leaves each anchor a contiguous
 // range of larger partners (computed on the host).  One wavefront owns an
 // anchor; its lanes take 64 partners at a time.
+//   group stage    the shifts |d| <= 16 split into two groups G; per group the
+//                  partner's sliding sums maximised over the group's shifts,
+//                  M_G[Y] = max_{d in G} W[(8 Y + d) mod 128], bound every
+//                  shift of the group at once: U(d) <= sum_Y min(A_rep[Y],
+//                  M_G[Y]).  The two groups share a packed 16-bit pair, so
+//                  the stage costs 16 min/add pairs a dimension (the coarse
+//                  stage 544).  It is looser than the coarse stage, so it only
+//                  drops pairs the coarse stage would drop (about two thirds of
+//                  the range on 128 x 128 layout clips); its survivors are
+//                  queued in LDS so the coarse stage runs on full waves,
+//                  reading each queued partner's own sliding sums.
 //   coarse stage   U(d) <= sum_Y min(A_rep[Y], W_mem[(8 Y + d) mod 128]) over the
 //                  16 row blocks Y, A = block sums of the anchor (uniform),
 //                  W = sliding 8-row sums of the partner (64 registers of packed
@@ -71,6 +82,20 @@ __device__ __forceinline__ int coarse_dim(const uint16_t* __restrict__ A, int st
   return best;
 }
 
+// Group bound of one dimension: max over the two shift groups of
+// sum_Y min(A[Y], M_G[Y]); G: the partner's packed group maxima (block Y at
+// row Y of a table of stride n).
+__device__ __forceinline__ int group_dim(const uint16_t* __restrict__ A, int stride, const uint32_t* __restrict__ G,
+                                         int64_t n, int64_t pos) {
+  u16x2 acc = u16x2{0, 0};
+#pragma unroll
+  for (int Y = 0; Y < 16; ++Y) {
+    const u16x2 a = as_u16x2((uint32_t)A[Y * stride] * 0x10001u);
+    acc += __builtin_elementwise_min(as_u16x2(G[Y * n + pos]), a);
+  }
+  return max((int)acc.x, (int)acc.y);
+}
+
 // Exact bound of one dimension: per direction the max over the window of
 // U(d) = sum_y min(Ra[y], Rb[(y + d) mod 128]).
 // Ra: the anchor's packed pairs (uniform, streamed); Be/Bo: partner pairs aligned at even / odd rows.
@@ -100,8 +125,8 @@ __device__ __forceinline__ void exact_dim(const uint32_t* __restrict__ Ra, const
 __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsDev cb, PruneArgs pa, Threshold thr,
                                                              const int64_t* __restrict__ range_off,
                                                              uint32_t* __restrict__ mask, int64_t block0) {
-  __shared__ int queue[128];
-  __shared__ int qlen;
+  __shared__ int q1[128], q2[128];  // group-stage and coarse-stage survivors (positions in the range)
+  __shared__ int q1len, q2len;
   const int64_t a = block0 + (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
   const int ia = pa.anchor_ids ? pa.anchor_ids[a] : pa.order[a];
@@ -120,13 +145,35 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
     }
   }
   const int64_t roff = range_off[a] - pa.mask_bit0;
-  if (lane == 0) qlen = 0;
+  if (lane == 0) {
+    q1len = 0;
+    q2len = 0;
+  }
   __syncthreads();
   int64_t found = 0;
 
+  // append the lanes with `keep` to a queue (its length in LDS)
+  auto push = [&](int* q, int* len, bool keep, int value) {
+    const unsigned long long km = __ballot(keep);
+    const int base = *len;
+    if (keep) q[base + __popcll(km & ((1ull << lane) - 1ull))] = value;
+    __syncthreads();
+    if (lane == 0) *len = base + __popcll(km);
+    __syncthreads();
+  };
+  // drop the first k (<= 64) entries of a queue
+  auto pop = [&](int* q, int* len, int k) {
+    const int rest = *len - k;
+    const int v = lane < rest ? q[k + lane] : 0;
+    __syncthreads();
+    if (lane < rest) q[lane] = v;
+    if (lane == 0) *len = rest;
+    __syncthreads();
+  };
+
   auto exact_flush = [&](int count) {
     // lanes < count take queued partners; the rest idle through the same code
-    const int pos = lane < count ? queue[lane] : -1;
+    const int pos = lane < count ? q2[lane] : -1;
     const int ib = pos >= 0 ? pa.order[start + pos] : pa.order[start];
     const int nb = cb.npix[ib];
     const int wb = cb.w[ib];
@@ -155,41 +202,67 @@ __global__ void __launch_bounds__(64) prune128_bounds_kernel(ClipsDev ca, ClipsD
     }
     found += __popcll(__ballot(ok));
   };
-
-  for (int64_t b0 = first; b0 < end; b0 += 64) {
-    const int64_t b = b0 + lane;
-    const bool valid = b < end;
-    const int ib = valid ? pa.order[b] : pa.order[start];
+  // the coarse stage on the first `count` group-stage survivors (lanes <
+  // count); its survivors go to the exact stage's queue
+  auto coarse_flush = [&](int count) {
+    const int rel = lane < count ? q1[lane] : 0;
+    const int64_t pos = start + rel;
+    const int ib = pa.order[pos];
     const int nb = cb.npix[ib];
     const int wb = cb.w[ib];
     const int64_t so_b = cb.sig_off[ib];
     uint32_t W[64];
     const int wmax = max(wa, wb);
-    const int64_t pos = valid ? b : start;
+    const uint4* wr = reinterpret_cast<const uint4*>(cb.winrow + so_b);
 #pragma unroll
-    for (int q = 0; q < 64; ++q) W[q] = pa.soa_row[q * pa.soa_n + pos];
-    const int cr = coarse_dim(ca.winrow + so_a, 8, W, wmax);
-#pragma unroll
-    for (int q = 0; q < 64; ++q) W[q] = pa.soa_col[q * pa.soa_n + pos];
-    const int cc = coarse_dim(ca.wincol + so_a, 8, W, wmax);
-    const bool keep = valid && na > 0 && nb > 0 && passes128(min(cr, cc), na, nb, thr);
-    const unsigned long long km = __ballot(keep);
-    const int qbase = qlen;
-    if (keep) queue[qbase + __popcll(km & ((1ull << lane) - 1ull))] = (int)(b - start);
-    __syncthreads();
-    if (lane == 0) qlen = qbase + __popcll(km);
-    __syncthreads();
-    if (qlen >= 64) {
-      exact_flush(64);
-      __syncthreads();
-      const int rest = qlen - 64;
-      if (lane < rest) queue[lane] = queue[64 + lane];
-      __syncthreads();
-      if (lane == 0) qlen = rest;
-      __syncthreads();
+    for (int q = 0; q < 16; ++q) {
+      const uint4 v = wr[q];
+      W[4 * q] = v.x; W[4 * q + 1] = v.y; W[4 * q + 2] = v.z; W[4 * q + 3] = v.w;
     }
+    const int cr = coarse_dim(ca.winrow + so_a, 8, W, wmax);
+    const uint4* wc = reinterpret_cast<const uint4*>(cb.wincol + so_b);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const uint4 v = wc[q];
+      W[4 * q] = v.x; W[4 * q + 1] = v.y; W[4 * q + 2] = v.z; W[4 * q + 3] = v.w;
+    }
+    const int cc = coarse_dim(ca.wincol + so_a, 8, W, wmax);
+    const bool keep = lane < count && passes128(min(cr, cc), na, nb, thr);
+    push(q2, &q2len, keep, rel);
+  };
+
+  // one call site per stage: each pass takes the next 64 partners through the
+  // group stage, then runs the coarse stage on a full queue (or the rest once
+  // the range is done) and the exact stage likewise
+  int64_t b0 = first;
+  for (;;) {
+    const bool more = b0 < end;
+    if (more) {
+      const int64_t b = b0 + lane;
+      const bool valid = b < end;
+      const int64_t pos = valid ? b : start;
+      const int nb = cb.npix[pa.order[pos]];
+      bool keep = valid && na > 0 && nb > 0;
+      if (pa.soa_grp) {
+        const int gr = group_dim(ca.winrow + so_a, 8, pa.soa_grp, pa.soa_n, pos);
+        const int gc = group_dim(ca.wincol + so_a, 8, pa.soa_grp + 16 * pa.soa_n, pa.soa_n, pos);
+        keep = keep && passes128(min(gr, gc), na, nb, thr);
+      }
+      push(q1, &q1len, keep, (int)(b - start));
+      b0 += 64;
+    }
+    if (q1len >= 64 || (!more && q1len > 0)) {
+      const int k = min(q1len, 64);
+      coarse_flush(k);
+      pop(q1, &q1len, k);
+    }
+    if (q2len >= 64 || (!more && q1len == 0 && q2len > 0)) {
+      const int k = min(q2len, 64);
+      exact_flush(k);
+      pop(q2, &q2len, k);
+    }
+    if (!more && q1len == 0 && q2len == 0) break;
   }
-  if (qlen > 0) exact_flush(qlen);
   if (lane == 0) pa.counts[pa.seg > 0 ? a * pa.n_seg + blockIdx.y : a] = found;
 }
 
@@ -245,12 +318,36 @@ __global__ void prune128_soa_kernel(ClipsDev cb, const int32_t* __restrict__ ord
   soa_col[t] = reinterpret_cast<const uint32_t*>(cb.wincol + so)[q];
 }
 
+// Transposed group maxima of the partner sliding sums: for dimension D (rows
+// 0, columns 1) and block Y, M_G[Y] = max over the shifts d of group G of
+// W[(8 Y + d) mod 128], groups [-16, 0] and [1, 16], packed as (M_0, M_1) at
+// row 16 D + Y of a table of stride n (the clip at position p of order in
+// column p).
+__global__ void prune128_group_kernel(ClipsDev cb, const int32_t* __restrict__ order, int64_t n,
+                                      uint32_t* __restrict__ soa_grp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 32 * n) return;
+  const int r = (int)(t / n);  // 16 D + Y
+  const int64_t p = t - (int64_t)r * n;
+  const int D = r >> 4, Y = r & 15;
+  const int64_t so = cb.sig_off[order[p]];
+  const uint16_t* W = (D ? cb.wincol : cb.winrow) + so;
+  int m0 = 0, m1 = 0;
+  for (int d = -16; d <= 0; ++d) m0 = max(m0, (int)W[(8 * Y + d + 128) & 127]);
+  for (int d = 1; d <= 16; ++d) m1 = max(m1, (int)W[(8 * Y + d + 128) & 127]);
+  soa_grp[(int64_t)(16 * D + Y) * n + p] = pk_u16((uint32_t)m0, (uint32_t)m1);
+}
+
 hipError_t launch_prune128_soa(const ClipsDev& cb, const int32_t* order, int64_t n, uint32_t* soa_row,
-                               uint32_t* soa_col, hipStream_t s) {
+                               uint32_t* soa_col, uint32_t* soa_grp, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t total = 64 * n;
   hipLaunchKernelGGL(prune128_soa_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, cb, order, n,
                      soa_row, soa_col);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !soa_grp) return e;
+  hipLaunchKernelGGL(prune128_group_kernel, dim3((unsigned)((32 * n + 255) / 256)), dim3(256), 0, s, cb, order, n,
+                     soa_grp);
   return hipGetLastError();
 }
 
