@@ -167,6 +167,8 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
   auto b_ord_of = [](int64_t n) { return aup(4 * (size_t)n); };
   auto b_rng_of = [](int64_t n) { return aup(8 * (size_t)n); };
   auto b_soa_of = [](int64_t n) { return aup(4 * 64 * (size_t)n); };
+  // edge: the box-size extremes after the polygon tables
+  auto ext_of = [&](char* tables, int64_t n) { return (uint32_t*)(tables + (topo ? 3 : 2) * b_soa_of(n)); };
   // the bounds pass over anchors [cuts[c], cuts[c + 1]), mask bits from cut_bit0[c]
   auto bounds_chunk = [&](char* base, size_t b_mask, int c) -> ca_status {
     const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na), b_soa = b_soa_of(na);
@@ -182,6 +184,8 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
       pa.soa_wh = (const uint32_t*)tables;
       pa.soa_np = (const int32_t*)(tables + b_soa);
       pa.soa_hash = topo ? (const uint32_t*)(tables + 2 * b_soa) : nullptr;
+      pa.soa_ext = ext_of(tables, na);
+      HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
       HIP_TRY(ctx, launch_edge_prune(dev_of(cs), pa, thr, d_roff, (unsigned long long*)d_mask, s));
     } else {
       HIP_TRY(ctx, hipMemsetAsync(d_mask, 0, b_mask, s));
@@ -258,8 +262,9 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     const size_t b_ord = b_ord_of(na), b_rng = b_rng_of(na), b_soa = b_soa_of(na);
     const size_t b_mask = aup(8 * (size_t)(max_bits / 64 + 1));
     // partner tables: cosine rows, columns and shift-group maxima; edge box
-    // sizes, polygon counts (and hashes)
-    const size_t need = 2 * b_ord + 3 * b_rng + b_mask + (edge && !topo ? 2 : 3) * b_soa;
+    // sizes, polygon counts (and hashes), box-size extremes
+    const size_t need =
+        2 * b_ord + 3 * b_rng + b_mask + (edge ? (topo ? 3 : 2) * b_soa + aup(8 * (size_t)na) : 3 * b_soa);
     pc->gen = 0;  // valid only once the counts are in
     pc->plan_gen = 0;
     if (pc->bytes < need) {
@@ -278,7 +283,7 @@ static ca_status prune_cached_device(ca_ctx* ctx, hipStream_t s, const ca_clipse
     char* tables = base + 2 * b_ord + 3 * b_rng + b_mask;
     if (edge)
       HIP_TRY(ctx, launch_edge_soa(dev_of(cs), d_order, na, (uint32_t*)tables, (int32_t*)(tables + b_soa), s,
-                                   topo ? (uint32_t*)(tables + 2 * b_soa) : nullptr));
+                                   topo ? (uint32_t*)(tables + 2 * b_soa) : nullptr, ext_of(tables, na)));
     else
       HIP_TRY(ctx, launch_prune128_soa(dev_of(cs), d_order, na, (uint32_t*)tables, (uint32_t*)(tables + b_soa),
                                        (uint32_t*)(tables + 2 * b_soa), s));

@@ -153,6 +153,9 @@ struct PruneArgs {
   // edge track over full boundary edges: polygon hashes in the layout of
   // soa_wh, and polygons match only with equal hashes (null: box track)
   const uint32_t* soa_hash = nullptr;
+  // edge track: the extremes of each partner's polygon box sizes, (min w |
+  // max w << 16) at [b] and (min h | max h << 16) at [soa_n + b]
+  const uint32_t* soa_ext = nullptr;
   int seg = 0;      // partners per workgroup (0: one workgroup per anchor range; > 0: n_seg
                     // segments per anchor, counts and offs indexed [a * n_seg + segment])
   int n_seg = 1;

@@ -61,13 +61,15 @@ hipError_t launch_edge_contour(const ClipsDev& cs, const PairIO& io, Threshold t
 // (io.shift, io.flags), then count, score and bit at them.
 hipError_t launch_xysep(const ClipsDev& cs, const PairIO& io, Threshold thr, hipStream_t s);
 hipError_t launch_cosine_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, int maxN, hipStream_t s);
-// Edge bounds pass: 64-bit chunk words of the survivor mask (ranges start on
-// words, range_off in bits) and survivor counts; the pairs are written by
-// launch_prune128(..., write = true) with order_ids set.
-// Transposed polygon box sizes (MAX_POLY x n words) and counts (n) of the clips in `order`, and
-// with soa_hash the polygon hashes in the layout of the sizes (edge track over contours).
+// Edge bounds pass: bits ORed into the survivor mask, which the caller
+// zeroes (ranges start on 64-bit words, range_off in bits), and survivor
+// counts; the pairs are written by launch_prune128(..., write = true) with
+// order_ids set.
+// Transposed polygon box sizes (MAX_POLY x n words) and counts (n) of the clips in `order`, with
+// soa_hash the polygon hashes in the layout of the sizes (edge track over contours), and with
+// soa_ext the extremes of the box sizes (2 x n words; the bounds pass needs them).
 hipError_t launch_edge_soa(const ClipsDev& cs, const int32_t* order, int64_t n, uint32_t* soa_wh, int32_t* soa_np,
-                           hipStream_t s, uint32_t* soa_hash = nullptr);
+                           hipStream_t s, uint32_t* soa_hash = nullptr, uint32_t* soa_ext = nullptr);
 hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
                              unsigned long long* mask, hipStream_t s);
 // Batched MFMA surface for raster 128, half-windows <= 16 (fragment tables from

@@ -12,7 +12,12 @@
 //
 // Edge track.  B3: every polygon on the side with fewer polygons (both if
 // equal) needs a partner polygon whose bounding box differs by at most
-// 2 T_edge in width and in height (E >= |width difference| / 2).
+// 2 T_edge in width and in height (E >= |width difference| / 2).  It implies
+// that the fewer side's widest polygon has a partner at most 2 T_edge
+// narrower, so max w(fewer) <= max w(other) + 2 T_edge, and likewise for the
+// narrowest and for heights: four comparisons of per-clip extremes that drop
+// most pairs of many-polygon clips before the polygon loops run, on queued
+// survivors.
 //
 // Both kernels run twice: once counting survivors per anchor, once writing
 // them at the anchor's exclusive-prefix offset in partner order, so the
@@ -163,13 +168,48 @@ __global__ void __launch_bounds__(64) cosine_prune_kernel(ClipsDev cs, PruneArgs
   if (!pa.offs && lane == 0) pa.counts[a] = written;
 }
 
+// B3 for the pair (anchor with Pa polygons, box sizes from ba and hashes
+// from ha; partner at position b with Pb polygons): the polygons of the fewer
+// side (both if equal) each need a size-compatible (and, over contours,
+// equally hashed) partner.
+__device__ __forceinline__ bool b3_pass(const PruneArgs& pa, const int16_t* ba, const uint32_t* ha, int Pa,
+                                        int64_t b, int Pb, int tol, bool topo) {
+  auto wh_a = [&](int q) { return (uint32_t)(uint16_t)(ba[4 * q + 1] - ba[4 * q]) |
+                                  ((uint32_t)(uint16_t)(ba[4 * q + 3] - ba[4 * q + 2]) << 16); };
+  auto wh_b = [&](int qq) { return pa.soa_wh[(int64_t)qq * pa.soa_n + b]; };
+  bool pass = true;
+  for (int side = 0; side < 2 && pass; ++side) {
+    const bool check = side == 0 ? (Pa <= Pb) : (Pb <= Pa);
+    if (!check) continue;
+    const int PX = side == 0 ? Pa : Pb, PY = side == 0 ? Pb : Pa;
+    for (int p = 0; p < PX && pass; ++p) {
+      const uint32_t x = side == 0 ? wh_a(p) : wh_b(p);
+      const int wx = (int)(x & 0xffffu), hx = (int)(x >> 16);
+      const uint32_t tx = !topo ? 0u : (side == 0 ? ha[p] : pa.soa_hash[(int64_t)p * pa.soa_n + b]);
+      bool hit = false;
+      for (int qq = 0; qq < PY && !hit; ++qq) {
+        const uint32_t y = side == 0 ? wh_b(qq) : wh_a(qq);
+        const int wy = (int)(y & 0xffffu), hy = (int)(y >> 16);
+        hit = abs(wx - wy) <= tol && abs(hx - hy) <= tol;
+        if (hit && topo) hit = tx == (side == 0 ? pa.soa_hash[(int64_t)qq * pa.soa_n + b] : ha[qq]);
+      }
+      if (!hit) pass = false;
+    }
+  }
+  return pass;
+}
+
 // Edge track: one 64-lane workgroup per anchor a; lanes take partners b in
-// [a+1, hi[a]) of the same raster size, 64 at a time.  Each chunk's pass flags
-// are one 64-bit word of the survivor mask (the anchor's range starts on a
-// word, range_off[a] in bits); counts[a] gets the survivors.
+// [a+1, hi[a]) of the same raster size, 64 at a time, through the extremes
+// test; its survivors are queued in LDS and run B3 on full waves, and their
+// pass bits are ORed into the mask, one atomic per mask word a wave touches.
+// The caller zeroes the mask; the anchor's range starts on a 64-bit word
+// (range_off[a] in bits); counts[a] gets the survivors.
 __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs pa, Threshold thr,
                                                         const int64_t* __restrict__ range_off,
                                                         unsigned long long* __restrict__ mask, int64_t block0) {
+  __shared__ int q[128];  // extremes-test survivors (offsets in the range)
+  __shared__ int qlen;
   const int64_t a = block0 + (int64_t)blockIdx.x;
   const int lane = threadIdx.x;
   const int ia = pa.order[a];
@@ -182,42 +222,68 @@ __global__ void __launch_bounds__(64) edge_prune_kernel(ClipsDev cs, PruneArgs p
   const int tol = (int)(2 * thr.p);
   unsigned long long* m = mask + ((range_off[a] - pa.mask_bit0) >> 6);
   int64_t found = 0;
-  // box size of polygon q: the anchor's from its own table (uniform reads), the
-  // partner's from the transposed table (one contiguous run across the wave)
-  auto wh_a = [&](int q) { return (uint32_t)(uint16_t)(ba[4 * q + 1] - ba[4 * q]) |
-                                  ((uint32_t)(uint16_t)(ba[4 * q + 3] - ba[4 * q + 2]) << 16); };
-  for (int64_t b0 = a + 1; b0 < end; b0 += 64) {
+  if (Pa <= 0) {  // uniform: an anchor without polygons matches nothing
+    if (lane == 0) pa.counts[a] = 0;
+    return;
+  }
+  const uint32_t ea_w = pa.soa_ext[a], ea_h = pa.soa_ext[pa.soa_n + a];
+  if (lane == 0) qlen = 0;
+  __syncthreads();
+  // the extremes of the fewer side X within tol of those of the other side Y
+  auto ext_ok = [&](uint32_t xw, uint32_t xh, uint32_t yw, uint32_t yh) {
+    return (int)(xw >> 16) <= (int)(yw >> 16) + tol && (int)(xw & 0xffffu) + tol >= (int)(yw & 0xffffu) &&
+           (int)(xh >> 16) <= (int)(yh >> 16) + tol && (int)(xh & 0xffffu) + tol >= (int)(yh & 0xffffu);
+  };
+  for (int64_t b0 = a + 1;;) {
+    const bool more = b0 < end;
+    if (qlen >= 64 || (!more && qlen > 0)) {
+      // B3 on the first `count` queued partners (lanes < count)
+      const int count = min(qlen, 64);
+      const int rel = lane < count ? q[lane] : -1;
+      bool pass = false;
+      if (rel >= 0) {
+        const int64_t b = a + 1 + rel;
+        pass = b3_pass(pa, ba, ha, Pa, b, pa.soa_np[b], tol, topo);
+      }
+      // lanes holding the same mask word are consecutive (the queue keeps the
+      // range order): OR their bits down the run, then its first lane alone
+      // writes the word
+      const int word = rel >= 0 ? (rel >> 6) : -1;
+      unsigned long long bits = pass ? 1ull << (rel & 63) : 0ull;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int w2 = __shfl_down(word, off);
+        const unsigned long long b2 = __shfl_down(bits, off);
+        if (lane + off < 64 && w2 == word) bits |= b2;
+      }
+      const int wprev = __shfl_up(word, 1);
+      if (word >= 0 && bits && (lane == 0 || wprev != word)) atomicOr(m + word, bits);
+      found += __popcll(__ballot(pass));
+      const int rest = qlen - count;
+      const int v = lane < rest ? q[count + lane] : 0;
+      __syncthreads();
+      if (lane < rest) q[lane] = v;
+      if (lane == 0) qlen = rest;
+      __syncthreads();
+      continue;
+    }
+    if (!more) break;
     const int64_t b = b0 + lane;
-    bool pass = false;
+    bool keep = false;
     if (b < end) {
       const int Pb = pa.soa_np[b];
-      if (Pa > 0 && Pb > 0) {
-        auto wh_b = [&](int q) { return pa.soa_wh[(int64_t)q * pa.soa_n + b]; };
-        pass = true;
-        // polygons of the fewer side each need a size-compatible partner
-        for (int side = 0; side < 2 && pass; ++side) {
-          const bool check = side == 0 ? (Pa <= Pb) : (Pb <= Pa);
-          if (!check) continue;
-          const int PX = side == 0 ? Pa : Pb, PY = side == 0 ? Pb : Pa;
-          for (int p = 0; p < PX && pass; ++p) {
-            const uint32_t x = side == 0 ? wh_a(p) : wh_b(p);
-            const int wx = (int)(x & 0xffffu), hx = (int)(x >> 16);
-            const uint32_t tx = !topo ? 0u : (side == 0 ? ha[p] : pa.soa_hash[(int64_t)p * pa.soa_n + b]);
-            bool hit = false;
-            for (int qq = 0; qq < PY && !hit; ++qq) {
-              const uint32_t y = side == 0 ? wh_b(qq) : wh_a(qq);
-              const int wy = (int)(y & 0xffffu), hy = (int)(y >> 16);
-              hit = abs(wx - wy) <= tol && abs(hx - hy) <= tol;
-              if (hit && topo) hit = tx == (side == 0 ? pa.soa_hash[(int64_t)qq * pa.soa_n + b] : ha[qq]);
-            }
-            if (!hit) pass = false;
-          }
-        }
+      if (Pb > 0) {
+        const uint32_t eb_w = pa.soa_ext[b], eb_h = pa.soa_ext[pa.soa_n + b];
+        keep = (Pa > Pb || ext_ok(ea_w, ea_h, eb_w, eb_h)) && (Pb > Pa || ext_ok(eb_w, eb_h, ea_w, ea_h));
       }
     }
-    const unsigned long long bm = __ballot(pass);
-    if (lane == 0) m[(b0 - a - 1) >> 6] = bm;
-    found += __popcll(bm);
+    const unsigned long long km = __ballot(keep);
+    const int base = qlen;
+    if (keep) q[base + __popcll(km & ((1ull << lane) - 1ull))] = (int)(b - a - 1);
+    __syncthreads();
+    if (lane == 0) qlen = base + __popcll(km);
+    __syncthreads();
+    b0 += 64;
   }
   if (lane == 0) pa.counts[a] = found;
 }
@@ -259,20 +325,45 @@ __global__ void edge_soa_kernel(ClipsDev cs, const int32_t* __restrict__ order, 
   if (q == 0) soa_np[p] = np;
 }
 
+// Extremes of the polygon box sizes of the clip at position p of order:
+// (min w | max w << 16) at [p], (min h | max h << 16) at [n + p]; zeros for a
+// clip without polygons (or, over contours, without contour data).
+__global__ void edge_ext_kernel(ClipsDev cs, const int32_t* __restrict__ order, int64_t n, bool topo,
+                                uint32_t* __restrict__ soa_ext) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int i = order[p];
+  const int np = (topo && cs.cstat[i] < 0) ? -1 : min(cs.npoly[i], MAX_POLY);
+  int w0 = 0xffff, w1 = 0, h0 = 0xffff, h1 = 0;
+  for (int q = 0; q < np; ++q) {
+    const int16_t* bx = cs.boxes + ((int64_t)i * MAX_POLY + q) * 4;
+    const int w = bx[1] - bx[0], h = bx[3] - bx[2];
+    w0 = min(w0, w); w1 = max(w1, w);
+    h0 = min(h0, h); h1 = max(h1, h);
+  }
+  if (np <= 0) w0 = h0 = 0;
+  soa_ext[p] = (uint32_t)w0 | ((uint32_t)w1 << 16);
+  soa_ext[n + p] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+}
+
 hipError_t launch_edge_soa(const ClipsDev& cs, const int32_t* order, int64_t n, uint32_t* soa_wh, int32_t* soa_np,
-                           hipStream_t s, uint32_t* soa_hash) {
+                           hipStream_t s, uint32_t* soa_hash, uint32_t* soa_ext) {
   if (n == 0) return hipSuccess;
   if (soa_hash && !cs.cstat) return hipErrorInvalidValue;  // hashes need the contour tables
   const int64_t total = (int64_t)MAX_POLY * n;
   hipLaunchKernelGGL(edge_soa_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, cs, order, n, soa_wh,
                      soa_np, soa_hash);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !soa_ext) return e;
+  hipLaunchKernelGGL(edge_ext_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cs, order, n,
+                     soa_hash != nullptr, soa_ext);
   return hipGetLastError();
 }
 
 hipError_t launch_edge_prune(const ClipsDev& cs, const PruneArgs& pa, Threshold thr, const int64_t* range_off,
                              unsigned long long* mask, hipStream_t s) {
   if (pa.n_anchor == 0) return hipSuccess;
-  if (!pa.soa_wh || !pa.soa_np || pa.soa_n <= 0) return hipErrorInvalidValue;  // the kernel reads them
+  if (!pa.soa_wh || !pa.soa_np || !pa.soa_ext || pa.soa_n <= 0) return hipErrorInvalidValue;  // the kernel reads them
   for (int64_t b0 = pa.a_begin; b0 < pa.n_anchor; b0 += LAUNCH_CHUNK) {
     const unsigned nb = (unsigned)std::min<int64_t>(LAUNCH_CHUNK, pa.n_anchor - b0);
     hipLaunchKernelGGL(edge_prune_kernel, dim3(nb), dim3(64), 0, s, cs, pa, thr, range_off, mask, b0);
