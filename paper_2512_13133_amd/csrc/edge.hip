@@ -389,7 +389,7 @@ constexpr int EDGE_PAIRS_PER_GROUP = 64;  // pairs per wave: one per lane
 // pixel work of each pair (the single-polygon overlap test, the polygon
 // relation), whose answers return to the pair's lane.  Clips with more than 8
 // polygons take the LDS path, one pair at a time.
-__global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, Threshold thr, int64_t block0) {
+__global__ void __launch_bounds__(64, 8) edge_batch_kernel(ClipsDev cs, PairIO io, Threshold thr, int64_t block0) {
   __shared__ unsigned long long relM[MAX_POLY], relR[MAX_POLY];
   __shared__ unsigned long long relM0[MAX_POLY], relR0[MAX_POLY];
   __shared__ int sflag;
@@ -509,10 +509,13 @@ __global__ void __launch_bounds__(64) edge_batch_kernel(ClipsDev cs, PairIO io, 
     for (unsigned long long m = mm; m; m &= m - 1ull) {
       const int t = __ffsll(m) - 1;
       const int nd = __builtin_amdgcn_readlane((int)mirror, t) ? 1 : 2;
-      for (int d = 0; d < nd; ++d) {
-        const unsigned long long r =
-            relation_of(t, d, __builtin_amdgcn_readlane(T0y[d], t), __builtin_amdgcn_readlane(T0x[d], t));
-        if (lane == t) rel0[d] = r;
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {  // unrolled, so rel0 stays in registers
+        if (d < nd) {
+          const unsigned long long r =
+              relation_of(t, d, __builtin_amdgcn_readlane(T0y[d], t), __builtin_amdgcn_readlane(T0x[d], t));
+          if (lane == t) rel0[d] = r;
+        }
       }
     }
     if (multi) {
