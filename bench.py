@@ -670,9 +670,12 @@ def copy_probe(nbytes, reps=3):
         src.sum()
     torch.cuda.synchronize()
     dt_sum = (time.perf_counter() - t) / reps
+    import paper_2512_13133_amd as ca
+    ms_read = ca.probe_read_bandwidth(src, reps=10)
     print(json.dumps({"copy_bytes": src.numel() * 4, "reps": reps, "ms": dt * 1e3,
                       "GBps_read_plus_write": 2 * src.numel() * 4 / dt / 1e9,
-                      "sum_ms": dt_sum * 1e3, "GBps_read_only_sum": src.numel() * 4 / dt_sum / 1e9}))
+                      "sum_ms": dt_sum * 1e3, "GBps_read_only_sum": src.numel() * 4 / dt_sum / 1e9,
+                      "read_probe_ms": ms_read, "GBps_read_probe": src.numel() * 4 / (ms_read * 1e-3) / 1e9}))
 
 
 def _cpu_worker(args):

@@ -580,6 +580,17 @@ ca_status ca_server_run_stats(ca_server* srv, ca_run_stats* out);
 /* Last error message of the server (valid until its next failing call). */
 const char* ca_server_last_error(ca_server* srv);
 
+/* ---- measurement aid (not part of the method) ----------------------------- */
+
+/* For callers that time the alignment kernels against the memory roof: reads
+ * the device buffer `buf` (16-byte aligned, `bytes` a multiple of 16) with a
+ * plain streaming kernel, reps + 1 times on `stream` (the first untimed), and
+ * returns the average milliseconds per read from HIP events, so bytes /
+ * ms_per_read is the read bandwidth an ordinary kernel reaches on the device.
+ * CA_EINVAL on a bad argument, CA_EDEVICE on a HIP failure.  Synchronises. */
+ca_status ca_probe_read_bandwidth(void* stream, const void* buf, uint64_t bytes, int32_t reps,
+                                  double* ms_per_read);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,6 +41,7 @@ SYMBOLS = [
     "ca_server_stats", "ca_server_run_stats", "ca_server_last_error",
     "ca_autotune_report", "ca_autotune_save", "ca_autotune_load", "ca_autotune_clear",
     "ca_graph_create", "ca_graph_launch", "ca_graph_invalid", "ca_graph_destroy",
+    "ca_probe_read_bandwidth",
 ]
 
 
@@ -128,6 +129,7 @@ def load():
     lib.ca_graph_launch.argtypes = [P, P]
     lib.ca_graph_invalid.argtypes = [P, P, C.POINTER(C.c_int64)]
     lib.ca_graph_destroy.argtypes = [P]
+    lib.ca_probe_read_bandwidth.argtypes = [P, P, C.c_uint64, C.c_int32, C.POINTER(C.c_double)]
     for name in SYMBOLS:
         if name not in ("ca_last_error", "ca_server_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -155,6 +157,19 @@ def constraint(kind, thr):
     if kind == "contour":
         return _Constraint(CA_EDGE, CA_EDGES_CONTOUR, int(thr), 1)
     raise ValueError(kind)
+
+
+def probe_read_bandwidth(tensor, reps=10):
+    """Milliseconds per plain streaming read of a CUDA tensor's bytes
+    (``ca_probe_read_bandwidth``, on the current stream): a measurement aid."""
+    import torch
+    lib = load()
+    ms = C.c_double(0.0)
+    st = lib.ca_probe_read_bandwidth(torch.cuda.current_stream(tensor.device).cuda_stream, tensor.data_ptr(),
+                                     tensor.numel() * tensor.element_size(), int(reps), C.byref(ms))
+    if st != CA_OK:
+        raise ClipAlignError(st, "read probe failed")
+    return ms.value
 
 
 class ClipSet:
