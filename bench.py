@@ -126,6 +126,16 @@ def main():
     P = ca.P
     import ctypes as C
 
+    # the read bandwidth a plain streaming kernel reaches on this device (best
+    # of three rounds of ten reads of a 4 GiB buffer, before the workload's
+    # allocations), beside which the main kernel's read rate is set
+    probe_buf = torch.empty(1 << 30, dtype=torch.float32, device=dev)
+    probe_ms = min(ca.probe_read_bandwidth(probe_buf, reps=10) for _ in range(3))
+    read_probe = {"bytes": probe_buf.numel() * 4, "GBps": round(probe_buf.numel() * 4 / (probe_ms * 1e-3) / 1e9, 1),
+                  "kernel": "ca_probe_read_bandwidth: sixteen 16-byte loads in flight per thread"}
+    del probe_buf
+    torch.cuda.empty_cache()
+
     def make_clips(fp32=False, contours=False):
         h = P()
         flags = ca.CA_CLIPS_DEVICE_PTRS | (ca.CA_CLIPS_FP32 if fp32 else 0) | (ca.CA_CLIPS_CONTOURS if contours else 0)
@@ -189,6 +199,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic("pcm_mfma128_kernel") if args.path == "mixed" else None,
                 "avg_launch_ms": round(main_ms, 3), "alg_bytes_per_launch": main_bytes}
+    read_probe["main_kernel_frac"] = round(achieved / read_probe["GBps"], 4)
 
     h, rep, mem, out = last
     n_pairs = rep.numel()
@@ -308,6 +319,7 @@ def main():
                                "cosine 19/20 + edge 3px", "clips": cs.n, "path": args.path,
                    "cosine_pairs_per_step": n_pairs, "edge_pairs_per_step": tot_e // max(args.steps, 1)},
         "roofline": roofline,
+        "hbm_read_probe": read_probe,
         "cpu_baseline": cpu,
         "kernel_pairs_per_s": kernel_rate,
         "plain_fp32": comparator,
