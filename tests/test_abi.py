@@ -46,3 +46,19 @@ def test_create_without_gpu_fails_cleanly():
     st = lib.ca_create(ctypes.byref(ca._Config(0, 0, 0)), ctypes.byref(h))
     assert st == ca.CA_EDEVICE
     assert b"device" in lib.ca_last_error(None)
+
+
+def test_read_probe_rejects_bad_arguments_before_any_device_call():
+    """The read-bandwidth probe validates its arguments on the host: a null
+    buffer, a size that is zero or not a multiple of 16, a misaligned buffer or
+    no repetitions return CA_EINVAL without touching the device."""
+    import paper_2512_13133_amd as ca
+    lib = ca.load()
+    ms = ctypes.c_double(-1.0)
+    aligned = 1 << 20  # never dereferenced: every call below fails validation first
+    cases = [(None, 1024, 1), (aligned, 0, 1), (aligned, 1000, 1), (aligned + 8, 1024, 1), (aligned, 1024, 0)]
+    for buf, size, reps in cases:
+        st = lib.ca_probe_read_bandwidth(None, buf, size, reps, ctypes.byref(ms))
+        assert st == ca.CA_EINVAL, (buf, size, reps)
+    assert ms.value == -1.0
+    assert lib.ca_probe_read_bandwidth(None, aligned, 1024, 1, None) == ca.CA_EINVAL
