@@ -397,6 +397,23 @@ def test_prune_is_safe_and_matches_bounds(ctx):
     h.close()
 
 
+def test_edge_prune_matches_b3_on_many_polygon_clips(ctx):
+    """Clips of the density workload (up to 18 polygons, 6 on average), where
+    the test of per-clip size extremes rejects most pairs before the polygon
+    loops of B3: the survivors equal the oracle's B3 set at 1, 3 and 6 px."""
+    cs = clipgen.dense(n_clips=400, n_templates=40)
+    h = ctx.clips(cs)
+    A = raster.rasters(cs)
+    boxes = [raster.components(a)[1] for a in A]
+    for t in (1, 3, 6):
+        r, m = ctx.prune(h, "edge", t)
+        got = set(zip(r.cpu().numpy().tolist(), m.cpu().numpy().tolist()))
+        want = {(i, j) for i in range(cs.n) for j in range(i + 1, cs.n) if prune.edge_pair_pass(boxes[i], boxes[j], t)}
+        say(f"[prune] edge on density clips, {t} px: {len(got)} survivors, oracle {len(want)}")
+        assert want and got == want
+    h.close()
+
+
 # ------------------------------------------------------------------ a10 clusters
 
 
