@@ -730,14 +730,15 @@ def test_launches_beyond_grid_limit(ctx, path, n_pairs):
 
 
 def _oracle_prune_chunk(args):
-    cs, pairs = args
+    cs, pairs = args[:2]
+    p, q = args[2] if len(args) > 2 else (19, 20)
     A = {}
     out = []
     for i, j in pairs:
         for c in (i, j):
             if c not in A:
                 A[c] = raster.clip_raster(cs, c)
-        if prune.cosine_pair_pass(A[i], A[j], int(cs.marker_w[i]), int(cs.marker_w[j]), 19, 20):
+        if prune.cosine_pair_pass(A[i], A[j], int(cs.marker_w[i]), int(cs.marker_w[j]), p, q):
             out.append((int(i), int(j)))
     return out
 
@@ -763,6 +764,27 @@ def test_prune128_matches_bounds(ctx):
     n_pix = np.array([raster.clip_raster(cs, i).sum() for i in range(cs.n)])
     keys = [(n_pix[a], a) for a in r]
     assert keys == sorted(keys)
+    h.close()
+
+
+def test_prune128_matches_bounds_density_clips(ctx):
+    """Density-workload clips (union densities 0.1-0.6) at 93/100, the loosest
+    threshold of the K = 3 schedule: the survivors of the shift-group, coarse
+    and exact stages equal the oracle's B1 + B2 set."""
+    import multiprocessing as mp
+    cs = clipgen.dense(n_clips=360, n_templates=36)
+    h = ctx.clips(cs)
+    r, m = ctx.prune(h, "cosine", (93, 100))
+    r, m = r.cpu().numpy(), m.cpu().numpy()
+    got = {(min(a, b), max(a, b)) for a, b in zip(r.tolist(), m.tolist())}
+    assert len(got) == r.size
+    ii, jj = np.triu_indices(cs.n, 1)
+    chunks = np.array_split(np.arange(ii.size), 64)
+    with mp.get_context("fork").Pool(WORKERS) as pool:
+        res = pool.map(_oracle_prune_chunk, [(cs, list(zip(ii[c], jj[c])), (93, 100)) for c in chunks])
+    want = set(p for part in res for p in part)
+    say(f"[prune128] density clips at 93/100: survivors got={len(got)} want={len(want)} of {ii.size}")
+    assert want and got == want
     h.close()
 
 
