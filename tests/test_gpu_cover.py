@@ -245,3 +245,24 @@ def test_cover_in_pieces_equals_one_pass(ctx, kind, thr, monkeypatch):
     assert np.abs(cov1["score"] - cov2["score"]).max(initial=0.0) <= 1e-12
     assert cl1["n_clusters"] == cl2["n_clusters"]
     assert (cl1["rep_of"] == cl2["rep_of"]).all() and (cl1["center_shift"] == cl2["center_shift"]).all()
+
+
+@pytest.mark.parametrize("path", ["xcorr", "xysep"])
+def test_cover_in_pieces_other_cosine_paths(ctx, small_case, path, monkeypatch):
+    """The exact objective and the XY-separation path feed the cover relation
+    too: aligned in pieces of at most n pairs, the relation equals the
+    one-pass relation of the same path."""
+    cs = small_case[0]
+    h1 = ctx.clips(cs, fp32=True)
+    one = _np(ctx.cover(h1, "cosine", (1, 2), path))
+    h1.close()
+    monkeypatch.setenv("CLIPALIGN_COVER_PIECE_PAIRS", "1")
+    h2 = ctx.clips(cs, fp32=True)
+    n_cand = ctx.prune(h2, "cosine", (1, 2))[0].numel()
+    pieces = _np(ctx.cover(h2, "cosine", (1, 2), path))
+    h2.close()
+    say(f"[cover pieces] {path}: {n_cand} candidates, {one['col'].size} entries")
+    assert n_cand > cs.n and one["col"].size > 0
+    for k in ("row_ptr", "col", "shift", "value"):
+        assert (one[k] == pieces[k]).all(), k
+    assert np.abs(one["score"] - pieces["score"]).max(initial=0.0) <= 1e-12
