@@ -249,6 +249,24 @@ def test_contour_prune_matches_oracle(ctx):
     h.close()
 
 
+def test_contour_prune_matches_oracle_many_polygons(ctx):
+    """Many-polygon clips (up to about 20 polygons), where the test of per-clip
+    size extremes rejects most pairs ahead of the hash and size loops: the
+    survivors over contours equal the oracle's pre-filter at 1, 3 and 6 px."""
+    cs = many_polygon_set(n=300)
+    data = [contour.clip_polygons(raster.clip_raster(cs, i)) for i in range(cs.n)]
+    rep, mem = clipgen.all_pairs(cs.n)
+    h = ctx.clips(cs, contours=True)
+    for t in (1, 3, 6):
+        g_rep, g_mem = (x.cpu().numpy() for x in ctx.prune(h, "contour", t))
+        got = set(zip(np.minimum(g_rep, g_mem).tolist(), np.maximum(g_rep, g_mem).tolist()))
+        want = {(min(a, b), max(a, b)) for a, b in zip(rep.tolist(), mem.tolist())
+                if contour.pair_pass(data[a], data[b], t)}
+        say(f"[contour] many-polygon prune t={t}: {len(got)} survive, oracle {len(want)} of {rep.size}")
+        assert want and got == want
+    h.close()
+
+
 def test_contour_cover_clusters_and_centers(ctx):
     cs = clipgen.concat([low_jitter_set(), low_jitter_set(seed=5, n=48, jitter=2)])
     rep, mem = clipgen.all_pairs(cs.n)
