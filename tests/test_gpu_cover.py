@@ -266,3 +266,26 @@ def test_cover_in_pieces_other_cosine_paths(ctx, small_case, path, monkeypatch):
     for k in ("row_ptr", "col", "shift", "value"):
         assert (one[k] == pieces[k]).all(), k
     assert np.abs(one["score"] - pieces["score"]).max(initial=0.0) <= 1e-12
+
+
+@pytest.mark.parametrize("kind,thr", [("cosine", (19, 20)), ("edge", 3), ("contour", 3)])
+def test_prune_after_chunked_cover_equals_one_pass(ctx, kind, thr, monkeypatch):
+    """The cover relation first, with the bounds pass in 4 KiB anchor chunks
+    (its sizing call only plans, one sweep then counts and writes), and
+    ca_prune after it (the counts are cached, each chunk's mask is rebuilt
+    for the writing pass): the candidate list equals a one-pass prune's."""
+    cs = clipgen.c128(n_clips=2000, n_templates=40)
+    h1 = ctx.clips(cs, contours=True)
+    rep1, mem1 = (x.cpu().numpy() for x in ctx.prune(h1, kind, thr))
+    cov1 = _np(ctx.cover(h1, kind, thr))
+    h1.close()
+    monkeypatch.setenv("CLIPALIGN_PRUNE_CHUNK_BYTES", "4096")
+    h2 = ctx.clips(cs, contours=True)
+    cov2 = _np(ctx.cover(h2, kind, thr))
+    rep2, mem2 = (x.cpu().numpy() for x in ctx.prune(h2, kind, thr))
+    h2.close()
+    say(f"[prune after cover] {kind}: {rep1.size} candidates, cover entries {cov1['col'].size}")
+    assert rep1.size > 0
+    assert (rep1 == rep2).all() and (mem1 == mem2).all()
+    for k in ("row_ptr", "col", "shift", "value"):
+        assert (cov1[k] == cov2[k]).all(), k
